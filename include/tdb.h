@@ -1,0 +1,151 @@
+/*
+ * tdb.h -- C ABI of the MI355X (gfx950) in situ compressor built on time-dependent
+ * bases (TDB): each streaming snapshot tensor V(t) of order p is kept as a core
+ * tensor C(t) times one orthonormal basis U_n(t) per mode, and advanced snapshot by
+ * snapshot with the paper's closed-form evolution equations.
+ *
+ * Paper: Zamani Ashtiani, Malik, Babaee, "Scalable In Situ Compression of Transient
+ * Simulation Data Using Time-Dependent Bases" (arXiv 2201.06958).
+ *   - problem statement: streaming multidimensional data, modes as groups of
+ *     variables, weighted inner products (Sec. 2.1, eq. (inner));
+ *   - the decomposition into core and bases (Sec. 2.2, eq. (reconstructed));
+ *   - discrete space-time form, quadrature weights, finite-difference derivative,
+ *     HOSVD initialisation (Sec. 2.3);
+ *   - error control and mode addition/removal (Sec. 2.5, eqs. (error), (percentage));
+ *   - storage of core and bases, compression ratio (Sec. 2.6).
+ *
+ * Conventions for every entry point:
+ *   - Return value: TDB_OK (0) or a positive tdb_status error code. No exception or
+ *     abort crosses the ABI; tdb_last_error() gives a message for the last failure
+ *     on a handle (or, for a NULL handle, for the last failed create call).
+ *   - Device pointers ("_dev") are HIP device addresses on the current device;
+ *     host pointers ("_host") are ordinary host memory and are copied before return.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). Work is
+ *     enqueued on it; calls that return host data synchronise it.
+ *   - Snapshots are dense C-contiguous tensors over (N_1, ..., N_p) in the
+ *     configured storage type (mode p has unit stride).
+ *   - A handle is not re-entrant: use one handle from one host thread at a time.
+ */
+#ifndef TDB_H
+#define TDB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tdb_status;
+enum {
+  TDB_OK = 0,
+  TDB_EINVAL = 1,        /* bad argument or configuration                         */
+  TDB_ENOMEM = 2,        /* device or host allocation failed                      */
+  TDB_EHIP = 3,          /* a HIP runtime call failed                             */
+  TDB_ESTATE = 4,        /* call out of order (e.g. ingest before init)           */
+  TDB_ENUMERIC = 5,      /* non-finite data, or an unrecoverable singular core    */
+  TDB_EUNSUPPORTED = 6   /* a valid request this build does not implement         */
+};
+
+enum { TDB_F64 = 0, TDB_F32 = 1 };                      /* snapshot storage type  */
+enum { TDB_PREC_F64 = 0, TDB_PREC_F32 = 1 };            /* bulk-pass arithmetic   */
+enum { TDB_PATH_AUTO = 0, TDB_PATH_PLAIN = 1, TDB_PATH_FUSED = 2 };
+enum { TDB_COPY = 0, TDB_BORROW = 1 };                  /* previous-snapshot mode */
+enum {                                                   /* controller events      */
+  TDB_EV_NONE = 0, TDB_EV_REINIT = 1, TDB_EV_ADD = 2, TDB_EV_REMOVE = 3, TDB_EV_NUMERIC = 4
+};
+
+#define TDB_MAX_ORDER 8       /* ABI array size; this build supports 2 <= p <= 4   */
+#define TDB_SIGMA_K 16        /* leading core singular values reported per mode    */
+
+typedef struct tdb_ctx* tdb_handle;
+
+/* Configuration of one stream (Sec. 2.3, 2.5). Copied at init. */
+typedef struct {
+  int32_t order;                       /* p, 2..4 in this build                        */
+  int64_t dims[TDB_MAX_ORDER];         /* N_n; a mode may be a flattened group of axes */
+  int32_t rank_init[TDB_MAX_ORDER];    /* all 0 => chosen by the rank rule at init     */
+  int32_t rank_max[TDB_MAX_ORDER];     /* caps; clamped to N_n and to the product of
+                                          the other caps; each <= 64 in this build     */
+  const double* weights[TDB_MAX_ORDER];/* host arrays of N_n positive quadrature
+                                          weights (diagonal W^(n)); NULL => 1/N_n      */
+  double dt;                           /* uniform snapshot spacing, > 0                */
+  int32_t data_dtype;                  /* TDB_F64 | TDB_F32                            */
+  int32_t precision;                   /* TDB_PREC_F64 | TDB_PREC_F32 (projection and
+                                          error passes; the small r x r work and the
+                                          state are always FP64)                       */
+  int32_t path;                        /* TDB_PATH_*: AUTO picks FUSED where supported */
+  int32_t adaptive;                    /* 0 = fixed ranks (eps is still reported)      */
+  int32_t snapshot_mode;               /* TDB_COPY: the library keeps its own copy of
+                                          the previous snapshot; TDB_BORROW: the caller
+                                          keeps the previous snapshot's buffer intact
+                                          until the next ingest has completed          */
+  double eps_th;                       /* error threshold on the weighted error eq. (error) */
+  double gamma_th;                     /* > 0: percentage budget of eq. (percentage),
+                                          (1 - gamma_th/100) ||V||^2; <= 0: (eps_th/2)^2 */
+  int32_t slope_window;                /* error-slope window for removal; 0 => 10      */
+} tdb_config;
+
+/* Per-step record (Sec. 2.5, 2.6). */
+typedef struct {
+  int64_t step;                        /* snapshots ingested since init                */
+  double t;                            /* step * dt                                    */
+  double eps;                          /* ||V - C x_n U_n||_W of the evolved state     */
+  double nu;                           /* ||V||_W                                      */
+  double eps_after;                    /* error after this step's reinit (NaN if none) */
+  int32_t ranks[TDB_MAX_ORDER];        /* ranks held after the step                    */
+  int32_t event;                       /* TDB_EV_* taken at this step                  */
+  double sigma[4][TDB_SIGMA_K];        /* leading singular values of each core
+                                          unfolding after the step (0-padded)          */
+  double cr;                           /* compression ratio at the current ranks       */
+  double crbar;                        /* time-weighted ratio since init               */
+  int32_t n_reinit, n_add, n_remove, n_numeric;
+} tdb_stats;
+
+/* Initialise from the first snapshot by a weighted HOSVD (Sec. 2.3). V0_dev: device
+ * tensor in data_dtype. Allocates all device workspace (sized by the caps). On
+ * success *out owns it; on failure *out is NULL. */
+tdb_status tdb_init(const tdb_config* cfg, const void* V0_dev, void* stream, tdb_handle* out);
+
+/* Initialise from given factors instead of a HOSVD (parity and restart use).
+ * ranks[n] gives the core shape; C_host is the C-contiguous r_1 x ... x r_p core;
+ * U_host[n] is the row-major N_n x r_n basis, expected W-orthonormal. */
+tdb_status tdb_init_from_factors(const tdb_config* cfg, const void* V0_dev,
+                                 const int32_t* ranks, const double* C_host,
+                                 const double* const* U_host, void* stream, tdb_handle* out);
+
+/* Advance from t_k to t_{k+1} with snapshot V_dev (Sec. 2.2-2.5): difference quotient,
+ * two Heun stages of eqs. (Corecont)/(basecont), W-orthonormal QR with the factor
+ * folded into the core, weighted error pass, controller (and HOSVD reinit when it
+ * fires). Returns after enqueueing and one small read-back of the controller result. */
+tdb_status tdb_ingest_snapshot(tdb_handle h, const void* V_dev, void* stream);
+
+/* Copy the current ranks, core and bases to the host. ranks_out: TDB_MAX_ORDER ints
+ * (may be NULL). C_host (prod r_n doubles) and U_host[n] (N_n x r_n row-major) may
+ * be NULL to skip. rotate != 0 applies the energetic rotation eq. (rot) first. */
+tdb_status tdb_get_core_and_bases(tdb_handle h, int32_t rotate, int32_t* ranks_out,
+                                  double* C_host, double* const* U_host);
+
+/* Write the dense reconstruction C x_1 U_1 ... x_p U_p into out_dev (data_dtype). */
+tdb_status tdb_reconstruct(tdb_handle h, void* out_dev, void* stream);
+
+/* Change the thresholds; applies from the next ingest. */
+tdb_status tdb_set_threshold(tdb_handle h, double eps_th, double gamma_th);
+
+/* Stats of the last step (or of init). */
+tdb_status tdb_get_stats(tdb_handle h, tdb_stats* out);
+
+/* Free everything the handle owns. NULL-safe. */
+void tdb_destroy(tdb_handle h);
+
+/* Layout check for language bindings: writes sizeof(tdb_config) and sizeof(tdb_stats)
+ * (either pointer may be NULL). Needs no device. */
+void tdb_struct_sizes(int64_t* config_bytes, int64_t* stats_bytes);
+
+/* Message for the last non-OK status on h (or of the last failed create when h is
+ * NULL). Owned by the library; valid until the next call on the same handle. */
+const char* tdb_last_error(tdb_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDB_H */

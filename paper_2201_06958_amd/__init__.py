@@ -1,0 +1,6 @@
+"""MI355X-native in situ compressor with time-dependent bases (arXiv 2201.06958).
+
+The compute path lives in libtdb.so (hand-written HIP for gfx950, C ABI in
+include/tdb.h); `Compressor` is its thin ctypes binding.
+"""
+from .tdb import Compressor, TDBError, load_library  # noqa: F401

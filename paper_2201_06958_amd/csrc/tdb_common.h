@@ -1,0 +1,83 @@
+// Shared device-side definitions of the TDB library (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define TDB_P 4          // largest tensor order handled by the kernels
+#define TDB_RCAP 64      // largest rank cap per mode
+#define TDB_WIN 64       // longest error-slope window
+#define TDB_NEIG 512     // largest mode size for the device HOSVD eigensolver
+#define TDB_BLOCK 256    // threads per block of the small FP64 kernels
+
+// Controller events (same values as the TDB_EV_* codes of the public header).
+enum { EV_NONE = 0, EV_REINIT = 1, EV_ADD = 2, EV_REMOVE = 3, EV_NUMERIC = 4 };
+
+// Controller decisions taken on the device after the error pass.
+enum { DEC_NONE = 0, DEC_ADD = 1, DEC_REMOVE = 2, DEC_NUMERIC = 3, DEC_INIT = 4 };
+
+// A direction whose full-data singular value is below this fraction of its mode's
+// largest is numerically absent: adding it would make a core Gram matrix singular.
+#define TDB_SIGMA_FLOOR 1e-6
+// Core Gram matrices whose smallest Cholesky pivot falls below this fraction of the
+// largest diagonal entry are treated as singular (a numerical event).
+#define TDB_PIVOT_FLOOR 1e-12
+
+// Device-resident controller state and per-step outputs (error control, Sec. 2.5).
+struct CtrlState {
+  // configuration
+  double eps_th, gamma_th, dt;
+  int adaptive, slope_window, p, pad0;
+  int caps[TDB_P];
+  long long dims[TDB_P];
+  // evolving state
+  double eps_trig;
+  int unmet;
+  int ranks[TDB_P];
+  int wcount, whead;
+  double window[TDB_WIN];
+  // outputs of the last step
+  int decision;       // DEC_*
+  int event;          // TDB_EV_* (see tdb.h)
+  int numeric;        // set when a core Gram or a basis Gram failed its Cholesky test
+  int rank_changed;
+  double eps2, nu2;   // from the error pass
+  double eps, nu, eps_after;
+  double sigma[TDB_P][TDB_RCAP];   // core unfolding singular values, descending
+  int n_events[5];
+};
+
+__device__ __forceinline__ double warp_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Block-wide sum (blockDim.x a multiple of 64, <= 1024); result valid in all threads.
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = warp_sum(v);
+  __syncthreads();
+  if (lane == 0) scratch[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; ++i) s += scratch[i];   // same order in every thread
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ double block_max(double v, double* scratch) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  __syncthreads();
+  if (lane == 0) scratch[wid] = v;
+  __syncthreads();
+  double s = scratch[0];
+  for (int i = 1; i < nw; ++i) s = fmax(s, scratch[i]);
+  __syncthreads();
+  return s;
+}
+
+// Index helpers for a C-ordered tensor viewed as (outer, N_n, inner) around mode n.
+struct ModeView {
+  long long outer, inner;
+  int n_len;
+};

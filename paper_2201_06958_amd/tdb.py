@@ -1,0 +1,247 @@
+"""ctypes binding of the C ABI in include/tdb.h (argument marshalling only).
+
+Every numerical step runs inside libtdb.so on the GPU; this module only converts
+Python arguments to the C structs, passes torch device pointers and streams, and
+raises TDBError on a non-zero status. If the library is missing it raises at
+load time instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtdb.so")
+
+MAX_ORDER = 8
+SIGMA_K = 16
+
+OK, EINVAL, ENOMEM, EHIP, ESTATE, ENUMERIC, EUNSUPPORTED = range(7)
+F64, F32 = 0, 1
+PREC_F64, PREC_F32 = 0, 1
+PATH_AUTO, PATH_PLAIN, PATH_FUSED = 0, 1, 2
+COPY, BORROW = 0, 1
+EVENTS = {0: "", 1: "reinit", 2: "add", 3: "remove", 4: "numeric"}
+
+_STATUS = {1: "TDB_EINVAL", 2: "TDB_ENOMEM", 3: "TDB_EHIP", 4: "TDB_ESTATE", 5: "TDB_ENUMERIC",
+           6: "TDB_EUNSUPPORTED"}
+
+
+class TDBError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class TdbConfig(ctypes.Structure):
+    _fields_ = [
+        ("order", ctypes.c_int32),
+        ("dims", ctypes.c_int64 * MAX_ORDER),
+        ("rank_init", ctypes.c_int32 * MAX_ORDER),
+        ("rank_max", ctypes.c_int32 * MAX_ORDER),
+        ("weights", ctypes.POINTER(ctypes.c_double) * MAX_ORDER),
+        ("dt", ctypes.c_double),
+        ("data_dtype", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("path", ctypes.c_int32),
+        ("adaptive", ctypes.c_int32),
+        ("snapshot_mode", ctypes.c_int32),
+        ("eps_th", ctypes.c_double),
+        ("gamma_th", ctypes.c_double),
+        ("slope_window", ctypes.c_int32),
+    ]
+
+
+class TdbStats(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int64),
+        ("t", ctypes.c_double),
+        ("eps", ctypes.c_double),
+        ("nu", ctypes.c_double),
+        ("eps_after", ctypes.c_double),
+        ("ranks", ctypes.c_int32 * MAX_ORDER),
+        ("event", ctypes.c_int32),
+        ("sigma", (ctypes.c_double * SIGMA_K) * 4),
+        ("cr", ctypes.c_double),
+        ("crbar", ctypes.c_double),
+        ("n_reinit", ctypes.c_int32),
+        ("n_add", ctypes.c_int32),
+        ("n_remove", ctypes.c_int32),
+        ("n_numeric", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libtdb.so and declare the C signatures. Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    H = ctypes.c_void_p
+    P = ctypes.c_void_p
+    lib.tdb_init.argtypes = [ctypes.POINTER(TdbConfig), P, P, ctypes.POINTER(H)]
+    lib.tdb_init_from_factors.argtypes = [ctypes.POINTER(TdbConfig), P, ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.POINTER(ctypes.c_double)), P,
+                                          ctypes.POINTER(H)]
+    lib.tdb_ingest_snapshot.argtypes = [H, P, P]
+    lib.tdb_get_core_and_bases.argtypes = [H, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.POINTER(ctypes.c_double))]
+    lib.tdb_reconstruct.argtypes = [H, P, P]
+    lib.tdb_set_threshold.argtypes = [H, ctypes.c_double, ctypes.c_double]
+    lib.tdb_get_stats.argtypes = [H, ctypes.POINTER(TdbStats)]
+    lib.tdb_destroy.argtypes = [H]
+    lib.tdb_destroy.restype = None
+    lib.tdb_last_error.argtypes = [H]
+    lib.tdb_last_error.restype = ctypes.c_char_p
+    lib.tdb_struct_sizes.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    lib.tdb_struct_sizes.restype = None
+    for name in ("tdb_init", "tdb_init_from_factors", "tdb_ingest_snapshot", "tdb_get_core_and_bases",
+                 "tdb_reconstruct", "tdb_set_threshold", "tdb_get_stats"):
+        getattr(lib, name).restype = ctypes.c_int32
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    lib.tdb_struct_sizes(ctypes.byref(a), ctypes.byref(b))
+    if a.value != ctypes.sizeof(TdbConfig) or b.value != ctypes.sizeof(TdbStats):
+        raise RuntimeError("tdb.h struct layout does not match the binding")
+    _lib = lib
+    return lib
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t):
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("snapshots must be contiguous device tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Compressor:
+    """One streaming tensor compressed with time-dependent bases (see tdb.h)."""
+
+    def __init__(self, dims: Sequence[int], dt: float, rank_max: Sequence[int],
+                 rank_init: Optional[Sequence[int]] = None,
+                 weights: Optional[Sequence[np.ndarray]] = None, data_dtype: str = "f32",
+                 precision: str = "f32", path: str = "auto", adaptive: bool = True,
+                 snapshot_mode: str = "copy", eps_th: float = 1e-4, gamma_th: float = 0.0,
+                 slope_window: int = 0):
+        self.lib = load_library()
+        p = len(dims)
+        self.dims = tuple(int(d) for d in dims)
+        self.data_dtype = data_dtype
+        cfg = TdbConfig()
+        cfg.order = p
+        for n in range(p):
+            cfg.dims[n] = int(dims[n])
+            cfg.rank_max[n] = int(rank_max[n])
+            cfg.rank_init[n] = int(rank_init[n]) if rank_init is not None else 0
+        self._w = []
+        if weights is not None:
+            for n in range(p):
+                arr = np.ascontiguousarray(weights[n], dtype=np.float64)
+                self._w.append(arr)
+                cfg.weights[n] = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        cfg.dt = float(dt)
+        cfg.data_dtype = F32 if data_dtype == "f32" else F64
+        cfg.precision = PREC_F32 if precision == "f32" else PREC_F64
+        cfg.path = {"auto": PATH_AUTO, "plain": PATH_PLAIN, "fused": PATH_FUSED}[path]
+        cfg.adaptive = 1 if adaptive else 0
+        cfg.snapshot_mode = BORROW if snapshot_mode == "borrow" else COPY
+        cfg.eps_th = float(eps_th)
+        cfg.gamma_th = float(gamma_th)
+        cfg.slope_window = int(slope_window)
+        self.cfg = cfg
+        self.h = ctypes.c_void_p()
+
+    # -- status handling
+    def _check(self, status: int):
+        if status != OK:
+            msg = self.lib.tdb_last_error(self.h if self.h else None)
+            raise TDBError(status, (msg or b"").decode())
+
+    def init(self, V0, stream=None):
+        st = self.lib.tdb_init(ctypes.byref(self.cfg), _dev_ptr(V0), _stream_ptr(stream),
+                               ctypes.byref(self.h))
+        self._check(st)
+        return self
+
+    def init_from_factors(self, V0, C: np.ndarray, U: List[np.ndarray], stream=None):
+        ranks = (ctypes.c_int32 * MAX_ORDER)(*([int(s) for s in C.shape] + [0] * (MAX_ORDER - C.ndim)))
+        Cc = np.ascontiguousarray(C, dtype=np.float64)
+        Us = [np.ascontiguousarray(u, dtype=np.float64) for u in U]
+        uptr = (ctypes.POINTER(ctypes.c_double) * MAX_ORDER)()
+        for n, u in enumerate(Us):
+            uptr[n] = u.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        st = self.lib.tdb_init_from_factors(ctypes.byref(self.cfg), _dev_ptr(V0), ranks,
+                                            Cc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), uptr,
+                                            _stream_ptr(stream), ctypes.byref(self.h))
+        self._check(st)
+        return self
+
+    def ingest(self, V, stream=None):
+        self._check(self.lib.tdb_ingest_snapshot(self.h, _dev_ptr(V), _stream_ptr(stream)))
+
+    def ranks(self):
+        r = (ctypes.c_int32 * MAX_ORDER)()
+        self._check(self.lib.tdb_get_core_and_bases(self.h, 0, r, None, None))
+        return tuple(r[: len(self.dims)])
+
+    def get_core_and_bases(self, rotate: bool = False):
+        r = self.ranks()
+        C = np.zeros(r, dtype=np.float64)
+        Us = [np.zeros((self.dims[n], r[n]), dtype=np.float64) for n in range(len(r))]
+        uptr = (ctypes.POINTER(ctypes.c_double) * MAX_ORDER)()
+        for n, u in enumerate(Us):
+            uptr[n] = u.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        rr = (ctypes.c_int32 * MAX_ORDER)()
+        self._check(self.lib.tdb_get_core_and_bases(self.h, 1 if rotate else 0, rr,
+                                                    C.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                    uptr))
+        return r, C, Us
+
+    def reconstruct(self, out=None, stream=None):
+        import torch
+        if out is None:
+            dt = torch.float32 if self.data_dtype == "f32" else torch.float64
+            out = torch.empty(self.dims, dtype=dt, device="cuda")
+        self._check(self.lib.tdb_reconstruct(self.h, _dev_ptr(out), _stream_ptr(stream)))
+        return out
+
+    def set_threshold(self, eps_th: float, gamma_th: float = 0.0):
+        self._check(self.lib.tdb_set_threshold(self.h, float(eps_th), float(gamma_th)))
+
+    def stats(self) -> dict:
+        s = TdbStats()
+        self._check(self.lib.tdb_get_stats(self.h, ctypes.byref(s)))
+        p = len(self.dims)
+        return {
+            "step": s.step, "t": s.t, "eps": s.eps, "nu": s.nu, "eps_after": s.eps_after,
+            "ranks": tuple(s.ranks[:p]), "event": EVENTS.get(s.event, str(s.event)),
+            "sigma": [list(s.sigma[n][: s.ranks[n]]) for n in range(p)], "cr": s.cr,
+            "crbar": s.crbar, "n_reinit": s.n_reinit, "n_add": s.n_add, "n_remove": s.n_remove,
+            "n_numeric": s.n_numeric,
+        }
+
+    def close(self):
+        if self.h:
+            self.lib.tdb_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
