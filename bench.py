@@ -1,0 +1,162 @@
+#!/usr/bin/env python3
+"""Throughput of the TDB in situ compressor on one MI355X.
+
+Workload (default): the reactive-flow-shaped stream, a 512 x 256 x 8 FP32 tensor
+(3 advected plumes with reaction fronts, 8 Arrhenius-scaled variables, 1e-6 noise),
+dt 5e-4, adaptive ranks from the rank rule with error threshold 1e-4 and caps
+(64, 64, 8). One step = one snapshot ingested: two Heun stages of the projection
+pass, the small FP64 work, the re-orthonormalisation, the weighted error pass and
+the controller (with any HOSVD reinitialisation it triggers).
+
+All snapshots of the run are generated on the device before timing (a ring far
+larger than the 256 MB last-level cache), so every stage pass streams its snapshot
+pair from HBM at least once. Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
+METRIC = "snapshots/s ingested + HBM GB/s vs plain FP64 GPU at <=1e-6 rel err"
+
+
+def _workload(args):
+    from streams import plume_spec
+    sp = plume_spec(steps=args.warmup + args.steps + 1)
+    desc = {"workload": "plume-512x256x8-fp32 (reactive-flow-shaped stream)",
+            "dims": list(sp.dims), "dt": sp.dt, "eps_th": sp.eps_th, "rank_max": [64, 64, 8],
+            "adaptive": True, "snapshot_storage": "f32", "noise": 1e-6}
+    return sp, desc
+
+
+def _make_snapshots(sp, n, device):
+    import torch
+    out = []
+    for k in range(n):
+        out.append(sp.snapshot(k, device=device))
+    torch.cuda.synchronize()
+    return out
+
+
+def _run_gpu(sp, snaps, warmup, steps, precision, path, profile=True):
+    import torch
+    from paper_2201_06958_amd import Compressor
+    cmp = Compressor(sp.dims, sp.dt, rank_max=(64, 64, 8), weights=sp.weights, data_dtype="f32",
+                     precision=precision, path=path, adaptive=True, snapshot_mode="borrow",
+                     eps_th=sp.eps_th)
+    cmp.init(snaps[0])
+    for k in range(1, warmup + 1):
+        cmp.ingest(snaps[k])
+    torch.cuda.synchronize()
+    if profile:
+        cmp.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(warmup + 1, warmup + steps + 1):
+        cmp.ingest(snaps[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = cmp.stats()
+    prof = {}
+    if profile:
+        prof = {"project": cmp.profile_read("project"), "error": cmp.profile_read("error")}
+    cmp.close()
+    return t1 - t0, st, prof
+
+
+def _cpu_baseline(sp, start, budget_s=15.0, max_steps=60):
+    """The FP64 numpy oracle on the host: init at snapshot `start`, then as many
+    steps as fit in the budget (bounded sample of the same workload)."""
+    import numpy as np
+    from oracle import tdb_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    cfg = O.OracleConfig(dims=sp.dims, weights=sp.weights, dt=sp.dt, rank_max=(64, 64, 8),
+                         rank_init=None, adaptive=True, eps_th=sp.eps_th)
+    o = O.OracleTDB(cfg).init(sp.snapshot_np(start).astype(np.float64), t0=sp.time(start))
+    n = 0
+    t0 = time.perf_counter()
+    while n < max_steps and time.perf_counter() - t0 < budget_s:
+        o.ingest(sp.snapshot_np(start + 1 + n).astype(np.float64))
+        n += 1
+    el = time.perf_counter() - t0
+    return {"value": n / el, "unit": "snapshots/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n} consecutive steps of the same stream after an HOSVD init at step {start} "
+                      f"(FP64 numpy oracle, {el:.1f} s, snapshot generation excluded)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--path", default="auto", choices=["auto", "plain", "fused"])
+    ap.add_argument("--plain-steps", type=int, default=200,
+                    help="steps of the plain FP64 GPU path timed for comparison (0 = skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, "
+              "'How the path would shard').", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    sp, desc = _workload(args)
+    print(f"[bench] generating {args.warmup + args.steps + 1} snapshots on the device", file=sys.stderr,
+          flush=True)
+    snaps = _make_snapshots(sp, args.warmup + args.steps + 1, "cuda")
+    print("[bench] timed run", file=sys.stderr, flush=True)
+    el, st, prof = _run_gpu(sp, snaps, args.warmup, args.steps, args.precision, args.path)
+    value = args.steps / el
+    pj = prof["project"]
+    avg_s = pj["total_ms"] / max(pj["launches"], 1) * 1e-3
+    achieved = pj["bytes_per_launch"] / avg_s / 1e9 if avg_s > 0 else 0.0
+    er = prof["error"]
+    er_avg_s = er["total_ms"] / max(er["launches"], 1) * 1e-3
+    plain = None
+    if args.plain_steps > 0:
+        print("[bench] plain FP64 GPU path", file=sys.stderr, flush=True)
+        n_pl = min(args.plain_steps, args.steps)
+        el_p, st_p, _ = _run_gpu(sp, snaps, args.warmup, n_pl, "f64", "plain", profile=False)
+        plain = {"value": n_pl / el_p, "unit": "snapshots/s", "steps": n_pl,
+                 "speedup": value / (n_pl / el_p)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = _cpu_baseline(sp, args.warmup)
+    line = {
+        "metric": METRIC, "value": value, "unit": "snapshots/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+        "config": dict(desc, path=args.path, precision=args.precision),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "stage projection pass (one Heun stage)",
+                     "avg_launch_us": avg_s * 1e6, "launches": pj["launches"],
+                     "algorithmic_bytes_per_launch": pj["bytes_per_launch"]},
+        "error_pass": {"avg_launch_us": er_avg_s * 1e6,
+                       "achieved_GBs": er["bytes_per_launch"] / er_avg_s / 1e9 if er_avg_s > 0 else 0.0},
+        "final_stats": {"ranks": st["ranks"], "eps": st["eps"], "crbar": st["crbar"],
+                        "n_add": st["n_add"], "n_reinit": st["n_reinit"], "n_remove": st["n_remove"]},
+        "plain_fp64_gpu": plain,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,98 @@
+// Argument blocks of the fused third-order path (internal).
+#pragma once
+#include "tdb_common.h"
+
+namespace tdb {
+
+#define FERR_T1 8   // mode-1 slabs per block of the error pass
+
+struct FPassArgs {
+  const void* V1;
+  const void* V0;
+  int N1, N2, N3, r1, r2, r3;
+  int T1, T2, nt1, nt2;
+  int need_h1, need_h2, need_f3;
+  long long slot;            // partial elements per tile
+  const void *B1, *B2, *B3;  // weighted bases, compute type, packed (ld = r)
+  const void *P1, *P2, *P3;  // pseudo-inverses, compute type
+  void* part;                // tiles x slot partials
+};
+
+struct FReduceArgs {
+  int stage;
+  double dt;
+  int N1, N2, N3, r1, r2, r3, T1, T2, nt1, nt2;
+  int need_h1, need_h2, need_f3;
+  long long slot;
+  const void* part;
+  double* H[3];
+  double* M[3];
+  double *C0, *Cs, *kC;
+};
+
+struct FFinishArgs {
+  int stage, rowblocks, core_in_lds;
+  double dt;
+  long long N[3];
+  int r[3], ldU[3];
+  const double* H[3];
+  const double* M[3];
+  const double* w[3];
+  double* U0[3];
+  double* Us[3];
+  double* kU[3];
+  void* B[3];
+  void* P[3];
+  const double* Cs;
+};
+
+struct FQrArgs {
+  long long N[3];
+  int r[3], ldU[3];
+  int u_in_lds[3];
+  double* U0[3];
+  const double* w[3];
+  double* Rq[3];
+  double* C0;
+  double* Ctmp;
+  unsigned* counter;
+};
+
+struct FPostArgs {
+  int eblocks, core_in_lds, want_pinv;
+  long long N[3];
+  int r[3], ldU[3];
+  const double* C;
+  const double* U[3];
+  const double* w[3];
+  void* B[3];
+  void* P[3];
+  void* E;                   // r1 x N2 x N3, compute type
+  void* U1c;                 // N1 x r1, compute type
+};
+
+struct FErrArgs {
+  const void* V;
+  int N1, r1, T1, gx, gy;
+  long long M;               // N2 * N3
+  const void* E;
+  const void* U1c;
+  const double* w1;
+  const double* w23;
+  double* part;
+  unsigned* counter;
+};
+
+template <typename TD, typename T>
+hipError_t launch_fpass(const FPassArgs& a, size_t lds, hipStream_t s);
+template <typename T>
+hipError_t launch_freduce(const FReduceArgs& a, CtrlState* c, hipStream_t s);
+template <typename T>
+hipError_t launch_ffinish(const FFinishArgs& a, size_t lds, CtrlState* c, hipStream_t s);
+hipError_t launch_fqr(const FQrArgs& a, size_t lds, CtrlState* c, hipStream_t s);
+template <typename T>
+hipError_t launch_fpost(const FPostArgs& a, size_t lds, CtrlState* c, hipStream_t s);
+template <typename TD, typename T>
+hipError_t launch_ferr(const FErrArgs& a, CtrlState* c, hipStream_t s);
+
+}  // namespace tdb

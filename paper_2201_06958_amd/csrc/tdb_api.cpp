@@ -3,6 +3,7 @@
 // (re)initialisation, and keeps the per-step statistics.
 #include "../../include/tdb.h"
 #include "tdb_kernels.h"
+#include "fused.h"
 
 #include <hip/hip_runtime.h>
 
@@ -65,8 +66,27 @@ struct tdb_ctx {
   double crbar_den = 0.0, t_now = 0.0;
   long long step = 0;
   bool ready = false;
+  // fused third-order path
+  bool fused = false;            // configuration allows the fused path
+  bool post_valid = false;       // B_n, P_n, E of the current state are prepared
+  int lds_max = 65536;
+  void* fpart = nullptr;
+  long long fpart_elems = 0;
+  double *Mred[TDB_P] = {}, *Rq[TDB_P] = {};
+  void *E = nullptr, *U1c = nullptr;
+  double *w23 = nullptr, *ferr_part = nullptr;
+  unsigned* counters = nullptr;
+  int ferr_gx = 1, ferr_gy = 1;
+  long long fused_steps = 0, plain_steps = 0;
+  // optional pass timing (events recorded on the caller's stream)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[2];
 
   ~tdb_ctx() {
+    for (auto& v : ev_used)
+      for (auto& e : v) { ev_pool.push_back(e.first); ev_pool.push_back(e.second); }
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* q : allocs) (void)hipFree(q);
     if (ctrl_h) (void)hipHostFree(ctrl_h);
   }
@@ -151,6 +171,46 @@ long long prod_ll(const int* a, int p, int skip = -1) {
     if (k != skip) q *= a[k];
   return q;
 }
+
+struct PassPlan {
+  int T1 = 1, T2 = 1, nt1 = 1, nt2 = 1;
+  long long slot = 0;
+  size_t lds = 0;
+  bool ok = false;
+};
+
+// Tile shape of the fused stage pass for ranks r: about `target` elements per tile,
+// shrunk until its LDS footprint fits.
+PassPlan plan_pass(const tdb_ctx* h, const int* r) {
+  PassPlan pl;
+  const long long N1 = h->N[0], N2 = h->N[1], N3 = h->N[2];
+  const int r1 = r[0], r2 = r[1], r3 = r[2];
+  const bool f3 = r3 < N3;
+  const size_t te = h->celt;
+  const long long target = h->f32 ? 4096 : 2048;
+  int T2 = (int)std::min<long long>(N2, 64);
+  int T1 = (int)std::max<long long>(1, std::min<long long>(N1, target / std::max<long long>(1, T2 * N3)));
+  auto lds_of = [&](int t1, int t2) {
+    long long e = (long long)t1 * t2 * N3 + (long long)t1 * t2 * r3 + (long long)t1 * r2 * r3 +
+                  (long long)r1 * t2 * r3 + 2LL * t1 * r1 + 2LL * t2 * r2 + 2LL * N3 * r3;
+    if (f3) e += (long long)t1 * r2 * N3 + (long long)r1 * r2 * N3;
+    return (size_t)e * te;
+  };
+  while (lds_of(T1, T2) > (size_t)h->lds_max && T1 > 1) T1 = std::max(1, T1 / 2);
+  while (lds_of(T1, T2) > (size_t)h->lds_max && T2 > 8) T2 = std::max(8, T2 / 2);
+  if (lds_of(T1, T2) > (size_t)h->lds_max) return pl;
+  pl.T1 = T1;
+  pl.T2 = T2;
+  pl.nt1 = (int)((N1 + T1 - 1) / T1);
+  pl.nt2 = (int)((N2 + T2 - 1) / T2);
+  pl.slot = (long long)T1 * r1 + (long long)T2 * r2 + N3 * r3 + (long long)r1 * r2 * r3 + (long long)r1 * r1 +
+            (long long)r2 * r2 + (long long)r3 * r3;
+  pl.lds = lds_of(T1, T2);
+  pl.ok = true;
+  return pl;
+}
+
+tdb_status setup_fused(tdb_ctx* h, const std::vector<std::vector<double>>& wh);
 
 tdb_status setup(tdb_ctx* h, const tdb_config* cfg) {
   h->cfg = *cfg;
@@ -270,6 +330,44 @@ tdb_status setup(tdb_ctx* h, const tdb_config* cfg) {
   c.eps_trig = cfg->eps_th;
   *h->ctrl_h = c;
   HIPCHK(hipMemcpy(h->ctrl, h->ctrl_h, sizeof(CtrlState), hipMemcpyHostToDevice));
+  TRY(setup_fused(h, wh));
+  return TDB_OK;
+}
+
+tdb_status setup_fused(tdb_ctx* h, const std::vector<std::vector<double>>& wh) {
+  h->fused = h->p == 3 && h->cfg.path != TDB_PATH_PLAIN;
+  if (!h->fused) return TDB_OK;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  int lds = 65536;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lds = 65536;
+  h->lds_max = lds;
+  // partial buffer: enough for the ranks-1 plan and the caps plan
+  int ones[3] = {1, 1, 1};
+  PassPlan p1 = plan_pass(h, ones), pc = plan_pass(h, h->caps);
+  long long tiles = std::max<long long>(p1.ok ? (long long)p1.nt1 * p1.nt2 : 1, pc.ok ? (long long)pc.nt1 * pc.nt2 : 1);
+  long long slot = pc.ok ? pc.slot : (p1.ok ? p1.slot : 1);
+  long long capslot = (long long)h->caps[0] * h->caps[1] * h->caps[2] + 3LL * 64 * 64 + 64 * (h->N[0] + h->N[1] + h->N[2]);
+  slot = std::max(slot, std::min(capslot, slot * 4));
+  h->fpart_elems = tiles * slot;
+  TRY(dalloc(h, &h->fpart, (size_t)h->fpart_elems * h->celt));
+  for (int n = 0; n < 3; ++n) {
+    TRY(dallocT(h, &h->Mred[n], (size_t)TDB_RCAP * TDB_RCAP));
+    TRY(dallocT(h, &h->Rq[n], (size_t)TDB_RCAP * TDB_RCAP));
+  }
+  TRY(dalloc(h, &h->E, (size_t)h->caps[0] * h->N[1] * h->N[2] * h->celt));
+  TRY(dalloc(h, &h->U1c, (size_t)h->N[0] * h->caps[0] * h->celt));
+  std::vector<double> w23((size_t)(h->N[1] * h->N[2]));
+  for (long long i = 0; i < h->N[1]; ++i)
+    for (long long j = 0; j < h->N[2]; ++j) w23[i * h->N[2] + j] = wh[1][i] * wh[2][j];
+  TRY(dallocT(h, &h->w23, w23.size()));
+  HIPCHK(hipMemcpy(h->w23, w23.data(), w23.size() * sizeof(double), hipMemcpyHostToDevice));
+  const long long M = h->N[1] * h->N[2];
+  h->ferr_gx = (int)std::max<long long>(1, std::min<long long>(64, (M + 255) / 256));
+  h->ferr_gy = (int)((h->N[0] + FERR_T1 - 1) / FERR_T1);
+  TRY(dallocT(h, &h->ferr_part, 2 * (size_t)h->ferr_gx * h->ferr_gy));
+  TRY(dalloc(h, reinterpret_cast<void**>(&h->counters), 4 * sizeof(unsigned)));
+  HIPCHK(hipMemset(h->counters, 0, 4 * sizeof(unsigned)));
   return TDB_OK;
 }
 
@@ -516,6 +614,36 @@ void fill_stats(tdb_ctx* h, bool initial) {
   st.n_numeric = c.n_events[EV_NUMERIC];
 }
 
+hipEvent_t take_event(tdb_ctx* h) {
+  if (!h->ev_pool.empty()) {
+    hipEvent_t e = h->ev_pool.back();
+    h->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets a pass with events when profiling is on.
+struct PassTimer {
+  tdb_ctx* h;
+  int pass;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  PassTimer(tdb_ctx* h_, int pass_, hipStream_t s_) : h(h_), pass(pass_), s(s_) {
+    if (!h->prof) return;
+    a = take_event(h);
+    b = take_event(h);
+    if (a && b) (void)hipEventRecord(a, s);
+  }
+  ~PassTimer() {
+    if (!a || !b) return;
+    (void)hipEventRecord(b, s);
+    h->ev_used[pass].push_back({a, b});
+  }
+};
+
 template <typename TD>
 tdb_status keep_previous(tdb_ctx* h, const TD* V, hipStream_t s) {
   if (h->cfg.snapshot_mode == TDB_COPY) {
@@ -551,12 +679,18 @@ tdb_status ingest_impl(tdb_ctx* h, const TD* V1, hipStream_t s) {
   }
   // stage 1 at S_k
   TRY(stage_prep<T>(h, h->C0, h->U0, s));
-  TRY((project_plain<TD, T>(h, V1, V0, s)));
+  {
+    PassTimer pt(h, TDB_PASS_PROJECT, s);
+    TRY((project_plain<TD, T>(h, V1, V0, s)));
+  }
   ra.stage = 1;
   HIPCHK(launch_rhs_stage(ra, h->ctrl, s));
   // stage 2 at S*
   TRY(stage_prep<T>(h, h->Cs, h->Us, s));
-  TRY((project_plain<TD, T>(h, V1, V0, s)));
+  {
+    PassTimer pt(h, TDB_PASS_PROJECT, s);
+    TRY((project_plain<TD, T>(h, V1, V0, s)));
+  }
   ra.stage = 2;
   HIPCHK(launch_rhs_stage(ra, h->ctrl, s));
   QrArgs qa{};
@@ -572,7 +706,10 @@ tdb_status ingest_impl(tdb_ctx* h, const TD* V1, hipStream_t s) {
   }
   HIPCHK(launch_qr_fold(qa, h->ctrl, s));
   TRY(core_sigma(h, false, s));
-  TRY((error_pass_plain<TD, T>(h, V1, s)));
+  {
+    PassTimer pt(h, TDB_PASS_ERROR, s);
+    TRY((error_pass_plain<TD, T>(h, V1, s)));
+  }
   HIPCHK(launch_controller(h->ctrl, s));
   TRY(pull_ctrl(h, s));
   h->step += 1;
@@ -589,8 +726,165 @@ tdb_status ingest_impl(tdb_ctx* h, const TD* V1, hipStream_t s) {
   return TDB_OK;
 }
 
+size_t small_lds(const tdb_ctx* h, bool* core_in_lds) {
+  const long long csz = prod_ll(h->r, h->p);
+  const size_t base = 2 * (size_t)TDB_RCAP * TDB_RCAP * 8;
+  *core_in_lds = base + (size_t)csz * 8 <= (size_t)h->lds_max;
+  return base + (*core_in_lds ? (size_t)csz * 8 : 0);
+}
+
+// Post-step preparation of the fused path at the committed state: core singular
+// values, B_n and P_n of the next stage 1, and the error-pass expansion E.
+template <typename T>
+tdb_status fused_post(tdb_ctx* h, hipStream_t s) {
+  FPostArgs pa{};
+  bool cil = false;
+  const size_t lds = small_lds(h, &cil);
+  pa.core_in_lds = cil ? 1 : 0;
+  pa.want_pinv = 1;
+  const long long etot = (long long)h->r[0] * h->N[1] * h->N[2];
+  pa.eblocks = (int)std::max<long long>(1, std::min<long long>(512, (etot + 255) / 256));
+  pa.C = h->C0;
+  pa.E = h->E;
+  pa.U1c = h->U1c;
+  for (int n = 0; n < 3; ++n) {
+    pa.N[n] = h->N[n];
+    pa.r[n] = h->r[n];
+    pa.ldU[n] = h->ldU[n];
+    pa.U[n] = h->U0[n];
+    pa.w[n] = h->w[n];
+    pa.B[n] = h->B[n];
+    pa.P[n] = h->P[n];
+  }
+  HIPCHK(launch_fpost<T>(pa, lds, h->ctrl, s));
+  h->post_valid = true;
+  return TDB_OK;
+}
+
+template <typename TD, typename T>
+tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
+  const TD* V0 = static_cast<const TD*>(h->Vprev);
+  const PassPlan pl = plan_pass(h, h->r);
+  if (!pl.ok || (long long)pl.nt1 * pl.nt2 * pl.slot > h->fpart_elems) {
+    h->post_valid = false;
+    h->plain_steps += 1;
+    return ingest_impl<TD, T>(h, V1, s);
+  }
+  h->fused_steps += 1;
+  if (!h->post_valid) TRY(fused_post<T>(h, s));
+  FPassArgs fa{};
+  fa.V1 = V1;
+  fa.V0 = V0;
+  fa.N1 = (int)h->N[0]; fa.N2 = (int)h->N[1]; fa.N3 = (int)h->N[2];
+  fa.r1 = h->r[0]; fa.r2 = h->r[1]; fa.r3 = h->r[2];
+  fa.T1 = pl.T1; fa.T2 = pl.T2; fa.nt1 = pl.nt1; fa.nt2 = pl.nt2;
+  fa.need_h1 = h->r[0] < h->N[0];
+  fa.need_h2 = h->r[1] < h->N[1];
+  fa.need_f3 = h->r[2] < h->N[2];
+  fa.slot = pl.slot;
+  fa.B1 = h->B[0]; fa.B2 = h->B[1]; fa.B3 = h->B[2];
+  fa.P1 = h->P[0]; fa.P2 = h->P[1]; fa.P3 = h->P[2];
+  fa.part = h->fpart;
+  FReduceArgs ra{};
+  ra.dt = h->cfg.dt;
+  ra.N1 = fa.N1; ra.N2 = fa.N2; ra.N3 = fa.N3; ra.r1 = fa.r1; ra.r2 = fa.r2; ra.r3 = fa.r3;
+  ra.T1 = pl.T1; ra.T2 = pl.T2; ra.nt1 = pl.nt1; ra.nt2 = pl.nt2;
+  ra.need_h1 = fa.need_h1; ra.need_h2 = fa.need_h2; ra.need_f3 = fa.need_f3;
+  ra.slot = pl.slot;
+  ra.part = h->fpart;
+  ra.C0 = h->C0; ra.Cs = h->Cs; ra.kC = h->kC;
+  FFinishArgs ga{};
+  bool cil = false;
+  const size_t slds = small_lds(h, &cil);
+  ga.core_in_lds = cil ? 1 : 0;
+  ga.dt = h->cfg.dt;
+  long long rows = 0;
+  for (int n = 0; n < 3; ++n) rows += h->N[n] * h->r[n];
+  ga.rowblocks = (int)std::max<long long>(1, std::min<long long>(1024, (rows + 255) / 256));
+  ga.Cs = h->Cs;
+  for (int n = 0; n < 3; ++n) {
+    ra.H[n] = h->H[n];
+    ra.M[n] = h->Mred[n];
+    ga.N[n] = h->N[n];
+    ga.r[n] = h->r[n];
+    ga.ldU[n] = h->ldU[n];
+    ga.H[n] = h->H[n];
+    ga.M[n] = h->Mred[n];
+    ga.w[n] = h->w[n];
+    ga.U0[n] = h->U0[n];
+    ga.Us[n] = h->Us[n];
+    ga.kU[n] = h->kU[n];
+    ga.B[n] = h->B[n];
+    ga.P[n] = h->P[n];
+  }
+  for (int stage = 1; stage <= 2; ++stage) {
+    {
+      PassTimer pt(h, TDB_PASS_PROJECT, s);
+      HIPCHK((launch_fpass<TD, T>(fa, pl.lds, s)));
+    }
+    ra.stage = stage;
+    HIPCHK(launch_freduce<T>(ra, h->ctrl, s));
+    ga.stage = stage;
+    HIPCHK(launch_ffinish<T>(ga, slds, h->ctrl, s));
+  }
+  FQrArgs qa{};
+  size_t qlds = 3 * (size_t)TDB_RCAP * TDB_RCAP * 8;
+  size_t ustage = 0;
+  for (int n = 0; n < 3; ++n) {
+    const size_t need = (size_t)h->N[n] * h->r[n] * 8;
+    qa.u_in_lds[n] = qlds + need <= (size_t)h->lds_max ? 1 : 0;
+    if (qa.u_in_lds[n]) ustage = std::max(ustage, need);
+    qa.N[n] = h->N[n];
+    qa.r[n] = h->r[n];
+    qa.ldU[n] = h->ldU[n];
+    qa.U0[n] = h->U0[n];
+    qa.w[n] = h->w[n];
+    qa.Rq[n] = h->Rq[n];
+  }
+  qa.C0 = h->C0;
+  qa.Ctmp = h->Ctmp;
+  qa.counter = h->counters;
+  HIPCHK(launch_fqr(qa, qlds + ustage, h->ctrl, s));
+  TRY(fused_post<T>(h, s));
+  FErrArgs ea{};
+  ea.V = V1;
+  ea.N1 = (int)h->N[0];
+  ea.r1 = h->r[0];
+  ea.T1 = FERR_T1;
+  ea.gx = h->ferr_gx;
+  ea.gy = h->ferr_gy;
+  ea.M = h->N[1] * h->N[2];
+  ea.E = h->E;
+  ea.U1c = h->U1c;
+  ea.w1 = h->w[0];
+  ea.w23 = h->w23;
+  ea.part = h->ferr_part;
+  ea.counter = h->counters + 1;
+  {
+    PassTimer pt(h, TDB_PASS_ERROR, s);
+    HIPCHK((launch_ferr<TD, T>(ea, h->ctrl, s)));
+  }
+  TRY(pull_ctrl(h, s));
+  h->step += 1;
+  h->t_now = h->step * h->cfg.dt;
+  const int dec = h->ctrl_h->decision;
+  if (dec != DEC_NONE) {
+    TRY(hosvd_select<TD>(h, V1, dec, s));
+    TRY(pull_ctrl(h, s));
+    TRY(fused_post<T>(h, s));
+    TRY(pull_ctrl(h, s));
+  }
+  TRY(keep_previous<TD>(h, V1, s));
+  fill_stats(h, false);
+  return TDB_OK;
+}
+
 template <typename TD>
 tdb_status ingest_dispatch(tdb_ctx* h, const void* V, hipStream_t s) {
+  if (h->fused) {
+    if (h->f32) return ingest_fused<TD, float>(h, static_cast<const TD*>(V), s);
+    return ingest_fused<TD, double>(h, static_cast<const TD*>(V), s);
+  }
   if (h->f32) return ingest_impl<TD, float>(h, static_cast<const TD*>(V), s);
   return ingest_impl<TD, double>(h, static_cast<const TD*>(V), s);
 }
@@ -816,6 +1110,35 @@ void tdb_destroy(tdb_handle h) {
   if (!h) return;
   (void)hipDeviceSynchronize();
   delete h;
+}
+
+tdb_status tdb_profile_enable(tdb_handle h, int32_t on) {
+  if (!h) { g_create_error = "handle is NULL"; return TDB_EINVAL; }
+  HIPCHK(hipDeviceSynchronize());
+  for (auto& v : h->ev_used) {
+    for (auto& e : v) { h->ev_pool.push_back(e.first); h->ev_pool.push_back(e.second); }
+    v.clear();
+  }
+  h->prof = on != 0;
+  return TDB_OK;
+}
+
+tdb_status tdb_profile_read(tdb_handle h, int32_t pass, int64_t* launches, double* total_ms,
+                            double* bytes_per_launch) {
+  if (!h) { g_create_error = "handle is NULL"; return TDB_EINVAL; }
+  if (pass != TDB_PASS_PROJECT && pass != TDB_PASS_ERROR) { h->err = "bad pass id"; return TDB_EINVAL; }
+  double ms = 0.0;
+  for (auto& e : h->ev_used[pass]) {
+    HIPCHK(hipEventSynchronize(e.second));
+    float x = 0.0f;
+    HIPCHK(hipEventElapsedTime(&x, e.first, e.second));
+    ms += x;
+  }
+  if (launches) *launches = (int64_t)h->ev_used[pass].size();
+  if (total_ms) *total_ms = ms;
+  if (bytes_per_launch)
+    *bytes_per_launch = (double)h->S * (double)h->delt * (pass == TDB_PASS_PROJECT ? 2.0 : 1.0);
+  return TDB_OK;
 }
 
 void tdb_struct_sizes(int64_t* config_bytes, int64_t* stats_bytes) {

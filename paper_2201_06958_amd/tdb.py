@@ -103,6 +103,11 @@ def load_library(path: str = LIB_PATH):
     lib.tdb_destroy.restype = None
     lib.tdb_last_error.argtypes = [H]
     lib.tdb_last_error.restype = ctypes.c_char_p
+    lib.tdb_profile_enable.argtypes = [H, ctypes.c_int32]
+    lib.tdb_profile_enable.restype = ctypes.c_int32
+    lib.tdb_profile_read.argtypes = [H, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.tdb_profile_read.restype = ctypes.c_int32
     lib.tdb_struct_sizes.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     lib.tdb_struct_sizes.restype = None
     for name in ("tdb_init", "tdb_init_from_factors", "tdb_ingest_snapshot", "tdb_get_core_and_bases",
@@ -234,6 +239,16 @@ class Compressor:
             "crbar": s.crbar, "n_reinit": s.n_reinit, "n_add": s.n_add, "n_remove": s.n_remove,
             "n_numeric": s.n_numeric,
         }
+
+    def profile_enable(self, on: bool = True):
+        self._check(self.lib.tdb_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self, pass_name: str = "project") -> dict:
+        n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        pid = {"project": 0, "error": 1}[pass_name]
+        self._check(self.lib.tdb_profile_read(self.h, pid, ctypes.byref(n), ctypes.byref(ms),
+                                              ctypes.byref(by)))
+        return {"launches": n.value, "total_ms": ms.value, "bytes_per_launch": by.value}
 
     def close(self):
         if self.h:

@@ -13,7 +13,8 @@ import numpy as np
 import pytest
 
 from oracle import tdb_oracle as O
-from streams import (analytic_cp5_spec, lowrank_manifold_spec, plume_spec, switched_term_spec)
+from streams import (analytic_cp5_spec, fourier_ensemble_specs, lowrank_manifold_spec, plume_spec,
+                     switched_term_spec)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -57,14 +58,15 @@ def _gpu():
     load_library()
 
 
-def test_analytic_plain_fp64_full_run_from_identical_factors():
+@pytest.mark.parametrize("path", ["plain", "fused"])
+def test_analytic_fp64_full_run_from_identical_factors(path):
     """64^3 analytic stream, fixed ranks (5,5,5), 200 Heun steps: every core entry,
     basis entry and error matches the oracle to 1e-10 relative."""
     sp = analytic_cp5_spec()
-    _say("case analytic-cp5 64^3 fp64 plain, 200 steps")
+    _say(f"case analytic-cp5 64^3 fp64 {path}, 200 steps")
     snaps = [sp.snapshot_np(k) for k in range(sp.steps + 1)]
     orc = O.OracleTDB(_ocfg(sp)).init(snaps[0])
-    g = _cmp_cfg(sp, path="plain")
+    g = _cmp_cfg(sp, path=path)
     g.init_from_factors(_dev(snaps[0]), orc.C, orc.U)
     for k in range(1, sp.steps + 1):
         rec = orc.ingest(snaps[k])
@@ -108,12 +110,15 @@ def test_hosvd_init_matches_oracle():
     g.close()
 
 
+@pytest.mark.parametrize("path", ["plain", "fused"])
 @pytest.mark.parametrize("dims,ranks", [((20, 17, 9), (3, 4, 2)), ((33, 8), (3, 3)),
-                                        ((9, 7, 6, 5), (2, 3, 2, 2)), ((16, 12, 3), (4, 3, 3))])
-def test_random_weighted_streams_fp64(dims, ranks):
+                                        ((9, 7, 6, 5), (2, 3, 2, 2)), ((16, 12, 3), (4, 3, 3)),
+                                        ((70, 130, 5), (6, 5, 4))])
+def test_random_weighted_streams_fp64(dims, ranks, path):
     """Random non-uniform weights, random snapshots around a low-rank base, orders 2
-    to 4, a full-rank mode in one case: raw state parity step by step."""
-    _say(f"case random fp64 dims {dims} ranks {ranks}")
+    to 4 (the fused path covers order 3; other orders run the plain path), a
+    full-rank mode, ragged tiles in both tiled modes: raw state parity per step."""
+    _say(f"case random fp64 dims {dims} ranks {ranks} {path}")
     rng = np.random.default_rng(sum(dims))
     w = []
     for n in dims:
@@ -126,7 +131,7 @@ def test_random_weighted_streams_fp64(dims, ranks):
     orc = O.OracleTDB(cfg).init(snaps[0])
     from paper_2201_06958_amd import Compressor
     g = Compressor(dims, 0.05, rank_max=ranks, rank_init=ranks, weights=w, data_dtype="f64",
-                   precision="f64", adaptive=False, path="plain", eps_th=1.0)
+                   precision="f64", adaptive=False, path=path, eps_th=1.0)
     g.init_from_factors(_dev(snaps[0]), orc.C, orc.U)
     for k in range(1, 8):
         rec = orc.ingest(snaps[k])
@@ -159,7 +164,8 @@ def test_reconstruct_and_rotation():
     g.close()
 
 
-def test_controller_add_and_remove_decisions_match():
+@pytest.mark.parametrize("path", ["plain", "fused"])
+def test_controller_add_and_remove_decisions_match(path):
     """Closed-form switched stream: the add fires on the same step as in the oracle,
     ranks grow to (4,4,4), then the removal fires on the same step."""
     t_on, t_peak, t_low, h_min = 0.05, 0.15, 0.35, 0.002
@@ -177,10 +183,10 @@ def test_controller_add_and_remove_decisions_match():
         return 0.004 * math.exp(-t)
 
     sp = switched_term_spec(steps=140, profile=h, profile2=gfun)
-    _say("case controller switched-term 140 steps")
+    _say(f"case controller switched-term 140 steps {path}")
     snaps = [sp.snapshot_np(k) for k in range(sp.steps + 1)]
     orc = O.OracleTDB(_ocfg(sp)).init(snaps[0])
-    g = _cmp_cfg(sp, path="plain")
+    g = _cmp_cfg(sp, path=path)
     g.init(_dev(snaps[0]))
     assert g.ranks() == orc.ranks
     ev_o, ev_g = [], []
@@ -198,14 +204,17 @@ def test_controller_add_and_remove_decisions_match():
     g.close()
 
 
-def test_plume_fp32_against_oracle():
-    """Reactive-flow-shaped stream at 128 x 64 x 8 (same generator), FP32 data and
-    FP32 bulk passes, adaptive from the rank rule: reconstruction and eps vs oracle."""
-    sp = plume_spec(nx=128, ny=64, nv=8, steps=30)
-    _say("case plume 128x64x8 fp32 adaptive 30 steps")
+@pytest.mark.parametrize("path,nx,ny,steps", [("plain", 128, 64, 30), ("fused", 128, 64, 30),
+                                              ("fused", 512, 256, 20)])
+def test_plume_fp32_against_oracle(path, nx, ny, steps):
+    """Reactive-flow-shaped stream (same generator; 512 x 256 x 8 is the full size),
+    FP32 data and FP32 bulk passes, adaptive from the rank rule: reconstruction and
+    eps vs the FP64 oracle within the 1e-6 FP32 bar."""
+    sp = plume_spec(nx=nx, ny=ny, nv=8, steps=steps)
+    _say(f"case plume {nx}x{ny}x8 fp32 adaptive {steps} steps {path}")
     snaps = [sp.snapshot_np(k) for k in range(sp.steps + 1)]
     orc = O.OracleTDB(_ocfg(sp, rank_max=(32, 32, 8))).init(snaps[0].astype(np.float64))
-    g = _cmp_cfg(sp, precision="f32", rank_max=(32, 32, 8), path="plain")
+    g = _cmp_cfg(sp, precision="f32", rank_max=(32, 32, 8), path=path)
     g.init(_dev(snaps[0]))
     assert g.ranks() == orc.ranks
     worst = 0.0
@@ -220,5 +229,29 @@ def test_plume_fp32_against_oracle():
     rec_g = O.reconstruct(C, U)
     rel = _rel(rec_g, orc.reconstruct())
     _say(f"  fp32 plume: reconstruction rel diff {rel:.3e}, worst eps diff / nu {worst:.3e}")
+    assert rel < 1e-6
+    g.close()
+
+
+@pytest.mark.parametrize("path", ["plain", "fused"])
+def test_ensemble_member_fp32_against_oracle(path):
+    """One stream of the batched ensemble (uneven grid, 4 variables, exactly low rank
+    <= 17 per spatial mode, caps 24, threshold 1e-5): FP32 path vs FP64 oracle."""
+    sp = fourier_ensemble_specs(n_streams=3, steps=12)[2]
+    _say(f"case ensemble member {sp.dims} fp32 {path}")
+    snaps = [sp.snapshot_np(k) for k in range(sp.steps + 1)]
+    orc = O.OracleTDB(_ocfg(sp)).init(snaps[0].astype(np.float64))
+    g = _cmp_cfg(sp, precision="f32", path=path)
+    g.init(_dev(snaps[0]))
+    assert g.ranks() == orc.ranks
+    for k in range(1, sp.steps + 1):
+        rec = orc.ingest(snaps[k].astype(np.float64))
+        g.ingest(_dev(snaps[k]))
+        st = g.stats()
+        assert st["event"] == rec.event, k
+        assert abs(st["eps"] - rec.eps) <= 1e-6 * rec.nu, k
+    r, C, U = g.get_core_and_bases()
+    rel = _rel(O.reconstruct(C, U), orc.reconstruct())
+    _say(f"  ensemble member: ranks {r}, reconstruction rel diff {rel:.3e}")
     assert rel < 1e-6
     g.close()
