@@ -12,6 +12,14 @@ static __device__ void jacobi_lds(double* A, double* V, int rn, int* pairs) {
   __shared__ int rotated;
   __shared__ double cs[TDB_RCAP], sn[TDB_RCAP];
   const int m = rn + (rn & 1);               // even size with a dummy index
+  __shared__ double dmax_l;
+  if (threadIdx.x == 0) {
+    double mx = 0.0;
+    for (int i = 0; i < rn; ++i) mx = fmax(mx, fabs(A[i * rn + i]));
+    dmax_l = mx;
+  }
+  __syncthreads();
+  const double tol = TDB_JACOBI_TOL * dmax_l;
   if (V)
     for (int t = threadIdx.x; t < rn * rn; t += blockDim.x) V[t] = (t / rn == t % rn) ? 1.0 : 0.0;
   __syncthreads();
@@ -31,7 +39,7 @@ static __device__ void jacobi_lds(double* A, double* V, int rn, int* pairs) {
         if (q_ < rn) {
           const double apq = A[p_ * rn + q_];
           const double app = A[p_ * rn + p_], aqq = A[q_ * rn + q_];
-          if (fabs(apq) > 1e-300 && fabs(apq) > 1e-17 * sqrt(fabs(app * aqq))) {
+          if (fabs(apq) > 1e-300 && fabs(apq) > tol) {
             const double theta = (aqq - app) / (2.0 * apq);
             const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
             c = 1.0 / sqrt(tt * tt + 1.0);
@@ -77,6 +85,69 @@ static __device__ void jacobi_lds(double* A, double* V, int rn, int* pairs) {
 
 static __device__ void jacobi_values(double* A, int rn, int* pairs) { jacobi_lds(A, nullptr, rn, pairs); }
 
+// Eigenvalues of a symmetric rn x rn LDS matrix (rn <= 64) by cyclic Jacobi run by one
+// wave (lanes 0..63 of the calling block, all of which must call it): round-robin
+// pairing, rotations computed by one lane per pair, row and column updates spread
+// over the lanes. Only wave-level ordering is needed, so no block barriers.
+static __device__ void jacobi_wave(double* A, int rn, int* pairs) {
+  __shared__ double cs_w[TDB_RCAP], sn_w[TDB_RCAP];
+  __shared__ int rot_w;
+  const int lane = threadIdx.x & 63;
+  const int m = rn + (rn & 1);
+  double mx = 0.0;
+  for (int i = lane; i < rn; i += 64) mx = fmax(mx, fabs(A[i * rn + i]));
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  const double tol = TDB_JACOBI_TOL * mx;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (lane == 0) rot_w = 0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    for (int round = 0; round < m - 1; ++round) {
+      for (int k = lane; k < m / 2; k += 64) {
+        int p_, q_;
+        if (k == 0) { p_ = m - 1; q_ = round; }
+        else { p_ = (round + k) % (m - 1); q_ = (round - k + (m - 1)) % (m - 1); }
+        if (p_ > q_) { const int t = p_; p_ = q_; q_ = t; }
+        pairs[2 * k] = p_;
+        pairs[2 * k + 1] = q_;
+        double c = 1.0, s = 0.0;
+        if (q_ < rn) {
+          const double apq = A[p_ * rn + q_];
+          const double app = A[p_ * rn + p_], aqq = A[q_ * rn + q_];
+          if (fabs(apq) > 1e-300 && fabs(apq) > tol) {
+            const double theta = (aqq - app) / (2.0 * apq);
+            const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(tt * tt + 1.0);
+            s = tt * c;
+            rot_w = 1;
+          }
+        }
+        cs_w[k] = c;
+        sn_w[k] = s;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      for (int t = lane; t < (m / 2) * rn; t += 64) {
+        const int k = t / rn, col = t % rn;
+        const int p_ = pairs[2 * k], q_ = pairs[2 * k + 1];
+        if (q_ >= rn || sn_w[k] == 0.0) continue;
+        const double ap = A[p_ * rn + col], aq = A[q_ * rn + col];
+        A[p_ * rn + col] = cs_w[k] * ap - sn_w[k] * aq;
+        A[q_ * rn + col] = sn_w[k] * ap + cs_w[k] * aq;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      for (int t = lane; t < (m / 2) * rn; t += 64) {
+        const int k = t / rn, row = t % rn;
+        const int p_ = pairs[2 * k], q_ = pairs[2 * k + 1];
+        if (q_ >= rn || sn_w[k] == 0.0) continue;
+        const double ap = A[row * rn + p_], aq = A[row * rn + q_];
+        A[row * rn + p_] = cs_w[k] * ap - sn_w[k] * aq;
+        A[row * rn + q_] = sn_w[k] * ap + cs_w[k] * aq;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    }
+    if (!rot_w) break;
+  }
+}
+
 // ---------------------------------------------------------------- controller
 // Single thread (called by one thread): reads eps^2, nu^2 of the error pass and decides the step's event
 // (Sec. 2.5): an add when eps exceeds the trigger, a removal check when the error
@@ -111,5 +182,192 @@ static __device__ void controller_decide(CtrlState* c) {
   }
 }
 
+
+}  // namespace tdb
+
+namespace tdb {
+
+// ===================================================================== one-wave kernels
+// The routines below are run by one full wave (64 lanes) of the calling block on small
+// (rn <= 64) row-major matrices in LDS. Lanes own rows or columns; ordering between
+// lanes only needs wave-level memory ordering, so no block barriers are used.
+__device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// In-place lower Cholesky factor of the SPD matrix A (lane i owns row i). Returns false
+// if a pivot is not positive or is below TDB_PIVOT_FLOOR times the largest diagonal.
+static __device__ bool wave_chol(double* A, int rn) {
+  const int i = threadIdx.x & 63;
+  const double dmax = wave_max_d(i < rn ? A[i * rn + i] : 0.0);
+  bool bad = false;
+  for (int k = 0; k < rn; ++k) {
+    const double piv = A[k * rn + k];
+    bad = bad || !(piv > TDB_PIVOT_FLOOR * dmax) || !(piv > 0.0);
+    const double lkk = sqrt(fmax(piv, 1e-300));
+    wave_fence();
+    if (i == k) A[k * rn + k] = lkk;
+    if (i > k && i < rn) A[i * rn + k] /= lkk;
+    wave_fence();
+    if (i > k && i < rn) {
+      const double lik = A[i * rn + k];
+      double* ai = A + i * rn;
+#pragma unroll 4
+      for (int j = k + 1; j <= i; ++j) ai[j] -= lik * A[j * rn + k];
+    }
+    wave_fence();
+  }
+  if (i < rn)
+    for (int j = i + 1; j < rn; ++j) A[i * rn + j] = 0.0;
+  wave_fence();
+  return !bad;
+}
+
+// Li = L^-1 for a lower-triangular L (lane j computes column j).
+static __device__ void wave_tri_inv(const double* L, double* Li, int rn) {
+  const int j = threadIdx.x & 63;
+  if (j < rn) {
+    for (int i = 0; i < j; ++i) Li[i * rn + j] = 0.0;
+    Li[j * rn + j] = 1.0 / L[j * rn + j];
+    for (int i = j + 1; i < rn; ++i) {
+      double s = 0.0;
+      for (int k = j; k < i; ++k) s += L[i * rn + k] * Li[k * rn + j];
+      Li[i * rn + j] = -s / L[i * rn + i];
+    }
+  }
+  wave_fence();
+}
+
+// Gi = Li^T Li (the inverse of L L^T), lanes over entries.
+static __device__ void wave_inv_from_linv(const double* Li, double* Gi, int rn) {
+  const int lane = threadIdx.x & 63;
+  for (int t = lane; t < rn * rn; t += 64) {
+    const int i = t / rn, j = t - (t / rn) * rn;
+    double s = 0.0;
+    for (int k = (i > j ? i : j); k < rn; ++k) s += Li[k * rn + i] * Li[k * rn + j];
+    Gi[t] = s;
+  }
+  wave_fence();
+}
+
+// Eigenvalues of the symmetric matrix A (destroyed), descending, into lam[0..rn):
+// Householder reduction to tridiagonal form (lane i owns row i of the trailing block),
+// then bisection on Sturm counts with one eigenvalue per lane. ws: LDS scratch of
+// 4*rn doubles.
+static __device__ void wave_eigvals(double* A, int rn, double* lam, double* ws) {
+  const int lane = threadIdx.x & 63;
+  double* d = ws;
+  double* e2 = ws + rn;
+  double* v = ws + 2 * rn;
+  double* wv = ws + 3 * rn;
+  for (int k = 0; k + 2 < rn; ++k) {
+    const int m = rn - k - 1;
+    const double x = lane < m ? A[(k + 1 + lane) * rn + k] : 0.0;
+    const double ss = wave_sum_d(x * x);
+    const double x0 = __shfl(x, 0, 64);
+    double bk = 0.0, ek = x0;
+    double vi = x;
+    if (ss > 0.0) {
+      const double xn = sqrt(ss);
+      const double alpha = x0 > 0.0 ? -xn : xn;
+      const double v0 = x0 - alpha;
+      bk = 2.0 / (ss - x0 * x0 + v0 * v0);
+      ek = alpha;
+      if (lane == 0) vi = v0;
+    }
+    if (lane == 0) { d[k] = A[k * rn + k]; e2[k] = ek * ek; }
+    if (lane < m) v[lane] = vi;
+    wave_fence();
+    if (bk != 0.0) {
+      double p = 0.0;
+      if (lane < m) {
+        const double* row = A + (k + 1 + lane) * rn + (k + 1);
+        for (int j = 0; j < m; ++j) p += row[j] * v[j];
+        p *= bk;
+      }
+      const double Kc = 0.5 * bk * wave_sum_d(lane < m ? p * vi : 0.0);
+      if (lane < m) wv[lane] = p - Kc * vi;
+      wave_fence();
+      if (lane < m) {
+        double* row = A + (k + 1 + lane) * rn + (k + 1);
+        const double wi = wv[lane];
+        for (int j = 0; j < m; ++j) row[j] -= vi * wv[j] + wi * v[j];
+      }
+      wave_fence();
+    }
+  }
+  if (lane == 0) {
+    if (rn >= 2) {
+      d[rn - 2] = A[(rn - 2) * rn + (rn - 2)];
+      const double el = A[(rn - 1) * rn + (rn - 2)];
+      e2[rn - 2] = el * el;
+    }
+    d[rn - 1] = A[(rn - 1) * rn + (rn - 1)];
+  }
+  wave_fence();
+  // Gershgorin interval
+  double lo = 1e300, hi = -1e300, mx = 0.0, me = 0.0;
+  for (int i = lane; i < rn; i += 64) {
+    const double off = (i > 0 ? sqrt(e2[i - 1]) : 0.0) + (i + 1 < rn ? sqrt(e2[i]) : 0.0);
+    lo = fmin(lo, d[i] - off);
+    hi = fmax(hi, d[i] + off);
+    mx = fmax(mx, fabs(d[i]) + off);
+    if (i + 1 < rn) me = fmax(me, e2[i]);
+  }
+  lo = -wave_max_d(-lo);
+  hi = wave_max_d(hi);
+  mx = wave_max_d(mx);
+  me = wave_max_d(me);
+  const double eps = 2.220446049250313e-16;
+  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, me);
+  lo -= 4.0 * eps * mx + 2.0 * pivmin;
+  hi += 4.0 * eps * mx + 2.0 * pivmin;
+  // multisection: L lanes per eigenvalue evaluate Sturm counts at L interior points
+  int L = 1;
+  while (L < 16 && (2 * L) * rn <= 64) L *= 2;
+  const int e = lane / L, sub = lane - (lane / L) * L;
+  const int idx = rn - 1 - e;               // ascending index of the e-th largest
+  double a = lo, b = hi;
+  const double invL1 = 1.0 / (double)(L + 1);
+  int its = 1;
+  {
+    int bits = 0;
+    for (int q = L + 1; q > 1; q >>= 1) ++bits;      // floor(log2(L+1)) bits per round
+    its = (56 + bits - 1) / bits + 1;
+  }
+  for (int it = 0; it < its; ++it) {
+    const double x = a + (b - a) * ((double)(sub + 1) * invL1);
+    int c = 0;
+    if (e < rn) {
+      double q = d[0] - x;
+      if (fabs(q) < pivmin) q = -pivmin;
+      c += q < 0.0;
+      for (int i = 1; i < rn; ++i) {
+        double r0 = __builtin_amdgcn_rcp(q);
+        r0 = r0 * (2.0 - q * r0);
+        r0 = r0 * (2.0 - q * r0);
+        q = d[i] - x - e2[i - 1] * r0;
+        if (fabs(q) < pivmin) q = -pivmin;
+        c += q < 0.0;
+      }
+    }
+    const unsigned long long mask = __ballot(c > idx);
+    const unsigned grp = (unsigned)((mask >> (e * L)) & ((L == 64) ? ~0ull : ((1ull << L) - 1ull)));
+    const int f = grp ? __builtin_ctz(grp) : L;   // first sub-point above the target
+    const double na = (f == 0) ? a : a + (b - a) * ((double)f * invL1);
+    const double nb = (f == L) ? b : a + (b - a) * ((double)(f + 1) * invL1);
+    a = na;
+    b = nb;
+  }
+  if (e < rn && sub == 0) lam[e] = 0.5 * (a + b);
+  wave_fence();
+}
 
 }  // namespace tdb

@@ -12,6 +12,7 @@ struct FPassArgs {
   int N1, N2, N3, r1, r2, r3;
   int T1, T2, nt1, nt2;
   int need_h1, need_h2, need_f3;
+  int stage_p;               // pseudo-inverses staged in LDS
   long long slot;            // partial elements per tile
   const void *B1, *B2, *B3;  // weighted bases, compute type, packed (ld = r)
   const void *P1, *P2, *P3;  // pseudo-inverses, compute type
@@ -26,27 +27,29 @@ struct FReduceArgs {
   long long slot;
   const void* part;
   double* H[3];
-  double* M[3];
-  double *C0, *Cs, *kC;
+  double *C0, *Cs, *kC, *Cdot2;
 };
 
 struct FFinishArgs {
-  int stage, rowblocks, core_in_lds;
+  int stage, rowblocks, core_in_lds, rmax;
   double dt;
   long long N[3];
   int r[3], ldU[3];
   const double* H[3];
-  const double* M[3];
+  const void* Pcur[3];       // pseudo-inverses used by this stage's pass
   const double* w[3];
   double* U0[3];
   double* Us[3];
   double* kU[3];
   void* B[3];
-  void* P[3];
+  void* P[3];                // stage 1 only: pseudo-inverses of the stage-2 core
   const double* Cs;
+  const double* kC;          // C_dot of stage 1
+  const double* Cdot2;       // C_dot of stage 2
 };
 
 struct FQrArgs {
+  int core_in_lds, rmax, rounds;
   long long N[3];
   int r[3], ldU[3];
   int u_in_lds[3];
@@ -59,7 +62,7 @@ struct FQrArgs {
 };
 
 struct FPostArgs {
-  int eblocks, core_in_lds, want_pinv;
+  int eblocks, core_in_lds, want_pinv, rmax;
   long long N[3];
   int r[3], ldU[3];
   const double* C;

@@ -35,6 +35,7 @@ __global__ void __launch_bounds__(256) k_fpass(FPassArgs a) {
   const int t1 = blockIdx.x / a.nt2, t2 = blockIdx.x % a.nt2;
   const int i1_0 = t1 * T1, i2_0 = t2 * T2;
   const int n1 = min(T1, a.N1 - i1_0), n2 = min(T2, N2 - i2_0);
+  const int R1 = r2 * r3, R2 = r1 * r3, R3 = r1 * r2;
   // LDS carve-up
   T* Ds = sm;                               // T1*T2*N3
   T* Zs = Ds + T1 * T2 * N3;                // T1*T2*r3
@@ -47,76 +48,118 @@ __global__ void __launch_bounds__(256) k_fpass(FPassArgs a) {
   T* H2s = H1s + T1 * r1;                   // T2*r2
   T* H3s = H2s + T2 * r2;                   // N3*r3
   T* Ys = H3s + N3 * r3;                    // T1*r2*N3 (need_f3)
-  T* F3 = Ys + (a.need_f3 ? T1 * r2 * N3 : 0);   // r1*r2*N3 (need_f3)
+  T* F3 = Ys + (a.need_f3 ? T1 * r2 * N3 : 0);       // r1*r2*N3 (need_f3)
+  T* Pl = F3 + (a.need_f3 ? r1 * r2 * N3 : 0);       // staged P1 | P2 | P3
   const int tid = threadIdx.x, nth = blockDim.x;
+  const T* P1 = static_cast<const T*>(a.P1);
+  const T* P2 = static_cast<const T*>(a.P2);
+  const T* P3 = static_cast<const T*>(a.P3);
 
-  // load the tile of the data difference and the local basis rows
+  // load the tile of the data difference (8 loads of each snapshot in flight per thread),
+  // the local basis rows and the pseudo-inverses
   const int row = T2 * N3;
-  for (int t = tid; t < T1 * row; t += nth) {
-    const int i1l = t / row, rest = t - i1l * row;
-    const int i2l = rest / N3;
-    T v = (T)0;
-    if (i1l < n1 && i2l < n2) {
-      const long long g = ((long long)(i1_0 + i1l) * N2 + i2_0) * N3 + rest;
-      v = (T)static_cast<const TD*>(a.V1)[g] - (T)static_cast<const TD*>(a.V0)[g];
+  const int total = T1 * row, nvalid = n2 * N3;
+  const TD* V1 = static_cast<const TD*>(a.V1);
+  const TD* V0 = static_cast<const TD*>(a.V0);
+  for (int base = 0; base < total; base += 8 * nth) {
+    TD va[8], vb[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = base + u * nth + tid;
+      va[u] = (TD)0;
+      vb[u] = (TD)0;
+      if (t < total) {
+        const int i1l = t / row, rest = t - (t / row) * row;
+        if (i1l < n1 && rest < nvalid) {
+          const long long g = ((long long)(i1_0 + i1l) * N2 + i2_0) * N3 + rest;
+          va[u] = V1[g];
+          vb[u] = V0[g];
+        }
+      }
     }
-    Ds[t] = v;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = base + u * nth + tid;
+      if (t < total) Ds[t] = (T)va[u] - (T)vb[u];
+    }
   }
   const T* B1 = static_cast<const T*>(a.B1);
   const T* B2 = static_cast<const T*>(a.B2);
   const T* B3 = static_cast<const T*>(a.B3);
-  for (int t = tid; t < T1 * r1; t += nth) {
-    const int i = t / r1;
-    B1s[t] = i < n1 ? B1[(long long)(i1_0 + i) * r1 + (t - i * r1)] : (T)0;
-  }
-  for (int t = tid; t < T2 * r2; t += nth) {
-    const int i = t / r2;
-    B2s[t] = i < n2 ? B2[(long long)(i2_0 + i) * r2 + (t - i * r2)] : (T)0;
-  }
+  for (int t = tid; t < T1 * r1; t += nth) B1s[t] = t < n1 * r1 ? B1[(long long)i1_0 * r1 + t] : (T)0;
+  for (int t = tid; t < T2 * r2; t += nth) B2s[t] = t < n2 * r2 ? B2[(long long)i2_0 * r2 + t] : (T)0;
   for (int t = tid; t < N3 * r3; t += nth) B3s[t] = B3[t];
+  if (a.stage_p) {
+    T* p = Pl;
+    if (a.need_h1) { for (int t = tid; t < R1 * r1; t += nth) p[t] = P1[t]; P1 = p; p += R1 * r1; }
+    if (a.need_h2) { for (int t = tid; t < R2 * r2; t += nth) p[t] = P2[t]; P2 = p; p += R2 * r2; }
+    if (a.need_f3) { for (int t = tid; t < R3 * r3; t += nth) p[t] = P3[t]; P3 = p; }
+  }
   __syncthreads();
 
-  // Z = D x_3 B3^T ; Y = D x_2 B2^T
-  for (int t = tid; t < T1 * T2 * r3; t += nth) {
-    const int c2 = t % r3, q = t / r3;          // q = i1l*T2 + i2l
+  // Z = D x_3 B3^T (one row of N3 values per thread iteration)
+  for (int q = tid; q < T1 * T2; q += nth) {
     const T* d = Ds + q * N3;
-    T s = (T)0;
-    for (int c = 0; c < N3; ++c) s += d[c] * B3s[c * r3 + c2];
-    Zs[t] = s;
+    T* z = Zs + q * r3;
+    for (int c2 = 0; c2 < r3; ++c2) {
+      T s = (T)0;
+      for (int c = 0; c < N3; ++c) s += d[c] * B3s[c * r3 + c2];
+      z[c2] = s;
+    }
   }
+  // Y = D x_2 B2^T
   if (a.need_f3) {
     for (int t = tid; t < T1 * r2 * N3; t += nth) {
       const int c = t % N3, q = t / N3;
       const int b = q % r2, i1l = q / r2;
-      T s = (T)0;
-      for (int i2l = 0; i2l < T2; ++i2l) s += B2s[i2l * r2 + b] * Ds[(i1l * T2 + i2l) * N3 + c];
-      Ys[t] = s;
+      const T* d = Ds + i1l * T2 * N3 + c;
+      T s0 = (T)0, s1 = (T)0, s2 = (T)0, s3 = (T)0;
+      int i2l = 0;
+      for (; i2l + 4 <= T2; i2l += 4) {
+        s0 += B2s[i2l * r2 + b] * d[i2l * N3];
+        s1 += B2s[(i2l + 1) * r2 + b] * d[(i2l + 1) * N3];
+        s2 += B2s[(i2l + 2) * r2 + b] * d[(i2l + 2) * N3];
+        s3 += B2s[(i2l + 3) * r2 + b] * d[(i2l + 3) * N3];
+      }
+      for (; i2l < T2; ++i2l) s0 += B2s[i2l * r2 + b] * d[i2l * N3];
+      Ys[t] = (s0 + s1) + (s2 + s3);
     }
   }
   __syncthreads();
 
-  // F1 = Z x_2 B2^T ; F2 = Z x_1 B1^T ; F3 = Y x_1 B1^T
+  // F1 = Z x_2 B2^T
   for (int t = tid; t < T1 * r2 * r3; t += nth) {
     const int c2 = t % r3, q = t / r3;
     const int b = q % r2, i1l = q / r2;
-    T s = (T)0;
-    for (int i2l = 0; i2l < T2; ++i2l) s += B2s[i2l * r2 + b] * Zs[(i1l * T2 + i2l) * r3 + c2];
-    F1[t] = s;
+    const T* z = Zs + i1l * T2 * r3 + c2;
+    T s0 = (T)0, s1 = (T)0, s2 = (T)0, s3 = (T)0;
+    int i2l = 0;
+    for (; i2l + 4 <= T2; i2l += 4) {
+      s0 += B2s[i2l * r2 + b] * z[i2l * r3];
+      s1 += B2s[(i2l + 1) * r2 + b] * z[(i2l + 1) * r3];
+      s2 += B2s[(i2l + 2) * r2 + b] * z[(i2l + 2) * r3];
+      s3 += B2s[(i2l + 3) * r2 + b] * z[(i2l + 3) * r3];
+    }
+    for (; i2l < T2; ++i2l) s0 += B2s[i2l * r2 + b] * z[i2l * r3];
+    F1[t] = (s0 + s1) + (s2 + s3);
   }
-  for (int t = tid; t < r1 * T2 * r3; t += nth) {
-    const int c2 = t % r3, q = t / r3;
-    const int i2l = q % T2, ai = q / T2;
-    T s = (T)0;
-    for (int i1l = 0; i1l < T1; ++i1l) s += B1s[i1l * r1 + ai] * Zs[(i1l * T2 + i2l) * r3 + c2];
-    F2[t] = s;
-  }
-  if (a.need_f3) {
-    for (int t = tid; t < r1 * r2 * N3; t += nth) {
-      const int c = t % N3, q = t / N3;
-      const int b = q % r2, ai = q / r2;
+  // F2 = Z x_1 B1^T: one (i2l, c2) column per thread iteration, all a
+  for (int q = tid; q < T2 * r3; q += nth) {
+    const int i2l = q / r3, c2 = q - (q / r3) * r3;
+    for (int ai = 0; ai < r1; ++ai) {
       T s = (T)0;
-      for (int i1l = 0; i1l < T1; ++i1l) s += B1s[i1l * r1 + ai] * Ys[(i1l * r2 + b) * N3 + c];
-      F3[t] = s;
+      for (int i1l = 0; i1l < T1; ++i1l) s += B1s[i1l * r1 + ai] * Zs[(i1l * T2 + i2l) * r3 + c2];
+      F2[(ai * T2 + i2l) * r3 + c2] = s;
+    }
+  }
+  // F3 = Y x_1 B1^T
+  if (a.need_f3) {
+    for (int q = tid; q < r2 * N3; q += nth) {
+      for (int ai = 0; ai < r1; ++ai) {
+        T s = (T)0;
+        for (int i1l = 0; i1l < T1; ++i1l) s += B1s[i1l * r1 + ai] * Ys[i1l * r2 * N3 + q];
+        F3[ai * r2 * N3 + q] = s;
+      }
     }
   }
   __syncthreads();
@@ -130,80 +173,96 @@ __global__ void __launch_bounds__(256) k_fpass(FPassArgs a) {
   T* oM1 = oC + r1 * r2 * r3;
   T* oM2 = oM1 + r1 * r1;
   T* oM3 = oM2 + r2 * r2;
-  const T* P1 = static_cast<const T*>(a.P1);
-  const T* P2 = static_cast<const T*>(a.P2);
-  const T* P3 = static_cast<const T*>(a.P3);
-  // core partial: Cdot_p[a][b][c2] = sum_i1 B1[i1][a] F1[i1][b][c2]
-  for (int t = tid; t < r1 * r2 * r3; t += nth) {
-    const int bc = t % (r2 * r3), ai = t / (r2 * r3);
-    T s = (T)0;
-    for (int i1l = 0; i1l < T1; ++i1l) s += B1s[i1l * r1 + ai] * F1[i1l * r2 * r3 + bc];
-    oC[t] = s;
+  // core partial: Cdot_p[a][b][c2] = sum_i1 B1[i1][a] F1[i1][b][c2] (one output per thread)
+  for (int t = tid; t < r1 * R1; t += nth) {
+    const int ai = t / R1, bc = t - (t / R1) * R1;
+    T s0 = (T)0, s1 = (T)0;
+    int i1l = 0;
+    for (; i1l + 2 <= T1; i1l += 2) {
+      s0 += B1s[i1l * r1 + ai] * F1[i1l * R1 + bc];
+      s1 += B1s[(i1l + 1) * r1 + ai] * F1[(i1l + 1) * R1 + bc];
+    }
+    if (i1l < T1) s0 += B1s[i1l * r1 + ai] * F1[i1l * R1 + bc];
+    oC[t] = s0 + s1;
   }
-  // H1_p[i1][a] = sum_(b,c2) F1[i1][b][c2] P1[(b,c2)][a]
+  // H1_p[i1][a] = sum_(b,c2) F1[i1][b][c2] P1[(b,c2)][a]: 4 lanes per output
   if (a.need_h1) {
-    for (int t = tid; t < T1 * r1; t += nth) {
+    for (int t4 = tid; t4 < 4 * T1 * r1; t4 += nth) {
+      const int t = t4 >> 2, part = t4 & 3;
       const int ai = t % r1, i1l = t / r1;
+      const T* f = F1 + i1l * R1;
       T s = (T)0;
-      const T* f = F1 + i1l * r2 * r3;
-      for (int k = 0; k < r2 * r3; ++k) s += f[k] * P1[k * r1 + ai];
-      H1s[t] = s;
-      oH1[t] = s;
+      for (int k = part; k < R1; k += 4) s += f[k] * P1[k * r1 + ai];
+      s += __shfl_xor(s, 1, 64);
+      s += __shfl_xor(s, 2, 64);
+      if (part == 0) oH1[t] = s;
     }
   }
-  // H2_p[i2][b] = sum_(a,c2) F2[a][i2][c2] P2[(a,c2)][b]
+  // H2_p[i2][b] = sum_(a,c2) F2[a][i2][c2] P2[(a,c2)][b]: two outputs per iteration
   if (a.need_h2) {
-    for (int t = tid; t < T2 * r2; t += nth) {
-      const int b = t % r2, i2l = t / r2;
-      T s = (T)0;
+    const int nout = T2 * r2;
+    for (int t = tid; t < nout; t += 2 * nth) {
+      const int tb = t + nth;
+      const bool two = tb < nout;
+      const int b0 = t % r2, i20 = t / r2;
+      const int b1 = two ? tb % r2 : 0, i21 = two ? tb / r2 : 0;
+      T s0 = (T)0, s1 = (T)0;
       for (int ai = 0; ai < r1; ++ai) {
-        const T* f = F2 + (ai * T2 + i2l) * r3;
-        const T* pp = P2 + (ai * r3) * r2 + b;
-        for (int c2 = 0; c2 < r3; ++c2) s += f[c2] * pp[c2 * r2];
+        const T* f0 = F2 + (ai * T2 + i20) * r3;
+        const T* f1 = F2 + (ai * T2 + i21) * r3;
+        const T* pp = P2 + (ai * r3) * r2;
+        for (int c2 = 0; c2 < r3; ++c2) {
+          s0 += f0[c2] * pp[c2 * r2 + b0];
+          s1 += f1[c2] * pp[c2 * r2 + b1];
+        }
       }
-      H2s[t] = s;
-      oH2[t] = s;
+      oH2[t] = s0;
+      if (two) oH2[tb] = s1;
     }
   }
-  // H3_p[c][c2] = sum_(a,b) F3[a][b][c] P3[(a,b)][c2]  (rows of mode 3 are all here)
+  // H3_p[c][c2] = sum_(a,b) F3[a][b][c] P3[(a,b)][c2]: 8 lanes per output
   if (a.need_f3) {
-    for (int t = tid; t < N3 * r3; t += nth) {
+    for (int t8 = tid; t8 < 8 * N3 * r3; t8 += nth) {
+      const int t = t8 >> 3, part = t8 & 7;
       const int c2 = t % r3, c = t / r3;
       T s = (T)0;
-      for (int k = 0; k < r1 * r2; ++k) s += F3[k * N3 + c] * P3[k * r3 + c2];
-      H3s[t] = s;
-      oH3[t] = s;
-    }
-  }
-  __syncthreads();
-  // M_n,p = B_n(rows)^T H_n,p
-  if (a.need_h1) {
-    for (int t = tid; t < r1 * r1; t += nth) {
-      const int j = t % r1, i = t / r1;
-      T s = (T)0;
-      for (int i1l = 0; i1l < T1; ++i1l) s += B1s[i1l * r1 + i] * H1s[i1l * r1 + j];
-      oM1[t] = s;
-    }
-  }
-  if (a.need_h2) {
-    for (int t = tid; t < r2 * r2; t += nth) {
-      const int j = t % r2, i = t / r2;
-      T s = (T)0;
-      for (int i2l = 0; i2l < T2; ++i2l) s += B2s[i2l * r2 + i] * H2s[i2l * r2 + j];
-      oM2[t] = s;
-    }
-  }
-  if (a.need_f3) {
-    for (int t = tid; t < r3 * r3; t += nth) {
-      const int j = t % r3, i = t / r3;
-      T s = (T)0;
-      for (int c = 0; c < N3; ++c) s += B3s[c * r3 + i] * H3s[c * r3 + j];
-      oM3[t] = s;
+      for (int k = part; k < R3; k += 8) s += F3[k * N3 + c] * P3[k * r3 + c2];
+      s += __shfl_xor(s, 1, 64);
+      s += __shfl_xor(s, 2, 64);
+      s += __shfl_xor(s, 4, 64);
+      if (part == 0) oH3[t] = s;
     }
   }
 }
 
 // ---------------------------------------------------------------- reduction
+// Sum of count values p[k*stride] in a fixed order with 8 independent partial sums
+// (so that 8 loads are in flight per thread); deterministic for a given count.
+template <typename T>
+__device__ __forceinline__ double sum_strided(const T* __restrict__ p, long long stride, int count) {
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0, s6 = 0, s7 = 0;
+  int k = 0;
+  for (; k + 8 <= count; k += 8) {
+    const T* q = p + (long long)k * stride;
+    s0 += (double)q[0];
+    s1 += (double)q[stride];
+    s2 += (double)q[2 * stride];
+    s3 += (double)q[3 * stride];
+    s4 += (double)q[4 * stride];
+    s5 += (double)q[5 * stride];
+    s6 += (double)q[6 * stride];
+    s7 += (double)q[7 * stride];
+  }
+  for (; k < count; ++k) {
+    const double v = (double)p[(long long)k * stride];
+    switch (k & 7) {
+      case 0: s0 += v; break; case 1: s1 += v; break; case 2: s2 += v; break; case 3: s3 += v; break;
+      case 4: s4 += v; break; case 5: s5 += v; break; case 6: s6 += v; break; default: s7 += v; break;
+    }
+  }
+  return ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7));
+}
+
 // Sums the per-tile partials in a fixed order (FP64) into H_n, M_n and C_dot, and
 // applies the Heun update to the core (stage 1: k = C_dot/dt, C* = C + dt k;
 // stage 2: C <- C + dt/2 (k + C_dot/dt)).
@@ -218,13 +277,10 @@ __global__ void __launch_bounds__(256) k_freduce(FReduceArgs a, CtrlState* ctrl)
   const long long nH2 = a.need_h2 ? (long long)a.N2 * a.r2 : 0;
   const long long nH3 = a.need_f3 ? (long long)a.N3 * a.r3 : 0;
   const long long nC = (long long)a.r1 * a.r2 * a.r3;
-  const long long nM1 = a.need_h1 ? a.r1 * a.r1 : 0, nM2 = a.need_h2 ? a.r2 * a.r2 : 0;
-  const long long nM3 = a.need_f3 ? a.r3 * a.r3 : 0;
-  const long long total = nH1 + nH2 + nH3 + nC + nM1 + nM2 + nM3;
+  const long long total = nH1 + nH2 + nH3 + nC;
   const int ntiles = a.nt1 * a.nt2;
   const long long oH2 = (long long)a.T1 * a.r1, oH3 = oH2 + (long long)a.T2 * a.r2;
-  const long long oC = oH3 + (long long)a.N3 * a.r3, oM1 = oC + nC, oM2 = oM1 + (long long)a.r1 * a.r1;
-  const long long oM3 = oM2 + (long long)a.r2 * a.r2;
+  const long long oC = oH3 + (long long)a.N3 * a.r3;
   const double inv_dt = 1.0 / a.dt;
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (long long)gridDim.x * blockDim.x) {
@@ -234,8 +290,7 @@ __global__ void __launch_bounds__(256) k_freduce(FReduceArgs a, CtrlState* ctrl)
       const long long i1 = q / a.r1;
       const int ai = (int)(q - i1 * a.r1);
       const int t1 = (int)(i1 / a.T1), i1l = (int)(i1 - (long long)t1 * a.T1);
-      for (int t2 = 0; t2 < a.nt2; ++t2)
-        s += (double)part[(long long)(t1 * a.nt2 + t2) * a.slot + i1l * a.r1 + ai];
+      s = sum_strided(part + (long long)(t1 * a.nt2) * a.slot + i1l * a.r1 + ai, a.slot, a.nt2);
       a.H[0][q] = s;
       continue;
     }
@@ -244,52 +299,66 @@ __global__ void __launch_bounds__(256) k_freduce(FReduceArgs a, CtrlState* ctrl)
       const long long i2 = q / a.r2;
       const int b = (int)(q - i2 * a.r2);
       const int t2 = (int)(i2 / a.T2), i2l = (int)(i2 - (long long)t2 * a.T2);
-      for (int t1 = 0; t1 < a.nt1; ++t1)
-        s += (double)part[(long long)(t1 * a.nt2 + t2) * a.slot + oH2 + i2l * a.r2 + b];
+      s = sum_strided(part + (long long)t2 * a.slot + oH2 + i2l * a.r2 + b, (long long)a.nt2 * a.slot, a.nt1);
       a.H[1][q] = s;
       continue;
     }
     q -= nH2;
     if (q < nH3) {
-      for (int k = 0; k < ntiles; ++k) s += (double)part[(long long)k * a.slot + oH3 + q];
+      s = sum_strided(part + oH3 + q, a.slot, ntiles);
       a.H[2][q] = s;
       continue;
     }
     q -= nH3;
     if (q < nC) {
-      for (int k = 0; k < ntiles; ++k) s += (double)part[(long long)k * a.slot + oC + q];
+      s = sum_strided(part + oC + q, a.slot, ntiles);
       const double cd = s * inv_dt;
       if (a.stage == 1) {
         a.kC[q] = cd;
         a.Cs[q] = a.C0[q] + a.dt * cd;
       } else {
+        a.Cdot2[q] = cd;
         a.C0[q] += 0.5 * a.dt * (a.kC[q] + cd);
       }
-      continue;
     }
-    q -= nC;
-    long long off = oM1;
-    int m = 0;
-    if (q >= nM1) { q -= nM1; off = oM2; m = 1; if (q >= nM2) { q -= nM2; off = oM3; m = 2; } }
-    for (int k = 0; k < ntiles; ++k) s += (double)part[(long long)k * a.slot + off + q];
-    a.M[m][q] = s;
   }
 }
 
 // ---------------------------------------------------------------- prep helpers
-// Core Gram of the mode-n unfolding into LDS G (rn x rn) from a core staged in LDS.
-__device__ void gram_from(const double* Cl, int rn, long long R, long long inner, double* G) {
+// Core Gram of the mode-n unfolding into LDS G (rn x rn) from a core (LDS or global),
+// with the unfolding columns walked as (outer, inner) loops.
+__device__ void gram_from(const double* Cl, int rn, long long R_, long long inner_, double* G) {
   const int npair = rn * (rn + 1) / 2;
+  const int inner = (int)inner_;
+  const int outer = (int)(R_ / inner_);
   for (int t = threadIdx.x; t < npair; t += blockDim.x) {
     int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
     while ((i + 1) * (i + 2) / 2 <= t) ++i;
     while (i * (i + 1) / 2 > t) --i;
     const int j = t - i * (i + 1) / 2;
-    double s = 0.0;
-    for (long long c = 0; c < R; ++c) {
-      const long long o = c / inner, in = c - o * inner;
-      s += Cl[(o * rn + i) * inner + in] * Cl[(o * rn + j) * inner + in];
+    double s0 = 0.0, s1 = 0.0;
+    if (inner == 1) {
+      const double* ci = Cl + i;
+      const double* cj = Cl + j;
+      int o = 0;
+      for (; o + 2 <= outer; o += 2) {
+        s0 += ci[o * rn] * cj[o * rn];
+        s1 += ci[(o + 1) * rn] * cj[(o + 1) * rn];
+      }
+      if (o < outer) s0 += ci[o * rn] * cj[o * rn];
+    } else {
+      for (int o = 0; o < outer; ++o) {
+        const double* ci = Cl + (o * rn + i) * inner;
+        const double* cj = Cl + (o * rn + j) * inner;
+        int in = 0;
+        for (; in + 2 <= inner; in += 2) {
+          s0 += ci[in] * cj[in];
+          s1 += ci[in + 1] * cj[in + 1];
+        }
+        if (in < inner) s0 += ci[in] * cj[in];
+      }
     }
+    const double s = s0 + s1;
     G[i * rn + j] = s;
     G[j * rn + i] = s;
   }
@@ -364,6 +433,21 @@ __device__ void write_pinv(const double* Cl, double* G, double* Li, int rn, long
   __syncthreads();
 }
 
+// P_n = C_(n)^T G^-1 from the inverse Gi (LDS), block-parallel.
+template <typename T>
+__device__ void write_p(const double* Cl, const double* Gi, int rn, long long R, long long inner, T* P) {
+  const int Ri = (int)R, in_ = (int)inner;
+  for (int t = threadIdx.x; t < Ri * rn; t += blockDim.x) {
+    const int c = t / rn, j = t - (t / rn) * rn;
+    const int o = c / in_, in = c - o * in_;
+    const double* cp = Cl + (o * rn) * in_ + in;
+    double s = 0.0;
+    for (int b = 0; b < rn; ++b) s += cp[b * in_] * Gi[b * rn + j];
+    P[t] = (T)s;
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------- finish a stage
 // Blocks [0, rowblocks): rows of every mode: U_dot = (H - U M)/dt, Heun update and,
 // in stage 1, the weighted basis B_n = W_n U* of the next stage.
@@ -376,6 +460,56 @@ __global__ void __launch_bounds__(256) k_ffinish(FFinishArgs a, CtrlState* ctrl)
   if (a.stage == 2 && ctrl->numeric) return;
   const double inv_dt = 1.0 / a.dt;
   if ((int)blockIdx.x < a.rowblocks) {
+    // M_n = U_n^T W_n F_(n) P_n = Cdot_(n) P_n (the same r x r matrix every block needs):
+    // stage C_dot and P_n in LDS, then contract with nested (outer, inner) loops
+    double* Ml[3];
+    {
+      const double* cd = a.stage == 1 ? a.kC : a.Cdot2;   // this stage's C_dot
+      const int csz = a.r[0] * a.r[1] * a.r[2];
+      double* cdl = lds;
+      T* pl = reinterpret_cast<T*>(cdl + csz);
+      for (int t = threadIdx.x; t < csz; t += blockDim.x) cdl[t] = cd[t];
+      int poff[3], moff = 0;
+      {
+        int off = 0;
+        for (int n = 0; n < 3; ++n) {
+          poff[n] = off;
+          if (a.r[n] < a.N[n]) {
+            const int Rn = csz / a.r[n];
+            const T* Pn = static_cast<const T*>(a.Pcur[n]);
+            for (int t = threadIdx.x; t < Rn * a.r[n]; t += blockDim.x) pl[off + t] = Pn[t];
+            off += Rn * a.r[n];
+          }
+        }
+        moff = (int)((csz * 8 + off * (int)sizeof(T) + 7) / 8);
+      }
+      __syncthreads();
+      int off = moff;
+      for (int n = 0; n < 3; ++n) {
+        Ml[n] = lds + off;
+        const int rr = a.r[n];
+        if (rr < a.N[n]) {
+          int inner = 1, outer = 1;
+          for (int k = 0; k < 3; ++k) {
+            if (k < n) outer *= a.r[k];
+            if (k > n) inner *= a.r[k];
+          }
+          const T* Pn = pl + poff[n];
+          for (int t = threadIdx.x; t < rr * rr; t += blockDim.x) {
+            const int i = t / rr, j = t - (t / rr) * rr;
+            double s = 0.0;
+            for (int o = 0; o < outer; ++o) {
+              const double* crow = cdl + (o * rr + i) * inner;
+              const T* prow = Pn + (o * inner) * rr + j;
+              for (int in = 0; in < inner; ++in) s += crow[in] * (double)prow[in * rr];
+            }
+            Ml[n][t] = s * a.dt;   // H is the raw (undivided) projection, so M is too
+          }
+        }
+        off += rr * rr;
+      }
+    }
+    __syncthreads();
     long long tot = 0;
     for (int n = 0; n < 3; ++n) tot += a.N[n] * a.r[n];
     for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot;
@@ -390,8 +524,9 @@ __global__ void __launch_bounds__(256) k_ffinish(FFinishArgs a, CtrlState* ctrl)
       double ud = 0.0;
       if (rn < a.N[n]) {
         double s = a.H[n][q];
-        const double* M = a.M[n];
-        for (int k = 0; k < rn; ++k) s -= Ust[i * ld + k] * M[k * rn + j];
+        const double* M = Ml[n];
+        const double* ur = Ust + i * ld;
+        for (int k = 0; k < rn; ++k) s -= ur[k] * M[k * rn + j];
         ud = s * inv_dt;
       }
       if (a.stage == 1) {
@@ -415,30 +550,47 @@ __global__ void __launch_bounds__(256) k_ffinish(FFinishArgs a, CtrlState* ctrl)
     if (k != n) R *= a.r[k];
     if (k > n) inner *= a.r[k];
   }
+  const int rq = a.rmax;
   double* G = lds;
-  double* Li = G + TDB_RCAP * TDB_RCAP;
-  double* Cl = Li + TDB_RCAP * TDB_RCAP;
+  double* Li = G + rq * rq;
+  double* Gi = Li + rq * rq;
+  double* Cl = Gi + rq * rq;
+  __shared__ int ok_s;
   const double* Csrc = a.Cs;
   if (a.core_in_lds) {
-    for (long long t = threadIdx.x; t < csz; t += blockDim.x) Cl[t] = Csrc[t];
+    for (int t = threadIdx.x; t < (int)csz; t += blockDim.x) Cl[t] = Csrc[t];
     __syncthreads();
     Csrc = Cl;
   }
   gram_from(Csrc, rn, R, inner, G);
-  if (!chol_inplace(G, rn)) {
-    if (threadIdx.x == 0) atomicOr(&ctrl->numeric, 1);
-    return;
+  if (threadIdx.x < 64) {
+    const bool ok = wave_chol(G, rn);
+    if (ok) {
+      wave_tri_inv(G, Li, rn);
+      wave_inv_from_linv(Li, Gi, rn);
+    }
+    if (threadIdx.x == 0) {
+      ok_s = ok ? 1 : 0;
+      if (!ok) atomicOr(&ctrl->numeric, 1);
+    }
   }
-  write_pinv<T>(Csrc, G, Li, rn, R, inner, static_cast<T*>(a.P[n]));
+  __syncthreads();
+  if (!ok_s) return;
+  write_p<T>(Csrc, Gi, rn, R, inner, static_cast<T*>(a.P[n]));
 }
 
 // ---------------------------------------------------------------- QR + fold
-// Block n: two rounds of Cholesky QR of U_n in the W inner product (U_n <- U_n R^-1,
-// R accumulated); the last block to finish folds every R_n into the core.
+// Block n: Cholesky QR of U_n in the W inner product (one round: the Heun update leaves
+// U_n W-orthonormal to O(dt^2), so a single round already reaches roundoff; a second
+// round can be requested): the Gram matrix
+// U^T W U from row-split partial sums (one quarter of the rows per wave, combined in
+// a fixed order), its Cholesky factor R^T R and R^-1 by one wave, then U <- U R^-1
+// row by row; R accumulates over the rounds. The last block to finish folds every
+// R_n into the core (C <- C x_n R_n), so the reconstruction is unchanged.
 __global__ void __launch_bounds__(256) k_fqr(FQrArgs a, CtrlState* ctrl) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
-  __shared__ int last, skip_s;
+  __shared__ int last, skip_s, ok_s;
   // every block takes part in the completion count, even when there is nothing to do;
   // the flag is read once per block so that the whole block takes the same branch
   if (threadIdx.x == 0)
@@ -447,49 +599,95 @@ __global__ void __launch_bounds__(256) k_fqr(FQrArgs a, CtrlState* ctrl) {
   const bool skip = skip_s != 0;
   const int n = blockIdx.x;
   const int rn = a.r[n], ld = a.ldU[n];
-  const long long Nn = a.N[n];
-  double* L = lds;                          // rn*rn
-  double* Rt = L + TDB_RCAP * TDB_RCAP;     // rn*rn
-  double* Tm = Rt + TDB_RCAP * TDB_RCAP;    // rn*rn
-  double* Ul = Tm + TDB_RCAP * TDB_RCAP;    // Nn*rn when staged
+  const int Nn = (int)a.N[n];
+  const int rq = a.rmax;
+  const int np = rn * (rn + 1) / 2;
+  const int npq = rq * (rq + 1) / 2;
+  double* L = lds;                          // rq*rq
+  double* Li = L + rq * rq;                 // rq*rq
+  double* Rt = Li + rq * rq;                // rq*rq
+  double* Tm = Rt + rq * rq;                // rq*rq
+  double* Gp = Tm + rq * rq;                // 4*npq partial Grams
+  double* wl = Gp + 4 * npq;                // Nn weights
+  double* Ul = wl + TDB_NEIG;               // Nn*rn when staged (or the core for the fold)
   double* U = a.U0[n];
-  const double* w = a.w[n];
   const bool stage = a.u_in_lds[n] && !skip;
-  if (stage) {
-    for (long long t = threadIdx.x; t < Nn * rn; t += blockDim.x) {
-      const long long i = t / rn;
-      Ul[t] = U[i * ld + (t - i * rn)];
-    }
+  if (!skip) {
+    for (int t = threadIdx.x; t < Nn; t += blockDim.x) wl[t] = a.w[n][t];
+    if (stage)
+      for (int base = 0; base < Nn * rn; base += 8 * blockDim.x) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int t = base + u * blockDim.x + threadIdx.x;
+          v[u] = 0.0;
+          if (t < Nn * rn) { const int i = t / rn; v[u] = U[i * ld + (t - i * rn)]; }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int t = base + u * blockDim.x + threadIdx.x;
+          if (t < Nn * rn) Ul[t] = v[u];
+        }
+      }
+    for (int t = threadIdx.x; t < rn * rn; t += blockDim.x) Rt[t] = (t / rn == t % rn) ? 1.0 : 0.0;
   }
-  for (int t = threadIdx.x; t < rn * rn; t += blockDim.x) Rt[t] = (t / rn == t % rn) ? 1.0 : 0.0;
   __syncthreads();
   double* Uw = stage ? Ul : U;
   const int ldw = stage ? rn : ld;
   bool ok = !skip;
-  for (int round = 0; round < 2 && ok; ++round) {
-    for (int t = threadIdx.x; t < rn * (rn + 1) / 2; t += blockDim.x) {
-      int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-      while ((i + 1) * (i + 2) / 2 <= t) ++i;
-      while (i * (i + 1) / 2 > t) --i;
-      const int j = t - i * (i + 1) / 2;
-      double s = 0.0;
-      for (long long q = 0; q < Nn; ++q) s += w[q] * Uw[q * ldw + i] * Uw[q * ldw + j];
-      L[i * rn + j] = s;
-      L[j * rn + i] = s;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int round = 0; round < a.rounds && ok; ++round) {
+    // partial Grams: wave `wid` sums rows [q0, q1)
+    const int per = (Nn + 3) / 4;
+    const int q0 = wid * per, q1 = min(Nn, q0 + per);
+    for (int pp = lane; pp < np; pp += 64) {
+      int i = (int)((sqrt(8.0 * pp + 1.0) - 1.0) * 0.5);
+      while ((i + 1) * (i + 2) / 2 <= pp) ++i;
+      while (i * (i + 1) / 2 > pp) --i;
+      const int j = pp - i * (i + 1) / 2;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int q = q0;
+      for (; q + 4 <= q1; q += 4) {
+        s0 += wl[q] * Uw[q * ldw + i] * Uw[q * ldw + j];
+        s1 += wl[q + 1] * Uw[(q + 1) * ldw + i] * Uw[(q + 1) * ldw + j];
+        s2 += wl[q + 2] * Uw[(q + 2) * ldw + i] * Uw[(q + 2) * ldw + j];
+        s3 += wl[q + 3] * Uw[(q + 3) * ldw + i] * Uw[(q + 3) * ldw + j];
+      }
+      for (; q < q1; ++q) s0 += wl[q] * Uw[q * ldw + i] * Uw[q * ldw + j];
+      Gp[wid * npq + pp] = (s0 + s1) + (s2 + s3);
     }
     __syncthreads();
-    ok = chol_inplace(L, rn);
+    for (int pp = threadIdx.x; pp < np; pp += blockDim.x) {
+      int i = (int)((sqrt(8.0 * pp + 1.0) - 1.0) * 0.5);
+      while ((i + 1) * (i + 2) / 2 <= pp) ++i;
+      while (i * (i + 1) / 2 > pp) --i;
+      const int j = pp - i * (i + 1) / 2;
+      const double g = (Gp[pp] + Gp[npq + pp]) + (Gp[2 * npq + pp] + Gp[3 * npq + pp]);
+      L[i * rn + j] = g;
+      L[j * rn + i] = g;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const bool okw = wave_chol(L, rn);
+      if (okw) wave_tri_inv(L, Li, rn);
+      if (threadIdx.x == 0) ok_s = okw ? 1 : 0;
+    }
+    __syncthreads();
+    ok = ok_s != 0;
     if (!ok) break;
-    for (long long q = threadIdx.x; q < Nn; q += blockDim.x) {
+    // U <- U R^-1 with R = L^T: x_j = sum_{k<=j} u_k Li[j][k], in place from the last column
+    for (int q = threadIdx.x; q < Nn; q += blockDim.x) {
       double* rowp = Uw + q * ldw;
-      for (int j = 0; j < rn; ++j) {
-        double s = rowp[j];
-        for (int k = 0; k < j; ++k) s -= L[j * rn + k] * rowp[k];
-        rowp[j] = s / L[j * rn + j];
+      for (int j = rn - 1; j >= 0; --j) {
+        double s = 0.0;
+        const double* lj = Li + j * rn;
+        for (int k = 0; k <= j; ++k) s += rowp[k] * lj[k];
+        rowp[j] = s;
       }
     }
+    // Rt <- L^T Rt
     for (int t = threadIdx.x; t < rn * rn; t += blockDim.x) {
-      const int i = t / rn, j = t % rn;
+      const int i = t / rn, j = t - (t / rn) * rn;
       double s = 0.0;
       for (int k = i; k < rn; ++k) s += L[k * rn + i] * Rt[k * rn + j];
       Tm[t] = s;
@@ -502,12 +700,11 @@ __global__ void __launch_bounds__(256) k_fqr(FQrArgs a, CtrlState* ctrl) {
   } else if (!ok) {
     if (threadIdx.x == 0) atomicOr(&ctrl->numeric, 2);
   } else {
-    if (stage) {
-      for (long long t = threadIdx.x; t < Nn * rn; t += blockDim.x) {
-        const long long i = t / rn;
+    if (stage)
+      for (int t = threadIdx.x; t < Nn * rn; t += blockDim.x) {
+        const int i = t / rn;
         U[i * ld + (t - i * rn)] = Ul[t];
       }
-    }
     for (int t = threadIdx.x; t < rn * rn; t += blockDim.x) a.Rq[n][t] = Rt[t];
   }
   // last block folds the factors into the core
@@ -522,27 +719,35 @@ __global__ void __launch_bounds__(256) k_fqr(FQrArgs a, CtrlState* ctrl) {
   __threadfence();
   if (threadIdx.x == 0) *a.counter = 0u;
   if (__hip_atomic_load(&ctrl->numeric, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) return;
-  long long csz = 1;
+  int csz = 1;
   for (int k = 0; k < 3; ++k) csz *= a.r[k];
+  // core in LDS (two buffers) when it fits, else ping-pong through global memory
+  double* ca = a.core_in_lds ? Ul : a.C0;
+  double* cb = a.core_in_lds ? Ul + csz : a.Ctmp;
+  if (a.core_in_lds) {
+    for (int t = threadIdx.x; t < csz; t += blockDim.x)
+      ca[t] = __hip_atomic_load(&a.C0[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
   for (int m = 0; m < 3; ++m) {
     const int rm = a.r[m];
     for (int t = threadIdx.x; t < rm * rm; t += blockDim.x)
       Rt[t] = __hip_atomic_load(&a.Rq[m][t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
-    long long inner = 1;
+    int inner = 1;
     for (int k = m + 1; k < 3; ++k) inner *= a.r[k];
-    for (long long t = threadIdx.x; t < csz; t += blockDim.x) {
-      const long long in = t % inner, rest = t / inner;
-      const int ai = (int)(rest % rm);
-      const long long o = rest / rm;
+    for (int t = threadIdx.x; t < csz; t += blockDim.x) {
+      const int in = t % inner, rest = t / inner;
+      const int ai = rest % rm;
+      const int o = rest / rm;
       double s = 0.0;
-      for (int b = ai; b < rm; ++b) s += Rt[ai * rm + b] * a.C0[(o * rm + b) * inner + in];
-      a.Ctmp[t] = s;
+      for (int b = ai; b < rm; ++b) s += Rt[ai * rm + b] * ca[(o * rm + b) * inner + in];
+      cb[t] = s;
     }
     __syncthreads();
-    for (long long t = threadIdx.x; t < csz; t += blockDim.x) a.C0[t] = a.Ctmp[t];
-    __syncthreads();
+    double* tswap = ca; ca = cb; cb = tswap;
   }
+  for (int t = threadIdx.x; t < csz; t += blockDim.x) a.C0[t] = ca[t];
 }
 
 // ---------------------------------------------------------------- post-step
@@ -557,25 +762,40 @@ __global__ void __launch_bounds__(256) k_fpost(FPostArgs a, CtrlState* ctrl) {
   __shared__ int pairs[TDB_RCAP + 2];
   __shared__ int order[TDB_RCAP];
   if ((int)blockIdx.x >= 3) {
+    // E[a][i2][i3] = sum_b U2[i2][b] T3[a][b][i3],  T3[a][b][i3] = sum_c C[a][b][c] U3[i3][c]
     const int eb = blockIdx.x - 3;
     const int r1 = a.r[0], r2 = a.r[1], r3 = a.r[2];
     const long long N2 = a.N[1], N3 = a.N[2];
-    const long long tot = (long long)r1 * N2 * N3;
-    T* E = static_cast<T*>(a.E);
-    for (long long t = (long long)eb * blockDim.x + threadIdx.x; t < tot; t += (long long)a.eblocks * blockDim.x) {
-      const long long i3 = t % N3, q = t / N3;
-      const long long i2 = q % N2;
-      const int ai = (int)(q / N2);
-      const double* u2 = a.U[1] + i2 * a.ldU[1];
-      const double* u3 = a.U[2] + i3 * a.ldU[2];
-      double s = 0.0;
-      for (int b = 0; b < r2; ++b) {
-        const double* cr = a.C + ((long long)ai * r2 + b) * r3;
-        double s3 = 0.0;
-        for (int c = 0; c < r3; ++c) s3 += cr[c] * u3[c];
-        s += u2[b] * s3;
+    double* T3 = lds;                                   // r1*r2*N3
+    double* U2l = T3 + (long long)r1 * r2 * N3;         // rows of U2 of this block
+    const long long per = (N2 + a.eblocks - 1) / a.eblocks;
+    const long long i2a = (long long)eb * per, i2b = min(N2, i2a + per);
+    if (i2a < i2b) {
+      for (long long t = threadIdx.x; t < (long long)r1 * r2 * N3; t += blockDim.x) {
+        const long long i3 = t % N3, ab = t / N3;
+        const double* cr = a.C + ab * r3;
+        const double* u3 = a.U[2] + i3 * a.ldU[2];
+        double s = 0.0;
+        for (int c = 0; c < r3; ++c) s += cr[c] * u3[c];
+        T3[t] = s;
       }
-      E[t] = (T)s;
+      for (long long t = threadIdx.x; t < (i2b - i2a) * r2; t += blockDim.x) {
+        const long long i = t / r2;
+        U2l[t] = a.U[1][(i2a + i) * a.ldU[1] + (t - i * r2)];
+      }
+      __syncthreads();
+      T* E = static_cast<T*>(a.E);
+      const long long nrow = i2b - i2a;
+      for (long long t = threadIdx.x; t < (long long)r1 * nrow * N3; t += blockDim.x) {
+        const long long i3 = t % N3, q = t / N3;
+        const long long il = q % nrow;
+        const int ai = (int)(q / nrow);
+        const double* u2 = U2l + il * r2;
+        const double* t3 = T3 + (long long)ai * r2 * N3 + i3;
+        double s = 0.0;
+        for (int b = 0; b < r2; ++b) s += u2[b] * t3[(long long)b * N3];
+        E[((long long)ai * N2 + i2a + il) * N3 + i3] = (T)s;
+      }
     }
     const long long tu = a.N[0] * r1;
     T* U1c = static_cast<T*>(a.U1c);
@@ -594,43 +814,55 @@ __global__ void __launch_bounds__(256) k_fpost(FPostArgs a, CtrlState* ctrl) {
     if (k > n) inner *= a.r[k];
   }
   // weighted basis of the next stage 1
-  T* B = static_cast<T*>(a.B[n]);
-  for (long long t = threadIdx.x; t < a.N[n] * rn; t += blockDim.x) {
-    const long long i = t / rn;
-    B[t] = (T)(a.w[n][i] * a.U[n][i * a.ldU[n] + (t - i * rn)]);
+  {
+    T* B = static_cast<T*>(a.B[n]);
+    const int Nn = (int)a.N[n], ld = a.ldU[n];
+    const double* U = a.U[n];
+    const double* w = a.w[n];
+    for (int i = threadIdx.x / 4; i < Nn; i += blockDim.x / 4) {
+      const double wi = w[i];
+      for (int j = threadIdx.x & 3; j < rn; j += 4) B[i * rn + j] = (T)(wi * U[i * ld + j]);
+    }
   }
+  const int rq = a.rmax;
   double* G = lds;
-  double* Li = G + TDB_RCAP * TDB_RCAP;
-  double* Cl = Li + TDB_RCAP * TDB_RCAP;
+  double* Li = G + rq * rq;
+  double* Gi = Li + rq * rq;
+  double* ws = Gi + rq * rq;                 // 4*rq
+  double* lam = ws + 4 * rq;                 // rq
+  double* Cl = lam + rq;
+  __shared__ int ok_s;
   const double* Csrc = a.C;
   if (a.core_in_lds) {
-    for (long long t = threadIdx.x; t < csz; t += blockDim.x) Cl[t] = Csrc[t];
+    for (int t = threadIdx.x; t < (int)csz; t += blockDim.x) Cl[t] = Csrc[t];
     __syncthreads();
     Csrc = Cl;
   }
   gram_from(Csrc, rn, R, inner, G);
-  // singular values: Jacobi on a copy in Li
-  for (int t = threadIdx.x; t < rn * rn; t += blockDim.x) Li[t] = G[t];
-  __syncthreads();
-  jacobi_values(Li, rn, pairs);
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < rn; ++i) order[i] = i;
-    for (int i = 0; i < rn; ++i) {
-      int best = i;
-      for (int j = i + 1; j < rn; ++j)
-        if (Li[order[j] * rn + order[j]] > Li[order[best] * rn + order[best]]) best = j;
-      const int tt = order[i]; order[i] = order[best]; order[best] = tt;
+  const bool need_p = rn < a.N[n] && a.want_pinv;
+  if (threadIdx.x < 64) {
+    // singular values of C_(n): eigenvalues of a copy of the Gram matrix
+    for (int t = threadIdx.x; t < rn * rn; t += 64) Gi[t] = G[t];
+    wave_fence();
+    wave_eigvals(Gi, rn, lam, ws);
+    for (int i = threadIdx.x; i < TDB_RCAP; i += 64)
+      ctrl->sigma[n][i] = i < rn ? sqrt(fmax(lam[i], 0.0)) : 0.0;
+    bool ok = true;
+    if (need_p) {
+      ok = wave_chol(G, rn);
+      if (ok) {
+        wave_tri_inv(G, Li, rn);
+        wave_inv_from_linv(Li, Gi, rn);
+      }
     }
-    for (int i = 0; i < TDB_RCAP; ++i)
-      ctrl->sigma[n][i] = (i < rn) ? sqrt(fmax(Li[order[i] * rn + order[i]], 0.0)) : 0.0;
+    if (threadIdx.x == 0) {
+      ok_s = ok ? 1 : 0;
+      if (!ok) atomicOr(&ctrl->numeric, 4);
+    }
   }
   __syncthreads();
-  if (rn >= a.N[n] || !a.want_pinv) return;
-  if (!chol_inplace(G, rn)) {
-    if (threadIdx.x == 0) atomicOr(&ctrl->numeric, 4);
-    return;
-  }
-  write_pinv<T>(Csrc, G, Li, rn, R, inner, static_cast<T*>(a.P[n]));
+  if (!need_p || !ok_s) return;
+  write_p<T>(Csrc, Gi, rn, R, inner, static_cast<T*>(a.P[n]));
 }
 
 // ---------------------------------------------------------------- error pass
@@ -640,13 +872,17 @@ __global__ void __launch_bounds__(256) k_fpost(FPostArgs a, CtrlState* ctrl) {
 template <typename TD, typename T>
 __global__ void __launch_bounds__(256) k_ferr(FErrArgs a, CtrlState* ctrl) {
   __shared__ double red[16];
-  __shared__ int last;
+  __shared__ double U1s[FERR_T1 * TDB_RCAP];
   const long long M = a.M;      // N2*N3
   const int r1 = a.r1;
   const int i1_0 = blockIdx.y * a.T1;
   const int n1 = min(a.T1, a.N1 - i1_0);
   const T* E = static_cast<const T*>(a.E);
-  const T* U1 = static_cast<const T*>(a.U1c);
+  for (int t = threadIdx.x; t < FERR_T1 * r1; t += blockDim.x) {
+    const int q = t / r1;
+    U1s[t] = q < n1 ? (double)static_cast<const T*>(a.U1c)[(long long)(i1_0 + q) * r1 + (t - q * r1)] : 0.0;
+  }
+  __syncthreads();
   double se = 0.0, sv = 0.0;
   for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < M; j += (long long)gridDim.x * blockDim.x) {
     T acc[FERR_T1];
@@ -654,7 +890,7 @@ __global__ void __launch_bounds__(256) k_ferr(FErrArgs a, CtrlState* ctrl) {
     for (int ai = 0; ai < r1; ++ai) {
       const T e = E[(long long)ai * M + j];
       for (int q = 0; q < FERR_T1; ++q)
-        if (q < n1) acc[q] += U1[(long long)(i1_0 + q) * r1 + ai] * e;
+        acc[q] += (T)U1s[q * r1 + ai] * e;
     }
     const double w23 = a.w23[j];
     for (int q = 0; q < FERR_T1; ++q) {
@@ -674,25 +910,19 @@ __global__ void __launch_bounds__(256) k_ferr(FErrArgs a, CtrlState* ctrl) {
     a.part[2 * bid] = se;
     a.part[2 * bid + 1] = sv;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = __hip_atomic_fetch_add(a.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (prev == gridDim.x * gridDim.y - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  const int nb = gridDim.x * gridDim.y;
+}
+
+// One block: fixed-order sum of the error-pass partials, then the controller.
+__global__ void __launch_bounds__(256) k_ferr_final(const double* __restrict__ part, int nb, CtrlState* ctrl) {
+  __shared__ double red[16];
   double s0 = 0.0, s1 = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-    s0 += __hip_atomic_load(&a.part[2 * i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s1 += __hip_atomic_load(&a.part[2 * i + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s0 += part[2 * i];
+    s1 += part[2 * i + 1];
   }
   s0 = block_sum(s0, red);
   s1 = block_sum(s1, red);
   if (threadIdx.x == 0) {
-    *a.counter = 0u;
     ctrl->eps2 = s0;
     ctrl->nu2 = s1;
     controller_decide(ctrl);
@@ -715,9 +945,8 @@ template hipError_t launch_fpass<double, float>(const FPassArgs&, size_t, hipStr
 
 template <typename T>
 hipError_t launch_freduce(const FReduceArgs& a, CtrlState* c, hipStream_t s) {
-  long long total = (long long)a.r1 * a.r2 * a.r3 + (a.need_h1 ? (long long)a.N1 * a.r1 + a.r1 * a.r1 : 0) +
-                    (a.need_h2 ? (long long)a.N2 * a.r2 + a.r2 * a.r2 : 0) +
-                    (a.need_f3 ? (long long)a.N3 * a.r3 + a.r3 * a.r3 : 0);
+  long long total = (long long)a.r1 * a.r2 * a.r3 + (a.need_h1 ? (long long)a.N1 * a.r1 : 0) +
+                    (a.need_h2 ? (long long)a.N2 * a.r2 : 0) + (a.need_f3 ? (long long)a.N3 * a.r3 : 0);
   long long blocks = (total + 255) / 256;
   if (blocks < 1) blocks = 1;
   if (blocks > 1024) blocks = 1024;
@@ -760,6 +989,9 @@ template hipError_t launch_fpost<double>(const FPostArgs&, size_t, CtrlState*, h
 template <typename TD, typename T>
 hipError_t launch_ferr(const FErrArgs& a, CtrlState* c, hipStream_t s) {
   hipLaunchKernelGGL((k_ferr<TD, T>), dim3(a.gx, a.gy), dim3(256), 0, s, a, c);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ferr_final, dim3(1), dim3(256), 0, s, a.part, a.gx * a.gy, c);
   return hipGetLastError();
 }
 template hipError_t launch_ferr<float, float>(const FErrArgs&, CtrlState*, hipStream_t);

@@ -296,7 +296,17 @@ __global__ void __launch_bounds__(TDB_BLOCK) k_core_sigma(SigmaArgs a, CtrlState
   }
   core_gram(a.C, rn, R, inner, G);
   const bool vec = a.Psi[n] != nullptr;
-  jacobi_lds(G, vec ? V : nullptr, rn, pairs);
+  if (!vec) {
+    // values only: one-wave tridiagonalisation and bisection
+    __shared__ double lam_s[TDB_RCAP], ws_s[4 * TDB_RCAP];
+    if (threadIdx.x < 64) {
+      wave_eigvals(G, rn, lam_s, ws_s);
+      for (int i = threadIdx.x; i < TDB_RCAP; i += 64)
+        ctrl->sigma[n][i] = i < rn ? sqrt(fmax(lam_s[i], 0.0)) : 0.0;
+    }
+    return;
+  }
+  jacobi_lds(G, V, rn, pairs);
   if (threadIdx.x == 0) {
     // selection sort of the eigenvalues, descending (stable on ties)
     for (int i = 0; i < rn; ++i) order[i] = i;

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -72,7 +73,8 @@ struct tdb_ctx {
   int lds_max = 65536;
   void* fpart = nullptr;
   long long fpart_elems = 0;
-  double *Mred[TDB_P] = {}, *Rq[TDB_P] = {};
+  double *Rq[TDB_P] = {}, *Cdot2 = nullptr;
+  void* P2[TDB_P] = {};          // pseudo-inverses of the stage-2 core
   void *E = nullptr, *U1c = nullptr;
   double *w23 = nullptr, *ferr_part = nullptr;
   unsigned* counters = nullptr;
@@ -173,7 +175,7 @@ long long prod_ll(const int* a, int p, int skip = -1) {
 }
 
 struct PassPlan {
-  int T1 = 1, T2 = 1, nt1 = 1, nt2 = 1;
+  int T1 = 1, T2 = 1, nt1 = 1, nt2 = 1, stage_p = 0;
   long long slot = 0;
   size_t lds = 0;
   bool ok = false;
@@ -187,7 +189,11 @@ PassPlan plan_pass(const tdb_ctx* h, const int* r) {
   const int r1 = r[0], r2 = r[1], r3 = r[2];
   const bool f3 = r3 < N3;
   const size_t te = h->celt;
-  const long long target = h->f32 ? 4096 : 2048;
+  long long target = h->f32 ? 4096 : 2048;
+  if (const char* env = std::getenv("TDB_PASS_TILE")) {
+    const long long v = std::atoll(env);
+    if (v >= 64 && v <= (1 << 20)) target = v;
+  }
   int T2 = (int)std::min<long long>(N2, 64);
   int T1 = (int)std::max<long long>(1, std::min<long long>(N1, target / std::max<long long>(1, T2 * N3)));
   auto lds_of = [&](int t1, int t2) {
@@ -199,13 +205,16 @@ PassPlan plan_pass(const tdb_ctx* h, const int* r) {
   while (lds_of(T1, T2) > (size_t)h->lds_max && T1 > 1) T1 = std::max(1, T1 / 2);
   while (lds_of(T1, T2) > (size_t)h->lds_max && T2 > 8) T2 = std::max(8, T2 / 2);
   if (lds_of(T1, T2) > (size_t)h->lds_max) return pl;
+  // stage the pseudo-inverses too when they fit
+  const long long pe = (r1 < N1 ? (long long)r1 * r2 * r3 : 0) + (r2 < N2 ? (long long)r1 * r2 * r3 : 0) +
+                       (f3 ? (long long)r1 * r2 * r3 : 0);
+  if (lds_of(T1, T2) + (size_t)pe * te <= (size_t)h->lds_max) pl.stage_p = 1;
   pl.T1 = T1;
   pl.T2 = T2;
   pl.nt1 = (int)((N1 + T1 - 1) / T1);
   pl.nt2 = (int)((N2 + T2 - 1) / T2);
-  pl.slot = (long long)T1 * r1 + (long long)T2 * r2 + N3 * r3 + (long long)r1 * r2 * r3 + (long long)r1 * r1 +
-            (long long)r2 * r2 + (long long)r3 * r3;
-  pl.lds = lds_of(T1, T2);
+  pl.slot = (long long)T1 * r1 + (long long)T2 * r2 + N3 * r3 + (long long)r1 * r2 * r3;
+  pl.lds = lds_of(T1, T2) + (pl.stage_p ? (size_t)pe * te : 0);
   pl.ok = true;
   return pl;
 }
@@ -341,7 +350,8 @@ tdb_status setup_fused(tdb_ctx* h, const std::vector<std::vector<double>>& wh) {
   HIPCHK(hipGetDevice(&dev));
   int lds = 65536;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lds = 65536;
-  h->lds_max = lds;
+  // dynamic LDS budget: the device limit minus room for the kernels' static LDS
+  h->lds_max = lds - 4096;
   // partial buffer: enough for the ranks-1 plan and the caps plan
   int ones[3] = {1, 1, 1};
   PassPlan p1 = plan_pass(h, ones), pc = plan_pass(h, h->caps);
@@ -352,9 +362,10 @@ tdb_status setup_fused(tdb_ctx* h, const std::vector<std::vector<double>>& wh) {
   h->fpart_elems = tiles * slot;
   TRY(dalloc(h, &h->fpart, (size_t)h->fpart_elems * h->celt));
   for (int n = 0; n < 3; ++n) {
-    TRY(dallocT(h, &h->Mred[n], (size_t)TDB_RCAP * TDB_RCAP));
     TRY(dallocT(h, &h->Rq[n], (size_t)TDB_RCAP * TDB_RCAP));
+    TRY(dalloc(h, &h->P2[n], (size_t)h->Rmax * h->caps[n] * h->celt));
   }
+  TRY(dallocT(h, &h->Cdot2, h->core_cap));
   TRY(dalloc(h, &h->E, (size_t)h->caps[0] * h->N[1] * h->N[2] * h->celt));
   TRY(dalloc(h, &h->U1c, (size_t)h->N[0] * h->caps[0] * h->celt));
   std::vector<double> w23((size_t)(h->N[1] * h->N[2]));
@@ -726,9 +737,22 @@ tdb_status ingest_impl(tdb_ctx* h, const TD* V1, hipStream_t s) {
   return TDB_OK;
 }
 
+int max_rank(const tdb_ctx* h) {
+  int m = 1;
+  for (int n = 0; n < h->p; ++n) m = std::max(m, h->r[n]);
+  return m;
+}
+
 size_t small_lds(const tdb_ctx* h, bool* core_in_lds) {
   const long long csz = prod_ll(h->r, h->p);
-  const size_t base = 2 * (size_t)TDB_RCAP * TDB_RCAP * 8;
+  const int rm = max_rank(h);
+  long long msum = 0;
+  for (int n = 0; n < h->p; ++n) msum += (long long)h->r[n] * h->r[n];
+  // finish rows stage C_dot, the three P_n and the three M_n
+  long long pel = 0;
+  for (int n = 0; n < h->p; ++n) pel += (csz / h->r[n]) * h->r[n];
+  const size_t rows = (size_t)csz * 8 + (size_t)pel * h->celt + 8 + (size_t)msum * 8;
+  const size_t base = std::max<size_t>((3 * (size_t)rm * rm + 5 * (size_t)rm + 64) * 8, rows);
   *core_in_lds = base + (size_t)csz * 8 <= (size_t)h->lds_max;
   return base + (*core_in_lds ? (size_t)csz * 8 : 0);
 }
@@ -739,11 +763,16 @@ template <typename T>
 tdb_status fused_post(tdb_ctx* h, hipStream_t s) {
   FPostArgs pa{};
   bool cil = false;
-  const size_t lds = small_lds(h, &cil);
+  size_t lds = small_lds(h, &cil);
   pa.core_in_lds = cil ? 1 : 0;
   pa.want_pinv = 1;
+  pa.rmax = max_rank(h);
   const long long etot = (long long)h->r[0] * h->N[1] * h->N[2];
-  pa.eblocks = (int)std::max<long long>(1, std::min<long long>(512, (etot + 255) / 256));
+  pa.eblocks = (int)std::max<long long>(1, std::min<long long>(std::min<long long>(256, h->N[1]), (etot + 255) / 256));
+  const long long per = (h->N[1] + pa.eblocks - 1) / pa.eblocks;
+  const size_t elds = ((size_t)h->r[0] * h->r[1] * h->N[2] + (size_t)per * h->r[1]) * 8;
+  if (elds > (size_t)h->lds_max) { h->err = "error-pass expansion does not fit in LDS"; return TDB_EUNSUPPORTED; }
+  lds = std::max(lds, elds);
   pa.C = h->C0;
   pa.E = h->E;
   pa.U1c = h->U1c;
@@ -781,6 +810,7 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
   fa.need_h1 = h->r[0] < h->N[0];
   fa.need_h2 = h->r[1] < h->N[1];
   fa.need_f3 = h->r[2] < h->N[2];
+  fa.stage_p = pl.stage_p;
   fa.slot = pl.slot;
   fa.B1 = h->B[0]; fa.B2 = h->B[1]; fa.B3 = h->B[2];
   fa.P1 = h->P[0]; fa.P2 = h->P[1]; fa.P3 = h->P[2];
@@ -792,32 +822,36 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
   ra.need_h1 = fa.need_h1; ra.need_h2 = fa.need_h2; ra.need_f3 = fa.need_f3;
   ra.slot = pl.slot;
   ra.part = h->fpart;
-  ra.C0 = h->C0; ra.Cs = h->Cs; ra.kC = h->kC;
+  ra.C0 = h->C0; ra.Cs = h->Cs; ra.kC = h->kC; ra.Cdot2 = h->Cdot2;
   FFinishArgs ga{};
   bool cil = false;
   const size_t slds = small_lds(h, &cil);
   ga.core_in_lds = cil ? 1 : 0;
+  ga.rmax = max_rank(h);
   ga.dt = h->cfg.dt;
   long long rows = 0;
   for (int n = 0; n < 3; ++n) rows += h->N[n] * h->r[n];
   ga.rowblocks = (int)std::max<long long>(1, std::min<long long>(1024, (rows + 255) / 256));
   ga.Cs = h->Cs;
+  ga.kC = h->kC;
+  ga.Cdot2 = h->Cdot2;
   for (int n = 0; n < 3; ++n) {
     ra.H[n] = h->H[n];
-    ra.M[n] = h->Mred[n];
     ga.N[n] = h->N[n];
     ga.r[n] = h->r[n];
     ga.ldU[n] = h->ldU[n];
     ga.H[n] = h->H[n];
-    ga.M[n] = h->Mred[n];
     ga.w[n] = h->w[n];
     ga.U0[n] = h->U0[n];
     ga.Us[n] = h->Us[n];
     ga.kU[n] = h->kU[n];
     ga.B[n] = h->B[n];
-    ga.P[n] = h->P[n];
+    ga.P[n] = h->P2[n];
   }
   for (int stage = 1; stage <= 2; ++stage) {
+    void* const* Pst = stage == 1 ? h->P : h->P2;
+    fa.P1 = Pst[0]; fa.P2 = Pst[1]; fa.P3 = Pst[2];
+    for (int n = 0; n < 3; ++n) ga.Pcur[n] = Pst[n];
     {
       PassTimer pt(h, TDB_PASS_PROJECT, s);
       HIPCHK((launch_fpass<TD, T>(fa, pl.lds, s)));
@@ -828,7 +862,10 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
     HIPCHK(launch_ffinish<T>(ga, slds, h->ctrl, s));
   }
   FQrArgs qa{};
-  size_t qlds = 3 * (size_t)TDB_RCAP * TDB_RCAP * 8;
+  qa.rmax = max_rank(h);
+  qa.rounds = 1;
+  const size_t npq = (size_t)qa.rmax * (qa.rmax + 1) / 2;
+  size_t qlds = (4 * (size_t)qa.rmax * qa.rmax + 4 * npq + TDB_NEIG) * 8;
   size_t ustage = 0;
   for (int n = 0; n < 3; ++n) {
     const size_t need = (size_t)h->N[n] * h->r[n] * 8;
@@ -841,6 +878,9 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
     qa.w[n] = h->w[n];
     qa.Rq[n] = h->Rq[n];
   }
+  const size_t cneed = 2 * (size_t)prod_ll(h->r, 3) * 8;
+  qa.core_in_lds = qlds + cneed <= (size_t)h->lds_max ? 1 : 0;
+  if (qa.core_in_lds) ustage = std::max(ustage, cneed);
   qa.C0 = h->C0;
   qa.Ctmp = h->Ctmp;
   qa.counter = h->counters;

@@ -18,6 +18,11 @@ enum { DEC_NONE = 0, DEC_ADD = 1, DEC_REMOVE = 2, DEC_NUMERIC = 3, DEC_INIT = 4 
 // A direction whose full-data singular value is below this fraction of its mode's
 // largest is numerically absent: adding it would make a core Gram matrix singular.
 #define TDB_SIGMA_FLOOR 1e-6
+// Jacobi rotations are skipped once |a_pq| <= TDB_JACOBI_TOL max_i |a_ii|: a few units
+// of roundoff relative to the matrix norm, the accuracy any backward-stable symmetric
+// eigensolver reaches (a tolerance relative to sqrt(a_pp a_qq) is never met by pairs
+// of tiny diagonal entries next to large ones, and the sweeps would not terminate).
+#define TDB_JACOBI_TOL 4e-16
 // Core Gram matrices whose smallest Cholesky pivot falls below this fraction of the
 // largest diagonal entry are treated as singular (a numerical event).
 #define TDB_PIVOT_FLOOR 1e-12
