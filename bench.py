@@ -25,6 +25,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
+# HBM bytes per stage-pass launch from hardware counters (FETCH_SIZE / WRITE_SIZE,
+# calibrated against a copy of known size); ignored once the kernel's sources change.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_pass_plume512x256x8_fp32.txt")
 METRIC = "snapshots/s ingested + HBM GB/s vs plain FP64 GPU at <=1e-6 rel err"
 
 
@@ -106,6 +109,9 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=200,
                     help="steps of the plain FP64 GPU path timed for comparison (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 256 MiB device-to-device copy (a known-size reference for "
+                         "hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, "
@@ -119,6 +125,13 @@ def main():
     print(f"[bench] generating {args.warmup + args.steps + 1} snapshots on the device", file=sys.stderr,
           flush=True)
     snaps = _make_snapshots(sp, args.warmup + args.steps + 1, "cuda")
+    if args.calibrate_copy:
+        x = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     print("[bench] timed run", file=sys.stderr, flush=True)
     el, st, prof = _run_gpu(sp, snaps, args.warmup, args.steps, args.precision, args.path)
     value = args.steps / el
@@ -127,6 +140,10 @@ def main():
     achieved = pj["bytes_per_launch"] / avg_s / 1e9 if avg_s > 0 else 0.0
     er = prof["error"]
     er_avg_s = er["total_ms"] / max(er["launches"], 1) * 1e-3
+    traffic = None
+    if args.precision == "f32" and args.path != "plain":
+        from paper_2201_06958_amd.profsum import read_pass_traffic
+        traffic = read_pass_traffic(TRAFFIC_FILE)
     plain = None
     if args.plain_steps > 0:
         print("[bench] plain FP64 GPU path", file=sys.stderr, flush=True)
@@ -144,7 +161,11 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
         "config": dict(desc, path=args.path, precision=args.precision),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic["traffic_bytes"] if traffic else None,
+                     "traffic_unit": "bytes/launch",
+                     "traffic_read_write": ([traffic["read_bytes"], traffic["write_bytes"]]
+                                            if traffic else None),
                      "kernel": "stage projection pass (one Heun stage)",
                      "avg_launch_us": avg_s * 1e6, "launches": pj["launches"],
                      "algorithmic_bytes_per_launch": pj["bytes_per_launch"]},

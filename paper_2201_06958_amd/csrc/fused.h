@@ -86,8 +86,10 @@ struct FErrArgs {
   unsigned* counter;
 };
 
+// ev0/ev1 (may be null): events stamped by the dispatch itself at kernel start and end.
 template <typename TD, typename T>
-hipError_t launch_fpass(const FPassArgs& a, size_t lds, hipStream_t s);
+hipError_t launch_fpass(const FPassArgs& a, size_t lds, hipStream_t s, hipEvent_t ev0 = nullptr,
+                        hipEvent_t ev1 = nullptr);
 template <typename T>
 hipError_t launch_freduce(const FReduceArgs& a, CtrlState* c, hipStream_t s);
 template <typename T>
@@ -96,6 +98,7 @@ hipError_t launch_fqr(const FQrArgs& a, size_t lds, CtrlState* c, hipStream_t s)
 template <typename T>
 hipError_t launch_fpost(const FPostArgs& a, size_t lds, CtrlState* c, hipStream_t s);
 template <typename TD, typename T>
-hipError_t launch_ferr(const FErrArgs& a, CtrlState* c, hipStream_t s);
+hipError_t launch_ferr(const FErrArgs& a, CtrlState* c, hipStream_t s, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr);
 
 }  // namespace tdb

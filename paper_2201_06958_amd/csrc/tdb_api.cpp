@@ -636,21 +636,28 @@ hipEvent_t take_event(tdb_ctx* h) {
   return e;
 }
 
-// Brackets a pass with events when profiling is on.
+// Times a pass with a pair of events when profiling is on. By default the events
+// bracket the pass on the stream; with by_dispatch the launcher hands them to the
+// kernel dispatch itself (start and end of that one kernel), which leaves out any
+// time the queue waits for the host to submit it.
 struct PassTimer {
   tdb_ctx* h;
   int pass;
   hipStream_t s;
+  bool by_dispatch;
   hipEvent_t a = nullptr, b = nullptr;
-  PassTimer(tdb_ctx* h_, int pass_, hipStream_t s_) : h(h_), pass(pass_), s(s_) {
+  PassTimer(tdb_ctx* h_, int pass_, hipStream_t s_, bool by_dispatch_ = false)
+      : h(h_), pass(pass_), s(s_), by_dispatch(by_dispatch_) {
     if (!h->prof) return;
     a = take_event(h);
     b = take_event(h);
-    if (a && b) (void)hipEventRecord(a, s);
+    if (a && b && !by_dispatch) (void)hipEventRecord(a, s);
   }
+  hipEvent_t start() const { return a && b ? a : nullptr; }
+  hipEvent_t stop() const { return a && b ? b : nullptr; }
   ~PassTimer() {
     if (!a || !b) return;
-    (void)hipEventRecord(b, s);
+    if (!by_dispatch) (void)hipEventRecord(b, s);
     h->ev_used[pass].push_back({a, b});
   }
 };
@@ -853,8 +860,8 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
     fa.P1 = Pst[0]; fa.P2 = Pst[1]; fa.P3 = Pst[2];
     for (int n = 0; n < 3; ++n) ga.Pcur[n] = Pst[n];
     {
-      PassTimer pt(h, TDB_PASS_PROJECT, s);
-      HIPCHK((launch_fpass<TD, T>(fa, pl.lds, s)));
+      PassTimer pt(h, TDB_PASS_PROJECT, s, true);
+      HIPCHK((launch_fpass<TD, T>(fa, pl.lds, s, pt.start(), pt.stop())));
     }
     ra.stage = stage;
     HIPCHK(launch_freduce<T>(ra, h->ctrl, s));
@@ -901,8 +908,8 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
   ea.part = h->ferr_part;
   ea.counter = h->counters + 1;
   {
-    PassTimer pt(h, TDB_PASS_ERROR, s);
-    HIPCHK((launch_ferr<TD, T>(ea, h->ctrl, s)));
+    PassTimer pt(h, TDB_PASS_ERROR, s, true);
+    HIPCHK((launch_ferr<TD, T>(ea, h->ctrl, s, pt.start(), pt.stop())));
   }
   TRY(pull_ctrl(h, s));
   h->step += 1;

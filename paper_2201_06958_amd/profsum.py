@@ -1,0 +1,181 @@
+"""Text summaries of rocprofv3 result databases for the library's kernels.
+
+    python -m paper_2201_06958_amd.profsum stats DB --command CMD [--bench JSON] [--out FILE]
+    python -m paper_2201_06958_amd.profsum pmc FETCH_DB WRITE_DB --command-fetch CMD
+        --command-write CMD [--copy-bytes N] [--out FILE]
+
+`stats` tabulates per-kernel call counts and average durations from a
+`rocprofv3 --kernel-trace --stats` run (and, given the JSON lines bench.py printed
+with and without the profiler, the stage-pass launch duration bench.py measured itself
+with dispatch-stamped HIP events, so the two clocks can be compared).
+
+`pmc` turns two counter runs (`--pmc FETCH_SIZE`, then `--pmc WRITE_SIZE`, each with
+`--kernel-trace`) into HBM bytes per dispatch. The raw counters are scaled by what
+they read for the largest device-to-device copy in the same run, whose size is known
+(`bench.py --calibrate-copy` issues a 256 MiB copy): read scale = bytes / FETCH
+reading, write scale = bytes / WRITE reading. The record line at the end of the
+output carries the stage-pass figures and a digest of the sources that kernel is
+built from, so a reader can tell when they no longer describe the current kernel.
+
+Only the standard library is used; nothing here touches the GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sqlite3
+from collections import defaultdict
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+# The stage pass and everything it includes.
+PASS_SOURCES = ("fused_pass.hip", "fused.h", "tdb_common.h", "tdb_kernels.h", "device_util.h")
+PASS_KERNEL = "k_fpass<float, float>"
+
+
+def pass_source_digest() -> str:
+    h = hashlib.sha256()
+    for name in PASS_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _short(name: str) -> str:
+    name = name.replace("void ", "")
+    cut = name.find("(")
+    return name if cut < 0 else name[:cut]
+
+
+def _bench_line(path: str) -> dict:
+    with open(path) as f:
+        line = [ln for ln in f.read().splitlines() if ln.startswith("{")][-1]
+    return json.loads(line)
+
+
+def stats_text(db: str, command: str, bench_json: str | None = None, bench_plain: str | None = None,
+               top: int = 30) -> str:
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, total_calls, total_duration, average, percentage "
+                       "from top_kernels order by total_duration desc").fetchall()
+    out = ["# rocprofv3 --kernel-trace --stats", "", "command:", f"    {command}", "",
+           "durations in microseconds (top_kernels table of the result database)", "",
+           f"{'kernel':60s} {'calls':>7s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}"]
+    for name, calls, total, avg, pct in rows[:top]:
+        out.append(f"{_short(name)[:60]:60s} {calls:7d} {avg:10.2f} {total / 1e3:10.3f} {pct:6.2f}")
+    prof = [r for r in rows if PASS_KERNEL in r[0]]
+    if bench_json:
+        b = _bench_line(bench_json)
+        rf = b["roofline"]
+        out += ["", "bench.py line printed by the profiled run:",
+                f"    value {b['value']:.1f} {b['unit']}, ms_per_step {b['ms_per_step']:.4f}",
+                f"    stage pass average launch (HIP events in bench.py): {rf['avg_launch_us']:.2f} us"
+                f" over {rf['launches']} launches"]
+        if prof:
+            out.append(f"    stage pass average (this trace, all launches incl. warmup): {prof[0][3]:.2f} us"
+                       f" over {prof[0][1]} launches")
+        out.append("    (under the tracer the dispatch-stamped events include its per-dispatch overhead)")
+    if bench_plain:
+        b = _bench_line(bench_plain)
+        rf = b["roofline"]
+        out += ["", "bench.py without the profiler (same build, same workload):",
+                f"    value {b['value']:.1f} {b['unit']} over {b['steps']} steps",
+                f"    stage pass average launch (HIP events): {rf['avg_launch_us']:.2f} us over "
+                f"{rf['launches']} launches -> {rf['achieved']:.1f} GB/s algorithmic"]
+    return "\n".join(out) + "\n"
+
+
+def _per_kernel(db: str):
+    con = sqlite3.connect(db)
+    rows = con.execute("select kernel_name, grid_size, value from counters_collection").fetchall()
+    agg = defaultdict(list)
+    for k, g, v in rows:
+        agg[(k, g)].append(v)
+    return agg
+
+
+def _calibration(agg):
+    copies = [(k, vals) for k, vals in agg.items() if "copyBuffer" in k[0]]
+    if not copies:
+        raise SystemExit("no copy kernel in the counter run: run bench.py with --calibrate-copy")
+    k, vals = max(copies, key=lambda kv: max(kv[1]))
+    return max(vals)
+
+
+def pmc_text(fetch_db: str, write_db: str, cmd_f: str, cmd_w: str, copy_bytes: int):
+    fa, wa = _per_kernel(fetch_db), _per_kernel(write_db)
+    f_cal, w_cal = _calibration(fa), _calibration(wa)
+    f_scale = copy_bytes / 1024.0 / f_cal
+    w_scale = copy_bytes / 1024.0 / w_cal
+    out = ["# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (HBM traffic per dispatch)", "",
+           "commands:", f"    {cmd_f}", f"    {cmd_w}", "",
+           f"calibration: a {copy_bytes} B device-to-device copy reads FETCH_SIZE {f_cal:.1f} KiB "
+           f"and WRITE_SIZE {w_cal:.1f} KiB",
+           f"    read scale {f_scale:.4f}, write scale {w_scale:.4f} (bytes = KiB reading x 1024 x scale)", "",
+           f"{'kernel':48s} {'grid':>9s} {'n':>5s} {'read_KiB':>11s} {'write_KiB':>11s}"]
+    record = None
+    keys = sorted(set(fa) | set(wa), key=lambda k: (-len(fa.get(k, [])), k))
+    for k in keys:
+        if "tdb::" not in k[0]:
+            continue
+        fv, wv = fa.get(k, [0.0]), wa.get(k, [0.0])
+        rd = sum(fv) / len(fv) * f_scale
+        wr = sum(wv) / len(wv) * w_scale
+        out.append(f"{_short(k[0])[:48]:48s} {k[1]:9d} {len(fv):5d} {rd:11.1f} {wr:11.1f}")
+        if PASS_KERNEL in k[0] and (record is None or len(fv) > record["dispatches"]):
+            record = {"kernel": PASS_KERNEL, "dispatches": len(fv), "read_bytes": rd * 1024.0,
+                      "write_bytes": wr * 1024.0, "traffic_bytes": (rd + wr) * 1024.0,
+                      "read_scale": f_scale, "write_scale": w_scale,
+                      "source_digest": pass_source_digest()}
+    if record is not None:
+        out += ["", "record: " + json.dumps(record)]
+    return "\n".join(out) + "\n", record
+
+
+def read_pass_traffic(path: str):
+    """The stage-pass record of a `pmc` summary, or None when the file is missing or
+    the kernel's sources have changed since the counters were taken."""
+    try:
+        with open(path) as f:
+            lines = [ln for ln in f.read().splitlines() if ln.startswith("record: ")]
+    except OSError:
+        return None
+    if not lines:
+        return None
+    rec = json.loads(lines[-1][len("record: "):])
+    if rec.get("source_digest") != pass_source_digest():
+        return None
+    return rec
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("db")
+    s.add_argument("--command", required=True)
+    s.add_argument("--bench", help="stdout of the profiled bench.py run")
+    s.add_argument("--bench-plain", help="JSON line of an unprofiled bench.py run of the same build")
+    s.add_argument("--out")
+    p = sub.add_parser("pmc")
+    p.add_argument("fetch_db")
+    p.add_argument("write_db")
+    p.add_argument("--command-fetch", required=True)
+    p.add_argument("--command-write", required=True)
+    p.add_argument("--copy-bytes", type=int, default=256 * 1024 * 1024)
+    p.add_argument("--out")
+    a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        text = stats_text(a.db, a.command, a.bench, a.bench_plain)
+    else:
+        text, _ = pmc_text(a.fetch_db, a.write_db, a.command_fetch, a.command_write, a.copy_bytes)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(text)
+    print(text, end="")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,52 @@
+"""Host logic of the rocprofv3 summary module (no GPU): counter calibration against a
+copy of known size, the stage-pass record and its source-digest check."""
+import json
+import sqlite3
+
+from paper_2201_06958_amd import profsum
+
+
+def _counter_db(path, rows):
+    con = sqlite3.connect(path)
+    con.execute("create table counters_collection (kernel_name text, grid_size int, value real)")
+    con.executemany("insert into counters_collection values (?, ?, ?)", rows)
+    con.commit()
+    con.close()
+
+
+def test_pmc_scaling_and_record(tmp_path):
+    copy = "__amd_rocclr_copyBuffer"
+    kpass = "void tdb::k_fpass<float, float>(tdb::FPassArgs)"
+    # the copy of 1 MiB reads as 512 KiB on FETCH and 1024 KiB on WRITE -> scales 2 and 1
+    f = tmp_path / "f.db"
+    w = tmp_path / "w.db"
+    _counter_db(f, [(copy, 4096, 512.0), (copy, 64, 1.0), (kpass, 1000, 100.0), (kpass, 1000, 110.0)])
+    _counter_db(w, [(copy, 4096, 1024.0), (copy, 64, 1.0), (kpass, 1000, 20.0), (kpass, 1000, 20.0)])
+    text, rec = profsum.pmc_text(str(f), str(w), "cmd f", "cmd w", 1024 * 1024)
+    assert abs(rec["read_scale"] - 2.0) < 1e-12 and abs(rec["write_scale"] - 1.0) < 1e-12
+    assert abs(rec["read_bytes"] - 105.0 * 2 * 1024) < 1e-6
+    assert abs(rec["write_bytes"] - 20.0 * 1024) < 1e-6
+    assert rec["source_digest"] == profsum.pass_source_digest()
+    out = tmp_path / "traffic.txt"
+    out.write_text(text)
+    assert profsum.read_pass_traffic(str(out))["traffic_bytes"] == rec["traffic_bytes"]
+    # a record taken from other sources is ignored
+    stale = dict(rec, source_digest="0" * 16)
+    out.write_text(text + "record: " + json.dumps(stale) + "\n")
+    assert profsum.read_pass_traffic(str(out)) is None
+    assert profsum.read_pass_traffic(str(tmp_path / "missing.txt")) is None
+
+
+def test_stats_text(tmp_path):
+    db = tmp_path / "s.db"
+    con = sqlite3.connect(db)
+    con.execute("create table top_kernels (name text, total_calls int, total_duration real, "
+                "average real, percentage real)")
+    con.executemany("insert into top_kernels values (?, ?, ?, ?, ?)",
+                    [("void tdb::k_fpass<float, float>(tdb::FPassArgs)", 10, 450.0, 45.0, 60.0),
+                     ("tdb::k_fqr(tdb::FQrArgs, CtrlState*)", 5, 300.0, 60.0, 40.0)])
+    con.commit()
+    con.close()
+    text = profsum.stats_text(str(db), "the command")
+    assert "tdb::k_fpass<float, float>" in text and "the command" in text
+    assert text.index("k_fpass") < text.index("k_fqr")
