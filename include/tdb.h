@@ -149,6 +149,39 @@ tdb_status tdb_profile_enable(tdb_handle h, int32_t on);
 tdb_status tdb_profile_read(tdb_handle h, int32_t pass, int64_t* launches, double* total_ms,
                             double* bytes_per_launch);
 
+/* ---- Many independent streams in one set of launches.
+ * Each stream is its own TDB of a third-order tensor (Sec. 2; the stochastic flow of
+ * Sec. 3.3 has one field per sample, here taken as independent streams of uneven
+ * sizes). A batch step runs every kernel of a fused step once for all streams, with
+ * tile shapes, grids and LDS sized at each stream's rank caps so that the launch
+ * sequence does not change when ranks do; the host reads one small summary per
+ * stream per step and reinitialises only the streams whose controller decided so.
+ *
+ * tdb_batch_create: n >= 1 configurations (order 3, path AUTO or FUSED, one common
+ *   data_dtype and precision) and n device snapshots V0_dev[i]; runs each stream's
+ *   HOSVD initialisation. TDB_EUNSUPPORTED when a stream's stage pass does not fit
+ *   the LDS at its caps.
+ * tdb_batch_ingest: V_dev is a host array of n device pointers, one snapshot per
+ *   stream, each C-contiguous in data_dtype. Snapshot ownership as in
+ *   tdb_ingest_snapshot, per stream.
+ * tdb_batch_stream: a handle of stream i for tdb_get_stats, tdb_get_core_and_bases,
+ *   tdb_reconstruct and tdb_set_threshold. The batch owns it: tdb_ingest_snapshot on
+ *   it returns TDB_ESTATE and tdb_destroy ignores it.
+ * tdb_batch_profile_enable / _read: as tdb_profile_enable / _read for the batched
+ *   stage pass and error pass (one launch covers all streams; the bytes per launch
+ *   are summed over streams).
+ * tdb_batch_destroy frees the batch and all its streams; NULL-safe. */
+typedef struct tdb_batch_ctx* tdb_batch;
+tdb_status tdb_batch_create(int32_t n, const tdb_config* cfgs, const void* const* V0_dev, void* stream,
+                            tdb_batch* out);
+tdb_status tdb_batch_ingest(tdb_batch b, const void* const* V_dev, void* stream);
+tdb_status tdb_batch_stream(tdb_batch b, int32_t i, tdb_handle* out);
+tdb_status tdb_batch_profile_enable(tdb_batch b, int32_t on);
+tdb_status tdb_batch_profile_read(tdb_batch b, int32_t pass, int64_t* launches, double* total_ms,
+                                  double* bytes_per_launch);
+void tdb_batch_destroy(tdb_batch b);
+const char* tdb_batch_last_error(tdb_batch b);
+
 /* Layout check for language bindings: writes sizeof(tdb_config) and sizeof(tdb_stats)
  * (either pointer may be NULL). Needs no device. */
 void tdb_struct_sizes(int64_t* config_bytes, int64_t* stats_bytes);

@@ -101,4 +101,43 @@ template <typename TD, typename T>
 hipError_t launch_ferr(const FErrArgs& a, CtrlState* c, hipStream_t s, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr);
 
+// ---------------------------------------------------------------- batched streams
+// Many independent streams in one launch per kernel: the global block index selects
+// a stream through `sid` and the block's index inside that stream's grid through
+// `start` (first global block of each stream, n + 1 entries). The per-stream
+// argument structs live in device tables; snapshot pointers come from their own
+// per-step tables.
+struct BatchMap {
+  const int* sid;
+  const int* start;
+};
+
+// What the host needs from each stream after a batched step.
+struct BatchSummary {
+  int decision, event, numeric, pad;
+  int n_events[5];
+  int pad2;
+  double eps, nu, eps2, nu2;
+};
+
+template <typename TD, typename T>
+hipError_t launch_batch_fpass(const FPassArgs* tab, const void* const* v1, const void* const* v0, BatchMap m,
+                              int blocks, size_t lds, hipStream_t s, hipEvent_t ev0 = nullptr,
+                              hipEvent_t ev1 = nullptr);
+template <typename T>
+hipError_t launch_batch_freduce(const FReduceArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, int stage,
+                                hipStream_t s);
+template <typename T>
+hipError_t launch_batch_ffinish(const FFinishArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, int stage,
+                                size_t lds, hipStream_t s);
+hipError_t launch_batch_fqr(const FQrArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, size_t lds,
+                            hipStream_t s);
+template <typename T>
+hipError_t launch_batch_fpost(const FPostArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, size_t lds,
+                              hipStream_t s);
+template <typename TD, typename T>
+hipError_t launch_batch_ferr(const FErrArgs* tab, const void* const* v1, BatchMap m, int blocks, int nstreams,
+                             CtrlState* const* ctab, BatchSummary* out, hipStream_t s, hipEvent_t ev0 = nullptr,
+                             hipEvent_t ev1 = nullptr);
+
 }  // namespace tdb

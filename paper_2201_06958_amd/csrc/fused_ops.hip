@@ -52,11 +52,11 @@ __device__ __forceinline__ double sum_strided(const T* __restrict__ p, long long
 // applies the Heun update to the core (stage 1: k = C_dot/dt, C* = C + dt k;
 // stage 2: C <- C + dt/2 (k + C_dot/dt)).
 template <typename T>
-__global__ void __launch_bounds__(256) k_freduce(FReduceArgs a, CtrlState* ctrl) {
+__device__ __forceinline__ void freduce_body(const FReduceArgs& a, CtrlState* ctrl, int bx, int gx) {
   if (a.stage == 2 && ctrl->numeric) return;
   // A singular core found while preparing this step (bit 4, set by k_fpost) belongs
   // to this step's first stage, like the failure of its pseudo-inverse would.
-  if (a.stage == 1 && blockIdx.x == 0 && threadIdx.x == 0 && (ctrl->numeric & 4)) ctrl->numeric = 1;
+  if (a.stage == 1 && bx == 0 && threadIdx.x == 0 && (ctrl->numeric & 4)) ctrl->numeric = 1;
   const T* part = static_cast<const T*>(a.part);
   const long long nH1 = a.need_h1 ? (long long)a.N1 * a.r1 : 0;
   const long long nH2 = a.need_h2 ? (long long)a.N2 * a.r2 : 0;
@@ -67,8 +67,8 @@ __global__ void __launch_bounds__(256) k_freduce(FReduceArgs a, CtrlState* ctrl)
   const long long oH2 = (long long)a.T1 * a.r1, oH3 = oH2 + (long long)a.T2 * a.r2;
   const long long oC = oH3 + (long long)a.N3 * a.r3;
   const double inv_dt = 1.0 / a.dt;
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-       t += (long long)gridDim.x * blockDim.x) {
+  for (long long t = (long long)bx * blockDim.x + threadIdx.x; t < total;
+       t += (long long)gx * blockDim.x) {
     double s = 0.0;
     long long q = t;
     if (q < nH1) {
@@ -107,6 +107,11 @@ __global__ void __launch_bounds__(256) k_freduce(FReduceArgs a, CtrlState* ctrl)
       }
     }
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_freduce(FReduceArgs a, CtrlState* ctrl) {
+  freduce_body<T>(a, ctrl, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------- prep helpers
@@ -239,12 +244,12 @@ __device__ void write_p(const double* Cl, const double* Gi, int rn, long long R,
 // Blocks [rowblocks, rowblocks + 3) (stage 1 only): pseudo-inverse P_n at the stage
 // core C* (already updated by the reduction).
 template <typename T>
-__global__ void __launch_bounds__(256) k_ffinish(FFinishArgs a, CtrlState* ctrl) {
+__device__ __forceinline__ void ffinish_body(const FFinishArgs& a, CtrlState* ctrl, int bx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
   if (a.stage == 2 && ctrl->numeric) return;
   const double inv_dt = 1.0 / a.dt;
-  if ((int)blockIdx.x < a.rowblocks) {
+  if ((int)bx < a.rowblocks) {
     // M_n = U_n^T W_n F_(n) P_n = Cdot_(n) P_n (the same r x r matrix every block needs):
     // stage C_dot and P_n in LDS, then contract with nested (outer, inner) loops
     double* Ml[3];
@@ -297,7 +302,7 @@ __global__ void __launch_bounds__(256) k_ffinish(FFinishArgs a, CtrlState* ctrl)
     __syncthreads();
     long long tot = 0;
     for (int n = 0; n < 3; ++n) tot += a.N[n] * a.r[n];
-    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot;
+    for (long long t = (long long)bx * blockDim.x + threadIdx.x; t < tot;
          t += (long long)a.rowblocks * blockDim.x) {
       long long q = t;
       int n = 0;
@@ -326,7 +331,7 @@ __global__ void __launch_bounds__(256) k_ffinish(FFinishArgs a, CtrlState* ctrl)
     return;
   }
   // pseudo-inverse at the stage core
-  const int n = blockIdx.x - a.rowblocks;
+  const int n = bx - a.rowblocks;
   const int rn = a.r[n];
   if (rn >= a.N[n]) return;
   long long inner = 1, R = 1, csz = 1;
@@ -364,6 +369,11 @@ __global__ void __launch_bounds__(256) k_ffinish(FFinishArgs a, CtrlState* ctrl)
   write_p<T>(Csrc, Gi, rn, R, inner, static_cast<T*>(a.P[n]));
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_ffinish(FFinishArgs a, CtrlState* ctrl) {
+  ffinish_body<T>(a, ctrl, blockIdx.x);
+}
+
 // ---------------------------------------------------------------- QR + fold
 // Block n: Cholesky QR of U_n in the W inner product (one round: the Heun update leaves
 // U_n W-orthonormal to O(dt^2), so a single round already reaches roundoff; a second
@@ -372,7 +382,7 @@ __global__ void __launch_bounds__(256) k_ffinish(FFinishArgs a, CtrlState* ctrl)
 // a fixed order), its Cholesky factor R^T R and R^-1 by one wave, then U <- U R^-1
 // row by row; R accumulates over the rounds. The last block to finish folds every
 // R_n into the core (C <- C x_n R_n), so the reconstruction is unchanged.
-__global__ void __launch_bounds__(256) k_fqr(FQrArgs a, CtrlState* ctrl) {
+__device__ __forceinline__ void fqr_body(const FQrArgs& a, CtrlState* ctrl, int bx, int gx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
   __shared__ int last, skip_s, ok_s;
@@ -382,7 +392,7 @@ __global__ void __launch_bounds__(256) k_fqr(FQrArgs a, CtrlState* ctrl) {
     skip_s = __hip_atomic_load(&ctrl->numeric, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
   __syncthreads();
   const bool skip = skip_s != 0;
-  const int n = blockIdx.x;
+  const int n = bx;
   const int rn = a.r[n], ld = a.ldU[n];
   const int Nn = (int)a.N[n];
   const int rq = a.rmax;
@@ -497,7 +507,7 @@ __global__ void __launch_bounds__(256) k_fqr(FQrArgs a, CtrlState* ctrl) {
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned prev = __hip_atomic_fetch_add(a.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (prev == gridDim.x - 1) ? 1 : 0;
+    last = (prev == gx - 1) ? 1 : 0;
   }
   __syncthreads();
   if (!last) return;
@@ -535,20 +545,24 @@ __global__ void __launch_bounds__(256) k_fqr(FQrArgs a, CtrlState* ctrl) {
   for (int t = threadIdx.x; t < csz; t += blockDim.x) a.C0[t] = ca[t];
 }
 
+__global__ void __launch_bounds__(256) k_fqr(FQrArgs a, CtrlState* ctrl) {
+  fqr_body(a, ctrl, blockIdx.x, gridDim.x);
+}
+
 // ---------------------------------------------------------------- post-step
 // Blocks [0, 3): for mode n at the new state: core singular values (Jacobi, into the
 // controller), pseudo-inverse P_n and weighted basis B_n for the next stage 1.
 // Blocks [3, 3 + eblocks): the partial expansion E = C x_2 U_2 x_3 U_3 used by the
 // error pass, and the mode-1 basis in the compute type.
 template <typename T>
-__global__ void __launch_bounds__(256) k_fpost(FPostArgs a, CtrlState* ctrl) {
+__device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, int bx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
   __shared__ int pairs[TDB_RCAP + 2];
   __shared__ int order[TDB_RCAP];
-  if ((int)blockIdx.x >= 3) {
+  if ((int)bx >= 3) {
     // E[a][i2][i3] = sum_b U2[i2][b] T3[a][b][i3],  T3[a][b][i3] = sum_c C[a][b][c] U3[i3][c]
-    const int eb = blockIdx.x - 3;
+    const int eb = bx - 3;
     const int r1 = a.r[0], r2 = a.r[1], r3 = a.r[2];
     const long long N2 = a.N[1], N3 = a.N[2];
     double* T3 = lds;                                   // r1*r2*N3
@@ -590,7 +604,7 @@ __global__ void __launch_bounds__(256) k_fpost(FPostArgs a, CtrlState* ctrl) {
     }
     return;
   }
-  const int n = blockIdx.x;
+  const int n = bx;
   const int rn = a.r[n];
   long long inner = 1, R = 1, csz = 1;
   for (int k = 0; k < 3; ++k) {
@@ -650,17 +664,22 @@ __global__ void __launch_bounds__(256) k_fpost(FPostArgs a, CtrlState* ctrl) {
   write_p<T>(Csrc, Gi, rn, R, inner, static_cast<T*>(a.P[n]));
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_fpost(FPostArgs a, CtrlState* ctrl) {
+  fpost_body<T>(a, ctrl, blockIdx.x);
+}
+
 // ---------------------------------------------------------------- error pass
 // Tile = T1 slabs of mode 1. rec[i1][j] = sum_a U1[i1][a] E[a][j] (j over modes 2,3);
 // partial sums of w (V - rec)^2 and w V^2 in FP64; the last block reduces them and
 // runs the controller decision.
 template <typename TD, typename T>
-__global__ void __launch_bounds__(256) k_ferr(FErrArgs a, CtrlState* ctrl) {
+__device__ __forceinline__ void ferr_body(const FErrArgs& a, int bx, int by, int gx) {
   __shared__ double red[16];
   __shared__ double U1s[FERR_T1 * TDB_RCAP];
   const long long M = a.M;      // N2*N3
   const int r1 = a.r1;
-  const int i1_0 = blockIdx.y * a.T1;
+  const int i1_0 = by * a.T1;
   const int n1 = min(a.T1, a.N1 - i1_0);
   const T* E = static_cast<const T*>(a.E);
   for (int t = threadIdx.x; t < FERR_T1 * r1; t += blockDim.x) {
@@ -669,7 +688,7 @@ __global__ void __launch_bounds__(256) k_ferr(FErrArgs a, CtrlState* ctrl) {
   }
   __syncthreads();
   double se = 0.0, sv = 0.0;
-  for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < M; j += (long long)gridDim.x * blockDim.x) {
+  for (long long j = (long long)bx * blockDim.x + threadIdx.x; j < M; j += (long long)gx * blockDim.x) {
     T acc[FERR_T1];
     for (int q = 0; q < FERR_T1; ++q) acc[q] = (T)0;
     for (int ai = 0; ai < r1; ++ai) {
@@ -690,11 +709,16 @@ __global__ void __launch_bounds__(256) k_ferr(FErrArgs a, CtrlState* ctrl) {
   }
   se = block_sum(se, red);
   sv = block_sum(sv, red);
-  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  const int bid = by * gx + bx;
   if (threadIdx.x == 0) {
     a.part[2 * bid] = se;
     a.part[2 * bid + 1] = sv;
   }
+}
+
+template <typename TD, typename T>
+__global__ void __launch_bounds__(256) k_ferr(FErrArgs a, CtrlState* ctrl) {
+  ferr_body<TD, T>(a, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // One block: fixed-order sum of the error-pass partials, then the controller.
@@ -771,5 +795,143 @@ template hipError_t launch_ferr<float, float>(const FErrArgs&, CtrlState*, hipSt
 template hipError_t launch_ferr<float, double>(const FErrArgs&, CtrlState*, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_ferr<double, double>(const FErrArgs&, CtrlState*, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_ferr<double, float>(const FErrArgs&, CtrlState*, hipStream_t, hipEvent_t, hipEvent_t);
+
+// ---------------------------------------------------------------- batched forms
+template <typename T>
+__global__ void __launch_bounds__(256) kb_freduce(const FReduceArgs* __restrict__ tab, CtrlState* const* ctab,
+                                                  BatchMap m, int stage) {
+  const int s = m.sid[blockIdx.x];
+  FReduceArgs a = tab[s];
+  a.stage = stage;
+  const int b0 = m.start[s];
+  freduce_body<T>(a, ctab[s], blockIdx.x - b0, m.start[s + 1] - b0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) kb_ffinish(const FFinishArgs* __restrict__ tab, CtrlState* const* ctab,
+                                                  BatchMap m, int stage) {
+  const int s = m.sid[blockIdx.x];
+  FFinishArgs a = tab[s];
+  a.stage = stage;
+  ffinish_body<T>(a, ctab[s], blockIdx.x - m.start[s]);
+}
+
+__global__ void __launch_bounds__(256) kb_fqr(const FQrArgs* __restrict__ tab, CtrlState* const* ctab, BatchMap m) {
+  const int s = m.sid[blockIdx.x];
+  const int b0 = m.start[s];
+  fqr_body(tab[s], ctab[s], blockIdx.x - b0, m.start[s + 1] - b0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) kb_fpost(const FPostArgs* __restrict__ tab, CtrlState* const* ctab,
+                                                BatchMap m) {
+  const int s = m.sid[blockIdx.x];
+  fpost_body<T>(tab[s], ctab[s], blockIdx.x - m.start[s]);
+}
+
+template <typename TD, typename T>
+__global__ void __launch_bounds__(256) kb_ferr(const FErrArgs* __restrict__ tab, const void* const* v1, BatchMap m) {
+  const int s = m.sid[blockIdx.x];
+  FErrArgs a = tab[s];
+  a.V = v1[s];
+  const int l = blockIdx.x - m.start[s];
+  ferr_body<TD, T>(a, l % a.gx, l / a.gx, a.gx);
+}
+
+// One block per stream: the fixed-order sum of that stream's error-pass partials,
+// its controller decision, and the summary the host reads.
+__global__ void __launch_bounds__(256) kb_ferr_final(const FErrArgs* __restrict__ tab, CtrlState* const* ctab,
+                                                     BatchSummary* out) {
+  __shared__ double red[16];
+  const int s = blockIdx.x;
+  const double* part = tab[s].part;
+  const int nb = tab[s].gx * tab[s].gy;
+  CtrlState* ctrl = ctab[s];
+  double s0 = 0.0, s1 = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    s0 += part[2 * i];
+    s1 += part[2 * i + 1];
+  }
+  s0 = block_sum(s0, red);
+  s1 = block_sum(s1, red);
+  if (threadIdx.x == 0) {
+    ctrl->eps2 = s0;
+    ctrl->nu2 = s1;
+    controller_decide(ctrl);
+    BatchSummary q;
+    q.decision = ctrl->decision;
+    q.event = ctrl->event;
+    q.numeric = ctrl->numeric;
+    q.pad = 0;
+    for (int k = 0; k < 5; ++k) q.n_events[k] = ctrl->n_events[k];
+    q.pad2 = 0;
+    q.eps = ctrl->eps;
+    q.nu = ctrl->nu;
+    q.eps2 = s0;
+    q.nu2 = s1;
+    out[s] = q;
+  }
+}
+
+template <typename T>
+hipError_t launch_batch_freduce(const FReduceArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, int stage,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(kb_freduce<T>, dim3(blocks), dim3(256), 0, s, tab, ctab, m, stage);
+  return hipGetLastError();
+}
+template hipError_t launch_batch_freduce<float>(const FReduceArgs*, CtrlState* const*, BatchMap, int, int, hipStream_t);
+template hipError_t launch_batch_freduce<double>(const FReduceArgs*, CtrlState* const*, BatchMap, int, int, hipStream_t);
+
+template <typename T>
+hipError_t launch_batch_ffinish(const FFinishArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, int stage,
+                                size_t lds, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute((const void*)kb_ffinish<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kb_ffinish<T>, dim3(blocks), dim3(256), lds, s, tab, ctab, m, stage);
+  return hipGetLastError();
+}
+template hipError_t launch_batch_ffinish<float>(const FFinishArgs*, CtrlState* const*, BatchMap, int, int, size_t,
+                                                hipStream_t);
+template hipError_t launch_batch_ffinish<double>(const FFinishArgs*, CtrlState* const*, BatchMap, int, int, size_t,
+                                                 hipStream_t);
+
+hipError_t launch_batch_fqr(const FQrArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, size_t lds,
+                            hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute((const void*)kb_fqr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kb_fqr, dim3(blocks), dim3(256), lds, s, tab, ctab, m);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batch_fpost(const FPostArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, size_t lds,
+                              hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute((const void*)kb_fpost<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kb_fpost<T>, dim3(blocks), dim3(256), lds, s, tab, ctab, m);
+  return hipGetLastError();
+}
+template hipError_t launch_batch_fpost<float>(const FPostArgs*, CtrlState* const*, BatchMap, int, size_t, hipStream_t);
+template hipError_t launch_batch_fpost<double>(const FPostArgs*, CtrlState* const*, BatchMap, int, size_t, hipStream_t);
+
+template <typename TD, typename T>
+hipError_t launch_batch_ferr(const FErrArgs* tab, const void* const* v1, BatchMap m, int blocks, int nstreams,
+                             CtrlState* const* ctab, BatchSummary* out, hipStream_t s, hipEvent_t ev0,
+                             hipEvent_t ev1) {
+  hipExtLaunchKernelGGL((kb_ferr<TD, T>), dim3(blocks), dim3(256), 0u, s, ev0, ev1, 0u, tab, v1, m);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kb_ferr_final, dim3(nstreams), dim3(256), 0, s, tab, ctab, out);
+  return hipGetLastError();
+}
+template hipError_t launch_batch_ferr<float, float>(const FErrArgs*, const void* const*, BatchMap, int, int, CtrlState* const*,
+                                                   BatchSummary*, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_batch_ferr<float, double>(const FErrArgs*, const void* const*, BatchMap, int, int, CtrlState* const*,
+                                                   BatchSummary*, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_batch_ferr<double, double>(const FErrArgs*, const void* const*, BatchMap, int, int, CtrlState* const*,
+                                                   BatchSummary*, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_batch_ferr<double, float>(const FErrArgs*, const void* const*, BatchMap, int, int, CtrlState* const*,
+                                                   BatchSummary*, hipStream_t, hipEvent_t, hipEvent_t);
 
 }  // namespace tdb

@@ -21,12 +21,12 @@
 namespace tdb {
 // ---------------------------------------------------------------- stage pass
 template <typename TD, typename T>
-__global__ void __launch_bounds__(256) k_fpass(FPassArgs a) {
+__device__ __forceinline__ void fpass_body(const FPassArgs& a, int bx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
   const int N2 = a.N2, N3 = a.N3, r1 = a.r1, r2 = a.r2, r3 = a.r3;
   const int T1 = a.T1, T2 = a.T2;
-  const int t1 = blockIdx.x / a.nt2, t2 = blockIdx.x % a.nt2;
+  const int t1 = bx / a.nt2, t2 = bx % a.nt2;
   const int i1_0 = t1 * T1, i2_0 = t2 * T2;
   const int n1 = min(T1, a.N1 - i1_0), n2 = min(T2, N2 - i2_0);
   const int R1 = r2 * r3, R2 = r1 * r3, R3 = r1 * r2;
@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(256) k_fpass(FPassArgs a) {
   __syncthreads();
 
   // partial outputs of this tile
-  T* out = static_cast<T*>(a.part) + (long long)blockIdx.x * a.slot;
+  T* out = static_cast<T*>(a.part) + (long long)bx * a.slot;
   T* oH1 = out;
   T* oH2 = oH1 + T1 * r1;
   T* oH3 = oH2 + T2 * r2;
@@ -230,6 +230,11 @@ __global__ void __launch_bounds__(256) k_fpass(FPassArgs a) {
 }
 
 template <typename TD, typename T>
+__global__ void __launch_bounds__(256) k_fpass(FPassArgs a) {
+  fpass_body<TD, T>(a, blockIdx.x);
+}
+
+template <typename TD, typename T>
 hipError_t launch_fpass(const FPassArgs& a, size_t lds, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   hipError_t e = hipFuncSetAttribute((const void*)k_fpass<TD, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
@@ -241,5 +246,34 @@ template hipError_t launch_fpass<float, float>(const FPassArgs&, size_t, hipStre
 template hipError_t launch_fpass<float, double>(const FPassArgs&, size_t, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_fpass<double, double>(const FPassArgs&, size_t, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_fpass<double, float>(const FPassArgs&, size_t, hipStream_t, hipEvent_t, hipEvent_t);
+
+// Batched form: one launch over the tiles of many streams.
+template <typename TD, typename T>
+__global__ void __launch_bounds__(256) kb_fpass(const FPassArgs* __restrict__ tab, const void* const* v1,
+                                                const void* const* v0, BatchMap m) {
+  const int s = m.sid[blockIdx.x];
+  FPassArgs a = tab[s];
+  a.V1 = v1[s];
+  a.V0 = v0[s];
+  fpass_body<TD, T>(a, blockIdx.x - m.start[s]);
+}
+
+template <typename TD, typename T>
+hipError_t launch_batch_fpass(const FPassArgs* tab, const void* const* v1, const void* const* v0, BatchMap m,
+                              int blocks, size_t lds, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  hipError_t e = hipFuncSetAttribute((const void*)kb_fpass<TD, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipExtLaunchKernelGGL((kb_fpass<TD, T>), dim3(blocks), dim3(256), (uint32_t)lds, s, ev0, ev1, 0u, tab, v1, v0, m);
+  return hipGetLastError();
+}
+template hipError_t launch_batch_fpass<float, float>(const FPassArgs*, const void* const*, const void* const*, BatchMap, int,
+                                                    size_t, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_batch_fpass<float, double>(const FPassArgs*, const void* const*, const void* const*, BatchMap, int,
+                                                    size_t, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_batch_fpass<double, double>(const FPassArgs*, const void* const*, const void* const*, BatchMap, int,
+                                                    size_t, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_batch_fpass<double, float>(const FPassArgs*, const void* const*, const void* const*, BatchMap, int,
+                                                    size_t, hipStream_t, hipEvent_t, hipEvent_t);
 
 }  // namespace tdb

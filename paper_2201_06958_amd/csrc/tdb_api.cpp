@@ -80,6 +80,8 @@ struct tdb_ctx {
   unsigned* counters = nullptr;
   int ferr_gx = 1, ferr_gy = 1;
   long long fused_steps = 0, plain_steps = 0;
+  bool batch_owned = false;      // lives inside a tdb_batch
+  bool sigma_stale = false;      // stats.sigma not refreshed since the last batched step
   // optional pass timing (events recorded on the caller's stream)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -181,14 +183,27 @@ struct PassPlan {
   bool ok = false;
 };
 
+// LDS bytes of one stage-pass tile of T1 x T2 x N3 at ranks r (without the staged
+// pseudo-inverses), and the bytes of the staged pseudo-inverses.
+size_t pass_lds(const tdb_ctx* h, const int* r, int T1, int T2) {
+  const long long N3 = h->N[2];
+  const int r1 = r[0], r2 = r[1], r3 = r[2];
+  long long e = (long long)T1 * T2 * N3 + (long long)T1 * T2 * r3 + (long long)T1 * r2 * r3 +
+                (long long)r1 * T2 * r3 + 2LL * T1 * r1 + 2LL * T2 * r2 + 2LL * N3 * r3;
+  if (r3 < N3) e += (long long)T1 * r2 * N3 + (long long)r1 * r2 * N3;
+  return (size_t)e * h->celt;
+}
+size_t pass_p_bytes(const tdb_ctx* h, const int* r) {
+  const long long c = (long long)r[0] * r[1] * r[2];
+  const long long pe = (r[0] < h->N[0] ? c : 0) + (r[1] < h->N[1] ? c : 0) + (r[2] < h->N[2] ? c : 0);
+  return (size_t)pe * h->celt;
+}
+
 // Tile shape of the fused stage pass for ranks r: about `target` elements per tile,
 // shrunk until its LDS footprint fits.
 PassPlan plan_pass(const tdb_ctx* h, const int* r) {
   PassPlan pl;
   const long long N1 = h->N[0], N2 = h->N[1], N3 = h->N[2];
-  const int r1 = r[0], r2 = r[1], r3 = r[2];
-  const bool f3 = r3 < N3;
-  const size_t te = h->celt;
   long long target = h->f32 ? 4096 : 2048;
   if (const char* env = std::getenv("TDB_PASS_TILE")) {
     const long long v = std::atoll(env);
@@ -196,26 +211,29 @@ PassPlan plan_pass(const tdb_ctx* h, const int* r) {
   }
   int T2 = (int)std::min<long long>(N2, 64);
   int T1 = (int)std::max<long long>(1, std::min<long long>(N1, target / std::max<long long>(1, T2 * N3)));
-  auto lds_of = [&](int t1, int t2) {
-    long long e = (long long)t1 * t2 * N3 + (long long)t1 * t2 * r3 + (long long)t1 * r2 * r3 +
-                  (long long)r1 * t2 * r3 + 2LL * t1 * r1 + 2LL * t2 * r2 + 2LL * N3 * r3;
-    if (f3) e += (long long)t1 * r2 * N3 + (long long)r1 * r2 * N3;
-    return (size_t)e * te;
-  };
-  while (lds_of(T1, T2) > (size_t)h->lds_max && T1 > 1) T1 = std::max(1, T1 / 2);
-  while (lds_of(T1, T2) > (size_t)h->lds_max && T2 > 8) T2 = std::max(8, T2 / 2);
-  if (lds_of(T1, T2) > (size_t)h->lds_max) return pl;
+  while (pass_lds(h, r, T1, T2) > (size_t)h->lds_max && T1 > 1) T1 = std::max(1, T1 / 2);
+  while (pass_lds(h, r, T1, T2) > (size_t)h->lds_max && T2 > 8) T2 = std::max(8, T2 / 2);
+  if (pass_lds(h, r, T1, T2) > (size_t)h->lds_max) return pl;
   // stage the pseudo-inverses too when they fit
-  const long long pe = (r1 < N1 ? (long long)r1 * r2 * r3 : 0) + (r2 < N2 ? (long long)r1 * r2 * r3 : 0) +
-                       (f3 ? (long long)r1 * r2 * r3 : 0);
-  if (lds_of(T1, T2) + (size_t)pe * te <= (size_t)h->lds_max) pl.stage_p = 1;
+  if (pass_lds(h, r, T1, T2) + pass_p_bytes(h, r) <= (size_t)h->lds_max) pl.stage_p = 1;
   pl.T1 = T1;
   pl.T2 = T2;
   pl.nt1 = (int)((N1 + T1 - 1) / T1);
   pl.nt2 = (int)((N2 + T2 - 1) / T2);
-  pl.slot = (long long)T1 * r1 + (long long)T2 * r2 + N3 * r3 + (long long)r1 * r2 * r3;
-  pl.lds = lds_of(T1, T2) + (pl.stage_p ? (size_t)pe * te : 0);
+  pl.slot = (long long)T1 * r[0] + (long long)T2 * r[1] + N3 * r[2] + (long long)r[0] * r[1] * r[2];
+  pl.lds = pass_lds(h, r, T1, T2) + (pl.stage_p ? pass_p_bytes(h, r) : 0);
   pl.ok = true;
+  return pl;
+}
+
+// The plan `base` (made for larger ranks) applied to ranks r: same tiles and LDS
+// budget, the partial slot and the staging decision of r.
+PassPlan plan_under(const tdb_ctx* h, const int* r, const PassPlan& base) {
+  PassPlan pl = base;
+  const size_t need = pass_lds(h, r, base.T1, base.T2);
+  if (!base.ok || need > base.lds) { pl.ok = false; return pl; }
+  pl.stage_p = need + pass_p_bytes(h, r) <= base.lds ? 1 : 0;
+  pl.slot = (long long)base.T1 * r[0] + (long long)base.T2 * r[1] + h->N[2] * r[2] + (long long)r[0] * r[1] * r[2];
   return pl;
 }
 
@@ -744,40 +762,53 @@ tdb_status ingest_impl(tdb_ctx* h, const TD* V1, hipStream_t s) {
   return TDB_OK;
 }
 
-int max_rank(const tdb_ctx* h) {
+int max_rank_of(const int* r, int p) {
   int m = 1;
-  for (int n = 0; n < h->p; ++n) m = std::max(m, h->r[n]);
+  for (int n = 0; n < p; ++n) m = std::max(m, r[n]);
   return m;
 }
 
-size_t small_lds(const tdb_ctx* h, bool* core_in_lds) {
-  const long long csz = prod_ll(h->r, h->p);
-  const int rm = max_rank(h);
+// LDS of the small per-mode kernels (finish, post) when sized for ranks rl.
+size_t small_lds(const tdb_ctx* h, const int* rl, bool* core_in_lds) {
+  const long long csz = prod_ll(rl, h->p);
+  const int rm = max_rank_of(rl, h->p);
   long long msum = 0;
-  for (int n = 0; n < h->p; ++n) msum += (long long)h->r[n] * h->r[n];
+  for (int n = 0; n < h->p; ++n) msum += (long long)rl[n] * rl[n];
   // finish rows stage C_dot, the three P_n and the three M_n
   long long pel = 0;
-  for (int n = 0; n < h->p; ++n) pel += (csz / h->r[n]) * h->r[n];
+  for (int n = 0; n < h->p; ++n) pel += (csz / rl[n]) * rl[n];
   const size_t rows = (size_t)csz * 8 + (size_t)pel * h->celt + 8 + (size_t)msum * 8;
   const size_t base = std::max<size_t>((3 * (size_t)rm * rm + 5 * (size_t)rm + 64) * 8, rows);
   *core_in_lds = base + (size_t)csz * 8 <= (size_t)h->lds_max;
   return base + (*core_in_lds ? (size_t)csz * 8 : 0);
 }
 
-// Post-step preparation of the fused path at the committed state: core singular
-// values, B_n and P_n of the next stage 1, and the error-pass expansion E.
-template <typename T>
-tdb_status fused_post(tdb_ctx* h, hipStream_t s) {
-  FPostArgs pa{};
+// Everything one fused step launches, for the current ranks h->r. LDS budgets, tile
+// shapes and grid sizes are taken for the ranks `rl` (h->r for a single stream; the
+// caps for a batch, so that a batch's launch shapes never change).
+struct StepArgs {
+  PassPlan pl;
+  FPassArgs fa[2];
+  FReduceArgs ra;
+  FFinishArgs ga[2];
+  FQrArgs qa;
+  FPostArgs pa;
+  FErrArgs ea;
+  size_t lds_fin = 0, lds_qr = 0, lds_post = 0;
+  int blocks_pass = 1, blocks_red = 1, blocks_fin[2] = {1, 1}, blocks_qr = 3, blocks_post = 1, blocks_err = 1;
+};
+
+tdb_status build_post_args(tdb_ctx* h, const int* rl, FPostArgs& pa, size_t& lds) {
+  pa = FPostArgs{};
   bool cil = false;
-  size_t lds = small_lds(h, &cil);
+  lds = small_lds(h, rl, &cil);
   pa.core_in_lds = cil ? 1 : 0;
   pa.want_pinv = 1;
-  pa.rmax = max_rank(h);
-  const long long etot = (long long)h->r[0] * h->N[1] * h->N[2];
+  pa.rmax = max_rank_of(rl, 3);
+  const long long etot = (long long)rl[0] * h->N[1] * h->N[2];
   pa.eblocks = (int)std::max<long long>(1, std::min<long long>(std::min<long long>(256, h->N[1]), (etot + 255) / 256));
   const long long per = (h->N[1] + pa.eblocks - 1) / pa.eblocks;
-  const size_t elds = ((size_t)h->r[0] * h->r[1] * h->N[2] + (size_t)per * h->r[1]) * 8;
+  const size_t elds = ((size_t)rl[0] * rl[1] * h->N[2] + (size_t)per * rl[1]) * 8;
   if (elds > (size_t)h->lds_max) { h->err = "error-pass expansion does not fit in LDS"; return TDB_EUNSUPPORTED; }
   lds = std::max(lds, elds);
   pa.C = h->C0;
@@ -792,22 +823,21 @@ tdb_status fused_post(tdb_ctx* h, hipStream_t s) {
     pa.B[n] = h->B[n];
     pa.P[n] = h->P[n];
   }
-  HIPCHK(launch_fpost<T>(pa, lds, h->ctrl, s));
-  h->post_valid = true;
   return TDB_OK;
 }
 
-template <typename TD, typename T>
-tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
-  const TD* V0 = static_cast<const TD*>(h->Vprev);
-  const PassPlan pl = plan_pass(h, h->r);
+// Returns TDB_EUNSUPPORTED when the stage pass does not fit (the caller may fall back
+// to the plain path).
+tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void* V0, StepArgs& A) {
+  const PassPlan base = plan_pass(h, rl);
+  if (!base.ok) { h->err = "stage-pass tile does not fit in LDS"; return TDB_EUNSUPPORTED; }
+  const PassPlan pl = rl == h->r ? base : plan_under(h, h->r, base);
   if (!pl.ok || (long long)pl.nt1 * pl.nt2 * pl.slot > h->fpart_elems) {
-    h->post_valid = false;
-    h->plain_steps += 1;
-    return ingest_impl<TD, T>(h, V1, s);
+    h->err = "stage-pass partials do not fit";
+    return TDB_EUNSUPPORTED;
   }
-  h->fused_steps += 1;
-  if (!h->post_valid) TRY(fused_post<T>(h, s));
+  A.pl = pl;
+  A.blocks_pass = pl.nt1 * pl.nt2;
   FPassArgs fa{};
   fa.V1 = V1;
   fa.V0 = V0;
@@ -820,9 +850,14 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
   fa.stage_p = pl.stage_p;
   fa.slot = pl.slot;
   fa.B1 = h->B[0]; fa.B2 = h->B[1]; fa.B3 = h->B[2];
-  fa.P1 = h->P[0]; fa.P2 = h->P[1]; fa.P3 = h->P[2];
   fa.part = h->fpart;
-  FReduceArgs ra{};
+  A.fa[0] = fa;
+  A.fa[0].P1 = h->P[0]; A.fa[0].P2 = h->P[1]; A.fa[0].P3 = h->P[2];
+  A.fa[1] = fa;
+  A.fa[1].P1 = h->P2[0]; A.fa[1].P2 = h->P2[1]; A.fa[1].P3 = h->P2[2];
+
+  FReduceArgs& ra = A.ra;
+  ra = FReduceArgs{};
   ra.dt = h->cfg.dt;
   ra.N1 = fa.N1; ra.N2 = fa.N2; ra.N3 = fa.N3; ra.r1 = fa.r1; ra.r2 = fa.r2; ra.r3 = fa.r3;
   ra.T1 = pl.T1; ra.T2 = pl.T2; ra.nt1 = pl.nt1; ra.nt2 = pl.nt2;
@@ -830,20 +865,26 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
   ra.slot = pl.slot;
   ra.part = h->fpart;
   ra.C0 = h->C0; ra.Cs = h->Cs; ra.kC = h->kC; ra.Cdot2 = h->Cdot2;
+  for (int n = 0; n < 3; ++n) ra.H[n] = h->H[n];
+  {
+    const long long total = (long long)rl[0] * rl[1] * rl[2] + (long long)h->N[0] * rl[0] +
+                            (long long)h->N[1] * rl[1] + (long long)h->N[2] * rl[2];
+    A.blocks_red = (int)std::max<long long>(1, std::min<long long>(1024, (total + 255) / 256));
+  }
+
   FFinishArgs ga{};
   bool cil = false;
-  const size_t slds = small_lds(h, &cil);
+  A.lds_fin = small_lds(h, rl, &cil);
   ga.core_in_lds = cil ? 1 : 0;
-  ga.rmax = max_rank(h);
+  ga.rmax = max_rank_of(rl, 3);
   ga.dt = h->cfg.dt;
   long long rows = 0;
-  for (int n = 0; n < 3; ++n) rows += h->N[n] * h->r[n];
+  for (int n = 0; n < 3; ++n) rows += h->N[n] * rl[n];
   ga.rowblocks = (int)std::max<long long>(1, std::min<long long>(1024, (rows + 255) / 256));
   ga.Cs = h->Cs;
   ga.kC = h->kC;
   ga.Cdot2 = h->Cdot2;
   for (int n = 0; n < 3; ++n) {
-    ra.H[n] = h->H[n];
     ga.N[n] = h->N[n];
     ga.r[n] = h->r[n];
     ga.ldU[n] = h->ldU[n];
@@ -855,27 +896,22 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
     ga.B[n] = h->B[n];
     ga.P[n] = h->P2[n];
   }
-  for (int stage = 1; stage <= 2; ++stage) {
-    void* const* Pst = stage == 1 ? h->P : h->P2;
-    fa.P1 = Pst[0]; fa.P2 = Pst[1]; fa.P3 = Pst[2];
-    for (int n = 0; n < 3; ++n) ga.Pcur[n] = Pst[n];
-    {
-      PassTimer pt(h, TDB_PASS_PROJECT, s, true);
-      HIPCHK((launch_fpass<TD, T>(fa, pl.lds, s, pt.start(), pt.stop())));
-    }
-    ra.stage = stage;
-    HIPCHK(launch_freduce<T>(ra, h->ctrl, s));
-    ga.stage = stage;
-    HIPCHK(launch_ffinish<T>(ga, slds, h->ctrl, s));
+  for (int st = 0; st < 2; ++st) {
+    A.ga[st] = ga;
+    A.ga[st].stage = st + 1;
+    for (int n = 0; n < 3; ++n) A.ga[st].Pcur[n] = st == 0 ? h->P[n] : h->P2[n];
+    A.blocks_fin[st] = ga.rowblocks + (st == 0 ? 3 : 0);
   }
-  FQrArgs qa{};
-  qa.rmax = max_rank(h);
+
+  FQrArgs& qa = A.qa;
+  qa = FQrArgs{};
+  qa.rmax = max_rank_of(rl, 3);
   qa.rounds = 1;
   const size_t npq = (size_t)qa.rmax * (qa.rmax + 1) / 2;
-  size_t qlds = (4 * (size_t)qa.rmax * qa.rmax + 4 * npq + TDB_NEIG) * 8;
+  const size_t qlds = (4 * (size_t)qa.rmax * qa.rmax + 4 * npq + TDB_NEIG) * 8;
   size_t ustage = 0;
   for (int n = 0; n < 3; ++n) {
-    const size_t need = (size_t)h->N[n] * h->r[n] * 8;
+    const size_t need = (size_t)h->N[n] * rl[n] * 8;
     qa.u_in_lds[n] = qlds + need <= (size_t)h->lds_max ? 1 : 0;
     if (qa.u_in_lds[n]) ustage = std::max(ustage, need);
     qa.N[n] = h->N[n];
@@ -885,15 +921,19 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
     qa.w[n] = h->w[n];
     qa.Rq[n] = h->Rq[n];
   }
-  const size_t cneed = 2 * (size_t)prod_ll(h->r, 3) * 8;
+  const size_t cneed = 2 * (size_t)prod_ll(rl, 3) * 8;
   qa.core_in_lds = qlds + cneed <= (size_t)h->lds_max ? 1 : 0;
   if (qa.core_in_lds) ustage = std::max(ustage, cneed);
   qa.C0 = h->C0;
   qa.Ctmp = h->Ctmp;
   qa.counter = h->counters;
-  HIPCHK(launch_fqr(qa, qlds + ustage, h->ctrl, s));
-  TRY(fused_post<T>(h, s));
-  FErrArgs ea{};
+  A.lds_qr = qlds + ustage;
+
+  TRY(build_post_args(h, rl, A.pa, A.lds_post));
+  A.blocks_post = 3 + A.pa.eblocks;
+
+  FErrArgs& ea = A.ea;
+  ea = FErrArgs{};
   ea.V = V1;
   ea.N1 = (int)h->N[0];
   ea.r1 = h->r[0];
@@ -907,11 +947,26 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
   ea.w23 = h->w23;
   ea.part = h->ferr_part;
   ea.counter = h->counters + 1;
-  {
-    PassTimer pt(h, TDB_PASS_ERROR, s, true);
-    HIPCHK((launch_ferr<TD, T>(ea, h->ctrl, s, pt.start(), pt.stop())));
-  }
-  TRY(pull_ctrl(h, s));
+  A.blocks_err = h->ferr_gx * h->ferr_gy;
+  return TDB_OK;
+}
+
+// Post-step preparation of the fused path at the committed state: core singular
+// values, B_n and P_n of the next stage 1, and the error-pass expansion E.
+template <typename T>
+tdb_status fused_post(tdb_ctx* h, hipStream_t s) {
+  FPostArgs pa{};
+  size_t lds = 0;
+  TRY(build_post_args(h, h->r, pa, lds));
+  HIPCHK(launch_fpost<T>(pa, lds, h->ctrl, s));
+  h->post_valid = true;
+  return TDB_OK;
+}
+
+// After a step's error pass: read the decision, reinitialise when one was taken,
+// keep the snapshot for the next difference quotient, record the statistics.
+template <typename TD, typename T>
+tdb_status finish_step(tdb_ctx* h, const TD* V1, hipStream_t s) {
   h->step += 1;
   h->t_now = h->step * h->cfg.dt;
   const int dec = h->ctrl_h->decision;
@@ -924,6 +979,38 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
   TRY(keep_previous<TD>(h, V1, s));
   fill_stats(h, false);
   return TDB_OK;
+}
+
+template <typename TD, typename T>
+tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
+  StepArgs A;
+  tdb_status bs = build_step_args(h, h->r, V1, h->Vprev, A);
+  if (bs == TDB_EUNSUPPORTED) {
+    h->post_valid = false;
+    h->plain_steps += 1;
+    return ingest_impl<TD, T>(h, V1, s);
+  }
+  TRY(bs);
+  h->fused_steps += 1;
+  if (!h->post_valid) TRY(fused_post<T>(h, s));
+  for (int stage = 1; stage <= 2; ++stage) {
+    {
+      PassTimer pt(h, TDB_PASS_PROJECT, s, true);
+      HIPCHK((launch_fpass<TD, T>(A.fa[stage - 1], A.pl.lds, s, pt.start(), pt.stop())));
+    }
+    A.ra.stage = stage;
+    HIPCHK(launch_freduce<T>(A.ra, h->ctrl, s));
+    HIPCHK(launch_ffinish<T>(A.ga[stage - 1], A.lds_fin, h->ctrl, s));
+  }
+  HIPCHK(launch_fqr(A.qa, A.lds_qr, h->ctrl, s));
+  HIPCHK(launch_fpost<T>(A.pa, A.lds_post, h->ctrl, s));
+  h->post_valid = true;
+  {
+    PassTimer pt(h, TDB_PASS_ERROR, s, true);
+    HIPCHK((launch_ferr<TD, T>(A.ea, h->ctrl, s, pt.start(), pt.stop())));
+  }
+  TRY(pull_ctrl(h, s));
+  return finish_step<TD, T>(h, V1, s);
 }
 
 template <typename TD>
@@ -960,6 +1047,260 @@ tdb_status create(const tdb_config* cfg, tdb_ctx** out) {
   return TDB_OK;
 }
 
+// HOSVD initialisation of a freshly created context from its first snapshot.
+tdb_status init_hosvd(tdb_ctx* h, const void* V0_dev, hipStream_t s) {
+  if (h->data32) TRY(hosvd_select<float>(h, static_cast<const float*>(V0_dev), DEC_INIT, s));
+  else TRY(hosvd_select<double>(h, static_cast<const double*>(V0_dev), DEC_INIT, s));
+  TRY(pull_ctrl(h, s));
+  TRY(core_sigma(h, false, s));
+  TRY(pull_ctrl(h, s));
+  if (h->data32) TRY(keep_previous<float>(h, static_cast<const float*>(V0_dev), s));
+  else TRY(keep_previous<double>(h, static_cast<const double*>(V0_dev), s));
+  fill_stats(h, true);
+  return TDB_OK;
+}
+
+// ---------------------------------------------------------------- batches of streams
+}  // namespace
+
+struct tdb_batch_ctx {
+  int n = 0;
+  std::vector<tdb_ctx*> st;
+  bool data32 = false, f32 = false;
+  std::string err;
+  std::vector<void*> dev, host;     // owned device / pinned host blocks
+  // per-stream argument tables (device) and their pinned host mirrors
+  FPassArgs *d_fa[2] = {}, *h_fa[2] = {};
+  FReduceArgs *d_ra = nullptr, *h_ra = nullptr;
+  FFinishArgs *d_ga[2] = {}, *h_ga[2] = {};
+  FQrArgs *d_qa = nullptr, *h_qa = nullptr;
+  FPostArgs *d_pa = nullptr, *h_pa = nullptr;
+  FErrArgs *d_ea = nullptr, *h_ea = nullptr;
+  CtrlState** d_ctab = nullptr;
+  const void **d_v1 = nullptr, **d_v0 = nullptr, **h_v1 = nullptr, **h_v0 = nullptr;
+  BatchSummary *d_sum = nullptr, *h_sum = nullptr;
+  // block maps (fixed at creation: grids are sized at the caps)
+  BatchMap m_pass{}, m_red{}, m_fin[2]{}, m_qr{}, m_post{}, m_err{};
+  int g_pass = 0, g_red = 0, g_fin[2] = {0, 0}, g_qr = 0, g_post = 0, g_err = 0;
+  size_t lds_pass = 0, lds_fin = 0, lds_qr = 0, lds_post = 0;
+  double bytes_pass = 0.0, bytes_err = 0.0;
+  bool dirty = true;
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[2];
+
+  ~tdb_batch_ctx() {
+    for (auto& v : ev_used)
+      for (auto& e : v) { ev_pool.push_back(e.first); ev_pool.push_back(e.second); }
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    for (tdb_ctx* h : st) delete h;
+    for (void* q : dev) (void)hipFree(q);
+    for (void* q : host) (void)hipHostFree(q);
+  }
+};
+
+#define BHIPCHK(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      b->err = std::string(#expr) + ": " + hipGetErrorString(e_);                      \
+      return TDB_EHIP;                                                                 \
+    }                                                                                  \
+  } while (0)
+
+namespace {
+
+template <typename X>
+tdb_status balloc(tdb_batch_ctx* b, X** d, X** hp, size_t count) {
+  void* q = nullptr;
+  BHIPCHK(hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(X)));
+  b->dev.push_back(q);
+  *d = static_cast<X*>(q);
+  if (hp) {
+    void* r = nullptr;
+    BHIPCHK(hipHostMalloc(&r, std::max<size_t>(count, 1) * sizeof(X), hipHostMallocDefault));
+    b->host.push_back(r);
+    *hp = static_cast<X*>(r);
+  }
+  return TDB_OK;
+}
+
+// Block map of one batched kernel from the per-stream block counts.
+tdb_status make_map(tdb_batch_ctx* b, const std::vector<int>& counts, BatchMap* m, int* total) {
+  std::vector<int> start(counts.size() + 1, 0);
+  for (size_t i = 0; i < counts.size(); ++i) start[i + 1] = start[i] + counts[i];
+  std::vector<int> sid(std::max(start.back(), 1), 0);
+  for (size_t i = 0; i < counts.size(); ++i)
+    for (int k = start[i]; k < start[i + 1]; ++k) sid[k] = (int)i;
+  int *d_sid = nullptr, *d_start = nullptr;
+  TRY(balloc<int>(b, &d_sid, nullptr, sid.size()));
+  TRY(balloc<int>(b, &d_start, nullptr, start.size()));
+  BHIPCHK(hipMemcpy(d_sid, sid.data(), sid.size() * sizeof(int), hipMemcpyHostToDevice));
+  BHIPCHK(hipMemcpy(d_start, start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice));
+  m->sid = d_sid;
+  m->start = d_start;
+  *total = start.back();
+  return TDB_OK;
+}
+
+hipEvent_t take_bevent(tdb_batch_ctx* b) {
+  if (!b->ev_pool.empty()) {
+    hipEvent_t e = b->ev_pool.back();
+    b->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Rebuild every stream's argument structs (current ranks, launch shapes at the caps)
+// and upload them.
+tdb_status batch_upload_args(tdb_batch_ctx* b, hipStream_t s) {
+  for (int i = 0; i < b->n; ++i) {
+    tdb_ctx* h = b->st[i];
+    StepArgs A;
+    tdb_status r = build_step_args(h, h->caps, nullptr, nullptr, A);
+    if (r != TDB_OK) { b->err = "stream " + std::to_string(i) + ": " + h->err; return r; }
+    b->h_fa[0][i] = A.fa[0];
+    b->h_fa[1][i] = A.fa[1];
+    A.ra.stage = 1;
+    b->h_ra[i] = A.ra;
+    b->h_ga[0][i] = A.ga[0];
+    b->h_ga[1][i] = A.ga[1];
+    b->h_qa[i] = A.qa;
+    b->h_pa[i] = A.pa;
+    b->h_ea[i] = A.ea;
+  }
+  const size_t n = (size_t)b->n;
+  BHIPCHK(hipMemcpyAsync(b->d_fa[0], b->h_fa[0], n * sizeof(FPassArgs), hipMemcpyHostToDevice, s));
+  BHIPCHK(hipMemcpyAsync(b->d_fa[1], b->h_fa[1], n * sizeof(FPassArgs), hipMemcpyHostToDevice, s));
+  BHIPCHK(hipMemcpyAsync(b->d_ra, b->h_ra, n * sizeof(FReduceArgs), hipMemcpyHostToDevice, s));
+  BHIPCHK(hipMemcpyAsync(b->d_ga[0], b->h_ga[0], n * sizeof(FFinishArgs), hipMemcpyHostToDevice, s));
+  BHIPCHK(hipMemcpyAsync(b->d_ga[1], b->h_ga[1], n * sizeof(FFinishArgs), hipMemcpyHostToDevice, s));
+  BHIPCHK(hipMemcpyAsync(b->d_qa, b->h_qa, n * sizeof(FQrArgs), hipMemcpyHostToDevice, s));
+  BHIPCHK(hipMemcpyAsync(b->d_pa, b->h_pa, n * sizeof(FPostArgs), hipMemcpyHostToDevice, s));
+  BHIPCHK(hipMemcpyAsync(b->d_ea, b->h_ea, n * sizeof(FErrArgs), hipMemcpyHostToDevice, s));
+  b->dirty = false;
+  return TDB_OK;
+}
+
+// Launch shapes at the caps, block maps, tables.
+tdb_status batch_setup(tdb_batch_ctx* b) {
+  const int n = b->n;
+  std::vector<int> c_pass(n), c_red(n), c_fin0(n), c_fin1(n), c_qr(n, 3), c_post(n), c_err(n);
+  for (int i = 0; i < n; ++i) {
+    tdb_ctx* h = b->st[i];
+    StepArgs A;
+    tdb_status r = build_step_args(h, h->caps, nullptr, nullptr, A);
+    if (r != TDB_OK) { b->err = "stream " + std::to_string(i) + ": " + h->err; return r; }
+    // the plan at the caps must also hold the partials of the caps
+    const PassPlan pc = plan_pass(h, h->caps);
+    if ((long long)pc.nt1 * pc.nt2 * pc.slot > h->fpart_elems) {
+      b->err = "stream " + std::to_string(i) + ": stage-pass partials at the caps do not fit";
+      return TDB_EUNSUPPORTED;
+    }
+    c_pass[i] = A.blocks_pass;
+    c_red[i] = A.blocks_red;
+    c_fin0[i] = A.blocks_fin[0];
+    c_fin1[i] = A.blocks_fin[1];
+    c_post[i] = A.blocks_post;
+    c_err[i] = A.blocks_err;
+    b->lds_pass = std::max(b->lds_pass, pc.lds);
+    b->lds_fin = std::max(b->lds_fin, A.lds_fin);
+    b->lds_qr = std::max(b->lds_qr, A.lds_qr);
+    b->lds_post = std::max(b->lds_post, A.lds_post);
+    b->bytes_pass += 2.0 * (double)h->S * (double)h->delt;
+    b->bytes_err += (double)h->S * (double)h->delt;
+  }
+  TRY(make_map(b, c_pass, &b->m_pass, &b->g_pass));
+  TRY(make_map(b, c_red, &b->m_red, &b->g_red));
+  TRY(make_map(b, c_fin0, &b->m_fin[0], &b->g_fin[0]));
+  TRY(make_map(b, c_fin1, &b->m_fin[1], &b->g_fin[1]));
+  TRY(make_map(b, c_qr, &b->m_qr, &b->g_qr));
+  TRY(make_map(b, c_post, &b->m_post, &b->g_post));
+  TRY(make_map(b, c_err, &b->m_err, &b->g_err));
+  const size_t nn = (size_t)n;
+  TRY(balloc(b, &b->d_fa[0], &b->h_fa[0], nn));
+  TRY(balloc(b, &b->d_fa[1], &b->h_fa[1], nn));
+  TRY(balloc(b, &b->d_ra, &b->h_ra, nn));
+  TRY(balloc(b, &b->d_ga[0], &b->h_ga[0], nn));
+  TRY(balloc(b, &b->d_ga[1], &b->h_ga[1], nn));
+  TRY(balloc(b, &b->d_qa, &b->h_qa, nn));
+  TRY(balloc(b, &b->d_pa, &b->h_pa, nn));
+  TRY(balloc(b, &b->d_ea, &b->h_ea, nn));
+  TRY(balloc(b, &b->d_v1, &b->h_v1, nn));
+  TRY(balloc(b, &b->d_v0, &b->h_v0, nn));
+  TRY(balloc(b, &b->d_sum, &b->h_sum, nn));
+  std::vector<CtrlState*> ct(nn);
+  for (int i = 0; i < n; ++i) ct[i] = b->st[i]->ctrl;
+  TRY(balloc<CtrlState*>(b, &b->d_ctab, nullptr, nn));
+  BHIPCHK(hipMemcpy(b->d_ctab, ct.data(), nn * sizeof(CtrlState*), hipMemcpyHostToDevice));
+  return TDB_OK;
+}
+
+template <typename TD, typename T>
+tdb_status batch_step(tdb_batch_ctx* b, const void* const* V, hipStream_t s) {
+  const int n = b->n;
+  for (int i = 0; i < n; ++i) {
+    b->h_v1[i] = V[i];
+    b->h_v0[i] = b->st[i]->Vprev;
+  }
+  BHIPCHK(hipMemcpyAsync(b->d_v1, b->h_v1, n * sizeof(void*), hipMemcpyHostToDevice, s));
+  BHIPCHK(hipMemcpyAsync(b->d_v0, b->h_v0, n * sizeof(void*), hipMemcpyHostToDevice, s));
+  if (b->dirty) TRY(batch_upload_args(b, s));
+  for (int st = 0; st < 2; ++st) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (b->prof) {
+      e0 = take_bevent(b);
+      e1 = take_bevent(b);
+      if (e0 && e1) b->ev_used[TDB_PASS_PROJECT].push_back({e0, e1});
+      else e0 = e1 = nullptr;
+    }
+    BHIPCHK((launch_batch_fpass<TD, T>(b->d_fa[st], b->d_v1, b->d_v0, b->m_pass, b->g_pass, b->lds_pass, s, e0,
+                                       e1)));
+    BHIPCHK(launch_batch_freduce<T>(b->d_ra, b->d_ctab, b->m_red, b->g_red, st + 1, s));
+    BHIPCHK(launch_batch_ffinish<T>(b->d_ga[st], b->d_ctab, b->m_fin[st], b->g_fin[st], st + 1, b->lds_fin, s));
+  }
+  BHIPCHK(launch_batch_fqr(b->d_qa, b->d_ctab, b->m_qr, b->g_qr, b->lds_qr, s));
+  BHIPCHK(launch_batch_fpost<T>(b->d_pa, b->d_ctab, b->m_post, b->g_post, b->lds_post, s));
+  {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (b->prof) {
+      e0 = take_bevent(b);
+      e1 = take_bevent(b);
+      if (e0 && e1) b->ev_used[TDB_PASS_ERROR].push_back({e0, e1});
+      else e0 = e1 = nullptr;
+    }
+    BHIPCHK((launch_batch_ferr<TD, T>(b->d_ea, b->d_v1, b->m_err, b->g_err, n, b->d_ctab, b->d_sum, s, e0, e1)));
+  }
+  BHIPCHK(hipMemcpyAsync(b->h_sum, b->d_sum, n * sizeof(BatchSummary), hipMemcpyDeviceToHost, s));
+  BHIPCHK(hipStreamSynchronize(s));
+  for (int i = 0; i < n; ++i) {
+    tdb_ctx* h = b->st[i];
+    const BatchSummary& q = b->h_sum[i];
+    CtrlState& c = *h->ctrl_h;
+    c.decision = q.decision;
+    c.event = q.event;
+    c.numeric = q.numeric;
+    for (int k = 0; k < 5; ++k) c.n_events[k] = q.n_events[k];
+    c.eps = q.eps;
+    c.nu = q.nu;
+    c.eps2 = q.eps2;
+    c.nu2 = q.nu2;
+    c.eps_after = NAN;   // as the controller leaves it on a step without an event
+    h->sigma_stale = true;
+    h->post_valid = true;
+    const int r0[3] = {h->r[0], h->r[1], h->r[2]};
+    tdb_status r = finish_step<TD, T>(h, static_cast<const TD*>(V[i]), s);
+    if (r != TDB_OK) { b->err = "stream " + std::to_string(i) + ": " + h->err; return r; }
+    if (q.decision != DEC_NONE) h->sigma_stale = false;   // pulled in full by the reinit
+    if (h->r[0] != r0[0] || h->r[1] != r0[1] || h->r[2] != r0[2]) b->dirty = true;
+    h->fused_steps += 1;
+  }
+  return TDB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -972,17 +1313,7 @@ tdb_status tdb_init(const tdb_config* cfg, const void* V0_dev, void* stream, tdb
   tdb_status st = create(cfg, &h);
   if (st != TDB_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  auto run = [&]() -> tdb_status {
-    if (h->data32) TRY(hosvd_select<float>(h, static_cast<const float*>(V0_dev), DEC_INIT, s));
-    else TRY(hosvd_select<double>(h, static_cast<const double*>(V0_dev), DEC_INIT, s));
-    TRY(pull_ctrl(h, s));
-    TRY(core_sigma(h, false, s));
-    TRY(pull_ctrl(h, s));
-    if (h->data32) TRY(keep_previous<float>(h, static_cast<const float*>(V0_dev), s));
-    else TRY(keep_previous<double>(h, static_cast<const double*>(V0_dev), s));
-    fill_stats(h, true);
-    return TDB_OK;
-  };
+  auto run = [&]() -> tdb_status { return init_hosvd(h, V0_dev, s); };
   st = run();
   if (st != TDB_OK) {
     g_create_error = h->err;
@@ -1052,6 +1383,7 @@ tdb_status tdb_ingest_snapshot(tdb_handle h, const void* V_dev, void* stream) {
   if (!h) { g_create_error = "handle is NULL"; return TDB_EINVAL; }
   if (!h->ready) { h->err = "handle is not initialised"; return TDB_ESTATE; }
   if (!V_dev) { h->err = "V_dev is NULL"; return TDB_EINVAL; }
+  if (h->batch_owned) { h->err = "this stream belongs to a batch: use tdb_batch_ingest"; return TDB_ESTATE; }
   hipStream_t s = static_cast<hipStream_t>(stream);
   tdb_status st = h->data32 ? ingest_dispatch<float>(h, V_dev, s) : ingest_dispatch<double>(h, V_dev, s);
   if (st == TDB_OK && !std::isfinite(h->stats.eps)) {
@@ -1149,12 +1481,21 @@ tdb_status tdb_get_stats(tdb_handle h, tdb_stats* out) {
   if (!h) { g_create_error = "handle is NULL"; return TDB_EINVAL; }
   if (!out) { h->err = "out is NULL"; return TDB_EINVAL; }
   if (!h->ready) { h->err = "handle is not initialised"; return TDB_ESTATE; }
+  if (h->sigma_stale) {
+    // a batched step returns only a summary; the singular values are read on demand
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(h->ctrl_h->sigma, h->ctrl->sigma, sizeof(h->ctrl_h->sigma), hipMemcpyDeviceToHost));
+    for (int n = 0; n < 4; ++n)
+      for (int i = 0; i < TDB_SIGMA_K; ++i)
+        h->stats.sigma[n][i] = (n < h->p && i < h->r[n]) ? h->ctrl_h->sigma[n][i] : 0.0;
+    h->sigma_stale = false;
+  }
   *out = h->stats;
   return TDB_OK;
 }
 
 void tdb_destroy(tdb_handle h) {
-  if (!h) return;
+  if (!h || h->batch_owned) return;
   (void)hipDeviceSynchronize();
   delete h;
 }
@@ -1186,6 +1527,122 @@ tdb_status tdb_profile_read(tdb_handle h, int32_t pass, int64_t* launches, doubl
   if (bytes_per_launch)
     *bytes_per_launch = (double)h->S * (double)h->delt * (pass == TDB_PASS_PROJECT ? 2.0 : 1.0);
   return TDB_OK;
+}
+
+tdb_status tdb_batch_create(int32_t n, const tdb_config* cfgs, const void* const* V0_dev, void* stream,
+                            tdb_batch* out) {
+  if (!out) { g_create_error = "out is NULL"; return TDB_EINVAL; }
+  *out = nullptr;
+  if (n < 1 || !cfgs || !V0_dev) { g_create_error = "need n >= 1 configurations and snapshots"; return TDB_EINVAL; }
+  tdb_batch_ctx* b = new (std::nothrow) tdb_batch_ctx();
+  if (!b) { g_create_error = "out of host memory"; return TDB_ENOMEM; }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto run = [&]() -> tdb_status {
+    b->n = n;
+    b->data32 = cfgs[0].data_dtype == TDB_F32;
+    b->f32 = cfgs[0].precision == TDB_PREC_F32;
+    for (int i = 0; i < n; ++i) {
+      const tdb_config& c = cfgs[i];
+      if (c.order != 3 || c.path == TDB_PATH_PLAIN) {
+        b->err = "stream " + std::to_string(i) + ": batches take third-order streams on the fused path";
+        return TDB_EUNSUPPORTED;
+      }
+      if ((c.data_dtype == TDB_F32) != b->data32 || (c.precision == TDB_PREC_F32) != b->f32) {
+        b->err = "all streams of a batch share data_dtype and precision";
+        return TDB_EINVAL;
+      }
+      if (!V0_dev[i]) { b->err = "stream " + std::to_string(i) + ": V0 is NULL"; return TDB_EINVAL; }
+      std::string msg;
+      const tdb_status v = validate(&c, msg);
+      if (v != TDB_OK) { b->err = "stream " + std::to_string(i) + ": " + msg; return v; }
+    }
+    for (int i = 0; i < n; ++i) {
+      const tdb_config& c = cfgs[i];
+      tdb_ctx* h = nullptr;
+      tdb_status r = create(&c, &h);
+      if (r != TDB_OK) { b->err = "stream " + std::to_string(i) + ": " + g_create_error; return r; }
+      b->st.push_back(h);
+      h->batch_owned = true;
+      r = init_hosvd(h, V0_dev[i], s);
+      if (r == TDB_OK) r = b->f32 ? fused_post<float>(h, s) : fused_post<double>(h, s);
+      if (r == TDB_OK) r = pull_ctrl(h, s);
+      if (r != TDB_OK) { b->err = "stream " + std::to_string(i) + ": " + h->err; return r; }
+      h->ready = true;
+    }
+    return batch_setup(b);
+  };
+  tdb_status st = run();
+  if (st != TDB_OK) {
+    g_create_error = b->err;
+    delete b;
+    return st;
+  }
+  *out = b;
+  return TDB_OK;
+}
+
+tdb_status tdb_batch_ingest(tdb_batch b, const void* const* V_dev, void* stream) {
+  if (!b) { g_create_error = "batch is NULL"; return TDB_EINVAL; }
+  if (!V_dev) { b->err = "V_dev is NULL"; return TDB_EINVAL; }
+  for (int i = 0; i < b->n; ++i)
+    if (!V_dev[i]) { b->err = "snapshot " + std::to_string(i) + " is NULL"; return TDB_EINVAL; }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  tdb_status st;
+  if (b->data32) st = b->f32 ? batch_step<float, float>(b, V_dev, s) : batch_step<float, double>(b, V_dev, s);
+  else st = b->f32 ? batch_step<double, float>(b, V_dev, s) : batch_step<double, double>(b, V_dev, s);
+  if (st != TDB_OK) return st;
+  for (int i = 0; i < b->n; ++i)
+    if (!std::isfinite(b->st[i]->stats.eps)) {
+      b->err = "stream " + std::to_string(i) + ": non-finite reconstruction error";
+      return TDB_ENUMERIC;
+    }
+  return TDB_OK;
+}
+
+tdb_status tdb_batch_stream(tdb_batch b, int32_t i, tdb_handle* out) {
+  if (!b) { g_create_error = "batch is NULL"; return TDB_EINVAL; }
+  if (!out || i < 0 || i >= b->n) { b->err = "bad stream index"; return TDB_EINVAL; }
+  *out = b->st[i];
+  return TDB_OK;
+}
+
+tdb_status tdb_batch_profile_enable(tdb_batch b, int32_t on) {
+  if (!b) { g_create_error = "batch is NULL"; return TDB_EINVAL; }
+  BHIPCHK(hipDeviceSynchronize());
+  for (auto& v : b->ev_used) {
+    for (auto& e : v) { b->ev_pool.push_back(e.first); b->ev_pool.push_back(e.second); }
+    v.clear();
+  }
+  b->prof = on != 0;
+  return TDB_OK;
+}
+
+tdb_status tdb_batch_profile_read(tdb_batch b, int32_t pass, int64_t* launches, double* total_ms,
+                                  double* bytes_per_launch) {
+  if (!b) { g_create_error = "batch is NULL"; return TDB_EINVAL; }
+  if (pass != TDB_PASS_PROJECT && pass != TDB_PASS_ERROR) { b->err = "bad pass id"; return TDB_EINVAL; }
+  double ms = 0.0;
+  for (auto& e : b->ev_used[pass]) {
+    BHIPCHK(hipEventSynchronize(e.second));
+    float x = 0.0f;
+    BHIPCHK(hipEventElapsedTime(&x, e.first, e.second));
+    ms += x;
+  }
+  if (launches) *launches = (int64_t)b->ev_used[pass].size();
+  if (total_ms) *total_ms = ms;
+  if (bytes_per_launch) *bytes_per_launch = pass == TDB_PASS_PROJECT ? b->bytes_pass : b->bytes_err;
+  return TDB_OK;
+}
+
+void tdb_batch_destroy(tdb_batch b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  delete b;
+}
+
+const char* tdb_batch_last_error(tdb_batch b) {
+  if (!b) return g_create_error.c_str();
+  return b->err.c_str();
 }
 
 void tdb_struct_sizes(int64_t* config_bytes, int64_t* stats_bytes) {

@@ -110,8 +110,21 @@ def load_library(path: str = LIB_PATH):
     lib.tdb_profile_read.restype = ctypes.c_int32
     lib.tdb_struct_sizes.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     lib.tdb_struct_sizes.restype = None
+    lib.tdb_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(TdbConfig), ctypes.POINTER(P), P,
+                                     ctypes.POINTER(H)]
+    lib.tdb_batch_ingest.argtypes = [H, ctypes.POINTER(P), P]
+    lib.tdb_batch_stream.argtypes = [H, ctypes.c_int32, ctypes.POINTER(H)]
+    lib.tdb_batch_profile_enable.argtypes = [H, ctypes.c_int32]
+    lib.tdb_batch_profile_read.argtypes = [H, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.tdb_batch_destroy.argtypes = [H]
+    lib.tdb_batch_destroy.restype = None
+    lib.tdb_batch_last_error.argtypes = [H]
+    lib.tdb_batch_last_error.restype = ctypes.c_char_p
     for name in ("tdb_init", "tdb_init_from_factors", "tdb_ingest_snapshot", "tdb_get_core_and_bases",
-                 "tdb_reconstruct", "tdb_set_threshold", "tdb_get_stats"):
+                 "tdb_reconstruct", "tdb_set_threshold", "tdb_get_stats", "tdb_batch_create",
+                 "tdb_batch_ingest", "tdb_batch_stream", "tdb_batch_profile_enable",
+                 "tdb_batch_profile_read"):
         getattr(lib, name).restype = ctypes.c_int32
     a, b = ctypes.c_int64(), ctypes.c_int64()
     lib.tdb_struct_sizes(ctypes.byref(a), ctypes.byref(b))
@@ -251,8 +264,71 @@ class Compressor:
         return {"launches": n.value, "total_ms": ms.value, "bytes_per_launch": by.value}
 
     def close(self):
-        if self.h:
+        if self.h and not getattr(self, "_borrowed", False):
             self.lib.tdb_destroy(self.h)
+        self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent third-order streams advanced together (see tdb.h): one launch
+    per kernel covers every stream. `configs` holds one keyword dict per stream with
+    the Compressor arguments (dims, dt, rank_max, ...); all share data_dtype and
+    precision."""
+
+    def __init__(self, configs: Sequence[dict]):
+        self.lib = load_library()
+        self._members = [Compressor(**kw) for kw in configs]
+        self.n = len(self._members)
+        self._cfgs = (TdbConfig * self.n)(*[m.cfg for m in self._members])
+        self.h = ctypes.c_void_p()
+        self.streams: List[Compressor] = []
+
+    def _check(self, status: int):
+        if status != OK:
+            msg = self.lib.tdb_batch_last_error(self.h if self.h else None)
+            raise TDBError(status, (msg or b"").decode())
+
+    def _ptrs(self, Vs):
+        if len(Vs) != self.n:
+            raise ValueError(f"need {self.n} snapshots, got {len(Vs)}")
+        return (ctypes.c_void_p * self.n)(*[_dev_ptr(v) for v in Vs])
+
+    def init(self, V0s, stream=None):
+        self._check(self.lib.tdb_batch_create(self.n, self._cfgs, self._ptrs(V0s), _stream_ptr(stream),
+                                              ctypes.byref(self.h)))
+        for i, m in enumerate(self._members):
+            hh = ctypes.c_void_p()
+            self._check(self.lib.tdb_batch_stream(self.h, i, ctypes.byref(hh)))
+            m.h = hh
+            m._borrowed = True
+            self.streams.append(m)
+        return self
+
+    def ingest(self, Vs, stream=None):
+        self._check(self.lib.tdb_batch_ingest(self.h, self._ptrs(Vs), _stream_ptr(stream)))
+
+    def profile_enable(self, on: bool = True):
+        self._check(self.lib.tdb_batch_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self, pass_name: str = "project") -> dict:
+        n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        pid = {"project": 0, "error": 1}[pass_name]
+        self._check(self.lib.tdb_batch_profile_read(self.h, pid, ctypes.byref(n), ctypes.byref(ms),
+                                                    ctypes.byref(by)))
+        return {"launches": n.value, "total_ms": ms.value, "bytes_per_launch": by.value}
+
+    def close(self):
+        for m in self.streams:
+            m.h = ctypes.c_void_p()
+        self.streams = []
+        if self.h:
+            self.lib.tdb_batch_destroy(self.h)
             self.h = ctypes.c_void_p()
 
     def __del__(self):

@@ -67,3 +67,51 @@ def test_null_handle_calls_fail_cleanly():
     s = tdb.TdbStats()
     assert lib.tdb_get_stats(None, ctypes.byref(s)) == tdb.EINVAL
     lib.tdb_destroy(None)
+
+
+def _cfg3(tdb):
+    cfg = tdb.TdbConfig()
+    cfg.order = 3
+    for n in range(3):
+        cfg.dims[n] = 8
+        cfg.rank_max[n] = 2
+    cfg.dt = 0.1
+    cfg.eps_th = 1e-3
+    cfg.adaptive = 1
+    return cfg
+
+
+@pytest.mark.parametrize("case,code", [("n0", 1), ("order4", 6), ("plain", 6), ("mixed_dtype", 1), ("dt0", 1)])
+def test_batch_create_validates_before_device_work(case, code):
+    from paper_2201_06958_amd import tdb
+    lib = tdb.load_library()
+    cfgs = (tdb.TdbConfig * 2)(_cfg3(tdb), _cfg3(tdb))
+    n = 2
+    if case == "n0":
+        n = 0
+    elif case == "order4":
+        cfgs[1].order = 4
+        cfgs[1].dims[3] = 2
+        cfgs[1].rank_max[3] = 1
+    elif case == "plain":
+        cfgs[0].path = 1
+    elif case == "mixed_dtype":
+        cfgs[1].data_dtype = 1
+    elif case == "dt0":
+        cfgs[0].dt = 0.0
+    ptrs = (ctypes.c_void_p * 2)(1, 1)   # never dereferenced: validation fails first
+    b = ctypes.c_void_p()
+    st = lib.tdb_batch_create(n, cfgs, ptrs, None, ctypes.byref(b))
+    assert st == code
+    assert not b.value
+    assert lib.tdb_batch_last_error(None)
+
+
+def test_batch_null_handle_calls():
+    from paper_2201_06958_amd import tdb
+    lib = tdb.load_library()
+    out = ctypes.c_void_p()
+    assert lib.tdb_batch_ingest(None, None, None) == 1
+    assert lib.tdb_batch_stream(None, 0, ctypes.byref(out)) == 1
+    assert lib.tdb_batch_profile_enable(None, 1) == 1
+    lib.tdb_batch_destroy(None)
