@@ -47,7 +47,7 @@ enum {
 };
 
 enum { TDB_F64 = 0, TDB_F32 = 1 };                      /* snapshot storage type  */
-enum { TDB_PREC_F64 = 0, TDB_PREC_F32 = 1 };            /* bulk-pass arithmetic   */
+enum { TDB_PREC_F64 = 0, TDB_PREC_F32 = 1, TDB_PREC_BF16SPLIT = 2 };  /* bulk-pass arithmetic */
 enum { TDB_PATH_AUTO = 0, TDB_PATH_PLAIN = 1, TDB_PATH_FUSED = 2 };
 enum { TDB_COPY = 0, TDB_BORROW = 1 };                  /* previous-snapshot mode */
 enum {                                                   /* controller events      */
@@ -70,9 +70,15 @@ typedef struct {
                                           weights (diagonal W^(n)); NULL => 1/N_n      */
   double dt;                           /* uniform snapshot spacing, > 0                */
   int32_t data_dtype;                  /* TDB_F64 | TDB_F32                            */
-  int32_t precision;                   /* TDB_PREC_F64 | TDB_PREC_F32 (projection and
-                                          error passes; the small r x r work and the
-                                          state are always FP64)                       */
+  int32_t precision;                   /* TDB_PREC_F64 | TDB_PREC_F32 |
+                                          TDB_PREC_BF16SPLIT (projection and error
+                                          passes; the small r x r work and the state
+                                          are always FP64). BF16SPLIT: the stage pass
+                                          on matrix cores with x = hi + lo in BF16
+                                          and the products hi*hi + hi*lo + lo*hi
+                                          accumulated in FP32, where the shapes allow
+                                          (order 3, N_3 <= 8, r_1, r_2 <= 32), else
+                                          as F32; the error pass in FP32            */
   int32_t path;                        /* TDB_PATH_*: AUTO picks FUSED where supported */
   int32_t adaptive;                    /* 0 = fixed ranks (eps is still reported)      */
   int32_t snapshot_mode;               /* TDB_COPY: the library keeps its own copy of

@@ -87,6 +87,25 @@ struct FErrArgs {
 };
 
 // ev0/ev1 (may be null): events stamped by the dispatch itself at kernel start and end.
+// Lanes that share one reduction output: a power of two (<= 64) such that each lane
+// sums at most 8 partials when possible.
+__host__ __device__ inline int red_lanes(int count) {
+  int L = 1;
+  while (L < 64 && L * 8 < count) L <<= 1;
+  return L;
+}
+__host__ __device__ inline long long pad64(long long x) { return (x + 63) / 64 * 64; }
+// Work items of the partial reduction (each output takes red_lanes(count) lanes; each
+// kind of output starts on a wave boundary).
+__host__ __device__ inline long long freduce_items(const FReduceArgs& a) {
+  const long long nH1 = a.need_h1 ? (long long)a.N1 * a.r1 : 0;
+  const long long nH2 = a.need_h2 ? (long long)a.N2 * a.r2 : 0;
+  const long long nH3 = a.need_f3 ? (long long)a.N3 * a.r3 : 0;
+  const long long nC = (long long)a.r1 * a.r2 * a.r3;
+  const int L3 = red_lanes(a.nt1 * a.nt2);
+  return pad64(nH1 * red_lanes(a.nt2)) + pad64(nH2 * red_lanes(a.nt1)) + pad64(nH3 * L3) + pad64(nC * L3);
+}
+
 template <typename TD, typename T>
 hipError_t launch_fpass(const FPassArgs& a, size_t lds, hipStream_t s, hipEvent_t ev0 = nullptr,
                         hipEvent_t ev1 = nullptr);
@@ -100,6 +119,14 @@ hipError_t launch_fpost(const FPostArgs& a, size_t lds, CtrlState* c, hipStream_
 template <typename TD, typename T>
 hipError_t launch_ferr(const FErrArgs& a, CtrlState* c, hipStream_t s, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr);
+
+// ---------------------------------------------------------------- matrix-core pass
+// Stage-pass flavours on the matrix cores (tile 16 x 64 x N3, N3 <= 8, r1, r2 <= 32).
+enum { MPASS_NONE = 0, MPASS_F32 = 1, MPASS_BF16S = 2 };
+size_t mpass_lds_bytes(int r1, int r2, int r3, int N3, int T2, bool h1, bool h2, bool f3, bool pst);
+template <typename TD>
+hipError_t launch_mpass(const FPassArgs& a, int flavor, size_t lds, hipStream_t s, hipEvent_t ev0 = nullptr,
+                        hipEvent_t ev1 = nullptr);
 
 // ---------------------------------------------------------------- batched streams
 // Many independent streams in one launch per kernel: the global block index selects
@@ -123,6 +150,10 @@ struct BatchSummary {
 template <typename TD, typename T>
 hipError_t launch_batch_fpass(const FPassArgs* tab, const void* const* v1, const void* const* v0, BatchMap m,
                               int blocks, size_t lds, hipStream_t s, hipEvent_t ev0 = nullptr,
+                              hipEvent_t ev1 = nullptr);
+template <typename TD>
+hipError_t launch_batch_mpass(const FPassArgs* tab, const void* const* v1, const void* const* v0, BatchMap m,
+                              int blocks, int flavor, size_t lds, hipStream_t s, hipEvent_t ev0 = nullptr,
                               hipEvent_t ev1 = nullptr);
 template <typename T>
 hipError_t launch_batch_freduce(const FReduceArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, int stage,

@@ -48,9 +48,11 @@ __device__ __forceinline__ double sum_strided(const T* __restrict__ p, long long
   return ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7));
 }
 
-// Sums the per-tile partials in a fixed order (FP64) into H_n, M_n and C_dot, and
-// applies the Heun update to the core (stage 1: k = C_dot/dt, C* = C + dt k;
-// stage 2: C <- C + dt/2 (k + C_dot/dt)).
+// Sums the per-tile partials in a fixed order (FP64) into H_n and C_dot, and applies
+// the Heun update to the core (stage 1: k = C_dot/dt, C* = C + dt k; stage 2:
+// C <- C + dt/2 (k + C_dot/dt)). Each output is summed by a group of L lanes (lane j
+// takes partials j, j + L, ...), then combined by a fixed butterfly, so the order of
+// the additions never depends on scheduling.
 template <typename T>
 __device__ __forceinline__ void freduce_body(const FReduceArgs& a, CtrlState* ctrl, int bx, int gx) {
   if (a.stage == 2 && ctrl->numeric) return;
@@ -62,41 +64,61 @@ __device__ __forceinline__ void freduce_body(const FReduceArgs& a, CtrlState* ct
   const long long nH2 = a.need_h2 ? (long long)a.N2 * a.r2 : 0;
   const long long nH3 = a.need_f3 ? (long long)a.N3 * a.r3 : 0;
   const long long nC = (long long)a.r1 * a.r2 * a.r3;
-  const long long total = nH1 + nH2 + nH3 + nC;
   const int ntiles = a.nt1 * a.nt2;
+  const int L1 = red_lanes(a.nt2), L2 = red_lanes(a.nt1), L3 = red_lanes(ntiles);
+  const long long e1 = pad64(nH1 * L1), e2 = e1 + pad64(nH2 * L2), e3 = e2 + pad64(nH3 * L3);
+  const long long e4 = e3 + pad64(nC * L3);
   const long long oH2 = (long long)a.T1 * a.r1, oH3 = oH2 + (long long)a.T2 * a.r2;
   const long long oC = oH3 + (long long)a.N3 * a.r3;
   const double inv_dt = 1.0 / a.dt;
-  for (long long t = (long long)bx * blockDim.x + threadIdx.x; t < total;
-       t += (long long)gx * blockDim.x) {
+  // e4 is a multiple of 64 and so is the stride: every wave runs the same trip count
+  for (long long t = (long long)bx * blockDim.x + threadIdx.x; t < e4; t += (long long)gx * blockDim.x) {
+    int kind, L;
+    long long u;
+    if (t < e1) { kind = 0; L = L1; u = t; }
+    else if (t < e2) { kind = 1; L = L2; u = t - e1; }
+    else if (t < e3) { kind = 2; L = L3; u = t - e2; }
+    else { kind = 3; L = L3; u = t - e3; }
+    const long long q = u / L;
+    const int j = (int)(u - q * L);
+    const long long nq = kind == 0 ? nH1 : kind == 1 ? nH2 : kind == 2 ? nH3 : nC;
+    const bool valid = q < nq;
     double s = 0.0;
-    long long q = t;
-    if (q < nH1) {
-      const long long i1 = q / a.r1;
-      const int ai = (int)(q - i1 * a.r1);
-      const int t1 = (int)(i1 / a.T1), i1l = (int)(i1 - (long long)t1 * a.T1);
-      s = sum_strided(part + (long long)(t1 * a.nt2) * a.slot + i1l * a.r1 + ai, a.slot, a.nt2);
+    if (valid) {
+      const T* base;
+      long long stride;
+      int count;
+      if (kind == 0) {
+        const long long i1 = q / a.r1;
+        const int ai = (int)(q - i1 * a.r1);
+        const int t1 = (int)(i1 / a.T1), i1l = (int)(i1 - (long long)t1 * a.T1);
+        base = part + (long long)(t1 * a.nt2) * a.slot + i1l * a.r1 + ai;
+        stride = a.slot;
+        count = a.nt2;
+      } else if (kind == 1) {
+        const long long i2 = q / a.r2;
+        const int b = (int)(q - i2 * a.r2);
+        const int t2 = (int)(i2 / a.T2), i2l = (int)(i2 - (long long)t2 * a.T2);
+        base = part + (long long)t2 * a.slot + oH2 + i2l * a.r2 + b;
+        stride = (long long)a.nt2 * a.slot;
+        count = a.nt1;
+      } else {
+        base = part + (kind == 2 ? oH3 : oC) + q;
+        stride = a.slot;
+        count = ntiles;
+      }
+      const int cnt = (count - j + L - 1) / L;
+      if (cnt > 0) s = sum_strided(base + (long long)j * stride, stride * L, cnt);
+    }
+    for (int o = L >> 1; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (!valid || j != 0) continue;
+    if (kind == 0) {
       a.H[0][q] = s;
-      continue;
-    }
-    q -= nH1;
-    if (q < nH2) {
-      const long long i2 = q / a.r2;
-      const int b = (int)(q - i2 * a.r2);
-      const int t2 = (int)(i2 / a.T2), i2l = (int)(i2 - (long long)t2 * a.T2);
-      s = sum_strided(part + (long long)t2 * a.slot + oH2 + i2l * a.r2 + b, (long long)a.nt2 * a.slot, a.nt1);
+    } else if (kind == 1) {
       a.H[1][q] = s;
-      continue;
-    }
-    q -= nH2;
-    if (q < nH3) {
-      s = sum_strided(part + oH3 + q, a.slot, ntiles);
+    } else if (kind == 2) {
       a.H[2][q] = s;
-      continue;
-    }
-    q -= nH3;
-    if (q < nC) {
-      s = sum_strided(part + oC + q, a.slot, ntiles);
+    } else {
       const double cd = s * inv_dt;
       if (a.stage == 1) {
         a.kC[q] = cd;
@@ -742,9 +764,7 @@ __global__ void __launch_bounds__(256) k_ferr_final(const double* __restrict__ p
 
 template <typename T>
 hipError_t launch_freduce(const FReduceArgs& a, CtrlState* c, hipStream_t s) {
-  long long total = (long long)a.r1 * a.r2 * a.r3 + (a.need_h1 ? (long long)a.N1 * a.r1 : 0) +
-                    (a.need_h2 ? (long long)a.N2 * a.r2 : 0) + (a.need_f3 ? (long long)a.N3 * a.r3 : 0);
-  long long blocks = (total + 255) / 256;
+  long long blocks = (freduce_items(a) + 255) / 256;
   if (blocks < 1) blocks = 1;
   if (blocks > 1024) blocks = 1024;
   hipLaunchKernelGGL(k_freduce<T>, dim3((unsigned)blocks), dim3(256), 0, s, a, c);

@@ -1,0 +1,313 @@
+// Stage pass on the matrix cores (eqs. (Corecont) and (basecont)) for third-order
+// streams whose first two ranks are at most 32 and whose third mode has at most 8
+// entries (the variables / species / components mode of the target workloads).
+//
+// Tile: 16 rows of mode 1 x T2 (16, 32 or 64) rows of mode 2 x all N3 of mode 3;
+// 4 waves. The pseudo-inverses are staged in LDS with the tile when they fit.
+//   Z[c2][i1][i2] = sum_c D[i1][i2][c] B3[c][c2]        (VALU, from the loaded fibers)
+//   Y[c][i1][b]   = sum_i2 D[c][i1][i2] B2[i2][b]      (only if mode 3 is not full rank)
+//   F1[i1][b,c2]  = sum_i2 Z[c2][i1][i2] B2[i2][b]
+//   F2[i2][a,c2]  = sum_i1 B1[i1][a] Z[c2][i1][i2]
+//   F3[a,b][c]    = sum_i1 B1[i1][a] Y[c][i1][b]
+//   H1p = F1 P1, H2p = F2 P2, H3p = F3^T P3, Cdot_p[a][b,c2] = sum_i1 B1[i1][a] F1[i1][b,c2]
+// Every product above is a sum of 16 x 16 output blocks computed by one wave each,
+// either with FP32 matrix instructions (16x16x4) or with BF16-split products
+// (x = hi + lo, hi·hi + hi·lo + lo·hi on 16x16x32 BF16 instructions), always
+// accumulated in FP32. The per-tile partial slot has the same layout as the generic
+// pass, so the reduction and the rest of the step are shared.
+#include "tdb_common.h"
+#include "tdb_kernels.h"
+#include "fused.h"
+#include <hip/hip_ext.h>
+
+namespace tdb {
+
+typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef __bf16 mbf8 __attribute__((ext_vector_type(8)));
+
+// One 16 x 16 block C += A B over K (valid K entries Kv): A(m, k) = A[m*sam + k*sak]
+// for m < Mv, B(k, n) = B[k*sbk + n*sbn] for n < Nv, zero elsewhere. Lane l feeds
+// row/column l % 16 and the K slice selected by l / 16.
+template <int MF>
+__device__ __forceinline__ mf4 mma_block(const float* A, int sam, int sak, int Mv, const float* B, int sbk, int sbn,
+                                         int Nv, int Kv, mf4 acc) {
+  const int l = threadIdx.x & 63;
+  const int mn = l & 15, kg = l >> 4;
+  const bool am = mn < Mv, bn = mn < Nv;
+  if (MF == MPASS_F32) {
+#pragma unroll 4
+    for (int k0 = 0; k0 < Kv; k0 += 4) {
+      const int k = k0 + kg;
+      const float a = (am && k < Kv) ? A[mn * sam + k * sak] : 0.0f;
+      const float b = (bn && k < Kv) ? B[k * sbk + mn * sbn] : 0.0f;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    }
+  } else {
+    for (int k0 = 0; k0 < Kv; k0 += 32) {
+      mbf8 ah, al, bh, bl;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + 8 * kg + j;
+        const float a = (am && k < Kv) ? A[mn * sam + k * sak] : 0.0f;
+        const float b = (bn && k < Kv) ? B[k * sbk + mn * sbn] : 0.0f;
+        const __bf16 a1 = (__bf16)a, b1 = (__bf16)b;
+        ah[j] = a1;
+        al[j] = (__bf16)(a - (float)a1);
+        bh[j] = b1;
+        bl[j] = (__bf16)(b - (float)b1);
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+    }
+  }
+  return acc;
+}
+
+// Store a 16 x 16 block: lane l holds rows 4*(l/16) + i, column l % 16.
+__device__ __forceinline__ void store_block(const mf4& acc, float* C, int scm, int scn, int Mv, int Nv) {
+  const int l = threadIdx.x & 63;
+  const int n = l & 15, m0 = 4 * (l >> 4);
+  if (n >= Nv) return;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (m0 + i < Mv) C[(m0 + i) * scm + n * scn] = acc[i];
+}
+
+// LDS floats of one tile (T1 = 16) for ranks (r1, r2, r3), N3 and T2; `pst` stages
+// the pseudo-inverses that are needed (h1, h2, f3).
+__host__ __device__ inline long long mpass_lds_floats(int r1, int r2, int r3, int N3, int T2, bool h1, bool h2,
+                                                     bool f3, bool pst) {
+  const long long R1 = (long long)r2 * r3, R2 = (long long)r1 * r3, R3 = (long long)r1 * r2;
+  long long e = (long long)r3 * 16 * T2 + 16LL * r1 + (long long)T2 * r2 + 64 + 16 * R1;
+  if (pst) e += (h1 ? R1 * r1 : 0) + (h2 ? R2 * r2 : 0) + (f3 ? R3 * r3 : 0);
+  long long x = (long long)T2 * R2 + (f3 ? R3 * N3 : 0);
+  if (f3) {
+    const long long dsz = (long long)N3 * 16 * T2;
+    x = x > dsz ? x : dsz;
+    e += (long long)N3 * 16 * r2;
+  }
+  return e + x;
+}
+
+template <typename TD, int MF>
+__device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float* sm = reinterpret_cast<float*>(smem_raw);
+  const int N2 = a.N2, N3 = a.N3, r1 = a.r1, r2 = a.r2, r3 = a.r3, T2 = a.T2;
+  const int t1 = bx / a.nt2, t2 = bx - (bx / a.nt2) * a.nt2;
+  const int i1_0 = t1 * 16, i2_0 = t2 * T2;
+  const int n1 = min(16, a.N1 - i1_0), n2 = min(T2, N2 - i2_0);
+  const int R1 = r2 * r3, R2 = r1 * r3, R3 = r1 * r2;
+  const bool f3 = a.need_f3 != 0;
+  const int TS = 16 * T2;                  // fibers per tile
+  float* Zs = sm;                          // r3 x 16 x T2
+  float* B1s = Zs + r3 * TS;               // 16 x r1
+  float* B2s = B1s + 16 * r1;              // T2 x r2
+  float* B3s = B2s + T2 * r2;              // N3 x r3 (<= 64)
+  float* F1s = B3s + 64;                   // 16 x R1
+  float* Pp = F1s + 16 * R1;               // staged P1 | P2 | P3
+  const float* P1 = static_cast<const float*>(a.P1);
+  const float* P2 = static_cast<const float*>(a.P2);
+  const float* P3 = static_cast<const float*>(a.P3);
+  float* pend = Pp;
+  if (a.stage_p) pend += (a.need_h1 ? R1 * r1 : 0) + (a.need_h2 ? R2 * r2 : 0) + (f3 ? R3 * r3 : 0);
+  float* Ys = pend;                        // N3 x 16 x r2 (f3)
+  float* X = Ys + (f3 ? N3 * 16 * r2 : 0); // D (N3 x 16 x T2), later F2 (T2 x R2) | F3 (R3 x N3)
+  float* Ds = X;
+  float* F2s = X;
+  float* F3s = X + T2 * R2;
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int per = TS >> 8;                 // fibers per thread: 1, 2 or 4
+
+  // 1. issue the snapshot loads: `per` fibers of N3 values per thread
+  const TD* V1 = static_cast<const TD*>(a.V1);
+  const TD* V0 = static_cast<const TD*>(a.V0);
+  float d[4][8];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int q = tid + 256 * u;
+    const int i1 = q / T2, i2 = q - (q / T2) * T2;
+    const bool ok = u < per && i1 < n1 && i2 < n2;
+    const long long g = ((long long)(i1_0 + i1) * N2 + i2_0 + i2) * N3;
+    if (sizeof(TD) == 4 && (N3 == 4 || N3 == 8) && ((reinterpret_cast<uintptr_t>(V1) | reinterpret_cast<uintptr_t>(V0)) & 15) == 0) {
+      // whole fibers as 16-byte loads (a fiber of 4 or 8 FP32 values is 16-byte aligned)
+      const float4* p1 = reinterpret_cast<const float4*>(V1 + g);
+      const float4* p0 = reinterpret_cast<const float4*>(V0 + g);
+      float4 x1 = make_float4(0.f, 0.f, 0.f, 0.f), x0 = x1, y1 = x1, y0 = x1;
+      if (ok) {
+        x1 = p1[0];
+        x0 = p0[0];
+        if (N3 == 8) { y1 = p1[1]; y0 = p0[1]; }
+      }
+      d[u][0] = x1.x - x0.x; d[u][1] = x1.y - x0.y; d[u][2] = x1.z - x0.z; d[u][3] = x1.w - x0.w;
+      d[u][4] = y1.x - y0.x; d[u][5] = y1.y - y0.y; d[u][6] = y1.z - y0.z; d[u][7] = y1.w - y0.w;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        float v = 0.0f;
+        if (ok && c < N3) v = (float)V1[g + c] - (float)V0[g + c];
+        d[u][c] = v;
+      }
+    }
+  }
+  // bases of this tile and the pseudo-inverses
+  const float* B1 = static_cast<const float*>(a.B1);
+  const float* B2 = static_cast<const float*>(a.B2);
+  const float* B3 = static_cast<const float*>(a.B3);
+  for (int t = tid; t < 16 * r1; t += 256) B1s[t] = t < n1 * r1 ? B1[(long long)i1_0 * r1 + t] : 0.0f;
+  for (int t = tid; t < T2 * r2; t += 256) B2s[t] = t < n2 * r2 ? B2[(long long)i2_0 * r2 + t] : 0.0f;
+  for (int t = tid; t < N3 * r3; t += 256) B3s[t] = B3[t];
+  if (a.stage_p) {
+    float* p = Pp;
+    if (a.need_h1) { for (int t = tid; t < R1 * r1; t += 256) p[t] = P1[t]; P1 = p; p += R1 * r1; }
+    if (a.need_h2) { for (int t = tid; t < R2 * r2; t += 256) p[t] = P2[t]; P2 = p; p += R2 * r2; }
+    if (f3) { for (int t = tid; t < R3 * r3; t += 256) p[t] = P3[t]; P3 = p; }
+  }
+  __syncthreads();
+  // 2. Z (and D for the third mode) into LDS
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    if (u >= per) break;
+    const int q = tid + 256 * u;
+    for (int c2 = 0; c2 < r3; ++c2) {
+      float s = 0.0f;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c < N3) s += d[u][c] * B3s[c * r3 + c2];
+      Zs[c2 * TS + q] = s;
+    }
+    if (f3)
+      for (int c = 0; c < N3; ++c) Ds[c * TS + q] = d[u][c];
+  }
+  __syncthreads();
+  const int nb1 = (r1 + 15) >> 4, nb2 = (r2 + 15) >> 4;
+  // 3. F1 (and Y)
+  {
+    const int nF1 = r3 * nb2, nY = f3 ? N3 * nb2 : 0;
+    for (int blk = wave; blk < nF1 + nY; blk += 4) {
+      mf4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (blk < nF1) {
+        const int c2 = blk / nb2, jb = blk - c2 * nb2;
+        acc = mma_block<MF>(Zs + c2 * TS, T2, 1, 16, B2s + 16 * jb, r2, 1, r2 - 16 * jb, T2, acc);
+        store_block(acc, F1s + (16 * jb) * r3 + c2, R1, r3, 16, r2 - 16 * jb);
+      } else {
+        const int q = blk - nF1;
+        const int c = q / nb2, jb = q - c * nb2;
+        acc = mma_block<MF>(Ds + c * TS, T2, 1, 16, B2s + 16 * jb, r2, 1, r2 - 16 * jb, T2, acc);
+        store_block(acc, Ys + c * 16 * r2 + 16 * jb, r2, 1, 16, r2 - 16 * jb);
+      }
+    }
+  }
+  __syncthreads();
+  // 4. F2 (over the former D) and F3
+  {
+    const int nib = T2 >> 4;
+    const int nF2 = r3 * nb1 * nib, nF3 = f3 ? N3 * nb1 * nb2 : 0;
+    for (int blk = wave; blk < nF2 + nF3; blk += 4) {
+      mf4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (blk < nF2) {
+        const int c2 = blk / (nb1 * nib), rem = blk - c2 * nb1 * nib;
+        const int ab = rem / nib, ib = rem - ab * nib;
+        // rows a (B1^T), columns i2 (Z[c2]), K = i1
+        acc = mma_block<MF>(B1s + 16 * ab, 1, r1, r1 - 16 * ab, Zs + c2 * TS + 16 * ib, T2, 1, 16, 16, acc);
+        // F2s[i2][a*r3 + c2]
+        store_block(acc, F2s + (16 * ib) * R2 + (16 * ab) * r3 + c2, r3, R2, r1 - 16 * ab, 16);
+      } else {
+        const int q = blk - nF2;
+        const int c = q / (nb1 * nb2), rem = q - c * nb1 * nb2;
+        const int ab = rem / nb2, jb = rem - ab * nb2;
+        acc = mma_block<MF>(B1s + 16 * ab, 1, r1, r1 - 16 * ab, Ys + c * 16 * r2 + 16 * jb, r2, 1, r2 - 16 * jb, 16,
+                            acc);
+        // F3s[(a*r2 + b)*N3 + c]
+        store_block(acc, F3s + ((16 * ab) * r2 + 16 * jb) * N3 + c, r2 * N3, N3, r1 - 16 * ab, r2 - 16 * jb);
+      }
+    }
+  }
+  __syncthreads();
+  // 5. folds into the partial slot
+  float* out = static_cast<float*>(a.part) + (long long)bx * a.slot;
+  float* oH1 = out;
+  float* oH2 = oH1 + 16 * r1;
+  float* oH3 = oH2 + T2 * r2;
+  float* oC = oH3 + N3 * r3;
+  const int nbR1 = (R1 + 15) >> 4;
+  const int nC = nb1 * nbR1, nH1 = a.need_h1 ? nb1 : 0, nH2 = a.need_h2 ? (T2 >> 4) * nb2 : 0, nH3 = f3 ? 1 : 0;
+  for (int blk = wave; blk < nC + nH1 + nH2 + nH3; blk += 4) {
+    mf4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (blk < nC) {
+      const int ab = blk / nbR1, kb = blk - ab * nbR1;
+      acc = mma_block<MF>(B1s + 16 * ab, 1, r1, r1 - 16 * ab, F1s + 16 * kb, R1, 1, R1 - 16 * kb, 16, acc);
+      store_block(acc, oC + (16 * ab) * R1 + 16 * kb, R1, 1, r1 - 16 * ab, R1 - 16 * kb);
+    } else if (blk < nC + nH1) {
+      const int ab = blk - nC;
+      acc = mma_block<MF>(F1s, R1, 1, 16, P1 + 16 * ab, r1, 1, r1 - 16 * ab, R1, acc);
+      store_block(acc, oH1 + 16 * ab, r1, 1, 16, r1 - 16 * ab);
+    } else if (blk < nC + nH1 + nH2) {
+      const int q = blk - nC - nH1;
+      const int ib = q / nb2, jb = q - ib * nb2;
+      acc = mma_block<MF>(F2s + (16 * ib) * R2, R2, 1, 16, P2 + 16 * jb, r2, 1, r2 - 16 * jb, R2, acc);
+      store_block(acc, oH2 + (16 * ib) * r2 + 16 * jb, r2, 1, 16, r2 - 16 * jb);
+    } else {
+      // H3p[c][c2] = sum_k F3[k][c] P3[k][c2]
+      acc = mma_block<MF>(F3s, 1, N3, N3, P3, r3, 1, r3, R3, acc);
+      store_block(acc, oH3, r3, 1, N3, r3);
+    }
+  }
+}
+
+template <typename TD, int MF>
+__global__ void __launch_bounds__(256) k_mpass(FPassArgs a) {
+  mpass_body<TD, MF>(a, blockIdx.x);
+}
+
+template <typename TD, int MF>
+__global__ void __launch_bounds__(256) kb_mpass(const FPassArgs* __restrict__ tab, const void* const* v1,
+                                                const void* const* v0, BatchMap m) {
+  const int s = m.sid[blockIdx.x];
+  FPassArgs a = tab[s];
+  a.V1 = v1[s];
+  a.V0 = v0[s];
+  mpass_body<TD, MF>(a, blockIdx.x - m.start[s]);
+}
+
+size_t mpass_lds_bytes(int r1, int r2, int r3, int N3, int T2, bool h1, bool h2, bool f3, bool pst) {
+  return (size_t)mpass_lds_floats(r1, r2, r3, N3, T2, h1, h2, f3, pst) * sizeof(float);
+}
+
+template <typename TD>
+hipError_t launch_mpass(const FPassArgs& a, int flavor, size_t lds, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  const void* f = flavor == MPASS_F32 ? (const void*)k_mpass<TD, MPASS_F32> : (const void*)k_mpass<TD, MPASS_BF16S>;
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  if (flavor == MPASS_F32)
+    hipExtLaunchKernelGGL((k_mpass<TD, MPASS_F32>), dim3(a.nt1 * a.nt2), dim3(256), (uint32_t)lds, s, ev0, ev1, 0u, a);
+  else
+    hipExtLaunchKernelGGL((k_mpass<TD, MPASS_BF16S>), dim3(a.nt1 * a.nt2), dim3(256), (uint32_t)lds, s, ev0, ev1, 0u,
+                          a);
+  return hipGetLastError();
+}
+template hipError_t launch_mpass<float>(const FPassArgs&, int, size_t, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_mpass<double>(const FPassArgs&, int, size_t, hipStream_t, hipEvent_t, hipEvent_t);
+
+template <typename TD>
+hipError_t launch_batch_mpass(const FPassArgs* tab, const void* const* v1, const void* const* v0, BatchMap m,
+                              int blocks, int flavor, size_t lds, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  const void* f =
+      flavor == MPASS_F32 ? (const void*)kb_mpass<TD, MPASS_F32> : (const void*)kb_mpass<TD, MPASS_BF16S>;
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  if (flavor == MPASS_F32)
+    hipExtLaunchKernelGGL((kb_mpass<TD, MPASS_F32>), dim3(blocks), dim3(256), (uint32_t)lds, s, ev0, ev1, 0u, tab, v1,
+                          v0, m);
+  else
+    hipExtLaunchKernelGGL((kb_mpass<TD, MPASS_BF16S>), dim3(blocks), dim3(256), (uint32_t)lds, s, ev0, ev1, 0u, tab,
+                          v1, v0, m);
+  return hipGetLastError();
+}
+template hipError_t launch_batch_mpass<float>(const FPassArgs*, const void* const*, const void* const*, BatchMap, int,
+                                              int, size_t, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_batch_mpass<double>(const FPassArgs*, const void* const*, const void* const*, BatchMap, int,
+                                               int, size_t, hipStream_t, hipEvent_t, hipEvent_t);
+
+}  // namespace tdb

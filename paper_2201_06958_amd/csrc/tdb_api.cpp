@@ -37,7 +37,9 @@ struct tdb_ctx {
   int caps[TDB_P] = {1, 1, 1, 1};
   int r[TDB_P] = {1, 1, 1, 1};
   int ldU[TDB_P] = {1, 1, 1, 1};
-  bool f32 = false;          // bulk passes in FP32
+  bool f32 = false;          // bulk passes in FP32 (or BF16-split products with FP32 sums)
+  bool bf16s = false;        // BF16-split products in the matrix-core stage pass
+  bool no_mfma = false;      // keep the generic stage pass (a batch with mixed shapes)
   bool data32 = false;       // snapshots stored as FP32
   size_t celt = 8;           // bytes per compute element
   size_t delt = 8;           // bytes per data element
@@ -154,7 +156,10 @@ tdb_status validate(const tdb_config* c, std::string& msg) {
   }
   if (!(c->dt > 0.0) || !std::isfinite(c->dt)) { msg = "dt must be positive"; return TDB_EINVAL; }
   if (c->data_dtype != TDB_F64 && c->data_dtype != TDB_F32) { msg = "bad data_dtype"; return TDB_EINVAL; }
-  if (c->precision != TDB_PREC_F64 && c->precision != TDB_PREC_F32) { msg = "bad precision"; return TDB_EINVAL; }
+  if (c->precision != TDB_PREC_F64 && c->precision != TDB_PREC_F32 && c->precision != TDB_PREC_BF16SPLIT) {
+    msg = "bad precision";
+    return TDB_EINVAL;
+  }
   if (c->path != TDB_PATH_AUTO && c->path != TDB_PATH_PLAIN && c->path != TDB_PATH_FUSED) {
     msg = "bad path";
     return TDB_EINVAL;
@@ -178,32 +183,72 @@ long long prod_ll(const int* a, int p, int skip = -1) {
 
 struct PassPlan {
   int T1 = 1, T2 = 1, nt1 = 1, nt2 = 1, stage_p = 0;
+  int mfma = 0;              // MPASS_* flavour of the stage pass
   long long slot = 0;
   size_t lds = 0;
   bool ok = false;
 };
 
 // LDS bytes of one stage-pass tile of T1 x T2 x N3 at ranks r (without the staged
-// pseudo-inverses), and the bytes of the staged pseudo-inverses.
-size_t pass_lds(const tdb_ctx* h, const int* r, int T1, int T2) {
+// pseudo-inverses), and the bytes of the staged pseudo-inverses. `worst` counts every
+// optional term (a plan made at the caps must also hold smaller ranks, for which the
+// third-mode terms may switch on).
+size_t pass_lds(const tdb_ctx* h, const int* r, int T1, int T2, bool worst = false) {
   const long long N3 = h->N[2];
   const int r1 = r[0], r2 = r[1], r3 = r[2];
   long long e = (long long)T1 * T2 * N3 + (long long)T1 * T2 * r3 + (long long)T1 * r2 * r3 +
                 (long long)r1 * T2 * r3 + 2LL * T1 * r1 + 2LL * T2 * r2 + 2LL * N3 * r3;
-  if (r3 < N3) e += (long long)T1 * r2 * N3 + (long long)r1 * r2 * N3;
+  if (r3 < N3 || worst) e += (long long)T1 * r2 * N3 + (long long)r1 * r2 * N3;
   return (size_t)e * h->celt;
 }
-size_t pass_p_bytes(const tdb_ctx* h, const int* r) {
+size_t pass_p_bytes(const tdb_ctx* h, const int* r, bool worst = false) {
   const long long c = (long long)r[0] * r[1] * r[2];
-  const long long pe = (r[0] < h->N[0] ? c : 0) + (r[1] < h->N[1] ? c : 0) + (r[2] < h->N[2] ? c : 0);
+  const long long pe = (r[0] < h->N[0] || worst ? c : 0) + (r[1] < h->N[1] || worst ? c : 0) +
+                       (r[2] < h->N[2] || worst ? c : 0);
   return (size_t)pe * h->celt;
 }
+size_t mpass_bytes(const tdb_ctx* h, const int* r, int T2, bool pst, bool worst) {
+  return mpass_lds_bytes(r[0], r[1], r[2], (int)h->N[2], T2, worst || r[0] < h->N[0], worst || r[1] < h->N[1],
+                         worst || r[2] < h->N[2], pst);
+}
 
-// Tile shape of the fused stage pass for ranks r: about `target` elements per tile,
-// shrunk until its LDS footprint fits.
-PassPlan plan_pass(const tdb_ctx* h, const int* r) {
+// Whether the matrix-core stage pass takes ranks r (FP32 arithmetic, order 3,
+// N3 <= 8, r1, r2 <= 32, LDS fits); TDB_MFMA=0 in the environment turns it off.
+bool mfma_ok(const tdb_ctx* h, const int* r, bool worst) {
+  if (!h->f32 || h->p != 3 || h->no_mfma || h->N[2] > 8 || r[0] > 32 || r[1] > 32 || r[2] > h->N[2]) return false;
+  if (const char* env = std::getenv("TDB_MFMA"))
+    if (env[0] == '0') return false;
+  return mpass_bytes(h, r, 16, false, worst) <= (size_t)h->lds_max;
+}
+
+// LDS up to which two matrix-core tiles still share a compute unit (160 KB each);
+// the pseudo-inverses are staged only within it, since occupancy hides more latency
+// than the staging saves.
+size_t mpass_occupancy_budget(const tdb_ctx* h) { return std::min<size_t>((size_t)h->lds_max, 78 * 1024); }
+
+// Tile shape of the fused stage pass for ranks r. Matrix-core tiles are 16 x T2 x N3
+// with T2 the largest of 64, 32, 16 that fits and (for a single stream) still gives
+// at least two tiles per compute unit; generic tiles hold about `target` elements,
+// shrunk until their LDS fits. `worst`: size for every rank up to r (batches).
+PassPlan plan_pass(const tdb_ctx* h, const int* r, bool worst = false) {
   PassPlan pl;
   const long long N1 = h->N[0], N2 = h->N[1], N3 = h->N[2];
+  if (mfma_ok(h, r, worst)) {
+    int T2 = 64;
+    while (T2 > 16 && mpass_bytes(h, r, T2, false, worst) > (size_t)h->lds_max) T2 /= 2;
+    if (!h->batch_owned)
+      while (T2 > 16 && ((N1 + 15) / 16) * ((N2 + T2 - 1) / T2) < 512) T2 /= 2;
+    pl.mfma = h->bf16s ? MPASS_BF16S : MPASS_F32;
+    pl.T1 = 16;
+    pl.T2 = T2;
+    pl.nt1 = (int)((N1 + 15) / 16);
+    pl.nt2 = (int)((N2 + T2 - 1) / T2);
+    pl.stage_p = mpass_bytes(h, r, T2, true, worst) <= mpass_occupancy_budget(h) ? 1 : 0;
+    pl.slot = 16LL * r[0] + (long long)T2 * r[1] + N3 * r[2] + (long long)r[0] * r[1] * r[2];
+    pl.lds = mpass_bytes(h, r, T2, pl.stage_p != 0, worst);
+    pl.ok = true;
+    return pl;
+  }
   long long target = h->f32 ? 4096 : 2048;
   if (const char* env = std::getenv("TDB_PASS_TILE")) {
     const long long v = std::atoll(env);
@@ -211,29 +256,41 @@ PassPlan plan_pass(const tdb_ctx* h, const int* r) {
   }
   int T2 = (int)std::min<long long>(N2, 64);
   int T1 = (int)std::max<long long>(1, std::min<long long>(N1, target / std::max<long long>(1, T2 * N3)));
-  while (pass_lds(h, r, T1, T2) > (size_t)h->lds_max && T1 > 1) T1 = std::max(1, T1 / 2);
-  while (pass_lds(h, r, T1, T2) > (size_t)h->lds_max && T2 > 8) T2 = std::max(8, T2 / 2);
-  if (pass_lds(h, r, T1, T2) > (size_t)h->lds_max) return pl;
+  while (pass_lds(h, r, T1, T2, worst) > (size_t)h->lds_max && T1 > 1) T1 = std::max(1, T1 / 2);
+  while (pass_lds(h, r, T1, T2, worst) > (size_t)h->lds_max && T2 > 8) T2 = std::max(8, T2 / 2);
+  if (pass_lds(h, r, T1, T2, worst) > (size_t)h->lds_max) return pl;
   // stage the pseudo-inverses too when they fit
-  if (pass_lds(h, r, T1, T2) + pass_p_bytes(h, r) <= (size_t)h->lds_max) pl.stage_p = 1;
+  if (pass_lds(h, r, T1, T2, worst) + pass_p_bytes(h, r, worst) <= (size_t)h->lds_max) pl.stage_p = 1;
   pl.T1 = T1;
   pl.T2 = T2;
   pl.nt1 = (int)((N1 + T1 - 1) / T1);
   pl.nt2 = (int)((N2 + T2 - 1) / T2);
   pl.slot = (long long)T1 * r[0] + (long long)T2 * r[1] + N3 * r[2] + (long long)r[0] * r[1] * r[2];
-  pl.lds = pass_lds(h, r, T1, T2) + (pl.stage_p ? pass_p_bytes(h, r) : 0);
+  pl.lds = pass_lds(h, r, T1, T2, worst) + (pl.stage_p ? pass_p_bytes(h, r, worst) : 0);
   pl.ok = true;
   return pl;
 }
 
-// The plan `base` (made for larger ranks) applied to ranks r: same tiles and LDS
-// budget, the partial slot and the staging decision of r.
+// The plan `base` (made with `worst` for larger ranks) applied to ranks r: same tiles
+// and LDS budget, the partial slot and the staging decision of r.
 PassPlan plan_under(const tdb_ctx* h, const int* r, const PassPlan& base) {
   PassPlan pl = base;
-  const size_t need = pass_lds(h, r, base.T1, base.T2);
-  if (!base.ok || need > base.lds) { pl.ok = false; return pl; }
-  pl.stage_p = need + pass_p_bytes(h, r) <= base.lds ? 1 : 0;
   pl.slot = (long long)base.T1 * r[0] + (long long)base.T2 * r[1] + h->N[2] * r[2] + (long long)r[0] * r[1] * r[2];
+  if (!base.ok) { pl.ok = false; return pl; }
+  if (base.mfma) {
+    // LDS of the current ranks (a batch launches with the largest over its streams)
+    if (r[0] > 32 || r[1] > 32 || mpass_bytes(h, r, base.T2, false, false) > (size_t)h->lds_max) {
+      pl.ok = false;
+      return pl;
+    }
+    pl.stage_p = mpass_bytes(h, r, base.T2, true, false) <= mpass_occupancy_budget(h) ? 1 : 0;
+    pl.lds = mpass_bytes(h, r, base.T2, pl.stage_p != 0, false);
+    return pl;
+  }
+  const size_t need = pass_lds(h, r, base.T1, base.T2);
+  if (need > base.lds) { pl.ok = false; return pl; }
+  pl.stage_p = need + pass_p_bytes(h, r) <= base.lds ? 1 : 0;
+  pl.lds = need + (pl.stage_p ? pass_p_bytes(h, r) : 0);
   return pl;
 }
 
@@ -258,7 +315,8 @@ tdb_status setup(tdb_ctx* h, const tdb_config* cfg) {
     if (h->caps[n] > o) h->caps[n] = (int)o;
   }
   for (int n = 0; n < h->p; ++n) h->ldU[n] = h->caps[n];
-  h->f32 = cfg->precision == TDB_PREC_F32;
+  h->f32 = cfg->precision != TDB_PREC_F64;
+  h->bf16s = cfg->precision == TDB_PREC_BF16SPLIT;
   h->data32 = cfg->data_dtype == TDB_F32;
   h->celt = h->f32 ? 4 : 8;
   h->delt = h->data32 ? 4 : 8;
@@ -371,10 +429,22 @@ tdb_status setup_fused(tdb_ctx* h, const std::vector<std::vector<double>>& wh) {
   // dynamic LDS budget: the device limit minus room for the kernels' static LDS
   h->lds_max = lds - 4096;
   // partial buffer: enough for the ranks-1 plan and the caps plan
+  // (for the generic and the matrix-core tiles alike: a batch may switch the latter off)
   int ones[3] = {1, 1, 1};
-  PassPlan p1 = plan_pass(h, ones), pc = plan_pass(h, h->caps);
-  long long tiles = std::max<long long>(p1.ok ? (long long)p1.nt1 * p1.nt2 : 1, pc.ok ? (long long)pc.nt1 * pc.nt2 : 1);
-  long long slot = pc.ok ? pc.slot : (p1.ok ? p1.slot : 1);
+  long long tiles = 1, slot = 1;
+  // (single-stream and batch tile choices too: a context may join a batch)
+  for (int variant = 0; variant < 4; ++variant) {
+    h->no_mfma = (variant & 1) == 0;
+    h->batch_owned = (variant & 2) != 0;
+    const PassPlan p1 = plan_pass(h, ones, h->batch_owned), pc = plan_pass(h, h->caps, h->batch_owned);
+    for (const PassPlan* q : {&p1, &pc})
+      if (q->ok) {
+        tiles = std::max(tiles, (long long)q->nt1 * q->nt2);
+        slot = std::max(slot, q->slot);
+      }
+  }
+  h->no_mfma = false;
+  h->batch_owned = false;
   long long capslot = (long long)h->caps[0] * h->caps[1] * h->caps[2] + 3LL * 64 * 64 + 64 * (h->N[0] + h->N[1] + h->N[2]);
   slot = std::max(slot, std::min(capslot, slot * 4));
   h->fpart_elems = tiles * slot;
@@ -829,7 +899,7 @@ tdb_status build_post_args(tdb_ctx* h, const int* rl, FPostArgs& pa, size_t& lds
 // Returns TDB_EUNSUPPORTED when the stage pass does not fit (the caller may fall back
 // to the plain path).
 tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void* V0, StepArgs& A) {
-  const PassPlan base = plan_pass(h, rl);
+  const PassPlan base = plan_pass(h, rl, rl != h->r);
   if (!base.ok) { h->err = "stage-pass tile does not fit in LDS"; return TDB_EUNSUPPORTED; }
   const PassPlan pl = rl == h->r ? base : plan_under(h, h->r, base);
   if (!pl.ok || (long long)pl.nt1 * pl.nt2 * pl.slot > h->fpart_elems) {
@@ -867,9 +937,11 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
   ra.C0 = h->C0; ra.Cs = h->Cs; ra.kC = h->kC; ra.Cdot2 = h->Cdot2;
   for (int n = 0; n < 3; ++n) ra.H[n] = h->H[n];
   {
-    const long long total = (long long)rl[0] * rl[1] * rl[2] + (long long)h->N[0] * rl[0] +
-                            (long long)h->N[1] * rl[1] + (long long)h->N[2] * rl[2];
-    A.blocks_red = (int)std::max<long long>(1, std::min<long long>(1024, (total + 255) / 256));
+    // grid for the largest work the launch shape must cover (all outputs at the ranks rl)
+    FReduceArgs big = ra;
+    big.r1 = rl[0]; big.r2 = rl[1]; big.r3 = rl[2];
+    big.need_h1 = big.need_h2 = big.need_f3 = 1;
+    A.blocks_red = (int)std::max<long long>(1, std::min<long long>(1024, (freduce_items(big) + 255) / 256));
   }
 
   FFinishArgs ga{};
@@ -996,7 +1068,10 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
   for (int stage = 1; stage <= 2; ++stage) {
     {
       PassTimer pt(h, TDB_PASS_PROJECT, s, true);
-      HIPCHK((launch_fpass<TD, T>(A.fa[stage - 1], A.pl.lds, s, pt.start(), pt.stop())));
+      if (A.pl.mfma)
+        HIPCHK((launch_mpass<TD>(A.fa[stage - 1], A.pl.mfma, A.pl.lds, s, pt.start(), pt.stop())));
+      else
+        HIPCHK((launch_fpass<TD, T>(A.fa[stage - 1], A.pl.lds, s, pt.start(), pt.stop())));
     }
     A.ra.stage = stage;
     HIPCHK(launch_freduce<T>(A.ra, h->ctrl, s));
@@ -1083,6 +1158,7 @@ struct tdb_batch_ctx {
   BatchMap m_pass{}, m_red{}, m_fin[2]{}, m_qr{}, m_post{}, m_err{};
   int g_pass = 0, g_red = 0, g_fin[2] = {0, 0}, g_qr = 0, g_post = 0, g_err = 0;
   size_t lds_pass = 0, lds_fin = 0, lds_qr = 0, lds_post = 0;
+  int mflavor = 0;                  // MPASS_* of the batched stage pass (one for all streams)
   double bytes_pass = 0.0, bytes_err = 0.0;
   bool dirty = true;
   bool prof = false;
@@ -1157,11 +1233,13 @@ hipEvent_t take_bevent(tdb_batch_ctx* b) {
 // Rebuild every stream's argument structs (current ranks, launch shapes at the caps)
 // and upload them.
 tdb_status batch_upload_args(tdb_batch_ctx* b, hipStream_t s) {
+  size_t lds_pass = 0;
   for (int i = 0; i < b->n; ++i) {
     tdb_ctx* h = b->st[i];
     StepArgs A;
     tdb_status r = build_step_args(h, h->caps, nullptr, nullptr, A);
     if (r != TDB_OK) { b->err = "stream " + std::to_string(i) + ": " + h->err; return r; }
+    lds_pass = std::max(lds_pass, A.pl.lds);
     b->h_fa[0][i] = A.fa[0];
     b->h_fa[1][i] = A.fa[1];
     A.ra.stage = 1;
@@ -1181,6 +1259,7 @@ tdb_status batch_upload_args(tdb_batch_ctx* b, hipStream_t s) {
   BHIPCHK(hipMemcpyAsync(b->d_qa, b->h_qa, n * sizeof(FQrArgs), hipMemcpyHostToDevice, s));
   BHIPCHK(hipMemcpyAsync(b->d_pa, b->h_pa, n * sizeof(FPostArgs), hipMemcpyHostToDevice, s));
   BHIPCHK(hipMemcpyAsync(b->d_ea, b->h_ea, n * sizeof(FErrArgs), hipMemcpyHostToDevice, s));
+  b->lds_pass = lds_pass;   // the stage pass of the current ranks
   b->dirty = false;
   return TDB_OK;
 }
@@ -1188,6 +1267,20 @@ tdb_status batch_upload_args(tdb_batch_ctx* b, hipStream_t s) {
 // Launch shapes at the caps, block maps, tables.
 tdb_status batch_setup(tdb_batch_ctx* b) {
   const int n = b->n;
+  // one stage-pass kernel serves every stream: the matrix-core pass only when all
+  // streams take it at their caps
+  {
+    int first = -1;
+    bool mixed = false;
+    for (int i = 0; i < n; ++i) {
+      const int f = plan_pass(b->st[i], b->st[i]->caps, true).mfma;
+      if (first < 0) first = f;
+      else if (f != first) mixed = true;
+    }
+    if (mixed)
+      for (int i = 0; i < n; ++i) b->st[i]->no_mfma = true;
+    b->mflavor = mixed ? 0 : first;
+  }
   std::vector<int> c_pass(n), c_red(n), c_fin0(n), c_fin1(n), c_qr(n, 3), c_post(n), c_err(n);
   for (int i = 0; i < n; ++i) {
     tdb_ctx* h = b->st[i];
@@ -1195,7 +1288,7 @@ tdb_status batch_setup(tdb_batch_ctx* b) {
     tdb_status r = build_step_args(h, h->caps, nullptr, nullptr, A);
     if (r != TDB_OK) { b->err = "stream " + std::to_string(i) + ": " + h->err; return r; }
     // the plan at the caps must also hold the partials of the caps
-    const PassPlan pc = plan_pass(h, h->caps);
+    const PassPlan pc = plan_pass(h, h->caps, true);
     if ((long long)pc.nt1 * pc.nt2 * pc.slot > h->fpart_elems) {
       b->err = "stream " + std::to_string(i) + ": stage-pass partials at the caps do not fit";
       return TDB_EUNSUPPORTED;
@@ -1257,8 +1350,12 @@ tdb_status batch_step(tdb_batch_ctx* b, const void* const* V, hipStream_t s) {
       if (e0 && e1) b->ev_used[TDB_PASS_PROJECT].push_back({e0, e1});
       else e0 = e1 = nullptr;
     }
-    BHIPCHK((launch_batch_fpass<TD, T>(b->d_fa[st], b->d_v1, b->d_v0, b->m_pass, b->g_pass, b->lds_pass, s, e0,
-                                       e1)));
+    if (b->mflavor)
+      BHIPCHK((launch_batch_mpass<TD>(b->d_fa[st], b->d_v1, b->d_v0, b->m_pass, b->g_pass, b->mflavor, b->lds_pass,
+                                      s, e0, e1)));
+    else
+      BHIPCHK((launch_batch_fpass<TD, T>(b->d_fa[st], b->d_v1, b->d_v0, b->m_pass, b->g_pass, b->lds_pass, s, e0,
+                                         e1)));
     BHIPCHK(launch_batch_freduce<T>(b->d_ra, b->d_ctab, b->m_red, b->g_red, st + 1, s));
     BHIPCHK(launch_batch_ffinish<T>(b->d_ga[st], b->d_ctab, b->m_fin[st], b->g_fin[st], st + 1, b->lds_fin, s));
   }
@@ -1540,14 +1637,14 @@ tdb_status tdb_batch_create(int32_t n, const tdb_config* cfgs, const void* const
   auto run = [&]() -> tdb_status {
     b->n = n;
     b->data32 = cfgs[0].data_dtype == TDB_F32;
-    b->f32 = cfgs[0].precision == TDB_PREC_F32;
+    b->f32 = cfgs[0].precision != TDB_PREC_F64;   // FP32 buffers for F32 and BF16SPLIT alike
     for (int i = 0; i < n; ++i) {
       const tdb_config& c = cfgs[i];
       if (c.order != 3 || c.path == TDB_PATH_PLAIN) {
         b->err = "stream " + std::to_string(i) + ": batches take third-order streams on the fused path";
         return TDB_EUNSUPPORTED;
       }
-      if ((c.data_dtype == TDB_F32) != b->data32 || (c.precision == TDB_PREC_F32) != b->f32) {
+      if ((c.data_dtype == TDB_F32) != b->data32 || c.precision != cfgs[0].precision) {
         b->err = "all streams of a batch share data_dtype and precision";
         return TDB_EINVAL;
       }
@@ -1563,6 +1660,10 @@ tdb_status tdb_batch_create(int32_t n, const tdb_config* cfgs, const void* const
       if (r != TDB_OK) { b->err = "stream " + std::to_string(i) + ": " + g_create_error; return r; }
       b->st.push_back(h);
       h->batch_owned = true;
+      if (h->f32 != b->f32 || h->data32 != b->data32) {
+        b->err = "internal: stream " + std::to_string(i) + " buffer precision differs from the batch";
+        return TDB_EINVAL;
+      }
       r = init_hosvd(h, V0_dev[i], s);
       if (r == TDB_OK) r = b->f32 ? fused_post<float>(h, s) : fused_post<double>(h, s);
       if (r == TDB_OK) r = pull_ctrl(h, s);

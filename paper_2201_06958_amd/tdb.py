@@ -21,7 +21,7 @@ SIGMA_K = 16
 
 OK, EINVAL, ENOMEM, EHIP, ESTATE, ENUMERIC, EUNSUPPORTED = range(7)
 F64, F32 = 0, 1
-PREC_F64, PREC_F32 = 0, 1
+PREC_F64, PREC_F32, PREC_BF16SPLIT = 0, 1, 2
 PATH_AUTO, PATH_PLAIN, PATH_FUSED = 0, 1, 2
 COPY, BORROW = 0, 1
 EVENTS = {0: "", 1: "reinit", 2: "add", 3: "remove", 4: "numeric"}
@@ -174,7 +174,7 @@ class Compressor:
                 cfg.weights[n] = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         cfg.dt = float(dt)
         cfg.data_dtype = F32 if data_dtype == "f32" else F64
-        cfg.precision = PREC_F32 if precision == "f32" else PREC_F64
+        cfg.precision = {"f64": PREC_F64, "f32": PREC_F32, "bf16s": PREC_BF16SPLIT}[precision]
         cfg.path = {"auto": PATH_AUTO, "plain": PATH_PLAIN, "fused": PATH_FUSED}[path]
         cfg.adaptive = 1 if adaptive else 0
         cfg.snapshot_mode = BORROW if snapshot_mode == "borrow" else COPY

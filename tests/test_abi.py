@@ -81,7 +81,8 @@ def _cfg3(tdb):
     return cfg
 
 
-@pytest.mark.parametrize("case,code", [("n0", 1), ("order4", 6), ("plain", 6), ("mixed_dtype", 1), ("dt0", 1)])
+@pytest.mark.parametrize("case,code", [("n0", 1), ("order4", 6), ("plain", 6), ("mixed_dtype", 1), ("dt0", 1),
+                                       ("mixed_precision", 1)])
 def test_batch_create_validates_before_device_work(case, code):
     from paper_2201_06958_amd import tdb
     lib = tdb.load_library()
@@ -99,6 +100,9 @@ def test_batch_create_validates_before_device_work(case, code):
         cfgs[1].data_dtype = 1
     elif case == "dt0":
         cfgs[0].dt = 0.0
+    elif case == "mixed_precision":
+        cfgs[0].precision = 1
+        cfgs[1].precision = 2
     ptrs = (ctypes.c_void_p * 2)(1, 1)   # never dereferenced: validation fails first
     b = ctypes.c_void_p()
     st = lib.tdb_batch_create(n, cfgs, ptrs, None, ctypes.byref(b))

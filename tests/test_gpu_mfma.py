@@ -1,0 +1,147 @@
+"""GPU parity of the matrix-core stage pass in its two flavours: FP32 products
+(bar 1e-6 relative, as every FP32 path) and BF16-split products (bar 1e-4 relative),
+against the FP64 oracle on the same snapshots; the generic stage pass (TDB_MFMA=0)
+on the same cases for comparison. Shapes cover ragged tiles in both tiled modes,
+ranks on both sides of 16, third modes of 3 to 8 entries, full and deficient
+third-mode ranks."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import tdb_oracle as O
+from streams import fourier_ensemble_specs, plume_spec
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+BAR = {"f32": 1e-6, "bf16s": 1e-4}
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2201_06958_amd import load_library
+    load_library()
+
+
+@pytest.fixture
+def pass_kernel(request):
+    old = os.environ.get("TDB_MFMA")
+    os.environ["TDB_MFMA"] = "0" if request.param == "generic" else "1"
+    yield request.param
+    if old is None:
+        os.environ.pop("TDB_MFMA", None)
+    else:
+        os.environ["TDB_MFMA"] = old
+
+
+CASES = [((37, 70, 5), (17, 9, 3)), ((50, 130, 7), (32, 20, 7)), ((21, 65, 8), (8, 32, 4)),
+         ((16, 64, 4), (16, 16, 4)), ((90, 40, 3), (24, 17, 2))]
+
+
+@pytest.mark.parametrize("pass_kernel,precision", [("mfma", "f32"), ("mfma", "bf16s"), ("generic", "f32")],
+                         indirect=["pass_kernel"])
+@pytest.mark.parametrize("dims,ranks", CASES)
+def test_fixed_rank_random_streams(dims, ranks, pass_kernel, precision):
+    """FP32 snapshots around a low-rank base with random weights, fixed ranks, started
+    from the oracle's factors: reconstruction, core and eps against the oracle."""
+    _say(f"case mfma-pass {pass_kernel} {precision} dims {dims} ranks {ranks}")
+    rng = np.random.default_rng(sum(dims) + 7)
+    w = []
+    for n in dims:
+        x = rng.uniform(0.5, 1.5, size=n)
+        w.append(x / x.sum())
+    base = rng.normal(size=dims)
+    snaps = [(base + 0.002 * k * rng.normal(size=dims)).astype(np.float32) for k in range(7)]
+    cfg = O.OracleConfig(dims=dims, weights=w, dt=0.05, rank_max=ranks, rank_init=ranks, adaptive=False, eps_th=1.0)
+    orc = O.OracleTDB(cfg).init(snaps[0].astype(np.float64))
+    from paper_2201_06958_amd import Compressor
+    g = Compressor(dims, 0.05, rank_max=ranks, rank_init=ranks, weights=w, data_dtype="f32", precision=precision,
+                   adaptive=False, path="fused", eps_th=1.0)
+    g.init_from_factors(_dev(snaps[0]), orc.C, orc.U)
+    bar = BAR[precision]
+    for k in range(1, len(snaps)):
+        rec = orc.ingest(snaps[k].astype(np.float64))
+        g.ingest(_dev(snaps[k]))
+        assert abs(g.stats()["eps"] - rec.eps) <= bar * rec.nu, k
+    r, C, U = g.get_core_and_bases()
+    rel = _rel(O.reconstruct(C, U), orc.reconstruct())
+    relc = _rel(C, orc.C)
+    _say(f"  reconstruction rel {rel:.2e}, core rel {relc:.2e}")
+    assert rel < bar and relc < 10 * bar
+    g.close()
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16s"])
+def test_plume_adaptive(precision):
+    """Reactive-flow-shaped stream (8 variables: the third mode is not full rank, so
+    the third-mode terms run too), adaptive ranks, matrix-core pass."""
+    sp = plume_spec(nx=128, ny=64, nv=8, steps=20)
+    _say(f"case mfma plume 128x64x8 {precision}")
+    snaps = [sp.snapshot_np(k) for k in range(sp.steps + 1)]
+    orc = O.OracleTDB(O.OracleConfig(dims=sp.dims, weights=sp.weights, dt=sp.dt, rank_max=(32, 32, 8),
+                                     rank_init=None, adaptive=True, eps_th=sp.eps_th)).init(snaps[0].astype(np.float64))
+    from paper_2201_06958_amd import Compressor
+    g = Compressor(sp.dims, sp.dt, rank_max=(32, 32, 8), weights=sp.weights, data_dtype="f32", precision=precision,
+                   adaptive=True, eps_th=sp.eps_th)
+    g.init(_dev(snaps[0]))
+    bar = BAR[precision]
+    for k in range(1, sp.steps + 1):
+        rec = orc.ingest(snaps[k].astype(np.float64))
+        g.ingest(_dev(snaps[k]))
+        st = g.stats()
+        assert st["event"] == rec.event, k
+        assert abs(st["eps"] - rec.eps) <= bar * rec.nu, k
+    r, C, U = g.get_core_and_bases()
+    rel = _rel(O.reconstruct(C, U), orc.reconstruct())
+    _say(f"  ranks {r}, reconstruction rel {rel:.2e}")
+    assert rel < bar
+    g.close()
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16s"])
+def test_batch_ensemble(precision):
+    """Three ensemble members in one batch on the matrix-core pass."""
+    steps = 6
+    specs = fourier_ensemble_specs(n_streams=3, steps=steps, seed0=2000)
+    _say(f"case mfma batch {[sp.dims for sp in specs]} {precision}")
+    from paper_2201_06958_amd import Batch
+    data = [[sp.snapshot_np(k) for k in range(steps + 1)] for sp in specs]
+    cfgs, orcs = [], []
+    for sp, d in zip(specs, data):
+        cfgs.append(dict(dims=sp.dims, dt=sp.dt, rank_max=sp.rank_max, weights=sp.weights, data_dtype="f32",
+                         precision=precision, adaptive=True, eps_th=sp.eps_th))
+        orcs.append(O.OracleTDB(O.OracleConfig(dims=sp.dims, weights=sp.weights, dt=sp.dt, rank_max=sp.rank_max,
+                                               rank_init=None, adaptive=True, eps_th=sp.eps_th))
+                    .init(d[0].astype(np.float64)))
+    b = Batch(cfgs).init([_dev(d[0]) for d in data])
+    bar = BAR[precision]
+    for k in range(1, steps + 1):
+        b.ingest([_dev(d[k]) for d in data])
+        for i, o in enumerate(orcs):
+            rec = o.ingest(data[i][k].astype(np.float64))
+            st = b.streams[i].stats()
+            assert st["event"] == rec.event, (k, i)
+            assert abs(st["eps"] - rec.eps) <= bar * rec.nu, (k, i)
+    for i, o in enumerate(orcs):
+        r, C, U = b.streams[i].get_core_and_bases()
+        rel = _rel(O.reconstruct(C, U), o.reconstruct())
+        _say(f"  stream {i} {specs[i].dims} ranks {r}: reconstruction rel {rel:.2e}")
+        assert rel < bar
+    b.close()
