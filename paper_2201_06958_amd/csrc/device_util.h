@@ -153,33 +153,47 @@ static __device__ void jacobi_wave(double* A, int rn, int* pairs) {
 // (Sec. 2.5): an add when eps exceeds the trigger, a removal check when the error
 // slope over the window is negative with headroom and some mode's weakest direction
 // fits in the budget, a restart on a numerical event.
-static __device__ void controller_decide(CtrlState* c) {
+// First part of the decision: error and norm, numerical events, additions, the slope
+// window. Returns true when the removal test has to run, which needs the singular
+// values of the core unfoldings (c->sigma).
+static __device__ bool controller_pre(CtrlState* c) {
   c->eps = sqrt(fmax(c->eps2, 0.0));
   c->nu = sqrt(fmax(c->nu2, 0.0));
   c->event = 0;
   c->eps_after = __builtin_nan("");
   c->rank_changed = 0;
-  if (c->numeric & 3) { c->decision = DEC_NUMERIC; return; }
-  if (!c->adaptive) { c->decision = DEC_NONE; return; }
+  if (c->numeric & 3) { c->decision = DEC_NUMERIC; return false; }
+  if (!c->adaptive) { c->decision = DEC_NONE; return false; }
   const double eps = c->eps;
-  if (eps > c->eps_trig) { c->decision = DEC_ADD; return; }
+  if (eps > c->eps_trig) { c->decision = DEC_ADD; return false; }
   const int nw = c->slope_window;
   c->window[c->whead] = eps;
   c->whead = (c->whead + 1) % TDB_WIN;
   c->wcount += 1;
   c->decision = DEC_NONE;
-  if (c->wcount < nw) return;
+  if (c->wcount < nw) return false;
   const double last = c->window[(c->whead - 1 + TDB_WIN) % TDB_WIN];
   const double first = c->window[(c->whead - nw + TDB_WIN) % TDB_WIN];
   const double slope = (last - first) / ((nw - 1) * c->dt);
-  if (!(slope < 0.0)) return;
-  if (eps > 0.5 * c->eps_th) return;
-  const double B = c->gamma_th > 0.0 ? (1.0 - c->gamma_th / 100.0) * c->nu2
-                                     : 0.25 * c->eps_th * c->eps_th;
+  if (!(slope < 0.0)) return false;
+  if (eps > 0.5 * c->eps_th) return false;
+  return true;
+}
+
+// Removal test (after controller_pre returned true): drop a direction if the error
+// stays within budget without it.
+static __device__ void controller_remove(CtrlState* c) {
+  const double eps = c->eps;
+  const double B = c->gamma_th > 0.0 ? (1.0 - c->gamma_th / 100.0) * c->nu2 : 0.25 * c->eps_th * c->eps_th;
   for (int n = 0; n < c->p; ++n) {
     const double s = c->sigma[n][c->ranks[n] - 1];
     if (eps * eps + s * s <= B) { c->decision = DEC_REMOVE; return; }
   }
+}
+
+// The whole decision, with c->sigma already current.
+static __device__ void controller_decide(CtrlState* c) {
+  if (controller_pre(c)) controller_remove(c);
 }
 
 

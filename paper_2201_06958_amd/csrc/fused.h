@@ -46,6 +46,8 @@ struct FFinishArgs {
   const double* Cs;
   const double* kC;          // C_dot of stage 1
   const double* Cdot2;       // C_dot of stage 2
+  double* M[3];              // M_n = dt C_dot_(n) P_n (r_n x r_n), written by k_fmprep
+  int m_inline;              // 1: each row block forms M_n itself (no k_fmprep launch)
 };
 
 struct FQrArgs {
@@ -59,6 +61,7 @@ struct FQrArgs {
   double* C0;
   double* Ctmp;
   unsigned* counter;
+  double* T3;                // C x_3 U_3 (r1 x r2 x N3) of the folded core, for the error pass
 };
 
 struct FPostArgs {
@@ -72,6 +75,9 @@ struct FPostArgs {
   void* P[3];
   void* E;                   // r1 x N2 x N3, compute type
   void* U1c;                 // N1 x r1, compute type
+  const double* T3;          // C x_3 U_3 when already formed (else NULL: formed per block)
+  int want_sigma;            // also form the singular values of the core unfoldings
+  double* G[3];              // core Grams C_(n) C_(n)^T kept for a later singular-value test
 };
 
 struct FErrArgs {
@@ -84,6 +90,8 @@ struct FErrArgs {
   const double* w23;
   double* part;
   unsigned* counter;
+  const double* G[3];        // core Grams of the committed state (lazy singular values)
+  int rmax;                  // largest rank (LDS of the final kernel)
 };
 
 // ev0/ev1 (may be null): events stamped by the dispatch itself at kernel start and end.
@@ -113,12 +121,16 @@ template <typename T>
 hipError_t launch_freduce(const FReduceArgs& a, CtrlState* c, hipStream_t s);
 template <typename T>
 hipError_t launch_ffinish(const FFinishArgs& a, size_t lds, CtrlState* c, hipStream_t s);
+template <typename T>
+hipError_t launch_fmprep(const FFinishArgs& a, size_t lds, CtrlState* c, hipStream_t s);
 hipError_t launch_fqr(const FQrArgs& a, size_t lds, CtrlState* c, hipStream_t s);
 template <typename T>
 hipError_t launch_fpost(const FPostArgs& a, size_t lds, CtrlState* c, hipStream_t s);
 template <typename TD, typename T>
 hipError_t launch_ferr(const FErrArgs& a, CtrlState* c, hipStream_t s, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr);
+// LDS of the final error kernel (singular values of three r x r Grams when needed).
+inline size_t ferr_final_lds(int rmax) { return (size_t)3 * ((size_t)rmax * rmax + 5 * (size_t)rmax) * 8 + 64; }
 
 // ---------------------------------------------------------------- matrix-core pass
 // Stage-pass flavours on the matrix cores (tile 16 x 64 x N3, N3 <= 8, r1, r2 <= 32).
@@ -161,6 +173,9 @@ hipError_t launch_batch_freduce(const FReduceArgs* tab, CtrlState* const* ctab, 
 template <typename T>
 hipError_t launch_batch_ffinish(const FFinishArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, int stage,
                                 size_t lds, hipStream_t s);
+template <typename T>
+hipError_t launch_batch_fmprep(const FFinishArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, int stage,
+                               size_t lds, hipStream_t s);
 hipError_t launch_batch_fqr(const FQrArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, size_t lds,
                             hipStream_t s);
 template <typename T>
@@ -168,7 +183,7 @@ hipError_t launch_batch_fpost(const FPostArgs* tab, CtrlState* const* ctab, Batc
                               hipStream_t s);
 template <typename TD, typename T>
 hipError_t launch_batch_ferr(const FErrArgs* tab, const void* const* v1, BatchMap m, int blocks, int nstreams,
-                             CtrlState* const* ctab, BatchSummary* out, hipStream_t s, hipEvent_t ev0 = nullptr,
-                             hipEvent_t ev1 = nullptr);
+                             CtrlState* const* ctab, BatchSummary* out, size_t lds_final, hipStream_t s,
+                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 }  // namespace tdb

@@ -260,6 +260,48 @@ __device__ void write_p(const double* Cl, const double* Gi, int rn, long long R,
   __syncthreads();
 }
 
+// ---------------------------------------------------------------- M_n of a stage
+// Block n: M_n = U_n^T W_n F_(n) P_n = C_dot_(n) P_n, scaled by dt like the raw H_n
+// (one r_n x r_n matrix per mode, shared by every row of the finish).
+template <typename T>
+__device__ __forceinline__ void fmprep_body(const FFinishArgs& a, CtrlState* ctrl, int bx) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* lds = reinterpret_cast<double*>(smem_raw);
+  if (a.stage == 2 && ctrl->numeric) return;
+  const int n = bx;
+  const int rr = a.r[n];
+  if (rr >= a.N[n]) return;
+  const double* cd = a.stage == 1 ? a.kC : a.Cdot2;   // this stage's C_dot
+  const int csz = a.r[0] * a.r[1] * a.r[2];
+  const int Rn = csz / rr;
+  double* cdl = lds;
+  T* pl = reinterpret_cast<T*>(cdl + csz);
+  const T* Pn = static_cast<const T*>(a.Pcur[n]);
+  for (int t = threadIdx.x; t < csz; t += blockDim.x) cdl[t] = cd[t];
+  for (int t = threadIdx.x; t < Rn * rr; t += blockDim.x) pl[t] = Pn[t];
+  __syncthreads();
+  int inner = 1, outer = 1;
+  for (int k = 0; k < 3; ++k) {
+    if (k < n) outer *= a.r[k];
+    if (k > n) inner *= a.r[k];
+  }
+  for (int t = threadIdx.x; t < rr * rr; t += blockDim.x) {
+    const int i = t / rr, j = t - (t / rr) * rr;
+    double s = 0.0;
+    for (int o = 0; o < outer; ++o) {
+      const double* crow = cdl + (o * rr + i) * inner;
+      const T* prow = pl + (o * inner) * rr + j;
+      for (int in = 0; in < inner; ++in) s += crow[in] * (double)prow[in * rr];
+    }
+    a.M[n][t] = s * a.dt;   // H is the raw (undivided) projection, so M is too
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fmprep(FFinishArgs a, CtrlState* ctrl) {
+  fmprep_body<T>(a, ctrl, blockIdx.x);
+}
+
 // ---------------------------------------------------------------- finish a stage
 // Blocks [0, rowblocks): rows of every mode: U_dot = (H - U M)/dt, Heun update and,
 // in stage 1, the weighted basis B_n = W_n U* of the next stage.
@@ -272,33 +314,28 @@ __device__ __forceinline__ void ffinish_body(const FFinishArgs& a, CtrlState* ct
   if (a.stage == 2 && ctrl->numeric) return;
   const double inv_dt = 1.0 / a.dt;
   if ((int)bx < a.rowblocks) {
-    // M_n = U_n^T W_n F_(n) P_n = Cdot_(n) P_n (the same r x r matrix every block needs):
-    // stage C_dot and P_n in LDS, then contract with nested (outer, inner) loops
+    // M_n (r_n x r_n) into LDS: formed once per stage by k_fmprep, or here (a single
+    // stream, where the extra launch would cost more than the repeated small product)
     double* Ml[3];
-    {
+    if (a.m_inline) {
       const double* cd = a.stage == 1 ? a.kC : a.Cdot2;   // this stage's C_dot
       const int csz = a.r[0] * a.r[1] * a.r[2];
       double* cdl = lds;
       T* pl = reinterpret_cast<T*>(cdl + csz);
       for (int t = threadIdx.x; t < csz; t += blockDim.x) cdl[t] = cd[t];
-      int poff[3], moff = 0;
-      {
-        int off = 0;
-        for (int n = 0; n < 3; ++n) {
-          poff[n] = off;
-          if (a.r[n] < a.N[n]) {
-            const int Rn = csz / a.r[n];
-            const T* Pn = static_cast<const T*>(a.Pcur[n]);
-            for (int t = threadIdx.x; t < Rn * a.r[n]; t += blockDim.x) pl[off + t] = Pn[t];
-            off += Rn * a.r[n];
-          }
+      int poff[3], off = 0;
+      for (int n = 0; n < 3; ++n) {
+        poff[n] = off;
+        if (a.r[n] < a.N[n]) {
+          const T* Pn = static_cast<const T*>(a.Pcur[n]);
+          for (int t = threadIdx.x; t < csz; t += blockDim.x) pl[off + t] = Pn[t];
+          off += csz;
         }
-        moff = (int)((csz * 8 + off * (int)sizeof(T) + 7) / 8);
       }
       __syncthreads();
-      int off = moff;
+      int moff = (int)((csz * 8 + off * (int)sizeof(T) + 7) / 8);
       for (int n = 0; n < 3; ++n) {
-        Ml[n] = lds + off;
+        Ml[n] = lds + moff;
         const int rr = a.r[n];
         if (rr < a.N[n]) {
           int inner = 1, outer = 1;
@@ -318,6 +355,15 @@ __device__ __forceinline__ void ffinish_body(const FFinishArgs& a, CtrlState* ct
             Ml[n][t] = s * a.dt;   // H is the raw (undivided) projection, so M is too
           }
         }
+        moff += rr * rr;
+      }
+    } else {
+      int off = 0;
+      for (int n = 0; n < 3; ++n) {
+        Ml[n] = lds + off;
+        const int rr = a.r[n];
+        if (rr < a.N[n])
+          for (int t = threadIdx.x; t < rr * rr; t += blockDim.x) Ml[n][t] = a.M[n][t];
         off += rr * rr;
       }
     }
@@ -565,6 +611,17 @@ __device__ __forceinline__ void fqr_body(const FQrArgs& a, CtrlState* ctrl, int 
     double* tswap = ca; ca = cb; cb = tswap;
   }
   for (int t = threadIdx.x; t < csz; t += blockDim.x) a.C0[t] = ca[t];
+  // T3 = C x_3 U_3 of the folded core, for the error-pass expansion
+  if (a.T3) {
+    const int r12 = a.r[0] * a.r[1], r3 = a.r[2], N3 = (int)a.N[2], ld3 = a.ldU[2];
+    for (int t = threadIdx.x; t < r12 * N3; t += blockDim.x) {
+      const int ab = t / N3, i3 = t - (t / N3) * N3;
+      double s = 0.0;
+      for (int c = 0; c < r3; ++c)
+        s += ca[ab * r3 + c] * __hip_atomic_load(&a.U0[2][i3 * ld3 + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      a.T3[t] = s;
+    }
+  }
 }
 
 __global__ void __launch_bounds__(256) k_fqr(FQrArgs a, CtrlState* ctrl) {
@@ -592,13 +649,17 @@ __device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, 
     const long long per = (N2 + a.eblocks - 1) / a.eblocks;
     const long long i2a = (long long)eb * per, i2b = min(N2, i2a + per);
     if (i2a < i2b) {
-      for (long long t = threadIdx.x; t < (long long)r1 * r2 * N3; t += blockDim.x) {
-        const long long i3 = t % N3, ab = t / N3;
-        const double* cr = a.C + ab * r3;
-        const double* u3 = a.U[2] + i3 * a.ldU[2];
-        double s = 0.0;
-        for (int c = 0; c < r3; ++c) s += cr[c] * u3[c];
-        T3[t] = s;
+      if (a.T3) {
+        for (long long t = threadIdx.x; t < (long long)r1 * r2 * N3; t += blockDim.x) T3[t] = a.T3[t];
+      } else {
+        for (long long t = threadIdx.x; t < (long long)r1 * r2 * N3; t += blockDim.x) {
+          const long long i3 = t % N3, ab = t / N3;
+          const double* cr = a.C + ab * r3;
+          const double* u3 = a.U[2] + i3 * a.ldU[2];
+          double s = 0.0;
+          for (int c = 0; c < r3; ++c) s += cr[c] * u3[c];
+          T3[t] = s;
+        }
       }
       for (long long t = threadIdx.x; t < (i2b - i2a) * r2; t += blockDim.x) {
         const long long i = t / r2;
@@ -662,12 +723,16 @@ __device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, 
   gram_from(Csrc, rn, R, inner, G);
   const bool need_p = rn < a.N[n] && a.want_pinv;
   if (threadIdx.x < 64) {
-    // singular values of C_(n): eigenvalues of a copy of the Gram matrix
-    for (int t = threadIdx.x; t < rn * rn; t += 64) Gi[t] = G[t];
-    wave_fence();
-    wave_eigvals(Gi, rn, lam, ws);
-    for (int i = threadIdx.x; i < TDB_RCAP; i += 64)
-      ctrl->sigma[n][i] = i < rn ? sqrt(fmax(lam[i], 0.0)) : 0.0;
+    if (a.G[n])
+      for (int t = threadIdx.x; t < rn * rn; t += 64) a.G[n][t] = G[t];
+    if (a.want_sigma) {
+      // singular values of C_(n): eigenvalues of a copy of the Gram matrix
+      for (int t = threadIdx.x; t < rn * rn; t += 64) Gi[t] = G[t];
+      wave_fence();
+      wave_eigvals(Gi, rn, lam, ws);
+      for (int i = threadIdx.x; i < TDB_RCAP; i += 64)
+        ctrl->sigma[n][i] = i < rn ? sqrt(fmax(lam[i], 0.0)) : 0.0;
+    }
     bool ok = true;
     if (need_p) {
       ok = wave_chol(G, rn);
@@ -743,21 +808,49 @@ __global__ void __launch_bounds__(256) k_ferr(FErrArgs a, CtrlState* ctrl) {
   ferr_body<TD, T>(a, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
+// Controller of the fused path: the decision up to the removal test; only when that
+// test has to run are the singular values of the core unfoldings formed, one wave per
+// mode, from the Grams kept by the post-step kernel.
+__device__ __forceinline__ void fused_decide(CtrlState* ctrl, const double* const* G, int rmax) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* lds = reinterpret_cast<double*>(smem_raw);
+  __shared__ int need;
+  if (threadIdx.x == 0) need = controller_pre(ctrl) ? 1 : 0;
+  __syncthreads();
+  if (!need) return;
+  const int w = threadIdx.x >> 6;
+  if (w < 3 && G[w]) {
+    const int rn = ctrl->ranks[w];
+    double* A = lds + w * (rmax * rmax + 5 * rmax);
+    double* lam = A + rmax * rmax;
+    double* ws = lam + rmax;
+    for (int t = threadIdx.x & 63; t < rn * rn; t += 64) A[t] = G[w][t];
+    wave_fence();
+    wave_eigvals(A, rn, lam, ws);
+    for (int i = threadIdx.x & 63; i < TDB_RCAP; i += 64)
+      ctrl->sigma[w][i] = i < rn ? sqrt(fmax(lam[i], 0.0)) : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) controller_remove(ctrl);
+}
+
 // One block: fixed-order sum of the error-pass partials, then the controller.
-__global__ void __launch_bounds__(256) k_ferr_final(const double* __restrict__ part, int nb, CtrlState* ctrl) {
+__global__ void __launch_bounds__(256) k_ferr_final(FErrArgs a, CtrlState* ctrl) {
   __shared__ double red[16];
+  const int nb = a.gx * a.gy;
   double s0 = 0.0, s1 = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-    s0 += part[2 * i];
-    s1 += part[2 * i + 1];
+    s0 += a.part[2 * i];
+    s1 += a.part[2 * i + 1];
   }
   s0 = block_sum(s0, red);
   s1 = block_sum(s1, red);
   if (threadIdx.x == 0) {
     ctrl->eps2 = s0;
     ctrl->nu2 = s1;
-    controller_decide(ctrl);
   }
+  __syncthreads();
+  fused_decide(ctrl, a.G, a.rmax);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -785,6 +878,16 @@ hipError_t launch_ffinish(const FFinishArgs& a, size_t lds, CtrlState* c, hipStr
 template hipError_t launch_ffinish<float>(const FFinishArgs&, size_t, CtrlState*, hipStream_t);
 template hipError_t launch_ffinish<double>(const FFinishArgs&, size_t, CtrlState*, hipStream_t);
 
+template <typename T>
+hipError_t launch_fmprep(const FFinishArgs& a, size_t lds, CtrlState* c, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_fmprep<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fmprep<T>, dim3(3), dim3(256), lds, s, a, c);
+  return hipGetLastError();
+}
+template hipError_t launch_fmprep<float>(const FFinishArgs&, size_t, CtrlState*, hipStream_t);
+template hipError_t launch_fmprep<double>(const FFinishArgs&, size_t, CtrlState*, hipStream_t);
+
 hipError_t launch_fqr(const FQrArgs& a, size_t lds, CtrlState* c, hipStream_t s) {
   hipError_t e = hipFuncSetAttribute((const void*)k_fqr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -808,7 +911,10 @@ hipError_t launch_ferr(const FErrArgs& a, CtrlState* c, hipStream_t s, hipEvent_
   hipExtLaunchKernelGGL((k_ferr<TD, T>), dim3(a.gx, a.gy), dim3(256), 0u, s, ev0, ev1, 0u, a, c);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_ferr_final, dim3(1), dim3(256), 0, s, a.part, a.gx * a.gy, c);
+  const size_t fl = ferr_final_lds(a.rmax);
+  e = hipFuncSetAttribute((const void*)k_ferr_final, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fl);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ferr_final, dim3(1), dim3(256), fl, s, a, c);
   return hipGetLastError();
 }
 template hipError_t launch_ferr<float, float>(const FErrArgs&, CtrlState*, hipStream_t, hipEvent_t, hipEvent_t);
@@ -834,6 +940,15 @@ __global__ void __launch_bounds__(256) kb_ffinish(const FFinishArgs* __restrict_
   FFinishArgs a = tab[s];
   a.stage = stage;
   ffinish_body<T>(a, ctab[s], blockIdx.x - m.start[s]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) kb_fmprep(const FFinishArgs* __restrict__ tab, CtrlState* const* ctab,
+                                                 BatchMap m, int stage) {
+  const int s = m.sid[blockIdx.x];
+  FFinishArgs a = tab[s];
+  a.stage = stage;
+  fmprep_body<T>(a, ctab[s], blockIdx.x - m.start[s]);
 }
 
 __global__ void __launch_bounds__(256) kb_fqr(const FQrArgs* __restrict__ tab, CtrlState* const* ctab, BatchMap m) {
@@ -877,7 +992,10 @@ __global__ void __launch_bounds__(256) kb_ferr_final(const FErrArgs* __restrict_
   if (threadIdx.x == 0) {
     ctrl->eps2 = s0;
     ctrl->nu2 = s1;
-    controller_decide(ctrl);
+  }
+  __syncthreads();
+  fused_decide(ctrl, tab[s].G, tab[s].rmax);
+  if (threadIdx.x == 0) {
     BatchSummary q;
     q.decision = ctrl->decision;
     q.event = ctrl->event;
@@ -916,6 +1034,20 @@ template hipError_t launch_batch_ffinish<float>(const FFinishArgs*, CtrlState* c
 template hipError_t launch_batch_ffinish<double>(const FFinishArgs*, CtrlState* const*, BatchMap, int, int, size_t,
                                                  hipStream_t);
 
+template <typename T>
+hipError_t launch_batch_fmprep(const FFinishArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, int stage,
+                               size_t lds, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute((const void*)kb_fmprep<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kb_fmprep<T>, dim3(blocks), dim3(256), lds, s, tab, ctab, m, stage);
+  return hipGetLastError();
+}
+template hipError_t launch_batch_fmprep<float>(const FFinishArgs*, CtrlState* const*, BatchMap, int, int, size_t,
+                                               hipStream_t);
+template hipError_t launch_batch_fmprep<double>(const FFinishArgs*, CtrlState* const*, BatchMap, int, int, size_t,
+                                                hipStream_t);
+
 hipError_t launch_batch_fqr(const FQrArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, size_t lds,
                             hipStream_t s) {
   hipError_t e = hipFuncSetAttribute((const void*)kb_fqr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -937,21 +1069,23 @@ template hipError_t launch_batch_fpost<double>(const FPostArgs*, CtrlState* cons
 
 template <typename TD, typename T>
 hipError_t launch_batch_ferr(const FErrArgs* tab, const void* const* v1, BatchMap m, int blocks, int nstreams,
-                             CtrlState* const* ctab, BatchSummary* out, hipStream_t s, hipEvent_t ev0,
-                             hipEvent_t ev1) {
+                             CtrlState* const* ctab, BatchSummary* out, size_t lds_final, hipStream_t s,
+                             hipEvent_t ev0, hipEvent_t ev1) {
   hipExtLaunchKernelGGL((kb_ferr<TD, T>), dim3(blocks), dim3(256), 0u, s, ev0, ev1, 0u, tab, v1, m);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kb_ferr_final, dim3(nstreams), dim3(256), 0, s, tab, ctab, out);
+  e = hipFuncSetAttribute((const void*)kb_ferr_final, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_final);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kb_ferr_final, dim3(nstreams), dim3(256), lds_final, s, tab, ctab, out);
   return hipGetLastError();
 }
 template hipError_t launch_batch_ferr<float, float>(const FErrArgs*, const void* const*, BatchMap, int, int, CtrlState* const*,
-                                                   BatchSummary*, hipStream_t, hipEvent_t, hipEvent_t);
+                                                   BatchSummary*, size_t, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_batch_ferr<float, double>(const FErrArgs*, const void* const*, BatchMap, int, int, CtrlState* const*,
-                                                   BatchSummary*, hipStream_t, hipEvent_t, hipEvent_t);
+                                                   BatchSummary*, size_t, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_batch_ferr<double, double>(const FErrArgs*, const void* const*, BatchMap, int, int, CtrlState* const*,
-                                                   BatchSummary*, hipStream_t, hipEvent_t, hipEvent_t);
+                                                   BatchSummary*, size_t, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_batch_ferr<double, float>(const FErrArgs*, const void* const*, BatchMap, int, int, CtrlState* const*,
-                                                   BatchSummary*, hipStream_t, hipEvent_t, hipEvent_t);
+                                                   BatchSummary*, size_t, hipStream_t, hipEvent_t, hipEvent_t);
 
 }  // namespace tdb

@@ -76,6 +76,9 @@ struct tdb_ctx {
   void* fpart = nullptr;
   long long fpart_elems = 0;
   double *Rq[TDB_P] = {}, *Cdot2 = nullptr;
+  double *Mbuf[TDB_P] = {}, *T3buf = nullptr;   // M_n of a stage; C x_3 U_3 after the QR
+  double* Gsave[TDB_P] = {};     // core Grams of the committed state (lazy singular values)
+  bool sigma_every_step = false; // form the core singular values at every step
   void* P2[TDB_P] = {};          // pseudo-inverses of the stage-2 core
   void *E = nullptr, *U1c = nullptr;
   double *w23 = nullptr, *ferr_part = nullptr;
@@ -454,6 +457,9 @@ tdb_status setup_fused(tdb_ctx* h, const std::vector<std::vector<double>>& wh) {
     TRY(dalloc(h, &h->P2[n], (size_t)h->Rmax * h->caps[n] * h->celt));
   }
   TRY(dallocT(h, &h->Cdot2, h->core_cap));
+  for (int n = 0; n < 3; ++n) TRY(dallocT(h, &h->Mbuf[n], (size_t)TDB_RCAP * TDB_RCAP));
+  for (int n = 0; n < 3; ++n) TRY(dallocT(h, &h->Gsave[n], (size_t)TDB_RCAP * TDB_RCAP));
+  TRY(dallocT(h, &h->T3buf, (size_t)h->caps[0] * h->caps[1] * h->N[2]));
   TRY(dalloc(h, &h->E, (size_t)h->caps[0] * h->N[1] * h->N[2] * h->celt));
   TRY(dalloc(h, &h->U1c, (size_t)h->N[0] * h->caps[0] * h->celt));
   std::vector<double> w23((size_t)(h->N[1] * h->N[2]));
@@ -828,6 +834,8 @@ tdb_status ingest_impl(tdb_ctx* h, const TD* V1, hipStream_t s) {
     TRY(pull_ctrl(h, s));
   }
   TRY(keep_previous<TD>(h, V1, s));
+  // the step formed the core singular values only if asked to or on a reinit
+  h->sigma_stale = !(h->sigma_every_step || dec != DEC_NONE);
   fill_stats(h, false);
   return TDB_OK;
 }
@@ -839,15 +847,13 @@ int max_rank_of(const int* r, int p) {
 }
 
 // LDS of the small per-mode kernels (finish, post) when sized for ranks rl.
-size_t small_lds(const tdb_ctx* h, const int* rl, bool* core_in_lds) {
+size_t small_lds(const tdb_ctx* h, const int* rl, bool* core_in_lds, bool m_inline = false) {
   const long long csz = prod_ll(rl, h->p);
   const int rm = max_rank_of(rl, h->p);
   long long msum = 0;
   for (int n = 0; n < h->p; ++n) msum += (long long)rl[n] * rl[n];
-  // finish rows stage C_dot, the three P_n and the three M_n
-  long long pel = 0;
-  for (int n = 0; n < h->p; ++n) pel += (csz / rl[n]) * rl[n];
-  const size_t rows = (size_t)csz * 8 + (size_t)pel * h->celt + 8 + (size_t)msum * 8;
+  // finish rows stage the three M_n (and, forming them inline, C_dot and the three P_n)
+  const size_t rows = (size_t)msum * 8 + (m_inline ? (size_t)csz * 8 + 3 * (size_t)csz * h->celt + 8 : 0);
   const size_t base = std::max<size_t>((3 * (size_t)rm * rm + 5 * (size_t)rm + 64) * 8, rows);
   *core_in_lds = base + (size_t)csz * 8 <= (size_t)h->lds_max;
   return base + (*core_in_lds ? (size_t)csz * 8 : 0);
@@ -864,7 +870,7 @@ struct StepArgs {
   FQrArgs qa;
   FPostArgs pa;
   FErrArgs ea;
-  size_t lds_fin = 0, lds_qr = 0, lds_post = 0;
+  size_t lds_fin = 0, lds_qr = 0, lds_post = 0, lds_mprep = 0;
   int blocks_pass = 1, blocks_red = 1, blocks_fin[2] = {1, 1}, blocks_qr = 3, blocks_post = 1, blocks_err = 1;
 };
 
@@ -884,6 +890,9 @@ tdb_status build_post_args(tdb_ctx* h, const int* rl, FPostArgs& pa, size_t& lds
   pa.C = h->C0;
   pa.E = h->E;
   pa.U1c = h->U1c;
+  pa.T3 = nullptr;
+  pa.want_sigma = 1;
+  for (int n = 0; n < 3; ++n) pa.G[n] = h->Gsave[n];
   for (int n = 0; n < 3; ++n) {
     pa.N[n] = h->N[n];
     pa.r[n] = h->r[n];
@@ -946,7 +955,8 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
 
   FFinishArgs ga{};
   bool cil = false;
-  A.lds_fin = small_lds(h, rl, &cil);
+  ga.m_inline = rl == h->r ? 1 : 0;   // a single stream forms M_n in the row blocks
+  A.lds_fin = small_lds(h, rl, &cil, ga.m_inline != 0);
   ga.core_in_lds = cil ? 1 : 0;
   ga.rmax = max_rank_of(rl, 3);
   ga.dt = h->cfg.dt;
@@ -967,6 +977,14 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
     ga.kU[n] = h->kU[n];
     ga.B[n] = h->B[n];
     ga.P[n] = h->P2[n];
+    ga.M[n] = h->Mbuf[n];
+  }
+  {
+    // M_n prep: the stage's C_dot and one P_n in LDS
+    const long long csz = prod_ll(rl, 3);
+    long long pmax = 0;
+    for (int n = 0; n < 3; ++n) pmax = std::max(pmax, csz);
+    A.lds_mprep = (size_t)csz * 8 + (size_t)pmax * h->celt + 16;
   }
   for (int st = 0; st < 2; ++st) {
     A.ga[st] = ga;
@@ -982,9 +1000,11 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
   const size_t npq = (size_t)qa.rmax * (qa.rmax + 1) / 2;
   const size_t qlds = (4 * (size_t)qa.rmax * qa.rmax + 4 * npq + TDB_NEIG) * 8;
   size_t ustage = 0;
+  // a batch keeps several QR blocks per compute unit rather than staging U_n
+  const size_t qbudget = rl != h->r ? std::min<size_t>((size_t)h->lds_max, 48 * 1024) : (size_t)h->lds_max;
   for (int n = 0; n < 3; ++n) {
     const size_t need = (size_t)h->N[n] * rl[n] * 8;
-    qa.u_in_lds[n] = qlds + need <= (size_t)h->lds_max ? 1 : 0;
+    qa.u_in_lds[n] = qlds + need <= qbudget ? 1 : 0;
     if (qa.u_in_lds[n]) ustage = std::max(ustage, need);
     qa.N[n] = h->N[n];
     qa.r[n] = h->r[n];
@@ -999,9 +1019,12 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
   qa.C0 = h->C0;
   qa.Ctmp = h->Ctmp;
   qa.counter = h->counters;
+  qa.T3 = h->T3buf;
   A.lds_qr = qlds + ustage;
 
   TRY(build_post_args(h, rl, A.pa, A.lds_post));
+  A.pa.T3 = h->T3buf;   // formed by the QR of this step
+  A.pa.want_sigma = h->sigma_every_step ? 1 : 0;
   A.blocks_post = 3 + A.pa.eblocks;
 
   FErrArgs& ea = A.ea;
@@ -1019,6 +1042,8 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
   ea.w23 = h->w23;
   ea.part = h->ferr_part;
   ea.counter = h->counters + 1;
+  for (int n = 0; n < 3; ++n) ea.G[n] = h->Gsave[n];
+  ea.rmax = max_rank_of(rl, 3);
   A.blocks_err = h->ferr_gx * h->ferr_gy;
   return TDB_OK;
 }
@@ -1049,6 +1074,8 @@ tdb_status finish_step(tdb_ctx* h, const TD* V1, hipStream_t s) {
     TRY(pull_ctrl(h, s));
   }
   TRY(keep_previous<TD>(h, V1, s));
+  // the step formed the core singular values only if asked to or on a reinit
+  h->sigma_stale = !(h->sigma_every_step || dec != DEC_NONE);
   fill_stats(h, false);
   return TDB_OK;
 }
@@ -1075,6 +1102,7 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
     }
     A.ra.stage = stage;
     HIPCHK(launch_freduce<T>(A.ra, h->ctrl, s));
+    if (!A.ga[stage - 1].m_inline) HIPCHK(launch_fmprep<T>(A.ga[stage - 1], A.lds_mprep, h->ctrl, s));
     HIPCHK(launch_ffinish<T>(A.ga[stage - 1], A.lds_fin, h->ctrl, s));
   }
   HIPCHK(launch_fqr(A.qa, A.lds_qr, h->ctrl, s));
@@ -1157,7 +1185,7 @@ struct tdb_batch_ctx {
   // block maps (fixed at creation: grids are sized at the caps)
   BatchMap m_pass{}, m_red{}, m_fin[2]{}, m_qr{}, m_post{}, m_err{};
   int g_pass = 0, g_red = 0, g_fin[2] = {0, 0}, g_qr = 0, g_post = 0, g_err = 0;
-  size_t lds_pass = 0, lds_fin = 0, lds_qr = 0, lds_post = 0;
+  size_t lds_pass = 0, lds_fin = 0, lds_qr = 0, lds_post = 0, lds_mprep = 0, lds_final = 0;
   int mflavor = 0;                  // MPASS_* of the batched stage pass (one for all streams)
   double bytes_pass = 0.0, bytes_err = 0.0;
   bool dirty = true;
@@ -1303,6 +1331,8 @@ tdb_status batch_setup(tdb_batch_ctx* b) {
     b->lds_fin = std::max(b->lds_fin, A.lds_fin);
     b->lds_qr = std::max(b->lds_qr, A.lds_qr);
     b->lds_post = std::max(b->lds_post, A.lds_post);
+    b->lds_mprep = std::max(b->lds_mprep, A.lds_mprep);
+    b->lds_final = std::max(b->lds_final, ferr_final_lds(A.ea.rmax));
     b->bytes_pass += 2.0 * (double)h->S * (double)h->delt;
     b->bytes_err += (double)h->S * (double)h->delt;
   }
@@ -1357,6 +1387,7 @@ tdb_status batch_step(tdb_batch_ctx* b, const void* const* V, hipStream_t s) {
       BHIPCHK((launch_batch_fpass<TD, T>(b->d_fa[st], b->d_v1, b->d_v0, b->m_pass, b->g_pass, b->lds_pass, s, e0,
                                          e1)));
     BHIPCHK(launch_batch_freduce<T>(b->d_ra, b->d_ctab, b->m_red, b->g_red, st + 1, s));
+    BHIPCHK(launch_batch_fmprep<T>(b->d_ga[st], b->d_ctab, b->m_qr, b->g_qr, st + 1, b->lds_mprep, s));
     BHIPCHK(launch_batch_ffinish<T>(b->d_ga[st], b->d_ctab, b->m_fin[st], b->g_fin[st], st + 1, b->lds_fin, s));
   }
   BHIPCHK(launch_batch_fqr(b->d_qa, b->d_ctab, b->m_qr, b->g_qr, b->lds_qr, s));
@@ -1369,7 +1400,8 @@ tdb_status batch_step(tdb_batch_ctx* b, const void* const* V, hipStream_t s) {
       if (e0 && e1) b->ev_used[TDB_PASS_ERROR].push_back({e0, e1});
       else e0 = e1 = nullptr;
     }
-    BHIPCHK((launch_batch_ferr<TD, T>(b->d_ea, b->d_v1, b->m_err, b->g_err, n, b->d_ctab, b->d_sum, s, e0, e1)));
+    BHIPCHK((launch_batch_ferr<TD, T>(b->d_ea, b->d_v1, b->m_err, b->g_err, n, b->d_ctab, b->d_sum, b->lds_final, s,
+                                      e0, e1)));
   }
   BHIPCHK(hipMemcpyAsync(b->h_sum, b->d_sum, n * sizeof(BatchSummary), hipMemcpyDeviceToHost, s));
   BHIPCHK(hipStreamSynchronize(s));
@@ -1386,12 +1418,10 @@ tdb_status batch_step(tdb_batch_ctx* b, const void* const* V, hipStream_t s) {
     c.eps2 = q.eps2;
     c.nu2 = q.nu2;
     c.eps_after = NAN;   // as the controller leaves it on a step without an event
-    h->sigma_stale = true;
     h->post_valid = true;
     const int r0[3] = {h->r[0], h->r[1], h->r[2]};
     tdb_status r = finish_step<TD, T>(h, static_cast<const TD*>(V[i]), s);
     if (r != TDB_OK) { b->err = "stream " + std::to_string(i) + ": " + h->err; return r; }
-    if (q.decision != DEC_NONE) h->sigma_stale = false;   // pulled in full by the reinit
     if (h->r[0] != r0[0] || h->r[1] != r0[1] || h->r[2] != r0[2]) b->dirty = true;
     h->fused_steps += 1;
   }
@@ -1579,7 +1609,10 @@ tdb_status tdb_get_stats(tdb_handle h, tdb_stats* out) {
   if (!out) { h->err = "out is NULL"; return TDB_EINVAL; }
   if (!h->ready) { h->err = "handle is not initialised"; return TDB_ESTATE; }
   if (h->sigma_stale) {
-    // a batched step returns only a summary; the singular values are read on demand
+    // fused steps form the core singular values only when the controller needs them;
+    // the statistics form them on demand from the committed core
+    HIPCHK(hipDeviceSynchronize());
+    TRY(core_sigma(h, false, nullptr));
     HIPCHK(hipDeviceSynchronize());
     HIPCHK(hipMemcpy(h->ctrl_h->sigma, h->ctrl->sigma, sizeof(h->ctrl_h->sigma), hipMemcpyDeviceToHost));
     for (int n = 0; n < 4; ++n)
