@@ -11,6 +11,11 @@ the controller (with any HOSVD reinitialisation it triggers).
 All snapshots of the run are generated on the device before timing (a ring far
 larger than the 256 MB last-level cache), so every stage pass streams its snapshot
 pair from HBM at least once. Prints one JSON line.
+
+Besides the headline line, the same JSON carries: the same stream with the stage
+pass in BF16-split products ("bf16_split"); the batched ensemble of independent
+Fourier-mode streams of uneven grids ("ensemble", 256 streams by default, one batch
+step = one snapshot of every stream); the plain FP64 GPU path; and the CPU oracle.
 """
 from __future__ import annotations
 
@@ -75,6 +80,44 @@ def _run_gpu(sp, snaps, warmup, steps, precision, path, profile=True):
     return t1 - t0, st, prof
 
 
+def _run_ensemble(n, warmup, steps, precision="f32"):
+    """The batched ensemble: n Fourier-mode streams of grids from {128,192,256}^2 x 4,
+    caps 24, threshold 1e-5, one batch step per snapshot of every stream."""
+    import torch
+    from streams import fourier_ensemble_specs
+    from paper_2201_06958_amd import Batch
+    specs = fourier_ensemble_specs(n_streams=n, steps=warmup + steps + 1)
+    snaps = [[sp.snapshot(k, device="cuda") for sp in specs] for k in range(warmup + steps + 1)]
+    torch.cuda.synchronize()
+    elems = sum(sp.dims[0] * sp.dims[1] * sp.dims[2] for sp in specs)
+    cfgs = [dict(dims=sp.dims, dt=sp.dt, rank_max=sp.rank_max, weights=sp.weights, data_dtype="f32",
+                 precision=precision, adaptive=True, eps_th=sp.eps_th, snapshot_mode="borrow") for sp in specs]
+    b = Batch(cfgs).init(snaps[0])
+    for k in range(1, warmup + 1):
+        b.ingest(snaps[k])
+    torch.cuda.synchronize()
+    b.profile_enable(True)
+    t0 = time.perf_counter()
+    for k in range(warmup + 1, warmup + steps + 1):
+        b.ingest(snaps[k])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    pj, er = b.profile_read("project"), b.profile_read("error")
+    pav = pj["total_ms"] / max(pj["launches"], 1) * 1e-3
+    eav = er["total_ms"] / max(er["launches"], 1) * 1e-3
+    ranks = [b.streams[i].ranks() for i in range(n)]
+    b.close()
+    step_bytes = 5.0 * 4.0 * elems   # two stage passes over two snapshots, one error pass
+    return {"workload": f"fourier-ensemble-{n}x{{128,192,256}}^2x4-fp32", "streams": n, "steps": steps,
+            "precision": precision, "elements_per_step": elems,
+            "value": n * steps / el, "unit": "snapshots/s", "ms_per_step": 1e3 * el / steps,
+            "step_hbm_frac": step_bytes / (el / steps) / (HBM_PEAK_GBS * 1e9),
+            "pass": {"avg_launch_us": pav * 1e6, "achieved_GBs": pj["bytes_per_launch"] / pav / 1e9,
+                     "frac": pj["bytes_per_launch"] / pav / 1e9 / HBM_PEAK_GBS},
+            "error_pass": {"avg_launch_us": eav * 1e6, "achieved_GBs": er["bytes_per_launch"] / eav / 1e9},
+            "max_ranks": [max(r[i] for r in ranks) for i in range(3)]}
+
+
 def _cpu_baseline(sp, start, budget_s=15.0, max_steps=60):
     """The FP64 numpy oracle on the host: init at snapshot `start`, then as many
     steps as fit in the budget (bounded sample of the same workload)."""
@@ -109,6 +152,11 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=200,
                     help="steps of the plain FP64 GPU path timed for comparison (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ensemble-streams", type=int, default=256,
+                    help="streams of the batched ensemble measurement (0 = skip)")
+    ap.add_argument("--ensemble-steps", type=int, default=20)
+    ap.add_argument("--bf16-steps", type=int, default=300,
+                    help="steps of the BF16-split form of the headline stream (0 = skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (a known-size reference for "
                          "hardware traffic counters)")
@@ -151,6 +199,22 @@ def main():
         el_p, st_p, _ = _run_gpu(sp, snaps, args.warmup, n_pl, "f64", "plain", profile=False)
         plain = {"value": n_pl / el_p, "unit": "snapshots/s", "steps": n_pl,
                  "speedup": value / (n_pl / el_p)}
+    bf16 = None
+    if args.bf16_steps > 0 and args.precision == "f32":
+        print("[bench] BF16-split stage pass", file=sys.stderr, flush=True)
+        n_b = min(args.bf16_steps, args.steps)
+        el_b, st_b, pr_b = _run_gpu(sp, snaps, args.warmup, n_b, "bf16s", args.path)
+        pb = pr_b["project"]
+        pbav = pb["total_ms"] / max(pb["launches"], 1) * 1e-3
+        bf16 = {"value": n_b / el_b, "unit": "snapshots/s", "steps": n_b, "pass_avg_launch_us": pbav * 1e6,
+                "pass_achieved_GBs": pb["bytes_per_launch"] / pbav / 1e9, "final_eps": st_b["eps"],
+                "final_ranks": st_b["ranks"]}
+    ens = None
+    if args.ensemble_streams > 0:
+        del snaps
+        torch.cuda.empty_cache()
+        print(f"[bench] batched ensemble of {args.ensemble_streams} streams", file=sys.stderr, flush=True)
+        ens = _run_ensemble(args.ensemble_streams, 3, args.ensemble_steps)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -174,6 +238,8 @@ def main():
         "final_stats": {"ranks": st["ranks"], "eps": st["eps"], "crbar": st["crbar"],
                         "n_add": st["n_add"], "n_reinit": st["n_reinit"], "n_remove": st["n_remove"]},
         "plain_fp64_gpu": plain,
+        "bf16_split": bf16,
+        "ensemble": ens,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
