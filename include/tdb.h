@@ -105,6 +105,10 @@ typedef struct {
   double cr;                           /* compression ratio at the current ranks       */
   double crbar;                        /* time-weighted ratio since init               */
   int32_t n_reinit, n_add, n_remove, n_numeric;
+  int32_t gated;                       /* 1: the learned gate skipped the exact error
+                                          pass of this step (eps is then NaN)          */
+  int32_t would_skip;                  /* the gate's verdict, also when it observes    */
+  double eps_pred;                     /* the gate's predicted eps (NaN without one)   */
 } tdb_stats;
 
 /* Initialise from the first snapshot by a weighted HOSVD (Sec. 2.3). V0_dev: device
@@ -187,6 +191,47 @@ tdb_status tdb_batch_profile_read(tdb_batch b, int32_t pass, int64_t* launches, 
                                   double* bytes_per_launch);
 void tdb_batch_destroy(tdb_batch b);
 const char* tdb_batch_last_error(tdb_batch b);
+
+/* ---- Learned error gate (not in the paper: a predictor of eq. (error) from the
+ * singular values of the core unfoldings, eq. (rot), so that the exact error pass of
+ * Sec. 2.5 can be skipped when the error is predicted to sit far below the threshold).
+ * Network 384 -> 128 -> 128 -> 1, tanh-form GELU, FP32; inputs: 8 consecutive steps x
+ * 3 modes x the 16 leading singular values, as log10(max(sigma, 1e-30)), oldest step
+ * first, mode-major, standardised per feature; output: log10 of the step's error.
+ * Parameters: one FP32 vector of TDB_GATE_PARAMS entries, W1 (128 x 384 row-major),
+ * b1, W2 (128 x 128), b2, w3 (128), b3.
+ *
+ * tdb_gate_create: a trainer owning the parameters, Adam moments and scratch for
+ *   batches of up to max_batch samples (device memory of the current device).
+ * tdb_gate_set_params / _get_params: host copies (set also clears Adam's moments).
+ * tdb_gate_forward: y_dev[i] = network(X_dev row i), X_dev n x 384 FP32 (device).
+ * tdb_gate_grad: gradient of the mean squared error against t_dev (n) into grad_dev
+ *   (TDB_GATE_PARAMS floats, device; NULL keeps it inside the trainer) and the loss
+ *   into *loss_host (NULL: not read back).
+ * tdb_gate_train_step: tdb_gate_grad, then one Adam step (lr; betas 0.9, 0.999;
+ *   eps 1e-8; bias correction by the trainer's own step count).
+ * tdb_batch_gate_attach: use trainer g's current parameters in batch b (not copied:
+ *   keep g alive). feat_mean_std_host: 384 means then 384 standard deviations
+ *   (copied). mode: TDB_GATE_OFF, TDB_GATE_RECORD (singular values every step, exact
+ *   pass always), TDB_GATE_ACTIVE (skip the exact pass when the gate allows), or
+ *   TDB_GATE_SHADOW (exact pass always; stats.would_skip reports the verdict).
+ * The gate runs the exact pass when fewer than 8 steps exist since the last
+ * reinitialisation, when the prediction is within half a decade of the threshold or
+ * above it, or when some mode's last singular value alone fits the removal budget. */
+enum { TDB_GATE_PARAMS = 65921, TDB_GATE_INPUTS = 384 };
+enum { TDB_GATE_OFF = 0, TDB_GATE_RECORD = 1, TDB_GATE_ACTIVE = 2, TDB_GATE_SHADOW = 3 };
+typedef struct tdb_gate_ctx* tdb_gate;
+tdb_status tdb_gate_create(int32_t max_batch, tdb_gate* out);
+tdb_status tdb_gate_set_params(tdb_gate g, const float* params_host);
+tdb_status tdb_gate_get_params(tdb_gate g, float* params_host);
+tdb_status tdb_gate_forward(tdb_gate g, const float* X_dev, int32_t n, float* y_dev, void* stream);
+tdb_status tdb_gate_grad(tdb_gate g, const float* X_dev, const float* t_dev, int32_t n, float* grad_dev,
+                         float* loss_host, void* stream);
+tdb_status tdb_gate_train_step(tdb_gate g, const float* X_dev, const float* t_dev, int32_t n, float lr,
+                               float* loss_host, void* stream);
+void tdb_gate_destroy(tdb_gate g);
+const char* tdb_gate_last_error(tdb_gate g);
+tdb_status tdb_batch_gate_attach(tdb_batch b, tdb_gate g, const float* feat_mean_std_host, int32_t mode);
 
 /* Layout check for language bindings: writes sizeof(tdb_config) and sizeof(tdb_stats)
  * (either pointer may be NULL). Needs no device. */

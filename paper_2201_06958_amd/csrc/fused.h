@@ -92,6 +92,9 @@ struct FErrArgs {
   unsigned* counter;
   const double* G[3];        // core Grams of the committed state (lazy singular values)
   int rmax;                  // largest rank (LDS of the final kernel)
+  const int* skip;           // the learned gate skips this pass (NULL: never)
+  const int* would_skip;     // the gate's verdict, recorded in the controller state
+  const float* yhat;         // the gate's prediction (log10 of the error)
 };
 
 // ev0/ev1 (may be null): events stamped by the dispatch itself at kernel start and end.
@@ -153,10 +156,10 @@ struct BatchMap {
 
 // What the host needs from each stream after a batched step.
 struct BatchSummary {
-  int decision, event, numeric, pad;
+  int decision, event, numeric, gated;
   int n_events[5];
-  int pad2;
-  double eps, nu, eps2, nu2;
+  int would_skip;
+  double eps, nu, eps2, nu2, eps_pred;
 };
 
 template <typename TD, typename T>

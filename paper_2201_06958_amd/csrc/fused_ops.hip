@@ -764,6 +764,15 @@ template <typename TD, typename T>
 __device__ __forceinline__ void ferr_body(const FErrArgs& a, int bx, int by, int gx) {
   __shared__ double red[16];
   __shared__ double U1s[FERR_T1 * TDB_RCAP];
+  if (a.skip && *a.skip) {
+    // the learned gate skips this step's pass
+    if (threadIdx.x == 0) {
+      const int b0 = by * gx + bx;
+      a.part[2 * b0] = 0.0;
+      a.part[2 * b0 + 1] = 0.0;
+    }
+    return;
+  }
   const long long M = a.M;      // N2*N3
   const int r1 = a.r1;
   const int i1_0 = by * a.T1;
@@ -811,11 +820,29 @@ __global__ void __launch_bounds__(256) k_ferr(FErrArgs a, CtrlState* ctrl) {
 // Controller of the fused path: the decision up to the removal test; only when that
 // test has to run are the singular values of the core unfoldings formed, one wave per
 // mode, from the Grams kept by the post-step kernel.
-__device__ __forceinline__ void fused_decide(CtrlState* ctrl, const double* const* G, int rmax) {
+__device__ __forceinline__ void fused_decide(CtrlState* ctrl, const double* const* G, int rmax, const int* skip,
+                                             const int* would_skip, const float* yhat) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
   __shared__ int need;
-  if (threadIdx.x == 0) need = controller_pre(ctrl) ? 1 : 0;
+  if (threadIdx.x == 0) {
+    ctrl->gated = (skip && *skip) ? 1 : 0;
+    ctrl->would_skip = would_skip ? *would_skip : 0;
+    ctrl->eps_pred = (yhat && isfinite(*yhat)) ? pow(10.0, (double)*yhat) : __builtin_nan("");
+    if (ctrl->gated) {
+      // no exact error this step: no decision, and the slope window starts over so that
+      // a removal always rests on consecutive exact errors
+      ctrl->eps = __builtin_nan("");
+      ctrl->event = 0;
+      ctrl->eps_after = __builtin_nan("");
+      ctrl->rank_changed = 0;
+      ctrl->decision = DEC_NONE;
+      ctrl->wcount = 0;
+      need = 0;
+    } else {
+      need = controller_pre(ctrl) ? 1 : 0;
+    }
+  }
   __syncthreads();
   if (!need) return;
   const int w = threadIdx.x >> 6;
@@ -845,12 +872,12 @@ __global__ void __launch_bounds__(256) k_ferr_final(FErrArgs a, CtrlState* ctrl)
   }
   s0 = block_sum(s0, red);
   s1 = block_sum(s1, red);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && !(a.skip && *a.skip)) {
     ctrl->eps2 = s0;
     ctrl->nu2 = s1;
   }
   __syncthreads();
-  fused_decide(ctrl, a.G, a.rmax);
+  fused_decide(ctrl, a.G, a.rmax, a.skip, a.would_skip, a.yhat);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -989,24 +1016,25 @@ __global__ void __launch_bounds__(256) kb_ferr_final(const FErrArgs* __restrict_
   }
   s0 = block_sum(s0, red);
   s1 = block_sum(s1, red);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && !(tab[s].skip && *tab[s].skip)) {
     ctrl->eps2 = s0;
     ctrl->nu2 = s1;
   }
   __syncthreads();
-  fused_decide(ctrl, tab[s].G, tab[s].rmax);
+  fused_decide(ctrl, tab[s].G, tab[s].rmax, tab[s].skip, tab[s].would_skip, tab[s].yhat);
   if (threadIdx.x == 0) {
     BatchSummary q;
     q.decision = ctrl->decision;
     q.event = ctrl->event;
     q.numeric = ctrl->numeric;
-    q.pad = 0;
+    q.gated = ctrl->gated;
     for (int k = 0; k < 5; ++k) q.n_events[k] = ctrl->n_events[k];
-    q.pad2 = 0;
+    q.would_skip = ctrl->would_skip;
     q.eps = ctrl->eps;
     q.nu = ctrl->nu;
-    q.eps2 = s0;
-    q.nu2 = s1;
+    q.eps2 = ctrl->eps2;
+    q.nu2 = ctrl->nu2;
+    q.eps_pred = ctrl->eps_pred;
     out[s] = q;
   }
 }

@@ -90,6 +90,10 @@ __global__ void __launch_bounds__(256) k_gram_reduce(const double* __restrict__ 
     const int il = t / 64, jl = t % 64;
     const long long i = (long long)ti * 64 + il, j = (long long)tj * 64 + jl;
     if (i >= m.Nn || j >= m.Nn) continue;
+    // a diagonal tile holds both (i, j) and (j, i), whose partial sums differ in rounding
+    // (the weight multiplies one operand): only the lower entry writes both, so the
+    // result never depends on which write lands last
+    if (ti == tj && jl > il) continue;
     double s = 0.0;
     for (int c = 0; c < nchunks; ++c) s += partials[((long long)pair * nchunks + c) * 4096 + t];
     s *= sqrt(m.wn[i] * m.wn[j]);

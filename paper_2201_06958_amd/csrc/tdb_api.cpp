@@ -4,6 +4,7 @@
 #include "../../include/tdb.h"
 #include "tdb_kernels.h"
 #include "fused.h"
+#include "gate.h"
 
 #include <hip/hip_runtime.h>
 
@@ -717,6 +718,9 @@ void fill_stats(tdb_ctx* h, bool initial) {
   st.n_add = c.n_events[EV_ADD];
   st.n_remove = c.n_events[EV_REMOVE];
   st.n_numeric = c.n_events[EV_NUMERIC];
+  st.gated = initial ? 0 : c.gated;
+  st.would_skip = initial ? 0 : c.would_skip;
+  st.eps_pred = initial ? NAN : c.eps_pred;
 }
 
 hipEvent_t take_event(tdb_ctx* h) {
@@ -834,8 +838,9 @@ tdb_status ingest_impl(tdb_ctx* h, const TD* V1, hipStream_t s) {
     TRY(pull_ctrl(h, s));
   }
   TRY(keep_previous<TD>(h, V1, s));
-  // the step formed the core singular values only if asked to or on a reinit
-  h->sigma_stale = !(h->sigma_every_step || dec != DEC_NONE);
+  // the host copy holds this step's singular values only after a reinit (pulled in
+  // full) or when a single stream formed them and pulled the controller state
+  h->sigma_stale = !(dec != DEC_NONE || (h->sigma_every_step && !h->batch_owned));
   fill_stats(h, false);
   return TDB_OK;
 }
@@ -1074,8 +1079,9 @@ tdb_status finish_step(tdb_ctx* h, const TD* V1, hipStream_t s) {
     TRY(pull_ctrl(h, s));
   }
   TRY(keep_previous<TD>(h, V1, s));
-  // the step formed the core singular values only if asked to or on a reinit
-  h->sigma_stale = !(h->sigma_every_step || dec != DEC_NONE);
+  // the host copy holds this step's singular values only after a reinit (pulled in
+  // full) or when a single stream formed them and pulled the controller state
+  h->sigma_stale = !(dec != DEC_NONE || (h->sigma_every_step && !h->batch_owned));
   fill_stats(h, false);
   return TDB_OK;
 }
@@ -1192,6 +1198,11 @@ struct tdb_batch_ctx {
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[2];
+  // learned gate (parameters owned by the trainer that was attached)
+  int gate_mode = GATE_OFF;
+  const float* gate_params = nullptr;
+  float *d_gmean = nullptr, *d_gstd = nullptr, *d_ghist = nullptr, *d_gyhat = nullptr;
+  int *d_ghcount = nullptr, *d_gskip = nullptr, *d_gwould = nullptr;
 
   ~tdb_batch_ctx() {
     for (auto& v : ev_used)
@@ -1202,6 +1213,27 @@ struct tdb_batch_ctx {
     for (void* q : host) (void)hipHostFree(q);
   }
 };
+
+struct tdb_gate_ctx {
+  int max_batch = 0;
+  std::vector<void*> dev;
+  float *P = nullptr, *M = nullptr, *V = nullptr, *G = nullptr, *loss = nullptr;
+  GateScratch w{};
+  int step = 0;
+  std::string err;
+  ~tdb_gate_ctx() {
+    for (void* q : dev) (void)hipFree(q);
+  }
+};
+
+#define GHIPCHK(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      g->err = std::string(#expr) + ": " + hipGetErrorString(e_);                      \
+      return TDB_EHIP;                                                                 \
+    }                                                                                  \
+  } while (0)
 
 #define BHIPCHK(expr)                                                                  \
   do {                                                                                 \
@@ -1277,6 +1309,11 @@ tdb_status batch_upload_args(tdb_batch_ctx* b, hipStream_t s) {
     b->h_qa[i] = A.qa;
     b->h_pa[i] = A.pa;
     b->h_ea[i] = A.ea;
+    if (b->gate_mode != GATE_OFF) {
+      b->h_ea[i].skip = b->d_gskip + i;
+      b->h_ea[i].would_skip = b->d_gwould + i;
+      b->h_ea[i].yhat = b->d_gyhat + i;
+    }
   }
   const size_t n = (size_t)b->n;
   BHIPCHK(hipMemcpyAsync(b->d_fa[0], b->h_fa[0], n * sizeof(FPassArgs), hipMemcpyHostToDevice, s));
@@ -1392,6 +1429,20 @@ tdb_status batch_step(tdb_batch_ctx* b, const void* const* V, hipStream_t s) {
   }
   BHIPCHK(launch_batch_fqr(b->d_qa, b->d_ctab, b->m_qr, b->g_qr, b->lds_qr, s));
   BHIPCHK(launch_batch_fpost<T>(b->d_pa, b->d_ctab, b->m_post, b->g_post, b->lds_post, s));
+  if (b->gate_mode != GATE_OFF) {
+    GateStepArgs g{};
+    g.params = b->gate_params;
+    g.mean = b->d_gmean;
+    g.stdv = b->d_gstd;
+    g.ctrl = b->d_ctab;
+    g.hist = b->d_ghist;
+    g.hcount = b->d_ghcount;
+    g.yhat = b->d_gyhat;
+    g.skip = b->d_gskip;
+    g.would_skip = b->d_gwould;
+    g.mode = b->gate_mode;
+    BHIPCHK(gate_infer(g, n, s));
+  }
   {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (b->prof) {
@@ -1418,11 +1469,16 @@ tdb_status batch_step(tdb_batch_ctx* b, const void* const* V, hipStream_t s) {
     c.eps2 = q.eps2;
     c.nu2 = q.nu2;
     c.eps_after = NAN;   // as the controller leaves it on a step without an event
+    c.gated = q.gated;
+    c.would_skip = q.would_skip;
+    c.eps_pred = q.eps_pred;
     h->post_valid = true;
     const int r0[3] = {h->r[0], h->r[1], h->r[2]};
     tdb_status r = finish_step<TD, T>(h, static_cast<const TD*>(V[i]), s);
     if (r != TDB_OK) { b->err = "stream " + std::to_string(i) + ": " + h->err; return r; }
     if (h->r[0] != r0[0] || h->r[1] != r0[1] || h->r[2] != r0[2]) b->dirty = true;
+    if (q.decision != DEC_NONE && b->gate_mode != GATE_OFF)   // the singular values start over
+      BHIPCHK(hipMemsetAsync(b->d_ghcount + i, 0, sizeof(int), s));
     h->fused_steps += 1;
   }
   return TDB_OK;
@@ -1726,7 +1782,7 @@ tdb_status tdb_batch_ingest(tdb_batch b, const void* const* V_dev, void* stream)
   else st = b->f32 ? batch_step<double, float>(b, V_dev, s) : batch_step<double, double>(b, V_dev, s);
   if (st != TDB_OK) return st;
   for (int i = 0; i < b->n; ++i)
-    if (!std::isfinite(b->st[i]->stats.eps)) {
+    if (!b->st[i]->stats.gated && !std::isfinite(b->st[i]->stats.eps)) {
       b->err = "stream " + std::to_string(i) + ": non-finite reconstruction error";
       return TDB_ENUMERIC;
     }
@@ -1777,6 +1833,153 @@ void tdb_batch_destroy(tdb_batch b) {
 const char* tdb_batch_last_error(tdb_batch b) {
   if (!b) return g_create_error.c_str();
   return b->err.c_str();
+}
+
+tdb_status tdb_gate_create(int32_t max_batch, tdb_gate* out) {
+  if (!out) { g_create_error = "out is NULL"; return TDB_EINVAL; }
+  *out = nullptr;
+  if (max_batch < 1 || max_batch > (1 << 20)) { g_create_error = "max_batch must be in [1, 2^20]"; return TDB_EINVAL; }
+  tdb_gate_ctx* g = new (std::nothrow) tdb_gate_ctx();
+  if (!g) { g_create_error = "out of host memory"; return TDB_ENOMEM; }
+  auto al = [&](float** p, size_t count) -> tdb_status {
+    void* q = nullptr;
+    if (hipMalloc(&q, count * sizeof(float)) != hipSuccess) { g->err = "hipMalloc failed"; return TDB_ENOMEM; }
+    g->dev.push_back(q);
+    *p = static_cast<float*>(q);
+    return TDB_OK;
+  };
+  auto run = [&]() -> tdb_status {
+    g->max_batch = max_batch;
+    TRY(al(&g->P, GATE_NP));
+    TRY(al(&g->M, GATE_NP));
+    TRY(al(&g->V, GATE_NP));
+    TRY(al(&g->G, GATE_NP));
+    TRY(al(&g->loss, 4));
+    const size_t nh = (size_t)max_batch * GATE_H;
+    TRY(al(&g->w.H1, nh));
+    TRY(al(&g->w.A1, nh));
+    TRY(al(&g->w.H2, nh));
+    TRY(al(&g->w.A2, nh));
+    TRY(al(&g->w.dH1, nh));
+    TRY(al(&g->w.dH2, nh));
+    TRY(al(&g->w.y, (size_t)max_batch));
+    TRY(al(&g->w.dY, (size_t)max_batch));
+    GHIPCHK(hipMemset(g->P, 0, GATE_NP * sizeof(float)));
+    GHIPCHK(hipMemset(g->M, 0, GATE_NP * sizeof(float)));
+    GHIPCHK(hipMemset(g->V, 0, GATE_NP * sizeof(float)));
+    return TDB_OK;
+  };
+  tdb_status st = run();
+  if (st != TDB_OK) {
+    g_create_error = g->err;
+    delete g;
+    return st;
+  }
+  *out = g;
+  return TDB_OK;
+}
+
+tdb_status tdb_gate_set_params(tdb_gate g, const float* params_host) {
+  if (!g) { g_create_error = "gate is NULL"; return TDB_EINVAL; }
+  if (!params_host) { g->err = "params is NULL"; return TDB_EINVAL; }
+  GHIPCHK(hipDeviceSynchronize());
+  GHIPCHK(hipMemcpy(g->P, params_host, GATE_NP * sizeof(float), hipMemcpyHostToDevice));
+  GHIPCHK(hipMemset(g->M, 0, GATE_NP * sizeof(float)));
+  GHIPCHK(hipMemset(g->V, 0, GATE_NP * sizeof(float)));
+  g->step = 0;
+  return TDB_OK;
+}
+
+tdb_status tdb_gate_get_params(tdb_gate g, float* params_host) {
+  if (!g) { g_create_error = "gate is NULL"; return TDB_EINVAL; }
+  if (!params_host) { g->err = "params is NULL"; return TDB_EINVAL; }
+  GHIPCHK(hipDeviceSynchronize());
+  GHIPCHK(hipMemcpy(params_host, g->P, GATE_NP * sizeof(float), hipMemcpyDeviceToHost));
+  return TDB_OK;
+}
+
+tdb_status tdb_gate_forward(tdb_gate g, const float* X_dev, int32_t n, float* y_dev, void* stream) {
+  if (!g) { g_create_error = "gate is NULL"; return TDB_EINVAL; }
+  if (!X_dev || !y_dev || n < 0) { g->err = "bad arguments"; return TDB_EINVAL; }
+  GHIPCHK(gate_forward(g->P, X_dev, n, nullptr, nullptr, nullptr, nullptr, y_dev, static_cast<hipStream_t>(stream)));
+  return TDB_OK;
+}
+
+tdb_status tdb_gate_grad(tdb_gate g, const float* X_dev, const float* t_dev, int32_t n, float* grad_dev,
+                         float* loss_host, void* stream) {
+  if (!g) { g_create_error = "gate is NULL"; return TDB_EINVAL; }
+  if (!X_dev || !t_dev || n < 1 || n > g->max_batch) { g->err = "bad arguments (1 <= n <= max_batch)"; return TDB_EINVAL; }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  GHIPCHK(gate_gradient(g->P, X_dev, t_dev, n, g->w, grad_dev ? grad_dev : g->G, loss_host ? g->loss : nullptr, s));
+  if (loss_host) {
+    GHIPCHK(hipMemcpyAsync(loss_host, g->loss, sizeof(float), hipMemcpyDeviceToHost, s));
+    GHIPCHK(hipStreamSynchronize(s));
+  }
+  return TDB_OK;
+}
+
+tdb_status tdb_gate_train_step(tdb_gate g, const float* X_dev, const float* t_dev, int32_t n, float lr,
+                               float* loss_host, void* stream) {
+  if (!g) { g_create_error = "gate is NULL"; return TDB_EINVAL; }
+  if (!X_dev || !t_dev || n < 1 || n > g->max_batch || !(lr > 0.0f)) { g->err = "bad arguments"; return TDB_EINVAL; }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  GHIPCHK(gate_gradient(g->P, X_dev, t_dev, n, g->w, g->G, loss_host ? g->loss : nullptr, s));
+  g->step += 1;
+  GHIPCHK(gate_adam(g->P, g->G, g->M, g->V, g->step, lr, s));
+  if (loss_host) {
+    GHIPCHK(hipMemcpyAsync(loss_host, g->loss, sizeof(float), hipMemcpyDeviceToHost, s));
+    GHIPCHK(hipStreamSynchronize(s));
+  }
+  return TDB_OK;
+}
+
+void tdb_gate_destroy(tdb_gate g) {
+  if (!g) return;
+  (void)hipDeviceSynchronize();
+  delete g;
+}
+
+const char* tdb_gate_last_error(tdb_gate g) {
+  if (!g) return g_create_error.c_str();
+  return g->err.c_str();
+}
+
+tdb_status tdb_batch_gate_attach(tdb_batch b, tdb_gate g, const float* feat_mean_std_host, int32_t mode) {
+  if (!b) { g_create_error = "batch is NULL"; return TDB_EINVAL; }
+  if (mode < GATE_OFF || mode > GATE_SHADOW) { b->err = "bad gate mode"; return TDB_EINVAL; }
+  if (mode != GATE_OFF && mode != GATE_RECORD && (!g || !feat_mean_std_host)) {
+    b->err = "a gate and its feature statistics are needed";
+    return TDB_EINVAL;
+  }
+  BHIPCHK(hipDeviceSynchronize());
+  const size_t n = (size_t)b->n;
+  if (!b->d_ghist) {
+    TRY(balloc<float>(b, &b->d_gmean, nullptr, GATE_IN));
+    TRY(balloc<float>(b, &b->d_gstd, nullptr, GATE_IN));
+    TRY(balloc<float>(b, &b->d_ghist, nullptr, n * GATE_W * GATE_ROW));
+    TRY(balloc<float>(b, &b->d_gyhat, nullptr, n));
+    TRY(balloc<int>(b, &b->d_ghcount, nullptr, n));
+    TRY(balloc<int>(b, &b->d_gskip, nullptr, n));
+    TRY(balloc<int>(b, &b->d_gwould, nullptr, n));
+  }
+  std::vector<float> ms(2 * GATE_IN, 0.0f);
+  for (int i = 0; i < GATE_IN; ++i) ms[GATE_IN + i] = 1.0f;
+  if (feat_mean_std_host) {
+    for (int i = 0; i < 2 * GATE_IN; ++i) ms[i] = feat_mean_std_host[i];
+    for (int i = 0; i < GATE_IN; ++i)
+      if (!(ms[GATE_IN + i] > 0.0f)) { b->err = "feature standard deviations must be positive"; return TDB_EINVAL; }
+  }
+  BHIPCHK(hipMemcpy(b->d_gmean, ms.data(), GATE_IN * sizeof(float), hipMemcpyHostToDevice));
+  BHIPCHK(hipMemcpy(b->d_gstd, ms.data() + GATE_IN, GATE_IN * sizeof(float), hipMemcpyHostToDevice));
+  BHIPCHK(hipMemset(b->d_ghcount, 0, n * sizeof(int)));
+  BHIPCHK(hipMemset(b->d_gskip, 0, n * sizeof(int)));
+  BHIPCHK(hipMemset(b->d_gwould, 0, n * sizeof(int)));
+  // RECORD without a network only keeps the singular values every step
+  b->gate_params = g ? g->P : nullptr;
+  b->gate_mode = (mode == GATE_RECORD && !g) ? GATE_OFF : mode;
+  for (tdb_ctx* h : b->st) h->sigma_every_step = mode != GATE_OFF;
+  b->dirty = true;
+  return TDB_OK;
 }
 
 void tdb_struct_sizes(int64_t* config_bytes, int64_t* stats_bytes) {

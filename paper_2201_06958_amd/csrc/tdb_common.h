@@ -49,6 +49,9 @@ struct CtrlState {
   double eps, nu, eps_after;
   double sigma[TDB_P][TDB_RCAP];   // core unfolding singular values, descending
   int n_events[5];
+  int gated;          // the learned gate skipped this step's error pass
+  int would_skip;     // the gate's verdict (also when it only observes)
+  double eps_pred;    // the gate's predicted error of this step (NaN without one)
 };
 
 __device__ __forceinline__ double warp_sum(double v) {

@@ -71,6 +71,9 @@ class TdbStats(ctypes.Structure):
         ("n_add", ctypes.c_int32),
         ("n_remove", ctypes.c_int32),
         ("n_numeric", ctypes.c_int32),
+        ("gated", ctypes.c_int32),
+        ("would_skip", ctypes.c_int32),
+        ("eps_pred", ctypes.c_double),
     ]
 
 
@@ -117,6 +120,18 @@ def load_library(path: str = LIB_PATH):
     lib.tdb_batch_profile_enable.argtypes = [H, ctypes.c_int32]
     lib.tdb_batch_profile_read.argtypes = [H, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.tdb_batch_gate_attach.argtypes = [H, H, ctypes.POINTER(ctypes.c_float), ctypes.c_int32]
+    F = ctypes.POINTER(ctypes.c_float)
+    lib.tdb_gate_create.argtypes = [ctypes.c_int32, ctypes.POINTER(H)]
+    lib.tdb_gate_set_params.argtypes = [H, F]
+    lib.tdb_gate_get_params.argtypes = [H, F]
+    lib.tdb_gate_forward.argtypes = [H, P, ctypes.c_int32, P, P]
+    lib.tdb_gate_grad.argtypes = [H, P, P, ctypes.c_int32, P, F, P]
+    lib.tdb_gate_train_step.argtypes = [H, P, P, ctypes.c_int32, ctypes.c_float, F, P]
+    lib.tdb_gate_destroy.argtypes = [H]
+    lib.tdb_gate_destroy.restype = None
+    lib.tdb_gate_last_error.argtypes = [H]
+    lib.tdb_gate_last_error.restype = ctypes.c_char_p
     lib.tdb_batch_destroy.argtypes = [H]
     lib.tdb_batch_destroy.restype = None
     lib.tdb_batch_last_error.argtypes = [H]
@@ -124,7 +139,8 @@ def load_library(path: str = LIB_PATH):
     for name in ("tdb_init", "tdb_init_from_factors", "tdb_ingest_snapshot", "tdb_get_core_and_bases",
                  "tdb_reconstruct", "tdb_set_threshold", "tdb_get_stats", "tdb_batch_create",
                  "tdb_batch_ingest", "tdb_batch_stream", "tdb_batch_profile_enable",
-                 "tdb_batch_profile_read"):
+                 "tdb_batch_profile_read", "tdb_batch_gate_attach", "tdb_gate_create", "tdb_gate_set_params",
+                 "tdb_gate_get_params", "tdb_gate_forward", "tdb_gate_grad", "tdb_gate_train_step"):
         getattr(lib, name).restype = ctypes.c_int32
     a, b = ctypes.c_int64(), ctypes.c_int64()
     lib.tdb_struct_sizes(ctypes.byref(a), ctypes.byref(b))
@@ -250,7 +266,9 @@ class Compressor:
             "ranks": tuple(s.ranks[:p]), "event": EVENTS.get(s.event, str(s.event)),
             "sigma": [list(s.sigma[n][: s.ranks[n]]) for n in range(p)], "cr": s.cr,
             "crbar": s.crbar, "n_reinit": s.n_reinit, "n_add": s.n_add, "n_remove": s.n_remove,
-            "n_numeric": s.n_numeric,
+            "n_numeric": s.n_numeric, "gated": bool(s.gated), "would_skip": bool(s.would_skip),
+            "eps_pred": s.eps_pred,
+            "sigma16": [list(s.sigma[n][:SIGMA_K]) for n in range(p)],
         }
 
     def profile_enable(self, on: bool = True):
@@ -313,6 +331,16 @@ class Batch:
     def ingest(self, Vs, stream=None):
         self._check(self.lib.tdb_batch_ingest(self.h, self._ptrs(Vs), _stream_ptr(stream)))
 
+    def gate_attach(self, gate, mean_std=None, mode: str = "active"):
+        """Use a trained Gate (kept alive by the caller) with the given feature statistics
+        (768 floats: means, then standard deviations). mode: off | record | active | shadow."""
+        mid = {"off": 0, "record": 1, "active": 2, "shadow": 3}[mode]
+        ms = None
+        if mean_std is not None:
+            self._ms = np.ascontiguousarray(mean_std, dtype=np.float32)
+            ms = self._ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        self._check(self.lib.tdb_batch_gate_attach(self.h, gate.h if gate is not None else None, ms, mid))
+
     def profile_enable(self, on: bool = True):
         self._check(self.lib.tdb_batch_profile_enable(self.h, 1 if on else 0))
 
@@ -329,6 +357,67 @@ class Batch:
         self.streams = []
         if self.h:
             self.lib.tdb_batch_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Gate:
+    """Trainer and holder of the learned error gate's parameters (see tdb.h)."""
+
+    N_PARAMS = 65921
+    N_IN = 384
+
+    def __init__(self, max_batch: int = 1024):
+        self.lib = load_library()
+        self.h = ctypes.c_void_p()
+        self._check(self.lib.tdb_gate_create(int(max_batch), ctypes.byref(self.h)))
+        self.max_batch = int(max_batch)
+
+    def _check(self, status: int):
+        if status != OK:
+            msg = self.lib.tdb_gate_last_error(self.h if self.h else None)
+            raise TDBError(status, (msg or b"").decode())
+
+    def set_params(self, theta: np.ndarray):
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        if t.size != self.N_PARAMS:
+            raise ValueError("wrong parameter count")
+        self._check(self.lib.tdb_gate_set_params(self.h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.N_PARAMS, dtype=np.float32)
+        self._check(self.lib.tdb_gate_get_params(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    def forward(self, X, stream=None):
+        import torch
+        X = X.contiguous()
+        y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        self._check(self.lib.tdb_gate_forward(self.h, _dev_ptr(X), X.shape[0], _dev_ptr(y), _stream_ptr(stream)))
+        return y
+
+    def grad(self, X, t, stream=None):
+        import torch
+        g = torch.empty(self.N_PARAMS, dtype=torch.float32, device=X.device)
+        loss = ctypes.c_float()
+        self._check(self.lib.tdb_gate_grad(self.h, _dev_ptr(X.contiguous()), _dev_ptr(t.contiguous()), X.shape[0],
+                                           _dev_ptr(g), ctypes.byref(loss), _stream_ptr(stream)))
+        return g, loss.value
+
+    def train_step(self, X, t, lr: float, want_loss: bool = False, stream=None):
+        loss = ctypes.c_float()
+        self._check(self.lib.tdb_gate_train_step(self.h, _dev_ptr(X), _dev_ptr(t), X.shape[0], float(lr),
+                                                 ctypes.byref(loss) if want_loss else None, _stream_ptr(stream)))
+        return loss.value if want_loss else None
+
+    def close(self):
+        if self.h:
+            self.lib.tdb_gate_destroy(self.h)
             self.h = ctypes.c_void_p()
 
     def __del__(self):

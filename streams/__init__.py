@@ -15,4 +15,5 @@ from .generators import (  # noqa: F401
     lowrank_manifold_spec,
     switched_term_spec,
     counter_normal,
+    gate_init_params,
 )

@@ -268,13 +268,13 @@ def _fourier_stream(s, nx, ny, nv, kx, ky, amp, ph, om, steps, dt) -> StreamSpec
         X = xs.to(device)
         Y = ys.to(device)
         out = torch.empty((nx, ny, nv), dtype=torch.float64, device=device)
+        # elementwise over (x, y, mode), then a sum over the modes (no library matrix
+        # product, so every device and run gives the same values)
         for v in range(nv):
-            ax = KX[v].to(device)[None, :] * X[:, None]                  # nx x m
-            by = KY[v].to(device)[None, :] * Y[:, None] + (PH[v] + OM[v] * t).to(device)[None, :]
-            a = A[v].to(device)
-            L = torch.cat([torch.cos(ax), torch.sin(ax)], dim=1)          # nx x 2m
-            R = torch.cat([a[None, :] * torch.cos(by), -a[None, :] * torch.sin(by)], dim=1)
-            out[:, :, v] = L @ R.T                                        # cos(ax + by)
+            kx, ky = KX[v].to(device), KY[v].to(device)
+            arg = (X[:, None, None] * kx[None, None, :] + Y[None, :, None] * ky[None, None, :]
+                   + (PH[v] + OM[v] * t).to(device)[None, None, :])
+            out[:, :, v] = (A[v].to(device)[None, None, :] * torch.cos(arg)).sum(dim=2)
         return out.to(dtype)
 
     dims = (nx, ny, nv)
@@ -503,3 +503,17 @@ def switched_term_spec(dims=(16, 14, 12), ranks=(3, 3, 3), t_on: float = 0.1,
         storage="f64", eps_th=eps_th, rank_init=tuple(ranks),
         rank_max=tuple(r + 2 for r in ranks), adaptive=True,
         meta={"t_on": t_on, "qnorm": qnorm, "h": h, "g": g})
+
+
+# --------------------------------------------------------------------------- gate init
+def gate_init_params(seed: int = 11) -> np.ndarray:
+    """Initial parameters of the 384-128-128-1 error-gate network (flat FP32 vector:
+    W1 128x384, b1, W2 128x128, b2, w3, b3), each layer's weights and biases uniform on
+    [-1/sqrt(fan_in), 1/sqrt(fan_in)] from PCG64(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for fan_in, shape in ((384, (128, 384)), (384, (128,)), (128, (128, 128)), (128, (128,)), (128, (128,)),
+                          (128, (1,))):
+        b = 1.0 / np.sqrt(fan_in)
+        parts.append(rng.uniform(-b, b, size=shape).ravel())
+    return np.concatenate(parts).astype(np.float32)
