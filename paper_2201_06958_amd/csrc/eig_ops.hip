@@ -1,0 +1,434 @@
+// Leading eigenpairs of the weighted mode Gram matrices of the HOSVD (Sec. 2.3):
+// Householder reduction to tridiagonal form spread over many workgroups (one launch
+// per reflector), bisection on Sturm counts for the leading K+1 eigenvalues, inverse
+// iteration for the K leading eigenvectors (clusters of close eigenvalues
+// orthogonalised within one wave), back-transformation by the stored reflectors and
+// a sign convention (largest-magnitude entry positive, lowest index on a tie).
+//
+// Reflector k (k = 0..n-3) acts on indices k+1..n-1; it is stored in row k of G
+// (entries k+1..n-1), its coefficient in beta[k]. Launch k applies the rank-2 update
+// of reflector k-1 to this workgroup's rows of the trailing block (columns k+1..n-1),
+// forms column k and the diagonal entry k of the updated matrix on the fly from the
+// not yet updated values (nobody writes them in this launch), computes reflector k
+// redundantly in every workgroup (the same fixed-order sums everywhere), and the
+// product p = beta A v for its rows into one of two buffers (the other still holds
+// the previous reflector's product, which every workgroup reads in this launch).
+#include "tdb_common.h"
+#include "tdb_kernels.h"
+#include <math.h>
+
+namespace tdb {
+
+#define NE TDB_NEIG
+
+// Per-mode workspace (after the K eigenvector columns): d, e, beta, p0, p1.
+struct EigWs {
+  double *X, *d, *e, *beta, *p[2];
+};
+__device__ __forceinline__ EigWs eig_ws(const EigArgs& a) {
+  EigWs w;
+  const long long n = a.Nn;
+  w.X = a.work;
+  w.d = a.work + n * a.k;
+  w.e = w.d + n;
+  w.beta = w.e + n;
+  w.p[0] = w.beta + n;
+  w.p[1] = w.p[0] + n;
+  return w;
+}
+
+__global__ void __launch_bounds__(256) k_tri_step(EigBatch batch, int k) {
+  const EigArgs a = batch.m[blockIdx.y];
+  const int n = a.Nn;
+  if (k + 2 >= n) return;
+  const EigWs w = eig_ws(a);
+  double* G = a.G;
+  __shared__ double vp[NE], wp[NE], v[NE];
+  __shared__ double red[16];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int nblk = gridDim.x;
+  // the pending update of reflector k-1 (acting on indices k..n-1)
+  const double bp = k > 0 ? w.beta[k - 1] : 0.0;
+  const int mp = n - k;
+  if (bp != 0.0) {
+    const double* pp = w.p[(k - 1) & 1];
+    double pvv = 0.0;
+    for (int i = tid; i < mp; i += blockDim.x) {
+      const double vi = G[(long long)(k - 1) * n + k + i];
+      vp[i] = vi;
+      pvv += pp[k + i] * vi;
+    }
+    pvv = block_sum(pvv, red);
+    const double Kc = 0.5 * bp * pvv;
+    for (int i = tid; i < mp; i += blockDim.x) wp[i] = pp[k + i] - Kc * vp[i];
+    __syncthreads();
+  }
+  // column k below the diagonal and the diagonal entry of the updated matrix
+  const int m = n - k - 1;
+  double ss = 0.0;
+  for (int i = tid; i < m; i += blockDim.x) {
+    double x = G[(long long)(k + 1 + i) * n + k];
+    if (bp != 0.0) x -= vp[1 + i] * wp[0] + wp[1 + i] * vp[0];
+    v[i] = x;
+    ss += x * x;
+  }
+  ss = block_sum(ss, red);
+  const double x0 = v[0];
+  double dk = G[(long long)k * n + k];
+  if (bp != 0.0) dk -= vp[0] * wp[0] + wp[0] * vp[0];
+  double bk = 0.0, ek = x0;
+  __syncthreads();
+  if (ss > 0.0) {
+    const double xn = sqrt(ss);
+    const double alpha = x0 > 0.0 ? -xn : xn;
+    const double v0 = x0 - alpha;
+    const double vtv = ss - x0 * x0 + v0 * v0;
+    bk = 2.0 / vtv;
+    ek = alpha;
+    if (tid == 0) v[0] = v0;
+  }
+  __syncthreads();
+  // rows of this workgroup: k+1+i for i = blockIdx.x, blockIdx.x + nblk, ...; one wave per row
+  double* pk = w.p[k & 1];
+  for (int i = blockIdx.x + nblk * wid; i < m; i += nblk * 4) {
+    double* row = G + (long long)(k + 1 + i) * n + (k + 1);
+    double s = 0.0;
+    if (bp != 0.0) {
+      const double vr = vp[1 + i], wr = wp[1 + i];
+      for (int j = lane; j < m; j += 64) {
+        const double x = row[j] - (vr * wp[1 + j] + wr * vp[1 + j]);
+        row[j] = x;
+        s += x * v[j];
+      }
+    } else {
+      for (int j = lane; j < m; j += 64) s += row[j] * v[j];
+    }
+    s = warp_sum(s);
+    if (lane == 0) pk[k + 1 + i] = bk * s;
+  }
+  if (blockIdx.x == 0) {
+    for (int i = tid; i < m; i += blockDim.x) G[(long long)k * n + k + 1 + i] = v[i];
+    if (tid == 0) {
+      w.d[k] = dk;
+      w.e[k] = ek;
+      w.beta[k] = bk;
+    }
+  }
+}
+
+// The last 2 x 2 block (with the pending update of reflector n-3), and e[n-1] = 0.
+__global__ void __launch_bounds__(64) k_tri_final(EigBatch batch) {
+  const EigArgs a = batch.m[blockIdx.x];
+  const int n = a.Nn;
+  const EigWs w = eig_ws(a);
+  const double* G = a.G;
+  if (threadIdx.x != 0) return;
+  if (n == 1) {
+    w.d[0] = G[0];
+    w.e[0] = 0.0;
+    return;
+  }
+  const int k = n - 2;   // first index of the block
+  double a00 = G[(long long)k * n + k], a10 = G[(long long)(k + 1) * n + k], a11 = G[(long long)(k + 1) * n + k + 1];
+  const double bp = k > 0 ? w.beta[k - 1] : 0.0;
+  if (bp != 0.0) {
+    const double* pp = w.p[(k - 1) & 1];
+    const double v0 = G[(long long)(k - 1) * n + k], v1 = G[(long long)(k - 1) * n + k + 1];
+    const double Kc = 0.5 * bp * (pp[k] * v0 + pp[k + 1] * v1);
+    const double w0 = pp[k] - Kc * v0, w1 = pp[k + 1] - Kc * v1;
+    a00 -= v0 * w0 + w0 * v0;
+    a10 -= v1 * w0 + w1 * v0;
+    a11 -= v1 * w1 + w1 * v1;
+  }
+  w.d[k] = a00;
+  w.e[k] = a10;
+  w.beta[k] = 0.0;
+  w.d[k + 1] = a11;
+  w.e[k + 1] = 0.0;
+}
+
+// Sturm count: number of eigenvalues of the tridiagonal (d, e2 = e^2) below x.
+__device__ int sturm_count2(const double* d, const double* e2, int n, double x, double pivmin) {
+  int c = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  if (q < 0.0) ++c;
+  for (int i = 1; i < n; ++i) {
+    q = d[i] - x - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++c;
+  }
+  return c;
+}
+
+__device__ __forceinline__ double hash_unit2(unsigned a, unsigned b) {
+  unsigned x = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u);
+  x ^= x >> 16; x *= 0x7FEB352Du; x ^= x >> 15; x *= 0x846CA68Bu; x ^= x >> 16;
+  return (double)x * (2.0 / 4294967296.0) - 1.0;
+}
+
+// One block per mode: the K+1 leading eigenvalues by bisection (one thread each), the
+// singular values sqrt(max(lambda, 0)), and the Gershgorin scale.
+__global__ void __launch_bounds__(128) k_eig_values(EigBatch batch, double* lam_out) {
+  const EigArgs a = batch.m[blockIdx.x];
+  const int n = a.Nn, K = a.k;
+  const EigWs w = eig_ws(a);
+  __shared__ double d[NE], e2[NE], red[16];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    d[i] = w.d[i];
+    e2[i] = w.e[i] * w.e[i];
+  }
+  __syncthreads();
+  double lo = 1e300, hi = -1e300, mx = 0.0, me = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double off = (i > 0 ? fabs(w.e[i - 1]) : 0.0) + (i + 1 < n ? fabs(w.e[i]) : 0.0);
+    lo = fmin(lo, d[i] - off);
+    hi = fmax(hi, d[i] + off);
+    mx = fmax(mx, fabs(d[i]) + off);
+    if (i + 1 < n) me = fmax(me, e2[i]);
+  }
+  double gl = -block_max(-lo, red);
+  double gu = block_max(hi, red);
+  const double tn = block_max(mx, red);
+  const double emax2 = block_max(me, red);
+  const double eps = 2.220446049250313e-16;
+  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+  gl -= 4.0 * eps * tn + 2.0 * pivmin;
+  gu += 4.0 * eps * tn + 2.0 * pivmin;
+  double* lam = lam_out + (long long)blockIdx.x * (TDB_RCAP + 2);
+  for (int t = threadIdx.x; t <= K; t += blockDim.x) {
+    double lt = 0.0;
+    if (t < n) {
+      const int idx = n - 1 - t;           // ascending index of the t-th largest
+      double l = gl, h = gu;
+      for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (l + h);
+        if (h - l <= 2.0 * eps * fmax(fabs(l), fabs(h)) + pivmin || mid == l || mid == h) break;
+        if (sturm_count2(d, e2, n, mid, pivmin) > idx) h = mid;
+        else l = mid;
+      }
+      lt = 0.5 * (l + h);
+    }
+    lam[t] = lt;
+    a.sig[t] = t < n ? sqrt(fmax(lt, 0.0)) : 0.0;
+  }
+  if (threadIdx.x == 0) lam[TDB_RCAP + 1] = tn;
+}
+
+// Inverse iteration for the K leading eigenvectors, all at once: one block per mode.
+// Vector j is shifted by its eigenvalue (shifts inside a cluster kept eps3 apart);
+// lane j of the first wave factors T - shift_j I and solves with it (partial
+// pivoting); after every solve round the whole block orthonormalises the vectors in
+// index order, each against the earlier members of its cluster (a cluster starts where
+// the gap to the previous eigenvalue exceeds 1e-3 of the matrix scale), so every
+// vector keeps the direction of its own eigenvalue. Vectors live interleaved
+// (entry i of vector j at i*64 + j) in a global workspace, as do the LU factors.
+__global__ void __launch_bounds__(256) k_eig_vectors(EigBatch batch, const double* lam_in, double* scratch) {
+  const EigArgs a = batch.m[blockIdx.x];
+  const int n = a.Nn, K = a.k;
+  const EigWs w = eig_ws(a);
+  const double* lam = lam_in + (long long)blockIdx.x * (TDB_RCAP + 2);
+  const double tn = lam[TDB_RCAP + 1];
+  double* xb = scratch + (long long)blockIdx.x * NE * 64 * 5;
+  double* dd = xb + NE * 64;
+  double* dl = dd + NE * 64;
+  double* du = dl + NE * 64;
+  double* du2 = du + NE * 64;
+  __shared__ double sh[TDB_RCAP], part[4][TDB_RCAP], red[16], dots[TDB_RCAP];
+  __shared__ int cend[TDB_RCAP];
+  __shared__ unsigned long long pivbits[NE];   // bit j: row swap of vector j at step i
+  const int tid = threadIdx.x;
+  const double eps = 2.220446049250313e-16;
+  double me = 0.0;
+  for (int i = tid; i + 1 < n; i += blockDim.x) me = fmax(me, w.e[i] * w.e[i]);
+  me = block_max(me, red);
+  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, me);
+  const double ortol = 1e-3 * tn;
+  const double eps3 = 10.0 * eps * tn;
+  if (tid == 0) {
+    double lam_prev = 0.0;
+    int cs = 0;
+    for (int j = 0; j < K; ++j) {
+      double lj = lam[j];
+      if (j == 0 || lam[j - 1] - lj > ortol) {
+        for (int q = cs; q < j; ++q) cend[q] = j;
+        cs = j;
+      } else if (lam_prev - lj < eps3) {
+        lj = lam_prev - eps3;   // keep shifts distinct in a cluster
+      }
+      lam_prev = lj;
+      sh[j] = lj;
+    }
+    for (int q = cs; q < K; ++q) cend[q] = K;
+  }
+  for (int i = tid; i < n; i += blockDim.x) pivbits[i] = 0ull;
+  __syncthreads();
+  const double ptiny = eps * tn + pivmin;
+  // factor and start vector: lane j of the first wave
+  if (tid < K) {
+    const int j = tid;
+    const double lj = sh[j];
+    for (int i = 0; i < n; ++i) {
+      dd[i * 64 + j] = w.d[i] - lj;
+      dl[i * 64 + j] = (i + 1 < n) ? w.e[i] : 0.0;
+      du[i * 64 + j] = (i + 1 < n) ? w.e[i] : 0.0;
+      du2[i * 64 + j] = 0.0;
+      xb[i * 64 + j] = hash_unit2((unsigned)i, (unsigned)j + 1u);
+    }
+    for (int i = 0; i + 1 < n; ++i) {
+      double di = dd[i * 64 + j];
+      const double li = dl[i * 64 + j];
+      if (fabs(di) >= fabs(li)) {
+        if (di == 0.0) { di = ptiny; dd[i * 64 + j] = di; }
+        const double f = li / di;
+        dl[i * 64 + j] = f;
+        dd[(i + 1) * 64 + j] -= f * du[i * 64 + j];
+      } else {
+        atomicOr(&pivbits[i], 1ull << j);
+        const double f = di / li;
+        const double dnext = dd[(i + 1) * 64 + j];
+        dd[i * 64 + j] = li;
+        dl[i * 64 + j] = f;
+        const double tmp = du[i * 64 + j];
+        du[i * 64 + j] = dnext;
+        dd[(i + 1) * 64 + j] = tmp - f * dnext;
+        if (i + 2 < n) {
+          du2[i * 64 + j] = du[(i + 1) * 64 + j];
+          du[(i + 1) * 64 + j] = -f * du[(i + 1) * 64 + j];
+        }
+      }
+    }
+    if (dd[(n - 1) * 64 + j] == 0.0) dd[(n - 1) * 64 + j] = ptiny;
+  }
+  __syncthreads();
+  const int qs = tid & 63, ig = tid >> 6;   // (vector slot, row group) of the block-wide passes
+  for (int it = 0; it < 3; ++it) {
+    if (tid < K) {
+      const int j = tid;
+      const unsigned long long bit = 1ull << j;
+      for (int i = 0; i + 1 < n; ++i) {
+        if (!(pivbits[i] & bit)) {
+          xb[(i + 1) * 64 + j] -= dl[i * 64 + j] * xb[i * 64 + j];
+        } else {
+          const double tmp = xb[i * 64 + j];
+          xb[i * 64 + j] = xb[(i + 1) * 64 + j];
+          xb[(i + 1) * 64 + j] = tmp - dl[i * 64 + j] * xb[i * 64 + j];
+        }
+      }
+      xb[(n - 1) * 64 + j] /= dd[(n - 1) * 64 + j];
+      if (n >= 2)
+        xb[(n - 2) * 64 + j] = (xb[(n - 2) * 64 + j] - du[(n - 2) * 64 + j] * xb[(n - 1) * 64 + j]) /
+                               dd[(n - 2) * 64 + j];
+      for (int i = n - 3; i >= 0; --i)
+        xb[i * 64 + j] = (xb[i * 64 + j] - du[i * 64 + j] * xb[(i + 1) * 64 + j] -
+                          du2[i * 64 + j] * xb[(i + 2) * 64 + j]) / dd[i * 64 + j];
+      // scale to unit max-norm (avoids overflow in the dot products)
+      double mx = 0.0;
+      for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(xb[i * 64 + j]));
+      const double sc = mx > 0.0 ? 1.0 / mx : 1.0;
+      for (int i = 0; i < n; ++i) xb[i * 64 + j] *= sc;
+    }
+    __syncthreads();
+    // orthonormalise in index order within clusters
+    for (int j = 0; j < K; ++j) {
+      double nr = 0.0;
+      for (int i = tid; i < n; i += blockDim.x) nr += xb[i * 64 + j] * xb[i * 64 + j];
+      nr = block_sum(nr, red);
+      const double inv = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
+      for (int i = tid; i < n; i += blockDim.x) xb[i * 64 + j] *= inv;
+      __syncthreads();
+      const int ce = cend[j];
+      if (ce <= j + 1) continue;
+      const int q = j + 1 + qs;
+      double pd = 0.0;
+      if (q < ce)
+        for (int i = ig; i < n; i += 4) pd += xb[i * 64 + q] * xb[i * 64 + j];
+      part[ig][qs] = pd;
+      __syncthreads();
+      if (tid < 64) dots[tid] = (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
+      __syncthreads();
+      if (q < ce) {
+        const double dq = dots[qs];
+        for (int i = ig; i < n; i += 4) xb[i * 64 + q] -= dq * xb[i * 64 + j];
+      }
+      __syncthreads();
+    }
+  }
+  // out to the column-major eigenvector block
+  for (long long t = tid; t < (long long)n * K; t += blockDim.x) {
+    const int j = (int)(t / n), i = (int)(t - (long long)j * n);
+    w.X[t] = xb[i * 64 + j];
+  }
+}
+
+// Back-transformation x <- H_0 H_1 ... H_{n-3} x and the sign convention; grid (mode,
+// vector), one wave per vector.
+__global__ void __launch_bounds__(64) k_eig_back(EigBatch batch) {
+  const EigArgs a = batch.m[blockIdx.x];
+  const int n = a.Nn, K = a.k;
+  const int j = blockIdx.y;
+  if (j >= K) return;
+  const EigWs w = eig_ws(a);
+  const int lane = threadIdx.x;
+  double* xj = w.X + (long long)j * n;
+  const double* G = a.G;
+  for (int k = n - 3; k >= 0; --k) {
+    const double bk = w.beta[k];
+    if (bk == 0.0) continue;
+    const int m = n - k - 1;
+    const double* vk = G + (long long)k * n + k + 1;
+    double s = 0.0;
+    for (int i = lane; i < m; i += 64) s += vk[i] * xj[k + 1 + i];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    s *= bk;
+    for (int i = lane; i < m; i += 64) xj[k + 1 + i] -= s * vk[i];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  }
+  double best = -1.0;
+  int bi = 0;
+  for (int i = lane; i < n; i += 64) {
+    const double av = fabs(xj[i]);
+    if (av > best) { best = av; bi = i; }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_xor(best, off, 64);
+    const int oi = __shfl_xor(bi, off, 64);
+    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  }
+  const double sg = xj[bi] < 0.0 ? -1.0 : 1.0;
+  for (int i = lane; i < n; i += 64) {
+    const double q = sg * xj[i];
+    const double sw = sqrt(a.wn[i]);
+    a.Umax[(long long)i * a.ldu + j] = q / sw;
+    a.Bmax[(long long)i * K + j] = q * sw;
+  }
+}
+
+hipError_t launch_sym_eig(const EigBatch& b, double* lam_scratch, double* vec_scratch, hipStream_t s) {
+  int nmax = 0, kmax = 0;
+  for (int i = 0; i < b.count; ++i) {
+    if (b.m[i].Nn > TDB_NEIG || b.m[i].k > TDB_RCAP || b.m[i].Nn < 1) return hipErrorInvalidValue;
+    nmax = b.m[i].Nn > nmax ? b.m[i].Nn : nmax;
+    kmax = b.m[i].k > kmax ? b.m[i].k : kmax;
+  }
+  // enough workgroups that each wave owns a row or two of the largest trailing block
+  const int nblk = nmax >= 512 ? 64 : nmax >= 128 ? 32 : 8;
+  for (int k = 0; k + 2 < nmax; ++k) {
+    hipLaunchKernelGGL(k_tri_step, dim3(nblk, b.count), dim3(256), 0, s, b, k);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_tri_final, dim3(b.count), dim3(64), 0, s, b);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_eig_values, dim3(b.count), dim3(128), 0, s, b, lam_scratch);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_eig_vectors, dim3(b.count), dim3(256), 0, s, b, lam_scratch, vec_scratch);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_eig_back, dim3(b.count, kmax), dim3(64), 0, s, b);
+  return hipGetLastError();
+}
+
+}  // namespace tdb

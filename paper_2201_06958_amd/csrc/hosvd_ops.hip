@@ -122,271 +122,6 @@ hipError_t launch_gram_reduce(const double* partials, double* G, const HosvdMode
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- symmetric eigensolver
-#define NE TDB_NEIG
-
-__device__ __forceinline__ double hash_unit(unsigned a, unsigned b) {
-  unsigned x = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u);
-  x ^= x >> 16; x *= 0x7FEB352Du; x ^= x >> 15; x *= 0x846CA68Bu; x ^= x >> 16;
-  return (double)x * (2.0 / 4294967296.0) - 1.0;
-}
-
-// Sturm count: number of eigenvalues of the tridiagonal (d, e2 = e^2) below x.
-__device__ int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
-  int c = 0;
-  double q = d[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  if (q < 0.0) ++c;
-  for (int i = 1; i < n; ++i) {
-    q = d[i] - x - e2[i - 1] / q;
-    if (fabs(q) < pivmin) q = -pivmin;
-    if (q < 0.0) ++c;
-  }
-  return c;
-}
-
-__global__ void __launch_bounds__(256) k_sym_eig(EigBatch batch) {
-  const EigArgs a = batch.m[blockIdx.x];
-  __shared__ double d[NE], e[NE], e2[NE], beta[NE], v[NE], pv[NE];
-  __shared__ double lu_dl[NE], lu_dd[NE], lu_du[NE], lu_du2[NE], xs[NE];
-  __shared__ unsigned char ipiv[NE];
-  __shared__ double lam[TDB_RCAP + 1];
-  __shared__ double red[16];
-  const int n = a.Nn, K = a.k;
-  double* G = a.G;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nwav = blockDim.x >> 6;
-
-  // ---- 1. Householder reduction to tridiagonal form; reflector k is stored in row k.
-  for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1;
-    double ss = 0.0;
-    for (int i = tid; i < m; i += blockDim.x) {
-      const double x = G[(long long)(k + 1 + i) * n + k];
-      v[i] = x;
-      ss += x * x;
-    }
-    ss = block_sum(ss, red);
-    const double x0 = v[0];
-    double bk = 0.0;
-    __syncthreads();
-    if (ss > 0.0) {
-      const double xn = sqrt(ss);
-      const double alpha = x0 > 0.0 ? -xn : xn;
-      const double v0 = x0 - alpha;
-      const double vtv = ss - x0 * x0 + v0 * v0;
-      bk = 2.0 / vtv;
-      if (tid == 0) { v[0] = v0; e[k] = alpha; }
-    } else if (tid == 0) {
-      e[k] = x0;
-    }
-    if (tid == 0) { d[k] = G[(long long)k * n + k]; beta[k] = bk; }
-    __syncthreads();
-    for (int i = tid; i < m; i += blockDim.x) G[(long long)k * n + k + 1 + i] = v[i];
-    if (bk == 0.0) { __syncthreads(); continue; }
-    // pv = bk * A_sub v, one wave per row
-    for (int i = wid; i < m; i += nwav) {
-      const double* row = G + (long long)(k + 1 + i) * n + (k + 1);
-      double s = 0.0;
-      for (int j = lane; j < m; j += 64) s += row[j] * v[j];
-      s = warp_sum(s);
-      if (lane == 0) pv[i] = bk * s;
-    }
-    __syncthreads();
-    double pvv = 0.0;
-    for (int i = tid; i < m; i += blockDim.x) pvv += pv[i] * v[i];
-    pvv = block_sum(pvv, red);
-    const double Kc = 0.5 * bk * pvv;
-    for (int i = tid; i < m; i += blockDim.x) pv[i] -= Kc * v[i];     // w
-    __syncthreads();
-    for (long long t = tid; t < (long long)m * m; t += blockDim.x) {
-      const int i = (int)(t / m), j = (int)(t - (long long)i * m);
-      G[(long long)(k + 1 + i) * n + (k + 1 + j)] -= v[i] * pv[j] + pv[i] * v[j];
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    if (n >= 2) {
-      d[n - 2] = G[(long long)(n - 2) * n + (n - 2)];
-      e[n - 2] = G[(long long)(n - 1) * n + (n - 2)];
-      beta[n - 2] = 0.0;
-    }
-    d[n - 1] = G[(long long)(n - 1) * n + (n - 1)];
-    e[n - 1] = 0.0;
-  }
-  __syncthreads();
-  for (int i = tid; i < n; i += blockDim.x) e2[i] = e[i] * e[i];
-  __syncthreads();
-
-  // ---- 2. leading K+1 eigenvalues by bisection on Sturm counts
-  double tn = 0.0, gl = 0.0, gu = 0.0, emax2 = 0.0;
-  {
-    double lo = 1e300, hi = -1e300, mx = 0.0, me = 0.0;
-    for (int i = tid; i < n; i += blockDim.x) {
-      const double off = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
-      lo = fmin(lo, d[i] - off);
-      hi = fmax(hi, d[i] + off);
-      mx = fmax(mx, fabs(d[i]) + off);
-      if (i + 1 < n) me = fmax(me, e2[i]);
-    }
-    gl = -block_max(-lo, red);
-    gu = block_max(hi, red);
-    tn = block_max(mx, red);
-    emax2 = block_max(me, red);
-  }
-  const double eps = 2.220446049250313e-16;
-  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
-  gl -= 4.0 * eps * tn + 2.0 * pivmin;
-  gu += 4.0 * eps * tn + 2.0 * pivmin;
-  for (int t = tid; t <= K; t += blockDim.x) {
-    if (t >= n) { lam[t] = 0.0; continue; }
-    const int idx = n - 1 - t;           // ascending index of the t-th largest
-    double lo = gl, hi = gu;
-    for (int it = 0; it < 200; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin || mid == lo || mid == hi) break;
-      if (sturm_count(d, e2, n, mid, pivmin) > idx) hi = mid;
-      else lo = mid;
-    }
-    lam[t] = 0.5 * (lo + hi);
-  }
-  __syncthreads();
-  for (int t = tid; t <= K; t += blockDim.x) a.sig[t] = t < n ? sqrt(fmax(lam[t], 0.0)) : 0.0;
-
-  // ---- 3. inverse iteration for the K leading eigenvectors (wave 0)
-  double* X = a.work;                  // column-major n x K
-  const double ortol = 1e-3 * tn;
-  const double eps3 = 10.0 * eps * tn;
-  if (wid == 0) {
-    int cstart = 0;
-    double lam_prev = 0.0;
-    for (int j = 0; j < K; ++j) {
-      double lj = lam[j];
-      if (j > 0) {
-        if (lam[j - 1] - lj > ortol) cstart = j;
-        if (lam_prev - lj < eps3) lj = lam_prev - eps3;   // keep shifts distinct in a cluster
-      }
-      lam_prev = lj;
-      for (int i = lane; i < n; i += 64) xs[i] = hash_unit((unsigned)i, (unsigned)j + 1u);
-      if (lane == 0) {
-        // LU with partial pivoting of T - lj I
-        for (int i = 0; i < n; ++i) {
-          lu_dd[i] = d[i] - lj;
-          lu_dl[i] = (i + 1 < n) ? e[i] : 0.0;
-          lu_du[i] = (i + 1 < n) ? e[i] : 0.0;
-          lu_du2[i] = 0.0;
-        }
-        const double ptiny = eps * tn + pivmin;
-        for (int i = 0; i + 1 < n; ++i) {
-          if (fabs(lu_dd[i]) >= fabs(lu_dl[i])) {
-            ipiv[i] = 0;
-            if (lu_dd[i] == 0.0) lu_dd[i] = ptiny;
-            const double f = lu_dl[i] / lu_dd[i];
-            lu_dl[i] = f;
-            lu_dd[i + 1] -= f * lu_du[i];
-          } else {
-            ipiv[i] = 1;
-            const double f = lu_dd[i] / lu_dl[i];
-            lu_dd[i] = lu_dl[i];
-            lu_dl[i] = f;
-            const double tmp = lu_du[i];
-            lu_du[i] = lu_dd[i + 1];
-            lu_dd[i + 1] = tmp - f * lu_dd[i + 1];
-            if (i + 2 < n) {
-              lu_du2[i] = lu_du[i + 1];
-              lu_du[i + 1] = -f * lu_du[i + 1];
-            }
-          }
-        }
-        if (lu_dd[n - 1] == 0.0) lu_dd[n - 1] = ptiny;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-      for (int it = 0; it < 3; ++it) {
-        if (lane == 0) {
-          for (int i = 0; i + 1 < n; ++i) {
-            if (ipiv[i] == 0) {
-              xs[i + 1] -= lu_dl[i] * xs[i];
-            } else {
-              const double tmp = xs[i];
-              xs[i] = xs[i + 1];
-              xs[i + 1] = tmp - lu_dl[i] * xs[i];
-            }
-          }
-          xs[n - 1] /= lu_dd[n - 1];
-          if (n >= 2) xs[n - 2] = (xs[n - 2] - lu_du[n - 2] * xs[n - 1]) / lu_dd[n - 2];
-          for (int i = n - 3; i >= 0; --i)
-            xs[i] = (xs[i] - lu_du[i] * xs[i + 1] - lu_du2[i] * xs[i + 2]) / lu_dd[i];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        // scale to unit max-norm first (avoids overflow in the dot products)
-        double mx = 0.0;
-        for (int i = lane; i < n; i += 64) mx = fmax(mx, fabs(xs[i]));
-        for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
-        const double sc = mx > 0.0 ? 1.0 / mx : 1.0;
-        for (int i = lane; i < n; i += 64) xs[i] *= sc;
-        for (int q = cstart; q < j; ++q) {
-          const double* xq = X + (long long)q * n;
-          double dt = 0.0;
-          for (int i = lane; i < n; i += 64) dt += xs[i] * xq[i];
-          for (int off = 32; off > 0; off >>= 1) dt += __shfl_xor(dt, off, 64);
-          for (int i = lane; i < n; i += 64) xs[i] -= dt * xq[i];
-        }
-        double nr = 0.0;
-        for (int i = lane; i < n; i += 64) nr += xs[i] * xs[i];
-        for (int off = 32; off > 0; off >>= 1) nr += __shfl_xor(nr, off, 64);
-        const double inv = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
-        for (int i = lane; i < n; i += 64) xs[i] *= inv;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-      }
-      double* xj = X + (long long)j * n;
-      for (int i = lane; i < n; i += 64) xj[i] = xs[i];
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    }
-  }
-  __syncthreads();
-
-  // ---- 4. back-transformation x <- H_0 H_1 ... H_{n-3} x, one wave per vector
-  for (int j = wid; j < K; j += nwav) {
-    double* xj = X + (long long)j * n;
-    for (int k = n - 3; k >= 0; --k) {
-      const double bk = beta[k];
-      if (bk == 0.0) continue;
-      const int m = n - k - 1;
-      const double* vk = G + (long long)k * n + k + 1;
-      double s = 0.0;
-      for (int i = lane; i < m; i += 64) s += vk[i] * xj[k + 1 + i];
-      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-      s *= bk;
-      for (int i = lane; i < m; i += 64) xj[k + 1 + i] -= s * vk[i];
-    }
-    // sign convention: largest-magnitude entry positive (lowest index on a tie)
-    double best = -1.0;
-    int bi = 0;
-    for (int i = lane; i < n; i += 64) {
-      const double av = fabs(xj[i]);
-      if (av > best) { best = av; bi = i; }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ob = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
-    const double sg = xj[bi] < 0.0 ? -1.0 : 1.0;
-    for (int i = lane; i < n; i += 64) {
-      const double q = sg * xj[i];
-      const double sw = sqrt(a.wn[i]);
-      a.Umax[(long long)i * a.ldu + j] = q / sw;
-      a.Bmax[(long long)i * K + j] = q * sw;
-    }
-  }
-}
-
-hipError_t launch_sym_eig(const EigBatch& b, hipStream_t s) {
-  for (int i = 0; i < b.count; ++i)
-    if (b.m[i].Nn > TDB_NEIG || b.m[i].k > TDB_RCAP || b.m[i].Nn < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_sym_eig, dim3(b.count), dim3(256), 0, s, b);
-  return hipGetLastError();
-}
-
 // ---------------------------------------------------------------- rank selection
 struct SelShared {
   int r[TDB_P];

@@ -60,6 +60,8 @@ struct tdb_ctx {
   double *G[TDB_P] = {}, *gpart = nullptr, *eigw[TDB_P] = {}, *sig[TDB_P] = {};
   double *Umax[TDB_P] = {}, *Bmax[TDB_P] = {}, *Cmax = nullptr, *hsA = nullptr, *hsB = nullptr;
   double *wa[TDB_P] = {}, *wb[TDB_P] = {}, *nu2h = nullptr;
+  double* eig_lam = nullptr;     // eigenvalues of the mode Grams (per mode, TDB_RCAP + 2)
+  double* eig_vec = nullptr;     // inverse-iteration workspace (per mode, TDB_NEIG x 64 x 5)
   double *Psi[TDB_P] = {};
   // snapshots
   const void* Vprev = nullptr;
@@ -359,7 +361,7 @@ tdb_status setup(tdb_ctx* h, const tdb_config* cfg) {
   size_t gpart = 0;
   for (int n = 0; n < h->p; ++n) {
     TRY(dallocT(h, &h->G[n], (size_t)h->N[n] * h->N[n]));
-    TRY(dallocT(h, &h->eigw[n], (size_t)h->N[n] * (h->caps[n] + 4)));
+    TRY(dallocT(h, &h->eigw[n], (size_t)h->N[n] * (h->caps[n] + 6)));
     TRY(dallocT(h, &h->sig[n], (size_t)h->caps[n] + 1));
     TRY(dallocT(h, &h->Umax[n], (size_t)h->N[n] * h->ldU[n]));
     TRY(dallocT(h, &h->Bmax[n], (size_t)h->N[n] * h->caps[n]));
@@ -373,6 +375,13 @@ tdb_status setup(tdb_ctx* h, const tdb_config* cfg) {
   TRY(dallocT(h, &h->hsA, (size_t)h->S));
   TRY(dallocT(h, &h->hsB, (size_t)h->S));
   TRY(dallocT(h, &h->nu2h, 1));
+  TRY(dallocT(h, &h->eig_lam, (size_t)TDB_P * (TDB_RCAP + 2)));
+  {
+    long long nmax = 1;
+    for (int n = 0; n < h->p; ++n) nmax = std::max(nmax, h->N[n]);
+    (void)nmax;
+    TRY(dallocT(h, &h->eig_vec, (size_t)TDB_P * TDB_NEIG * 64 * 5));
+  }
   if (cfg->snapshot_mode == TDB_COPY) TRY(dalloc(h, &h->Vcopy, (size_t)h->S * h->delt));
 
   // ---- weights and their mode-wise products
@@ -635,7 +644,7 @@ tdb_status hosvd_select(tdb_ctx* h, const TD* V, int mode, hipStream_t s) {
     e.wn = h->w[n];
   }
   HIPCHK(launch_trace(h->G[0], h->N[0], h->nu2h, s));
-  HIPCHK(launch_sym_eig(eb, s));
+  HIPCHK(launch_sym_eig(eb, h->eig_lam, h->eig_vec, s));
   // Cmax = V x_n (W_n Umax_n)^T over all modes, most reducing mode first
   std::vector<int> order(p);
   for (int k = 0; k < p; ++k) order[k] = k;

@@ -101,7 +101,7 @@ hipError_t launch_gram_reduce(const double* partials, double* G, const HosvdMode
 struct EigArgs {
   int Nn, k, ldu;
   double* G;
-  double* work;          // >= Nn * (k + 4) doubles
+  double* work;          // >= Nn * (k + 6) doubles
   double* sig;           // k + 1
   double* Umax;
   double* Bmax;
@@ -111,7 +111,9 @@ struct EigBatch {
   int count;
   EigArgs m[TDB_P];
 };
-hipError_t launch_sym_eig(const EigBatch& b, hipStream_t s);
+// lam_scratch: count x (TDB_RCAP + 2) doubles; vec_scratch: count x TDB_NEIG x 64 x 5
+// doubles of device workspace.
+hipError_t launch_sym_eig(const EigBatch& b, double* lam_scratch, double* vec_scratch, hipStream_t s);
 
 struct SelectArgs {
   int p, mode;           // DEC_*

@@ -255,3 +255,39 @@ def test_ensemble_member_fp32_against_oracle(path):
     _say(f"  ensemble member: ranks {r}, reconstruction rel diff {rel:.3e}")
     assert rel < 1e-6
     g.close()
+
+
+@pytest.mark.parametrize("dims,caps", [((300, 40, 6), (40, 24, 6)), ((512, 32, 4), (64, 32, 4))])
+def test_hosvd_init_large_mode_matches_oracle(dims, caps):
+    """Device HOSVD with a long first mode (the multi-workgroup tridiagonal reduction,
+    bisection and inverse iteration on a 300 x 300 and a 512 x 512 Gram) against the
+    oracle's LAPACK eigendecomposition: projectors of the chosen ranks, core singular
+    values and eps0."""
+    _say(f"case hosvd-init large mode {dims}")
+    rng = np.random.default_rng(11)
+    w = []
+    for n in dims:
+        x = rng.uniform(0.5, 1.5, size=n)
+        w.append(x / x.sum())
+    # a decaying spectrum in every mode
+    base = np.zeros(dims)
+    for q in range(30):
+        a = [rng.normal(size=n) for n in dims]
+        base += 0.7 ** q * np.einsum("i,j,k->ijk", *a)
+    V0 = base + 1e-6 * rng.normal(size=dims)
+    cfg = O.OracleConfig(dims=dims, weights=w, dt=0.01, rank_max=caps, rank_init=None, adaptive=True, eps_th=1e-3)
+    orc = O.OracleTDB(cfg).init(V0)
+    from paper_2201_06958_amd import Compressor
+    g = Compressor(dims, 0.01, rank_max=caps, weights=w, data_dtype="f64", precision="f64", adaptive=True,
+                   eps_th=1e-3)
+    g.init(_dev(V0))
+    r, C, U = g.get_core_and_bases()
+    _say(f"  ranks gpu {r} oracle {orc.ranks}")
+    assert r == orc.ranks
+    for n in range(3):
+        Pg = U[n] @ U[n].T * w[n][None, :]
+        Po = orc.U[n] @ orc.U[n].T * w[n][None, :]
+        assert np.abs(Pg - Po).max() < 1e-9, n
+    assert _rel(O.reconstruct(C, U), O.reconstruct(orc.C, orc.U)) < 1e-9
+    assert g.stats()["eps"] == pytest.approx(orc.records[0].eps, rel=1e-6)
+    g.close()
