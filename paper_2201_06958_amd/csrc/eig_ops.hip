@@ -167,9 +167,10 @@ __device__ __forceinline__ double hash_unit2(unsigned a, unsigned b) {
   return (double)x * (2.0 / 4294967296.0) - 1.0;
 }
 
-// One block per mode: the K+1 leading eigenvalues by bisection (one thread each), the
-// singular values sqrt(max(lambda, 0)), and the Gershgorin scale.
-__global__ void __launch_bounds__(128) k_eig_values(EigBatch batch, double* lam_out) {
+// One block per mode: the K+1 leading eigenvalues by multisection on Sturm counts
+// (8 lanes per eigenvalue evaluate 8 interior points of its interval, which shrinks
+// 9-fold per round), the singular values sqrt(max(lambda, 0)), and the Gershgorin scale.
+__global__ void __launch_bounds__(576) k_eig_values(EigBatch batch, double* lam_out) {
   const EigArgs a = batch.m[blockIdx.x];
   const int n = a.Nn, K = a.k;
   const EigWs w = eig_ws(a);
@@ -196,19 +197,31 @@ __global__ void __launch_bounds__(128) k_eig_values(EigBatch batch, double* lam_
   gl -= 4.0 * eps * tn + 2.0 * pivmin;
   gu += 4.0 * eps * tn + 2.0 * pivmin;
   double* lam = lam_out + (long long)blockIdx.x * (TDB_RCAP + 2);
-  for (int t = threadIdx.x; t <= K; t += blockDim.x) {
-    double lt = 0.0;
-    if (t < n) {
-      const int idx = n - 1 - t;           // ascending index of the t-th largest
-      double l = gl, h = gu;
-      for (int it = 0; it < 200; ++it) {
-        const double mid = 0.5 * (l + h);
-        if (h - l <= 2.0 * eps * fmax(fabs(l), fabs(h)) + pivmin || mid == l || mid == h) break;
-        if (sturm_count2(d, e2, n, mid, pivmin) > idx) h = mid;
-        else l = mid;
-      }
-      lt = 0.5 * (l + h);
+  const int t = threadIdx.x >> 3, sub = threadIdx.x & 7;   // eigenvalue slot, lane in the group
+  double l = gl, h = gu;
+  const bool live = t <= K && t < n;
+  const int idx = n - 1 - t;                                  // ascending index of the t-th largest
+  for (int it = 0; it < 80; ++it) {
+    bool done = !live || h - l <= 2.0 * eps * fmax(fabs(l), fabs(h)) + pivmin;
+    // the whole wave leaves together once every group in it has converged
+    if (__all(done)) break;
+    const double x = l + (double)(sub + 1) * ((h - l) / 9.0);
+    const int c = live && !done ? sturm_count2(d, e2, n, x, pivmin) : 0;
+    // first point whose count exceeds idx bounds the eigenvalue from above
+    const unsigned long long above = __ballot(c > idx);
+    const int base = (threadIdx.x & 63) & ~7;
+    const unsigned grp = (unsigned)((above >> base) & 0xffull);
+    if (live && !done) {
+      const int first = grp ? __builtin_ctz(grp) : 8;     // points 0..7; 8: above all
+      const double nl = first == 0 ? l : l + (double)first * ((h - l) / 9.0);
+      const double nh = first == 8 ? h : l + (double)(first + 1) * ((h - l) / 9.0);
+      if (nl == l && nh == h) { h = l; }                  // no progress in floating point
+      l = nl;
+      h = nh;
     }
+  }
+  if (sub == 0 && t <= K) {
+    const double lt = t < n ? 0.5 * (l + h) : 0.0;
     lam[t] = lt;
     a.sig[t] = t < n ? sqrt(fmax(lt, 0.0)) : 0.0;
   }
@@ -234,7 +247,7 @@ __global__ void __launch_bounds__(256) k_eig_vectors(EigBatch batch, const doubl
   double* dl = dd + NE * 64;
   double* du = dl + NE * 64;
   double* du2 = du + NE * 64;
-  __shared__ double sh[TDB_RCAP], part[4][TDB_RCAP], red[16], dots[TDB_RCAP];
+  __shared__ double sh[TDB_RCAP], part[4][TDB_RCAP], red[16], dots[TDB_RCAP], xj[NE];
   __shared__ int cend[TDB_RCAP];
   __shared__ unsigned long long pivbits[NE];   // bit j: row swap of vector j at step i
   const int tid = threadIdx.x;
@@ -275,29 +288,37 @@ __global__ void __launch_bounds__(256) k_eig_vectors(EigBatch batch, const doubl
       du2[i * 64 + j] = 0.0;
       xb[i * 64 + j] = hash_unit2((unsigned)i, (unsigned)j + 1u);
     }
+    // the running pivot row (cd, cu) and the next row's original entries are carried in
+    // registers, so each step's loads do not wait for the previous step's stores
+    double cd = dd[j], cu = du[j];
     for (int i = 0; i + 1 < n; ++i) {
-      double di = dd[i * 64 + j];
       const double li = dl[i * 64 + j];
-      if (fabs(di) >= fabs(li)) {
-        if (di == 0.0) { di = ptiny; dd[i * 64 + j] = di; }
-        const double f = li / di;
+      const double dn = dd[(i + 1) * 64 + j];
+      const double un = (i + 2 < n) ? du[(i + 1) * 64 + j] : 0.0;
+      if (fabs(cd) >= fabs(li)) {
+        if (cd == 0.0) cd = ptiny;
+        const double f = li / cd;
+        dd[i * 64 + j] = cd;
         dl[i * 64 + j] = f;
-        dd[(i + 1) * 64 + j] -= f * du[i * 64 + j];
+        du[i * 64 + j] = cu;
+        cd = dn - f * cu;
+        cu = un;
       } else {
         atomicOr(&pivbits[i], 1ull << j);
-        const double f = di / li;
-        const double dnext = dd[(i + 1) * 64 + j];
+        const double f = cd / li;
         dd[i * 64 + j] = li;
         dl[i * 64 + j] = f;
-        const double tmp = du[i * 64 + j];
-        du[i * 64 + j] = dnext;
-        dd[(i + 1) * 64 + j] = tmp - f * dnext;
+        du[i * 64 + j] = dn;
+        cd = cu - f * dn;
         if (i + 2 < n) {
-          du2[i * 64 + j] = du[(i + 1) * 64 + j];
-          du[(i + 1) * 64 + j] = -f * du[(i + 1) * 64 + j];
+          du2[i * 64 + j] = un;
+          cu = -f * un;
+        } else {
+          cu = 0.0;
         }
       }
     }
+    dd[(n - 1) * 64 + j] = cd;
     if (dd[(n - 1) * 64 + j] == 0.0) dd[(n - 1) * 64 + j] = ptiny;
   }
   __syncthreads();
@@ -306,22 +327,35 @@ __global__ void __launch_bounds__(256) k_eig_vectors(EigBatch batch, const doubl
     if (tid < K) {
       const int j = tid;
       const unsigned long long bit = 1ull << j;
+      // forward elimination with the row interchanges, the running entry in a register
+      double cur = xb[j];
       for (int i = 0; i + 1 < n; ++i) {
+        const double nx = xb[(i + 1) * 64 + j];
+        const double l = dl[i * 64 + j];
         if (!(pivbits[i] & bit)) {
-          xb[(i + 1) * 64 + j] -= dl[i * 64 + j] * xb[i * 64 + j];
+          xb[i * 64 + j] = cur;
+          cur = nx - l * cur;
         } else {
-          const double tmp = xb[i * 64 + j];
-          xb[i * 64 + j] = xb[(i + 1) * 64 + j];
-          xb[(i + 1) * 64 + j] = tmp - dl[i * 64 + j] * xb[i * 64 + j];
+          xb[i * 64 + j] = nx;
+          cur = cur - l * nx;
         }
       }
-      xb[(n - 1) * 64 + j] /= dd[(n - 1) * 64 + j];
-      if (n >= 2)
-        xb[(n - 2) * 64 + j] = (xb[(n - 2) * 64 + j] - du[(n - 2) * 64 + j] * xb[(n - 1) * 64 + j]) /
-                               dd[(n - 2) * 64 + j];
-      for (int i = n - 3; i >= 0; --i)
-        xb[i * 64 + j] = (xb[i * 64 + j] - du[i * 64 + j] * xb[(i + 1) * 64 + j] -
-                          du2[i * 64 + j] * xb[(i + 2) * 64 + j]) / dd[i * 64 + j];
+      // back substitution, the two later entries in registers
+      double x1 = cur / dd[(n - 1) * 64 + j];
+      xb[(n - 1) * 64 + j] = x1;
+      double x2 = 0.0;
+      if (n >= 2) {
+        const double x0 = (xb[(n - 2) * 64 + j] - du[(n - 2) * 64 + j] * x1) / dd[(n - 2) * 64 + j];
+        xb[(n - 2) * 64 + j] = x0;
+        x2 = x1;
+        x1 = x0;
+      }
+      for (int i = n - 3; i >= 0; --i) {
+        const double x0 = (xb[i * 64 + j] - du[i * 64 + j] * x1 - du2[i * 64 + j] * x2) / dd[i * 64 + j];
+        xb[i * 64 + j] = x0;
+        x2 = x1;
+        x1 = x0;
+      }
       // scale to unit max-norm (avoids overflow in the dot products)
       double mx = 0.0;
       for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(xb[i * 64 + j]));
@@ -329,27 +363,62 @@ __global__ void __launch_bounds__(256) k_eig_vectors(EigBatch batch, const doubl
       for (int i = 0; i < n; ++i) xb[i * 64 + j] *= sc;
     }
     __syncthreads();
-    // orthonormalise in index order within clusters
+    // orthonormalise in index order within clusters (vector j staged in LDS; each
+    // thread's rows are loaded in batches of 8 before any of them is updated)
     for (int j = 0; j < K; ++j) {
       double nr = 0.0;
-      for (int i = tid; i < n; i += blockDim.x) nr += xb[i * 64 + j] * xb[i * 64 + j];
+      for (int i = tid; i < n; i += blockDim.x) {
+        const double x = xb[i * 64 + j];
+        xj[i] = x;
+        nr += x * x;
+      }
       nr = block_sum(nr, red);
       const double inv = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
-      for (int i = tid; i < n; i += blockDim.x) xb[i * 64 + j] *= inv;
+      for (int i = tid; i < n; i += blockDim.x) {
+        const double x = xj[i] * inv;
+        xj[i] = x;
+        xb[i * 64 + j] = x;
+      }
       __syncthreads();
       const int ce = cend[j];
       if (ce <= j + 1) continue;
       const int q = j + 1 + qs;
+      const bool act = q < ce;
       double pd = 0.0;
-      if (q < ce)
-        for (int i = ig; i < n; i += 4) pd += xb[i * 64 + q] * xb[i * 64 + j];
+      if (act) {
+        for (int i0 = ig; i0 < n; i0 += 32) {
+          double v8[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int i = i0 + 4 * u;
+            v8[u] = i < n ? xb[i * 64 + q] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int i = i0 + 4 * u;
+            if (i < n) pd += v8[u] * xj[i];
+          }
+        }
+      }
       part[ig][qs] = pd;
       __syncthreads();
       if (tid < 64) dots[tid] = (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
       __syncthreads();
-      if (q < ce) {
+      if (act) {
         const double dq = dots[qs];
-        for (int i = ig; i < n; i += 4) xb[i * 64 + q] -= dq * xb[i * 64 + j];
+        for (int i0 = ig; i0 < n; i0 += 32) {
+          double v8[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int i = i0 + 4 * u;
+            v8[u] = i < n ? xb[i * 64 + q] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int i = i0 + 4 * u;
+            if (i < n) xb[i * 64 + q] = v8[u] - dq * xj[i];
+          }
+        }
       }
       __syncthreads();
     }
@@ -421,7 +490,7 @@ hipError_t launch_sym_eig(const EigBatch& b, double* lam_scratch, double* vec_sc
   hipLaunchKernelGGL(k_tri_final, dim3(b.count), dim3(64), 0, s, b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_eig_values, dim3(b.count), dim3(128), 0, s, b, lam_scratch);
+  hipLaunchKernelGGL(k_eig_values, dim3(b.count), dim3(576), 0, s, b, lam_scratch);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_eig_vectors, dim3(b.count), dim3(256), 0, s, b, lam_scratch, vec_scratch);

@@ -367,7 +367,7 @@ tdb_status setup(tdb_ctx* h, const tdb_config* cfg) {
     TRY(dallocT(h, &h->Bmax[n], (size_t)h->N[n] * h->caps[n]));
     const long long nt = (h->N[n] + 63) / 64;
     const long long K = h->S / h->N[n];
-    const long long nch = std::max<long long>(1, std::min<long long>(64, (K + 4095) / 4096));
+    const long long nch = std::max<long long>(1, std::min<long long>(64, (K + 511) / 512));
     gpart = std::max(gpart, (size_t)(nt * (nt + 1) / 2 * nch * 4096));
   }
   TRY(dallocT(h, &h->gpart, gpart));
@@ -627,7 +627,7 @@ tdb_status hosvd_select(tdb_ctx* h, const TD* V, int mode, hipStream_t s) {
     m.wb = h->wb[n];
     m.wn = h->w[n];
     const long long K = m.A * m.Bsz;
-    const int nch = (int)std::max<long long>(1, std::min<long long>(64, (K + 4095) / 4096));
+    const int nch = (int)std::max<long long>(1, std::min<long long>(64, (K + 511) / 512));
     long long kchunk = (K + nch - 1) / nch;
     kchunk = (kchunk + 15) / 16 * 16;
     HIPCHK(launch_gram_partials<TD>(V, m, h->gpart, kchunk, nch, s));
