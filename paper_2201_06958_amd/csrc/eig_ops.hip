@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(256) k_tri_step(EigBatch batch, int k) {
   const double bp = k > 0 ? w.beta[k - 1] : 0.0;
   const int mp = n - k;
   if (bp != 0.0) {
-    const double* pp = w.p[(k - 1) & 1];
+    const double* pp = ((k - 1) & 1) ? w.p[1] : w.p[0];
     double pvv = 0.0;
     for (int i = tid; i < mp; i += blockDim.x) {
       const double vi = G[(long long)(k - 1) * n + k + i];
@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(256) k_tri_step(EigBatch batch, int k) {
   }
   __syncthreads();
   // rows of this workgroup: k+1+i for i = blockIdx.x, blockIdx.x + nblk, ...; one wave per row
-  double* pk = w.p[k & 1];
+  double* pk = (k & 1) ? w.p[1] : w.p[0];
   for (int i = blockIdx.x + nblk * wid; i < m; i += nblk * 4) {
     double* row = G + (long long)(k + 1 + i) * n + (k + 1);
     double s = 0.0;
@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(64) k_tri_final(EigBatch batch) {
   double a00 = G[(long long)k * n + k], a10 = G[(long long)(k + 1) * n + k], a11 = G[(long long)(k + 1) * n + k + 1];
   const double bp = k > 0 ? w.beta[k - 1] : 0.0;
   if (bp != 0.0) {
-    const double* pp = w.p[(k - 1) & 1];
+    const double* pp = ((k - 1) & 1) ? w.p[1] : w.p[0];
     const double v0 = G[(long long)(k - 1) * n + k], v1 = G[(long long)(k - 1) * n + k + 1];
     const double Kc = 0.5 * bp * (pp[k] * v0 + pp[k + 1] * v1);
     const double w0 = pp[k] - Kc * v0, w1 = pp[k + 1] - Kc * v1;

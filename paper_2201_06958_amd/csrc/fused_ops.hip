@@ -50,15 +50,17 @@ __device__ __forceinline__ double sum_strided(const T* __restrict__ p, long long
 
 // Sums the per-tile partials in a fixed order (FP64) into H_n and C_dot, and applies
 // the Heun update to the core (stage 1: k = C_dot/dt, C* = C + dt k; stage 2:
-// C <- C + dt/2 (k + C_dot/dt)). Each output is summed by a group of L lanes (lane j
-// takes partials j, j + L, ...), then combined by a fixed butterfly, so the order of
-// the additions never depends on scheduling.
+// C <- C + dt/2 (k + C_dot/dt)). Each output is summed by L lanes of one wave (lane
+// group j takes partials j, j + L, ...), combined by a fixed butterfly, so the order of
+// the additions never depends on scheduling. A wave covers Q = 64/L consecutive
+// outputs: lane = j*Q + (output within the wave), so neighbouring lanes read
+// neighbouring partials of the same tile.
 template <typename T>
-__device__ __forceinline__ void freduce_body(const FReduceArgs& a, CtrlState* ctrl, int bx, int gx) {
-  if (a.stage == 2 && ctrl->numeric) return;
+__device__ __forceinline__ void freduce_body(const FReduceArgs& a, int stage, CtrlState* ctrl, int bx, int gx) {
+  if (stage == 2 && ctrl->numeric) return;
   // A singular core found while preparing this step (bit 4, set by k_fpost) belongs
   // to this step's first stage, like the failure of its pseudo-inverse would.
-  if (a.stage == 1 && bx == 0 && threadIdx.x == 0 && (ctrl->numeric & 4)) ctrl->numeric = 1;
+  if (stage == 1 && bx == 0 && threadIdx.x == 0 && (ctrl->numeric & 4)) ctrl->numeric = 1;
   const T* part = static_cast<const T*>(a.part);
   const long long nH1 = a.need_h1 ? (long long)a.N1 * a.r1 : 0;
   const long long nH2 = a.need_h2 ? (long long)a.N2 * a.r2 : 0;
@@ -79,8 +81,10 @@ __device__ __forceinline__ void freduce_body(const FReduceArgs& a, CtrlState* ct
     else if (t < e2) { kind = 1; L = L2; u = t - e1; }
     else if (t < e3) { kind = 2; L = L3; u = t - e2; }
     else { kind = 3; L = L3; u = t - e3; }
-    const long long q = u / L;
-    const int j = (int)(u - q * L);
+    const int Q = 64 / L;
+    const int lw = (int)(u & 63);
+    const long long q = (u >> 6) * Q + (lw % Q);
+    const int j = lw / Q;
     const long long nq = kind == 0 ? nH1 : kind == 1 ? nH2 : kind == 2 ? nH3 : nC;
     const bool valid = q < nq;
     double s = 0.0;
@@ -110,7 +114,7 @@ __device__ __forceinline__ void freduce_body(const FReduceArgs& a, CtrlState* ct
       const int cnt = (count - j + L - 1) / L;
       if (cnt > 0) s = sum_strided(base + (long long)j * stride, stride * L, cnt);
     }
-    for (int o = L >> 1; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    for (int o = L >> 1; o >= 1; o >>= 1) s += __shfl_xor(s, o * Q, 64);
     if (!valid || j != 0) continue;
     if (kind == 0) {
       a.H[0][q] = s;
@@ -120,7 +124,7 @@ __device__ __forceinline__ void freduce_body(const FReduceArgs& a, CtrlState* ct
       a.H[2][q] = s;
     } else {
       const double cd = s * inv_dt;
-      if (a.stage == 1) {
+      if (stage == 1) {
         a.kC[q] = cd;
         a.Cs[q] = a.C0[q] + a.dt * cd;
       } else {
@@ -133,7 +137,7 @@ __device__ __forceinline__ void freduce_body(const FReduceArgs& a, CtrlState* ct
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_freduce(FReduceArgs a, CtrlState* ctrl) {
-  freduce_body<T>(a, ctrl, blockIdx.x, gridDim.x);
+  freduce_body<T>(a, a.stage, ctrl, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------- prep helpers
@@ -264,14 +268,14 @@ __device__ void write_p(const double* Cl, const double* Gi, int rn, long long R,
 // Block n: M_n = U_n^T W_n F_(n) P_n = C_dot_(n) P_n, scaled by dt like the raw H_n
 // (one r_n x r_n matrix per mode, shared by every row of the finish).
 template <typename T>
-__device__ __forceinline__ void fmprep_body(const FFinishArgs& a, CtrlState* ctrl, int bx) {
+__device__ __forceinline__ void fmprep_body(const FFinishArgs& a, int stage, CtrlState* ctrl, int bx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
-  if (a.stage == 2 && ctrl->numeric) return;
+  if (stage == 2 && ctrl->numeric) return;
   const int n = bx;
   const int rr = a.r[n];
   if (rr >= a.N[n]) return;
-  const double* cd = a.stage == 1 ? a.kC : a.Cdot2;   // this stage's C_dot
+  const double* cd = stage == 1 ? a.kC : a.Cdot2;   // this stage's C_dot
   const int csz = a.r[0] * a.r[1] * a.r[2];
   const int Rn = csz / rr;
   double* cdl = lds;
@@ -299,7 +303,7 @@ __device__ __forceinline__ void fmprep_body(const FFinishArgs& a, CtrlState* ctr
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_fmprep(FFinishArgs a, CtrlState* ctrl) {
-  fmprep_body<T>(a, ctrl, blockIdx.x);
+  fmprep_body<T>(a, a.stage, ctrl, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- finish a stage
@@ -308,17 +312,17 @@ __global__ void __launch_bounds__(256) k_fmprep(FFinishArgs a, CtrlState* ctrl) 
 // Blocks [rowblocks, rowblocks + 3) (stage 1 only): pseudo-inverse P_n at the stage
 // core C* (already updated by the reduction).
 template <typename T>
-__device__ __forceinline__ void ffinish_body(const FFinishArgs& a, CtrlState* ctrl, int bx) {
+__device__ __forceinline__ void ffinish_body(const FFinishArgs& a, int stage, CtrlState* ctrl, int bx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
-  if (a.stage == 2 && ctrl->numeric) return;
+  if (stage == 2 && ctrl->numeric) return;
   const double inv_dt = 1.0 / a.dt;
   if ((int)bx < a.rowblocks) {
     // M_n (r_n x r_n) into LDS: formed once per stage by k_fmprep, or here (a single
     // stream, where the extra launch would cost more than the repeated small product)
     double* Ml[3];
     if (a.m_inline) {
-      const double* cd = a.stage == 1 ? a.kC : a.Cdot2;   // this stage's C_dot
+      const double* cd = stage == 1 ? a.kC : a.Cdot2;   // this stage's C_dot
       const int csz = a.r[0] * a.r[1] * a.r[2];
       double* cdl = lds;
       T* pl = reinterpret_cast<T*>(cdl + csz);
@@ -378,7 +382,7 @@ __device__ __forceinline__ void ffinish_body(const FFinishArgs& a, CtrlState* ct
       const int rn = a.r[n], ld = a.ldU[n];
       const long long i = q / rn;
       const int j = (int)(q - i * rn);
-      const double* Ust = a.stage == 1 ? a.U0[n] : a.Us[n];
+      const double* Ust = stage == 1 ? a.U0[n] : a.Us[n];
       double ud = 0.0;
       if (rn < a.N[n]) {
         double s = a.H[n][q];
@@ -387,7 +391,7 @@ __device__ __forceinline__ void ffinish_body(const FFinishArgs& a, CtrlState* ct
         for (int k = 0; k < rn; ++k) s -= ur[k] * M[k * rn + j];
         ud = s * inv_dt;
       }
-      if (a.stage == 1) {
+      if (stage == 1) {
         a.kU[n][i * ld + j] = ud;
         const double us = a.U0[n][i * ld + j] + a.dt * ud;
         a.Us[n][i * ld + j] = us;
@@ -439,7 +443,7 @@ __device__ __forceinline__ void ffinish_body(const FFinishArgs& a, CtrlState* ct
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_ffinish(FFinishArgs a, CtrlState* ctrl) {
-  ffinish_body<T>(a, ctrl, blockIdx.x);
+  ffinish_body<T>(a, a.stage, ctrl, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- QR + fold
@@ -954,28 +958,22 @@ template <typename T>
 __global__ void __launch_bounds__(256) kb_freduce(const FReduceArgs* __restrict__ tab, CtrlState* const* ctab,
                                                   BatchMap m, int stage) {
   const int s = m.sid[blockIdx.x];
-  FReduceArgs a = tab[s];
-  a.stage = stage;
   const int b0 = m.start[s];
-  freduce_body<T>(a, ctab[s], blockIdx.x - b0, m.start[s + 1] - b0);
+  freduce_body<T>(tab[s], stage, ctab[s], blockIdx.x - b0, m.start[s + 1] - b0);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) kb_ffinish(const FFinishArgs* __restrict__ tab, CtrlState* const* ctab,
                                                   BatchMap m, int stage) {
   const int s = m.sid[blockIdx.x];
-  FFinishArgs a = tab[s];
-  a.stage = stage;
-  ffinish_body<T>(a, ctab[s], blockIdx.x - m.start[s]);
+  ffinish_body<T>(tab[s], stage, ctab[s], blockIdx.x - m.start[s]);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) kb_fmprep(const FFinishArgs* __restrict__ tab, CtrlState* const* ctab,
                                                  BatchMap m, int stage) {
   const int s = m.sid[blockIdx.x];
-  FFinishArgs a = tab[s];
-  a.stage = stage;
-  fmprep_body<T>(a, ctab[s], blockIdx.x - m.start[s]);
+  fmprep_body<T>(tab[s], stage, ctab[s], blockIdx.x - m.start[s]);
 }
 
 __global__ void __launch_bounds__(256) kb_fqr(const FQrArgs* __restrict__ tab, CtrlState* const* ctab, BatchMap m) {

@@ -29,14 +29,21 @@ import sqlite3
 from collections import defaultdict
 
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
-# The stage pass and everything it includes.
-PASS_SOURCES = ("fused_pass.hip", "fused.h", "tdb_common.h", "tdb_kernels.h", "device_util.h")
-PASS_KERNEL = "k_fpass<float, float>"
+# The stage-pass kernels and the sources each is built from.
+_GENERIC = ("fused_pass.hip", "fused.h", "tdb_common.h", "tdb_kernels.h", "device_util.h")
+_MATRIX = ("mfma_pass.hip", "fused.h", "tdb_common.h", "tdb_kernels.h")
+PASS_KERNELS = {
+    "k_mpass<float, 1>": _MATRIX,        # matrix-core pass, FP32 products, one stream
+    "kb_mpass<float, 1>": _MATRIX,       # the same for a batch of streams
+    "k_mpass<float, 2>": _MATRIX,        # BF16-split products
+    "k_fpass<float, float>": _GENERIC,   # generic pass
+}
+PASS_KERNEL = "k_mpass<float, 1>"
 
 
-def pass_source_digest() -> str:
+def pass_source_digest(kernel: str = PASS_KERNEL) -> str:
     h = hashlib.sha256()
-    for name in PASS_SOURCES:
+    for name in PASS_KERNELS[kernel]:
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
@@ -65,7 +72,7 @@ def stats_text(db: str, command: str, bench_json: str | None = None, bench_plain
            f"{'kernel':60s} {'calls':>7s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}"]
     for name, calls, total, avg, pct in rows[:top]:
         out.append(f"{_short(name)[:60]:60s} {calls:7d} {avg:10.2f} {total / 1e3:10.3f} {pct:6.2f}")
-    prof = [r for r in rows if PASS_KERNEL in r[0]]
+    prof = [r for r in rows if ("tdb::" + PASS_KERNEL + "(") in r[0]]
     if bench_json:
         b = _bench_line(bench_json)
         rf = b["roofline"]
@@ -115,7 +122,7 @@ def pmc_text(fetch_db: str, write_db: str, cmd_f: str, cmd_w: str, copy_bytes: i
            f"and WRITE_SIZE {w_cal:.1f} KiB",
            f"    read scale {f_scale:.4f}, write scale {w_scale:.4f} (bytes = KiB reading x 1024 x scale)", "",
            f"{'kernel':48s} {'grid':>9s} {'n':>5s} {'read_KiB':>11s} {'write_KiB':>11s}"]
-    record = None
+    records = {}
     keys = sorted(set(fa) | set(wa), key=lambda k: (-len(fa.get(k, [])), k))
     for k in keys:
         if "tdb::" not in k[0]:
@@ -124,30 +131,31 @@ def pmc_text(fetch_db: str, write_db: str, cmd_f: str, cmd_w: str, copy_bytes: i
         rd = sum(fv) / len(fv) * f_scale
         wr = sum(wv) / len(wv) * w_scale
         out.append(f"{_short(k[0])[:48]:48s} {k[1]:9d} {len(fv):5d} {rd:11.1f} {wr:11.1f}")
-        if PASS_KERNEL in k[0] and (record is None or len(fv) > record["dispatches"]):
-            record = {"kernel": PASS_KERNEL, "dispatches": len(fv), "read_bytes": rd * 1024.0,
-                      "write_bytes": wr * 1024.0, "traffic_bytes": (rd + wr) * 1024.0,
-                      "read_scale": f_scale, "write_scale": w_scale,
-                      "source_digest": pass_source_digest()}
-    if record is not None:
-        out += ["", "record: " + json.dumps(record)]
-    return "\n".join(out) + "\n", record
+        for kern in PASS_KERNELS:
+            if ("tdb::" + kern + "(") in k[0] and (kern not in records or len(fv) > records[kern]["dispatches"]):
+                records[kern] = {"kernel": kern, "dispatches": len(fv), "read_bytes": rd * 1024.0,
+                                 "write_bytes": wr * 1024.0, "traffic_bytes": (rd + wr) * 1024.0,
+                                 "read_scale": f_scale, "write_scale": w_scale,
+                                 "source_digest": pass_source_digest(kern)}
+    if records:
+        out.append("")
+        out += ["record: " + json.dumps(r) for r in records.values()]
+    return "\n".join(out) + "\n", records
 
 
-def read_pass_traffic(path: str):
-    """The stage-pass record of a `pmc` summary, or None when the file is missing or
-    the kernel's sources have changed since the counters were taken."""
+def read_pass_traffic(path: str, kernel: str = PASS_KERNEL):
+    """The record of `kernel` in a `pmc` summary, or None when the file or the record is
+    missing or the kernel's sources have changed since the counters were taken."""
     try:
         with open(path) as f:
             lines = [ln for ln in f.read().splitlines() if ln.startswith("record: ")]
     except OSError:
         return None
-    if not lines:
-        return None
-    rec = json.loads(lines[-1][len("record: "):])
-    if rec.get("source_digest") != pass_source_digest():
-        return None
-    return rec
+    for ln in reversed(lines):   # the last record of a kernel is the current one
+        rec = json.loads(ln[len("record: "):])
+        if rec.get("kernel") == kernel:
+            return rec if rec.get("source_digest") == pass_source_digest(kernel) else None
+    return None
 
 
 def main(argv=None):
