@@ -33,6 +33,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
 # HBM bytes per stage-pass launch from hardware counters (FETCH_SIZE / WRITE_SIZE,
 # calibrated against a copy of known size); ignored once the kernel's sources change.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_pass_plume512x256x8_fp32.txt")
+ENSEMBLE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_ensemble256_fp32.txt")
 METRIC = "snapshots/s ingested + HBM GB/s vs plain FP64 GPU at <=1e-6 rel err"
 
 
@@ -108,12 +109,19 @@ def _run_ensemble(n, warmup, steps, precision="f32"):
     ranks = [b.streams[i].ranks() for i in range(n)]
     b.close()
     step_bytes = 5.0 * 4.0 * elems   # two stage passes over two snapshots, one error pass
+    traffic = None
+    if precision == "f32" and n == 256:
+        from paper_2201_06958_amd.profsum import read_pass_traffic
+        traffic = read_pass_traffic(ENSEMBLE_TRAFFIC_FILE, "kb_mpass<float, 1>")
     return {"workload": f"fourier-ensemble-{n}x{{128,192,256}}^2x4-fp32", "streams": n, "steps": steps,
             "precision": precision, "elements_per_step": elems,
             "value": n * steps / el, "unit": "snapshots/s", "ms_per_step": 1e3 * el / steps,
             "step_hbm_frac": step_bytes / (el / steps) / (HBM_PEAK_GBS * 1e9),
             "pass": {"avg_launch_us": pav * 1e6, "achieved_GBs": pj["bytes_per_launch"] / pav / 1e9,
-                     "frac": pj["bytes_per_launch"] / pav / 1e9 / HBM_PEAK_GBS},
+                     "frac": pj["bytes_per_launch"] / pav / 1e9 / HBM_PEAK_GBS,
+                     "algorithmic_bytes_per_launch": pj["bytes_per_launch"],
+                     "traffic": traffic["traffic_bytes"] if traffic else None,
+                     "traffic_read_write": [traffic["read_bytes"], traffic["write_bytes"]] if traffic else None},
             "error_pass": {"avg_launch_us": eav * 1e6, "achieved_GBs": er["bytes_per_launch"] / eav / 1e9},
             "max_ranks": [max(r[i] for r in ranks) for i in range(3)]}
 
