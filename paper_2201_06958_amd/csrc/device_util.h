@@ -201,6 +201,58 @@ static __device__ void controller_decide(CtrlState* c) {
 
 namespace tdb {
 
+// ===================================================================== block copies
+// Copy n values from global memory into LDS (converted to the LDS type), with up to 16
+// loads in flight per thread before any is stored, so that a short copy costs one
+// memory round trip rather than one per loop iteration.
+template <typename TS, typename TL>
+__device__ __forceinline__ void g2l(TL* dst, const TS* src, int n) {
+  for (int base = 0; base < n; base += 16 * (int)blockDim.x) {
+    TS v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int t = base + u * (int)blockDim.x + (int)threadIdx.x;
+      v[u] = t < n ? src[t] : (TS)0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int t = base + u * (int)blockDim.x + (int)threadIdx.x;
+      if (t < n) dst[t] = (TL)v[u];
+    }
+  }
+}
+
+// Up to five such copies in one pass (one round trip for all of them); a segment with
+// n = 0 is skipped.
+__device__ __forceinline__ void g2l5(double* d0, const double* s0, int n0, double* d1, const double* s1, int n1,
+                                     double* d2, const double* s2, int n2, double* d3, const double* s3, int n3,
+                                     double* d4, const double* s4, int n4) {
+  const int e0 = n0, e1 = e0 + n1, e2 = e1 + n2, e3 = e2 + n3, e4 = e3 + n4;
+  for (int base = 0; base < e4; base += 16 * (int)blockDim.x) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int t = base + u * (int)blockDim.x + (int)threadIdx.x;
+      double x = 0.0;
+      if (t < e0) x = s0[t];
+      else if (t < e1) x = s1[t - e0];
+      else if (t < e2) x = s2[t - e1];
+      else if (t < e3) x = s3[t - e2];
+      else if (t < e4) x = s4[t - e3];
+      v[u] = x;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int t = base + u * (int)blockDim.x + (int)threadIdx.x;
+      if (t < e0) d0[t] = v[u];
+      else if (t < e1) d1[t - e0] = v[u];
+      else if (t < e2) d2[t - e1] = v[u];
+      else if (t < e3) d3[t - e2] = v[u];
+      else if (t < e4) d4[t - e3] = v[u];
+    }
+  }
+}
+
 // ===================================================================== one-wave kernels
 // The routines below are run by one full wave (64 lanes) of the calling block on small
 // (rn <= 64) row-major matrices in LDS. Lanes own rows or columns; ordering between
@@ -269,6 +321,109 @@ static __device__ void wave_inv_from_linv(const double* Li, double* Gi, int rn) 
     Gi[t] = s;
   }
   wave_fence();
+}
+
+// ------------------------------------------------ register-resident forms (rn <= 32)
+// The same factorizations with the working rows or columns in registers: lane i keeps
+// row i (or column i) in a fixed-size array indexed only by compile-time constants.
+// Entries another lane owns are read with v_readlane during the factorization, and from
+// LDS at wave-uniform addresses afterwards, so no step waits on a store-to-load chain
+// through LDS. The whole wave must execute these (no lane may be masked off around the
+// broadcasts). The arithmetic and its order are those of the LDS routines above.
+
+// Value of v held by lane `src` (uniform), as a wave-uniform double.
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// 1/sqrt(x) for x > 0 to full FP64 accuracy: the hardware estimate and two Newton steps.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  r = fma(r, fma(-h * r, r, 0.5), r);
+  r = fma(r, fma(-h * r, r, 0.5), r);
+  return r;
+}
+
+// The factorization runs over all RB indices without branches: rows and columns from
+// rn to RB are those of the identity, which leaves the leading rn x rn block exactly
+// as it would be alone. Entries above the diagonal are not read while factoring and
+// are cleared at the end.
+template <int RB>
+__device__ __forceinline__ bool wave_chol_inv_rb(double* A, int rn, double* Li, double* Gi) {
+  const int l = threadIdx.x & 63;
+  double a[RB];
+  double rdl = 0.0;                              // lane k: 1 / L[k][k]
+#pragma unroll
+  for (int j = 0; j < RB; ++j) a[j] = (l < rn && j < rn) ? A[l * rn + j] : (l == j ? 1.0 : 0.0);
+  double dmax = 0.0;
+#pragma unroll
+  for (int k = 0; k < RB; ++k) dmax = fmax(dmax, k < rn ? lane_bcast(a[k], k) : 0.0);
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < RB; ++k) {
+    const double piv = lane_bcast(a[k], k);
+    bad = bad || (k < rn && (!(piv > TDB_PIVOT_FLOOR * dmax) || !(piv > 0.0)));
+    const double pv = fmax(piv, 1e-300);
+    const double r = rsqrt_nr(pv);
+    rdl = (l == k) ? r : rdl;
+    a[k] = (l == k) ? pv * r : a[k] * r;        // column k of L (lanes above k: unused)
+#pragma unroll
+    for (int j = k + 1; j < RB; ++j) a[j] -= a[k] * lane_bcast(a[k], j);
+  }
+#pragma unroll
+  for (int j = 0; j < RB; ++j) a[j] = (j > l) ? 0.0 : a[j];
+  if (l < rn)
+#pragma unroll
+    for (int j = 0; j < RB; ++j)
+      if (j < rn) A[l * rn + j] = a[j];
+  if (!bad && Li) {
+    // lane l: column l of L^-1 by forward substitution, column-oriented so that the
+    // chain from one entry to the next is a single update; L[m][i] is lane m's a[i]
+    double x[RB];
+#pragma unroll
+    for (int m = 0; m < RB; ++m) x[m] = (l == m) ? 1.0 : 0.0;
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      x[i] *= lane_bcast(rdl, i);
+#pragma unroll
+      for (int m = i + 1; m < RB; ++m) x[m] -= lane_bcast(a[i], m) * x[i];
+    }
+    if (l < rn)
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+        if (i < rn) Li[i * rn + l] = x[i];
+    if (Gi) {
+      // lane l: column l of Li^T Li, Li[k][i] broadcast from lane i
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        double g = 0.0;
+#pragma unroll
+        for (int k = i; k < RB; ++k) g += lane_bcast(x[k], i) * x[k];
+        if (l < rn && i < rn) Gi[i * rn + l] = g;
+      }
+    }
+  }
+  wave_fence();
+  return !bad;
+}
+
+__device__ __attribute__((noinline)) bool wave_chol_inv_lds(double* A, int rn, double* Li, double* Gi) {
+  const bool ok = wave_chol(A, rn);
+  if (ok && Li) {
+    wave_tri_inv(A, Li, rn);
+    if (Gi) wave_inv_from_linv(Li, Gi, rn);
+  }
+  return ok;
+}
+
+__device__ __forceinline__ bool wave_chol_inv(double* A, int rn, double* Li, double* Gi) {
+  if (rn <= 16) return wave_chol_inv_rb<16>(A, rn, Li, Gi);
+  if (rn <= 32) return wave_chol_inv_rb<32>(A, rn, Li, Gi);
+  return wave_chol_inv_lds(A, rn, Li, Gi);   // out of line: keeps the register forms' allocation lean
 }
 
 // Eigenvalues of the symmetric matrix A (destroyed), descending, into lam[0..rn):

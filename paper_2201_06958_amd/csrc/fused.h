@@ -5,6 +5,8 @@
 namespace tdb {
 
 #define FERR_T1 8   // mode-1 slabs per block of the error pass
+#define FIN_PART 1024 // LDS doubles for the partial blocks of the small matrix-core products
+#define FQR_GP 1024   // LDS doubles for the QR's partial Gram blocks (four 16 x 16)
 
 struct FPassArgs {
   const void* V1;
@@ -51,7 +53,7 @@ struct FFinishArgs {
 };
 
 struct FQrArgs {
-  int core_in_lds, rmax, rounds;
+  int core_in_lds, rmax;
   long long N[3];
   int r[3], ldU[3];
   int u_in_lds[3];

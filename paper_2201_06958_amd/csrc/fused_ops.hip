@@ -20,6 +20,8 @@
 
 namespace tdb {
 
+typedef double md4 __attribute__((ext_vector_type(4)));
+
 // ---------------------------------------------------------------- reduction
 // Sum of count values p[k*stride] in a fixed order with 8 independent partial sums
 // (so that 8 loads are in flight per thread); deterministic for a given count.
@@ -141,112 +143,89 @@ __global__ void __launch_bounds__(256) k_freduce(FReduceArgs a, CtrlState* ctrl)
 }
 
 // ---------------------------------------------------------------- prep helpers
-// Core Gram of the mode-n unfolding into LDS G (rn x rn) from a core (LDS or global),
-// with the unfolding columns walked as (outer, inner) loops.
-__device__ void gram_from(const double* Cl, int rn, long long R_, long long inner_, double* G) {
-  const int npair = rn * (rn + 1) / 2;
-  const int inner = (int)inner_;
-  const int outer = (int)(R_ / inner_);
-  for (int t = threadIdx.x; t < npair; t += blockDim.x) {
-    int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-    while ((i + 1) * (i + 2) / 2 <= t) ++i;
-    while (i * (i + 1) / 2 > t) --i;
-    const int j = t - i * (i + 1) / 2;
-    double s0 = 0.0, s1 = 0.0;
-    if (inner == 1) {
-      const double* ci = Cl + i;
-      const double* cj = Cl + j;
-      int o = 0;
-      for (; o + 2 <= outer; o += 2) {
-        s0 += ci[o * rn] * cj[o * rn];
-        s1 += ci[(o + 1) * rn] * cj[(o + 1) * rn];
-      }
-      if (o < outer) s0 += ci[o * rn] * cj[o * rn];
+// G[i][j] = sum_k XA(i, k) XB(j, k) for i, j < n on the FP64 matrix cores (16x16x4),
+// by the whole block (four waves). xa(i, k) and xb(j, k) return the operands (zero is
+// never requested outside i, j < n, k < K). With sym only the blocks bi >= bj are
+// formed and emit(r, c, v) is called for r >= c (the caller mirrors). A single output
+// block is split over the waves along k and the four partials (part: 1024 doubles of
+// LDS) are added in a fixed order; otherwise the waves share out the blocks and each
+// covers all of k. Ends with a block barrier.
+template <typename FA, typename FB, typename Emit>
+__device__ __forceinline__ void block_xyt_f64(int n, int K, bool sym, FA xa, FB xb, Emit emit, double* part) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lm = lane & 15, lk = lane >> 4;
+  const int nb = (n + 15) >> 4;
+  const int nblk = sym ? nb * (nb + 1) / 2 : nb * nb;
+  const bool split = nblk == 1;
+  const int per = split ? (((K + 3) / 4 + 3) & ~3) : K;
+  const int k0 = split ? wid * per : 0, k1 = split ? min(K, k0 + per) : K;
+  for (int blk = split ? 0 : wid; blk < nblk; blk += split ? 1 : 4) {
+    int bi, bj;
+    if (sym) {
+      bi = 0;
+      while ((bi + 1) * (bi + 2) / 2 <= blk) ++bi;
+      bj = blk - bi * (bi + 1) / 2;
     } else {
-      for (int o = 0; o < outer; ++o) {
-        const double* ci = Cl + (o * rn + i) * inner;
-        const double* cj = Cl + (o * rn + j) * inner;
-        int in = 0;
-        for (; in + 2 <= inner; in += 2) {
-          s0 += ci[in] * cj[in];
-          s1 += ci[in + 1] * cj[in + 1];
-        }
-        if (in < inner) s0 += ci[in] * cj[in];
+      bi = blk / nb;
+      bj = blk - bi * nb;
+    }
+    const int ia = 16 * bi + lm, jb = 16 * bj + lm;
+    md4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int kk = k0; kk < k1; kk += 4) {
+      const int k = kk + lk;
+      const double av = (k < k1 && ia < n) ? xa(ia, k) : 0.0;
+      const double bv = (k < k1 && jb < n) ? xb(jb, k) : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    // FP64 16x16x4 result: lane holds rows 16 bi + lk + 4 i, column 16 bj + lm
+    if (split) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) part[wid * 256 + (lk + 4 * i) * 16 + lm] = acc[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 16 * bi + lk + 4 * i, c = 16 * bj + lm;
+        if (r < n && c < n && (!sym || bi > bj || r >= c)) emit(r, c, acc[i]);
       }
     }
-    const double s = s0 + s1;
-    G[i * rn + j] = s;
-    G[j * rn + i] = s;
   }
   __syncthreads();
+  if (split) {
+    const int t = threadIdx.x, r = t >> 4, c = t & 15;
+    if (r < n && c < n && (!sym || r >= c)) emit(r, c, (part[t] + part[256 + t]) + (part[512 + t] + part[768 + t]));
+    __syncthreads();
+  }
 }
 
-// Cholesky with the singularity test (pivot below TDB_PIVOT_FLOOR x max diagonal).
-__device__ bool chol_inplace(double* A, int rn) {
-  __shared__ int bad;
-  __shared__ double dmax;
-  if (threadIdx.x == 0) {
-    bad = 0;
-    double m = 0.0;
-    for (int i = 0; i < rn; ++i) m = fmax(m, A[i * rn + i]);
-    dmax = m;
-  }
-  __syncthreads();
-  for (int k = 0; k < rn; ++k) {
-    if (threadIdx.x == 0) {
-      const double piv = A[k * rn + k];
-      if (!(piv > TDB_PIVOT_FLOOR * dmax) || !(piv > 0.0)) bad = 1;
-      A[k * rn + k] = sqrt(fmax(piv, 1e-300));
-    }
-    __syncthreads();
-    const double lkk = A[k * rn + k];
-    for (int i = k + 1 + threadIdx.x; i < rn; i += blockDim.x) A[i * rn + k] /= lkk;
-    __syncthreads();
-    const int m = rn - k - 1;
-    for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
-      const int i = k + 1 + t / m, j = k + 1 + t % m;
-      if (j <= i) A[i * rn + j] -= A[i * rn + k] * A[j * rn + k];
-    }
-    __syncthreads();
-  }
-  for (int t = threadIdx.x; t < rn * rn; t += blockDim.x)
-    if (t % rn > t / rn) A[t] = 0.0;
-  __syncthreads();
-  return bad == 0;
+// Entry (i, c) of the mode-n unfolding of a core stored with `inner` = prod_{k>n} r_k:
+// column c = o*inner + in sits at (o*rn + i)*inner + in.
+__device__ __forceinline__ int unfold_at(int i, int c, int rn, int inner) {
+  const int o = c / inner;
+  return (o * rn + i) * inner + (c - o * inner);
 }
 
-// P_n = C_(n)^T G^-1 from the Cholesky factor L (in G) of the core Gram; Li scratch.
+// Core Gram of the mode-n unfolding into LDS G (rn x rn) from a core (LDS or global);
+// part: 1024 doubles of LDS scratch.
+__device__ void gram_from(const double* Cl, int rn, long long R, long long inner_, double* G, double* part) {
+  const int inner = (int)inner_;
+  auto x = [&](int i, int c) { return Cl[unfold_at(i, c, rn, inner)]; };
+  block_xyt_f64(rn, (int)R, true, x, x,
+                [&](int r, int c, double v) {
+                  G[r * rn + c] = v;
+                  G[c * rn + r] = v;
+                },
+                part);
+}
+
+// M_n = dt * C_dot_(n) P_n (rn x rn) into Ml from LDS copies of C_dot and P_n (R x rn);
+// part: 1024 doubles of LDS scratch.
 template <typename T>
-__device__ void write_pinv(const double* Cl, double* G, double* Li, int rn, long long R, long long inner,
-                           T* P) {
-  for (int t = threadIdx.x; t < rn * rn; t += blockDim.x) Li[t] = 0.0;
-  __syncthreads();
-  for (int j = threadIdx.x; j < rn; j += blockDim.x) {
-    Li[j * rn + j] = 1.0 / G[j * rn + j];
-    for (int i = j + 1; i < rn; ++i) {
-      double s = 0.0;
-      for (int k = j; k < i; ++k) s += G[i * rn + k] * Li[k * rn + j];
-      Li[i * rn + j] = -s / G[i * rn + i];
-    }
-  }
-  __syncthreads();
-  // G <- Li^T Li = G^-1
-  for (int t = threadIdx.x; t < rn * rn; t += blockDim.x) {
-    const int i = t / rn, j = t % rn;
-    double s = 0.0;
-    for (int k = (i > j ? i : j); k < rn; ++k) s += Li[k * rn + i] * Li[k * rn + j];
-    G[t] = s;   // safe: every thread reads only Li here
-  }
-  __syncthreads();
-  for (long long t = threadIdx.x; t < R * rn; t += blockDim.x) {
-    const long long c = t / rn;
-    const int j = (int)(t - c * rn);
-    const long long o = c / inner, in = c - o * inner;
-    double s = 0.0;
-    for (int b = 0; b < rn; ++b) s += Cl[(o * rn + b) * inner + in] * G[b * rn + j];
-    P[t] = (T)s;
-  }
-  __syncthreads();
+__device__ void form_m(const double* cdl, const T* Pn, int rn, int R, int inner, double dt, double* Ml, double* part) {
+  block_xyt_f64(
+      rn, R, false, [&](int i, int c) { return cdl[unfold_at(i, c, rn, inner)]; },
+      [&](int j, int c) { return (double)Pn[c * rn + j]; },
+      [&](int r, int c, double v) { Ml[r * rn + c] = v * dt; },   // H is the raw (undivided) projection, so M is too
+      part);
 }
 
 // P_n = C_(n)^T G^-1 from the inverse Gi (LDS), block-parallel.
@@ -281,24 +260,15 @@ __device__ __forceinline__ void fmprep_body(const FFinishArgs& a, int stage, Ctr
   double* cdl = lds;
   T* pl = reinterpret_cast<T*>(cdl + csz);
   const T* Pn = static_cast<const T*>(a.Pcur[n]);
-  for (int t = threadIdx.x; t < csz; t += blockDim.x) cdl[t] = cd[t];
-  for (int t = threadIdx.x; t < Rn * rr; t += blockDim.x) pl[t] = Pn[t];
+  g2l(cdl, cd, csz);
+  g2l(pl, Pn, Rn * rr);
   __syncthreads();
-  int inner = 1, outer = 1;
-  for (int k = 0; k < 3; ++k) {
-    if (k < n) outer *= a.r[k];
-    if (k > n) inner *= a.r[k];
-  }
-  for (int t = threadIdx.x; t < rr * rr; t += blockDim.x) {
-    const int i = t / rr, j = t - (t / rr) * rr;
-    double s = 0.0;
-    for (int o = 0; o < outer; ++o) {
-      const double* crow = cdl + (o * rr + i) * inner;
-      const T* prow = pl + (o * inner) * rr + j;
-      for (int in = 0; in < inner; ++in) s += crow[in] * (double)prow[in * rr];
-    }
-    a.M[n][t] = s * a.dt;   // H is the raw (undivided) projection, so M is too
-  }
+  int inner = 1;
+  for (int k = n + 1; k < 3; ++k) inner *= a.r[k];
+  double* Ml = lds + (csz * 8 + Rn * rr * (int)sizeof(T) + 7) / 8;
+  double* part = Ml + rr * rr;
+  form_m<T>(cdl, pl, rr, Rn, inner, a.dt, Ml, part);
+  for (int t = threadIdx.x; t < rr * rr; t += blockDim.x) a.M[n][t] = Ml[t];
 }
 
 template <typename T>
@@ -326,38 +296,54 @@ __device__ __forceinline__ void ffinish_body(const FFinishArgs& a, int stage, Ct
       const int csz = a.r[0] * a.r[1] * a.r[2];
       double* cdl = lds;
       T* pl = reinterpret_cast<T*>(cdl + csz);
-      for (int t = threadIdx.x; t < csz; t += blockDim.x) cdl[t] = cd[t];
       int poff[3], off = 0;
       for (int n = 0; n < 3; ++n) {
         poff[n] = off;
-        if (a.r[n] < a.N[n]) {
-          const T* Pn = static_cast<const T*>(a.Pcur[n]);
-          for (int t = threadIdx.x; t < csz; t += blockDim.x) pl[off + t] = Pn[t];
-          off += csz;
+        if (a.r[n] < a.N[n]) off += csz;
+      }
+      {
+        // C_dot and the active P_n in one pass, 16 loads in flight per thread
+        const T* P0 = static_cast<const T*>(a.Pcur[0]);
+        const T* P1 = static_cast<const T*>(a.Pcur[1]);
+        const T* P2 = static_cast<const T*>(a.Pcur[2]);
+        const bool a0 = a.r[0] < a.N[0], a1 = a.r[1] < a.N[1];
+        const T* Pfirst = a0 ? P0 : (a1 ? P1 : P2);
+        const T* Psecond = (a0 && a1) ? P1 : P2;
+        const int tot = csz + off;
+        for (int base = 0; base < tot; base += 16 * blockDim.x) {
+          double v[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int t = base + u * blockDim.x + threadIdx.x;
+            double x = 0.0;
+            if (t < csz) x = cd[t];
+            else if (t < tot) {
+              const int q = t - csz, seg = q / csz, e = q - seg * csz;
+              const T* src = seg == 0 ? Pfirst : (seg == 1 ? Psecond : P2);
+              x = (double)src[e];
+            }
+            v[u] = x;
+          }
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int t = base + u * blockDim.x + threadIdx.x;
+            if (t < csz) cdl[t] = v[u];
+            else if (t < tot) pl[t - csz] = (T)v[u];
+          }
         }
       }
       __syncthreads();
       int moff = (int)((csz * 8 + off * (int)sizeof(T) + 7) / 8);
+      int msum = 0;
+      for (int n = 0; n < 3; ++n) msum += a.r[n] * a.r[n];
+      double* part = lds + moff + msum;
       for (int n = 0; n < 3; ++n) {
         Ml[n] = lds + moff;
         const int rr = a.r[n];
         if (rr < a.N[n]) {
-          int inner = 1, outer = 1;
-          for (int k = 0; k < 3; ++k) {
-            if (k < n) outer *= a.r[k];
-            if (k > n) inner *= a.r[k];
-          }
-          const T* Pn = pl + poff[n];
-          for (int t = threadIdx.x; t < rr * rr; t += blockDim.x) {
-            const int i = t / rr, j = t - (t / rr) * rr;
-            double s = 0.0;
-            for (int o = 0; o < outer; ++o) {
-              const double* crow = cdl + (o * rr + i) * inner;
-              const T* prow = Pn + (o * inner) * rr + j;
-              for (int in = 0; in < inner; ++in) s += crow[in] * (double)prow[in * rr];
-            }
-            Ml[n][t] = s * a.dt;   // H is the raw (undivided) projection, so M is too
-          }
+          int inner = 1;
+          for (int k = n + 1; k < 3; ++k) inner *= a.r[k];
+          form_m<T>(cdl, pl + poff[n], rr, csz / rr, inner, a.dt, Ml[n], part);
         }
         moff += rr * rr;
       }
@@ -367,7 +353,7 @@ __device__ __forceinline__ void ffinish_body(const FFinishArgs& a, int stage, Ct
         Ml[n] = lds + off;
         const int rr = a.r[n];
         if (rr < a.N[n])
-          for (int t = threadIdx.x; t < rr * rr; t += blockDim.x) Ml[n][t] = a.M[n][t];
+          g2l(Ml[n], a.M[n], rr * rr);
         off += rr * rr;
       }
     }
@@ -416,21 +402,18 @@ __device__ __forceinline__ void ffinish_body(const FFinishArgs& a, int stage, Ct
   double* G = lds;
   double* Li = G + rq * rq;
   double* Gi = Li + rq * rq;
-  double* Cl = Gi + rq * rq;
+  double* Gp = Gi + rq * rq;                 // FQR_GP partial blocks
+  double* Cl = Gp + FQR_GP;
   __shared__ int ok_s;
   const double* Csrc = a.Cs;
   if (a.core_in_lds) {
-    for (int t = threadIdx.x; t < (int)csz; t += blockDim.x) Cl[t] = Csrc[t];
+    g2l(Cl, Csrc, (int)csz);
     __syncthreads();
     Csrc = Cl;
   }
-  gram_from(Csrc, rn, R, inner, G);
+  gram_from(Csrc, rn, R, inner, G, Gp);
   if (threadIdx.x < 64) {
-    const bool ok = wave_chol(G, rn);
-    if (ok) {
-      wave_tri_inv(G, Li, rn);
-      wave_inv_from_linv(Li, Gi, rn);
-    }
+    const bool ok = wave_chol_inv(G, rn, Li, Gi);
     if (threadIdx.x == 0) {
       ok_s = ok ? 1 : 0;
       if (!ok) atomicOr(&ctrl->numeric, 1);
@@ -447,13 +430,11 @@ __global__ void __launch_bounds__(256) k_ffinish(FFinishArgs a, CtrlState* ctrl)
 }
 
 // ---------------------------------------------------------------- QR + fold
-// Block n: Cholesky QR of U_n in the W inner product (one round: the Heun update leaves
-// U_n W-orthonormal to O(dt^2), so a single round already reaches roundoff; a second
-// round can be requested): the Gram matrix
-// U^T W U from row-split partial sums (one quarter of the rows per wave, combined in
-// a fixed order), its Cholesky factor R^T R and R^-1 by one wave, then U <- U R^-1
-// row by row; R accumulates over the rounds. The last block to finish folds every
-// R_n into the core (C <- C x_n R_n), so the reconstruction is unchanged.
+// Block n: one round of Cholesky QR of U_n in the W inner product (the Heun update
+// leaves U_n W-orthonormal to O(dt^2), so a single round reaches roundoff): the Gram
+// matrix U^T W U on the FP64 matrix cores, its Cholesky factor R^T R and R^-1 by one
+// wave, then U <- U R^-1, again on the matrix cores. The last block to finish folds
+// every R_n into the core (C <- C x_n R_n), so the reconstruction is unchanged.
 __device__ __forceinline__ void fqr_body(const FQrArgs& a, CtrlState* ctrl, int bx, int gx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
@@ -468,99 +449,87 @@ __device__ __forceinline__ void fqr_body(const FQrArgs& a, CtrlState* ctrl, int 
   const int rn = a.r[n], ld = a.ldU[n];
   const int Nn = (int)a.N[n];
   const int rq = a.rmax;
-  const int np = rn * (rn + 1) / 2;
-  const int npq = rq * (rq + 1) / 2;
   double* L = lds;                          // rq*rq
   double* Li = L + rq * rq;                 // rq*rq
   double* Rt = Li + rq * rq;                // rq*rq
   double* Tm = Rt + rq * rq;                // rq*rq
-  double* Gp = Tm + rq * rq;                // 4*npq partial Grams
-  double* wl = Gp + 4 * npq;                // Nn weights
+  double* Gp = Tm + rq * rq;                // FQR_GP partial Gram blocks
+  double* wl = Gp + FQR_GP;                 // Nn weights
   double* Ul = wl + TDB_NEIG;               // Nn*rn when staged (or the core for the fold)
   double* U = a.U0[n];
   const bool stage = a.u_in_lds[n] && !skip;
   if (!skip) {
-    for (int t = threadIdx.x; t < Nn; t += blockDim.x) wl[t] = a.w[n][t];
-    if (stage)
-      for (int base = 0; base < Nn * rn; base += 8 * blockDim.x) {
-        double v[8];
+    // the weights and (when staged) U_n, with up to 16 loads in flight per thread
+    const int tot = Nn + (stage ? Nn * rn : 0);
+    const double* w = a.w[n];
+    for (int base = 0; base < tot; base += 16 * blockDim.x) {
+      double v[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int t = base + u * blockDim.x + threadIdx.x;
-          v[u] = 0.0;
-          if (t < Nn * rn) { const int i = t / rn; v[u] = U[i * ld + (t - i * rn)]; }
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int t = base + u * blockDim.x + threadIdx.x;
-          if (t < Nn * rn) Ul[t] = v[u];
-        }
+      for (int u = 0; u < 16; ++u) {
+        const int t = base + u * blockDim.x + threadIdx.x;
+        v[u] = 0.0;
+        if (t < Nn) v[u] = w[t];
+        else if (t < tot) { const int q = t - Nn, i = q / rn; v[u] = U[i * ld + (q - i * rn)]; }
       }
-    for (int t = threadIdx.x; t < rn * rn; t += blockDim.x) Rt[t] = (t / rn == t % rn) ? 1.0 : 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int t = base + u * blockDim.x + threadIdx.x;
+        if (t < Nn) wl[t] = v[u];
+        else if (t < tot) Ul[t - Nn] = v[u];
+      }
+    }
   }
   __syncthreads();
   double* Uw = stage ? Ul : U;
   const int ldw = stage ? rn : ld;
   bool ok = !skip;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int round = 0; round < a.rounds && ok; ++round) {
-    // partial Grams: wave `wid` sums rows [q0, q1)
-    const int per = (Nn + 3) / 4;
-    const int q0 = wid * per, q1 = min(Nn, q0 + per);
-    for (int pp = lane; pp < np; pp += 64) {
-      int i = (int)((sqrt(8.0 * pp + 1.0) - 1.0) * 0.5);
-      while ((i + 1) * (i + 2) / 2 <= pp) ++i;
-      while (i * (i + 1) / 2 > pp) --i;
-      const int j = pp - i * (i + 1) / 2;
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      int q = q0;
-      for (; q + 4 <= q1; q += 4) {
-        s0 += wl[q] * Uw[q * ldw + i] * Uw[q * ldw + j];
-        s1 += wl[q + 1] * Uw[(q + 1) * ldw + i] * Uw[(q + 1) * ldw + j];
-        s2 += wl[q + 2] * Uw[(q + 2) * ldw + i] * Uw[(q + 2) * ldw + j];
-        s3 += wl[q + 3] * Uw[(q + 3) * ldw + i] * Uw[(q + 3) * ldw + j];
-      }
-      for (; q < q1; ++q) s0 += wl[q] * Uw[q * ldw + i] * Uw[q * ldw + j];
-      Gp[wid * npq + pp] = (s0 + s1) + (s2 + s3);
-    }
-    __syncthreads();
-    for (int pp = threadIdx.x; pp < np; pp += blockDim.x) {
-      int i = (int)((sqrt(8.0 * pp + 1.0) - 1.0) * 0.5);
-      while ((i + 1) * (i + 2) / 2 <= pp) ++i;
-      while (i * (i + 1) / 2 > pp) --i;
-      const int j = pp - i * (i + 1) / 2;
-      const double g = (Gp[pp] + Gp[npq + pp]) + (Gp[2 * npq + pp] + Gp[3 * npq + pp]);
-      L[i * rn + j] = g;
-      L[j * rn + i] = g;
-    }
-    __syncthreads();
+  const int lm = lane & 15, lk = lane >> 4;
+  const int nb = (rn + 15) >> 4;            // 16-wide blocks of the rank
+  if (ok) {
+    // Gram U^T W U on the FP64 matrix cores
+    block_xyt_f64(
+        rn, Nn, true, [&](int i, int q) { return wl[q] * Uw[q * ldw + i]; }, [&](int j, int q) { return Uw[q * ldw + j]; },
+        [&](int r, int c, double v) {
+          L[r * rn + c] = v;
+          L[c * rn + r] = v;
+        },
+        Gp);
     if (threadIdx.x < 64) {
-      const bool okw = wave_chol(L, rn);
-      if (okw) wave_tri_inv(L, Li, rn);
+      const bool okw = wave_chol_inv(L, rn, Li, nullptr);
       if (threadIdx.x == 0) ok_s = okw ? 1 : 0;
     }
     __syncthreads();
     ok = ok_s != 0;
-    if (!ok) break;
-    // U <- U R^-1 with R = L^T: x_j = sum_{k<=j} u_k Li[j][k], in place from the last column
-    for (int q = threadIdx.x; q < Nn; q += blockDim.x) {
-      double* rowp = Uw + q * ldw;
-      for (int j = rn - 1; j >= 0; --j) {
-        double s = 0.0;
-        const double* lj = Li + j * rn;
-        for (int k = 0; k <= j; ++k) s += rowp[k] * lj[k];
-        rowp[j] = s;
+  }
+  if (ok) {
+    // U <- U R^-1 = U Li^T on the matrix cores: 16-row blocks, one per wave at a time.
+    // Column j of the result needs columns k <= j only, so taking the column blocks
+    // from the last to the first lets each block be stored in place at once.
+    for (int rb = wid; rb * 16 < Nn; rb += 4) {
+      const int q = rb * 16 + lm;
+      for (int cj = nb - 1; cj >= 0; --cj) {
+        md4 acc = {0.0, 0.0, 0.0, 0.0};
+        const int j = 16 * cj + lm;
+        const int kend = min(rn, 16 * cj + 16);
+        for (int k0 = 0; k0 < kend; k0 += 4) {
+          const int k = k0 + lk;
+          const double av = (q < Nn && k < kend) ? Uw[q * ldw + k] : 0.0;
+          const double bv = (j < rn && k < kend) ? Li[j * rn + k] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int qr = rb * 16 + lk + 4 * i;
+          if (qr < Nn && j < rn) Uw[qr * ldw + j] = acc[i];
+        }
       }
     }
-    // Rt <- L^T Rt
+    // R = L^T
     for (int t = threadIdx.x; t < rn * rn; t += blockDim.x) {
       const int i = t / rn, j = t - (t / rn) * rn;
-      double s = 0.0;
-      for (int k = i; k < rn; ++k) s += L[k * rn + i] * Rt[k * rn + j];
-      Tm[t] = s;
+      Rt[t] = L[j * rn + i];
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t < rn * rn; t += blockDim.x) Rt[t] = Tm[t];
     __syncthreads();
   }
   if (skip) {
@@ -583,24 +552,24 @@ __device__ __forceinline__ void fqr_body(const FQrArgs& a, CtrlState* ctrl, int 
   }
   __syncthreads();
   if (!last) return;
+  // the fence orders the plain loads below after every block's stores of R_n and U_n
   __threadfence();
   if (threadIdx.x == 0) *a.counter = 0u;
   if (__hip_atomic_load(&ctrl->numeric, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) return;
   int csz = 1;
   for (int k = 0; k < 3; ++k) csz *= a.r[k];
-  // core in LDS (two buffers) when it fits, else ping-pong through global memory
+  // core in LDS (two buffers) when it fits, else ping-pong through global memory; the
+  // three factors and (when it fits) U_3 in one load phase
   double* ca = a.core_in_lds ? Ul : a.C0;
   double* cb = a.core_in_lds ? Ul + csz : a.Ctmp;
-  if (a.core_in_lds) {
-    for (int t = threadIdx.x; t < csz; t += blockDim.x)
-      ca[t] = __hip_atomic_load(&a.C0[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  const int N3 = (int)a.N[2], ld3 = a.ldU[2];
+  const bool u3l = a.T3 && N3 * ld3 <= FQR_GP;
+  g2l5(ca, a.C0, a.core_in_lds ? csz : 0, L, a.Rq[0], a.r[0] * a.r[0], Li, a.Rq[1], a.r[1] * a.r[1], Tm, a.Rq[2],
+       a.r[2] * a.r[2], Gp, a.U0[2], u3l ? N3 * ld3 : 0);
   __syncthreads();
   for (int m = 0; m < 3; ++m) {
     const int rm = a.r[m];
-    for (int t = threadIdx.x; t < rm * rm; t += blockDim.x)
-      Rt[t] = __hip_atomic_load(&a.Rq[m][t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
+    const double* Rm = m == 0 ? L : (m == 1 ? Li : Tm);
     int inner = 1;
     for (int k = m + 1; k < 3; ++k) inner *= a.r[k];
     for (int t = threadIdx.x; t < csz; t += blockDim.x) {
@@ -608,7 +577,7 @@ __device__ __forceinline__ void fqr_body(const FQrArgs& a, CtrlState* ctrl, int 
       const int ai = rest % rm;
       const int o = rest / rm;
       double s = 0.0;
-      for (int b = ai; b < rm; ++b) s += Rt[ai * rm + b] * ca[(o * rm + b) * inner + in];
+      for (int b = ai; b < rm; ++b) s += Rm[ai * rm + b] * ca[(o * rm + b) * inner + in];
       cb[t] = s;
     }
     __syncthreads();
@@ -617,12 +586,12 @@ __device__ __forceinline__ void fqr_body(const FQrArgs& a, CtrlState* ctrl, int 
   for (int t = threadIdx.x; t < csz; t += blockDim.x) a.C0[t] = ca[t];
   // T3 = C x_3 U_3 of the folded core, for the error-pass expansion
   if (a.T3) {
-    const int r12 = a.r[0] * a.r[1], r3 = a.r[2], N3 = (int)a.N[2], ld3 = a.ldU[2];
+    const int r12 = a.r[0] * a.r[1], r3 = a.r[2];
+    const double* U3 = u3l ? Gp : a.U0[2];
     for (int t = threadIdx.x; t < r12 * N3; t += blockDim.x) {
       const int ab = t / N3, i3 = t - (t / N3) * N3;
       double s = 0.0;
-      for (int c = 0; c < r3; ++c)
-        s += ca[ab * r3 + c] * __hip_atomic_load(&a.U0[2][i3 * ld3 + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int c = 0; c < r3; ++c) s += ca[ab * r3 + c] * U3[i3 * ld3 + c];
       a.T3[t] = s;
     }
   }
@@ -633,10 +602,11 @@ __global__ void __launch_bounds__(256) k_fqr(FQrArgs a, CtrlState* ctrl) {
 }
 
 // ---------------------------------------------------------------- post-step
-// Blocks [0, 3): for mode n at the new state: core singular values (Jacobi, into the
-// controller), pseudo-inverse P_n and weighted basis B_n for the next stage 1.
-// Blocks [3, 3 + eblocks): the partial expansion E = C x_2 U_2 x_3 U_3 used by the
-// error pass, and the mode-1 basis in the compute type.
+// Blocks [0, 3): for mode n at the new state: the core Gram (kept for the controller),
+// its eigenvalues when asked for (core singular values) and the pseudo-inverse P_n for
+// the next stage 1. Blocks [3, 3 + eblocks): the partial expansion E = C x_2 U_2 x_3 U_3
+// used by the error pass, the mode-1 basis in the compute type and the weighted bases
+// B_n of the next stage 1.
 template <typename T>
 __device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, int bx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -654,7 +624,7 @@ __device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, 
     const long long i2a = (long long)eb * per, i2b = min(N2, i2a + per);
     if (i2a < i2b) {
       if (a.T3) {
-        for (long long t = threadIdx.x; t < (long long)r1 * r2 * N3; t += blockDim.x) T3[t] = a.T3[t];
+        g2l(T3, a.T3, r1 * r2 * (int)N3);
       } else {
         for (long long t = threadIdx.x; t < (long long)r1 * r2 * N3; t += blockDim.x) {
           const long long i3 = t % N3, ab = t / N3;
@@ -685,9 +655,22 @@ __device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, 
     }
     const long long tu = a.N[0] * r1;
     T* U1c = static_cast<T*>(a.U1c);
-    for (long long t = (long long)eb * blockDim.x + threadIdx.x; t < tu; t += (long long)a.eblocks * blockDim.x) {
+    const long long gstride = (long long)a.eblocks * blockDim.x;
+    for (long long t = (long long)eb * blockDim.x + threadIdx.x; t < tu; t += gstride) {
       const long long i = t / r1;
       U1c[t] = (T)a.U[0][i * a.ldU[0] + (t - i * r1)];
+    }
+    // weighted bases B_n = W_n U_n of the next stage 1
+    for (int m = 0; m < 3; ++m) {
+      const int rm = a.r[m], ld = a.ldU[m];
+      const long long tot = a.N[m] * rm;
+      const double* U = a.U[m];
+      const double* w = a.w[m];
+      T* B = static_cast<T*>(a.B[m]);
+      for (long long t = (long long)eb * blockDim.x + threadIdx.x; t < tot; t += gstride) {
+        const long long i = t / rm;
+        B[t] = (T)(w[i] * U[i * ld + (t - i * rm)]);
+      }
     }
     return;
   }
@@ -699,32 +682,22 @@ __device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, 
     if (k != n) R *= a.r[k];
     if (k > n) inner *= a.r[k];
   }
-  // weighted basis of the next stage 1
-  {
-    T* B = static_cast<T*>(a.B[n]);
-    const int Nn = (int)a.N[n], ld = a.ldU[n];
-    const double* U = a.U[n];
-    const double* w = a.w[n];
-    for (int i = threadIdx.x / 4; i < Nn; i += blockDim.x / 4) {
-      const double wi = w[i];
-      for (int j = threadIdx.x & 3; j < rn; j += 4) B[i * rn + j] = (T)(wi * U[i * ld + j]);
-    }
-  }
   const int rq = a.rmax;
   double* G = lds;
   double* Li = G + rq * rq;
   double* Gi = Li + rq * rq;
   double* ws = Gi + rq * rq;                 // 4*rq
   double* lam = ws + 4 * rq;                 // rq
-  double* Cl = lam + rq;
+  double* Gp = lam + rq;                     // FQR_GP partial blocks
+  double* Cl = Gp + FQR_GP;
   __shared__ int ok_s;
   const double* Csrc = a.C;
   if (a.core_in_lds) {
-    for (int t = threadIdx.x; t < (int)csz; t += blockDim.x) Cl[t] = Csrc[t];
+    g2l(Cl, Csrc, (int)csz);
     __syncthreads();
     Csrc = Cl;
   }
-  gram_from(Csrc, rn, R, inner, G);
+  gram_from(Csrc, rn, R, inner, G, Gp);
   const bool need_p = rn < a.N[n] && a.want_pinv;
   if (threadIdx.x < 64) {
     if (a.G[n])
@@ -738,13 +711,7 @@ __device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, 
         ctrl->sigma[n][i] = i < rn ? sqrt(fmax(lam[i], 0.0)) : 0.0;
     }
     bool ok = true;
-    if (need_p) {
-      ok = wave_chol(G, rn);
-      if (ok) {
-        wave_tri_inv(G, Li, rn);
-        wave_inv_from_linv(Li, Gi, rn);
-      }
-    }
+    if (need_p) ok = wave_chol_inv(G, rn, Li, Gi);
     if (threadIdx.x == 0) {
       ok_s = ok ? 1 : 0;
       if (!ok) atomicOr(&ctrl->numeric, 4);

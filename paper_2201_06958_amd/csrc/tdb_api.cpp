@@ -867,8 +867,8 @@ size_t small_lds(const tdb_ctx* h, const int* rl, bool* core_in_lds, bool m_inli
   long long msum = 0;
   for (int n = 0; n < h->p; ++n) msum += (long long)rl[n] * rl[n];
   // finish rows stage the three M_n (and, forming them inline, C_dot and the three P_n)
-  const size_t rows = (size_t)msum * 8 + (m_inline ? (size_t)csz * 8 + 3 * (size_t)csz * h->celt + 8 : 0);
-  const size_t base = std::max<size_t>((3 * (size_t)rm * rm + 5 * (size_t)rm + 64) * 8, rows);
+  const size_t rows = (size_t)msum * 8 + (m_inline ? (size_t)csz * 8 + 3 * (size_t)csz * h->celt + 8 + FIN_PART * 8 : 0);
+  const size_t base = std::max<size_t>((3 * (size_t)rm * rm + 5 * (size_t)rm + 64 + FQR_GP) * 8, rows);
   *core_in_lds = base + (size_t)csz * 8 <= (size_t)h->lds_max;
   return base + (*core_in_lds ? (size_t)csz * 8 : 0);
 }
@@ -998,7 +998,8 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
     const long long csz = prod_ll(rl, 3);
     long long pmax = 0;
     for (int n = 0; n < 3; ++n) pmax = std::max(pmax, csz);
-    A.lds_mprep = (size_t)csz * 8 + (size_t)pmax * h->celt + 16;
+    const size_t rmq = (size_t)max_rank_of(rl, 3);
+    A.lds_mprep = (size_t)csz * 8 + (size_t)pmax * h->celt + 16 + (rmq * rmq + FIN_PART) * 8;
   }
   for (int st = 0; st < 2; ++st) {
     A.ga[st] = ga;
@@ -1010,9 +1011,8 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
   FQrArgs& qa = A.qa;
   qa = FQrArgs{};
   qa.rmax = max_rank_of(rl, 3);
-  qa.rounds = 1;
   const size_t npq = (size_t)qa.rmax * (qa.rmax + 1) / 2;
-  const size_t qlds = (4 * (size_t)qa.rmax * qa.rmax + 4 * npq + TDB_NEIG) * 8;
+  const size_t qlds = (4 * (size_t)qa.rmax * qa.rmax + FQR_GP + TDB_NEIG) * 8;
   size_t ustage = 0;
   // a batch keeps several QR blocks per compute unit rather than staging U_n
   const size_t qbudget = rl != h->r ? std::min<size_t>((size_t)h->lds_max, 48 * 1024) : (size_t)h->lds_max;
