@@ -126,8 +126,25 @@ tdb_status tdb_init_from_factors(const tdb_config* cfg, const void* V0_dev,
 /* Advance from t_k to t_{k+1} with snapshot V_dev (Sec. 2.2-2.5): difference quotient,
  * two Heun stages of eqs. (Corecont)/(basecont), W-orthonormal QR with the factor
  * folded into the core, weighted error pass, controller (and HOSVD reinit when it
- * fires). Returns after enqueueing and one small read-back of the controller result. */
+ * fires).
+ * With TDB_COPY snapshots it returns after one small read-back of the controller
+ * result, so the step is complete. With TDB_BORROW snapshots on the fused third-order
+ * path the call is pipelined: it enqueues this step on `stream`, then reads the
+ * previous step's decision and acts on it (a reinitialisation, with the previous
+ * snapshot, which the caller keeps until this call returns; this step is then enqueued
+ * again), so the device never waits for the host between steps. The newest step's
+ * decision is read by the next ingest or by any call that returns results
+ * (tdb_get_stats, tdb_get_core_and_bases, tdb_reconstruct, tdb_set_threshold,
+ * tdb_profile_*) or tdb_flush; TDB_ENUMERIC for a non-finite error is reported by the
+ * call that reads it. Reads of V_dev are ordered on `stream`: overwrite it only in
+ * work ordered after the next call's. Setting TDB_PIPELINE=0 in the environment
+ * turns the pipelining off. */
 tdb_status tdb_ingest_snapshot(tdb_handle h, const void* V_dev, void* stream);
+
+/* Read the newest enqueued step's decision and act on it (see tdb_ingest_snapshot);
+ * afterwards every step is complete and the statistics are those of the last one.
+ * No effect when nothing is pending. TDB_ENUMERIC if that step's error is not finite. */
+tdb_status tdb_flush(tdb_handle h);
 
 /* Copy the current ranks, core and bases to the host. ranks_out: TDB_MAX_ORDER ints
  * (may be NULL). C_host (prod r_n doubles) and U_host[n] (N_n x r_n row-major) may

@@ -19,6 +19,7 @@ struct FPassArgs {
   const void *B1, *B2, *B3;  // weighted bases, compute type, packed (ld = r)
   const void *P1, *P2, *P3;  // pseudo-inverses, compute type
   void* part;                // tiles x slot partials
+  const int* hold;           // the controller's hold flag (the pass does nothing while set)
 };
 
 struct FReduceArgs {

@@ -59,7 +59,7 @@ __device__ __forceinline__ double sum_strided(const T* __restrict__ p, long long
 // neighbouring partials of the same tile.
 template <typename T>
 __device__ __forceinline__ void freduce_body(const FReduceArgs& a, int stage, CtrlState* ctrl, int bx, int gx) {
-  if (stage == 2 && ctrl->numeric) return;
+  if (ctrl->hold || (stage == 2 && ctrl->numeric)) return;
   // A singular core found while preparing this step (bit 4, set by k_fpost) belongs
   // to this step's first stage, like the failure of its pseudo-inverse would.
   if (stage == 1 && bx == 0 && threadIdx.x == 0 && (ctrl->numeric & 4)) ctrl->numeric = 1;
@@ -250,7 +250,7 @@ template <typename T>
 __device__ __forceinline__ void fmprep_body(const FFinishArgs& a, int stage, CtrlState* ctrl, int bx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
-  if (stage == 2 && ctrl->numeric) return;
+  if (ctrl->hold || (stage == 2 && ctrl->numeric)) return;
   const int n = bx;
   const int rr = a.r[n];
   if (rr >= a.N[n]) return;
@@ -285,7 +285,7 @@ template <typename T>
 __device__ __forceinline__ void ffinish_body(const FFinishArgs& a, int stage, CtrlState* ctrl, int bx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
-  if (stage == 2 && ctrl->numeric) return;
+  if (ctrl->hold || (stage == 2 && ctrl->numeric)) return;
   const double inv_dt = 1.0 / a.dt;
   if ((int)bx < a.rowblocks) {
     // M_n (r_n x r_n) into LDS: formed once per stage by k_fmprep, or here (a single
@@ -439,6 +439,7 @@ __device__ __forceinline__ void fqr_body(const FQrArgs& a, CtrlState* ctrl, int 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
   __shared__ int last, skip_s, ok_s;
+  if (ctrl->hold) return;   // every block alike, so the completion count stays at zero
   // every block takes part in the completion count, even when there is nothing to do;
   // the flag is read once per block so that the whole block takes the same branch
   if (threadIdx.x == 0)
@@ -613,6 +614,7 @@ __device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, 
   double* lds = reinterpret_cast<double*>(smem_raw);
   __shared__ int pairs[TDB_RCAP + 2];
   __shared__ int order[TDB_RCAP];
+  if (ctrl->hold) return;
   if ((int)bx >= 3) {
     // E[a][i2][i3] = sum_b U2[i2][b] T3[a][b][i3],  T3[a][b][i3] = sum_c C[a][b][c] U3[i3][c]
     const int eb = bx - 3;
@@ -785,6 +787,7 @@ __device__ __forceinline__ void ferr_body(const FErrArgs& a, int bx, int by, int
 
 template <typename TD, typename T>
 __global__ void __launch_bounds__(256) k_ferr(FErrArgs a, CtrlState* ctrl) {
+  if (ctrl->hold) return;
   ferr_body<TD, T>(a, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
@@ -832,9 +835,11 @@ __device__ __forceinline__ void fused_decide(CtrlState* ctrl, const double* cons
   if (threadIdx.x == 0) controller_remove(ctrl);
 }
 
-// One block: fixed-order sum of the error-pass partials, then the controller.
+// One block: fixed-order sum of the error-pass partials, then the controller. A
+// decision other than none raises the hold flag for the host.
 __global__ void __launch_bounds__(256) k_ferr_final(FErrArgs a, CtrlState* ctrl) {
   __shared__ double red[16];
+  if (ctrl->hold) return;
   const int nb = a.gx * a.gy;
   double s0 = 0.0, s1 = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) {
@@ -849,6 +854,7 @@ __global__ void __launch_bounds__(256) k_ferr_final(FErrArgs a, CtrlState* ctrl)
   }
   __syncthreads();
   fused_decide(ctrl, a.G, a.rmax, a.skip, a.would_skip, a.yhat);
+  if (threadIdx.x == 0) ctrl->hold = ctrl->decision != DEC_NONE ? 1 : 0;
 }
 
 // ---------------------------------------------------------------- launchers

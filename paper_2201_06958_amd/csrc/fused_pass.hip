@@ -22,6 +22,7 @@ namespace tdb {
 // ---------------------------------------------------------------- stage pass
 template <typename TD, typename T>
 __device__ __forceinline__ void fpass_body(const FPassArgs& a, int bx) {
+  if (a.hold && *a.hold) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
   const int N2 = a.N2, N3 = a.N3, r1 = a.r1, r2 = a.r2, r3 = a.r3;

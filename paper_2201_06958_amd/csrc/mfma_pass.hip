@@ -92,6 +92,7 @@ __host__ __device__ inline long long mpass_lds_floats(int r1, int r2, int r3, in
 
 template <typename TD, int MF>
 __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
+  if (a.hold && *a.hold) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   float* sm = reinterpret_cast<float*>(smem_raw);
   const int N2 = a.N2, N3 = a.N3, r1 = a.r1, r2 = a.r2, r3 = a.r3, T2 = a.T2;

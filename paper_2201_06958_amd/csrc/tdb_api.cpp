@@ -90,6 +90,16 @@ struct tdb_ctx {
   long long fused_steps = 0, plain_steps = 0;
   bool batch_owned = false;      // lives inside a tdb_batch
   bool sigma_stale = false;      // stats.sigma not refreshed since the last batched step
+  // pipelined ingest (fused path, borrowed snapshots): each call enqueues its step and
+  // then reads the previous step's decision, so the device never waits for the host
+  // between steps; a decision that needs the host holds the steps enqueued after it
+  bool pipelined = false;
+  bool pending = false;          // the newest step's decision has not been read yet
+  const void* Vpend = nullptr;   // its snapshot (kept by the caller until the next call)
+  hipStream_t pend_stream = nullptr;
+  CtrlState* ctrl_hb[2] = {};    // pinned mirrors of the controller state, one per step in flight
+  hipEvent_t ev_ctrl[2] = {};
+  int mirror = 0;                // mirror of the newest step
   // optional pass timing (events recorded on the caller's stream)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -99,8 +109,11 @@ struct tdb_ctx {
     for (auto& v : ev_used)
       for (auto& e : v) { ev_pool.push_back(e.first); ev_pool.push_back(e.second); }
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ev_ctrl)
+      if (e) (void)hipEventDestroy(e);
     for (void* q : allocs) (void)hipFree(q);
-    if (ctrl_h) (void)hipHostFree(ctrl_h);
+    for (CtrlState* m : ctrl_hb)
+      if (m) (void)hipHostFree(m);
   }
 };
 
@@ -353,9 +366,15 @@ tdb_status setup(tdb_ctx* h, const tdb_config* cfg) {
   TRY(dalloc(h, &h->wsB, (size_t)h->S * h->celt));
   TRY(dallocT(h, &h->err_part, 2 * (size_t)h->err_blocks));
   TRY(dalloc(h, reinterpret_cast<void**>(&h->ctrl), sizeof(CtrlState)));
-  {
-    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->ctrl_h), sizeof(CtrlState), hipHostMallocDefault);
+  for (int m = 0; m < 2; ++m) {
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->ctrl_hb[m]), sizeof(CtrlState), hipHostMallocDefault);
     if (e != hipSuccess) { h->err = "hipHostMalloc failed"; return TDB_ENOMEM; }
+    HIPCHK(hipEventCreateWithFlags(&h->ev_ctrl[m], hipEventDisableTiming));
+  }
+  h->ctrl_h = h->ctrl_hb[0];
+  {
+    const char* env = std::getenv("TDB_PIPELINE");
+    h->pipelined = cfg->snapshot_mode == TDB_BORROW && !(env && env[0] == '0');
   }
   // ---- HOSVD buffers
   size_t gpart = 0;
@@ -613,6 +632,8 @@ tdb_status core_sigma(tdb_ctx* h, bool with_vectors, hipStream_t s) {
 template <typename TD>
 tdb_status hosvd_select(tdb_ctx* h, const TD* V, int mode, hipStream_t s) {
   const int p = h->p;
+  // the decision is being acted on: release the steps held behind it
+  HIPCHK(hipMemsetAsync(&h->ctrl->hold, 0, sizeof(int), s));
   EigBatch eb{};
   eb.count = p;
   for (int n = 0; n < p; ++n) {
@@ -944,6 +965,7 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
   fa.slot = pl.slot;
   fa.B1 = h->B[0]; fa.B2 = h->B[1]; fa.B3 = h->B[2];
   fa.part = h->fpart;
+  fa.hold = &h->ctrl->hold;
   A.fa[0] = fa;
   A.fa[0].P1 = h->P[0]; A.fa[0].P2 = h->P[1]; A.fa[0].P3 = h->P[2];
   A.fa[1] = fa;
@@ -1095,17 +1117,9 @@ tdb_status finish_step(tdb_ctx* h, const TD* V1, hipStream_t s) {
   return TDB_OK;
 }
 
+// The kernels of one fused step, enqueued on s (no host synchronisation).
 template <typename TD, typename T>
-tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
-  StepArgs A;
-  tdb_status bs = build_step_args(h, h->r, V1, h->Vprev, A);
-  if (bs == TDB_EUNSUPPORTED) {
-    h->post_valid = false;
-    h->plain_steps += 1;
-    return ingest_impl<TD, T>(h, V1, s);
-  }
-  TRY(bs);
-  h->fused_steps += 1;
+tdb_status enqueue_fused_step(tdb_ctx* h, StepArgs& A, hipStream_t s) {
   if (!h->post_valid) TRY(fused_post<T>(h, s));
   for (int stage = 1; stage <= 2; ++stage) {
     {
@@ -1127,8 +1141,86 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
     PassTimer pt(h, TDB_PASS_ERROR, s, true);
     HIPCHK((launch_ferr<TD, T>(A.ea, h->ctrl, s, pt.start(), pt.stop())));
   }
-  TRY(pull_ctrl(h, s));
-  return finish_step<TD, T>(h, V1, s);
+  return TDB_OK;
+}
+
+// Reads the decision of the newest enqueued step and acts on it (reinitialisation,
+// statistics). Waits only for that step's controller state.
+template <typename TD, typename T>
+tdb_status resolve_step(tdb_ctx* h) {
+  if (!h->pending) return TDB_OK;
+  h->pending = false;
+  HIPCHK(hipEventSynchronize(h->ev_ctrl[h->mirror]));
+  h->ctrl_h = h->ctrl_hb[h->mirror];
+  for (int n = 0; n < h->p; ++n) h->r[n] = h->ctrl_h->ranks[n];
+  return finish_step<TD, T>(h, static_cast<const TD*>(h->Vpend), h->pend_stream);
+}
+
+tdb_status resolve_pending(tdb_ctx* h) {
+  if (!h->pending) return TDB_OK;
+  if (h->data32) return h->f32 ? resolve_step<float, float>(h) : resolve_step<float, double>(h);
+  return h->f32 ? resolve_step<double, float>(h) : resolve_step<double, double>(h);
+}
+
+template <typename TD, typename T>
+tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
+  // work enqueued earlier on another stream comes first
+  if (h->pending && h->pend_stream != s) HIPCHK(hipStreamWaitEvent(s, h->ev_ctrl[h->mirror], 0));
+  StepArgs A;
+  tdb_status bs = build_step_args(h, h->r, V1, h->Vprev, A);
+  if (bs == TDB_EUNSUPPORTED) {
+    TRY(resolve_pending(h));
+    bs = build_step_args(h, h->r, V1, h->Vprev, A);   // the ranks may have changed
+  }
+  if (bs == TDB_EUNSUPPORTED) {
+    h->post_valid = false;
+    h->plain_steps += 1;
+    return ingest_impl<TD, T>(h, V1, s);
+  }
+  TRY(bs);
+  h->fused_steps += 1;
+  if (!h->pipelined) {
+    TRY((enqueue_fused_step<TD, T>(h, A, s)));
+    TRY(pull_ctrl(h, s));
+    return finish_step<TD, T>(h, V1, s);
+  }
+  // Pipelined: enqueue this step, then read the previous one's decision. When that
+  // decision needs the host, this step's kernels find the hold flag raised and do
+  // nothing; the host acts on the decision and enqueues this step again.
+  const int m_new = h->pending ? 1 - h->mirror : h->mirror;
+  auto enqueue = [&](StepArgs& Ax) -> tdb_status {
+    TRY((enqueue_fused_step<TD, T>(h, Ax, s)));
+    HIPCHK(hipMemcpyAsync(h->ctrl_hb[m_new], h->ctrl, sizeof(CtrlState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(h->ev_ctrl[m_new], s));
+    return TDB_OK;
+  };
+  TRY(enqueue(A));
+  if (h->pending) {
+    h->pending = false;
+    HIPCHK(hipEventSynchronize(h->ev_ctrl[h->mirror]));
+    h->ctrl_h = h->ctrl_hb[h->mirror];
+    for (int n = 0; n < h->p; ++n) h->r[n] = h->ctrl_h->ranks[n];
+    const bool acted = h->ctrl_h->decision != DEC_NONE;
+    if (acted) HIPCHK(hipStreamSynchronize(s));   // the held step has drained
+    TRY((finish_step<TD, T>(h, static_cast<const TD*>(h->Vpend), h->pend_stream)));
+    if (acted) {
+      StepArgs A2;
+      tdb_status b2 = build_step_args(h, h->r, V1, h->Vprev, A2);
+      if (b2 == TDB_EUNSUPPORTED) {
+        h->post_valid = false;
+        h->plain_steps += 1;
+        return ingest_impl<TD, T>(h, V1, s);
+      }
+      TRY(b2);
+      TRY(enqueue(A2));
+    }
+  }
+  h->Vprev = V1;
+  h->Vpend = V1;
+  h->pend_stream = s;
+  h->mirror = m_new;
+  h->pending = true;
+  return TDB_OK;
 }
 
 template <typename TD>
@@ -1585,10 +1677,22 @@ tdb_status tdb_ingest_snapshot(tdb_handle h, const void* V_dev, void* stream) {
   return st;
 }
 
+tdb_status tdb_flush(tdb_handle h) {
+  if (!h) { g_create_error = "handle is NULL"; return TDB_EINVAL; }
+  if (!h->ready) { h->err = "handle is not initialised"; return TDB_ESTATE; }
+  TRY(resolve_pending(h));
+  if (!std::isfinite(h->stats.eps)) {
+    h->err = "non-finite reconstruction error (NaN or Inf in the snapshot?)";
+    return TDB_ENUMERIC;
+  }
+  return TDB_OK;
+}
+
 tdb_status tdb_get_core_and_bases(tdb_handle h, int32_t rotate, int32_t* ranks_out, double* C_host,
                                   double* const* U_host) {
   if (!h) { g_create_error = "handle is NULL"; return TDB_EINVAL; }
   if (!h->ready) { h->err = "handle is not initialised"; return TDB_ESTATE; }
+  TRY(resolve_pending(h));
   HIPCHK(hipDeviceSynchronize());
   if (ranks_out)
     for (int n = 0; n < TDB_MAX_ORDER; ++n) ranks_out[n] = n < h->p ? h->r[n] : 0;
@@ -1638,6 +1742,7 @@ tdb_status tdb_get_core_and_bases(tdb_handle h, int32_t rotate, int32_t* ranks_o
 tdb_status tdb_reconstruct(tdb_handle h, void* out_dev, void* stream) {
   if (!h) { g_create_error = "handle is NULL"; return TDB_EINVAL; }
   if (!h->ready) { h->err = "handle is not initialised"; return TDB_ESTATE; }
+  TRY(resolve_pending(h));
   if (!out_dev) { h->err = "out_dev is NULL"; return TDB_EINVAL; }
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (h->f32) {
@@ -1658,6 +1763,7 @@ tdb_status tdb_set_threshold(tdb_handle h, double eps_th, double gamma_th) {
   if (!h) { g_create_error = "handle is NULL"; return TDB_EINVAL; }
   if (!h->ready) { h->err = "handle is not initialised"; return TDB_ESTATE; }
   if (!(eps_th > 0.0) || gamma_th >= 100.0) { h->err = "bad threshold"; return TDB_EINVAL; }
+  TRY(resolve_pending(h));
   HIPCHK(hipDeviceSynchronize());
   HIPCHK(hipMemcpy(h->ctrl_h, h->ctrl, sizeof(CtrlState), hipMemcpyDeviceToHost));
   h->ctrl_h->eps_th = eps_th;
@@ -1673,6 +1779,7 @@ tdb_status tdb_get_stats(tdb_handle h, tdb_stats* out) {
   if (!h) { g_create_error = "handle is NULL"; return TDB_EINVAL; }
   if (!out) { h->err = "out is NULL"; return TDB_EINVAL; }
   if (!h->ready) { h->err = "handle is not initialised"; return TDB_ESTATE; }
+  TRY(resolve_pending(h));
   if (h->sigma_stale) {
     // fused steps form the core singular values only when the controller needs them;
     // the statistics form them on demand from the committed core
@@ -1697,6 +1804,7 @@ void tdb_destroy(tdb_handle h) {
 
 tdb_status tdb_profile_enable(tdb_handle h, int32_t on) {
   if (!h) { g_create_error = "handle is NULL"; return TDB_EINVAL; }
+  TRY(resolve_pending(h));
   HIPCHK(hipDeviceSynchronize());
   for (auto& v : h->ev_used) {
     for (auto& e : v) { h->ev_pool.push_back(e.first); h->ev_pool.push_back(e.second); }
@@ -1709,6 +1817,7 @@ tdb_status tdb_profile_enable(tdb_handle h, int32_t on) {
 tdb_status tdb_profile_read(tdb_handle h, int32_t pass, int64_t* launches, double* total_ms,
                             double* bytes_per_launch) {
   if (!h) { g_create_error = "handle is NULL"; return TDB_EINVAL; }
+  TRY(resolve_pending(h));
   if (pass != TDB_PASS_PROJECT && pass != TDB_PASS_ERROR) { h->err = "bad pass id"; return TDB_EINVAL; }
   double ms = 0.0;
   for (auto& e : h->ev_used[pass]) {

@@ -52,6 +52,8 @@ struct CtrlState {
   int gated;          // the learned gate skipped this step's error pass
   int would_skip;     // the gate's verdict (also when it only observes)
   double eps_pred;    // the gate's predicted error of this step (NaN without one)
+  int hold;           // a decision awaits the host: the fused kernels of a step enqueued
+                      // after it do nothing until the host has acted and cleared it
 };
 
 __device__ __forceinline__ double warp_sum(double v) {

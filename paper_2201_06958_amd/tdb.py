@@ -96,6 +96,7 @@ def load_library(path: str = LIB_PATH):
                                           ctypes.POINTER(ctypes.POINTER(ctypes.c_double)), P,
                                           ctypes.POINTER(H)]
     lib.tdb_ingest_snapshot.argtypes = [H, P, P]
+    lib.tdb_flush.argtypes = [H]
     lib.tdb_get_core_and_bases.argtypes = [H, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.POINTER(ctypes.c_double))]
@@ -136,7 +137,7 @@ def load_library(path: str = LIB_PATH):
     lib.tdb_batch_destroy.restype = None
     lib.tdb_batch_last_error.argtypes = [H]
     lib.tdb_batch_last_error.restype = ctypes.c_char_p
-    for name in ("tdb_init", "tdb_init_from_factors", "tdb_ingest_snapshot", "tdb_get_core_and_bases",
+    for name in ("tdb_init", "tdb_init_from_factors", "tdb_ingest_snapshot", "tdb_flush", "tdb_get_core_and_bases",
                  "tdb_reconstruct", "tdb_set_threshold", "tdb_get_stats", "tdb_batch_create",
                  "tdb_batch_ingest", "tdb_batch_stream", "tdb_batch_profile_enable",
                  "tdb_batch_profile_read", "tdb_batch_gate_attach", "tdb_gate_create", "tdb_gate_set_params",
@@ -227,6 +228,11 @@ class Compressor:
 
     def ingest(self, V, stream=None):
         self._check(self.lib.tdb_ingest_snapshot(self.h, _dev_ptr(V), _stream_ptr(stream)))
+
+    def flush(self):
+        """Act on the newest enqueued step's decision (borrowed snapshots pipeline the
+        ingest: a step's decision is otherwise read by the next call)."""
+        self._check(self.lib.tdb_flush(self.h))
 
     def ranks(self):
         r = (ctypes.c_int32 * MAX_ORDER)()

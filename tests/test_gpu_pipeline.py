@@ -1,0 +1,99 @@
+"""Pipelined ingest (borrowed snapshots, fused path): each call enqueues its step and
+reads the previous step's decision afterwards. The result must be the synchronous
+ingest's, bit for bit, including across add, removal and reinitialisation events, and
+whichever calls happen to read the decisions."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from streams import plume_spec, switched_term_spec
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2201_06958_amd import load_library
+    load_library()
+
+
+def _switched():
+    t_on, t_peak, t_low, h_min = 0.05, 0.15, 0.35, 0.002
+
+    def h(t):
+        if t <= t_on:
+            return 0.0
+        if t <= t_peak:
+            return 2.0 * (t - t_on)
+        if t <= t_low:
+            return 0.2 + (h_min - 0.2) * (t - t_peak) / (t_low - t_peak)
+        return h_min
+
+    return switched_term_spec(steps=140, profile=h, profile2=lambda t: 0.004 * math.exp(-t))
+
+
+def _run(sp, snaps, mode, precision, read_every, rank_max=None):
+    """Ingest every snapshot; read the statistics after every `read_every`-th call
+    (0: only at the end). Returns (events seen, final stats, ranks, core, bases)."""
+    from paper_2201_06958_amd import Compressor
+    g = Compressor(sp.dims, sp.dt, rank_max=rank_max or sp.rank_max, rank_init=sp.rank_init, weights=sp.weights,
+                   data_dtype=sp.storage, precision=precision, path="fused", adaptive=sp.adaptive,
+                   eps_th=sp.eps_th if sp.eps_th > 0 else 1.0, snapshot_mode=mode)
+    g.init(snaps[0])
+    events = []
+    for k in range(1, len(snaps)):
+        g.ingest(snaps[k])
+        if read_every and k % read_every == 0:
+            st = g.stats()
+            if st["event"]:
+                events.append((k, st["event"], st["ranks"]))
+    g.flush()
+    st = g.stats()
+    r, C, U = g.get_core_and_bases()
+    g.close()
+    return events, st, r, C, U
+
+
+def _same(a, b):
+    ea, sa, ra, Ca, Ua = a
+    eb, sb, rb, Cb, Ub = b
+    assert ra == rb
+    assert np.array_equal(Ca, Cb)
+    for x, y in zip(Ua, Ub):
+        assert np.array_equal(x, y)
+    for key in ("eps", "nu", "n_add", "n_remove", "n_reinit", "n_numeric", "crbar"):
+        assert sa[key] == sb[key], key
+
+
+def test_pipelined_switched_stream_matches_synchronous():
+    sp = _switched()
+    _say("case pipelined ingest, switched-term stream 140 steps, fused FP64")
+    snaps = [torch.from_numpy(np.ascontiguousarray(sp.snapshot_np(k))).to("cuda") for k in range(sp.steps + 1)]
+    torch.cuda.synchronize()
+    sync_each = _run(sp, snaps, "copy", "f64", 1)
+    assert sync_each[1]["n_add"] >= 1 and sync_each[1]["n_remove"] >= 1, "the stream must exercise both events"
+    pipe_each = _run(sp, snaps, "borrow", "f64", 1)
+    assert pipe_each[0] == sync_each[0]
+    _same(pipe_each, sync_each)
+    for every in (0, 7):
+        _same(_run(sp, snaps, "borrow", "f64", every), sync_each)
+    _say("  events", sync_each[0])
+
+
+def test_pipelined_plume_fp32_matches_synchronous():
+    sp = plume_spec(nx=128, ny=64, nv=8, steps=30)
+    _say("case pipelined ingest, plume 128x64x8 FP32 30 steps")
+    snaps = [torch.from_numpy(np.ascontiguousarray(sp.snapshot_np(k))).to("cuda") for k in range(sp.steps + 1)]
+    torch.cuda.synchronize()
+    ref = _run(sp, snaps, "copy", "f32", 1, rank_max=(32, 32, 8))
+    _same(_run(sp, snaps, "borrow", "f32", 0, rank_max=(32, 32, 8)), ref)
