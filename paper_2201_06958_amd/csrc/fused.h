@@ -176,9 +176,12 @@ hipError_t launch_batch_mpass(const FPassArgs* tab, const void* const* v1, const
 template <typename T>
 hipError_t launch_batch_freduce(const FReduceArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, int stage,
                                 hipStream_t s);
+// Roles of the finish and post-step kernels: the whole kernel (one stream), or one of
+// its two block kinds launched on its own (a batch).
+enum { ROLE_ALL = 0, ROLE_ROWS = 1, ROLE_PINV = 2, ROLE_MODES = 1, ROLE_EXP = 2 };
 template <typename T>
 hipError_t launch_batch_ffinish(const FFinishArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, int stage,
-                                size_t lds, hipStream_t s);
+                                size_t lds, int role, hipStream_t s);
 template <typename T>
 hipError_t launch_batch_fmprep(const FFinishArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, int stage,
                                size_t lds, hipStream_t s);
@@ -186,7 +189,7 @@ hipError_t launch_batch_fqr(const FQrArgs* tab, CtrlState* const* ctab, BatchMap
                             hipStream_t s);
 template <typename T>
 hipError_t launch_batch_fpost(const FPostArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, size_t lds,
-                              hipStream_t s);
+                              int role, hipStream_t s);
 template <typename TD, typename T>
 hipError_t launch_batch_ferr(const FErrArgs* tab, const void* const* v1, BatchMap m, int blocks, int nstreams,
                              CtrlState* const* ctab, BatchSummary* out, size_t lds_final, hipStream_t s,

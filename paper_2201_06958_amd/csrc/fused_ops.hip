@@ -280,18 +280,20 @@ __global__ void __launch_bounds__(256) k_fmprep(FFinishArgs a, CtrlState* ctrl) 
 // Blocks [0, rowblocks): rows of every mode: U_dot = (H - U M)/dt, Heun update and,
 // in stage 1, the weighted basis B_n = W_n U* of the next stage.
 // Blocks [rowblocks, rowblocks + 3) (stage 1 only): pseudo-inverse P_n at the stage
-// core C* (already updated by the reduction).
-template <typename T>
+// core C* (already updated by the reduction). A batch launches the two roles as
+// separate kernels (ROLE_ROWS, ROLE_PINV: block bx is mode bx), so that the row blocks
+// do not carry the factorisation's registers.
+template <typename T, int ROLE>
 __device__ __forceinline__ void ffinish_body(const FFinishArgs& a, int stage, CtrlState* ctrl, int bx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
   if (ctrl->hold || (stage == 2 && ctrl->numeric)) return;
   const double inv_dt = 1.0 / a.dt;
-  if ((int)bx < a.rowblocks) {
+  if (ROLE == ROLE_ROWS || (ROLE == ROLE_ALL && (int)bx < a.rowblocks)) {
     // M_n (r_n x r_n) into LDS: formed once per stage by k_fmprep, or here (a single
     // stream, where the extra launch would cost more than the repeated small product)
     double* Ml[3];
-    if (a.m_inline) {
+    if (ROLE == ROLE_ALL && a.m_inline) {   // (a batch forms M_n in its own kernel)
       const double* cd = stage == 1 ? a.kC : a.Cdot2;   // this stage's C_dot
       const int csz = a.r[0] * a.r[1] * a.r[2];
       double* cdl = lds;
@@ -388,8 +390,9 @@ __device__ __forceinline__ void ffinish_body(const FFinishArgs& a, int stage, Ct
     }
     return;
   }
+  if (ROLE == ROLE_ROWS) return;
   // pseudo-inverse at the stage core
-  const int n = bx - a.rowblocks;
+  const int n = ROLE == ROLE_PINV ? bx : bx - a.rowblocks;
   const int rn = a.r[n];
   if (rn >= a.N[n]) return;
   long long inner = 1, R = 1, csz = 1;
@@ -426,7 +429,7 @@ __device__ __forceinline__ void ffinish_body(const FFinishArgs& a, int stage, Ct
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_ffinish(FFinishArgs a, CtrlState* ctrl) {
-  ffinish_body<T>(a, a.stage, ctrl, blockIdx.x);
+  ffinish_body<T, ROLE_ALL>(a, a.stage, ctrl, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- QR + fold
@@ -607,17 +610,18 @@ __global__ void __launch_bounds__(256) k_fqr(FQrArgs a, CtrlState* ctrl) {
 // its eigenvalues when asked for (core singular values) and the pseudo-inverse P_n for
 // the next stage 1. Blocks [3, 3 + eblocks): the partial expansion E = C x_2 U_2 x_3 U_3
 // used by the error pass, the mode-1 basis in the compute type and the weighted bases
-// B_n of the next stage 1.
-template <typename T>
+// B_n of the next stage 1. A batch launches the two roles as separate kernels
+// (ROLE_MODES: block bx is mode bx; ROLE_EXP: block bx is expansion block bx).
+template <typename T, int ROLE>
 __device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, int bx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
   __shared__ int pairs[TDB_RCAP + 2];
   __shared__ int order[TDB_RCAP];
   if (ctrl->hold) return;
-  if ((int)bx >= 3) {
+  if (ROLE == ROLE_EXP || (ROLE == ROLE_ALL && (int)bx >= 3)) {
     // E[a][i2][i3] = sum_b U2[i2][b] T3[a][b][i3],  T3[a][b][i3] = sum_c C[a][b][c] U3[i3][c]
-    const int eb = bx - 3;
+    const int eb = ROLE == ROLE_EXP ? bx : bx - 3;
     const int r1 = a.r[0], r2 = a.r[1], r3 = a.r[2];
     const long long N2 = a.N[1], N3 = a.N[2];
     double* T3 = lds;                                   // r1*r2*N3
@@ -676,6 +680,7 @@ __device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, 
     }
     return;
   }
+  if (ROLE == ROLE_EXP) return;
   const int n = bx;
   const int rn = a.r[n];
   long long inner = 1, R = 1, csz = 1;
@@ -726,7 +731,7 @@ __device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, 
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_fpost(FPostArgs a, CtrlState* ctrl) {
-  fpost_body<T>(a, ctrl, blockIdx.x);
+  fpost_body<T, ROLE_ALL>(a, ctrl, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- error pass
@@ -935,11 +940,11 @@ __global__ void __launch_bounds__(256) kb_freduce(const FReduceArgs* __restrict_
   freduce_body<T>(tab[s], stage, ctab[s], blockIdx.x - b0, m.start[s + 1] - b0);
 }
 
-template <typename T>
+template <typename T, int ROLE>
 __global__ void __launch_bounds__(256) kb_ffinish(const FFinishArgs* __restrict__ tab, CtrlState* const* ctab,
                                                   BatchMap m, int stage) {
   const int s = m.sid[blockIdx.x];
-  ffinish_body<T>(tab[s], stage, ctab[s], blockIdx.x - m.start[s]);
+  ffinish_body<T, ROLE>(tab[s], stage, ctab[s], blockIdx.x - m.start[s]);
 }
 
 template <typename T>
@@ -955,11 +960,11 @@ __global__ void __launch_bounds__(256) kb_fqr(const FQrArgs* __restrict__ tab, C
   fqr_body(tab[s], ctab[s], blockIdx.x - b0, m.start[s + 1] - b0);
 }
 
-template <typename T>
+template <typename T, int ROLE>
 __global__ void __launch_bounds__(256) kb_fpost(const FPostArgs* __restrict__ tab, CtrlState* const* ctab,
                                                 BatchMap m) {
   const int s = m.sid[blockIdx.x];
-  fpost_body<T>(tab[s], ctab[s], blockIdx.x - m.start[s]);
+  fpost_body<T, ROLE>(tab[s], ctab[s], blockIdx.x - m.start[s]);
 }
 
 template <typename TD, typename T>
@@ -1021,17 +1026,20 @@ template hipError_t launch_batch_freduce<double>(const FReduceArgs*, CtrlState* 
 
 template <typename T>
 hipError_t launch_batch_ffinish(const FFinishArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, int stage,
-                                size_t lds, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute((const void*)kb_ffinish<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
+                                size_t lds, int role, hipStream_t s) {
+  const void* f = role == ROLE_PINV ? (const void*)kb_ffinish<T, ROLE_PINV> : (const void*)kb_ffinish<T, ROLE_ROWS>;
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kb_ffinish<T>, dim3(blocks), dim3(256), lds, s, tab, ctab, m, stage);
+  if (role == ROLE_PINV)
+    hipLaunchKernelGGL((kb_ffinish<T, ROLE_PINV>), dim3(blocks), dim3(256), lds, s, tab, ctab, m, stage);
+  else
+    hipLaunchKernelGGL((kb_ffinish<T, ROLE_ROWS>), dim3(blocks), dim3(256), lds, s, tab, ctab, m, stage);
   return hipGetLastError();
 }
 template hipError_t launch_batch_ffinish<float>(const FFinishArgs*, CtrlState* const*, BatchMap, int, int, size_t,
-                                                hipStream_t);
+                                                int, hipStream_t);
 template hipError_t launch_batch_ffinish<double>(const FFinishArgs*, CtrlState* const*, BatchMap, int, int, size_t,
-                                                 hipStream_t);
+                                                 int, hipStream_t);
 
 template <typename T>
 hipError_t launch_batch_fmprep(const FFinishArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, int stage,
@@ -1057,14 +1065,20 @@ hipError_t launch_batch_fqr(const FQrArgs* tab, CtrlState* const* ctab, BatchMap
 
 template <typename T>
 hipError_t launch_batch_fpost(const FPostArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, size_t lds,
-                              hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute((const void*)kb_fpost<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                              int role, hipStream_t s) {
+  const void* f = role == ROLE_EXP ? (const void*)kb_fpost<T, ROLE_EXP> : (const void*)kb_fpost<T, ROLE_MODES>;
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kb_fpost<T>, dim3(blocks), dim3(256), lds, s, tab, ctab, m);
+  if (role == ROLE_EXP)
+    hipLaunchKernelGGL((kb_fpost<T, ROLE_EXP>), dim3(blocks), dim3(256), lds, s, tab, ctab, m);
+  else
+    hipLaunchKernelGGL((kb_fpost<T, ROLE_MODES>), dim3(blocks), dim3(256), lds, s, tab, ctab, m);
   return hipGetLastError();
 }
-template hipError_t launch_batch_fpost<float>(const FPostArgs*, CtrlState* const*, BatchMap, int, size_t, hipStream_t);
-template hipError_t launch_batch_fpost<double>(const FPostArgs*, CtrlState* const*, BatchMap, int, size_t, hipStream_t);
+template hipError_t launch_batch_fpost<float>(const FPostArgs*, CtrlState* const*, BatchMap, int, size_t, int,
+                                              hipStream_t);
+template hipError_t launch_batch_fpost<double>(const FPostArgs*, CtrlState* const*, BatchMap, int, size_t, int,
+                                               hipStream_t);
 
 template <typename TD, typename T>
 hipError_t launch_batch_ferr(const FErrArgs* tab, const void* const* v1, BatchMap m, int blocks, int nstreams,

@@ -1290,9 +1290,10 @@ struct tdb_batch_ctx {
   const void **d_v1 = nullptr, **d_v0 = nullptr, **h_v1 = nullptr, **h_v0 = nullptr;
   BatchSummary *d_sum = nullptr, *h_sum = nullptr;
   // block maps (fixed at creation: grids are sized at the caps)
-  BatchMap m_pass{}, m_red{}, m_fin[2]{}, m_qr{}, m_post{}, m_err{};
-  int g_pass = 0, g_red = 0, g_fin[2] = {0, 0}, g_qr = 0, g_post = 0, g_err = 0;
+  BatchMap m_pass{}, m_red{}, m_fin[2]{}, m_qr{}, m_post{}, m_exp{}, m_err{};
+  int g_pass = 0, g_red = 0, g_fin[2] = {0, 0}, g_qr = 0, g_post = 0, g_exp = 0, g_err = 0;
   size_t lds_pass = 0, lds_fin = 0, lds_qr = 0, lds_post = 0, lds_mprep = 0, lds_final = 0;
+  size_t lds_rows = 0, lds_exp = 0;   // row blocks of the finish, expansion blocks of the post-step
   int mflavor = 0;                  // MPASS_* of the batched stage pass (one for all streams)
   double bytes_pass = 0.0, bytes_err = 0.0;
   bool dirty = true;
@@ -1447,7 +1448,7 @@ tdb_status batch_setup(tdb_batch_ctx* b) {
       for (int i = 0; i < n; ++i) b->st[i]->no_mfma = true;
     b->mflavor = mixed ? 0 : first;
   }
-  std::vector<int> c_pass(n), c_red(n), c_fin0(n), c_fin1(n), c_qr(n, 3), c_post(n), c_err(n);
+  std::vector<int> c_pass(n), c_red(n), c_fin0(n), c_fin1(n), c_qr(n, 3), c_post(n), c_exp(n), c_err(n);
   for (int i = 0; i < n; ++i) {
     tdb_ctx* h = b->st[i];
     StepArgs A;
@@ -1464,7 +1465,15 @@ tdb_status batch_setup(tdb_batch_ctx* b) {
     c_fin0[i] = A.blocks_fin[0];
     c_fin1[i] = A.blocks_fin[1];
     c_post[i] = A.blocks_post;
+    c_exp[i] = A.pa.eblocks;
     c_err[i] = A.blocks_err;
+    {
+      long long msum = 0;
+      for (int k = 0; k < 3; ++k) msum += (long long)h->caps[k] * h->caps[k];
+      b->lds_rows = std::max(b->lds_rows, (size_t)msum * 8);
+      const long long per = (h->N[1] + A.pa.eblocks - 1) / A.pa.eblocks;
+      b->lds_exp = std::max(b->lds_exp, ((size_t)h->caps[0] * h->caps[1] * (size_t)h->N[2] + (size_t)per * h->caps[1]) * 8);
+    }
     b->lds_pass = std::max(b->lds_pass, pc.lds);
     b->lds_fin = std::max(b->lds_fin, A.lds_fin);
     b->lds_qr = std::max(b->lds_qr, A.lds_qr);
@@ -1480,6 +1489,7 @@ tdb_status batch_setup(tdb_batch_ctx* b) {
   TRY(make_map(b, c_fin1, &b->m_fin[1], &b->g_fin[1]));
   TRY(make_map(b, c_qr, &b->m_qr, &b->g_qr));
   TRY(make_map(b, c_post, &b->m_post, &b->g_post));
+  TRY(make_map(b, c_exp, &b->m_exp, &b->g_exp));
   TRY(make_map(b, c_err, &b->m_err, &b->g_err));
   const size_t nn = (size_t)n;
   TRY(balloc(b, &b->d_fa[0], &b->h_fa[0], nn));
@@ -1526,10 +1536,15 @@ tdb_status batch_step(tdb_batch_ctx* b, const void* const* V, hipStream_t s) {
                                          e1)));
     BHIPCHK(launch_batch_freduce<T>(b->d_ra, b->d_ctab, b->m_red, b->g_red, st + 1, s));
     BHIPCHK(launch_batch_fmprep<T>(b->d_ga[st], b->d_ctab, b->m_qr, b->g_qr, st + 1, b->lds_mprep, s));
-    BHIPCHK(launch_batch_ffinish<T>(b->d_ga[st], b->d_ctab, b->m_fin[st], b->g_fin[st], st + 1, b->lds_fin, s));
+    // the row blocks (both stages) and the stage-1 pseudo-inverses as separate kernels
+    BHIPCHK(launch_batch_ffinish<T>(b->d_ga[st], b->d_ctab, b->m_fin[1], b->g_fin[1], st + 1, b->lds_rows, ROLE_ROWS,
+                                    s));
+    if (st == 0)
+      BHIPCHK(launch_batch_ffinish<T>(b->d_ga[st], b->d_ctab, b->m_qr, b->g_qr, st + 1, b->lds_fin, ROLE_PINV, s));
   }
   BHIPCHK(launch_batch_fqr(b->d_qa, b->d_ctab, b->m_qr, b->g_qr, b->lds_qr, s));
-  BHIPCHK(launch_batch_fpost<T>(b->d_pa, b->d_ctab, b->m_post, b->g_post, b->lds_post, s));
+  BHIPCHK(launch_batch_fpost<T>(b->d_pa, b->d_ctab, b->m_qr, b->g_qr, b->lds_post, ROLE_MODES, s));
+  BHIPCHK(launch_batch_fpost<T>(b->d_pa, b->d_ctab, b->m_exp, b->g_exp, b->lds_exp, ROLE_EXP, s));
   if (b->gate_mode != GATE_OFF) {
     GateStepArgs g{};
     g.params = b->gate_params;
