@@ -3,7 +3,9 @@
 // entries (the variables / species / components mode of the target workloads).
 //
 // Tile: 16 rows of mode 1 x T2 (16, 32 or 64) rows of mode 2 x all N3 of mode 3;
-// 4 waves. The pseudo-inverses are staged in LDS with the tile when they fit.
+// 4 waves. The pseudo-inverses are staged in LDS with the tile when they fit. Z and D
+// are kept in LDS as [c][i2][i1] with the mode-1 index XOR-swizzled by the low bits of
+// i2, so that the operand reads of every product below fall in distinct LDS banks.
 //   Z[c2][i1][i2] = sum_c D[i1][i2][c] B3[c][c2]        (VALU, from the loaded fibers)
 //   Y[c][i1][b]   = sum_i2 D[c][i1][i2] B2[i2][b]      (only if mode 3 is not full rank)
 //   F1[i1][b,c2]  = sum_i2 Z[c2][i1][i2] B2[i2][b]
@@ -25,12 +27,11 @@ namespace tdb {
 typedef float mf4 __attribute__((ext_vector_type(4)));
 typedef __bf16 mbf8 __attribute__((ext_vector_type(8)));
 
-// One 16 x 16 block C += A B over K (valid K entries Kv): A(m, k) = A[m*sam + k*sak]
-// for m < Mv, B(k, n) = B[k*sbk + n*sbn] for n < Nv, zero elsewhere. Lane l feeds
-// row/column l % 16 and the K slice selected by l / 16.
-template <int MF>
-__device__ __forceinline__ mf4 mma_block(const float* A, int sam, int sak, int Mv, const float* B, int sbk, int sbn,
-                                         int Nv, int Kv, mf4 acc) {
+// One 16 x 16 block C += A B over K (valid K entries Kv): A(m, k) = fa(m, k) for
+// m < Mv, B(k, n) = fb(k, n) for n < Nv, zero elsewhere. Lane l feeds row/column
+// l % 16 and the K slice selected by l / 16.
+template <int MF, typename FA, typename FB>
+__device__ __forceinline__ mf4 mma_blockf(FA fa, int Mv, FB fb, int Nv, int Kv, mf4 acc) {
   const int l = threadIdx.x & 63;
   const int mn = l & 15, kg = l >> 4;
   const bool am = mn < Mv, bn = mn < Nv;
@@ -38,8 +39,8 @@ __device__ __forceinline__ mf4 mma_block(const float* A, int sam, int sak, int M
 #pragma unroll 4
     for (int k0 = 0; k0 < Kv; k0 += 4) {
       const int k = k0 + kg;
-      const float a = (am && k < Kv) ? A[mn * sam + k * sak] : 0.0f;
-      const float b = (bn && k < Kv) ? B[k * sbk + mn * sbn] : 0.0f;
+      const float a = (am && k < Kv) ? fa(mn, k) : 0.0f;
+      const float b = (bn && k < Kv) ? fb(k, mn) : 0.0f;
       acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
     }
   } else {
@@ -48,8 +49,8 @@ __device__ __forceinline__ mf4 mma_block(const float* A, int sam, int sak, int M
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int k = k0 + 8 * kg + j;
-        const float a = (am && k < Kv) ? A[mn * sam + k * sak] : 0.0f;
-        const float b = (bn && k < Kv) ? B[k * sbk + mn * sbn] : 0.0f;
+        const float a = (am && k < Kv) ? fa(mn, k) : 0.0f;
+        const float b = (bn && k < Kv) ? fb(k, mn) : 0.0f;
         const __bf16 a1 = (__bf16)a, b1 = (__bf16)b;
         ah[j] = a1;
         al[j] = (__bf16)(a - (float)a1);
@@ -63,6 +64,19 @@ __device__ __forceinline__ mf4 mma_block(const float* A, int sam, int sak, int M
   }
   return acc;
 }
+
+// The same with strided operands: A(m, k) = A[m*sam + k*sak], B(k, n) = B[k*sbk + n*sbn].
+template <int MF>
+__device__ __forceinline__ mf4 mma_block(const float* A, int sam, int sak, int Mv, const float* B, int sbk, int sbn,
+                                         int Nv, int Kv, mf4 acc) {
+  return mma_blockf<MF>([&](int m, int k) { return A[m * sam + k * sak]; }, Mv,
+                        [&](int k, int n) { return B[k * sbk + n * sbn]; }, Nv, Kv, acc);
+}
+
+// Z and D slices in LDS: entry (i1, i2) of a 16 x T2 slice at i2*16 + (i1 ^ (i2 & 15)).
+// Reading a 16-row column block along i2 (F1, Y) or a 16-column row block along i1
+// (F2) then touches 64 distinct banks per instruction, with no padding.
+__device__ __forceinline__ int zsw(int i1, int i2) { return i2 * 16 + (i1 ^ (i2 & 15)); }
 
 // Store a 16 x 16 block: lane l holds rows 4*(l/16) + i, column l % 16.
 __device__ __forceinline__ void store_block(const mf4& acc, float* C, int scm, int scn, int Mv, int Nv) {
@@ -102,8 +116,9 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
   const int R1 = r2 * r3, R2 = r1 * r3, R3 = r1 * r2;
   const bool f3 = a.need_f3 != 0;
   const int TS = 16 * T2;                  // fibers per tile
-  float* Zs = sm;                          // r3 x 16 x T2
-  float* B1s = Zs + r3 * TS;               // 16 x r1
+  const int ZS = TS;                       // LDS floats of one Z (or D) slice
+  float* Zs = sm;                          // r3 x (T2 x 16, swizzled)
+  float* B1s = Zs + r3 * ZS;               // 16 x r1
   float* B2s = B1s + 16 * r1;              // T2 x r2
   float* B3s = B2s + T2 * r2;              // N3 x r3 (<= 64)
   float* F1s = B3s + 64;                   // 16 x R1
@@ -114,7 +129,7 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
   float* pend = Pp;
   if (a.stage_p) pend += (a.need_h1 ? R1 * r1 : 0) + (a.need_h2 ? R2 * r2 : 0) + (f3 ? R3 * r3 : 0);
   float* Ys = pend;                        // N3 x 16 x r2 (f3)
-  float* X = Ys + (f3 ? N3 * 16 * r2 : 0); // D (N3 x 16 x T2), later F2 (T2 x R2) | F3 (R3 x N3)
+  float* X = Ys + (f3 ? N3 * 16 * r2 : 0); // D (N3 x T2 x 16), later F2 (T2 x R2) | F3 (R3 x N3)
   float* Ds = X;
   float* F2s = X;
   float* F3s = X + T2 * R2;
@@ -171,15 +186,16 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
   for (int u = 0; u < 4; ++u) {
     if (u >= per) break;
     const int q = tid + 256 * u;
+    const int zo = zsw(q / T2, q - (q / T2) * T2);
     for (int c2 = 0; c2 < r3; ++c2) {
       float s = 0.0f;
 #pragma unroll
       for (int c = 0; c < 8; ++c)
         if (c < N3) s += d[u][c] * B3s[c * r3 + c2];
-      Zs[c2 * TS + q] = s;
+      Zs[c2 * ZS + zo] = s;
     }
     if (f3)
-      for (int c = 0; c < N3; ++c) Ds[c * TS + q] = d[u][c];
+      for (int c = 0; c < N3; ++c) Ds[c * ZS + zo] = d[u][c];
   }
   __syncthreads();
   const int nb1 = (r1 + 15) >> 4, nb2 = (r2 + 15) >> 4;
@@ -190,12 +206,18 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
       mf4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
       if (blk < nF1) {
         const int c2 = blk / nb2, jb = blk - c2 * nb2;
-        acc = mma_block<MF>(Zs + c2 * TS, T2, 1, 16, B2s + 16 * jb, r2, 1, r2 - 16 * jb, T2, acc);
+        const float* Zc = Zs + c2 * ZS;
+        const float* Bb = B2s + 16 * jb;
+        acc = mma_blockf<MF>([&](int m, int k) { return Zc[zsw(m, k)]; }, 16,
+                             [&](int k, int n) { return Bb[k * r2 + n]; }, r2 - 16 * jb, T2, acc);
         store_block(acc, F1s + (16 * jb) * r3 + c2, R1, r3, 16, r2 - 16 * jb);
       } else {
         const int q = blk - nF1;
         const int c = q / nb2, jb = q - c * nb2;
-        acc = mma_block<MF>(Ds + c * TS, T2, 1, 16, B2s + 16 * jb, r2, 1, r2 - 16 * jb, T2, acc);
+        const float* Dc = Ds + c * ZS;
+        const float* Bb = B2s + 16 * jb;
+        acc = mma_blockf<MF>([&](int m, int k) { return Dc[zsw(m, k)]; }, 16,
+                             [&](int k, int n) { return Bb[k * r2 + n]; }, r2 - 16 * jb, T2, acc);
         store_block(acc, Ys + c * 16 * r2 + 16 * jb, r2, 1, 16, r2 - 16 * jb);
       }
     }
@@ -211,7 +233,11 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
         const int c2 = blk / (nb1 * nib), rem = blk - c2 * nb1 * nib;
         const int ab = rem / nib, ib = rem - ab * nib;
         // rows a (B1^T), columns i2 (Z[c2]), K = i1
-        acc = mma_block<MF>(B1s + 16 * ab, 1, r1, r1 - 16 * ab, Zs + c2 * TS + 16 * ib, T2, 1, 16, 16, acc);
+        const float* Zc = Zs + c2 * ZS;
+        const float* Ab = B1s + 16 * ab;
+        const int i20 = 16 * ib;
+        acc = mma_blockf<MF>([&](int m, int k) { return Ab[m + k * r1]; }, r1 - 16 * ab,
+                             [&](int k, int n) { return Zc[zsw(k, i20 + n)]; }, 16, 16, acc);
         // F2s[i2][a*r3 + c2]
         store_block(acc, F2s + (16 * ib) * R2 + (16 * ab) * r3 + c2, r3, R2, r1 - 16 * ab, 16);
       } else {
