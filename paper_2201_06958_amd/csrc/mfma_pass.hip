@@ -27,21 +27,54 @@ namespace tdb {
 typedef float mf4 __attribute__((ext_vector_type(4)));
 typedef __bf16 mbf8 __attribute__((ext_vector_type(8)));
 
-// One 16 x 16 block C += A B over K (valid K entries Kv): A(m, k) = fa(m, k) for
-// m < Mv, B(k, n) = fb(k, n) for n < Nv, zero elsewhere. Lane l feeds row/column
-// l % 16 and the K slice selected by l / 16.
+// One 16 x 16 block C += A B over K (valid K entries Kv): A(m, k) = fa(m, k0, j) and
+// B(k, n) = fb(k0, j, n) with k = k0 + j, k0 a multiple of 16 and j < 16, for m < Mv,
+// n < Nv, zero elsewhere. Lane l feeds row/column l % 16 and the K slice selected by
+// l / 16. Operand reads are never predicated: lanes outside the block read a valid
+// entry (indices clamped into the block) and zero it, so each group of 16 K entries
+// is loaded in one go, and the next group while the current one's matrix
+// instructions run.
 template <int MF, typename FA, typename FB>
 __device__ __forceinline__ mf4 mma_blockf(FA fa, int Mv, FB fb, int Nv, int Kv, mf4 acc) {
   const int l = threadIdx.x & 63;
   const int mn = l & 15, kg = l >> 4;
   const bool am = mn < Mv, bn = mn < Nv;
+  const int mc = am ? mn : Mv - 1, nc = bn ? mn : Nv - 1;
   if (MF == MPASS_F32) {
-#pragma unroll 4
-    for (int k0 = 0; k0 < Kv; k0 += 4) {
-      const int k = k0 + kg;
-      const float a = (am && k < Kv) ? fa(mn, k) : 0.0f;
-      const float b = (bn && k < Kv) ? fb(k, mn) : 0.0f;
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    const int nfull = Kv & ~15;
+    float xa[4], xb[4];
+    auto load = [&](int k0) {
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        xa[st] = fa(mc, k0, 4 * st + kg);
+        xb[st] = fb(k0, 4 * st + kg, nc);
+      }
+    };
+    if (nfull > 0) load(0);
+    for (int k0 = 0; k0 < nfull; k0 += 16) {
+      float a[4], b[4];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        a[st] = am ? xa[st] : 0.0f;
+        b[st] = bn ? xb[st] : 0.0f;
+      }
+      if (k0 + 16 < nfull) load(k0 + 16);
+#pragma unroll
+      for (int st = 0; st < 4; ++st) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st], b[st], acc, 0, 0, 0);
+    }
+    if (nfull < Kv) {
+      float a[4], b[4];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int j = 4 * st + kg;
+        const bool kv = nfull + j < Kv;
+        const int jc = kv ? j : Kv - 1 - nfull;
+        const float x = fa(mc, nfull, jc), y = fb(nfull, jc, nc);
+        a[st] = (am && kv) ? x : 0.0f;
+        b[st] = (bn && kv) ? y : 0.0f;
+      }
+#pragma unroll
+      for (int st = 0; st < 4; ++st) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st], b[st], acc, 0, 0, 0);
     }
   } else {
     for (int k0 = 0; k0 < Kv; k0 += 32) {
@@ -49,8 +82,12 @@ __device__ __forceinline__ mf4 mma_blockf(FA fa, int Mv, FB fb, int Nv, int Kv, 
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int k = k0 + 8 * kg + j;
-        const float a = (am && k < Kv) ? fa(mn, k) : 0.0f;
-        const float b = (bn && k < Kv) ? fb(k, mn) : 0.0f;
+        const bool kv = k < Kv;
+        const int kc = kv ? k : Kv - 1;
+        const int kb = kc & ~15;
+        const float x = fa(mc, kb, kc - kb), y = fb(kb, kc - kb, nc);
+        const float a = (am && kv) ? x : 0.0f;
+        const float b = (bn && kv) ? y : 0.0f;
         const __bf16 a1 = (__bf16)a, b1 = (__bf16)b;
         ah[j] = a1;
         al[j] = (__bf16)(a - (float)a1);
@@ -69,14 +106,16 @@ __device__ __forceinline__ mf4 mma_blockf(FA fa, int Mv, FB fb, int Nv, int Kv, 
 template <int MF>
 __device__ __forceinline__ mf4 mma_block(const float* A, int sam, int sak, int Mv, const float* B, int sbk, int sbn,
                                          int Nv, int Kv, mf4 acc) {
-  return mma_blockf<MF>([&](int m, int k) { return A[m * sam + k * sak]; }, Mv,
-                        [&](int k, int n) { return B[k * sbk + n * sbn]; }, Nv, Kv, acc);
+  return mma_blockf<MF>([&](int m, int k0, int j) { return A[m * sam + (k0 + j) * sak]; }, Mv,
+                        [&](int k0, int j, int n) { return B[(k0 + j) * sbk + n * sbn]; }, Nv, Kv, acc);
 }
 
 // Z and D slices in LDS: entry (i1, i2) of a 16 x T2 slice at i2*16 + (i1 ^ (i2 & 15)).
 // Reading a 16-row column block along i2 (F1, Y) or a 16-column row block along i1
 // (F2) then touches 64 distinct banks per instruction, with no padding.
 __device__ __forceinline__ int zsw(int i1, int i2) { return i2 * 16 + (i1 ^ (i2 & 15)); }
+// The same for i2 = k0 + j with k0 a multiple of 16 and j < 16.
+__device__ __forceinline__ int zsw16(int i1, int k0, int j) { return (k0 + j) * 16 + (i1 ^ j); }
 
 // Store a 16 x 16 block: lane l holds rows 4*(l/16) + i, column l % 16.
 __device__ __forceinline__ void store_block(const mf4& acc, float* C, int scm, int scn, int Mv, int Nv) {
@@ -167,18 +206,49 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
       }
     }
   }
-  // bases of this tile and the pseudo-inverses
-  const float* B1 = static_cast<const float*>(a.B1);
-  const float* B2 = static_cast<const float*>(a.B2);
-  const float* B3 = static_cast<const float*>(a.B3);
-  for (int t = tid; t < 16 * r1; t += 256) B1s[t] = t < n1 * r1 ? B1[(long long)i1_0 * r1 + t] : 0.0f;
-  for (int t = tid; t < T2 * r2; t += 256) B2s[t] = t < n2 * r2 ? B2[(long long)i2_0 * r2 + t] : 0.0f;
-  for (int t = tid; t < N3 * r3; t += 256) B3s[t] = B3[t];
-  if (a.stage_p) {
-    float* p = Pp;
-    if (a.need_h1) { for (int t = tid; t < R1 * r1; t += 256) p[t] = P1[t]; P1 = p; p += R1 * r1; }
-    if (a.need_h2) { for (int t = tid; t < R2 * r2; t += 256) p[t] = P2[t]; P2 = p; p += R2 * r2; }
-    if (f3) { for (int t = tid; t < R3 * r3; t += 256) p[t] = P3[t]; P3 = p; }
+  // bases of this tile and the pseudo-inverses, all in one batch of loads (up to 16
+  // in flight per thread) rather than one round trip per copy loop
+  {
+    const float* B1 = static_cast<const float*>(a.B1) + (long long)i1_0 * r1;
+    const float* B2 = static_cast<const float*>(a.B2) + (long long)i2_0 * r2;
+    const float* B3 = static_cast<const float*>(a.B3);
+    const bool sp = a.stage_p != 0;
+    const int e0 = 16 * r1, e1 = e0 + T2 * r2, e2 = e1 + N3 * r3;
+    const int e3 = e2 + (sp && a.need_h1 ? R1 * r1 : 0);
+    const int e4 = e3 + (sp && a.need_h2 ? R2 * r2 : 0);
+    const int e5 = e4 + (sp && f3 ? R3 * r3 : 0);
+    const int v0 = n1 * r1, v1 = n2 * r2;
+    float* P1l = Pp;
+    float* P2l = P1l + (e3 - e2);
+    float* P3l = P2l + (e4 - e3);
+    for (int base = 0; base < e5; base += 16 * 256) {
+      float v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int t = base + u * 256 + tid;
+        float x = 0.0f;
+        if (t < e0) x = t < v0 ? B1[t] : 0.0f;
+        else if (t < e1) x = t - e0 < v1 ? B2[t - e0] : 0.0f;
+        else if (t < e2) x = B3[t - e1];
+        else if (t < e3) x = P1[t - e2];
+        else if (t < e4) x = P2[t - e3];
+        else if (t < e5) x = P3[t - e4];
+        v[u] = x;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int t = base + u * 256 + tid;
+        if (t < e0) B1s[t] = v[u];
+        else if (t < e1) B2s[t - e0] = v[u];
+        else if (t < e2) B3s[t - e1] = v[u];
+        else if (t < e3) P1l[t - e2] = v[u];
+        else if (t < e4) P2l[t - e3] = v[u];
+        else if (t < e5) P3l[t - e4] = v[u];
+      }
+    }
+    if (e3 > e2) P1 = P1l;
+    if (e4 > e3) P2 = P2l;
+    if (e5 > e4) P3 = P3l;
   }
   __syncthreads();
   // 2. Z (and D for the third mode) into LDS
@@ -208,16 +278,16 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
         const int c2 = blk / nb2, jb = blk - c2 * nb2;
         const float* Zc = Zs + c2 * ZS;
         const float* Bb = B2s + 16 * jb;
-        acc = mma_blockf<MF>([&](int m, int k) { return Zc[zsw(m, k)]; }, 16,
-                             [&](int k, int n) { return Bb[k * r2 + n]; }, r2 - 16 * jb, T2, acc);
+        acc = mma_blockf<MF>([&](int m, int k0, int j) { return Zc[zsw16(m, k0, j)]; }, 16,
+                             [&](int k0, int j, int n) { return Bb[(k0 + j) * r2 + n]; }, r2 - 16 * jb, T2, acc);
         store_block(acc, F1s + (16 * jb) * r3 + c2, R1, r3, 16, r2 - 16 * jb);
       } else {
         const int q = blk - nF1;
         const int c = q / nb2, jb = q - c * nb2;
         const float* Dc = Ds + c * ZS;
         const float* Bb = B2s + 16 * jb;
-        acc = mma_blockf<MF>([&](int m, int k) { return Dc[zsw(m, k)]; }, 16,
-                             [&](int k, int n) { return Bb[k * r2 + n]; }, r2 - 16 * jb, T2, acc);
+        acc = mma_blockf<MF>([&](int m, int k0, int j) { return Dc[zsw16(m, k0, j)]; }, 16,
+                             [&](int k0, int j, int n) { return Bb[(k0 + j) * r2 + n]; }, r2 - 16 * jb, T2, acc);
         store_block(acc, Ys + c * 16 * r2 + 16 * jb, r2, 1, 16, r2 - 16 * jb);
       }
     }
@@ -236,8 +306,8 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
         const float* Zc = Zs + c2 * ZS;
         const float* Ab = B1s + 16 * ab;
         const int i20 = 16 * ib;
-        acc = mma_blockf<MF>([&](int m, int k) { return Ab[m + k * r1]; }, r1 - 16 * ab,
-                             [&](int k, int n) { return Zc[zsw(k, i20 + n)]; }, 16, 16, acc);
+        acc = mma_blockf<MF>([&](int m, int k0, int j) { return Ab[m + (k0 + j) * r1]; }, r1 - 16 * ab,
+                             [&](int k0, int j, int n) { return Zc[(i20 + n) * 16 + ((k0 + j) ^ n)]; }, 16, 16, acc);
         // F2s[i2][a*r3 + c2]
         store_block(acc, F2s + (16 * ib) * R2 + (16 * ab) * r3 + c2, r3, R2, r1 - 16 * ab, 16);
       } else {
