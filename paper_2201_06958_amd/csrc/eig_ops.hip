@@ -20,6 +20,7 @@
 namespace tdb {
 
 #define NE TDB_NEIG
+#define EC 8    // rows per chunk of the per-lane tridiagonal sweeps
 
 // Per-mode workspace (after the K eigenvector columns): d, e, beta, p0, p1.
 struct EigWs {
@@ -147,14 +148,20 @@ __global__ void __launch_bounds__(64) k_tri_final(EigBatch batch) {
   w.e[k + 1] = 0.0;
 }
 
-// Sturm count: number of eigenvalues of the tridiagonal (d, e2 = e^2) below x.
+// Sturm count: number of eigenvalues of the tridiagonal (d, e2 = e^2) below x. The
+// quotient e2/q of the recurrence is taken as e2 times the reciprocal of q from the
+// hardware estimate and two Newton steps (full precision, a shorter dependent chain
+// than a division).
 __device__ int sturm_count2(const double* d, const double* e2, int n, double x, double pivmin) {
   int c = 0;
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   if (q < 0.0) ++c;
   for (int i = 1; i < n; ++i) {
-    q = d[i] - x - e2[i - 1] / q;
+    double r = __builtin_amdgcn_rcp(q);
+    r = r * (2.0 - q * r);
+    r = r * (2.0 - q * r);
+    q = d[i] - x - e2[i - 1] * r;
     if (fabs(q) < pivmin) q = -pivmin;
     if (q < 0.0) ++c;
   }
@@ -202,7 +209,9 @@ __global__ void __launch_bounds__(576) k_eig_values(EigBatch batch, double* lam_
   const bool live = t <= K && t < n;
   const int idx = n - 1 - t;                                  // ascending index of the t-th largest
   for (int it = 0; it < 80; ++it) {
-    bool done = !live || h - l <= 2.0 * eps * fmax(fabs(l), fabs(h)) + pivmin;
+    // converged to the accuracy of the eigenvalues themselves: a few ulps of the matrix
+    // scale (an eigenvalue below that is numerically zero)
+    bool done = !live || h - l <= fmax(2.0 * eps * fmax(fabs(l), fabs(h)), 4.0 * eps * tn) + pivmin;
     // the whole wave leaves together once every group in it has converged
     if (__all(done)) break;
     const double x = l + (double)(sub + 1) * ((h - l) / 9.0);
@@ -290,31 +299,44 @@ __global__ void __launch_bounds__(256) k_eig_vectors(EigBatch batch, const doubl
     }
     // the running pivot row (cd, cu) and the next row's original entries are carried in
     // registers, so each step's loads do not wait for the previous step's stores
+    // (rows are taken in chunks of EC: a chunk's loads are all issued before any of its
+    // stores, so a chunk costs one memory round trip rather than one per row)
     double cd = dd[j], cu = du[j];
-    for (int i = 0; i + 1 < n; ++i) {
-      const double li = dl[i * 64 + j];
-      const double dn = dd[(i + 1) * 64 + j];
-      const double un = (i + 2 < n) ? du[(i + 1) * 64 + j] : 0.0;
-      if (fabs(cd) >= fabs(li)) {
-        if (cd == 0.0) cd = ptiny;
-        const double f = li / cd;
-        dd[i * 64 + j] = cd;
-        dl[i * 64 + j] = f;
-        du[i * 64 + j] = cu;
-        cd = dn - f * cu;
-        cu = un;
-      } else {
-        atomicOr(&pivbits[i], 1ull << j);
-        const double f = cd / li;
-        dd[i * 64 + j] = li;
-        dl[i * 64 + j] = f;
-        du[i * 64 + j] = dn;
-        cd = cu - f * dn;
-        if (i + 2 < n) {
-          du2[i * 64 + j] = un;
-          cu = -f * un;
+    for (int i0 = 0; i0 + 1 < n; i0 += EC) {
+      double li_[EC], dn_[EC], un_[EC];
+#pragma unroll
+      for (int u = 0; u < EC; ++u) {
+        const int i = min(i0 + u, n - 2);
+        li_[u] = dl[i * 64 + j];
+        dn_[u] = dd[(i + 1) * 64 + j];
+        un_[u] = (i + 2 < n) ? du[(i + 1) * 64 + j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < EC; ++u) {
+        const int i = i0 + u;
+        if (i + 1 >= n) break;
+        const double li = li_[u], dn = dn_[u], un = un_[u];
+        if (fabs(cd) >= fabs(li)) {
+          if (cd == 0.0) cd = ptiny;
+          const double f = li / cd;
+          dd[i * 64 + j] = cd;
+          dl[i * 64 + j] = f;
+          du[i * 64 + j] = cu;
+          cd = dn - f * cu;
+          cu = un;
         } else {
-          cu = 0.0;
+          atomicOr(&pivbits[i], 1ull << j);
+          const double f = cd / li;
+          dd[i * 64 + j] = li;
+          dl[i * 64 + j] = f;
+          du[i * 64 + j] = dn;
+          cd = cu - f * dn;
+          if (i + 2 < n) {
+            du2[i * 64 + j] = un;
+            cu = -f * un;
+          } else {
+            cu = 0.0;
+          }
         }
       }
     }
@@ -329,15 +351,26 @@ __global__ void __launch_bounds__(256) k_eig_vectors(EigBatch batch, const doubl
       const unsigned long long bit = 1ull << j;
       // forward elimination with the row interchanges, the running entry in a register
       double cur = xb[j];
-      for (int i = 0; i + 1 < n; ++i) {
-        const double nx = xb[(i + 1) * 64 + j];
-        const double l = dl[i * 64 + j];
-        if (!(pivbits[i] & bit)) {
-          xb[i * 64 + j] = cur;
-          cur = nx - l * cur;
-        } else {
-          xb[i * 64 + j] = nx;
-          cur = cur - l * nx;
+      for (int i0 = 0; i0 + 1 < n; i0 += EC) {
+        double nx_[EC], l_[EC];
+#pragma unroll
+        for (int u = 0; u < EC; ++u) {
+          const int i = min(i0 + u, n - 2);
+          nx_[u] = xb[(i + 1) * 64 + j];
+          l_[u] = dl[i * 64 + j];
+        }
+#pragma unroll
+        for (int u = 0; u < EC; ++u) {
+          const int i = i0 + u;
+          if (i + 1 >= n) break;
+          const double nx = nx_[u], l = l_[u];
+          if (!(pivbits[i] & bit)) {
+            xb[i * 64 + j] = cur;
+            cur = nx - l * cur;
+          } else {
+            xb[i * 64 + j] = nx;
+            cur = cur - l * nx;
+          }
         }
       }
       // back substitution, the two later entries in registers
@@ -350,11 +383,25 @@ __global__ void __launch_bounds__(256) k_eig_vectors(EigBatch batch, const doubl
         x2 = x1;
         x1 = x0;
       }
-      for (int i = n - 3; i >= 0; --i) {
-        const double x0 = (xb[i * 64 + j] - du[i * 64 + j] * x1 - du2[i * 64 + j] * x2) / dd[i * 64 + j];
-        xb[i * 64 + j] = x0;
-        x2 = x1;
-        x1 = x0;
+      for (int i0 = n - 3; i0 >= 0; i0 -= EC) {
+        double b_[EC], u1_[EC], u2_[EC], d_[EC];
+#pragma unroll
+        for (int u = 0; u < EC; ++u) {
+          const int i = max(i0 - u, 0);
+          b_[u] = xb[i * 64 + j];
+          u1_[u] = du[i * 64 + j];
+          u2_[u] = du2[i * 64 + j];
+          d_[u] = dd[i * 64 + j];
+        }
+#pragma unroll
+        for (int u = 0; u < EC; ++u) {
+          const int i = i0 - u;
+          if (i < 0) break;
+          const double x0 = (b_[u] - u1_[u] * x1 - u2_[u] * x2) / d_[u];
+          xb[i * 64 + j] = x0;
+          x2 = x1;
+          x1 = x0;
+        }
       }
       // scale to unit max-norm (avoids overflow in the dot products)
       double mx = 0.0;
