@@ -1,7 +1,8 @@
 // Leading eigenpairs of the weighted mode Gram matrices of the HOSVD (Sec. 2.3):
 // Householder reduction to tridiagonal form spread over many workgroups (one launch
-// per reflector), bisection on Sturm counts for the leading K+1 eigenvalues, inverse
-// iteration for the K leading eigenvectors (clusters of close eigenvalues
+// per reflector; the last reflectors in one workgroup per mode, the trailing block in
+// LDS), bisection on Sturm counts for the leading K+1 eigenvalues, inverse iteration
+// for the K leading eigenvectors (clusters of close eigenvalues
 // orthogonalised within one wave), back-transformation by the stored reflectors and
 // a sign convention (largest-magnitude entry positive, lowest index on a tie).
 //
@@ -21,6 +22,7 @@ namespace tdb {
 
 #define NE TDB_NEIG
 #define EC 8    // rows per chunk of the per-lane tridiagonal sweeps
+#define TRI_TAIL 128   // largest trailing block reduced by a single workgroup
 
 // Per-mode workspace (after the K eigenvector columns): d, e, beta, p0, p1.
 struct EigWs {
@@ -41,7 +43,7 @@ __device__ __forceinline__ EigWs eig_ws(const EigArgs& a) {
 __global__ void __launch_bounds__(256) k_tri_step(EigBatch batch, int k) {
   const EigArgs a = batch.m[blockIdx.y];
   const int n = a.Nn;
-  if (k + 2 >= n) return;
+  if (k + 2 >= n || k >= a.k0) return;
   const EigWs w = eig_ws(a);
   double* G = a.G;
   __shared__ double vp[NE], wp[NE], v[NE];
@@ -117,35 +119,120 @@ __global__ void __launch_bounds__(256) k_tri_step(EigBatch batch, int k) {
   }
 }
 
-// The last 2 x 2 block (with the pending update of reflector n-3), and e[n-1] = 0.
-__global__ void __launch_bounds__(64) k_tri_final(EigBatch batch) {
+// Reflectors k0 .. n-3 and the last 2 x 2 block in one workgroup per mode, with the
+// trailing block A[k0..n-1][k0..n-1] (at most TRI_TAIL rows, full and symmetric) in
+// LDS: the distributed steps above cost a launch each, and once the trailing block is
+// this small a workgroup does a step in far less than a launch. It first applies the
+// pending update of reflector k0-1, then runs the same reflector formulas as
+// k_tri_step (sums in a fixed order), storing each reflector in row k of G for the
+// back-transformation.
+__global__ void __launch_bounds__(256) k_tri_tail(EigBatch batch) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* A = reinterpret_cast<double*>(smem_raw);
   const EigArgs a = batch.m[blockIdx.x];
-  const int n = a.Nn;
+  const int n = a.Nn, k0 = a.k0, T = n - k0;   // block size (<= TRI_TAIL)
   const EigWs w = eig_ws(a);
-  const double* G = a.G;
-  if (threadIdx.x != 0) return;
+  double* G = a.G;
+  double* v = A + (long long)T * T;            // TRI_TAIL
+  double* wv = v + TRI_TAIL;                   // TRI_TAIL
+  double* half = wv + TRI_TAIL;                // 2 * TRI_TAIL partial products
+  __shared__ double red[16];
+  const int tid = threadIdx.x;
+  // thread layout over the block: column c = tid % TRI_TAIL, rows h, h + 2, ...
+  const int c = tid & (TRI_TAIL - 1), h = tid >> 7;
   if (n == 1) {
-    w.d[0] = G[0];
-    w.e[0] = 0.0;
+    if (tid == 0) { w.d[0] = G[0]; w.e[0] = 0.0; w.beta[0] = 0.0; }
     return;
   }
-  const int k = n - 2;   // first index of the block
-  double a00 = G[(long long)k * n + k], a10 = G[(long long)(k + 1) * n + k], a11 = G[(long long)(k + 1) * n + k + 1];
-  const double bp = k > 0 ? w.beta[k - 1] : 0.0;
+  if (c < T)
+    for (int i = h; i < T; i += 2) A[i * T + c] = G[(long long)(k0 + i) * n + k0 + c];
+  __syncthreads();
+  // the pending update of reflector k0-1 (acting on indices k0..n-1)
+  const double bp = k0 > 0 ? w.beta[k0 - 1] : 0.0;
   if (bp != 0.0) {
-    const double* pp = ((k - 1) & 1) ? w.p[1] : w.p[0];
-    const double v0 = G[(long long)(k - 1) * n + k], v1 = G[(long long)(k - 1) * n + k + 1];
-    const double Kc = 0.5 * bp * (pp[k] * v0 + pp[k + 1] * v1);
-    const double w0 = pp[k] - Kc * v0, w1 = pp[k + 1] - Kc * v1;
-    a00 -= v0 * w0 + w0 * v0;
-    a10 -= v1 * w0 + w1 * v0;
-    a11 -= v1 * w1 + w1 * v1;
+    const double* pp = ((k0 - 1) & 1) ? w.p[1] : w.p[0];
+    double pvv = 0.0;
+    for (int i = tid; i < T; i += blockDim.x) {
+      const double vi = G[(long long)(k0 - 1) * n + k0 + i];
+      v[i] = vi;
+      pvv += pp[k0 + i] * vi;
+    }
+    pvv = block_sum(pvv, red);
+    const double Kc = 0.5 * bp * pvv;
+    for (int i = tid; i < T; i += blockDim.x) wv[i] = pp[k0 + i] - Kc * v[i];
+    __syncthreads();
+    if (c < T) {
+      const double vc = v[c], wc = wv[c];
+      for (int i = h; i < T; i += 2) A[i * T + c] -= v[i] * wc + wv[i] * vc;
+    }
+    __syncthreads();
   }
-  w.d[k] = a00;
-  w.e[k] = a10;
-  w.beta[k] = 0.0;
-  w.d[k + 1] = a11;
-  w.e[k + 1] = 0.0;
+  for (int k = k0; k + 2 < n; ++k) {
+    const int r1 = k - k0 + 1;         // block row/column of index k+1
+    const int m = n - k - 1;
+    // column k below the diagonal
+    double ss = 0.0;
+    for (int i = tid; i < m; i += blockDim.x) {
+      const double x = A[(r1 + i) * T + r1 - 1];
+      v[i] = x;
+      ss += x * x;
+    }
+    ss = block_sum(ss, red);
+    const double x0 = v[0];
+    double bk = 0.0, ek = x0;
+    if (ss > 0.0) {
+      const double xn = sqrt(ss);
+      const double alpha = x0 > 0.0 ? -xn : xn;
+      const double v0 = x0 - alpha;
+      const double vtv = ss - x0 * x0 + v0 * v0;
+      bk = 2.0 / vtv;
+      ek = alpha;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      if (ss > 0.0) v[0] = x0 - ek;
+      w.d[k] = A[(r1 - 1) * T + r1 - 1];
+      w.e[k] = ek;
+      w.beta[k] = bk;
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += blockDim.x) G[(long long)k * n + k + 1 + i] = v[i];
+    if (bk != 0.0) {
+      // p = bk A v over the trailing block: column c of A (= row c), the two halves of
+      // the sum in the two halves of the workgroup
+      const int hm = (m + 1) >> 1;
+      if (c < m) {
+        double s = 0.0;
+        const int j1 = h ? m : hm;
+        for (int j = h * hm; j < j1; ++j) s += A[(r1 + j) * T + r1 + c] * v[j];
+        half[h * TRI_TAIL + c] = s;
+      }
+      __syncthreads();
+      double pv = 0.0;
+      if (tid < m) {
+        const double pi = bk * (half[tid] + half[TRI_TAIL + tid]);
+        wv[tid] = pi;
+        pv = pi * v[tid];
+      }
+      pv = block_sum(pv, red);
+      const double Kc = 0.5 * bk * pv;
+      if (tid < m) wv[tid] -= Kc * v[tid];
+      __syncthreads();
+      if (c < m) {
+        const double vc = v[c], wc = wv[c];
+        for (int i = h; i < m; i += 2) A[(r1 + i) * T + r1 + c] -= v[i] * wc + wv[i] * vc;
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    const int k = n - 2, r0 = k - k0;
+    w.d[k] = A[r0 * T + r0];
+    w.e[k] = A[(r0 + 1) * T + r0];
+    w.beta[k] = 0.0;
+    w.d[k + 1] = A[(r0 + 1) * T + r0 + 1];
+    w.e[k + 1] = 0.0;
+  }
 }
 
 // Sturm count: number of eigenvalues of the tridiagonal (d, e2 = e^2) below x. The
@@ -237,243 +324,226 @@ __global__ void __launch_bounds__(576) k_eig_values(EigBatch batch, double* lam_
   if (threadIdx.x == 0) lam[TDB_RCAP + 1] = tn;
 }
 
-// Inverse iteration for the K leading eigenvectors, all at once: one block per mode.
-// Vector j is shifted by its eigenvalue (shifts inside a cluster kept eps3 apart);
-// lane j of the first wave factors T - shift_j I and solves with it (partial
-// pivoting); after every solve round the whole block orthonormalises the vectors in
-// index order, each against the earlier members of its cluster (a cluster starts where
-// the gap to the previous eigenvalue exceeds 1e-3 of the matrix scale), so every
-// vector keeps the direction of its own eigenvalue. Vectors live interleaved
-// (entry i of vector j at i*64 + j) in a global workspace, as do the LU factors.
-__global__ void __launch_bounds__(256) k_eig_vectors(EigBatch batch, const double* lam_in, double* scratch) {
+// Inverse iteration for the K leading eigenvectors in rounds of two kernels: a solve
+// (one wave per vector: T - shift_j I factored with partial pivoting and the right-hand
+// side eliminated in the same top-down pass, then back substitution, all in LDS), and
+// an orthonormalisation of all vectors of a mode in one workgroup (index order, each
+// vector against the earlier members of its cluster, the vectors held in registers).
+// Shifts inside a cluster are kept eps3 apart; a cluster starts where the gap to the
+// previous eigenvalue exceeds 1e-3 of the matrix scale. Between the kernels the vectors
+// live interleaved (entry i of vector j at i*64 + j) in a global workspace.
+#define EIG_VPB 4   // vectors (waves) per workgroup of the solve
+
+// Shift of vector j (the serial cluster walk over eigenvalues 0..j).
+__device__ double eig_shift(const double* lam, int j, double ortol, double eps3) {
+  double lam_prev = 0.0, lj = 0.0;
+  for (int q = 0; q <= j; ++q) {
+    lj = lam[q];
+    if (!(q == 0 || lam[q - 1] - lj > ortol) && lam_prev - lj < eps3) lj = lam_prev - eps3;
+    lam_prev = lj;
+  }
+  return lj;
+}
+
+__global__ void __launch_bounds__(64 * EIG_VPB) k_eig_solve(EigBatch batch, const double* lam_in, double* scratch,
+                                                           int first) {
   const EigArgs a = batch.m[blockIdx.x];
   const int n = a.Nn, K = a.k;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int j = blockIdx.y * EIG_VPB + wv;
   const EigWs w = eig_ws(a);
   const double* lam = lam_in + (long long)blockIdx.x * (TDB_RCAP + 2);
   const double tn = lam[TDB_RCAP + 1];
-  double* xb = scratch + (long long)blockIdx.x * NE * 64 * 5;
-  double* dd = xb + NE * 64;
-  double* dl = dd + NE * 64;
-  double* du = dl + NE * 64;
-  double* du2 = du + NE * 64;
-  __shared__ double sh[TDB_RCAP], part[4][TDB_RCAP], red[16], dots[TDB_RCAP], xj[NE];
-  __shared__ int cend[TDB_RCAP];
-  __shared__ unsigned long long pivbits[NE];   // bit j: row swap of vector j at step i
-  const int tid = threadIdx.x;
+  double* xb = scratch + (long long)blockIdx.x * NE * 64;
+  __shared__ double d[NE], e[NE];
+  __shared__ double U0[EIG_VPB][NE], U1[EIG_VPB][NE], U2[EIG_VPB][NE], rb[EIG_VPB][NE];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    d[i] = w.d[i];
+    e[i] = i + 1 < n ? w.e[i] : 0.0;
+  }
+  __syncthreads();
+  if (j >= K) return;   // whole waves; no barrier follows
+  double* dd = U0[wv];
+  double* du = U1[wv];
+  double* du2 = U2[wv];
+  double* x = rb[wv];
   const double eps = 2.220446049250313e-16;
   double me = 0.0;
-  for (int i = tid; i + 1 < n; i += blockDim.x) me = fmax(me, w.e[i] * w.e[i]);
-  me = block_max(me, red);
+  for (int i = lane; i + 1 < n; i += 64) me = fmax(me, e[i] * e[i]);
+  for (int off = 32; off > 0; off >>= 1) me = fmax(me, __shfl_xor(me, off, 64));
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, me);
-  const double ortol = 1e-3 * tn;
-  const double eps3 = 10.0 * eps * tn;
-  if (tid == 0) {
-    double lam_prev = 0.0;
-    int cs = 0;
-    for (int j = 0; j < K; ++j) {
-      double lj = lam[j];
-      if (j == 0 || lam[j - 1] - lj > ortol) {
-        for (int q = cs; q < j; ++q) cend[q] = j;
-        cs = j;
-      } else if (lam_prev - lj < eps3) {
-        lj = lam_prev - eps3;   // keep shifts distinct in a cluster
-      }
-      lam_prev = lj;
-      sh[j] = lj;
-    }
-    for (int q = cs; q < K; ++q) cend[q] = K;
-  }
-  for (int i = tid; i < n; i += blockDim.x) pivbits[i] = 0ull;
-  __syncthreads();
   const double ptiny = eps * tn + pivmin;
-  // factor and start vector: lane j of the first wave
-  if (tid < K) {
-    const int j = tid;
-    const double lj = sh[j];
-    for (int i = 0; i < n; ++i) {
-      dd[i * 64 + j] = w.d[i] - lj;
-      dl[i * 64 + j] = (i + 1 < n) ? w.e[i] : 0.0;
-      du[i * 64 + j] = (i + 1 < n) ? w.e[i] : 0.0;
-      du2[i * 64 + j] = 0.0;
-      xb[i * 64 + j] = hash_unit2((unsigned)i, (unsigned)j + 1u);
-    }
-    // the running pivot row (cd, cu) and the next row's original entries are carried in
-    // registers, so each step's loads do not wait for the previous step's stores
-    // (rows are taken in chunks of EC: a chunk's loads are all issued before any of its
-    // stores, so a chunk costs one memory round trip rather than one per row)
-    double cd = dd[j], cu = du[j];
+  for (int i = lane; i < n; i += 64) x[i] = first ? hash_unit2((unsigned)i, (unsigned)j + 1u) : xb[i * 64 + j];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (lane == 0) {
+    const double lj = eig_shift(lam, j, 1e-3 * tn, 10.0 * eps * tn);
+    // factor and eliminate: row i of U is (dd, du, du2), its right-hand side in x[i];
+    // the running pivot row (cd, cu, cb) stays in registers, the next rows' entries are
+    // loaded EC at a time ahead of the chain
+    double cd = d[0] - lj, cu = e[0], cb = x[0];
     for (int i0 = 0; i0 + 1 < n; i0 += EC) {
-      double li_[EC], dn_[EC], un_[EC];
+      double li_[EC], dn_[EC], un_[EC], nb_[EC];
 #pragma unroll
       for (int u = 0; u < EC; ++u) {
         const int i = min(i0 + u, n - 2);
-        li_[u] = dl[i * 64 + j];
-        dn_[u] = dd[(i + 1) * 64 + j];
-        un_[u] = (i + 2 < n) ? du[(i + 1) * 64 + j] : 0.0;
+        li_[u] = e[i];
+        dn_[u] = d[i + 1] - lj;
+        un_[u] = e[i + 1];   // zero past the end
+        nb_[u] = x[i + 1];
       }
 #pragma unroll
       for (int u = 0; u < EC; ++u) {
         const int i = i0 + u;
         if (i + 1 >= n) break;
-        const double li = li_[u], dn = dn_[u], un = un_[u];
+        const double li = li_[u], dn = dn_[u], un = un_[u], nb = nb_[u];
         if (fabs(cd) >= fabs(li)) {
           if (cd == 0.0) cd = ptiny;
           const double f = li / cd;
-          dd[i * 64 + j] = cd;
-          dl[i * 64 + j] = f;
-          du[i * 64 + j] = cu;
+          dd[i] = cd;
+          du[i] = cu;
+          du2[i] = 0.0;
+          x[i] = cb;
           cd = dn - f * cu;
           cu = un;
+          cb = nb - f * cb;
         } else {
-          atomicOr(&pivbits[i], 1ull << j);
           const double f = cd / li;
-          dd[i * 64 + j] = li;
-          dl[i * 64 + j] = f;
-          du[i * 64 + j] = dn;
+          dd[i] = li;
+          du[i] = dn;
+          du2[i] = un;
+          x[i] = nb;
           cd = cu - f * dn;
-          if (i + 2 < n) {
-            du2[i * 64 + j] = un;
-            cu = -f * un;
-          } else {
-            cu = 0.0;
-          }
+          cu = -f * un;
+          cb = cb - f * nb;
         }
       }
     }
-    dd[(n - 1) * 64 + j] = cd;
-    if (dd[(n - 1) * 64 + j] == 0.0) dd[(n - 1) * 64 + j] = ptiny;
-  }
-  __syncthreads();
-  const int qs = tid & 63, ig = tid >> 6;   // (vector slot, row group) of the block-wide passes
-  for (int it = 0; it < 3; ++it) {
-    if (tid < K) {
-      const int j = tid;
-      const unsigned long long bit = 1ull << j;
-      // forward elimination with the row interchanges, the running entry in a register
-      double cur = xb[j];
-      for (int i0 = 0; i0 + 1 < n; i0 += EC) {
-        double nx_[EC], l_[EC];
+    if (cd == 0.0) cd = ptiny;
+    // back substitution, the two later entries in registers
+    double x1 = cb / cd, x2 = 0.0;
+    x[n - 1] = x1;
+    for (int i0 = n - 2; i0 >= 0; i0 -= EC) {
+      double b_[EC], u1_[EC], u2_[EC], d_[EC];
 #pragma unroll
-        for (int u = 0; u < EC; ++u) {
-          const int i = min(i0 + u, n - 2);
-          nx_[u] = xb[(i + 1) * 64 + j];
-          l_[u] = dl[i * 64 + j];
-        }
-#pragma unroll
-        for (int u = 0; u < EC; ++u) {
-          const int i = i0 + u;
-          if (i + 1 >= n) break;
-          const double nx = nx_[u], l = l_[u];
-          if (!(pivbits[i] & bit)) {
-            xb[i * 64 + j] = cur;
-            cur = nx - l * cur;
-          } else {
-            xb[i * 64 + j] = nx;
-            cur = cur - l * nx;
-          }
-        }
+      for (int u = 0; u < EC; ++u) {
+        const int i = max(i0 - u, 0);
+        b_[u] = x[i];
+        u1_[u] = du[i];
+        u2_[u] = du2[i];
+        d_[u] = dd[i];
       }
-      // back substitution, the two later entries in registers
-      double x1 = cur / dd[(n - 1) * 64 + j];
-      xb[(n - 1) * 64 + j] = x1;
-      double x2 = 0.0;
-      if (n >= 2) {
-        const double x0 = (xb[(n - 2) * 64 + j] - du[(n - 2) * 64 + j] * x1) / dd[(n - 2) * 64 + j];
-        xb[(n - 2) * 64 + j] = x0;
+#pragma unroll
+      for (int u = 0; u < EC; ++u) {
+        const int i = i0 - u;
+        if (i < 0) break;
+        const double x0 = (b_[u] - u1_[u] * x1 - u2_[u] * x2) / d_[u];
+        x[i] = x0;
         x2 = x1;
         x1 = x0;
       }
-      for (int i0 = n - 3; i0 >= 0; i0 -= EC) {
-        double b_[EC], u1_[EC], u2_[EC], d_[EC];
-#pragma unroll
-        for (int u = 0; u < EC; ++u) {
-          const int i = max(i0 - u, 0);
-          b_[u] = xb[i * 64 + j];
-          u1_[u] = du[i * 64 + j];
-          u2_[u] = du2[i * 64 + j];
-          d_[u] = dd[i * 64 + j];
-        }
-#pragma unroll
-        for (int u = 0; u < EC; ++u) {
-          const int i = i0 - u;
-          if (i < 0) break;
-          const double x0 = (b_[u] - u1_[u] * x1 - u2_[u] * x2) / d_[u];
-          xb[i * 64 + j] = x0;
-          x2 = x1;
-          x1 = x0;
-        }
-      }
-      // scale to unit max-norm (avoids overflow in the dot products)
-      double mx = 0.0;
-      for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(xb[i * 64 + j]));
-      const double sc = mx > 0.0 ? 1.0 / mx : 1.0;
-      for (int i = 0; i < n; ++i) xb[i * 64 + j] *= sc;
-    }
-    __syncthreads();
-    // orthonormalise in index order within clusters (vector j staged in LDS; each
-    // thread's rows are loaded in batches of 8 before any of them is updated)
-    for (int j = 0; j < K; ++j) {
-      double nr = 0.0;
-      for (int i = tid; i < n; i += blockDim.x) {
-        const double x = xb[i * 64 + j];
-        xj[i] = x;
-        nr += x * x;
-      }
-      nr = block_sum(nr, red);
-      const double inv = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
-      for (int i = tid; i < n; i += blockDim.x) {
-        const double x = xj[i] * inv;
-        xj[i] = x;
-        xb[i * 64 + j] = x;
-      }
-      __syncthreads();
-      const int ce = cend[j];
-      if (ce <= j + 1) continue;
-      const int q = j + 1 + qs;
-      const bool act = q < ce;
-      double pd = 0.0;
-      if (act) {
-        for (int i0 = ig; i0 < n; i0 += 32) {
-          double v8[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int i = i0 + 4 * u;
-            v8[u] = i < n ? xb[i * 64 + q] : 0.0;
-          }
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int i = i0 + 4 * u;
-            if (i < n) pd += v8[u] * xj[i];
-          }
-        }
-      }
-      part[ig][qs] = pd;
-      __syncthreads();
-      if (tid < 64) dots[tid] = (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
-      __syncthreads();
-      if (act) {
-        const double dq = dots[qs];
-        for (int i0 = ig; i0 < n; i0 += 32) {
-          double v8[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int i = i0 + 4 * u;
-            v8[u] = i < n ? xb[i * 64 + q] : 0.0;
-          }
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int i = i0 + 4 * u;
-            if (i < n) xb[i * 64 + q] = v8[u] - dq * xj[i];
-          }
-        }
-      }
-      __syncthreads();
     }
   }
-  // out to the column-major eigenvector block
-  for (long long t = tid; t < (long long)n * K; t += blockDim.x) {
-    const int j = (int)(t / n), i = (int)(t - (long long)j * n);
-    w.X[t] = xb[i * 64 + j];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // scale to unit max-norm (keeps the later dot products in range)
+  double mx = 0.0;
+  for (int i = lane; i < n; i += 64) mx = fmax(mx, fabs(x[i]));
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  const double sc = mx > 0.0 ? 1.0 / mx : 1.0;
+  for (int i = lane; i < n; i += 64) xb[i * 64 + j] = x[i] * sc;
+}
+
+// Orthonormalisation of one mode's K vectors: thread (q = tid % 64, g = tid / 64) holds
+// entries g, g + 16, ... of vector q in registers. Step j normalises vector j (its
+// owners publish it in LDS) and removes its component from the later members of its
+// cluster; LDS buffers alternate between steps, so a step needs at most two barriers.
+// The last round writes the column-major eigenvector block instead.
+#define MGS_G 16
+#define MGS_R (NE / MGS_G)
+__global__ void __launch_bounds__(1024) k_eig_orth(EigBatch batch, const double* lam_in, double* scratch, int last) {
+  const EigArgs a = batch.m[blockIdx.x];
+  const int n = a.Nn, K = a.k;
+  const EigWs w = eig_ws(a);
+  const double* lam = lam_in + (long long)blockIdx.x * (TDB_RCAP + 2);
+  const double tn = lam[TDB_RCAP + 1];
+  double* xb = scratch + (long long)blockIdx.x * NE * 64;
+  __shared__ double y[2][NE], part[2][MGS_G][64], red[2][MGS_G];
+  __shared__ int cend[TDB_RCAP];
+  const int q = threadIdx.x & 63, g = threadIdx.x >> 6;
+  if (threadIdx.x == 0) {
+    const double ortol = 1e-3 * tn;
+    int cs = 0;
+    for (int j = 1; j < K; ++j)
+      if (lam[j - 1] - lam[j] > ortol) {
+        for (int t = cs; t < j; ++t) cend[t] = j;
+        cs = j;
+      }
+    for (int t = cs; t < K; ++t) cend[t] = K;
+  }
+  double x[MGS_R];
+#pragma unroll
+  for (int s = 0; s < MGS_R; ++s) {
+    const int i = g + MGS_G * s;
+    x[s] = (q < K && i < n) ? xb[i * 64 + q] : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < K; ++j) {
+    const int b = j & 1;
+    if (q == j) {
+      double ps = 0.0;
+#pragma unroll
+      for (int s = 0; s < MGS_R; ++s) {
+        const int i = g + MGS_G * s;
+        if (i < n) y[b][i] = x[s];
+        ps += x[s] * x[s];
+      }
+      red[b][g] = ps;
+    }
+    __syncthreads();
+    double nr = 0.0;
+#pragma unroll
+    for (int t = 0; t < MGS_G; ++t) nr += red[b][t];
+    const double inv = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
+    if (q == j) {
+#pragma unroll
+      for (int s = 0; s < MGS_R; ++s) x[s] *= inv;
+    }
+    const int ce = cend[j];
+    if (ce <= j + 1) continue;
+    const bool act = q > j && q < ce;
+    if (act) {
+      double pd = 0.0;
+#pragma unroll
+      for (int s = 0; s < MGS_R; ++s) {
+        const int i = g + MGS_G * s;
+        if (i < n) pd += x[s] * y[b][i];
+      }
+      part[b][g][q] = pd;
+    }
+    __syncthreads();
+    if (act) {
+      double dq = 0.0;
+#pragma unroll
+      for (int t = 0; t < MGS_G; ++t) dq += part[b][t][q];
+      const double c = dq * inv * inv;
+#pragma unroll
+      for (int s = 0; s < MGS_R; ++s) {
+        const int i = g + MGS_G * s;
+        if (i < n) x[s] -= c * y[b][i];
+      }
+    }
+  }
+  if (q >= K) return;
+#pragma unroll
+  for (int s = 0; s < MGS_R; ++s) {
+    const int i = g + MGS_G * s;
+    if (i < n) {
+      if (last) w.X[(long long)q * n + i] = x[s];
+      else xb[i * 64 + q] = x[s];
+    }
   }
 }
 
@@ -527,23 +597,39 @@ hipError_t launch_sym_eig(const EigBatch& b, double* lam_scratch, double* vec_sc
     nmax = b.m[i].Nn > nmax ? b.m[i].Nn : nmax;
     kmax = b.m[i].k > kmax ? b.m[i].k : kmax;
   }
-  // enough workgroups that each wave owns a row or two of the largest trailing block
+  // enough workgroups that each wave owns a row or two of the largest trailing block;
+  // the last TRI_TAIL rows of every mode in one workgroup with the block in LDS
   const int nblk = nmax >= 512 ? 64 : nmax >= 128 ? 32 : 8;
-  for (int k = 0; k + 2 < nmax; ++k) {
-    hipLaunchKernelGGL(k_tri_step, dim3(nblk, b.count), dim3(256), 0, s, b, k);
+  EigBatch bt = b;
+  int kdist = 0;
+  for (int i = 0; i < bt.count; ++i) {
+    bt.m[i].k0 = bt.m[i].Nn > TRI_TAIL ? bt.m[i].Nn - TRI_TAIL : 0;
+    kdist = bt.m[i].k0 > kdist ? bt.m[i].k0 : kdist;
+  }
+  for (int k = 0; k < kdist; ++k) {
+    hipLaunchKernelGGL(k_tri_step, dim3(nblk, bt.count), dim3(256), 0, s, bt, k);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_tri_final, dim3(b.count), dim3(64), 0, s, b);
-  hipError_t e = hipGetLastError();
+  const size_t tl = ((size_t)TRI_TAIL * TRI_TAIL + 4 * TRI_TAIL) * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_tri_tail, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tl);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_eig_values, dim3(b.count), dim3(576), 0, s, b, lam_scratch);
+  hipLaunchKernelGGL(k_tri_tail, dim3(bt.count), dim3(256), tl, s, bt);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_eig_vectors, dim3(b.count), dim3(256), 0, s, b, lam_scratch, vec_scratch);
+  hipLaunchKernelGGL(k_eig_values, dim3(b.count), dim3(576), 0, s, bt, lam_scratch);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_eig_back, dim3(b.count, kmax), dim3(64), 0, s, b);
+  for (int it = 0; it < 3; ++it) {
+    hipLaunchKernelGGL(k_eig_solve, dim3(b.count, (kmax + EIG_VPB - 1) / EIG_VPB), dim3(64 * EIG_VPB), 0, s, bt,
+                       lam_scratch, vec_scratch, it == 0 ? 1 : 0);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_eig_orth, dim3(b.count), dim3(1024), 0, s, bt, lam_scratch, vec_scratch, it == 2 ? 1 : 0);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_eig_back, dim3(b.count, kmax), dim3(64), 0, s, bt);
   return hipGetLastError();
 }
 

@@ -100,6 +100,7 @@ hipError_t launch_gram_reduce(const double* partials, double* G, const HosvdMode
 // Umax (Nn x ldu, unscaled bases Q / sqrt(w_n)) and Bmax (Nn x k, W Umax).
 struct EigArgs {
   int Nn, k, ldu;
+  int k0;                // first reflector of the single-workgroup tail (set by the launcher)
   double* G;
   double* work;          // >= Nn * (k + 6) doubles
   double* sig;           // k + 1
@@ -111,7 +112,7 @@ struct EigBatch {
   int count;
   EigArgs m[TDB_P];
 };
-// lam_scratch: count x (TDB_RCAP + 2) doubles; vec_scratch: count x TDB_NEIG x 64 x 5
+// lam_scratch: count x (TDB_RCAP + 2) doubles; vec_scratch: count x TDB_NEIG x 64
 // doubles of device workspace.
 hipError_t launch_sym_eig(const EigBatch& b, double* lam_scratch, double* vec_scratch, hipStream_t s);
 
