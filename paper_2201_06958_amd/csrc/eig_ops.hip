@@ -325,14 +325,18 @@ __global__ void __launch_bounds__(576) k_eig_values(EigBatch batch, double* lam_
 }
 
 // Inverse iteration for the K leading eigenvectors in rounds of two kernels: a solve
-// (one wave per vector: T - shift_j I factored with partial pivoting and the right-hand
-// side eliminated in the same top-down pass, then back substitution, all in LDS), and
-// an orthonormalisation of all vectors of a mode in one workgroup (index order, each
-// vector against the earlier members of its cluster, the vectors held in registers).
-// Shifts inside a cluster are kept eps3 apart; a cluster starts where the gap to the
-// previous eigenvalue exceeds 1e-3 of the matrix scale. Between the kernels the vectors
-// live interleaved (entry i of vector j at i*64 + j) in a global workspace.
+// (one wave per vector, its chains run by one lane out of LDS) and an orthonormalisation
+// of all vectors of a mode in one workgroup (index order, each vector against the
+// earlier members of its cluster). The first solve factors T - shift_j I with partial
+// pivoting, eliminating the random start vector in the same top-down pass, and keeps
+// the factors (multipliers, the two superdiagonals of U, reciprocal pivots, row
+// interchanges) for the later rounds. Shifts inside a cluster are kept eps3 apart; a
+// cluster starts where the gap to the previous eigenvalue exceeds 1e-3 of the matrix
+// scale. Between the kernels the vectors live interleaved (entry i of vector j at
+// i*64 + j) in a global workspace; the factors follow, one block of EIG_NF rows of NE
+// per vector.
 #define EIG_VPB 4   // vectors (waves) per workgroup of the solve
+#define EIG_NF 5    // factor rows per vector: multiplier, U superdiagonals 1 and 2, 1/pivot, interchange
 
 // Shift of vector j (the serial cluster walk over eigenvalues 0..j).
 __device__ double eig_shift(const double* lam, int j, double ortol, double eps3) {
@@ -345,6 +349,12 @@ __device__ double eig_shift(const double* lam, int j, double ortol, double eps3)
   return lj;
 }
 
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ void __launch_bounds__(64 * EIG_VPB) k_eig_solve(EigBatch batch, const double* lam_in, double* scratch,
                                                            int first) {
   const EigArgs a = batch.m[blockIdx.x];
@@ -354,100 +364,150 @@ __global__ void __launch_bounds__(64 * EIG_VPB) k_eig_solve(EigBatch batch, cons
   const EigWs w = eig_ws(a);
   const double* lam = lam_in + (long long)blockIdx.x * (TDB_RCAP + 2);
   const double tn = lam[TDB_RCAP + 1];
-  double* xb = scratch + (long long)blockIdx.x * NE * 64;
+  double* xb = scratch + (long long)blockIdx.x * NE * 64 * (1 + EIG_NF);
+  double* fac = xb + NE * 64 + (long long)j * EIG_NF * NE;
   __shared__ double d[NE], e[NE];
-  __shared__ double U0[EIG_VPB][NE], U1[EIG_VPB][NE], U2[EIG_VPB][NE], rb[EIG_VPB][NE];
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    d[i] = w.d[i];
-    e[i] = i + 1 < n ? w.e[i] : 0.0;
+  __shared__ double F[EIG_VPB][EIG_NF][NE], rb[EIG_VPB][NE];
+  if (first) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      d[i] = w.d[i];
+      e[i] = i + 1 < n ? w.e[i] : 0.0;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   if (j >= K) return;   // whole waves; no barrier follows
-  double* dd = U0[wv];
-  double* du = U1[wv];
-  double* du2 = U2[wv];
+  double* fl = F[wv][0];   // multipliers
+  double* u1 = F[wv][1];   // U superdiagonal 1
+  double* u2 = F[wv][2];   // U superdiagonal 2
+  double* rp = F[wv][3];   // 1 / pivot
+  double* pv = F[wv][4];   // 1: rows i and i+1 interchanged
   double* x = rb[wv];
-  const double eps = 2.220446049250313e-16;
-  double me = 0.0;
-  for (int i = lane; i + 1 < n; i += 64) me = fmax(me, e[i] * e[i]);
-  for (int off = 32; off > 0; off >>= 1) me = fmax(me, __shfl_xor(me, off, 64));
-  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, me);
-  const double ptiny = eps * tn + pivmin;
-  for (int i = lane; i < n; i += 64) x[i] = first ? hash_unit2((unsigned)i, (unsigned)j + 1u) : xb[i * 64 + j];
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  if (lane == 0) {
-    const double lj = eig_shift(lam, j, 1e-3 * tn, 10.0 * eps * tn);
-    // factor and eliminate: row i of U is (dd, du, du2), its right-hand side in x[i];
-    // the running pivot row (cd, cu, cb) stays in registers, the next rows' entries are
-    // loaded EC at a time ahead of the chain
-    double cd = d[0] - lj, cu = e[0], cb = x[0];
-    for (int i0 = 0; i0 + 1 < n; i0 += EC) {
-      double li_[EC], dn_[EC], un_[EC], nb_[EC];
+  if (first) {
+    const double eps = 2.220446049250313e-16;
+    double me = 0.0;
+    for (int i = lane; i + 1 < n; i += 64) me = fmax(me, e[i] * e[i]);
+    for (int off = 32; off > 0; off >>= 1) me = fmax(me, __shfl_xor(me, off, 64));
+    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, me);
+    const double ptiny = eps * tn + pivmin;
+    for (int i = lane; i < n; i += 64) x[i] = hash_unit2((unsigned)i, (unsigned)j + 1u);
+    wave_lds_sync();
+    if (lane == 0) {
+      const double lj = eig_shift(lam, j, 1e-3 * tn, 10.0 * eps * tn);
+      // the running pivot row (cd, cu) and right-hand side entry cb stay in registers,
+      // the next rows' entries are loaded EC at a time ahead of the chain
+      double cd = d[0] - lj, cu = e[0], cb = x[0];
+      for (int i0 = 0; i0 + 1 < n; i0 += EC) {
+        double li_[EC], dn_[EC], un_[EC], nb_[EC];
 #pragma unroll
-      for (int u = 0; u < EC; ++u) {
-        const int i = min(i0 + u, n - 2);
-        li_[u] = e[i];
-        dn_[u] = d[i + 1] - lj;
-        un_[u] = e[i + 1];   // zero past the end
-        nb_[u] = x[i + 1];
-      }
+        for (int u = 0; u < EC; ++u) {
+          const int i = min(i0 + u, n - 2);
+          li_[u] = e[i];
+          dn_[u] = d[i + 1] - lj;
+          un_[u] = e[i + 1];   // zero past the end
+          nb_[u] = x[i + 1];
+        }
 #pragma unroll
-      for (int u = 0; u < EC; ++u) {
-        const int i = i0 + u;
-        if (i + 1 >= n) break;
-        const double li = li_[u], dn = dn_[u], un = un_[u], nb = nb_[u];
-        if (fabs(cd) >= fabs(li)) {
-          if (cd == 0.0) cd = ptiny;
-          const double f = li / cd;
-          dd[i] = cd;
-          du[i] = cu;
-          du2[i] = 0.0;
-          x[i] = cb;
-          cd = dn - f * cu;
-          cu = un;
-          cb = nb - f * cb;
-        } else {
-          const double f = cd / li;
-          dd[i] = li;
-          du[i] = dn;
-          du2[i] = un;
-          x[i] = nb;
-          cd = cu - f * dn;
-          cu = -f * un;
-          cb = cb - f * nb;
+        for (int u = 0; u < EC; ++u) {
+          const int i = i0 + u;
+          if (i + 1 >= n) break;
+          const double li = li_[u], dn = dn_[u], un = un_[u], nb = nb_[u];
+          if (fabs(cd) >= fabs(li)) {
+            if (cd == 0.0) cd = ptiny;
+            const double f = li / cd;
+            fl[i] = f;
+            rp[i] = 1.0 / cd;
+            u1[i] = cu;
+            u2[i] = 0.0;
+            pv[i] = 0.0;
+            x[i] = cb;
+            cd = dn - f * cu;
+            cu = un;
+            cb = nb - f * cb;
+          } else {
+            const double f = cd / li;
+            fl[i] = f;
+            rp[i] = 1.0 / li;
+            u1[i] = dn;
+            u2[i] = un;
+            pv[i] = 1.0;
+            x[i] = nb;
+            cd = cu - f * dn;
+            cu = -f * un;
+            cb = cb - f * nb;
+          }
         }
       }
+      if (cd == 0.0) cd = ptiny;
+      rp[n - 1] = 1.0 / cd;
+      u1[n - 1] = 0.0;
+      u2[n - 1] = 0.0;
+      fl[n - 1] = 0.0;
+      pv[n - 1] = 0.0;
+      x[n - 1] = cb;
     }
-    if (cd == 0.0) cd = ptiny;
+    wave_lds_sync();
+    for (int t = lane; t < EIG_NF * NE; t += 64) {
+      const int r = t / NE, i = t - r * NE;
+      if (i < n) fac[t] = F[wv][r][i];
+    }
+  } else {
+    for (int t = lane; t < EIG_NF * NE; t += 64) {
+      const int r = t / NE, i = t - r * NE;
+      if (i < n) F[wv][r][i] = fac[t];
+    }
+    for (int i = lane; i < n; i += 64) x[i] = xb[i * 64 + j];
+    wave_lds_sync();
+    if (lane == 0) {
+      // forward elimination with the row interchanges, the running entry in a register
+      double cur = x[0];
+      for (int i0 = 0; i0 + 1 < n; i0 += EC) {
+        double nx_[EC], l_[EC], p_[EC];
+#pragma unroll
+        for (int u = 0; u < EC; ++u) {
+          const int i = min(i0 + u, n - 2);
+          nx_[u] = x[i + 1];
+          l_[u] = fl[i];
+          p_[u] = pv[i];
+        }
+#pragma unroll
+        for (int u = 0; u < EC; ++u) {
+          const int i = i0 + u;
+          if (i + 1 >= n) break;
+          const double nx = nx_[u], l = l_[u];
+          const bool sw = p_[u] != 0.0;
+          x[i] = sw ? nx : cur;
+          cur = sw ? cur - l * nx : nx - l * cur;
+        }
+      }
+      x[n - 1] = cur;
+    }
+  }
+  if (lane == 0) {
     // back substitution, the two later entries in registers
-    double x1 = cb / cd, x2 = 0.0;
+    double x1 = x[n - 1] * rp[n - 1], x2 = 0.0;
     x[n - 1] = x1;
     for (int i0 = n - 2; i0 >= 0; i0 -= EC) {
-      double b_[EC], u1_[EC], u2_[EC], d_[EC];
+      double b_[EC], u1_[EC], u2_[EC], r_[EC];
 #pragma unroll
       for (int u = 0; u < EC; ++u) {
         const int i = max(i0 - u, 0);
         b_[u] = x[i];
-        u1_[u] = du[i];
-        u2_[u] = du2[i];
-        d_[u] = dd[i];
+        u1_[u] = u1[i];
+        u2_[u] = u2[i];
+        r_[u] = rp[i];
       }
 #pragma unroll
       for (int u = 0; u < EC; ++u) {
         const int i = i0 - u;
         if (i < 0) break;
-        const double x0 = (b_[u] - u1_[u] * x1 - u2_[u] * x2) / d_[u];
+        const double x0 = (b_[u] - u1_[u] * x1 - u2_[u] * x2) * r_[u];
         x[i] = x0;
         x2 = x1;
         x1 = x0;
       }
     }
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  wave_lds_sync();
   // scale to unit max-norm (keeps the later dot products in range)
   double mx = 0.0;
   for (int i = lane; i < n; i += 64) mx = fmax(mx, fabs(x[i]));
@@ -456,21 +516,29 @@ __global__ void __launch_bounds__(64 * EIG_VPB) k_eig_solve(EigBatch batch, cons
   for (int i = lane; i < n; i += 64) xb[i * 64 + j] = x[i] * sc;
 }
 
-// Orthonormalisation of one mode's K vectors: thread (q = tid % 64, g = tid / 64) holds
-// entries g, g + 16, ... of vector q in registers. Step j normalises vector j (its
-// owners publish it in LDS) and removes its component from the later members of its
-// cluster; LDS buffers alternate between steps, so a step needs at most two barriers.
-// The last round writes the column-major eigenvector block instead.
+// Orthonormalisation of one mode's K vectors: wave g holds rows g*MGS_R .. g*MGS_R +
+// MGS_R - 1 of all vectors, lane q those of vector q, in registers. Step j reads vector
+// j's entries from lane j of each wave, forms every wave's partial squared norm of it
+// and partial dot products with the later members of its cluster, and after one
+// barrier normalises vector j and removes its component from those members (partials
+// in LDS buffers that alternate between steps). The last round writes the column-major
+// eigenvector block instead.
 #define MGS_G 16
 #define MGS_R (NE / MGS_G)
+__device__ __forceinline__ double lane_get(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 __global__ void __launch_bounds__(1024) k_eig_orth(EigBatch batch, const double* lam_in, double* scratch, int last) {
   const EigArgs a = batch.m[blockIdx.x];
   const int n = a.Nn, K = a.k;
   const EigWs w = eig_ws(a);
   const double* lam = lam_in + (long long)blockIdx.x * (TDB_RCAP + 2);
   const double tn = lam[TDB_RCAP + 1];
-  double* xb = scratch + (long long)blockIdx.x * NE * 64;
-  __shared__ double y[2][NE], part[2][MGS_G][64], red[2][MGS_G];
+  double* xb = scratch + (long long)blockIdx.x * NE * 64 * (1 + EIG_NF);
+  __shared__ double part[2][MGS_G][64], red[2][MGS_G];
   __shared__ int cend[TDB_RCAP];
   const int q = threadIdx.x & 63, g = threadIdx.x >> 6;
   if (threadIdx.x == 0) {
@@ -486,60 +554,48 @@ __global__ void __launch_bounds__(1024) k_eig_orth(EigBatch batch, const double*
   double x[MGS_R];
 #pragma unroll
   for (int s = 0; s < MGS_R; ++s) {
-    const int i = g + MGS_G * s;
+    const int i = g * MGS_R + s;
     x[s] = (q < K && i < n) ? xb[i * 64 + q] : 0.0;
   }
   __syncthreads();
   for (int j = 0; j < K; ++j) {
     const int b = j & 1;
-    if (q == j) {
-      double ps = 0.0;
+    const int ce = cend[j];
+    double ps = 0.0, pd = 0.0;
 #pragma unroll
-      for (int s = 0; s < MGS_R; ++s) {
-        const int i = g + MGS_G * s;
-        if (i < n) y[b][i] = x[s];
-        ps += x[s] * x[s];
-      }
-      red[b][g] = ps;
+    for (int s = 0; s < MGS_R; ++s) {
+      const double y = lane_get(x[s], j);
+      ps += y * y;
+      pd += x[s] * y;
     }
+    if (q == 0) red[b][g] = ps;
+    part[b][g][q] = pd;
     __syncthreads();
     double nr = 0.0;
 #pragma unroll
     for (int t = 0; t < MGS_G; ++t) nr += red[b][t];
     const double inv = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
-    if (q == j) {
-#pragma unroll
-      for (int s = 0; s < MGS_R; ++s) x[s] *= inv;
-    }
-    const int ce = cend[j];
-    if (ce <= j + 1) continue;
     const bool act = q > j && q < ce;
-    if (act) {
-      double pd = 0.0;
-#pragma unroll
-      for (int s = 0; s < MGS_R; ++s) {
-        const int i = g + MGS_G * s;
-        if (i < n) pd += x[s] * y[b][i];
-      }
-      part[b][g][q] = pd;
-    }
-    __syncthreads();
+    double c = 0.0;
     if (act) {
       double dq = 0.0;
 #pragma unroll
       for (int t = 0; t < MGS_G; ++t) dq += part[b][t][q];
-      const double c = dq * inv * inv;
+      c = dq * inv * inv;
+    }
+    const double sj = q == j ? inv : 1.0;
+    if (j + 1 < ce || q == j) {
 #pragma unroll
       for (int s = 0; s < MGS_R; ++s) {
-        const int i = g + MGS_G * s;
-        if (i < n) x[s] -= c * y[b][i];
+        const double y = lane_get(x[s], j);
+        x[s] = x[s] * sj - c * y;
       }
     }
   }
   if (q >= K) return;
 #pragma unroll
   for (int s = 0; s < MGS_R; ++s) {
-    const int i = g + MGS_G * s;
+    const int i = g * MGS_R + s;
     if (i < n) {
       if (last) w.X[(long long)q * n + i] = x[s];
       else xb[i * 64 + q] = x[s];

@@ -61,7 +61,7 @@ struct tdb_ctx {
   double *Umax[TDB_P] = {}, *Bmax[TDB_P] = {}, *Cmax = nullptr, *hsA = nullptr, *hsB = nullptr;
   double *wa[TDB_P] = {}, *wb[TDB_P] = {}, *nu2h = nullptr;
   double* eig_lam = nullptr;     // eigenvalues of the mode Grams (per mode, TDB_RCAP + 2)
-  double* eig_vec = nullptr;     // inverse-iteration vectors (per mode, TDB_NEIG x 64)
+  double* eig_vec = nullptr;     // inverse-iteration vectors and factors (per mode, TDB_NEIG x 64 x 6)
   double *Psi[TDB_P] = {};
   // snapshots
   const void* Vprev = nullptr;
@@ -399,7 +399,7 @@ tdb_status setup(tdb_ctx* h, const tdb_config* cfg) {
     long long nmax = 1;
     for (int n = 0; n < h->p; ++n) nmax = std::max(nmax, h->N[n]);
     (void)nmax;
-    TRY(dallocT(h, &h->eig_vec, (size_t)TDB_P * TDB_NEIG * 64));
+    TRY(dallocT(h, &h->eig_vec, (size_t)TDB_P * TDB_NEIG * 64 * 6));
   }
   if (cfg->snapshot_mode == TDB_COPY) TRY(dalloc(h, &h->Vcopy, (size_t)h->S * h->delt));
 

@@ -112,7 +112,7 @@ struct EigBatch {
   int count;
   EigArgs m[TDB_P];
 };
-// lam_scratch: count x (TDB_RCAP + 2) doubles; vec_scratch: count x TDB_NEIG x 64
+// lam_scratch: count x (TDB_RCAP + 2) doubles; vec_scratch: count x TDB_NEIG x 64 x 6
 // doubles of device workspace.
 hipError_t launch_sym_eig(const EigBatch& b, double* lam_scratch, double* vec_scratch, hipStream_t s);
 
