@@ -201,6 +201,17 @@ static __device__ void controller_decide(CtrlState* c) {
 
 namespace tdb {
 
+// floor(t / d) for 0 <= t < 2^22 and d >= 1, given inv = 1.0f / d: the float quotient
+// is within one of the exact one (relative error below 2^-23), and the remainder
+// corrects it.
+__device__ __forceinline__ int small_div(int t, int d, float inv) {
+  int q = (int)((float)t * inv);
+  const int r = t - q * d;
+  q += (r >= d) ? 1 : 0;
+  q -= (r < 0) ? 1 : 0;
+  return q;
+}
+
 // ===================================================================== block copies
 // Copy n values from global memory into LDS (converted to the LDS type), with up to 16
 // loads in flight per thread before any is stored, so that a short copy costs one
@@ -309,6 +320,40 @@ static __device__ void wave_tri_inv(const double* L, double* Li, int rn) {
     }
   }
   wave_fence();
+}
+
+// L^-1 of the lower-triangular L (rn x rn, row-major in LDS) by one wave, lane j
+// forming column j by forward substitution in registers; the entries of L are read
+// from LDS at addresses common to all lanes, and rdiag holds 1 / L[i][i].
+template <int RB>
+__device__ __forceinline__ void wave_tri_inv_reg(const double* L, double* Li, int rn, const double* rdiag) {
+  const int j = threadIdx.x & 63;
+  double y[RB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i) {
+    double s = (i == j) ? 1.0 : 0.0;
+    if (i < rn) {
+#pragma unroll
+      for (int k = 0; k < i; ++k) s -= L[i * rn + k] * y[k];
+      s *= rdiag[i];
+    }
+    y[i] = s;
+  }
+  if (j < rn)
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+      if (i < rn) Li[i * rn + j] = y[i];
+  wave_fence();
+}
+
+// L^-1 by one wave (rdiag: LDS scratch of rn doubles).
+__device__ __forceinline__ void wave_tri_inv_fast(const double* L, double* Li, int rn, double* rdiag) {
+  const int l = threadIdx.x & 63;
+  for (int i = l; i < rn; i += 64) rdiag[i] = 1.0 / L[i * rn + i];
+  wave_fence();
+  if (rn <= 16) wave_tri_inv_reg<16>(L, Li, rn, rdiag);
+  else if (rn <= 32) wave_tri_inv_reg<32>(L, Li, rn, rdiag);
+  else wave_tri_inv(L, Li, rn);
 }
 
 // Gi = Li^T Li (the inverse of L L^T), lanes over entries.

@@ -53,17 +53,21 @@ struct FFinishArgs {
   int m_inline;              // 1: each row block forms M_n itself (no k_fmprep launch)
 };
 
+#define QR_ROWS 64     // rows of U_n per block of the QR kernels
+#define FOLD_R 8       // core entries per thread when the QR folds the core in place (256 threads)
+
 struct FQrArgs {
-  int core_in_lds, rmax;
+  int core_in_lds, rmax;     // core_in_lds: 2 folded in place, 1 in two LDS buffers, 0 in global memory
   long long N[3];
   int r[3], ldU[3];
-  int u_in_lds[3];
+  int nb[3];                 // QR_ROWS-row slabs of U_n (blocks of mode n in both QR kernels)
   double* U0[3];
   const double* w[3];
-  double* Rq[3];
+  double* Li[3];             // L_n^-1 (U_n <- U_n L_n^-T by the post-step)
+  double* gpart[3];          // nb[n] slab partial Grams of r_n x r_n
   double* C0;
   double* Ctmp;
-  unsigned* counter;
+  unsigned* counter;         // blocks done
   double* T3;                // C x_3 U_3 (r1 x r2 x N3) of the folded core, for the error pass
 };
 
@@ -81,7 +85,11 @@ struct FPostArgs {
   const double* T3;          // C x_3 U_3 when already formed (else NULL: formed per block)
   int want_sigma;            // also form the singular values of the core unfoldings
   double* G[3];              // core Grams C_(n) C_(n)^T kept for a later singular-value test
+  const double* Li[3];       // when set: U_n is not yet normalised, U_n <- U_n L_n^-T first
+  double* Uw[3];             // U_n (written back normalised when Li is set)
+  int stage_all;             // expansion blocks stage all their rows at once (else POST_CH at a time)
 };
+#define POST_CH 64           // rows per chunk of the expansion blocks
 
 struct FErrArgs {
   const void* V;

@@ -408,23 +408,27 @@ __device__ __forceinline__ void ffinish_body(const FFinishArgs& a, int stage, Ct
   double* Gp = Gi + rq * rq;                 // FQR_GP partial blocks
   double* Cl = Gp + FQR_GP;
   __shared__ int ok_s;
-  const double* Csrc = a.Cs;
-  if (a.core_in_lds) {
-    g2l(Cl, Csrc, (int)csz);
-    __syncthreads();
-    Csrc = Cl;
-  }
-  gram_from(Csrc, rn, R, inner, G, Gp);
-  if (threadIdx.x < 64) {
-    const bool ok = wave_chol_inv(G, rn, Li, Gi);
-    if (threadIdx.x == 0) {
-      ok_s = ok ? 1 : 0;
-      if (!ok) atomicOr(&ctrl->numeric, 1);
+  // the core from LDS or from global memory (separate instances: fixed address spaces)
+  auto pinv = [&](const double* Csrc) {
+    gram_from(Csrc, rn, R, inner, G, Gp);
+    if (threadIdx.x < 64) {
+      const bool ok = wave_chol_inv(G, rn, Li, Gi);
+      if (threadIdx.x == 0) {
+        ok_s = ok ? 1 : 0;
+        if (!ok) atomicOr(&ctrl->numeric, 1);
+      }
     }
+    __syncthreads();
+    if (!ok_s) return;
+    write_p<T>(Csrc, Gi, rn, R, inner, static_cast<T*>(a.P[n]));
+  };
+  if (a.core_in_lds) {
+    g2l(Cl, a.Cs, (int)csz);
+    __syncthreads();
+    pinv(Cl);
+  } else {
+    pinv(a.Cs);
   }
-  __syncthreads();
-  if (!ok_s) return;
-  write_p<T>(Csrc, Gi, rn, R, inner, static_cast<T*>(a.P[n]));
 }
 
 template <typename T>
@@ -433,15 +437,131 @@ __global__ void __launch_bounds__(256) k_ffinish(FFinishArgs a, CtrlState* ctrl)
 }
 
 // ---------------------------------------------------------------- QR + fold
-// Block n: one round of Cholesky QR of U_n in the W inner product (the Heun update
-// leaves U_n W-orthonormal to O(dt^2), so a single round reaches roundoff): the Gram
-// matrix U^T W U on the FP64 matrix cores, its Cholesky factor R^T R and R^-1 by one
-// wave, then U <- U R^-1, again on the matrix cores. The last block to finish folds
-// every R_n into the core (C <- C x_n R_n), so the reconstruction is unchanged.
-__device__ __forceinline__ void fqr_body(const FQrArgs& a, CtrlState* ctrl, int bx, int gx) {
+// One round of Cholesky QR of every U_n in the W inner product (the Heun update leaves
+// U_n W-orthonormal to O(dt^2), so a single round reaches roundoff). Block (n, slab):
+// the slab's partial Gram sum_q w_q u_q u_q^T. The last block to finish sums every
+// mode's partials in slab order, factors the three Grams as L_n L_n^T (one wave per
+// mode), publishes L_n^-1, and folds R_n = L_n^T into the core (C <- C x_n R_n, so the
+// reconstruction is unchanged), forming T3 = C x_3 U_3 of the folded core on the way.
+// The post-step then takes U_n <- U_n R_n^-1 = U_n L_n^-T (it reads every row anyway).
+__device__ __forceinline__ int qr_mode(const FQrArgs& a, int bx, int& rb) {
+  if (bx < a.nb[0]) { rb = bx; return 0; }
+  bx -= a.nb[0];
+  if (bx < a.nb[1]) { rb = bx; return 1; }
+  rb = bx - a.nb[1];
+  return 2;
+}
+
+// C <- C x_1 R_1 x_2 R_2 x_3 R_3 with R_m = L_m^T (L_m lower triangular with zeros
+// above the diagonal, in LDS) and, between the second and third products,
+// T3 = (C x_1 R_1 x_2 R_2) x_3 U_3 = C_new x_3 (U_3 R_3^-1) with U_3 before its
+// normalisation. CM 2: the core is in LDS (X) and each product is taken in place
+// through registers (at most FOLD_R outputs per thread); CM 1: the products alternate
+// between two LDS buffers; CM 0: between C0 and Ctmp in global memory. They are
+// separate instances so that every access has a fixed address space.
+template <int CM>
+__device__ __forceinline__ void fold_core(const FQrArgs& a, const double* L0, const double* L1, const double* L2,
+                                          const double* Gp, double* X, int csz, bool u3l) {
+  const int N3 = (int)a.N[2], ld3 = a.ldU[2];
+  double* ca = CM ? X : a.C0;
+  double* cb = CM == 2 ? X : (CM == 1 ? X + csz : a.Ctmp);
+  for (int m = 0; m < 3; ++m) {
+    const int rm = a.r[m];
+    const double* Lm = m == 0 ? L0 : (m == 1 ? L1 : L2);
+    if (m == 2 && a.T3) {
+      const int r12 = a.r[0] * a.r[1], r3 = a.r[2];
+      const float i_n3 = 1.0f / (float)N3;
+      const bool fast = r12 * N3 < (1 << 22);
+      if (u3l) {
+        for (int t = threadIdx.x; t < r12 * N3; t += blockDim.x) {
+          const int ab = fast ? small_div(t, N3, i_n3) : t / N3, i3 = t - ab * N3;
+          double sv = 0.0;
+          for (int c = 0; c < r3; ++c) sv += ca[ab * r3 + c] * Gp[i3 * ld3 + c];
+          a.T3[t] = sv;
+        }
+      } else {
+        const double* U3 = a.U0[2];
+        for (int t = threadIdx.x; t < r12 * N3; t += blockDim.x) {
+          const int ab = fast ? small_div(t, N3, i_n3) : t / N3, i3 = t - ab * N3;
+          double sv = 0.0;
+          for (int c = 0; c < r3; ++c) sv += ca[ab * r3 + c] * U3[i3 * ld3 + c];
+          a.T3[t] = sv;
+        }
+      }
+    }
+    int inner = 1;
+    for (int k = m + 1; k < 3; ++k) inner *= a.r[k];
+    const float i_inner = 1.0f / (float)inner, i_rm = 1.0f / (float)rm;
+    // output (o, ai, in) = sum_{b >= ai} R[ai][b] C[o][b][in], R[ai][b] = L[b][ai]
+    // (zero for b < ai); outputs in groups of four with their sums interleaved
+    if (CM == 2) {
+      double sv[FOLD_R];
+      const int nug = (csz + (int)blockDim.x - 1) / (int)blockDim.x;   // common to the block
+#pragma unroll
+      for (int g = 0; g < FOLD_R; g += 4) {
+        sv[g] = sv[g + 1] = sv[g + 2] = sv[g + 3] = 0.0;
+        if (g < nug) {
+          int ai_[4], bs_[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int t = min((int)threadIdx.x + (g + u) * (int)blockDim.x, csz - 1);
+            const int rest = small_div(t, inner, i_inner), in = t - rest * inner;
+            const int o = small_div(rest, rm, i_rm);
+            ai_[u] = rest - o * rm;
+            bs_[u] = o * rm * inner + in;
+          }
+#pragma unroll 4
+          for (int b = 0; b < rm; ++b) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) sv[g + u] += Lm[b * rm + ai_[u]] * ca[bs_[u] + b * inner];
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < FOLD_R; ++u) {
+        const int t = (int)threadIdx.x + u * (int)blockDim.x;
+        if (t < csz) ca[t] = sv[u];
+      }
+      __syncthreads();
+    } else {
+      for (int t0 = threadIdx.x; t0 < csz; t0 += 4 * (int)blockDim.x) {
+        int ai_[4], bs_[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int t = min(t0 + u * (int)blockDim.x, csz - 1);
+          const int rest = csz < (1 << 22) ? small_div(t, inner, i_inner) : t / inner, in = t - rest * inner;
+          const int o = rest / rm;
+          ai_[u] = rest - o * rm;
+          bs_[u] = o * rm * inner + in;
+        }
+        double sv[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int b = 0; b < rm; ++b) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) sv[u] += Lm[b * rm + ai_[u]] * ca[bs_[u] + b * inner];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int t = t0 + u * (int)blockDim.x;
+          if (t < csz) cb[t] = sv[u];
+        }
+      }
+      __syncthreads();
+      double* tswap = ca; ca = cb; cb = tswap;
+    }
+  }
+  if (CM) {
+    for (int t = threadIdx.x; t < csz; t += blockDim.x) a.C0[t] = ca[t];
+  } else if (ca != a.C0) {
+    for (int t = threadIdx.x; t < csz; t += blockDim.x) a.C0[t] = ca[t];
+  }
+}
+
+__device__ __forceinline__ void fqr_body(const FQrArgs& a, CtrlState* ctrl, int bx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
-  __shared__ int last, skip_s, ok_s;
+  __shared__ int last, skip_s, ok_s[3];
   if (ctrl->hold) return;   // every block alike, so the completion count stays at zero
   // every block takes part in the completion count, even when there is nothing to do;
   // the flag is read once per block so that the whole block takes the same branch
@@ -449,161 +569,132 @@ __device__ __forceinline__ void fqr_body(const FQrArgs& a, CtrlState* ctrl, int 
     skip_s = __hip_atomic_load(&ctrl->numeric, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
   __syncthreads();
   const bool skip = skip_s != 0;
-  const int n = bx;
-  const int rn = a.r[n], ld = a.ldU[n];
-  const int Nn = (int)a.N[n];
-  const int rq = a.rmax;
-  double* L = lds;                          // rq*rq
-  double* Li = L + rq * rq;                 // rq*rq
-  double* Rt = Li + rq * rq;                // rq*rq
-  double* Tm = Rt + rq * rq;                // rq*rq
-  double* Gp = Tm + rq * rq;                // FQR_GP partial Gram blocks
-  double* wl = Gp + FQR_GP;                 // Nn weights
-  double* Ul = wl + TDB_NEIG;               // Nn*rn when staged (or the core for the fold)
-  double* U = a.U0[n];
-  const bool stage = a.u_in_lds[n] && !skip;
+  int rb;
+  const int n = qr_mode(a, bx, rb);
   if (!skip) {
-    // the weights and (when staged) U_n, with up to 16 loads in flight per thread
-    const int tot = Nn + (stage ? Nn * rn : 0);
-    const double* w = a.w[n];
-    for (int base = 0; base < tot; base += 16 * blockDim.x) {
-      double v[16];
+    const int rn = a.r[n], ld = a.ldU[n];
+    const int Nn = (int)a.N[n];
+    const int rr = rn * rn;
+    // the slab's rows u_q and w_q u_q, up to 8 loads in flight per thread
+    const int q0 = rb * QR_ROWS, nr = min(QR_ROWS, Nn - q0);
+    double* Ul = lds;
+    double* Wl = lds + QR_ROWS * rn;
+    const double* U = a.U0[n] + (long long)q0 * ld;
+    const double* w = a.w[n] + q0;
+    const int tot = nr * rn;
+    for (int base = 0; base < tot; base += 8 * (int)blockDim.x) {
+      double v[8], wv[8];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int t = base + u * blockDim.x + threadIdx.x;
-        v[u] = 0.0;
-        if (t < Nn) v[u] = w[t];
-        else if (t < tot) { const int q = t - Nn, i = q / rn; v[u] = U[i * ld + (q - i * rn)]; }
+      for (int u = 0; u < 8; ++u) {
+        const int t = base + u * (int)blockDim.x + (int)threadIdx.x;
+        const int q = t / rn;
+        v[u] = t < tot ? U[q * ld + (t - q * rn)] : 0.0;
+        wv[u] = t < tot ? w[q] : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int t = base + u * blockDim.x + threadIdx.x;
-        if (t < Nn) wl[t] = v[u];
-        else if (t < tot) Ul[t - Nn] = v[u];
-      }
-    }
-  }
-  __syncthreads();
-  double* Uw = stage ? Ul : U;
-  const int ldw = stage ? rn : ld;
-  bool ok = !skip;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int lm = lane & 15, lk = lane >> 4;
-  const int nb = (rn + 15) >> 4;            // 16-wide blocks of the rank
-  if (ok) {
-    // Gram U^T W U on the FP64 matrix cores
-    block_xyt_f64(
-        rn, Nn, true, [&](int i, int q) { return wl[q] * Uw[q * ldw + i]; }, [&](int j, int q) { return Uw[q * ldw + j]; },
-        [&](int r, int c, double v) {
-          L[r * rn + c] = v;
-          L[c * rn + r] = v;
-        },
-        Gp);
-    if (threadIdx.x < 64) {
-      const bool okw = wave_chol_inv(L, rn, Li, nullptr);
-      if (threadIdx.x == 0) ok_s = okw ? 1 : 0;
-    }
-    __syncthreads();
-    ok = ok_s != 0;
-  }
-  if (ok) {
-    // U <- U R^-1 = U Li^T on the matrix cores: 16-row blocks, one per wave at a time.
-    // Column j of the result needs columns k <= j only, so taking the column blocks
-    // from the last to the first lets each block be stored in place at once.
-    for (int rb = wid; rb * 16 < Nn; rb += 4) {
-      const int q = rb * 16 + lm;
-      for (int cj = nb - 1; cj >= 0; --cj) {
-        md4 acc = {0.0, 0.0, 0.0, 0.0};
-        const int j = 16 * cj + lm;
-        const int kend = min(rn, 16 * cj + 16);
-        for (int k0 = 0; k0 < kend; k0 += 4) {
-          const int k = k0 + lk;
-          const double av = (q < Nn && k < kend) ? Uw[q * ldw + k] : 0.0;
-          const double bv = (j < rn && k < kend) ? Li[j * rn + k] : 0.0;
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int qr = rb * 16 + lk + 4 * i;
-          if (qr < Nn && j < rn) Uw[qr * ldw + j] = acc[i];
+      for (int u = 0; u < 8; ++u) {
+        const int t = base + u * (int)blockDim.x + (int)threadIdx.x;
+        if (t < tot) {
+          Ul[t] = v[u];
+          Wl[t] = wv[u] * v[u];
         }
       }
     }
-    // R = L^T
-    for (int t = threadIdx.x; t < rn * rn; t += blockDim.x) {
-      const int i = t / rn, j = t - (t / rn) * rn;
-      Rt[t] = L[j * rn + i];
-    }
     __syncthreads();
-  }
-  if (skip) {
-  } else if (!ok) {
-    if (threadIdx.x == 0) atomicOr(&ctrl->numeric, 2);
-  } else {
-    if (stage)
-      for (int t = threadIdx.x; t < Nn * rn; t += blockDim.x) {
-        const int i = t / rn;
-        U[i * ld + (t - i * rn)] = Ul[t];
+    // upper triangle (mirrored), four partial sums over the rows
+    double* g = a.gpart[n] + (long long)rb * rr;
+    for (int e = threadIdx.x; e < rr; e += blockDim.x) {
+      const int i = e / rn, j = e - (e / rn) * rn;
+      if (j < i) continue;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int q = 0;
+      for (; q + 4 <= nr; q += 4) {
+        s0 += Wl[q * rn + i] * Ul[q * rn + j];
+        s1 += Wl[(q + 1) * rn + i] * Ul[(q + 1) * rn + j];
+        s2 += Wl[(q + 2) * rn + i] * Ul[(q + 2) * rn + j];
+        s3 += Wl[(q + 3) * rn + i] * Ul[(q + 3) * rn + j];
       }
-    for (int t = threadIdx.x; t < rn * rn; t += blockDim.x) a.Rq[n][t] = Rt[t];
+      for (; q < nr; ++q) s0 += Wl[q * rn + i] * Ul[q * rn + j];
+      const double sv = (s0 + s1) + (s2 + s3);
+      g[i * rn + j] = sv;
+      g[j * rn + i] = sv;
+    }
   }
-  // last block folds the factors into the core
+  // the last block factors the three Grams and folds the core
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned prev = __hip_atomic_fetch_add(a.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (prev == gx - 1) ? 1 : 0;
+    last = (prev == (unsigned)(a.nb[0] + a.nb[1] + a.nb[2]) - 1) ? 1 : 0;
   }
   __syncthreads();
   if (!last) return;
-  // the fence orders the plain loads below after every block's stores of R_n and U_n
+  // the fence orders the plain loads below after every block's stores of its partials
   __threadfence();
   if (threadIdx.x == 0) *a.counter = 0u;
-  if (__hip_atomic_load(&ctrl->numeric, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) return;
-  int csz = 1;
-  for (int k = 0; k < 3; ++k) csz *= a.r[k];
-  // core in LDS (two buffers) when it fits, else ping-pong through global memory; the
-  // three factors and (when it fits) U_3 in one load phase
-  double* ca = a.core_in_lds ? Ul : a.C0;
-  double* cb = a.core_in_lds ? Ul + csz : a.Ctmp;
+  if (skip) return;
+  const int r0 = a.r[0], r1 = a.r[1], r2 = a.r[2];
+  const int rq = a.rmax;
+  double* L0 = lds;                         // rq*rq each
+  double* L1 = L0 + rq * rq;
+  double* L2 = L1 + rq * rq;
+  double* rdg = L2 + rq * rq;               // 3 x 64: reciprocal diagonals
+  double* Gp = rdg + 3 * 64;                // FQR_GP (U_3 when it fits)
+  double* X = Gp + FQR_GP;                  // the core (one or two buffers) when folded in LDS
+  int csz = r0 * r1 * r2;
   const int N3 = (int)a.N[2], ld3 = a.ldU[2];
   const bool u3l = a.T3 && N3 * ld3 <= FQR_GP;
-  g2l5(ca, a.C0, a.core_in_lds ? csz : 0, L, a.Rq[0], a.r[0] * a.r[0], Li, a.Rq[1], a.r[1] * a.r[1], Tm, a.Rq[2],
-       a.r[2] * a.r[2], Gp, a.U0[2], u3l ? N3 * ld3 : 0);
+  {
+    // one load phase: the summed Grams (partials in slab order), the core (when it is
+    // folded in LDS) and U_3 (when it fits)
+    const int g0 = r0 * r0, g1 = g0 + r1 * r1, g2 = g1 + r2 * r2;
+    const int c1 = g2 + (a.core_in_lds ? csz : 0), tot = c1 + (u3l ? N3 * ld3 : 0);
+    for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+      if (t < g2) {
+        const int m = t < g0 ? 0 : (t < g1 ? 1 : 2);
+        const int e = t - (m == 0 ? 0 : (m == 1 ? g0 : g1));
+        const int rr = m == 0 ? r0 * r0 : (m == 1 ? r1 * r1 : r2 * r2);
+        const int nbm = m == 0 ? a.nb[0] : (m == 1 ? a.nb[1] : a.nb[2]);
+        const double* gp = (m == 0 ? a.gpart[0] : (m == 1 ? a.gpart[1] : a.gpart[2])) + e;
+        double sv = 0.0;
+        int b = 0;
+        for (; b + 8 <= nbm; b += 8) {
+          double v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] = gp[(long long)(b + u) * rr];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) sv += v[u];
+        }
+        for (; b < nbm; ++b) sv += gp[(long long)b * rr];
+        (m == 0 ? L0 : (m == 1 ? L1 : L2))[e] = sv;
+      } else if (t < c1) {
+        X[t - g2] = a.C0[t - g2];
+      } else {
+        Gp[t - c1] = a.U0[2][t - c1];
+      }
+    }
+  }
   __syncthreads();
-  for (int m = 0; m < 3; ++m) {
-    const int rm = a.r[m];
-    const double* Rm = m == 0 ? L : (m == 1 ? Li : Tm);
-    int inner = 1;
-    for (int k = m + 1; k < 3; ++k) inner *= a.r[k];
-    for (int t = threadIdx.x; t < csz; t += blockDim.x) {
-      const int in = t % inner, rest = t / inner;
-      const int ai = rest % rm;
-      const int o = rest / rm;
-      double s = 0.0;
-      for (int b = ai; b < rm; ++b) s += Rm[ai * rm + b] * ca[(o * rm + b) * inner + in];
-      cb[t] = s;
-    }
-    __syncthreads();
-    double* tswap = ca; ca = cb; cb = tswap;
+  const int wid = threadIdx.x >> 6;
+  if (wid < 3) {
+    // wave m: L_m L_m^T = G_m and L_m^-1 (published for the post-step)
+    const int rm = wid == 0 ? r0 : (wid == 1 ? r1 : r2);
+    double* Lm = wid == 0 ? L0 : (wid == 1 ? L1 : L2);
+    const bool ok = wave_chol_inv(Lm, rm, nullptr, nullptr);
+    if (ok) wave_tri_inv_fast(Lm, wid == 0 ? a.Li[0] : (wid == 1 ? a.Li[1] : a.Li[2]), rm, rdg + 64 * wid);
+    if ((threadIdx.x & 63) == 0) ok_s[wid] = ok ? 1 : 0;
   }
-  for (int t = threadIdx.x; t < csz; t += blockDim.x) a.C0[t] = ca[t];
-  // T3 = C x_3 U_3 of the folded core, for the error-pass expansion
-  if (a.T3) {
-    const int r12 = a.r[0] * a.r[1], r3 = a.r[2];
-    const double* U3 = u3l ? Gp : a.U0[2];
-    for (int t = threadIdx.x; t < r12 * N3; t += blockDim.x) {
-      const int ab = t / N3, i3 = t - (t / N3) * N3;
-      double s = 0.0;
-      for (int c = 0; c < r3; ++c) s += ca[ab * r3 + c] * U3[i3 * ld3 + c];
-      a.T3[t] = s;
-    }
+  __syncthreads();
+  if (!(ok_s[0] && ok_s[1] && ok_s[2])) {
+    if (threadIdx.x == 0) atomicOr(&ctrl->numeric, 2);
+    return;
   }
+  if (a.core_in_lds == 2) fold_core<2>(a, L0, L1, L2, Gp, X, csz, u3l);
+  else if (a.core_in_lds == 1) fold_core<1>(a, L0, L1, L2, Gp, X, csz, u3l);
+  else fold_core<0>(a, L0, L1, L2, Gp, X, csz, u3l);
 }
 
-__global__ void __launch_bounds__(256) k_fqr(FQrArgs a, CtrlState* ctrl) {
-  fqr_body(a, ctrl, blockIdx.x, gridDim.x);
-}
+__global__ void __launch_bounds__(256) k_fqr(FQrArgs a, CtrlState* ctrl) { fqr_body(a, ctrl, blockIdx.x); }
 
 // ---------------------------------------------------------------- post-step
 // Blocks [0, 3): for mode n at the new state: the core Gram (kept for the controller),
@@ -620,15 +711,23 @@ __device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, 
   __shared__ int order[TDB_RCAP];
   if (ctrl->hold) return;
   if (ROLE == ROLE_EXP || (ROLE == ROLE_ALL && (int)bx >= 3)) {
-    // E[a][i2][i3] = sum_b U2[i2][b] T3[a][b][i3],  T3[a][b][i3] = sum_c C[a][b][c] U3[i3][c]
+    // Block eb takes rows [eb*per_n, (eb+1)*per_n) of every mode, POST_CH at a time:
+    // when the QR left U_n unnormalised, U_n <- U_n L_n^-T and the rows are written
+    // back; then B_n = W_n U_n, the mode-1 basis in the compute type, and from the
+    // mode-2 rows the expansion E[a][i2][i3] = sum_b U2[i2][b] T3[a][b][i3] with
+    // T3[a][b][i3] = sum_c C[a][b][c] U3[i3][c].
     const int eb = ROLE == ROLE_EXP ? bx : bx - 3;
     const int r1 = a.r[0], r2 = a.r[1], r3 = a.r[2];
     const long long N2 = a.N[1], N3 = a.N[2];
+    const int rq = a.rmax;
     double* T3 = lds;                                   // r1*r2*N3
-    double* U2l = T3 + (long long)r1 * r2 * N3;         // rows of U2 of this block
-    const long long per = (N2 + a.eblocks - 1) / a.eblocks;
-    const long long i2a = (long long)eb * per, i2b = min(N2, i2a + per);
-    if (i2a < i2b) {
+    double* Lil = T3 + (long long)r1 * r2 * N3;         // rq*rq
+    double* Ul = Lil + rq * rq;                         // POST_CH * rq (raw rows)
+    double* Un = Ul + POST_CH * rq;                     // POST_CH * rq (normalised rows)
+    const bool norm = a.Li[0] != nullptr && !ctrl->numeric;
+    const long long per2 = (N2 + a.eblocks - 1) / a.eblocks;
+    const bool erows = (long long)eb * per2 < N2;
+    if (erows) {
       if (a.T3) {
         g2l(T3, a.T3, r1 * r2 * (int)N3);
       } else {
@@ -636,46 +735,210 @@ __device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, 
           const long long i3 = t % N3, ab = t / N3;
           const double* cr = a.C + ab * r3;
           const double* u3 = a.U[2] + i3 * a.ldU[2];
-          double s = 0.0;
-          for (int c = 0; c < r3; ++c) s += cr[c] * u3[c];
-          T3[t] = s;
+          double sv = 0.0;
+          for (int c = 0; c < r3; ++c) sv += cr[c] * u3[c];
+          T3[t] = sv;
         }
       }
-      for (long long t = threadIdx.x; t < (i2b - i2a) * r2; t += blockDim.x) {
-        const long long i = t / r2;
-        U2l[t] = a.U[1][(i2a + i) * a.ldU[1] + (t - i * r2)];
+    }
+    if (a.stage_all) {
+      // every input of the block in one load phase: T3 (already in LDS), the three
+      // L^-1 and this block's rows of all three modes
+      // (per-mode values in named scalars: a runtime mode index picks among them)
+      double* base = Lil;
+      int ia0, ia1, ia2, nr0, nr1, nr2;
+      {
+        int* iav[3] = {&ia0, &ia1, &ia2};
+        int* nrv[3] = {&nr0, &nr1, &nr2};
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          const long long per = (a.N[m] + a.eblocks - 1) / a.eblocks;
+          const long long ia = (long long)eb * per, ib = min(a.N[m], ia + per);
+          *iav[m] = (int)ia;
+          *nrv[m] = ia < ib ? (int)(ib - ia) : 0;
+        }
+      }
+      const int q0 = a.r[0], q1 = a.r[1], q2 = a.r[2];
+      const int l0 = norm ? q0 * q0 : 0, l1 = norm ? q1 * q1 : 0, l2 = norm ? q2 * q2 : 0;
+      const int e0 = nr0 * q0, e1 = nr1 * q1, e2 = nr2 * q2;
+      const int oL0 = 0, oL1 = l0, oL2 = l0 + l1;
+      const int oU0 = l0 + l1 + l2, oU1 = oU0 + e0, oU2 = oU1 + e1;
+      const int tot = oU2 + e2, nsum = e0 + e1 + e2;
+      const int oN0 = tot, oN1 = tot + e0, oN2 = tot + e0 + e1;
+      const double* Li0 = a.Li[0];
+      const double* Li1 = a.Li[1];
+      const double* Li2 = a.Li[2];
+      const double* Ug0 = a.U[0] + (long long)ia0 * a.ldU[0];
+      const double* Ug1 = a.U[1] + (long long)ia1 * a.ldU[1];
+      const double* Ug2 = a.U[2] + (long long)ia2 * a.ldU[2];
+      const int ld0 = a.ldU[0], ld1 = a.ldU[1], ld2 = a.ldU[2];
+      for (int b0 = 0; b0 < tot; b0 += 16 * (int)blockDim.x) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int t = b0 + u * (int)blockDim.x + (int)threadIdx.x;
+          double x = 0.0;
+          if (t < tot) {
+            if (t < oL1) x = Li0[t];
+            else if (t < oL2) x = Li1[t - oL1];
+            else if (t < oU0) x = Li2[t - oL2];
+            else if (t < oU1) { const int e = t - oU0, q = e / q0; x = Ug0[(long long)q * ld0 + (e - q * q0)]; }
+            else if (t < oU2) { const int e = t - oU1, q = e / q1; x = Ug1[(long long)q * ld1 + (e - q * q1)]; }
+            else { const int e = t - oU2, q = e / q2; x = Ug2[(long long)q * ld2 + (e - q * q2)]; }
+          }
+          v[u] = x;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int t = b0 + u * (int)blockDim.x + (int)threadIdx.x;
+          if (t < tot) base[t] = v[u];
+        }
       }
       __syncthreads();
-      T* E = static_cast<T*>(a.E);
-      const long long nrow = i2b - i2a;
-      for (long long t = threadIdx.x; t < (long long)r1 * nrow * N3; t += blockDim.x) {
-        const long long i3 = t % N3, q = t / N3;
-        const long long il = q % nrow;
-        const int ai = (int)(q / nrow);
-        const double* u2 = U2l + il * r2;
-        const double* t3 = T3 + (long long)ai * r2 * N3 + i3;
-        double s = 0.0;
-        for (int b = 0; b < r2; ++b) s += u2[b] * t3[(long long)b * N3];
-        E[((long long)ai * N2 + i2a + il) * N3 + i3] = (T)s;
+      if (norm) {
+        // (U L^-T)[q][j] = sum_{k <= j} U[q][k] L^-1[j][k], four entries per thread at a time
+        for (int t0 = threadIdx.x; t0 < nsum; t0 += 4 * (int)blockDim.x) {
+          // entry u: row offset ur, L^-1 row offset lr, column jj, output index on
+          int ur[4], lr[4], jj[4], on[4], mm[4], qq[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int t = min(t0 + u * (int)blockDim.x, nsum - 1);
+            const int m = t < e0 ? 0 : (t < e0 + e1 ? 1 : 2);
+            const int e = t - (m == 0 ? 0 : (m == 1 ? e0 : e0 + e1));
+            const int rm = m == 0 ? q0 : (m == 1 ? q1 : q2);
+            const int q = e / rm, j = e - q * rm;
+            mm[u] = m;
+            qq[u] = q;
+            jj[u] = j;
+            ur[u] = (m == 0 ? oU0 : (m == 1 ? oU1 : oU2)) + q * rm;
+            lr[u] = (m == 0 ? oL0 : (m == 1 ? oL1 : oL2)) + j * rm;
+            on[u] = (m == 0 ? oN0 : (m == 1 ? oN1 : oN2)) + e;
+          }
+          double sv[4] = {0.0, 0.0, 0.0, 0.0};
+          const int kmax = max(max(jj[0], jj[1]), max(jj[2], jj[3]));
+          for (int k = 0; k <= kmax; ++k) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (k <= jj[u]) sv[u] += base[ur[u] + k] * base[lr[u] + k];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int t = t0 + u * (int)blockDim.x;
+            if (t < nsum) {
+              base[on[u]] = sv[u];
+              const int m = mm[u];
+              double* Uw = m == 0 ? a.Uw[0] : (m == 1 ? a.Uw[1] : a.Uw[2]);
+              const int ia = m == 0 ? ia0 : (m == 1 ? ia1 : ia2);
+              const int ld = m == 0 ? ld0 : (m == 1 ? ld1 : ld2);
+              Uw[(long long)(ia + qq[u]) * ld + jj[u]] = sv[u];
+            }
+          }
+        }
+        __syncthreads();
       }
+      // the normalised rows
+      const int oR0 = norm ? oN0 : oU0, oR1 = norm ? oN1 : oU1, oR2 = norm ? oN2 : oU2;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const int rm = m == 0 ? q0 : (m == 1 ? q1 : q2);
+        const int n_e = m == 0 ? e0 : (m == 1 ? e1 : e2);
+        const int ia = m == 0 ? ia0 : (m == 1 ? ia1 : ia2);
+        const double* Ur = base + (m == 0 ? oR0 : (m == 1 ? oR1 : oR2));
+        const double* w = a.w[m] + ia;
+        T* B = static_cast<T*>(a.B[m]) + (long long)ia * rm;
+        for (int t = threadIdx.x; t < n_e; t += blockDim.x) {
+          const int q = t / rm;
+          B[t] = (T)(w[q] * Ur[t]);
+        }
+        if (m == 0) {
+          T* U1c = static_cast<T*>(a.U1c) + (long long)ia * rm;
+          for (int t = threadIdx.x; t < n_e; t += blockDim.x) U1c[t] = (T)Ur[t];
+        }
+      }
+      if (nr1 > 0) {
+        T* E = static_cast<T*>(a.E);
+        const double* U2r = base + oR1;
+        const int nr = nr1;
+        for (long long t = threadIdx.x; t < (long long)r1 * nr * N3; t += blockDim.x) {
+          const long long i3 = t % N3, q = t / N3;
+          const int il = (int)(q % nr), ai = (int)(q / nr);
+          const double* u2 = U2r + il * r2;
+          const double* t3 = T3 + (long long)ai * r2 * N3 + i3;
+          double sv = 0.0;
+          for (int b = 0; b < r2; ++b) sv += u2[b] * t3[(long long)b * N3];
+          E[((long long)ai * N2 + ia1 + il) * N3 + i3] = (T)sv;
+        }
+      }
+      return;
     }
-    const long long tu = a.N[0] * r1;
-    T* U1c = static_cast<T*>(a.U1c);
-    const long long gstride = (long long)a.eblocks * blockDim.x;
-    for (long long t = (long long)eb * blockDim.x + threadIdx.x; t < tu; t += gstride) {
-      const long long i = t / r1;
-      U1c[t] = (T)a.U[0][i * a.ldU[0] + (t - i * r1)];
-    }
-    // weighted bases B_n = W_n U_n of the next stage 1
     for (int m = 0; m < 3; ++m) {
       const int rm = a.r[m], ld = a.ldU[m];
-      const long long tot = a.N[m] * rm;
-      const double* U = a.U[m];
+      const long long per = (a.N[m] + a.eblocks - 1) / a.eblocks;
+      const long long ia = (long long)eb * per, ib = min(a.N[m], ia + per);
+      if (ia >= ib) continue;
+      if (norm) {
+        __syncthreads();
+        g2l(Lil, a.Li[m], rm * rm);
+      }
       const double* w = a.w[m];
       T* B = static_cast<T*>(a.B[m]);
-      for (long long t = (long long)eb * blockDim.x + threadIdx.x; t < tot; t += gstride) {
-        const long long i = t / rm;
-        B[t] = (T)(w[i] * U[i * ld + (t - i * rm)]);
+      for (long long c0 = ia; c0 < ib; c0 += POST_CH) {
+        const int nr = (int)min((long long)POST_CH, ib - c0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < nr * rm; t += blockDim.x) {
+          const int q = t / rm;
+          Ul[t] = a.U[m][(c0 + q) * ld + (t - q * rm)];
+        }
+        __syncthreads();
+        const double* Uc = Ul;
+        if (norm) {
+          // (U L^-T)[q][j] = sum_{k <= j} U[q][k] L^-1[j][k], four entries per thread at a time
+          for (int t0 = threadIdx.x; t0 < nr * rm; t0 += 4 * (int)blockDim.x) {
+            int qq[4], jj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int t = min(t0 + u * (int)blockDim.x, nr * rm - 1);
+              qq[u] = t / rm;
+              jj[u] = t - qq[u] * rm;
+            }
+            double sv[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int k = 0; k < rm; ++k) {
+#pragma unroll
+              for (int u = 0; u < 4; ++u)
+                if (k <= jj[u]) sv[u] += Ul[qq[u] * rm + k] * Lil[jj[u] * rm + k];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int t = t0 + u * (int)blockDim.x;
+              if (t < nr * rm) {
+                Un[t] = sv[u];
+                a.Uw[m][(c0 + qq[u]) * ld + jj[u]] = sv[u];
+              }
+            }
+          }
+          __syncthreads();
+          Uc = Un;
+        }
+        for (int t = threadIdx.x; t < nr * rm; t += blockDim.x) {
+          const int q = t / rm;
+          B[(c0 + q) * rm + (t - q * rm)] = (T)(w[c0 + q] * Uc[t]);
+        }
+        if (m == 0) {
+          T* U1c = static_cast<T*>(a.U1c);
+          for (int t = threadIdx.x; t < nr * rm; t += blockDim.x) U1c[c0 * rm + t] = (T)Uc[t];
+        }
+        if (m == 1) {
+          T* E = static_cast<T*>(a.E);
+          for (long long t = threadIdx.x; t < (long long)r1 * nr * N3; t += blockDim.x) {
+            const long long i3 = t % N3, q = t / N3;
+            const int il = (int)(q % nr), ai = (int)(q / nr);
+            const double* u2 = Uc + il * r2;
+            const double* t3 = T3 + (long long)ai * r2 * N3 + i3;
+            double sv = 0.0;
+            for (int b = 0; b < r2; ++b) sv += u2[b] * t3[(long long)b * N3];
+            E[((long long)ai * N2 + c0 + il) * N3 + i3] = (T)sv;
+          }
+        }
       }
     }
     return;
@@ -698,35 +961,39 @@ __device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, 
   double* Gp = lam + rq;                     // FQR_GP partial blocks
   double* Cl = Gp + FQR_GP;
   __shared__ int ok_s;
-  const double* Csrc = a.C;
-  if (a.core_in_lds) {
-    g2l(Cl, Csrc, (int)csz);
+  // the core from LDS or from global memory (separate instances: fixed address spaces)
+  auto modes = [&](const double* Csrc) {
+    gram_from(Csrc, rn, R, inner, G, Gp);
+    const bool need_p = rn < a.N[n] && a.want_pinv;
+    if (threadIdx.x < 64) {
+      if (a.G[n])
+        for (int t = threadIdx.x; t < rn * rn; t += 64) a.G[n][t] = G[t];
+      if (a.want_sigma) {
+        // singular values of C_(n): eigenvalues of a copy of the Gram matrix
+        for (int t = threadIdx.x; t < rn * rn; t += 64) Gi[t] = G[t];
+        wave_fence();
+        wave_eigvals(Gi, rn, lam, ws);
+        for (int i = threadIdx.x; i < TDB_RCAP; i += 64)
+          ctrl->sigma[n][i] = i < rn ? sqrt(fmax(lam[i], 0.0)) : 0.0;
+      }
+      bool ok = true;
+      if (need_p) ok = wave_chol_inv(G, rn, Li, Gi);
+      if (threadIdx.x == 0) {
+        ok_s = ok ? 1 : 0;
+        if (!ok) atomicOr(&ctrl->numeric, 4);
+      }
+    }
     __syncthreads();
-    Csrc = Cl;
+    if (!need_p || !ok_s) return;
+    write_p<T>(Csrc, Gi, rn, R, inner, static_cast<T*>(a.P[n]));
+  };
+  if (a.core_in_lds) {
+    g2l(Cl, a.C, (int)csz);
+    __syncthreads();
+    modes(Cl);
+  } else {
+    modes(a.C);
   }
-  gram_from(Csrc, rn, R, inner, G, Gp);
-  const bool need_p = rn < a.N[n] && a.want_pinv;
-  if (threadIdx.x < 64) {
-    if (a.G[n])
-      for (int t = threadIdx.x; t < rn * rn; t += 64) a.G[n][t] = G[t];
-    if (a.want_sigma) {
-      // singular values of C_(n): eigenvalues of a copy of the Gram matrix
-      for (int t = threadIdx.x; t < rn * rn; t += 64) Gi[t] = G[t];
-      wave_fence();
-      wave_eigvals(Gi, rn, lam, ws);
-      for (int i = threadIdx.x; i < TDB_RCAP; i += 64)
-        ctrl->sigma[n][i] = i < rn ? sqrt(fmax(lam[i], 0.0)) : 0.0;
-    }
-    bool ok = true;
-    if (need_p) ok = wave_chol_inv(G, rn, Li, Gi);
-    if (threadIdx.x == 0) {
-      ok_s = ok ? 1 : 0;
-      if (!ok) atomicOr(&ctrl->numeric, 4);
-    }
-  }
-  __syncthreads();
-  if (!need_p || !ok_s) return;
-  write_p<T>(Csrc, Gi, rn, R, inner, static_cast<T*>(a.P[n]));
 }
 
 template <typename T>
@@ -900,7 +1167,7 @@ template hipError_t launch_fmprep<double>(const FFinishArgs&, size_t, CtrlState*
 hipError_t launch_fqr(const FQrArgs& a, size_t lds, CtrlState* c, hipStream_t s) {
   hipError_t e = hipFuncSetAttribute((const void*)k_fqr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fqr, dim3(3), dim3(256), lds, s, a, c);
+  hipLaunchKernelGGL(k_fqr, dim3(a.nb[0] + a.nb[1] + a.nb[2]), dim3(256), lds, s, a, c);
   return hipGetLastError();
 }
 
@@ -956,8 +1223,7 @@ __global__ void __launch_bounds__(256) kb_fmprep(const FFinishArgs* __restrict__
 
 __global__ void __launch_bounds__(256) kb_fqr(const FQrArgs* __restrict__ tab, CtrlState* const* ctab, BatchMap m) {
   const int s = m.sid[blockIdx.x];
-  const int b0 = m.start[s];
-  fqr_body(tab[s], ctab[s], blockIdx.x - b0, m.start[s + 1] - b0);
+  fqr_body(tab[s], ctab[s], blockIdx.x - m.start[s]);
 }
 
 template <typename T, int ROLE>

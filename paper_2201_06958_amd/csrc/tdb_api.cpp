@@ -78,7 +78,8 @@ struct tdb_ctx {
   int lds_max = 65536;
   void* fpart = nullptr;
   long long fpart_elems = 0;
-  double *Rq[TDB_P] = {}, *Cdot2 = nullptr;
+  double* Cdot2 = nullptr;
+  double *Lq[TDB_P] = {}, *qpart[TDB_P] = {};   // L_n^-1 of the QR; its slab partial Grams
   double *Mbuf[TDB_P] = {}, *T3buf = nullptr;   // M_n of a stage; C x_3 U_3 after the QR
   double* Gsave[TDB_P] = {};     // core Grams of the committed state (lazy singular values)
   bool sigma_every_step = false; // form the core singular values at every step
@@ -482,7 +483,8 @@ tdb_status setup_fused(tdb_ctx* h, const std::vector<std::vector<double>>& wh) {
   h->fpart_elems = tiles * slot;
   TRY(dalloc(h, &h->fpart, (size_t)h->fpart_elems * h->celt));
   for (int n = 0; n < 3; ++n) {
-    TRY(dallocT(h, &h->Rq[n], (size_t)TDB_RCAP * TDB_RCAP));
+    TRY(dallocT(h, &h->Lq[n], (size_t)TDB_RCAP * TDB_RCAP));
+    TRY(dallocT(h, &h->qpart[n], (size_t)((h->N[n] + QR_ROWS - 1) / QR_ROWS) * h->caps[n] * h->caps[n]));
     TRY(dalloc(h, &h->P2[n], (size_t)h->Rmax * h->caps[n] * h->celt));
   }
   TRY(dallocT(h, &h->Cdot2, h->core_cap));
@@ -500,8 +502,8 @@ tdb_status setup_fused(tdb_ctx* h, const std::vector<std::vector<double>>& wh) {
   h->ferr_gx = (int)std::max<long long>(1, std::min<long long>(64, (M + 255) / 256));
   h->ferr_gy = (int)((h->N[0] + FERR_T1 - 1) / FERR_T1);
   TRY(dallocT(h, &h->ferr_part, 2 * (size_t)h->ferr_gx * h->ferr_gy));
-  TRY(dalloc(h, reinterpret_cast<void**>(&h->counters), 4 * sizeof(unsigned)));
-  HIPCHK(hipMemset(h->counters, 0, 4 * sizeof(unsigned)));
+  TRY(dalloc(h, reinterpret_cast<void**>(&h->counters), 8 * sizeof(unsigned)));
+  HIPCHK(hipMemset(h->counters, 0, 8 * sizeof(unsigned)));
   return TDB_OK;
 }
 
@@ -881,6 +883,22 @@ int max_rank_of(const int* r, int p) {
   return m;
 }
 
+// LDS of the post-step expansion blocks for ranks rl with eb blocks: T3, and either
+// the three L_n^-1 with every row of the block before and after the normalisation
+// (*all = true, when that fits) or one L_n^-1 and a chunk of rows.
+size_t post_exp_lds(const tdb_ctx* h, const int* rl, int eb, bool* all) {
+  const size_t rq = (size_t)max_rank_of(rl, 3);
+  const size_t t3 = (size_t)rl[0] * rl[1] * (size_t)h->N[2];
+  size_t rows = 0, ll = 0;
+  for (int m = 0; m < 3; ++m) {
+    rows += (size_t)((h->N[m] + eb - 1) / eb) * rl[m];
+    ll += (size_t)rl[m] * rl[m];
+  }
+  const size_t staged = (t3 + ll + 2 * rows) * 8;
+  *all = staged <= (size_t)h->lds_max;
+  return *all ? staged : (t3 + rq * rq + 2 * (size_t)POST_CH * rq) * 8;
+}
+
 // LDS of the small per-mode kernels (finish, post) when sized for ranks rl.
 size_t small_lds(const tdb_ctx* h, const int* rl, bool* core_in_lds, bool m_inline = false) {
   const long long csz = prod_ll(rl, h->p);
@@ -918,8 +936,9 @@ tdb_status build_post_args(tdb_ctx* h, const int* rl, FPostArgs& pa, size_t& lds
   pa.rmax = max_rank_of(rl, 3);
   const long long etot = (long long)rl[0] * h->N[1] * h->N[2];
   pa.eblocks = (int)std::max<long long>(1, std::min<long long>(std::min<long long>(256, h->N[1]), (etot + 255) / 256));
-  const long long per = (h->N[1] + pa.eblocks - 1) / pa.eblocks;
-  const size_t elds = ((size_t)rl[0] * rl[1] * h->N[2] + (size_t)per * rl[1]) * 8;
+  bool sall = false;
+  const size_t elds = post_exp_lds(h, rl, pa.eblocks, &sall);
+  pa.stage_all = sall ? 1 : 0;
   if (elds > (size_t)h->lds_max) { h->err = "error-pass expansion does not fit in LDS"; return TDB_EUNSUPPORTED; }
   lds = std::max(lds, elds);
   pa.C = h->C0;
@@ -933,6 +952,7 @@ tdb_status build_post_args(tdb_ctx* h, const int* rl, FPostArgs& pa, size_t& lds
     pa.r[n] = h->r[n];
     pa.ldU[n] = h->ldU[n];
     pa.U[n] = h->U0[n];
+    pa.Uw[n] = h->U0[n];
     pa.w[n] = h->w[n];
     pa.B[n] = h->B[n];
     pa.P[n] = h->P[n];
@@ -1033,33 +1053,42 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
   FQrArgs& qa = A.qa;
   qa = FQrArgs{};
   qa.rmax = max_rank_of(rl, 3);
-  const size_t npq = (size_t)qa.rmax * (qa.rmax + 1) / 2;
-  const size_t qlds = (4 * (size_t)qa.rmax * qa.rmax + FQR_GP + TDB_NEIG) * 8;
-  size_t ustage = 0;
-  // a batch keeps several QR blocks per compute unit rather than staging U_n
-  const size_t qbudget = rl != h->r ? std::min<size_t>((size_t)h->lds_max, 48 * 1024) : (size_t)h->lds_max;
+  {
+    const size_t rq = (size_t)qa.rmax;
+    // slab rows and weighted rows; then the Gram, its factors and the fold's buffers
+    const size_t slab = 2 * (size_t)QR_ROWS * rq * 8;
+    const size_t fold = (3 * rq * rq + 3 * 64 + FQR_GP) * 8;
+    // the core folded in place through registers (FOLD_R entries per thread), else in
+    // two LDS buffers, else in global memory; a batch keeps several QR blocks per
+    // compute unit rather than staging a large core
+    const long long csz = prod_ll(rl, 3);
+    const size_t cneed = (size_t)csz * 8;
+    const size_t qbudget = rl != h->r ? std::min<size_t>((size_t)h->lds_max, 48 * 1024) : (size_t)h->lds_max;
+    if (csz <= (long long)FOLD_R * 256 && fold + cneed <= qbudget) qa.core_in_lds = 2;
+    else if (fold + 2 * cneed <= qbudget) qa.core_in_lds = 1;
+    else qa.core_in_lds = 0;
+    A.lds_qr = std::max(slab, fold + (qa.core_in_lds == 2 ? cneed : qa.core_in_lds == 1 ? 2 * cneed : 0));
+  }
+  A.blocks_qr = 0;
   for (int n = 0; n < 3; ++n) {
-    const size_t need = (size_t)h->N[n] * rl[n] * 8;
-    qa.u_in_lds[n] = qlds + need <= qbudget ? 1 : 0;
-    if (qa.u_in_lds[n]) ustage = std::max(ustage, need);
     qa.N[n] = h->N[n];
     qa.r[n] = h->r[n];
     qa.ldU[n] = h->ldU[n];
+    qa.nb[n] = (int)((h->N[n] + QR_ROWS - 1) / QR_ROWS);
+    A.blocks_qr += qa.nb[n];
     qa.U0[n] = h->U0[n];
     qa.w[n] = h->w[n];
-    qa.Rq[n] = h->Rq[n];
+    qa.Li[n] = h->Lq[n];
+    qa.gpart[n] = h->qpart[n];
   }
-  const size_t cneed = 2 * (size_t)prod_ll(rl, 3) * 8;
-  qa.core_in_lds = qlds + cneed <= (size_t)h->lds_max ? 1 : 0;
-  if (qa.core_in_lds) ustage = std::max(ustage, cneed);
   qa.C0 = h->C0;
   qa.Ctmp = h->Ctmp;
   qa.counter = h->counters;
   qa.T3 = h->T3buf;
-  A.lds_qr = qlds + ustage;
 
   TRY(build_post_args(h, rl, A.pa, A.lds_post));
   A.pa.T3 = h->T3buf;   // formed by the QR of this step
+  for (int n = 0; n < 3; ++n) A.pa.Li[n] = h->Lq[n];   // U_n normalised by the post-step
   A.pa.want_sigma = h->sigma_every_step ? 1 : 0;
   A.blocks_post = 3 + A.pa.eblocks;
 
@@ -1290,8 +1319,8 @@ struct tdb_batch_ctx {
   const void **d_v1 = nullptr, **d_v0 = nullptr, **h_v1 = nullptr, **h_v0 = nullptr;
   BatchSummary *d_sum = nullptr, *h_sum = nullptr;
   // block maps (fixed at creation: grids are sized at the caps)
-  BatchMap m_pass{}, m_red{}, m_fin[2]{}, m_qr{}, m_post{}, m_exp{}, m_err{};
-  int g_pass = 0, g_red = 0, g_fin[2] = {0, 0}, g_qr = 0, g_post = 0, g_exp = 0, g_err = 0;
+  BatchMap m_pass{}, m_red{}, m_fin[2]{}, m_qr{}, m_qa{}, m_post{}, m_exp{}, m_err{};
+  int g_pass = 0, g_red = 0, g_fin[2] = {0, 0}, g_qr = 0, g_qa = 0, g_post = 0, g_exp = 0, g_err = 0;
   size_t lds_pass = 0, lds_fin = 0, lds_qr = 0, lds_post = 0, lds_mprep = 0, lds_final = 0;
   size_t lds_rows = 0, lds_exp = 0;   // row blocks of the finish, expansion blocks of the post-step
   int mflavor = 0;                  // MPASS_* of the batched stage pass (one for all streams)
@@ -1448,7 +1477,7 @@ tdb_status batch_setup(tdb_batch_ctx* b) {
       for (int i = 0; i < n; ++i) b->st[i]->no_mfma = true;
     b->mflavor = mixed ? 0 : first;
   }
-  std::vector<int> c_pass(n), c_red(n), c_fin0(n), c_fin1(n), c_qr(n, 3), c_post(n), c_exp(n), c_err(n);
+  std::vector<int> c_pass(n), c_red(n), c_fin0(n), c_fin1(n), c_qr(n, 3), c_qa(n), c_post(n), c_exp(n), c_err(n);
   for (int i = 0; i < n; ++i) {
     tdb_ctx* h = b->st[i];
     StepArgs A;
@@ -1465,14 +1494,15 @@ tdb_status batch_setup(tdb_batch_ctx* b) {
     c_fin0[i] = A.blocks_fin[0];
     c_fin1[i] = A.blocks_fin[1];
     c_post[i] = A.blocks_post;
+    c_qa[i] = A.blocks_qr;
     c_exp[i] = A.pa.eblocks;
     c_err[i] = A.blocks_err;
     {
       long long msum = 0;
       for (int k = 0; k < 3; ++k) msum += (long long)h->caps[k] * h->caps[k];
       b->lds_rows = std::max(b->lds_rows, (size_t)msum * 8);
-      const long long per = (h->N[1] + A.pa.eblocks - 1) / A.pa.eblocks;
-      b->lds_exp = std::max(b->lds_exp, ((size_t)h->caps[0] * h->caps[1] * (size_t)h->N[2] + (size_t)per * h->caps[1]) * 8);
+      bool sall = false;
+      b->lds_exp = std::max(b->lds_exp, post_exp_lds(h, h->caps, A.pa.eblocks, &sall));
     }
     b->lds_pass = std::max(b->lds_pass, pc.lds);
     b->lds_fin = std::max(b->lds_fin, A.lds_fin);
@@ -1488,6 +1518,7 @@ tdb_status batch_setup(tdb_batch_ctx* b) {
   TRY(make_map(b, c_fin0, &b->m_fin[0], &b->g_fin[0]));
   TRY(make_map(b, c_fin1, &b->m_fin[1], &b->g_fin[1]));
   TRY(make_map(b, c_qr, &b->m_qr, &b->g_qr));
+  TRY(make_map(b, c_qa, &b->m_qa, &b->g_qa));
   TRY(make_map(b, c_post, &b->m_post, &b->g_post));
   TRY(make_map(b, c_exp, &b->m_exp, &b->g_exp));
   TRY(make_map(b, c_err, &b->m_err, &b->g_err));
@@ -1542,7 +1573,7 @@ tdb_status batch_step(tdb_batch_ctx* b, const void* const* V, hipStream_t s) {
     if (st == 0)
       BHIPCHK(launch_batch_ffinish<T>(b->d_ga[st], b->d_ctab, b->m_qr, b->g_qr, st + 1, b->lds_fin, ROLE_PINV, s));
   }
-  BHIPCHK(launch_batch_fqr(b->d_qa, b->d_ctab, b->m_qr, b->g_qr, b->lds_qr, s));
+  BHIPCHK(launch_batch_fqr(b->d_qa, b->d_ctab, b->m_qa, b->g_qa, b->lds_qr, s));
   BHIPCHK(launch_batch_fpost<T>(b->d_pa, b->d_ctab, b->m_qr, b->g_qr, b->lds_post, ROLE_MODES, s));
   BHIPCHK(launch_batch_fpost<T>(b->d_pa, b->d_ctab, b->m_exp, b->g_exp, b->lds_exp, ROLE_EXP, s));
   if (b->gate_mode != GATE_OFF) {
