@@ -883,6 +883,16 @@ int max_rank_of(const int* r, int p) {
   return m;
 }
 
+// Where the QR folds a core of csz entries, given the LDS of its factors (fold) and
+// the LDS available: 2 in place through registers, 1 in two LDS buffers, 0 in global
+// memory.
+int qr_core_mode(long long csz, size_t fold, size_t budget) {
+  const size_t cneed = (size_t)csz * 8;
+  if (csz <= (long long)FOLD_R * 256 && fold + cneed <= budget) return 2;
+  if (fold + 2 * cneed <= budget) return 1;
+  return 0;
+}
+
 // LDS of the post-step expansion blocks for ranks rl with eb blocks: T3, and either
 // the three L_n^-1 with every row of the block before and after the normalisation
 // (*all = true, when that fits) or one L_n^-1 and a chunk of rows.
@@ -1064,9 +1074,7 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
     const long long csz = prod_ll(rl, 3);
     const size_t cneed = (size_t)csz * 8;
     const size_t qbudget = rl != h->r ? std::min<size_t>((size_t)h->lds_max, 48 * 1024) : (size_t)h->lds_max;
-    if (csz <= (long long)FOLD_R * 256 && fold + cneed <= qbudget) qa.core_in_lds = 2;
-    else if (fold + 2 * cneed <= qbudget) qa.core_in_lds = 1;
-    else qa.core_in_lds = 0;
+    qa.core_in_lds = qr_core_mode(csz, fold, qbudget);
     A.lds_qr = std::max(slab, fold + (qa.core_in_lds == 2 ? cneed : qa.core_in_lds == 1 ? 2 * cneed : 0));
   }
   A.blocks_qr = 0;
@@ -1438,6 +1446,14 @@ tdb_status batch_upload_args(tdb_batch_ctx* b, hipStream_t s) {
     b->h_ga[0][i] = A.ga[0];
     b->h_ga[1][i] = A.ga[1];
     b->h_qa[i] = A.qa;
+    {
+      // the QR's last block lays out its factors for the current ranks, which leaves
+      // room in the batch's LDS (sized at the caps) to fold a core of the current size
+      FQrArgs& q = b->h_qa[i];
+      q.rmax = max_rank_of(h->r, 3);
+      const size_t rq = (size_t)q.rmax;
+      q.core_in_lds = qr_core_mode(prod_ll(h->r, 3), (3 * rq * rq + 3 * 64 + FQR_GP) * 8, b->lds_qr);
+    }
     b->h_pa[i] = A.pa;
     b->h_ea[i] = A.ea;
     if (b->gate_mode != GATE_OFF) {
