@@ -60,7 +60,9 @@ struct FQrArgs {
   int core_in_lds, rmax;     // core_in_lds: 2 folded in place, 1 in two LDS buffers, 0 in global memory
   long long N[3];
   int r[3], ldU[3];
-  int nb[3];                 // QR_ROWS-row slabs of U_n (blocks of mode n in both QR kernels)
+  int nb[3];                 // QR_ROWS-row slabs of U_n (one block each, unless whole)
+  int whole;                 // one block takes every slab (no partials through global memory)
+  int slab_off;              // whole: LDS offset (doubles) of the slab rows, past the fold's buffers
   double* U0[3];
   const double* w[3];
   double* Li[3];             // L_n^-1 (U_n <- U_n L_n^-T by the post-step)

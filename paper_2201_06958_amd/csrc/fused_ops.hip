@@ -558,6 +558,62 @@ __device__ __forceinline__ void fold_core(const FQrArgs& a, const double* L0, co
   }
 }
 
+// Partial Gram sum_q w_q u_q u_q^T of slab rb of mode n (rows staged at Ul, weighted rows
+// at Wl), upper triangle mirrored: stored to g, or added to g when acc (one block
+// summing the slabs in order).
+__device__ __forceinline__ void qr_slab_gram(const FQrArgs& a, int n, int rb, double* Ul, double* Wl, double* g,
+                                             bool acc) {
+  const int rn = a.r[n], ld = a.ldU[n];
+  const int Nn = (int)a.N[n];
+  const int rr = rn * rn;
+  // the slab's rows u_q and w_q u_q, up to 8 loads in flight per thread
+  const int q0 = rb * QR_ROWS, nr = min(QR_ROWS, Nn - q0);
+  const double* U = a.U0[n] + (long long)q0 * ld;
+  const double* w = a.w[n] + q0;
+  const int tot = nr * rn;
+  for (int base = 0; base < tot; base += 8 * (int)blockDim.x) {
+    double v[8], wv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = base + u * (int)blockDim.x + (int)threadIdx.x;
+      const int q = t / rn;
+      v[u] = t < tot ? U[q * ld + (t - q * rn)] : 0.0;
+      wv[u] = t < tot ? w[q] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = base + u * (int)blockDim.x + (int)threadIdx.x;
+      if (t < tot) {
+        Ul[t] = v[u];
+        Wl[t] = wv[u] * v[u];
+      }
+    }
+  }
+  __syncthreads();
+  // upper triangle (mirrored), four partial sums over the rows
+  for (int e = threadIdx.x; e < rr; e += blockDim.x) {
+    const int i = e / rn, j = e - (e / rn) * rn;
+    if (j < i) continue;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int q = 0;
+    for (; q + 4 <= nr; q += 4) {
+      s0 += Wl[q * rn + i] * Ul[q * rn + j];
+      s1 += Wl[(q + 1) * rn + i] * Ul[(q + 1) * rn + j];
+      s2 += Wl[(q + 2) * rn + i] * Ul[(q + 2) * rn + j];
+      s3 += Wl[(q + 3) * rn + i] * Ul[(q + 3) * rn + j];
+    }
+    for (; q < nr; ++q) s0 += Wl[q * rn + i] * Ul[q * rn + j];
+    const double sv = (s0 + s1) + (s2 + s3);
+    if (acc) {
+      g[i * rn + j] += sv;
+      if (j != i) g[j * rn + i] += sv;
+    } else {
+      g[i * rn + j] = sv;
+      g[j * rn + i] = sv;
+    }
+  }
+}
+
 __device__ __forceinline__ void fqr_body(const FQrArgs& a, CtrlState* ctrl, int bx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
@@ -569,70 +625,6 @@ __device__ __forceinline__ void fqr_body(const FQrArgs& a, CtrlState* ctrl, int 
     skip_s = __hip_atomic_load(&ctrl->numeric, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
   __syncthreads();
   const bool skip = skip_s != 0;
-  int rb;
-  const int n = qr_mode(a, bx, rb);
-  if (!skip) {
-    const int rn = a.r[n], ld = a.ldU[n];
-    const int Nn = (int)a.N[n];
-    const int rr = rn * rn;
-    // the slab's rows u_q and w_q u_q, up to 8 loads in flight per thread
-    const int q0 = rb * QR_ROWS, nr = min(QR_ROWS, Nn - q0);
-    double* Ul = lds;
-    double* Wl = lds + QR_ROWS * rn;
-    const double* U = a.U0[n] + (long long)q0 * ld;
-    const double* w = a.w[n] + q0;
-    const int tot = nr * rn;
-    for (int base = 0; base < tot; base += 8 * (int)blockDim.x) {
-      double v[8], wv[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int t = base + u * (int)blockDim.x + (int)threadIdx.x;
-        const int q = t / rn;
-        v[u] = t < tot ? U[q * ld + (t - q * rn)] : 0.0;
-        wv[u] = t < tot ? w[q] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int t = base + u * (int)blockDim.x + (int)threadIdx.x;
-        if (t < tot) {
-          Ul[t] = v[u];
-          Wl[t] = wv[u] * v[u];
-        }
-      }
-    }
-    __syncthreads();
-    // upper triangle (mirrored), four partial sums over the rows
-    double* g = a.gpart[n] + (long long)rb * rr;
-    for (int e = threadIdx.x; e < rr; e += blockDim.x) {
-      const int i = e / rn, j = e - (e / rn) * rn;
-      if (j < i) continue;
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      int q = 0;
-      for (; q + 4 <= nr; q += 4) {
-        s0 += Wl[q * rn + i] * Ul[q * rn + j];
-        s1 += Wl[(q + 1) * rn + i] * Ul[(q + 1) * rn + j];
-        s2 += Wl[(q + 2) * rn + i] * Ul[(q + 2) * rn + j];
-        s3 += Wl[(q + 3) * rn + i] * Ul[(q + 3) * rn + j];
-      }
-      for (; q < nr; ++q) s0 += Wl[q * rn + i] * Ul[q * rn + j];
-      const double sv = (s0 + s1) + (s2 + s3);
-      g[i * rn + j] = sv;
-      g[j * rn + i] = sv;
-    }
-  }
-  // the last block factors the three Grams and folds the core
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = __hip_atomic_fetch_add(a.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (prev == (unsigned)(a.nb[0] + a.nb[1] + a.nb[2]) - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!last) return;
-  // the fence orders the plain loads below after every block's stores of its partials
-  __threadfence();
-  if (threadIdx.x == 0) *a.counter = 0u;
-  if (skip) return;
   const int r0 = a.r[0], r1 = a.r[1], r2 = a.r[2];
   const int rq = a.rmax;
   double* L0 = lds;                         // rq*rq each
@@ -644,37 +636,73 @@ __device__ __forceinline__ void fqr_body(const FQrArgs& a, CtrlState* ctrl, int 
   int csz = r0 * r1 * r2;
   const int N3 = (int)a.N[2], ld3 = a.ldU[2];
   const bool u3l = a.T3 && N3 * ld3 <= FQR_GP;
-  {
-    // one load phase: the summed Grams (partials in slab order), the core (when it is
-    // folded in LDS) and U_3 (when it fits)
-    const int g0 = r0 * r0, g1 = g0 + r1 * r1, g2 = g1 + r2 * r2;
-    const int c1 = g2 + (a.core_in_lds ? csz : 0), tot = c1 + (u3l ? N3 * ld3 : 0);
-    for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-      if (t < g2) {
-        const int m = t < g0 ? 0 : (t < g1 ? 1 : 2);
-        const int e = t - (m == 0 ? 0 : (m == 1 ? g0 : g1));
-        const int rr = m == 0 ? r0 * r0 : (m == 1 ? r1 * r1 : r2 * r2);
-        const int nbm = m == 0 ? a.nb[0] : (m == 1 ? a.nb[1] : a.nb[2]);
-        const double* gp = (m == 0 ? a.gpart[0] : (m == 1 ? a.gpart[1] : a.gpart[2])) + e;
-        double sv = 0.0;
-        int b = 0;
-        for (; b + 8 <= nbm; b += 8) {
-          double v[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) v[u] = gp[(long long)(b + u) * rr];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) sv += v[u];
-        }
-        for (; b < nbm; ++b) sv += gp[(long long)b * rr];
-        (m == 0 ? L0 : (m == 1 ? L1 : L2))[e] = sv;
-      } else if (t < c1) {
-        X[t - g2] = a.C0[t - g2];
-      } else {
-        Gp[t - c1] = a.U0[2][t - c1];
+  if (a.whole) {
+    // every slab in this block, the Grams summed in LDS in slab order
+    if (ctrl->hold || skip) return;
+    double* Ul = lds + a.slab_off;
+    double* Wl = Ul + QR_ROWS * rq;
+    for (int t = threadIdx.x; t < 3 * rq * rq; t += blockDim.x) L0[t] = 0.0;
+    for (int n = 0; n < 3; ++n) {
+      double* Ln = n == 0 ? L0 : (n == 1 ? L1 : L2);
+      for (int rb = 0; rb < a.nb[n]; ++rb) {
+        __syncthreads();
+        qr_slab_gram(a, n, rb, Ul, Wl, Ln, true);
       }
     }
+    for (int t = threadIdx.x; t < (a.core_in_lds ? csz : 0) + (u3l ? N3 * ld3 : 0); t += blockDim.x) {
+      if (t < (a.core_in_lds ? csz : 0)) X[t] = a.C0[t];
+      else Gp[t - (a.core_in_lds ? csz : 0)] = a.U0[2][t - (a.core_in_lds ? csz : 0)];
+    }
+    __syncthreads();
+  } else {
+    int rb;
+    const int n = qr_mode(a, bx, rb);
+    if (!skip) qr_slab_gram(a, n, rb, lds, lds + QR_ROWS * a.r[n], a.gpart[n] + (long long)rb * a.r[n] * a.r[n], false);
+    // the last block factors the three Grams and folds the core
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned prev = __hip_atomic_fetch_add(a.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      last = (prev == (unsigned)(a.nb[0] + a.nb[1] + a.nb[2]) - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!last) return;
+    // the fence orders the plain loads below after every block's stores of its partials
+    __threadfence();
+    if (threadIdx.x == 0) *a.counter = 0u;
+    if (skip) return;
+    {
+      // one load phase: the summed Grams (partials in slab order), the core (when it is
+      // folded in LDS) and U_3 (when it fits)
+      const int g0 = r0 * r0, g1 = g0 + r1 * r1, g2 = g1 + r2 * r2;
+      const int c1 = g2 + (a.core_in_lds ? csz : 0), tot = c1 + (u3l ? N3 * ld3 : 0);
+      for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+        if (t < g2) {
+          const int m = t < g0 ? 0 : (t < g1 ? 1 : 2);
+          const int e = t - (m == 0 ? 0 : (m == 1 ? g0 : g1));
+          const int rr = m == 0 ? r0 * r0 : (m == 1 ? r1 * r1 : r2 * r2);
+          const int nbm = m == 0 ? a.nb[0] : (m == 1 ? a.nb[1] : a.nb[2]);
+          const double* gp = (m == 0 ? a.gpart[0] : (m == 1 ? a.gpart[1] : a.gpart[2])) + e;
+          double sv = 0.0;
+          int b = 0;
+          for (; b + 8 <= nbm; b += 8) {
+            double v[8];
+  #pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = gp[(long long)(b + u) * rr];
+  #pragma unroll
+            for (int u = 0; u < 8; ++u) sv += v[u];
+          }
+          for (; b < nbm; ++b) sv += gp[(long long)b * rr];
+          (m == 0 ? L0 : (m == 1 ? L1 : L2))[e] = sv;
+        } else if (t < c1) {
+          X[t - g2] = a.C0[t - g2];
+        } else {
+          Gp[t - c1] = a.U0[2][t - c1];
+        }
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const int wid = threadIdx.x >> 6;
   if (wid < 3) {
     // wave m: L_m L_m^T = G_m and L_m^-1 (published for the post-step)

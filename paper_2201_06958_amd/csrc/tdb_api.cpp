@@ -945,7 +945,10 @@ tdb_status build_post_args(tdb_ctx* h, const int* rl, FPostArgs& pa, size_t& lds
   pa.want_pinv = 1;
   pa.rmax = max_rank_of(rl, 3);
   const long long etot = (long long)rl[0] * h->N[1] * h->N[2];
-  pa.eblocks = (int)std::max<long long>(1, std::min<long long>(std::min<long long>(256, h->N[1]), (etot + 255) / 256));
+  // a batch gives each expansion block four times the work (fewer blocks, each of which
+  // stages T3 and the factors once)
+  const long long eper = rl != h->r ? 1024 : 256;
+  pa.eblocks = (int)std::max<long long>(1, std::min<long long>(std::min<long long>(256, h->N[1]), (etot + eper - 1) / eper));
   bool sall = false;
   const size_t elds = post_exp_lds(h, rl, pa.eblocks, &sall);
   pa.stage_all = sall ? 1 : 0;
@@ -1069,26 +1072,38 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
     const size_t slab = 2 * (size_t)QR_ROWS * rq * 8;
     const size_t fold = (3 * rq * rq + 3 * 64 + FQR_GP) * 8;
     // the core folded in place through registers (FOLD_R entries per thread), else in
-    // two LDS buffers, else in global memory; a batch keeps several QR blocks per
-    // compute unit rather than staging a large core
+    // two LDS buffers, else in global memory
     const long long csz = prod_ll(rl, 3);
     const size_t cneed = (size_t)csz * 8;
-    const size_t qbudget = rl != h->r ? std::min<size_t>((size_t)h->lds_max, 48 * 1024) : (size_t)h->lds_max;
-    qa.core_in_lds = qr_core_mode(csz, fold, qbudget);
-    A.lds_qr = std::max(slab, fold + (qa.core_in_lds == 2 ? cneed : qa.core_in_lds == 1 ? 2 * cneed : 0));
+    if (rl == h->r) {
+      // one block per slab; the last one to finish factors and folds
+      qa.core_in_lds = qr_core_mode(csz, fold, (size_t)h->lds_max);
+      A.lds_qr = std::max(slab, fold + (qa.core_in_lds == 2 ? cneed : qa.core_in_lds == 1 ? 2 * cneed : 0));
+    } else {
+      // a batch: one block per stream takes every slab (its streams are small, and many
+      // blocks each publishing partials cost a device-wide fence apiece); room for the
+      // factors, an in-place fold of up to FOLD_R entries per thread and the slab rows.
+      // The factors are laid out for the current ranks when the arguments are uploaded.
+      qa.whole = 1;
+      qa.core_in_lds = qr_core_mode(csz, fold, (size_t)h->lds_max - slab);
+      qa.slab_off = (int)(fold / 8) + (qa.core_in_lds == 2 ? (int)csz : qa.core_in_lds == 1 ? 2 * (int)csz : 0);
+      A.lds_qr = fold + slab + std::min(cneed, (size_t)FOLD_R * 256 * 8);
+      if (qa.core_in_lds == 1) A.lds_qr = fold + slab + 2 * cneed;
+    }
   }
   A.blocks_qr = 0;
   for (int n = 0; n < 3; ++n) {
+    qa.nb[n] = (int)((h->N[n] + QR_ROWS - 1) / QR_ROWS);
     qa.N[n] = h->N[n];
     qa.r[n] = h->r[n];
     qa.ldU[n] = h->ldU[n];
-    qa.nb[n] = (int)((h->N[n] + QR_ROWS - 1) / QR_ROWS);
-    A.blocks_qr += qa.nb[n];
+    A.blocks_qr += qa.whole ? 0 : qa.nb[n];
     qa.U0[n] = h->U0[n];
     qa.w[n] = h->w[n];
     qa.Li[n] = h->Lq[n];
     qa.gpart[n] = h->qpart[n];
   }
+  if (qa.whole) A.blocks_qr = 1;
   qa.C0 = h->C0;
   qa.Ctmp = h->Ctmp;
   qa.counter = h->counters;
@@ -1452,7 +1467,10 @@ tdb_status batch_upload_args(tdb_batch_ctx* b, hipStream_t s) {
       FQrArgs& q = b->h_qa[i];
       q.rmax = max_rank_of(h->r, 3);
       const size_t rq = (size_t)q.rmax;
-      q.core_in_lds = qr_core_mode(prod_ll(h->r, 3), (3 * rq * rq + 3 * 64 + FQR_GP) * 8, b->lds_qr);
+      const size_t fold = (3 * rq * rq + 3 * 64 + FQR_GP) * 8, slab = 2 * (size_t)QR_ROWS * rq * 8;
+      const long long csz = prod_ll(h->r, 3);
+      q.core_in_lds = qr_core_mode(csz, fold, b->lds_qr - slab);
+      q.slab_off = (int)(fold / 8) + (q.core_in_lds == 2 ? (int)csz : q.core_in_lds == 1 ? 2 * (int)csz : 0);
     }
     b->h_pa[i] = A.pa;
     b->h_ea[i] = A.ea;
