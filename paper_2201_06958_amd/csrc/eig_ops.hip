@@ -6,8 +6,10 @@
 // orthogonalised within one wave), back-transformation by the stored reflectors and
 // a sign convention (largest-magnitude entry positive, lowest index on a tie).
 //
-// Reflector k (k = 0..n-3) acts on indices k+1..n-1; it is stored in row k of G
-// (entries k+1..n-1), its coefficient in beta[k]. Launch k applies the rank-2 update
+// Reflector k (k = 0..n-3) acts on indices k+1..n-1; it ends up in row k of G (entries
+// k+1..n-1), its coefficient in beta[k]. While the distributed steps run it lives in
+// one of two vectors vr (entries k+1..n-1), and the next launch copies it into G, so
+// that row k of G, read in place of column k, is not overwritten while it is read. Launch k applies the rank-2 update
 // of reflector k-1 to this workgroup's rows of the trailing block (columns k+1..n-1),
 // forms column k and the diagonal entry k of the updated matrix on the fly from the
 // not yet updated values (nobody writes them in this launch), computes reflector k
@@ -24,9 +26,9 @@ namespace tdb {
 #define EC 8    // rows per chunk of the per-lane tridiagonal sweeps
 #define TRI_TAIL 128   // largest trailing block reduced by a single workgroup
 
-// Per-mode workspace (after the K eigenvector columns): d, e, beta, p0, p1.
+// Per-mode workspace (after the K eigenvector columns): d, e, beta, p0, p1, vr0, vr1.
 struct EigWs {
-  double *X, *d, *e, *beta, *p[2];
+  double *X, *d, *e, *beta, *p[2], *vr[2];
 };
 __device__ __forceinline__ EigWs eig_ws(const EigArgs& a) {
   EigWs w;
@@ -37,27 +39,28 @@ __device__ __forceinline__ EigWs eig_ws(const EigArgs& a) {
   w.beta = w.e + n;
   w.p[0] = w.beta + n;
   w.p[1] = w.p[0] + n;
+  w.vr[0] = w.p[1] + n;
+  w.vr[1] = w.vr[0] + n;
   return w;
 }
 
-__global__ void __launch_bounds__(256) k_tri_step(EigBatch batch, int k) {
-  const EigArgs a = batch.m[blockIdx.y];
+// Step k of the distributed reduction for one mode, as workgroup bx of nblk.
+__device__ __forceinline__ void tri_step_body(const EigArgs& a, int k, int bx, int nblk, double* vp, double* wp,
+                                              double* v, double* red) {
   const int n = a.Nn;
   if (k + 2 >= n || k >= a.k0) return;
   const EigWs w = eig_ws(a);
   double* G = a.G;
-  __shared__ double vp[NE], wp[NE], v[NE];
-  __shared__ double red[16];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int nblk = gridDim.x;
   // the pending update of reflector k-1 (acting on indices k..n-1)
   const double bp = k > 0 ? w.beta[k - 1] : 0.0;
   const int mp = n - k;
   if (bp != 0.0) {
     const double* pp = ((k - 1) & 1) ? w.p[1] : w.p[0];
+    const double* vq = ((k - 1) & 1) ? w.vr[1] : w.vr[0];
     double pvv = 0.0;
     for (int i = tid; i < mp; i += blockDim.x) {
-      const double vi = G[(long long)(k - 1) * n + k + i];
+      const double vi = vq[k + i];
       vp[i] = vi;
       pvv += pp[k + i] * vi;
     }
@@ -66,12 +69,14 @@ __global__ void __launch_bounds__(256) k_tri_step(EigBatch batch, int k) {
     for (int i = tid; i < mp; i += blockDim.x) wp[i] = pp[k + i] - Kc * vp[i];
     __syncthreads();
   }
-  // column k below the diagonal and the diagonal entry of the updated matrix
+  // column k below the diagonal and the diagonal entry of the updated matrix; the
+  // trailing block stays exactly symmetric (each update forms the same two products and
+  // only the order of their sum differs), so column k is read as the contiguous row k
   const int m = n - k - 1;
   double ss = 0.0;
   for (int i = tid; i < m; i += blockDim.x) {
-    double x = G[(long long)(k + 1 + i) * n + k];
-    if (bp != 0.0) x -= vp[1 + i] * wp[0] + wp[1 + i] * vp[0];
+    double x = G[(long long)k * n + k + 1 + i];
+    if (bp != 0.0) x -= vp[0] * wp[1 + i] + wp[0] * vp[1 + i];
     v[i] = x;
     ss += x * x;
   }
@@ -93,7 +98,7 @@ __global__ void __launch_bounds__(256) k_tri_step(EigBatch batch, int k) {
   __syncthreads();
   // rows of this workgroup: k+1+i for i = blockIdx.x, blockIdx.x + nblk, ...; one wave per row
   double* pk = (k & 1) ? w.p[1] : w.p[0];
-  for (int i = blockIdx.x + nblk * wid; i < m; i += nblk * 4) {
+  for (int i = bx + nblk * wid; i < m; i += nblk * 4) {
     double* row = G + (long long)(k + 1 + i) * n + (k + 1);
     double s = 0.0;
     if (bp != 0.0) {
@@ -109,14 +114,27 @@ __global__ void __launch_bounds__(256) k_tri_step(EigBatch batch, int k) {
     s = warp_sum(s);
     if (lane == 0) pk[k + 1 + i] = bk * s;
   }
-  if (blockIdx.x == 0) {
-    for (int i = tid; i < m; i += blockDim.x) G[(long long)k * n + k + 1 + i] = v[i];
+  if (bx == 0) {
+    // this reflector into its vector; the previous one (read by every workgroup above,
+    // from the other vector) into row k-1 of G, which nobody reads in this launch
+    double* vk = (k & 1) ? w.vr[1] : w.vr[0];
+    for (int i = tid; i < m; i += blockDim.x) vk[k + 1 + i] = v[i];
+    if (k > 0) {
+      const double* vq = ((k - 1) & 1) ? w.vr[1] : w.vr[0];
+      for (int i = tid; i < mp; i += blockDim.x) G[(long long)(k - 1) * n + k + i] = vq[k + i];
+    }
     if (tid == 0) {
       w.d[k] = dk;
       w.e[k] = ek;
       w.beta[k] = bk;
     }
   }
+}
+
+__global__ void __launch_bounds__(256) k_tri_step(EigBatch batch, int k) {
+  __shared__ double vp[NE], wp[NE], v[NE];
+  __shared__ double red[16];
+  tri_step_body(batch.m[blockIdx.y], k, blockIdx.x, gridDim.x, vp, wp, v, red);
 }
 
 // Reflectors k0 .. n-3 and the last 2 x 2 block in one workgroup per mode, with the
@@ -149,11 +167,17 @@ __global__ void __launch_bounds__(256) k_tri_tail(EigBatch batch) {
   __syncthreads();
   // the pending update of reflector k0-1 (acting on indices k0..n-1)
   const double bp = k0 > 0 ? w.beta[k0 - 1] : 0.0;
+  if (k0 > 0) {
+    // the last distributed reflector into row k0-1 of G
+    const double* vq = ((k0 - 1) & 1) ? w.vr[1] : w.vr[0];
+    for (int i = tid; i < T; i += blockDim.x) G[(long long)(k0 - 1) * n + k0 + i] = vq[k0 + i];
+  }
   if (bp != 0.0) {
     const double* pp = ((k0 - 1) & 1) ? w.p[1] : w.p[0];
+    const double* vq = ((k0 - 1) & 1) ? w.vr[1] : w.vr[0];
     double pvv = 0.0;
     for (int i = tid; i < T; i += blockDim.x) {
-      const double vi = G[(long long)(k0 - 1) * n + k0 + i];
+      const double vi = vq[k0 + i];
       v[i] = vi;
       pvv += pp[k0 + i] * vi;
     }
@@ -604,7 +628,10 @@ __global__ void __launch_bounds__(1024) k_eig_orth(EigBatch batch, const double*
 }
 
 // Back-transformation x <- H_0 H_1 ... H_{n-3} x and the sign convention; grid (mode,
-// vector), one wave per vector.
+// vector), one wave per vector. Lane l holds entries l, l+64, ... of the vector in
+// registers; each reflector's entries are loaded one step ahead of its use.
+#define BK_R (NE / 64)
+#define BK_G 4   // reflectors per prefetch group
 __global__ void __launch_bounds__(64) k_eig_back(EigBatch batch) {
   const EigArgs a = batch.m[blockIdx.x];
   const int n = a.Nn, K = a.k;
@@ -612,37 +639,76 @@ __global__ void __launch_bounds__(64) k_eig_back(EigBatch batch) {
   if (j >= K) return;
   const EigWs w = eig_ws(a);
   const int lane = threadIdx.x;
-  double* xj = w.X + (long long)j * n;
+  const double* xj = w.X + (long long)j * n;
   const double* G = a.G;
-  for (int k = n - 3; k >= 0; --k) {
-    const double bk = w.beta[k];
-    if (bk == 0.0) continue;
-    const int m = n - k - 1;
-    const double* vk = G + (long long)k * n + k + 1;
-    double s = 0.0;
-    for (int i = lane; i < m; i += 64) s += vk[i] * xj[k + 1 + i];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    s *= bk;
-    for (int i = lane; i < m; i += 64) xj[k + 1 + i] -= s * vk[i];
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  double x[BK_R];
+#pragma unroll
+  for (int r = 0; r < BK_R; ++r) {
+    const int c = lane + 64 * r;
+    x[r] = c < n ? xj[c] : 0.0;
   }
-  double best = -1.0;
+  // reflectors in groups of BK_G (k, k-1, ...), the next group's loads issued before
+  // this group's arithmetic
+  double va[BK_G][BK_R], vb[BK_G][BK_R], ba[BK_G], bb[BK_G];
+  auto load = [&](int k0, double (&vv)[BK_G][BK_R], double (&bv)[BK_G]) {
+#pragma unroll
+    for (int g = 0; g < BK_G; ++g) {
+      const int k = k0 - g;
+      bv[g] = k >= 0 ? w.beta[k] : 0.0;
+#pragma unroll
+      for (int r = 0; r < BK_R; ++r) {
+        const int c = lane + 64 * r;
+        vv[g][r] = (k >= 0 && c > k && c < n) ? G[(long long)k * n + c] : 0.0;
+      }
+    }
+  };
+  load(n - 3, va, ba);
+  for (int k0 = n - 3; k0 >= 0; k0 -= BK_G) {
+    load(k0 - BK_G, vb, bb);
+#pragma unroll
+    for (int g = 0; g < BK_G; ++g) {
+      if (ba[g] != 0.0) {
+        double sv = 0.0;
+#pragma unroll
+        for (int r = 0; r < BK_R; ++r) sv += va[g][r] * x[r];
+        for (int off = 32; off > 0; off >>= 1) sv += __shfl_xor(sv, off, 64);
+        sv *= ba[g];
+#pragma unroll
+        for (int r = 0; r < BK_R; ++r) x[r] -= sv * va[g][r];
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < BK_G; ++g) {
+      ba[g] = bb[g];
+#pragma unroll
+      for (int r = 0; r < BK_R; ++r) va[g][r] = vb[g][r];
+    }
+  }
+  // sign: the largest-magnitude entry positive (the lowest index on a tie)
+  double best = -1.0, bval = 0.0;
   int bi = 0;
-  for (int i = lane; i < n; i += 64) {
-    const double av = fabs(xj[i]);
-    if (av > best) { best = av; bi = i; }
+#pragma unroll
+  for (int r = 0; r < BK_R; ++r) {
+    const int c = lane + 64 * r;
+    const double av = fabs(x[r]);
+    if (c < n && av > best) { best = av; bi = c; bval = x[r]; }
   }
   for (int off = 32; off > 0; off >>= 1) {
     const double ob = __shfl_xor(best, off, 64);
     const int oi = __shfl_xor(bi, off, 64);
-    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    const double ov = __shfl_xor(bval, off, 64);
+    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; bval = ov; }
   }
-  const double sg = xj[bi] < 0.0 ? -1.0 : 1.0;
-  for (int i = lane; i < n; i += 64) {
-    const double q = sg * xj[i];
-    const double sw = sqrt(a.wn[i]);
-    a.Umax[(long long)i * a.ldu + j] = q / sw;
-    a.Bmax[(long long)i * K + j] = q * sw;
+  const double sg = bval < 0.0 ? -1.0 : 1.0;
+#pragma unroll
+  for (int r = 0; r < BK_R; ++r) {
+    const int i = lane + 64 * r;
+    if (i < n) {
+      const double q = sg * x[r];
+      const double sw = sqrt(a.wn[i]);
+      a.Umax[(long long)i * a.ldu + j] = q / sw;
+      a.Bmax[(long long)i * K + j] = q * sw;
+    }
   }
 }
 

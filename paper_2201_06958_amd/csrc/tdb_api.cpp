@@ -381,7 +381,7 @@ tdb_status setup(tdb_ctx* h, const tdb_config* cfg) {
   size_t gpart = 0;
   for (int n = 0; n < h->p; ++n) {
     TRY(dallocT(h, &h->G[n], (size_t)h->N[n] * h->N[n]));
-    TRY(dallocT(h, &h->eigw[n], (size_t)h->N[n] * (h->caps[n] + 6)));
+    TRY(dallocT(h, &h->eigw[n], (size_t)h->N[n] * (h->caps[n] + 7)));
     TRY(dallocT(h, &h->sig[n], (size_t)h->caps[n] + 1));
     TRY(dallocT(h, &h->Umax[n], (size_t)h->N[n] * h->ldU[n]));
     TRY(dallocT(h, &h->Bmax[n], (size_t)h->N[n] * h->caps[n]));

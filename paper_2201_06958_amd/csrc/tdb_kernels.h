@@ -102,7 +102,7 @@ struct EigArgs {
   int Nn, k, ldu;
   int k0;                // first reflector of the single-workgroup tail (set by the launcher)
   double* G;
-  double* work;          // >= Nn * (k + 6) doubles
+  double* work;          // >= Nn * (k + 7) doubles
   double* sig;           // k + 1
   double* Umax;
   double* Bmax;
