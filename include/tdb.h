@@ -89,7 +89,15 @@ typedef struct {
   double gamma_th;                     /* > 0: percentage budget of eq. (percentage),
                                           (1 - gamma_th/100) ||V||^2; <= 0: (eps_th/2)^2 */
   int32_t slope_window;                /* error-slope window for removal; 0 => 10      */
+  int32_t integrator;                  /* TDB_INT_HEUN (0, default): the second-order
+                                          Runge-Kutta (Heun) step; TDB_INT_EULER: the
+                                          explicit first-order Euler step (Sec. 2.4,
+                                          the time-scheme comparison of Sec. 3.1);
+                                          single streams only                          */
 } tdb_config;
+
+#define TDB_INT_HEUN 0
+#define TDB_INT_EULER 1
 
 /* Per-step record (Sec. 2.5, 2.6). */
 typedef struct {

@@ -148,6 +148,20 @@ hipError_t launch_ferr(const FErrArgs& a, CtrlState* c, hipStream_t s, hipEvent_
 // LDS of the final error kernel (singular values of three r x r Grams when needed).
 inline size_t ferr_final_lds(int rmax) { return (size_t)3 * ((size_t)rmax * rmax + 5 * (size_t)rmax) * 8 + 64; }
 
+// Explicit Euler: commit the stage-1 state (C* and U*_n) as the new state, unless the
+// step is held or a factorisation failed.
+struct CommitArgs {
+  int p;
+  long long csz;
+  double* C0;
+  const double* Cs;
+  long long N[4];
+  int r[4], ldU[4];
+  double* U0[4];
+  const double* Us[4];
+};
+hipError_t launch_euler_commit(const CommitArgs& a, CtrlState* c, hipStream_t s);
+
 // ---------------------------------------------------------------- matrix-core pass
 // Stage-pass flavours on the matrix cores (tile 16 x 64 x N3, N3 <= 8, r1, r2 <= 32).
 enum { MPASS_NONE = 0, MPASS_F32 = 1, MPASS_BF16S = 2 };

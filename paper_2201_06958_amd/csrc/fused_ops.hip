@@ -1192,6 +1192,30 @@ hipError_t launch_fmprep(const FFinishArgs& a, size_t lds, CtrlState* c, hipStre
 template hipError_t launch_fmprep<float>(const FFinishArgs&, size_t, CtrlState*, hipStream_t);
 template hipError_t launch_fmprep<double>(const FFinishArgs&, size_t, CtrlState*, hipStream_t);
 
+__global__ void __launch_bounds__(256) k_euler_commit(CommitArgs a, CtrlState* ctrl) {
+  if (ctrl->hold || ctrl->numeric) return;
+  const long long gs = (long long)gridDim.x * blockDim.x;
+  const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (long long t = t0; t < a.csz; t += gs) a.C0[t] = a.Cs[t];
+  for (int n = 0; n < a.p; ++n) {
+    const int rn = a.r[n], ld = a.ldU[n];
+    const long long tot = a.N[n] * rn;
+    for (long long t = t0; t < tot; t += gs) {
+      const long long i = t / rn;
+      const long long o = i * ld + (t - i * rn);
+      a.U0[n][o] = a.Us[n][o];
+    }
+  }
+}
+
+hipError_t launch_euler_commit(const CommitArgs& a, CtrlState* c, hipStream_t s) {
+  long long m = a.csz;
+  for (int n = 0; n < a.p; ++n) m = std::max(m, a.N[n] * a.r[n]);
+  const int blocks = (int)std::max<long long>(1, std::min<long long>(1024, (m + 255) / 256));
+  hipLaunchKernelGGL(k_euler_commit, dim3(blocks), dim3(256), 0, s, a, c);
+  return hipGetLastError();
+}
+
 hipError_t launch_fqr(const FQrArgs& a, size_t lds, CtrlState* c, hipStream_t s) {
   hipError_t e = hipFuncSetAttribute((const void*)k_fqr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;

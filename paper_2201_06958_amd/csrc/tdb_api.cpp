@@ -191,6 +191,7 @@ tdb_status validate(const tdb_config* c, std::string& msg) {
     msg = "slope_window must be 0 (default) or in [2, 64]";
     return TDB_EINVAL;
   }
+  if (c->integrator != TDB_INT_HEUN && c->integrator != TDB_INT_EULER) { msg = "bad integrator"; return TDB_EINVAL; }
   return TDB_OK;
 }
 
@@ -803,6 +804,8 @@ tdb_status keep_previous(tdb_ctx* h, const TD* V, hipStream_t s) {
   return TDB_OK;
 }
 
+tdb_status euler_commit(tdb_ctx* h, hipStream_t s);
+
 template <typename TD, typename T>
 tdb_status ingest_impl(tdb_ctx* h, const TD* V1, hipStream_t s) {
   const TD* V0 = static_cast<const TD*>(h->Vprev);
@@ -833,14 +836,18 @@ tdb_status ingest_impl(tdb_ctx* h, const TD* V1, hipStream_t s) {
   }
   ra.stage = 1;
   HIPCHK(launch_rhs_stage(ra, h->ctrl, s));
-  // stage 2 at S*
-  TRY(stage_prep<T>(h, h->Cs, h->Us, s));
-  {
-    PassTimer pt(h, TDB_PASS_PROJECT, s);
-    TRY((project_plain<TD, T>(h, V1, V0, s)));
+  if (h->cfg.integrator == TDB_INT_EULER) {
+    TRY(euler_commit(h, s));
+  } else {
+    // stage 2 at S*
+    TRY(stage_prep<T>(h, h->Cs, h->Us, s));
+    {
+      PassTimer pt(h, TDB_PASS_PROJECT, s);
+      TRY((project_plain<TD, T>(h, V1, V0, s)));
+    }
+    ra.stage = 2;
+    HIPCHK(launch_rhs_stage(ra, h->ctrl, s));
   }
-  ra.stage = 2;
-  HIPCHK(launch_rhs_stage(ra, h->ctrl, s));
   QrArgs qa{};
   qa.p = p;
   qa.C0 = h->C0;
@@ -1136,6 +1143,24 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
   return TDB_OK;
 }
 
+// Explicit Euler: the stage-1 state becomes the state.
+tdb_status euler_commit(tdb_ctx* h, hipStream_t s) {
+  CommitArgs ca{};
+  ca.p = h->p;
+  ca.csz = prod_ll(h->r, h->p);
+  ca.C0 = h->C0;
+  ca.Cs = h->Cs;
+  for (int n = 0; n < h->p; ++n) {
+    ca.N[n] = h->N[n];
+    ca.r[n] = h->r[n];
+    ca.ldU[n] = h->ldU[n];
+    ca.U0[n] = h->U0[n];
+    ca.Us[n] = h->Us[n];
+  }
+  HIPCHK(launch_euler_commit(ca, h->ctrl, s));
+  return TDB_OK;
+}
+
 // Post-step preparation of the fused path at the committed state: core singular
 // values, B_n and P_n of the next stage 1, and the error-pass expansion E.
 template <typename T>
@@ -1173,7 +1198,8 @@ tdb_status finish_step(tdb_ctx* h, const TD* V1, hipStream_t s) {
 template <typename TD, typename T>
 tdb_status enqueue_fused_step(tdb_ctx* h, StepArgs& A, hipStream_t s) {
   if (!h->post_valid) TRY(fused_post<T>(h, s));
-  for (int stage = 1; stage <= 2; ++stage) {
+  const int stages = h->cfg.integrator == TDB_INT_EULER ? 1 : 2;
+  for (int stage = 1; stage <= stages; ++stage) {
     {
       PassTimer pt(h, TDB_PASS_PROJECT, s, true);
       if (A.pl.mfma)
@@ -1186,6 +1212,7 @@ tdb_status enqueue_fused_step(tdb_ctx* h, StepArgs& A, hipStream_t s) {
     if (!A.ga[stage - 1].m_inline) HIPCHK(launch_fmprep<T>(A.ga[stage - 1], A.lds_mprep, h->ctrl, s));
     HIPCHK(launch_ffinish<T>(A.ga[stage - 1], A.lds_fin, h->ctrl, s));
   }
+  if (stages == 1) TRY(euler_commit(h, s));
   HIPCHK(launch_fqr(A.qa, A.lds_qr, h->ctrl, s));
   HIPCHK(launch_fpost<T>(A.pa, A.lds_post, h->ctrl, s));
   h->post_valid = true;
@@ -1929,6 +1956,10 @@ tdb_status tdb_batch_create(int32_t n, const tdb_config* cfgs, const void* const
       const tdb_config& c = cfgs[i];
       if (c.order != 3 || c.path == TDB_PATH_PLAIN) {
         b->err = "stream " + std::to_string(i) + ": batches take third-order streams on the fused path";
+        return TDB_EUNSUPPORTED;
+      }
+      if (c.integrator != TDB_INT_HEUN) {
+        b->err = "stream " + std::to_string(i) + ": batches step with the Heun integrator only";
         return TDB_EUNSUPPORTED;
       }
       if ((c.data_dtype == TDB_F32) != b->data32 || c.precision != cfgs[0].precision) {

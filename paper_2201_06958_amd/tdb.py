@@ -23,6 +23,7 @@ OK, EINVAL, ENOMEM, EHIP, ESTATE, ENUMERIC, EUNSUPPORTED = range(7)
 F64, F32 = 0, 1
 PREC_F64, PREC_F32, PREC_BF16SPLIT = 0, 1, 2
 PATH_AUTO, PATH_PLAIN, PATH_FUSED = 0, 1, 2
+INT_HEUN, INT_EULER = 0, 1
 COPY, BORROW = 0, 1
 EVENTS = {0: "", 1: "reinit", 2: "add", 3: "remove", 4: "numeric"}
 
@@ -52,6 +53,7 @@ class TdbConfig(ctypes.Structure):
         ("eps_th", ctypes.c_double),
         ("gamma_th", ctypes.c_double),
         ("slope_window", ctypes.c_int32),
+        ("integrator", ctypes.c_int32),
     ]
 
 
@@ -172,7 +174,7 @@ class Compressor:
                  weights: Optional[Sequence[np.ndarray]] = None, data_dtype: str = "f32",
                  precision: str = "f32", path: str = "auto", adaptive: bool = True,
                  snapshot_mode: str = "copy", eps_th: float = 1e-4, gamma_th: float = 0.0,
-                 slope_window: int = 0):
+                 slope_window: int = 0, integrator: str = "heun"):
         self.lib = load_library()
         p = len(dims)
         self.dims = tuple(int(d) for d in dims)
@@ -198,6 +200,7 @@ class Compressor:
         cfg.eps_th = float(eps_th)
         cfg.gamma_th = float(gamma_th)
         cfg.slope_window = int(slope_window)
+        cfg.integrator = {"heun": INT_HEUN, "euler": INT_EULER}[integrator]
         self.cfg = cfg
         self.h = ctypes.c_void_p()
 
