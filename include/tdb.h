@@ -149,6 +149,16 @@ tdb_status tdb_init_from_factors(const tdb_config* cfg, const void* V0_dev,
  * turns the pipelining off. */
 tdb_status tdb_ingest_snapshot(tdb_handle h, const void* V_dev, void* stream);
 
+/* One step with a given data derivative (Sec. 2.3, and the exact-derivative runs of
+ * the time-scheme study, Sec. 3.1): as tdb_ingest_snapshot with snapshot V_dev at
+ * t_{k+1}, except that the stage projections use D_dev (same shape, dtype and layout
+ * as a snapshot; the derivative of the data, held over the step's stages as the
+ * difference quotient is) instead of (V_{k+1} - V_k)/dt. V_dev still serves the
+ * weighted error and becomes the previous snapshot of the next difference quotient.
+ * The step runs synchronously (any pipelined step is resolved first): D_dev is read
+ * by this call only. TDB_EINVAL for NULL pointers; otherwise as tdb_ingest_snapshot. */
+tdb_status tdb_ingest_with_derivative(tdb_handle h, const void* V_dev, const void* D_dev, void* stream);
+
 /* Read the newest enqueued step's decision and act on it (see tdb_ingest_snapshot);
  * afterwards every step is complete and the statistics are those of the last one.
  * No effect when nothing is pending. TDB_ENUMERIC if that step's error is not finite. */

@@ -10,7 +10,7 @@ namespace tdb {
 
 struct FPassArgs {
   const void* V1;
-  const void* V0;
+  const void* V0;            // NULL: the operand is V1 itself (a given derivative), else V1 - V0
   int N1, N2, N3, r1, r2, r3;
   int T1, T2, nt1, nt2;
   int need_h1, need_h2, need_f3;
@@ -25,6 +25,7 @@ struct FPassArgs {
 struct FReduceArgs {
   int stage;
   double dt;
+  double dscale;             // the data derivative is dscale times the pass's operand
   int N1, N2, N3, r1, r2, r3, T1, T2, nt1, nt2;
   int need_h1, need_h2, need_f3;
   long long slot;
@@ -36,6 +37,7 @@ struct FReduceArgs {
 struct FFinishArgs {
   int stage, rowblocks, core_in_lds, rmax;
   double dt;
+  double dscale;             // the data derivative is dscale times the pass's operand
   long long N[3];
   int r[3], ldU[3];
   const double* H[3];

@@ -74,7 +74,7 @@ __device__ __forceinline__ void freduce_body(const FReduceArgs& a, int stage, Ct
   const long long e4 = e3 + pad64(nC * L3);
   const long long oH2 = (long long)a.T1 * a.r1, oH3 = oH2 + (long long)a.T2 * a.r2;
   const long long oC = oH3 + (long long)a.N3 * a.r3;
-  const double inv_dt = 1.0 / a.dt;
+  const double inv_dt = a.dscale;   // 1/dt for a difference quotient, 1 for a given derivative
   // e4 is a multiple of 64 and so is the stride: every wave runs the same trip count
   for (long long t = (long long)bx * blockDim.x + threadIdx.x; t < e4; t += (long long)gx * blockDim.x) {
     int kind, L;
@@ -217,7 +217,8 @@ __device__ void gram_from(const double* Cl, int rn, long long R, long long inner
                 part);
 }
 
-// M_n = dt * C_dot_(n) P_n (rn x rn) into Ml from LDS copies of C_dot and P_n (R x rn);
+// M_n = C_dot_(n) P_n / dscale (rn x rn; dt C_dot_(n) P_n for a difference quotient) into
+// Ml from LDS copies of C_dot and P_n (R x rn);
 // part: 1024 doubles of LDS scratch.
 template <typename T>
 __device__ void form_m(const double* cdl, const T* Pn, int rn, int R, int inner, double dt, double* Ml, double* part) {
@@ -267,7 +268,7 @@ __device__ __forceinline__ void fmprep_body(const FFinishArgs& a, int stage, Ctr
   for (int k = n + 1; k < 3; ++k) inner *= a.r[k];
   double* Ml = lds + (csz * 8 + Rn * rr * (int)sizeof(T) + 7) / 8;
   double* part = Ml + rr * rr;
-  form_m<T>(cdl, pl, rr, Rn, inner, a.dt, Ml, part);
+  form_m<T>(cdl, pl, rr, Rn, inner, 1.0 / a.dscale, Ml, part);
   for (int t = threadIdx.x; t < rr * rr; t += blockDim.x) a.M[n][t] = Ml[t];
 }
 
@@ -288,7 +289,7 @@ __device__ __forceinline__ void ffinish_body(const FFinishArgs& a, int stage, Ct
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
   if (ctrl->hold || (stage == 2 && ctrl->numeric)) return;
-  const double inv_dt = 1.0 / a.dt;
+  const double inv_dt = a.dscale;   // 1/dt for a difference quotient, 1 for a given derivative
   if (ROLE == ROLE_ROWS || (ROLE == ROLE_ALL && (int)bx < a.rowblocks)) {
     // M_n (r_n x r_n) into LDS: formed once per stage by k_fmprep, or here (a single
     // stream, where the extra launch would cost more than the repeated small product)
@@ -345,7 +346,7 @@ __device__ __forceinline__ void ffinish_body(const FFinishArgs& a, int stage, Ct
         if (rr < a.N[n]) {
           int inner = 1;
           for (int k = n + 1; k < 3; ++k) inner *= a.r[k];
-          form_m<T>(cdl, pl + poff[n], rr, csz / rr, inner, a.dt, Ml[n], part);
+          form_m<T>(cdl, pl + poff[n], rr, csz / rr, inner, 1.0 / a.dscale, Ml[n], part);
         }
         moff += rr * rr;
       }

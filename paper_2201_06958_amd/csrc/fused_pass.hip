@@ -68,7 +68,7 @@ __device__ __forceinline__ void fpass_body(const FPassArgs& a, int bx) {
         if (i1l < n1 && rest < nvalid) {
           const long long g = ((long long)(i1_0 + i1l) * N2 + i2_0) * N3 + rest;
           va[u] = V1[g];
-          vb[u] = V0[g];
+          if (V0) vb[u] = V0[g];
         }
       }
     }

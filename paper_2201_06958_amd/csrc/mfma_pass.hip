@@ -192,8 +192,11 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
       float4 x1 = make_float4(0.f, 0.f, 0.f, 0.f), x0 = x1, y1 = x1, y0 = x1;
       if (ok) {
         x1 = p1[0];
-        x0 = p0[0];
-        if (N3 == 8) { y1 = p1[1]; y0 = p0[1]; }
+        if (V0) x0 = p0[0];
+        if (N3 == 8) {
+          y1 = p1[1];
+          if (V0) y0 = p0[1];
+        }
       }
       d[u][0] = x1.x - x0.x; d[u][1] = x1.y - x0.y; d[u][2] = x1.z - x0.z; d[u][3] = x1.w - x0.w;
       d[u][4] = y1.x - y0.x; d[u][5] = y1.y - y0.y; d[u][6] = y1.z - y0.z; d[u][7] = y1.w - y0.w;
@@ -201,7 +204,7 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         float v = 0.0f;
-        if (ok && c < N3) v = (float)V1[g + c] - (float)V0[g + c];
+        if (ok && c < N3) v = (float)V1[g + c] - (V0 ? (float)V0[g + c] : 0.0f);
         d[u][c] = v;
       }
     }

@@ -148,13 +148,13 @@ __global__ void __launch_bounds__(TDB_BLOCK) k_stage_prep(StageArgs a, CtrlState
 // ---------------------------------------------------------------- basis RHS and Heun
 // blockIdx.x = n < p: U_dot_n = (H_n - U_n (W_n U_n)^T H_n) / dt, the complement
 // projection of eq. (basecont) written with U_n^T W_n F_(n) P_n = (W_n U_n)^T H_n.
-// blockIdx.x == p: the core derivative of eq. (Corecont), C_dot = Cdot_raw / dt.
+// blockIdx.x == p: the core derivative of eq. (Corecont), C_dot = Cdot_raw * dscale.
 // stage 1: k = RHS(S_k), S* = S_k + dt k.  stage 2: S_{k+1} = S_k + dt/2 (k + RHS(S*)).
 __global__ void __launch_bounds__(TDB_BLOCK) k_rhs_stage(RhsArgs a, CtrlState* ctrl) {
   __shared__ double M[TDB_RCAP * TDB_RCAP];
   if (a.stage == 2 && ctrl->numeric) return;
   const int n = blockIdx.x;
-  const double inv_dt = 1.0 / a.dt;
+  const double inv_dt = a.dscale;   // 1/dt for a difference quotient, 1 for a given derivative
   if (n == a.p) {
     const long long nc = a.core_size;
     for (long long t = blockIdx.y * blockDim.x + threadIdx.x; t < nc; t += (long long)gridDim.y * blockDim.x) {

@@ -806,13 +806,17 @@ tdb_status keep_previous(tdb_ctx* h, const TD* V, hipStream_t s) {
 
 tdb_status euler_commit(tdb_ctx* h, hipStream_t s);
 
+// D (may be NULL): a given data derivative in place of (V1 - V_prev)/dt.
 template <typename TD, typename T>
-tdb_status ingest_impl(tdb_ctx* h, const TD* V1, hipStream_t s) {
-  const TD* V0 = static_cast<const TD*>(h->Vprev);
+tdb_status ingest_impl(tdb_ctx* h, const TD* V1, hipStream_t s, const TD* D = nullptr) {
+  // the projected operand: V1 - V_prev (scaled by 1/dt), or D itself
+  const TD* Vp = D ? D : V1;
+  const TD* V0 = D ? nullptr : static_cast<const TD*>(h->Vprev);
   const int p = h->p;
   RhsArgs ra{};
   ra.p = p;
   ra.dt = h->cfg.dt;
+  ra.dscale = D ? 1.0 : 1.0 / h->cfg.dt;
   ra.core_size = prod_ll(h->r, p);
   ra.Cdot = h->Cdot;
   ra.C0 = h->C0;
@@ -832,7 +836,7 @@ tdb_status ingest_impl(tdb_ctx* h, const TD* V1, hipStream_t s) {
   TRY(stage_prep<T>(h, h->C0, h->U0, s));
   {
     PassTimer pt(h, TDB_PASS_PROJECT, s);
-    TRY((project_plain<TD, T>(h, V1, V0, s)));
+    TRY((project_plain<TD, T>(h, Vp, V0, s)));
   }
   ra.stage = 1;
   HIPCHK(launch_rhs_stage(ra, h->ctrl, s));
@@ -843,7 +847,7 @@ tdb_status ingest_impl(tdb_ctx* h, const TD* V1, hipStream_t s) {
     TRY(stage_prep<T>(h, h->Cs, h->Us, s));
     {
       PassTimer pt(h, TDB_PASS_PROJECT, s);
-      TRY((project_plain<TD, T>(h, V1, V0, s)));
+      TRY((project_plain<TD, T>(h, Vp, V0, s)));
     }
     ra.stage = 2;
     HIPCHK(launch_rhs_stage(ra, h->ctrl, s));
@@ -982,7 +986,9 @@ tdb_status build_post_args(tdb_ctx* h, const int* rl, FPostArgs& pa, size_t& lds
 
 // Returns TDB_EUNSUPPORTED when the stage pass does not fit (the caller may fall back
 // to the plain path).
-tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void* V0, StepArgs& A) {
+// D (may be NULL): a given data derivative, projected in place of (V1 - V0)/dt.
+tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void* V0, StepArgs& A,
+                           const void* D = nullptr) {
   const PassPlan base = plan_pass(h, rl, rl != h->r);
   if (!base.ok) { h->err = "stage-pass tile does not fit in LDS"; return TDB_EUNSUPPORTED; }
   const PassPlan pl = rl == h->r ? base : plan_under(h, h->r, base);
@@ -993,8 +999,9 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
   A.pl = pl;
   A.blocks_pass = pl.nt1 * pl.nt2;
   FPassArgs fa{};
-  fa.V1 = V1;
-  fa.V0 = V0;
+  fa.V1 = D ? D : V1;
+  fa.V0 = D ? nullptr : V0;
+  const double dscale = D ? 1.0 : 1.0 / h->cfg.dt;
   fa.N1 = (int)h->N[0]; fa.N2 = (int)h->N[1]; fa.N3 = (int)h->N[2];
   fa.r1 = h->r[0]; fa.r2 = h->r[1]; fa.r3 = h->r[2];
   fa.T1 = pl.T1; fa.T2 = pl.T2; fa.nt1 = pl.nt1; fa.nt2 = pl.nt2;
@@ -1014,6 +1021,7 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
   FReduceArgs& ra = A.ra;
   ra = FReduceArgs{};
   ra.dt = h->cfg.dt;
+  ra.dscale = dscale;
   ra.N1 = fa.N1; ra.N2 = fa.N2; ra.N3 = fa.N3; ra.r1 = fa.r1; ra.r2 = fa.r2; ra.r3 = fa.r3;
   ra.T1 = pl.T1; ra.T2 = pl.T2; ra.nt1 = pl.nt1; ra.nt2 = pl.nt2;
   ra.need_h1 = fa.need_h1; ra.need_h2 = fa.need_h2; ra.need_f3 = fa.need_f3;
@@ -1036,6 +1044,7 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
   ga.core_in_lds = cil ? 1 : 0;
   ga.rmax = max_rank_of(rl, 3);
   ga.dt = h->cfg.dt;
+  ga.dscale = dscale;
   long long rows = 0;
   for (int n = 0; n < 3; ++n) rows += h->N[n] * rl[n];
   ga.rowblocks = (int)std::max<long long>(1, std::min<long long>(1024, (rows + 255) / 256));
@@ -1241,24 +1250,27 @@ tdb_status resolve_pending(tdb_ctx* h) {
   return h->f32 ? resolve_step<double, float>(h) : resolve_step<double, double>(h);
 }
 
+// D (may be NULL): a given data derivative; such a step runs synchronously (D is read
+// by this call only).
 template <typename TD, typename T>
-tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
+tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s, const TD* D = nullptr) {
+  if (D) TRY(resolve_pending(h));
   // work enqueued earlier on another stream comes first
   if (h->pending && h->pend_stream != s) HIPCHK(hipStreamWaitEvent(s, h->ev_ctrl[h->mirror], 0));
   StepArgs A;
-  tdb_status bs = build_step_args(h, h->r, V1, h->Vprev, A);
+  tdb_status bs = build_step_args(h, h->r, V1, h->Vprev, A, D);
   if (bs == TDB_EUNSUPPORTED) {
     TRY(resolve_pending(h));
-    bs = build_step_args(h, h->r, V1, h->Vprev, A);   // the ranks may have changed
+    bs = build_step_args(h, h->r, V1, h->Vprev, A, D);   // the ranks may have changed
   }
   if (bs == TDB_EUNSUPPORTED) {
     h->post_valid = false;
     h->plain_steps += 1;
-    return ingest_impl<TD, T>(h, V1, s);
+    return ingest_impl<TD, T>(h, V1, s, D);
   }
   TRY(bs);
   h->fused_steps += 1;
-  if (!h->pipelined) {
+  if (!h->pipelined || D) {
     TRY((enqueue_fused_step<TD, T>(h, A, s)));
     TRY(pull_ctrl(h, s));
     return finish_step<TD, T>(h, V1, s);
@@ -1303,13 +1315,15 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s) {
 }
 
 template <typename TD>
-tdb_status ingest_dispatch(tdb_ctx* h, const void* V, hipStream_t s) {
+tdb_status ingest_dispatch(tdb_ctx* h, const void* V, hipStream_t s, const void* D = nullptr) {
+  const TD* Vt = static_cast<const TD*>(V);
+  const TD* Dt = static_cast<const TD*>(D);
   if (h->fused) {
-    if (h->f32) return ingest_fused<TD, float>(h, static_cast<const TD*>(V), s);
-    return ingest_fused<TD, double>(h, static_cast<const TD*>(V), s);
+    if (h->f32) return ingest_fused<TD, float>(h, Vt, s, Dt);
+    return ingest_fused<TD, double>(h, Vt, s, Dt);
   }
-  if (h->f32) return ingest_impl<TD, float>(h, static_cast<const TD*>(V), s);
-  return ingest_impl<TD, double>(h, static_cast<const TD*>(V), s);
+  if (h->f32) return ingest_impl<TD, float>(h, Vt, s, Dt);
+  return ingest_impl<TD, double>(h, Vt, s, Dt);
 }
 
 template <typename TD>
@@ -1779,6 +1793,20 @@ tdb_status tdb_ingest_snapshot(tdb_handle h, const void* V_dev, void* stream) {
   tdb_status st = h->data32 ? ingest_dispatch<float>(h, V_dev, s) : ingest_dispatch<double>(h, V_dev, s);
   if (st == TDB_OK && !std::isfinite(h->stats.eps)) {
     h->err = "non-finite reconstruction error (NaN or Inf in the snapshot?)";
+    return TDB_ENUMERIC;
+  }
+  return st;
+}
+
+tdb_status tdb_ingest_with_derivative(tdb_handle h, const void* V_dev, const void* D_dev, void* stream) {
+  if (!h) { g_create_error = "handle is NULL"; return TDB_EINVAL; }
+  if (!h->ready) { h->err = "handle is not initialised"; return TDB_ESTATE; }
+  if (!V_dev || !D_dev) { h->err = "V_dev and D_dev must not be NULL"; return TDB_EINVAL; }
+  if (h->batch_owned) { h->err = "this stream belongs to a batch: use tdb_batch_ingest"; return TDB_ESTATE; }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  tdb_status st = h->data32 ? ingest_dispatch<float>(h, V_dev, s, D_dev) : ingest_dispatch<double>(h, V_dev, s, D_dev);
+  if (st == TDB_OK && !std::isfinite(h->stats.eps)) {
+    h->err = "non-finite reconstruction error (NaN or Inf in the snapshot or derivative?)";
     return TDB_ENUMERIC;
   }
   return st;

@@ -20,6 +20,7 @@ struct StageArgs {
 struct RhsArgs {
   int p, stage;
   double dt;
+  double dscale;         // the data derivative is dscale times the projected operand
   int r[TDB_P];
   long long N[TDB_P];
   int ldU[TDB_P];

@@ -98,6 +98,7 @@ def load_library(path: str = LIB_PATH):
                                           ctypes.POINTER(ctypes.POINTER(ctypes.c_double)), P,
                                           ctypes.POINTER(H)]
     lib.tdb_ingest_snapshot.argtypes = [H, P, P]
+    lib.tdb_ingest_with_derivative.argtypes = [H, P, P, P]
     lib.tdb_flush.argtypes = [H]
     lib.tdb_get_core_and_bases.argtypes = [H, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_double),
@@ -231,6 +232,10 @@ class Compressor:
 
     def ingest(self, V, stream=None):
         self._check(self.lib.tdb_ingest_snapshot(self.h, _dev_ptr(V), _stream_ptr(stream)))
+
+    def ingest_with_derivative(self, V, D, stream=None):
+        """One step with the given data derivative D (same shape and dtype as V)."""
+        self._check(self.lib.tdb_ingest_with_derivative(self.h, _dev_ptr(V), _dev_ptr(D), _stream_ptr(stream)))
 
     def flush(self):
         """Act on the newest enqueued step's decision (borrowed snapshots pipeline the

@@ -63,6 +63,7 @@ def test_null_handle_calls_fail_cleanly():
     from paper_2201_06958_amd import tdb
     lib = tdb.load_library()
     assert lib.tdb_ingest_snapshot(None, None, None) == tdb.EINVAL
+    assert lib.tdb_ingest_with_derivative(None, None, None, None) == tdb.EINVAL
     assert lib.tdb_set_threshold(None, 1.0, 0.0) == tdb.EINVAL
     s = tdb.TdbStats()
     assert lib.tdb_get_stats(None, ctypes.byref(s)) == tdb.EINVAL

@@ -1,8 +1,10 @@
-"""GPU parity of the explicit Euler integrator (the first-order scheme of the
-time-scheme comparison, Sec. 3.1) against the FP64 oracle's Euler step, raw state per
-step at 1e-10 relative on both paths; and the scheme study on an exactly low-rank
-stream, where the error is pure time-integration error: the observed order of the
-device's Heun step is two, of its Euler step one, as the oracle's are."""
+"""GPU parity of the time-scheme options (Sec. 3.1): the explicit Euler integrator
+against the FP64 oracle's Euler step, and steps with a given data derivative
+(tdb_ingest_with_derivative) against the oracle fed the same derivative, raw state per
+step at 1e-10 relative (FP64) on both paths, 1e-6 on the reconstruction for FP32; and
+the scheme study on an exactly low-rank stream, where the error is pure
+time-integration error: the observed order of the device's Heun step is two, of its
+Euler step one, with the difference quotient and with the exact derivative."""
 import math
 import sys
 
@@ -99,6 +101,75 @@ def test_scheme_order_on_exactly_low_rank_stream(integrator, order, path):
     sp = lowrank_manifold_spec(dims=(12, 10, 8), ranks=(3, 3, 2), seed=0, rot=0.8)
     T = 0.4
     e = [_device_error(sp, T, dt, integrator, path) for dt in (0.02, 0.01, 0.005)]
+    o2 = math.log2(e[1] / e[2])
+    _say(f"  errors {e}, observed order {o2:.3f}")
+    assert abs(o2 - order) < 0.2, (e, o2)
+
+
+@pytest.mark.parametrize("integrator", ["heun", "euler"])
+@pytest.mark.parametrize("path,precision", [("plain", "f64"), ("fused", "f64"), ("fused", "f32")])
+def test_derivative_ingest_matches_oracle(path, precision, integrator):
+    """Steps with a given data derivative (here an arbitrary random field, so that the
+    projections see nothing of the snapshots' difference): raw state per step at 1e-10
+    (FP64), reconstruction at 1e-6 (FP32 data and passes), eps as the oracle's."""
+    _say(f"case derivative ingest {path} {precision} {integrator}")
+    dims, ranks = (20, 17, 9), (3, 4, 2)
+    rng = np.random.default_rng(29)
+    w = []
+    for n in dims:
+        x = rng.uniform(0.5, 1.5, size=n)
+        w.append(x / x.sum())
+    base = rng.normal(size=dims)
+    st = np.float64 if precision == "f64" else np.float32
+    snaps = [(base + 0.005 * k * rng.normal(size=dims)).astype(st) for k in range(6)]
+    ders = [(0.1 * rng.normal(size=dims)).astype(st) for k in range(6)]
+    cfg = O.OracleConfig(dims=dims, weights=w, dt=0.05, rank_max=ranks, rank_init=ranks,
+                         adaptive=False, eps_th=1.0, integrator=integrator)
+    orc = O.OracleTDB(cfg).init(snaps[0].astype(np.float64))
+    from paper_2201_06958_amd import Compressor
+    g = Compressor(dims, 0.05, rank_max=ranks, rank_init=ranks, weights=w, data_dtype=precision,
+                   precision=precision, adaptive=False, path=path, eps_th=1.0, integrator=integrator)
+    g.init_from_factors(_dev(snaps[0]), orc.C, orc.U)
+    for k in range(1, len(snaps)):
+        rec = orc.ingest(snaps[k].astype(np.float64), D=ders[k].astype(np.float64))
+        g.ingest_with_derivative(_dev(snaps[k]), _dev(ders[k]))
+        r, C, U = g.get_core_and_bases()
+        if precision == "f64":
+            assert _rel(C, orc.C) < 1e-10, k
+            for n in range(len(dims)):
+                assert _rel(U[n], orc.U[n]) < 1e-10, (k, n)
+            assert g.stats()["eps"] == pytest.approx(rec.eps, rel=1e-9)
+        else:
+            assert _rel(O.reconstruct(C, U), orc.reconstruct()) < 1e-6, k
+            assert abs(g.stats()["eps"] - rec.eps) <= 1e-6 * rec.nu, k
+    g.close()
+
+
+def _device_error_exact(sp, T, dt, integrator):
+    from paper_2201_06958_amd import Compressor
+    sp.dt = dt
+    steps = int(round(T / dt))
+    g = Compressor(sp.dims, dt, rank_max=sp.rank_max, rank_init=sp.rank_init, weights=sp.weights,
+                   data_dtype="f64", precision="f64", adaptive=False, path="fused", eps_th=1.0,
+                   integrator=integrator)
+    g.init(_dev(sp.snapshot_np(0)))
+    for k in range(1, steps + 1):
+        # the exact derivative at the step's midpoint, held over the step's stages
+        D = sp.deriv_fn(sp.time(k - 1) + 0.5 * dt, "cpu", torch.float64).numpy()
+        g.ingest_with_derivative(_dev(sp.snapshot_np(k)), _dev(D))
+    st = g.stats()
+    g.close()
+    return st["eps"] / st["nu"]
+
+
+@pytest.mark.parametrize("integrator,order", [("heun", 2.0), ("euler", 1.0)])
+def test_scheme_order_with_exact_derivative(integrator, order):
+    """The time-scheme comparison with the exact data derivative on an exactly
+    low-rank stream: Heun second order, Euler first, Heun's error the smaller."""
+    _say(f"case exact-derivative order {integrator}")
+    sp = lowrank_manifold_spec(dims=(12, 10, 8), ranks=(3, 3, 2), seed=0, rot=0.8)
+    T = 0.4
+    e = [_device_error_exact(sp, T, dt, integrator) for dt in (0.02, 0.01, 0.005)]
     o2 = math.log2(e[1] / e[2])
     _say(f"  errors {e}, observed order {o2:.3f}")
     assert abs(o2 - order) < 0.2, (e, o2)
