@@ -25,6 +25,8 @@ namespace tdb {
 #define NE TDB_NEIG
 #define EC 8    // rows per chunk of the per-lane tridiagonal sweeps
 #define TRI_TAIL 128   // largest trailing block reduced by a single workgroup
+#define TT_PARTS 8     // thread groups of TRI_TAIL threads in that workgroup
+#define TT_THREADS (TRI_TAIL * TT_PARTS)
 
 // Per-mode workspace (after the K eigenvector columns): d, e, beta, p0, p1, vr0, vr1.
 struct EigWs {
@@ -144,7 +146,7 @@ __global__ void __launch_bounds__(256) k_tri_step(EigBatch batch, int k) {
 // pending update of reflector k0-1, then runs the same reflector formulas as
 // k_tri_step (sums in a fixed order), storing each reflector in row k of G for the
 // back-transformation.
-__global__ void __launch_bounds__(256) k_tri_tail(EigBatch batch) {
+__global__ void __launch_bounds__(TT_THREADS) k_tri_tail(EigBatch batch) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* A = reinterpret_cast<double*>(smem_raw);
   const EigArgs a = batch.m[blockIdx.x];
@@ -153,17 +155,17 @@ __global__ void __launch_bounds__(256) k_tri_tail(EigBatch batch) {
   double* G = a.G;
   double* v = A + (long long)T * T;            // TRI_TAIL
   double* wv = v + TRI_TAIL;                   // TRI_TAIL
-  double* half = wv + TRI_TAIL;                // 2 * TRI_TAIL partial products
+  double* part = wv + TRI_TAIL;                // TT_PARTS * TRI_TAIL partial products
   __shared__ double red[16];
   const int tid = threadIdx.x;
-  // thread layout over the block: column c = tid % TRI_TAIL, rows h, h + 2, ...
+  // thread layout over the block: column c = tid % TRI_TAIL, rows h, h + TT_PARTS, ...
   const int c = tid & (TRI_TAIL - 1), h = tid >> 7;
   if (n == 1) {
     if (tid == 0) { w.d[0] = G[0]; w.e[0] = 0.0; w.beta[0] = 0.0; }
     return;
   }
   if (c < T)
-    for (int i = h; i < T; i += 2) A[i * T + c] = G[(long long)(k0 + i) * n + k0 + c];
+    for (int i = h; i < T; i += TT_PARTS) A[i * T + c] = G[(long long)(k0 + i) * n + k0 + c];
   __syncthreads();
   // the pending update of reflector k0-1 (acting on indices k0..n-1)
   const double bp = k0 > 0 ? w.beta[k0 - 1] : 0.0;
@@ -187,7 +189,7 @@ __global__ void __launch_bounds__(256) k_tri_tail(EigBatch batch) {
     __syncthreads();
     if (c < T) {
       const double vc = v[c], wc = wv[c];
-      for (int i = h; i < T; i += 2) A[i * T + c] -= v[i] * wc + wv[i] * vc;
+      for (int i = h; i < T; i += TT_PARTS) A[i * T + c] -= v[i] * wc + wv[i] * vc;
     }
     __syncthreads();
   }
@@ -222,19 +224,22 @@ __global__ void __launch_bounds__(256) k_tri_tail(EigBatch batch) {
     __syncthreads();
     for (int i = tid; i < m; i += blockDim.x) G[(long long)k * n + k + 1 + i] = v[i];
     if (bk != 0.0) {
-      // p = bk A v over the trailing block: column c of A (= row c), the two halves of
-      // the sum in the two halves of the workgroup
-      const int hm = (m + 1) >> 1;
+      // p = bk A v over the trailing block: column c of A (= row c), the sum split in
+      // TT_PARTS ranges over the workgroup's thread groups, added in a fixed order
+      const int hm = (m + TT_PARTS - 1) / TT_PARTS;
       if (c < m) {
         double s = 0.0;
-        const int j1 = h ? m : hm;
+        const int j1 = min(m, (h + 1) * hm);
         for (int j = h * hm; j < j1; ++j) s += A[(r1 + j) * T + r1 + c] * v[j];
-        half[h * TRI_TAIL + c] = s;
+        part[h * TRI_TAIL + c] = s;
       }
       __syncthreads();
       double pv = 0.0;
       if (tid < m) {
-        const double pi = bk * (half[tid] + half[TRI_TAIL + tid]);
+        double ps = 0.0;
+#pragma unroll
+        for (int q = 0; q < TT_PARTS; ++q) ps += part[q * TRI_TAIL + tid];
+        const double pi = bk * ps;
         wv[tid] = pi;
         pv = pi * v[tid];
       }
@@ -244,7 +249,7 @@ __global__ void __launch_bounds__(256) k_tri_tail(EigBatch batch) {
       __syncthreads();
       if (c < m) {
         const double vc = v[c], wc = wv[c];
-        for (int i = h; i < m; i += 2) A[(r1 + i) * T + r1 + c] -= v[i] * wc + wv[i] * vc;
+        for (int i = h; i < m; i += TT_PARTS) A[(r1 + i) * T + r1 + c] -= v[i] * wc + wv[i] * vc;
       }
       __syncthreads();
     }
@@ -285,10 +290,12 @@ __device__ __forceinline__ double hash_unit2(unsigned a, unsigned b) {
   return (double)x * (2.0 / 4294967296.0) - 1.0;
 }
 
-// One block per mode: the K+1 leading eigenvalues by multisection on Sturm counts
-// (8 lanes per eigenvalue evaluate 8 interior points of its interval, which shrinks
-// 9-fold per round), the singular values sqrt(max(lambda, 0)), and the Gershgorin scale.
-__global__ void __launch_bounds__(576) k_eig_values(EigBatch batch, double* lam_out) {
+// Grid (mode, group of EV_PER eigenvalues): the K+1 leading eigenvalues by
+// multisection on Sturm counts (8 lanes per eigenvalue evaluate 8 interior points of its
+// interval, which shrinks 9-fold per round), the singular values sqrt(max(lambda, 0)),
+// and the Gershgorin scale. The groups spread the FP64 work over many compute units.
+#define EV_PER 16
+__global__ void __launch_bounds__(8 * EV_PER) k_eig_values(EigBatch batch, double* lam_out) {
   const EigArgs a = batch.m[blockIdx.x];
   const int n = a.Nn, K = a.k;
   const EigWs w = eig_ws(a);
@@ -315,7 +322,7 @@ __global__ void __launch_bounds__(576) k_eig_values(EigBatch batch, double* lam_
   gl -= 4.0 * eps * tn + 2.0 * pivmin;
   gu += 4.0 * eps * tn + 2.0 * pivmin;
   double* lam = lam_out + (long long)blockIdx.x * (TDB_RCAP + 2);
-  const int t = threadIdx.x >> 3, sub = threadIdx.x & 7;   // eigenvalue slot, lane in the group
+  const int t = blockIdx.y * EV_PER + (threadIdx.x >> 3), sub = threadIdx.x & 7;   // eigenvalue, lane in its group
   double l = gl, h = gu;
   const bool live = t <= K && t < n;
   const int idx = n - 1 - t;                                  // ascending index of the t-th largest
@@ -345,7 +352,7 @@ __global__ void __launch_bounds__(576) k_eig_values(EigBatch batch, double* lam_
     lam[t] = lt;
     a.sig[t] = t < n ? sqrt(fmax(lt, 0.0)) : 0.0;
   }
-  if (threadIdx.x == 0) lam[TDB_RCAP + 1] = tn;
+  if (blockIdx.y == 0 && threadIdx.x == 0) lam[TDB_RCAP + 1] = tn;
 }
 
 // Inverse iteration for the K leading eigenvectors in rounds of two kernels: a solve
@@ -733,13 +740,14 @@ hipError_t launch_sym_eig(const EigBatch& b, double* lam_scratch, double* vec_sc
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  const size_t tl = ((size_t)TRI_TAIL * TRI_TAIL + 4 * TRI_TAIL) * sizeof(double);
+  const size_t tl = ((size_t)TRI_TAIL * TRI_TAIL + (2 + TT_PARTS) * TRI_TAIL) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_tri_tail, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tl);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_tri_tail, dim3(bt.count), dim3(256), tl, s, bt);
+  hipLaunchKernelGGL(k_tri_tail, dim3(bt.count), dim3(TT_THREADS), tl, s, bt);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_eig_values, dim3(b.count), dim3(576), 0, s, bt, lam_scratch);
+  hipLaunchKernelGGL(k_eig_values, dim3(b.count, (kmax + 1 + EV_PER - 1) / EV_PER), dim3(8 * EV_PER), 0, s, bt,
+                     lam_scratch);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   for (int it = 0; it < 3; ++it) {
