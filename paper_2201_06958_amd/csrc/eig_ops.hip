@@ -290,12 +290,13 @@ __device__ __forceinline__ double hash_unit2(unsigned a, unsigned b) {
   return (double)x * (2.0 / 4294967296.0) - 1.0;
 }
 
-// Grid (mode, group of EV_PER eigenvalues): the K+1 leading eigenvalues by
-// multisection on Sturm counts (8 lanes per eigenvalue evaluate 8 interior points of its
-// interval, which shrinks 9-fold per round), the singular values sqrt(max(lambda, 0)),
-// and the Gershgorin scale. The groups spread the FP64 work over many compute units.
-#define EV_PER 16
-__global__ void __launch_bounds__(8 * EV_PER) k_eig_values(EigBatch batch, double* lam_out) {
+// Grid (mode, eigenvalue): the K+1 leading eigenvalues by multisection on Sturm counts
+// (the 64 lanes of one wave evaluate 64 interior points of the eigenvalue's interval,
+// which shrinks 65-fold per round: a round costs one serial Sturm recurrence, so fewer
+// rounds is what counts), the singular values sqrt(max(lambda, 0)), and the Gershgorin
+// scale.
+#define EV_PTS 64
+__global__ void __launch_bounds__(EV_PTS) k_eig_values(EigBatch batch, double* lam_out) {
   const EigArgs a = batch.m[blockIdx.x];
   const int n = a.Nn, K = a.k;
   const EigWs w = eig_ws(a);
@@ -322,7 +323,7 @@ __global__ void __launch_bounds__(8 * EV_PER) k_eig_values(EigBatch batch, doubl
   gl -= 4.0 * eps * tn + 2.0 * pivmin;
   gu += 4.0 * eps * tn + 2.0 * pivmin;
   double* lam = lam_out + (long long)blockIdx.x * (TDB_RCAP + 2);
-  const int t = blockIdx.y * EV_PER + (threadIdx.x >> 3), sub = threadIdx.x & 7;   // eigenvalue, lane in its group
+  const int t = blockIdx.y, sub = threadIdx.x;   // eigenvalue, interior point
   double l = gl, h = gu;
   const bool live = t <= K && t < n;
   const int idx = n - 1 - t;                                  // ascending index of the t-th largest
@@ -330,18 +331,15 @@ __global__ void __launch_bounds__(8 * EV_PER) k_eig_values(EigBatch batch, doubl
     // converged to the accuracy of the eigenvalues themselves: a few ulps of the matrix
     // scale (an eigenvalue below that is numerically zero)
     bool done = !live || h - l <= fmax(2.0 * eps * fmax(fabs(l), fabs(h)), 4.0 * eps * tn) + pivmin;
-    // the whole wave leaves together once every group in it has converged
-    if (__all(done)) break;
-    const double x = l + (double)(sub + 1) * ((h - l) / 9.0);
-    const int c = live && !done ? sturm_count2(d, e2, n, x, pivmin) : 0;
+    if (done) break;   // common to the wave
+    const double x = l + (double)(sub + 1) * ((h - l) / (double)(EV_PTS + 1));
+    const int c = sturm_count2(d, e2, n, x, pivmin);
     // first point whose count exceeds idx bounds the eigenvalue from above
     const unsigned long long above = __ballot(c > idx);
-    const int base = (threadIdx.x & 63) & ~7;
-    const unsigned grp = (unsigned)((above >> base) & 0xffull);
-    if (live && !done) {
-      const int first = grp ? __builtin_ctz(grp) : 8;     // points 0..7; 8: above all
-      const double nl = first == 0 ? l : l + (double)first * ((h - l) / 9.0);
-      const double nh = first == 8 ? h : l + (double)(first + 1) * ((h - l) / 9.0);
+    {
+      const int first = above ? __builtin_ctzll(above) : EV_PTS;   // EV_PTS: above all
+      const double nl = first == 0 ? l : l + (double)first * ((h - l) / (double)(EV_PTS + 1));
+      const double nh = first == EV_PTS ? h : l + (double)(first + 1) * ((h - l) / (double)(EV_PTS + 1));
       if (nl == l && nh == h) { h = l; }                  // no progress in floating point
       l = nl;
       h = nh;
@@ -746,8 +744,7 @@ hipError_t launch_sym_eig(const EigBatch& b, double* lam_scratch, double* vec_sc
   hipLaunchKernelGGL(k_tri_tail, dim3(bt.count), dim3(TT_THREADS), tl, s, bt);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_eig_values, dim3(b.count, (kmax + 1 + EV_PER - 1) / EV_PER), dim3(8 * EV_PER), 0, s, bt,
-                     lam_scratch);
+  hipLaunchKernelGGL(k_eig_values, dim3(b.count, kmax + 1), dim3(EV_PTS), 0, s, bt, lam_scratch);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   for (int it = 0; it < 3; ++it) {
