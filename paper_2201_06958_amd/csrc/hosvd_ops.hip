@@ -95,7 +95,16 @@ __global__ void __launch_bounds__(256) k_gram_reduce(const double* __restrict__ 
     // result never depends on which write lands last
     if (ti == tj && jl > il) continue;
     double s = 0.0;
-    for (int c = 0; c < nchunks; ++c) s += partials[((long long)pair * nchunks + c) * 4096 + t];
+    const double* pp = partials + (long long)pair * nchunks * 4096 + t;
+    int c = 0;
+    for (; c + 8 <= nchunks; c += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = pp[(long long)(c + u) * 4096];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; c < nchunks; ++c) s += pp[(long long)c * 4096];
     s *= sqrt(m.wn[i] * m.wn[j]);
     G[i * m.Nn + j] = s;
     G[j * m.Nn + i] = s;

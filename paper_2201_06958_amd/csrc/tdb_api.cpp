@@ -195,6 +195,10 @@ tdb_status validate(const tdb_config* c, std::string& msg) {
   return TDB_OK;
 }
 
+// K-chunks of the HOSVD Gram partials for a contraction of length K: about 256 terms per
+// block (the kernel is latency-bound, so more, shorter blocks), at most 256 chunks.
+long long gram_chunks(long long K) { return std::max<long long>(1, std::min<long long>(256, (K + 255) / 256)); }
+
 long long prod_ll(const int* a, int p, int skip = -1) {
   long long q = 1;
   for (int k = 0; k < p; ++k)
@@ -388,7 +392,7 @@ tdb_status setup(tdb_ctx* h, const tdb_config* cfg) {
     TRY(dallocT(h, &h->Bmax[n], (size_t)h->N[n] * h->caps[n]));
     const long long nt = (h->N[n] + 63) / 64;
     const long long K = h->S / h->N[n];
-    const long long nch = std::max<long long>(1, std::min<long long>(64, (K + 511) / 512));
+    const long long nch = gram_chunks(K);
     gpart = std::max(gpart, (size_t)(nt * (nt + 1) / 2 * nch * 4096));
   }
   TRY(dallocT(h, &h->gpart, gpart));
@@ -651,7 +655,7 @@ tdb_status hosvd_select(tdb_ctx* h, const TD* V, int mode, hipStream_t s) {
     m.wb = h->wb[n];
     m.wn = h->w[n];
     const long long K = m.A * m.Bsz;
-    const int nch = (int)std::max<long long>(1, std::min<long long>(64, (K + 511) / 512));
+    const int nch = (int)gram_chunks(K);
     long long kchunk = (K + nch - 1) / nch;
     kchunk = (kchunk + 15) / 16 * 16;
     HIPCHK(launch_gram_partials<TD>(V, m, h->gpart, kchunk, nch, s));
