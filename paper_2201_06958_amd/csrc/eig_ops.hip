@@ -47,6 +47,11 @@ __device__ __forceinline__ EigWs eig_ws(const EigArgs& a) {
 }
 
 // Step k of the distributed reduction for one mode, as workgroup bx of nblk.
+// Every global load of a step (the previous reflector and its product, row k, and this
+// workgroup's rows of the trailing block) is issued at entry into registers: one round
+// trip to memory per launch rather than three. A wave owns at most TS_ROWS rows.
+#define TS_ROWS 4
+#define TS_COLS (NE / 64)
 __device__ __forceinline__ void tri_step_body(const EigArgs& a, int k, int bx, int nblk, double* vp, double* wp,
                                               double* v, double* red) {
   const int n = a.Nn;
@@ -54,37 +59,67 @@ __device__ __forceinline__ void tri_step_body(const EigArgs& a, int k, int bx, i
   const EigWs w = eig_ws(a);
   double* G = a.G;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  // the pending update of reflector k-1 (acting on indices k..n-1)
+  const int mp = n - k, m = n - k - 1;
+  const double* pp = ((k - 1) & 1) ? w.p[1] : w.p[0];
+  const double* vq = ((k - 1) & 1) ? w.vr[1] : w.vr[0];
+  // ---- loads
   const double bp = k > 0 ? w.beta[k - 1] : 0.0;
-  const int mp = n - k;
+  const double dk0 = G[(long long)k * n + k];
+  double vl[2], pl[2], cl[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int i = tid + 256 * u;
+    vl[u] = (k > 0 && i < mp) ? vq[k + i] : 0.0;
+    pl[u] = (k > 0 && i < mp) ? pp[k + i] : 0.0;
+    cl[u] = i < m ? G[(long long)k * n + k + 1 + i] : 0.0;
+  }
+  double rv[TS_ROWS][TS_COLS];
+#pragma unroll
+  for (int q = 0; q < TS_ROWS; ++q) {
+    const int i = bx + nblk * wid + 4 * nblk * q;
+#pragma unroll
+    for (int c = 0; c < TS_COLS; ++c) {
+      const int j = lane + 64 * c;
+      rv[q][c] = (i < m && j < m) ? G[(long long)(k + 1 + i) * n + k + 1 + j] : 0.0;
+    }
+  }
+  // ---- the pending update of reflector k-1 (acting on indices k..n-1)
   if (bp != 0.0) {
-    const double* pp = ((k - 1) & 1) ? w.p[1] : w.p[0];
-    const double* vq = ((k - 1) & 1) ? w.vr[1] : w.vr[0];
     double pvv = 0.0;
-    for (int i = tid; i < mp; i += blockDim.x) {
-      const double vi = vq[k + i];
-      vp[i] = vi;
-      pvv += pp[k + i] * vi;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int i = tid + 256 * u;
+      if (i < mp) {
+        vp[i] = vl[u];
+        pvv += pl[u] * vl[u];
+      }
     }
     pvv = block_sum(pvv, red);
     const double Kc = 0.5 * bp * pvv;
-    for (int i = tid; i < mp; i += blockDim.x) wp[i] = pp[k + i] - Kc * vp[i];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int i = tid + 256 * u;
+      if (i < mp) wp[i] = pl[u] - Kc * vl[u];
+    }
     __syncthreads();
   }
   // column k below the diagonal and the diagonal entry of the updated matrix; the
   // trailing block stays exactly symmetric (each update forms the same two products and
   // only the order of their sum differs), so column k is read as the contiguous row k
-  const int m = n - k - 1;
   double ss = 0.0;
-  for (int i = tid; i < m; i += blockDim.x) {
-    double x = G[(long long)k * n + k + 1 + i];
-    if (bp != 0.0) x -= vp[0] * wp[1 + i] + wp[0] * vp[1 + i];
-    v[i] = x;
-    ss += x * x;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int i = tid + 256 * u;
+    if (i < m) {
+      double x = cl[u];
+      if (bp != 0.0) x -= vp[0] * wp[1 + i] + wp[0] * vp[1 + i];
+      v[i] = x;
+      ss += x * x;
+    }
   }
   ss = block_sum(ss, red);
   const double x0 = v[0];
-  double dk = G[(long long)k * n + k];
+  double dk = dk0;
   if (bp != 0.0) dk -= vp[0] * wp[0] + wp[0] * vp[0];
   double bk = 0.0, ek = x0;
   __syncthreads();
@@ -98,23 +133,35 @@ __device__ __forceinline__ void tri_step_body(const EigArgs& a, int k, int bx, i
     if (tid == 0) v[0] = v0;
   }
   __syncthreads();
-  // rows of this workgroup: k+1+i for i = blockIdx.x, blockIdx.x + nblk, ...; one wave per row
+  // rows of this workgroup: k+1+i for i = bx + nblk*wid + 4*nblk*q; one wave per row
   double* pk = (k & 1) ? w.p[1] : w.p[0];
-  for (int i = bx + nblk * wid; i < m; i += nblk * 4) {
-    double* row = G + (long long)(k + 1 + i) * n + (k + 1);
-    double s = 0.0;
-    if (bp != 0.0) {
-      const double vr = vp[1 + i], wr = wp[1 + i];
-      for (int j = lane; j < m; j += 64) {
-        const double x = row[j] - (vr * wp[1 + j] + wr * vp[1 + j]);
-        row[j] = x;
-        s += x * v[j];
+#pragma unroll
+  for (int q = 0; q < TS_ROWS; ++q) {
+    const int i = bx + nblk * wid + 4 * nblk * q;
+    if (i < m) {
+      double* row = G + (long long)(k + 1 + i) * n + (k + 1);
+      double sv = 0.0;
+      if (bp != 0.0) {
+        const double vr = vp[1 + i], wr = wp[1 + i];
+#pragma unroll
+        for (int c = 0; c < TS_COLS; ++c) {
+          const int j = lane + 64 * c;
+          if (j < m) {
+            const double x = rv[q][c] - (vr * wp[1 + j] + wr * vp[1 + j]);
+            row[j] = x;
+            sv += x * v[j];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < TS_COLS; ++c) {
+          const int j = lane + 64 * c;
+          if (j < m) sv += rv[q][c] * v[j];
+        }
       }
-    } else {
-      for (int j = lane; j < m; j += 64) s += row[j] * v[j];
+      sv = warp_sum(sv);
+      if (lane == 0) pk[k + 1 + i] = bk * sv;
     }
-    s = warp_sum(s);
-    if (lane == 0) pk[k + 1 + i] = bk * s;
   }
   if (bx == 0) {
     // this reflector into its vector; the previous one (read by every workgroup above,
@@ -122,8 +169,11 @@ __device__ __forceinline__ void tri_step_body(const EigArgs& a, int k, int bx, i
     double* vk = (k & 1) ? w.vr[1] : w.vr[0];
     for (int i = tid; i < m; i += blockDim.x) vk[k + 1 + i] = v[i];
     if (k > 0) {
-      const double* vq = ((k - 1) & 1) ? w.vr[1] : w.vr[0];
-      for (int i = tid; i < mp; i += blockDim.x) G[(long long)(k - 1) * n + k + i] = vq[k + i];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int i = tid + 256 * u;
+        if (i < mp) G[(long long)(k - 1) * n + k + i] = vl[u];
+      }
     }
     if (tid == 0) {
       w.d[k] = dk;
@@ -727,6 +777,7 @@ hipError_t launch_sym_eig(const EigBatch& b, double* lam_scratch, double* vec_sc
   // enough workgroups that each wave owns a row or two of the largest trailing block;
   // the last TRI_TAIL rows of every mode in one workgroup with the block in LDS
   const int nblk = nmax >= 512 ? 64 : nmax >= 128 ? 32 : 8;
+  if (nmax > TDB_NEIG || 4 * nblk * TS_ROWS < nmax) return hipErrorInvalidValue;   // rows per wave in registers
   EigBatch bt = b;
   int kdist = 0;
   for (int i = 0; i < bt.count; ++i) {
