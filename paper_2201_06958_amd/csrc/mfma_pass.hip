@@ -3,7 +3,7 @@
 // entries (the variables / species / components mode of the target workloads).
 //
 // Tile: 16 rows of mode 1 x T2 (16, 32 or 64) rows of mode 2 x all N3 of mode 3;
-// 4 waves. The pseudo-inverses are staged in LDS with the tile when they fit. Z and D
+// 8 waves (4 for large grids and batches). The pseudo-inverses are staged in LDS with the tile when they fit. Z and D
 // are kept in LDS as [c][i2][i1] with the mode-1 index XOR-swizzled by the low bits of
 // i2, so that the operand reads of every product below fall in distinct LDS banks.
 //   Z[c2][i1][i2] = sum_c D[i1][i2][c] B3[c][c2]        (VALU, from the loaded fibers)
@@ -143,7 +143,7 @@ __host__ __device__ inline long long mpass_lds_floats(int r1, int r2, int r3, in
   return e + x;
 }
 
-template <typename TD, int MF>
+template <typename TD, int MF, int NW>
 __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
   if (a.hold && *a.hold) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -159,12 +159,15 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
   float* Zs = sm;                          // r3 x (T2 x 16, swizzled)
   float* B1s = Zs + r3 * ZS;               // 16 x r1
   float* B2s = B1s + 16 * r1;              // T2 x r2
-  float* B3s = B2s + T2 * r2;              // N3 x r3 (<= 64)
+  float* B3s = B2s + T2 * r2;              // r3 x 8 (B3 transposed, <= 64)
   float* F1s = B3s + 64;                   // 16 x R1
   float* Pp = F1s + 16 * R1;               // staged P1 | P2 | P3
   const float* P1 = static_cast<const float*>(a.P1);
   const float* P2 = static_cast<const float*>(a.P2);
   const float* P3 = static_cast<const float*>(a.P3);
+  const float* P1g = P1;                   // staging sources (P1..P3 switch to LDS)
+  const float* P2g = P2;
+  const float* P3g = P3;
   float* pend = Pp;
   if (a.stage_p) pend += (a.need_h1 ? R1 * r1 : 0) + (a.need_h2 ? R2 * r2 : 0) + (f3 ? R3 * r3 : 0);
   float* Ys = pend;                        // N3 x 16 x r2 (f3)
@@ -172,99 +175,174 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
   float* Ds = X;
   float* F2s = X;
   float* F3s = X + T2 * R2;
-  const int tid = threadIdx.x, wave = tid >> 6;
+  // NW = 8: waves 0-3 load the snapshot fibers and form Z (and D) while waves 4-7
+  // stage the bases and pseudo-inverses; NW = 4: every wave issues its staging loads,
+  // then its fiber loads, then stores the staged batch. All waves share the products.
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const bool stager = NW == 8 && wave >= 4;
+  const int tid = threadIdx.x & 255;
   const int per = TS >> 8;                 // fibers per thread: 1, 2 or 4
 
-  // 1. issue the snapshot loads: `per` fibers of N3 values per thread
-  const TD* V1 = static_cast<const TD*>(a.V1);
-  const TD* V0 = static_cast<const TD*>(a.V0);
-  float d[4][8];
+  // 1. loads. The staging loads bring the bases of this tile and the pseudo-inverses
+  // into LDS (B3 transposed, one column of 8 per c2, so that Z reads it as two
+  // vectors); the fiber loads leave the snapshot differences in registers. Each source
+  // array is copied through a register array of its own, one slot per 256 entries,
+  // so that a slot's source is fixed at compile time: a slot that holds none of the
+  // wave's entries is skipped by a wave-uniform test, and entries past the end (or
+  // past a ragged edge) load a valid entry and are dropped (or zeroed) when stored.
+  // No register is written by anything but its load, so a batch's loads stay in
+  // flight together.
+  const float* B1 = static_cast<const float*>(a.B1) + (long long)i1_0 * r1;
+  const float* B2 = static_cast<const float*>(a.B2) + (long long)i2_0 * r2;
+  const float* B3 = static_cast<const float*>(a.B3);
+  const bool sp = a.stage_p != 0;
+  const int lB1 = 16 * r1, lB2 = T2 * r2, lB3 = N3 * r3;
+  const int lP1 = sp && a.need_h1 ? R1 * r1 : 0;
+  const int lP2 = sp && a.need_h2 ? R2 * r2 : 0;
+  const int lP3 = sp && f3 ? R3 * r3 : 0;
+  const int v0 = n1 * r1, v1 = n2 * r2;
+  float* P1l = Pp;
+  float* P2l = P1l + lP1;
+  float* P3l = P2l + lP2;
+  const int wq = 64 * (wave & 3);
+  // entries [j0, j0 + 256 S) of an array of len entries, of which the first `valid`
+  // exist in the source
+  auto rload = [&](auto& r, const float* src, int len, int valid, int j0) {
+    constexpr int S = sizeof(r) / sizeof(float);
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int q = tid + 256 * u;
-    const int i1 = q / T2, i2 = q - (q / T2) * T2;
-    const bool ok = u < per && i1 < n1 && i2 < n2;
-    const long long g = ((long long)(i1_0 + i1) * N2 + i2_0 + i2) * N3;
+    for (int u = 0; u < S; ++u)
+      if (j0 + u * 256 + wq < len) r[u] = src[min(j0 + u * 256 + tid, valid - 1)];
+  };
+  auto rstore = [&](const auto& r, float* dst, int len, int valid, int j0) {
+    constexpr int S = sizeof(r) / sizeof(float);
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+      const int j = j0 + u * 256 + tid;
+      if (j0 + u * 256 + wq < len && j < len) dst[j] = j < valid ? r[u] : 0.0f;
+    }
+  };
+  constexpr int SB2 = 8, SP = 6;           // slots: B2 (T2 r2 <= 2048), each P batch
+  float b1r[2], b2r[SB2], b3r[1], p1r[SP], p2r[SP], p3r[SP];
+  auto load_bases = [&]() {
+    rload(b1r, B1, lB1, v0, 0);
+    rload(b2r, B2, lB2, v1, 0);
+    rload(b3r, B3, lB3, lB3, 0);
+  };
+  auto store_bases = [&]() {
+    rstore(b1r, B1s, lB1, v0, 0);
+    rstore(b2r, B2s, lB2, v1, 0);
+    if (wq < lB3 && tid < lB3) {
+      const int c = tid / r3, c2 = tid - c * r3;
+      B3s[c2 * 8 + c] = b3r[0];
+    }
+  };
+  auto load_p = [&](int j0) {
+    rload(p1r, P1g, lP1, lP1, j0);
+    rload(p2r, P2g, lP2, lP2, j0);
+    rload(p3r, P3g, lP3, lP3, j0);
+  };
+  auto store_p = [&](int j0) {
+    rstore(p1r, P1l, lP1, lP1, j0);
+    rstore(p2r, P2l, lP2, lP2, j0);
+    rstore(p3r, P3l, lP3, lP3, j0);
+  };
+  const int lPmax = max(lP1, max(lP2, lP3));
+  // the snapshot differences of this thread's fibers, every load issued before any
+  // difference is formed
+  float d[4][8];
+  auto load_fibers = [&]() {
+    const TD* V1 = static_cast<const TD*>(a.V1);
+    const TD* V0 = static_cast<const TD*>(a.V0);
     if (sizeof(TD) == 4 && (N3 == 4 || N3 == 8) && ((reinterpret_cast<uintptr_t>(V1) | reinterpret_cast<uintptr_t>(V0)) & 15) == 0) {
       // whole fibers as 16-byte loads (a fiber of 4 or 8 FP32 values is 16-byte aligned)
-      const float4* p1 = reinterpret_cast<const float4*>(V1 + g);
-      const float4* p0 = reinterpret_cast<const float4*>(V0 + g);
-      float4 x1 = make_float4(0.f, 0.f, 0.f, 0.f), x0 = x1, y1 = x1, y0 = x1;
-      if (ok) {
-        x1 = p1[0];
-        if (V0) x0 = p0[0];
-        if (N3 == 8) {
-          y1 = p1[1];
-          if (V0) y0 = p0[1];
+      float4 x1[4][2], x0[4][2];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = tid + 256 * u;
+        const int i1 = q / T2, i2 = q - (q / T2) * T2;
+        const bool ok = u < per && i1 < n1 && i2 < n2;
+        const long long g = ((long long)(i1_0 + i1) * N2 + i2_0 + i2) * N3;
+        const float4* p1 = reinterpret_cast<const float4*>(V1 + g);
+        const float4* p0 = reinterpret_cast<const float4*>(V0 + g);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          x1[u][h] = make_float4(0.f, 0.f, 0.f, 0.f);
+          x0[u][h] = x1[u][h];
+        }
+        if (ok) {
+          x1[u][0] = p1[0];
+          if (N3 == 8) x1[u][1] = p1[1];
+          if (V0) {
+            x0[u][0] = p0[0];
+            if (N3 == 8) x0[u][1] = p0[1];
+          }
         }
       }
-      d[u][0] = x1.x - x0.x; d[u][1] = x1.y - x0.y; d[u][2] = x1.z - x0.z; d[u][3] = x1.w - x0.w;
-      d[u][4] = y1.x - y0.x; d[u][5] = y1.y - y0.y; d[u][6] = y1.z - y0.z; d[u][7] = y1.w - y0.w;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        d[u][0] = x1[u][0].x - x0[u][0].x; d[u][1] = x1[u][0].y - x0[u][0].y;
+        d[u][2] = x1[u][0].z - x0[u][0].z; d[u][3] = x1[u][0].w - x0[u][0].w;
+        d[u][4] = x1[u][1].x - x0[u][1].x; d[u][5] = x1[u][1].y - x0[u][1].y;
+        d[u][6] = x1[u][1].z - x0[u][1].z; d[u][7] = x1[u][1].w - x0[u][1].w;
+      }
     } else {
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        float v = 0.0f;
-        if (ok && c < N3) v = (float)V1[g + c] - (V0 ? (float)V0[g + c] : 0.0f);
-        d[u][c] = v;
+      for (int u = 0; u < 4; ++u) {
+        const int q = tid + 256 * u;
+        const int i1 = q / T2, i2 = q - (q / T2) * T2;
+        const bool ok = u < per && i1 < n1 && i2 < n2;
+        const long long g = ((long long)(i1_0 + i1) * N2 + i2_0 + i2) * N3;
+        TD y1[8], y0[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          y1[c] = TD(0);
+          y0[c] = TD(0);
+          if (ok && c < N3) {
+            y1[c] = V1[g + c];
+            if (V0) y0[c] = V0[g + c];
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) d[u][c] = (float)y1[c] - (float)y0[c];
       }
     }
-  }
-  // bases of this tile and the pseudo-inverses, all in one batch of loads (up to 16
-  // in flight per thread) rather than one round trip per copy loop
-  {
-    const float* B1 = static_cast<const float*>(a.B1) + (long long)i1_0 * r1;
-    const float* B2 = static_cast<const float*>(a.B2) + (long long)i2_0 * r2;
-    const float* B3 = static_cast<const float*>(a.B3);
-    const bool sp = a.stage_p != 0;
-    const int e0 = 16 * r1, e1 = e0 + T2 * r2, e2 = e1 + N3 * r3;
-    const int e3 = e2 + (sp && a.need_h1 ? R1 * r1 : 0);
-    const int e4 = e3 + (sp && a.need_h2 ? R2 * r2 : 0);
-    const int e5 = e4 + (sp && f3 ? R3 * r3 : 0);
-    const int v0 = n1 * r1, v1 = n2 * r2;
-    float* P1l = Pp;
-    float* P2l = P1l + (e3 - e2);
-    float* P3l = P2l + (e4 - e3);
-    for (int base = 0; base < e5; base += 16 * 256) {
-      float v[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int t = base + u * 256 + tid;
-        float x = 0.0f;
-        if (t < e0) x = t < v0 ? B1[t] : 0.0f;
-        else if (t < e1) x = t - e0 < v1 ? B2[t - e0] : 0.0f;
-        else if (t < e2) x = B3[t - e1];
-        else if (t < e3) x = P1[t - e2];
-        else if (t < e4) x = P2[t - e3];
-        else if (t < e5) x = P3[t - e4];
-        v[u] = x;
-      }
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int t = base + u * 256 + tid;
-        if (t < e0) B1s[t] = v[u];
-        else if (t < e1) B2s[t - e0] = v[u];
-        else if (t < e2) B3s[t - e1] = v[u];
-        else if (t < e3) P1l[t - e2] = v[u];
-        else if (t < e4) P2l[t - e3] = v[u];
-        else if (t < e5) P3l[t - e4] = v[u];
-      }
+  };
+  // The first batch of pseudo-inverse loads is issued after the bases and kept in
+  // registers through Z, F1 and F2 (only the folds read it); it is stored, and any
+  // further batch copied, just before the folds. NW = 8: the staging waves do this
+  // while the fiber waves load the snapshots; NW = 4: every wave does both.
+  if (NW == 8) {
+    if (stager) {
+      load_bases();
+      store_bases();
+      load_p(0);
+    } else {
+      load_fibers();
     }
-    if (e3 > e2) P1 = P1l;
-    if (e4 > e3) P2 = P2l;
-    if (e5 > e4) P3 = P3l;
+  } else {
+    load_bases();
+    load_fibers();
+    store_bases();
+    load_p(0);
   }
+  if (lP1) P1 = P1l;
+  if (lP2) P2 = P2l;
+  if (lP3) P3 = P3l;
   __syncthreads();
   // 2. Z (and D for the third mode) into LDS
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    if (u >= per) break;
+    if (stager || u >= per) break;
     const int q = tid + 256 * u;
     const int zo = zsw(q / T2, q - (q / T2) * T2);
     for (int c2 = 0; c2 < r3; ++c2) {
+      const float4 b0 = *reinterpret_cast<const float4*>(B3s + c2 * 8);
+      const float4 b1 = *reinterpret_cast<const float4*>(B3s + c2 * 8 + 4);
+      const float bc[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
       float s = 0.0f;
 #pragma unroll
       for (int c = 0; c < 8; ++c)
-        if (c < N3) s += d[u][c] * B3s[c * r3 + c2];
+        if (c < N3) s += d[u][c] * bc[c];
       Zs[c2 * ZS + zo] = s;
     }
     if (f3)
@@ -275,7 +353,7 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
   // 3. F1 (and Y)
   {
     const int nF1 = r3 * nb2, nY = f3 ? N3 * nb2 : 0;
-    for (int blk = wave; blk < nF1 + nY; blk += 4) {
+    for (int blk = wave; blk < nF1 + nY; blk += NW) {
       mf4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
       if (blk < nF1) {
         const int c2 = blk / nb2, jb = blk - c2 * nb2;
@@ -300,7 +378,7 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
   {
     const int nib = T2 >> 4;
     const int nF2 = r3 * nb1 * nib, nF3 = f3 ? N3 * nb1 * nb2 : 0;
-    for (int blk = wave; blk < nF2 + nF3; blk += 4) {
+    for (int blk = wave; blk < nF2 + nF3; blk += NW) {
       mf4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
       if (blk < nF2) {
         const int c2 = blk / (nb1 * nib), rem = blk - c2 * nb1 * nib;
@@ -324,6 +402,13 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
       }
     }
   }
+  if (NW == 4 || stager) {
+    store_p(0);
+    for (int j0 = SP * 256; j0 < lPmax; j0 += SP * 256) {
+      load_p(j0);
+      store_p(j0);
+    }
+  }
   __syncthreads();
   // 5. folds into the partial slot
   float* out = static_cast<float*>(a.part) + (long long)bx * a.slot;
@@ -333,7 +418,7 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
   float* oC = oH3 + N3 * r3;
   const int nbR1 = (R1 + 15) >> 4;
   const int nC = nb1 * nbR1, nH1 = a.need_h1 ? nb1 : 0, nH2 = a.need_h2 ? (T2 >> 4) * nb2 : 0, nH3 = f3 ? 1 : 0;
-  for (int blk = wave; blk < nC + nH1 + nH2 + nH3; blk += 4) {
+  for (int blk = wave; blk < nC + nH1 + nH2 + nH3; blk += NW) {
     mf4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
     if (blk < nC) {
       const int ab = blk / nbR1, kb = blk - ab * nbR1;
@@ -356,9 +441,17 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
   }
 }
 
+// Eight waves per tile, at most 128 registers so that two tiles share a compute unit:
+// for grids the chip holds at once, where a tile's latency is the launch's.
 template <typename TD, int MF>
-__global__ void __launch_bounds__(256) k_mpass(FPassArgs a) {
-  mpass_body<TD, MF>(a, blockIdx.x);
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_mpass(FPassArgs a) {
+  mpass_body<TD, MF, 8>(a, blockIdx.x);
+}
+
+// Four waves per tile: more tiles per compute unit, for larger grids.
+template <typename TD, int MF>
+__global__ void __launch_bounds__(256) k_mpass_w4(FPassArgs a) {
+  mpass_body<TD, MF, 4>(a, blockIdx.x);
 }
 
 template <typename TD, int MF>
@@ -368,23 +461,36 @@ __global__ void __launch_bounds__(256) kb_mpass(const FPassArgs* __restrict__ ta
   FPassArgs a = tab[s];
   a.V1 = v1[s];
   a.V0 = v0[s];
-  mpass_body<TD, MF>(a, blockIdx.x - m.start[s]);
+  mpass_body<TD, MF, 4>(a, blockIdx.x - m.start[s]);
 }
 
 size_t mpass_lds_bytes(int r1, int r2, int r3, int N3, int T2, bool h1, bool h2, bool f3, bool pst) {
   return (size_t)mpass_lds_floats(r1, r2, r3, N3, T2, h1, h2, f3, pst) * sizeof(float);
 }
 
+// Tiles up to which the eight-wave kernel runs (two per compute unit of 256).
+static constexpr int MPASS_W8_TILES = 512;
+
 template <typename TD>
 hipError_t launch_mpass(const FPassArgs& a, int flavor, size_t lds, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  const void* f = flavor == MPASS_F32 ? (const void*)k_mpass<TD, MPASS_F32> : (const void*)k_mpass<TD, MPASS_BF16S>;
+  const int tiles = a.nt1 * a.nt2;
+  const bool w8 = tiles <= MPASS_W8_TILES;
+  const void* f = w8 ? (flavor == MPASS_F32 ? (const void*)k_mpass<TD, MPASS_F32> : (const void*)k_mpass<TD, MPASS_BF16S>)
+                     : (flavor == MPASS_F32 ? (const void*)k_mpass_w4<TD, MPASS_F32>
+                                            : (const void*)k_mpass_w4<TD, MPASS_BF16S>);
   hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  if (flavor == MPASS_F32)
-    hipExtLaunchKernelGGL((k_mpass<TD, MPASS_F32>), dim3(a.nt1 * a.nt2), dim3(256), (uint32_t)lds, s, ev0, ev1, 0u, a);
-  else
-    hipExtLaunchKernelGGL((k_mpass<TD, MPASS_BF16S>), dim3(a.nt1 * a.nt2), dim3(256), (uint32_t)lds, s, ev0, ev1, 0u,
-                          a);
+  if (w8) {
+    if (flavor == MPASS_F32)
+      hipExtLaunchKernelGGL((k_mpass<TD, MPASS_F32>), dim3(tiles), dim3(512), (uint32_t)lds, s, ev0, ev1, 0u, a);
+    else
+      hipExtLaunchKernelGGL((k_mpass<TD, MPASS_BF16S>), dim3(tiles), dim3(512), (uint32_t)lds, s, ev0, ev1, 0u, a);
+  } else {
+    if (flavor == MPASS_F32)
+      hipExtLaunchKernelGGL((k_mpass_w4<TD, MPASS_F32>), dim3(tiles), dim3(256), (uint32_t)lds, s, ev0, ev1, 0u, a);
+    else
+      hipExtLaunchKernelGGL((k_mpass_w4<TD, MPASS_BF16S>), dim3(tiles), dim3(256), (uint32_t)lds, s, ev0, ev1, 0u, a);
+  }
   return hipGetLastError();
 }
 template hipError_t launch_mpass<float>(const FPassArgs&, int, size_t, hipStream_t, hipEvent_t, hipEvent_t);
