@@ -1037,7 +1037,8 @@ __global__ void __launch_bounds__(256) k_fpost(FPostArgs a, CtrlState* ctrl) {
 template <typename TD, typename T>
 __device__ __forceinline__ void ferr_body(const FErrArgs& a, int bx, int by, int gx) {
   __shared__ double red[16];
-  __shared__ double U1s[FERR_T1 * TDB_RCAP];
+  // U1 rows of the slab, row q at q * TDB_RCAP, zero past r1 and past the slab's rows
+  __shared__ T U1s[FERR_T1 * TDB_RCAP];
   if (a.skip && *a.skip) {
     // the learned gate skips this step's pass
     if (threadIdx.x == 0) {
@@ -1052,29 +1053,59 @@ __device__ __forceinline__ void ferr_body(const FErrArgs& a, int bx, int by, int
   const int i1_0 = by * a.T1;
   const int n1 = min(a.T1, a.N1 - i1_0);
   const T* E = static_cast<const T*>(a.E);
-  for (int t = threadIdx.x; t < FERR_T1 * r1; t += blockDim.x) {
-    const int q = t / r1;
-    U1s[t] = q < n1 ? (double)static_cast<const T*>(a.U1c)[(long long)(i1_0 + q) * r1 + (t - q * r1)] : 0.0;
+  const TD* V = static_cast<const TD*>(a.V);
+  {
+    T x[FERR_T1 * TDB_RCAP / 256];
+#pragma unroll
+    for (int u = 0; u < FERR_T1 * TDB_RCAP / 256; ++u) {
+      const int t = u * 256 + threadIdx.x;
+      const int q = t / TDB_RCAP, ai = t - q * TDB_RCAP;
+      x[u] = static_cast<const T*>(a.U1c)[(long long)(i1_0 + min(q, n1 - 1)) * r1 + min(ai, r1 - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < FERR_T1 * TDB_RCAP / 256; ++u) {
+      const int t = u * 256 + threadIdx.x;
+      const int q = t / TDB_RCAP, ai = t - q * TDB_RCAP;
+      U1s[t] = q < n1 && ai < r1 ? x[u] : (T)0;
+    }
   }
   __syncthreads();
   double se = 0.0, sv = 0.0;
+  constexpr int EC = 16;        // entries of E per batch of loads
   for (long long j = (long long)bx * blockDim.x + threadIdx.x; j < M; j += (long long)gx * blockDim.x) {
-    T acc[FERR_T1];
-    for (int q = 0; q < FERR_T1; ++q) acc[q] = (T)0;
-    for (int ai = 0; ai < r1; ++ai) {
-      const T e = E[(long long)ai * M + j];
-      for (int q = 0; q < FERR_T1; ++q)
-        acc[q] += (T)U1s[q * r1 + ai] * e;
-    }
+    // the slab's snapshot values first (rows past the slab load the last row and are
+    // dropped), then E in batches of EC, the next batch in flight while one is used
+    TD vv[FERR_T1];
+#pragma unroll
+    for (int q = 0; q < FERR_T1; ++q) vv[q] = V[(long long)(i1_0 + min(q, n1 - 1)) * M + j];
     const double w23 = a.w23[j];
+    T e[EC];
+    auto eload = [&](int a0) {
+#pragma unroll
+      for (int k = 0; k < EC; ++k) e[k] = E[(long long)min(a0 + k, r1 - 1) * M + j];
+    };
+    T acc[FERR_T1];
+#pragma unroll
+    for (int q = 0; q < FERR_T1; ++q) acc[q] = (T)0;
+    eload(0);
+    for (int a0 = 0; a0 < r1; a0 += EC) {
+      T cur[EC];
+#pragma unroll
+      for (int k = 0; k < EC; ++k) cur[k] = e[k];
+      if (a0 + EC < r1) eload(a0 + EC);
+#pragma unroll
+      for (int k = 0; k < EC; ++k)
+#pragma unroll
+        for (int q = 0; q < FERR_T1; ++q) acc[q] += U1s[q * TDB_RCAP + a0 + k] * cur[k];
+    }
+#pragma unroll
     for (int q = 0; q < FERR_T1; ++q) {
-      if (q >= n1) break;
-      const long long g = (long long)(i1_0 + q) * M + j;
-      const TD v = static_cast<const TD*>(a.V)[g];
-      const double d = (double)((T)v - acc[q]);
-      const double ww = a.w1[i1_0 + q] * w23;
-      se += ww * d * d;
-      sv += ww * (double)v * (double)v;
+      if (q < n1) {
+        const double d = (double)((T)vv[q] - acc[q]);
+        const double ww = a.w1[i1_0 + q] * w23;
+        se += ww * d * d;
+        sv += ww * (double)vv[q] * (double)vv[q];
+      }
     }
   }
   se = block_sum(se, red);
