@@ -201,7 +201,7 @@ def main():
     traffic = None
     if args.precision == "f32" and args.path != "plain":
         from paper_2201_06958_amd.profsum import read_pass_traffic
-        traffic = read_pass_traffic(TRAFFIC_FILE, "k_mpass<float, 1>")
+        traffic = read_pass_traffic(TRAFFIC_FILE, "k_mpass_w16<float, 1>")
     plain = None
     if args.plain_steps > 0:
         print("[bench] plain FP64 GPU path", file=sys.stderr, flush=True)
@@ -240,7 +240,7 @@ def main():
                      "traffic_unit": "bytes/launch",
                      "traffic_read_write": ([traffic["read_bytes"], traffic["write_bytes"]]
                                             if traffic else None),
-                     "kernel": "stage projection pass (one Heun stage; k_mpass, matrix cores)",
+                     "kernel": "stage projection pass (one Heun stage; k_mpass_w16, matrix cores)",
                      "avg_launch_us": avg_s * 1e6, "launches": pj["launches"],
                      "algorithmic_bytes_per_launch": pj["bytes_per_launch"]},
         "error_pass": {"avg_launch_us": er_avg_s * 1e6,

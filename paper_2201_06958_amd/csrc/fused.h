@@ -168,6 +168,12 @@ hipError_t launch_euler_commit(const CommitArgs& a, CtrlState* c, hipStream_t s)
 // Stage-pass flavours on the matrix cores (tile 16 x 64 x N3, N3 <= 8, r1, r2 <= 32).
 enum { MPASS_NONE = 0, MPASS_F32 = 1, MPASS_BF16S = 2 };
 size_t mpass_lds_bytes(int r1, int r2, int r3, int N3, int T2, bool h1, bool h2, bool f3, bool pst);
+// Waves per tile of the single-stream matrix-core pass: 16 (one tile per compute unit)
+// for up to MPASS_W16_TILES tiles of 16 x 32 or more, 8 (two per compute unit) for up
+// to MPASS_W8_TILES, else 4.
+#define MPASS_W16_TILES 256
+#define MPASS_W8_TILES 512
+int mpass_waves(int tiles, int T2);
 template <typename TD>
 hipError_t launch_mpass(const FPassArgs& a, int flavor, size_t lds, hipStream_t s, hipEvent_t ev0 = nullptr,
                         hipEvent_t ev1 = nullptr);

@@ -175,18 +175,20 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
   float* Ds = X;
   float* F2s = X;
   float* F3s = X + T2 * R2;
-  // NW = 8: waves 0-3 load the snapshot fibers and form Z (and D) while waves 4-7
-  // stage the bases and pseudo-inverses; NW = 4: every wave issues its staging loads,
-  // then its fiber loads, then stores the staged batch. All waves share the products.
+  // NW = 8 or 16: the first half of the waves load the snapshot fibers and form Z (and
+  // D) while the second half stage the bases and pseudo-inverses; NW = 4: every wave
+  // issues its staging loads, then its fiber loads, then stores the staged batch. All
+  // waves share the products. FT threads load fibers (up to four each), ST stage.
+  constexpr bool split = NW != 4;
+  constexpr int FT = split ? NW * 32 : 256, ST = FT;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const bool stager = NW == 8 && wave >= 4;
-  const int tid = threadIdx.x & 255;
-  const int per = TS >> 8;                 // fibers per thread: 1, 2 or 4
+  const bool stager = split && wave >= NW / 2;
+  const int tid = stager ? (int)threadIdx.x - FT : (int)threadIdx.x;
 
   // 1. loads. The staging loads bring the bases of this tile and the pseudo-inverses
   // into LDS (B3 transposed, one column of 8 per c2, so that Z reads it as two
   // vectors); the fiber loads leave the snapshot differences in registers. Each source
-  // array is copied through a register array of its own, one slot per 256 entries,
+  // array is copied through a register array of its own, one slot per ST entries,
   // so that a slot's source is fixed at compile time: a slot that holds none of the
   // wave's entries is skipped by a wave-uniform test, and entries past the end (or
   // past a ragged edge) load a valid entry and are dropped (or zeroed) when stored.
@@ -204,24 +206,24 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
   float* P1l = Pp;
   float* P2l = P1l + lP1;
   float* P3l = P2l + lP2;
-  const int wq = 64 * (wave & 3);
-  // entries [j0, j0 + 256 S) of an array of len entries, of which the first `valid`
+  const int wq = 64 * (split ? wave % (NW / 2) : wave);
+  // entries [j0, j0 + ST S) of an array of len entries, of which the first `valid`
   // exist in the source
   auto rload = [&](auto& r, const float* src, int len, int valid, int j0) {
     constexpr int S = sizeof(r) / sizeof(float);
 #pragma unroll
     for (int u = 0; u < S; ++u)
-      if (j0 + u * 256 + wq < len) r[u] = src[min(j0 + u * 256 + tid, valid - 1)];
+      if (j0 + u * ST + wq < len) r[u] = src[min(j0 + u * ST + tid, valid - 1)];
   };
   auto rstore = [&](const auto& r, float* dst, int len, int valid, int j0) {
     constexpr int S = sizeof(r) / sizeof(float);
 #pragma unroll
     for (int u = 0; u < S; ++u) {
-      const int j = j0 + u * 256 + tid;
-      if (j0 + u * 256 + wq < len && j < len) dst[j] = j < valid ? r[u] : 0.0f;
+      const int j = j0 + u * ST + tid;
+      if (j0 + u * ST + wq < len && j < len) dst[j] = j < valid ? r[u] : 0.0f;
     }
   };
-  constexpr int SB2 = 8, SP = 6;           // slots: B2 (T2 r2 <= 2048), each P batch
+  constexpr int SB2 = 2048 / ST, SP = 1536 / ST;  // slots: B2 (T2 r2 <= 2048), each P batch
   float b1r[2], b2r[SB2], b3r[1], p1r[SP], p2r[SP], p3r[SP];
   auto load_bases = [&]() {
     rload(b1r, B1, lB1, v0, 0);
@@ -258,9 +260,9 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
       float4 x1[4][2], x0[4][2];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int q = tid + 256 * u;
+        const int q = tid + FT * u;
         const int i1 = q / T2, i2 = q - (q / T2) * T2;
-        const bool ok = u < per && i1 < n1 && i2 < n2;
+        const bool ok = q < TS && i1 < n1 && i2 < n2;
         const long long g = ((long long)(i1_0 + i1) * N2 + i2_0 + i2) * N3;
         const float4* p1 = reinterpret_cast<const float4*>(V1 + g);
         const float4* p0 = reinterpret_cast<const float4*>(V0 + g);
@@ -288,9 +290,9 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
     } else {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int q = tid + 256 * u;
+        const int q = tid + FT * u;
         const int i1 = q / T2, i2 = q - (q / T2) * T2;
-        const bool ok = u < per && i1 < n1 && i2 < n2;
+        const bool ok = q < TS && i1 < n1 && i2 < n2;
         const long long g = ((long long)(i1_0 + i1) * N2 + i2_0 + i2) * N3;
         TD y1[8], y0[8];
 #pragma unroll
@@ -309,9 +311,9 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
   };
   // The first batch of pseudo-inverse loads is issued after the bases and kept in
   // registers through Z, F1 and F2 (only the folds read it); it is stored, and any
-  // further batch copied, just before the folds. NW = 8: the staging waves do this
-  // while the fiber waves load the snapshots; NW = 4: every wave does both.
-  if (NW == 8) {
+  // further batch copied, just before the folds. NW = 8 or 16: the staging waves do
+  // this while the fiber waves load the snapshots; NW = 4: every wave does both.
+  if (split) {
     if (stager) {
       load_bases();
       store_bases();
@@ -332,8 +334,9 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
   // 2. Z (and D for the third mode) into LDS
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    if (stager || u >= per) break;
-    const int q = tid + 256 * u;
+    if (stager || FT * u >= TS) break;
+    const int q = tid + FT * u;
+    if (q >= TS) break;
     const int zo = zsw(q / T2, q - (q / T2) * T2);
     for (int c2 = 0; c2 < r3; ++c2) {
       const float4 b0 = *reinterpret_cast<const float4*>(B3s + c2 * 8);
@@ -402,9 +405,9 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
       }
     }
   }
-  if (NW == 4 || stager) {
+  if (!split || stager) {
     store_p(0);
-    for (int j0 = SP * 256; j0 < lPmax; j0 += SP * 256) {
+    for (int j0 = SP * ST; j0 < lPmax; j0 += SP * ST) {
       load_p(j0);
       store_p(j0);
     }
@@ -441,8 +444,15 @@ __device__ __forceinline__ void mpass_body(const FPassArgs& a, int bx) {
   }
 }
 
-// Eight waves per tile, at most 128 registers so that two tiles share a compute unit:
-// for grids the chip holds at once, where a tile's latency is the launch's.
+// Sixteen waves per tile, one tile per compute unit (tiles of 16 x 32 or more): for
+// grids the chip holds at once, where a tile's latency is the launch's and a second
+// tile on the same compute unit would only slow the first.
+template <typename TD, int MF>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) k_mpass_w16(FPassArgs a) {
+  mpass_body<TD, MF, 16>(a, blockIdx.x);
+}
+
+// Eight waves per tile, at most 128 registers so that two tiles share a compute unit.
 template <typename TD, int MF>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_mpass(FPassArgs a) {
   mpass_body<TD, MF, 8>(a, blockIdx.x);
@@ -468,25 +478,33 @@ size_t mpass_lds_bytes(int r1, int r2, int r3, int N3, int T2, bool h1, bool h2,
   return (size_t)mpass_lds_floats(r1, r2, r3, N3, T2, h1, h2, f3, pst) * sizeof(float);
 }
 
-// Tiles up to which the eight-wave kernel runs (two per compute unit of 256).
-static constexpr int MPASS_W8_TILES = 512;
+int mpass_waves(int tiles, int T2) {
+  if (tiles <= MPASS_W16_TILES && T2 >= 32) return 16;
+  return tiles <= MPASS_W8_TILES ? 8 : 4;
+}
 
 template <typename TD>
 hipError_t launch_mpass(const FPassArgs& a, int flavor, size_t lds, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const int tiles = a.nt1 * a.nt2;
-  const bool w8 = tiles <= MPASS_W8_TILES;
-  const void* f = w8 ? (flavor == MPASS_F32 ? (const void*)k_mpass<TD, MPASS_F32> : (const void*)k_mpass<TD, MPASS_BF16S>)
-                     : (flavor == MPASS_F32 ? (const void*)k_mpass_w4<TD, MPASS_F32>
-                                            : (const void*)k_mpass_w4<TD, MPASS_BF16S>);
+  const int nw = mpass_waves(tiles, a.T2);
+  const bool f32 = flavor == MPASS_F32;
+  const void* f = nw == 16 ? (f32 ? (const void*)k_mpass_w16<TD, MPASS_F32> : (const void*)k_mpass_w16<TD, MPASS_BF16S>)
+                  : nw == 8 ? (f32 ? (const void*)k_mpass<TD, MPASS_F32> : (const void*)k_mpass<TD, MPASS_BF16S>)
+                            : (f32 ? (const void*)k_mpass_w4<TD, MPASS_F32> : (const void*)k_mpass_w4<TD, MPASS_BF16S>);
   hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  if (w8) {
-    if (flavor == MPASS_F32)
+  if (nw == 16) {
+    if (f32)
+      hipExtLaunchKernelGGL((k_mpass_w16<TD, MPASS_F32>), dim3(tiles), dim3(1024), (uint32_t)lds, s, ev0, ev1, 0u, a);
+    else
+      hipExtLaunchKernelGGL((k_mpass_w16<TD, MPASS_BF16S>), dim3(tiles), dim3(1024), (uint32_t)lds, s, ev0, ev1, 0u, a);
+  } else if (nw == 8) {
+    if (f32)
       hipExtLaunchKernelGGL((k_mpass<TD, MPASS_F32>), dim3(tiles), dim3(512), (uint32_t)lds, s, ev0, ev1, 0u, a);
     else
       hipExtLaunchKernelGGL((k_mpass<TD, MPASS_BF16S>), dim3(tiles), dim3(512), (uint32_t)lds, s, ev0, ev1, 0u, a);
   } else {
-    if (flavor == MPASS_F32)
+    if (f32)
       hipExtLaunchKernelGGL((k_mpass_w4<TD, MPASS_F32>), dim3(tiles), dim3(256), (uint32_t)lds, s, ev0, ev1, 0u, a);
     else
       hipExtLaunchKernelGGL((k_mpass_w4<TD, MPASS_BF16S>), dim3(tiles), dim3(256), (uint32_t)lds, s, ev0, ev1, 0u, a);

@@ -253,7 +253,7 @@ size_t mpass_occupancy_budget(const tdb_ctx* h) { return std::min<size_t>((size_
 
 // Tile shape of the fused stage pass for ranks r. Matrix-core tiles are 16 x T2 x N3
 // with T2 the largest of 64, 32, 16 that fits and (for a single stream) still gives
-// at least two tiles per compute unit; generic tiles hold about `target` elements,
+// at least one tile per compute unit; generic tiles hold about `target` elements,
 // shrunk until their LDS fits. `worst`: size for every rank up to r (batches).
 PassPlan plan_pass(const tdb_ctx* h, const int* r, bool worst = false) {
   PassPlan pl;
@@ -262,13 +262,15 @@ PassPlan plan_pass(const tdb_ctx* h, const int* r, bool worst = false) {
     int T2 = 64;
     while (T2 > 16 && mpass_bytes(h, r, T2, false, worst) > (size_t)h->lds_max) T2 /= 2;
     if (!h->batch_owned)
-      while (T2 > 16 && ((N1 + 15) / 16) * ((N2 + T2 - 1) / T2) < 512) T2 /= 2;
+      while (T2 > 16 && ((N1 + 15) / 16) * ((N2 + T2 - 1) / T2) < MPASS_W16_TILES) T2 /= 2;
     pl.mfma = h->bf16s ? MPASS_BF16S : MPASS_F32;
     pl.T1 = 16;
     pl.T2 = T2;
     pl.nt1 = (int)((N1 + 15) / 16);
     pl.nt2 = (int)((N2 + T2 - 1) / T2);
-    pl.stage_p = mpass_bytes(h, r, T2, true, worst) <= mpass_occupancy_budget(h) ? 1 : 0;
+    // a tile that has its compute unit to itself may stage into all of its LDS
+    const bool alone = !h->batch_owned && mpass_waves(pl.nt1 * pl.nt2, T2) == 16;
+    pl.stage_p = mpass_bytes(h, r, T2, true, worst) <= (alone ? (size_t)h->lds_max : mpass_occupancy_budget(h)) ? 1 : 0;
     pl.slot = 16LL * r[0] + (long long)T2 * r[1] + N3 * r[2] + (long long)r[0] * r[1] * r[2];
     pl.lds = mpass_bytes(h, r, T2, pl.stage_p != 0, worst);
     pl.ok = true;
@@ -308,7 +310,8 @@ PassPlan plan_under(const tdb_ctx* h, const int* r, const PassPlan& base) {
       pl.ok = false;
       return pl;
     }
-    pl.stage_p = mpass_bytes(h, r, base.T2, true, false) <= mpass_occupancy_budget(h) ? 1 : 0;
+    const bool alone = !h->batch_owned && mpass_waves(base.nt1 * base.nt2, base.T2) == 16;
+    pl.stage_p = mpass_bytes(h, r, base.T2, true, false) <= (alone ? (size_t)h->lds_max : mpass_occupancy_budget(h)) ? 1 : 0;
     pl.lds = mpass_bytes(h, r, base.T2, pl.stage_p != 0, false);
     return pl;
   }

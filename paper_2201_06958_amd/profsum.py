@@ -33,12 +33,16 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 _GENERIC = ("fused_pass.hip", "fused.h", "tdb_common.h", "tdb_kernels.h", "device_util.h")
 _MATRIX = ("mfma_pass.hip", "fused.h", "tdb_common.h", "tdb_kernels.h")
 PASS_KERNELS = {
-    "k_mpass<float, 1>": _MATRIX,        # matrix-core pass, FP32 products, one stream
-    "kb_mpass<float, 1>": _MATRIX,       # the same for a batch of streams
-    "k_mpass<float, 2>": _MATRIX,        # BF16-split products
+    "k_mpass_w16<float, 1>": _MATRIX,    # matrix-core pass, FP32 products, one stream,
+                                         # one 16-wave tile per compute unit
+    "k_mpass_w16<float, 2>": _MATRIX,    # the same with BF16-split products
+    "k_mpass<float, 1>": _MATRIX,        # eight-wave tiles, two per compute unit
+    "k_mpass<float, 2>": _MATRIX,
+    "k_mpass_w4<float, 1>": _MATRIX,     # four-wave tiles (larger grids)
+    "kb_mpass<float, 1>": _MATRIX,       # four-wave tiles for a batch of streams
     "k_fpass<float, float>": _GENERIC,   # generic pass
 }
-PASS_KERNEL = "k_mpass<float, 1>"
+PASS_KERNEL = "k_mpass_w16<float, 1>"     # the pass of the reactive-flow workload
 
 
 def pass_source_digest(kernel: str = PASS_KERNEL) -> str:

@@ -52,7 +52,26 @@ def pass_kernel(request):
 
 
 CASES = [((37, 70, 5), (17, 9, 3)), ((50, 130, 7), (32, 20, 7)), ((21, 65, 8), (8, 32, 4)),
-         ((16, 64, 4), (16, 16, 4)), ((90, 40, 3), (24, 17, 2))]
+         ((16, 64, 4), (16, 16, 4)), ((90, 40, 3), (24, 17, 2)),
+         # one 16 x 32 tile per compute unit (sixteen waves): exact tiles with 16-byte
+         # fiber loads; ragged tiles in both modes, a 6-entry third mode, ranks past 16
+         ((256, 512, 8), (15, 15, 4)), ((250, 500, 6), (20, 18, 4))]
+
+
+def _mpass_waves(dims):
+    """Waves per tile the library's single-stream plan gives a matrix-core pass: T2
+    halves from 64 (not below 16) while there are fewer than 256 tiles of 16 x T2;
+    sixteen waves for at most 256 tiles with T2 >= 32, eight for at most 512."""
+    n1, n2 = dims[0], dims[1]
+    t2 = 64
+    while t2 > 16 and -(-n1 // 16) * -(-n2 // t2) < 256:
+        t2 //= 2
+    tiles = -(-n1 // 16) * -(-n2 // t2)
+    return 16 if tiles <= 256 and t2 >= 32 else (8 if tiles <= 512 else 4)
+
+
+def test_cases_cover_every_single_stream_tile_shape():
+    assert {_mpass_waves(d) for d, _ in CASES} == {8, 16}
 
 
 @pytest.mark.parametrize("pass_kernel,precision", [("mfma", "f32"), ("mfma", "bf16s"), ("generic", "f32")],
@@ -61,7 +80,7 @@ CASES = [((37, 70, 5), (17, 9, 3)), ((50, 130, 7), (32, 20, 7)), ((21, 65, 8), (
 def test_fixed_rank_random_streams(dims, ranks, pass_kernel, precision):
     """FP32 snapshots around a low-rank base with random weights, fixed ranks, started
     from the oracle's factors: reconstruction, core and eps against the oracle."""
-    _say(f"case mfma-pass {pass_kernel} {precision} dims {dims} ranks {ranks}")
+    _say(f"case mfma-pass {pass_kernel} {precision} dims {dims} ranks {ranks} waves {_mpass_waves(dims)}")
     rng = np.random.default_rng(sum(dims) + 7)
     w = []
     for n in dims:

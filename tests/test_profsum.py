@@ -16,18 +16,18 @@ def _counter_db(path, rows):
 
 def test_pmc_scaling_and_record(tmp_path):
     copy = "__amd_rocclr_copyBuffer"
-    kpass = "void tdb::k_mpass<float, 1>(tdb::FPassArgs)"
+    kpass = "void tdb::k_mpass_w16<float, 1>(tdb::FPassArgs)"
     # the copy of 1 MiB reads as 512 KiB on FETCH and 1024 KiB on WRITE -> scales 2 and 1
     f = tmp_path / "f.db"
     w = tmp_path / "w.db"
     _counter_db(f, [(copy, 4096, 512.0), (copy, 64, 1.0), (kpass, 1000, 100.0), (kpass, 1000, 110.0)])
     _counter_db(w, [(copy, 4096, 1024.0), (copy, 64, 1.0), (kpass, 1000, 20.0), (kpass, 1000, 20.0)])
     text, recs = profsum.pmc_text(str(f), str(w), "cmd f", "cmd w", 1024 * 1024)
-    rec = recs["k_mpass<float, 1>"]
+    rec = recs["k_mpass_w16<float, 1>"]
     assert abs(rec["read_scale"] - 2.0) < 1e-12 and abs(rec["write_scale"] - 1.0) < 1e-12
     assert abs(rec["read_bytes"] - 105.0 * 2 * 1024) < 1e-6
     assert abs(rec["write_bytes"] - 20.0 * 1024) < 1e-6
-    assert rec["source_digest"] == profsum.pass_source_digest("k_mpass<float, 1>")
+    assert rec["source_digest"] == profsum.pass_source_digest("k_mpass_w16<float, 1>")
     out = tmp_path / "traffic.txt"
     out.write_text(text)
     assert profsum.read_pass_traffic(str(out))["traffic_bytes"] == rec["traffic_bytes"]
@@ -44,10 +44,10 @@ def test_stats_text(tmp_path):
     con.execute("create table top_kernels (name text, total_calls int, total_duration real, "
                 "average real, percentage real)")
     con.executemany("insert into top_kernels values (?, ?, ?, ?, ?)",
-                    [("void tdb::k_mpass<float, 1>(tdb::FPassArgs)", 10, 450.0, 45.0, 60.0),
+                    [("void tdb::k_mpass_w16<float, 1>(tdb::FPassArgs)", 10, 450.0, 45.0, 60.0),
                      ("tdb::k_fqr(tdb::FQrArgs, CtrlState*)", 5, 300.0, 60.0, 40.0)])
     con.commit()
     con.close()
     text = profsum.stats_text(str(db), "the command")
-    assert "tdb::k_mpass<float, 1>" in text and "the command" in text
+    assert "tdb::k_mpass_w16<float, 1>" in text and "the command" in text
     assert text.index("k_mpass") < text.index("k_fqr")
