@@ -110,6 +110,8 @@ struct FErrArgs {
   const int* skip;           // the learned gate skips this pass (NULL: never)
   const int* would_skip;     // the gate's verdict, recorded in the controller state
   const float* yhat;         // the gate's prediction (log10 of the error)
+  CtrlState* mirror;         // pinned host copy of the controller state the final kernel
+                             // writes at its end (NULL: none)
 };
 
 // ev0/ev1 (may be null): events stamped by the dispatch itself at kernel start and end.

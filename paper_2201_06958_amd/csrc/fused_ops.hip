@@ -1169,9 +1169,24 @@ __device__ __forceinline__ void fused_decide(CtrlState* ctrl, const double* cons
 
 // One block: fixed-order sum of the error-pass partials, then the controller. A
 // decision other than none raises the hold flag for the host.
+// The controller state copied by the whole block into its pinned host mirror (the
+// host reads it once the step's event has completed).
+__device__ __forceinline__ void mirror_ctrl(CtrlState* dst, const CtrlState* src) {
+  static_assert(sizeof(CtrlState) % 8 == 0, "controller state copied in 8-byte words");
+  if (!dst) return;
+  __syncthreads();
+  const unsigned long long* s = reinterpret_cast<const unsigned long long*>(src);
+  unsigned long long* d = reinterpret_cast<unsigned long long*>(dst);
+  for (int i = threadIdx.x; i < (int)(sizeof(CtrlState) / 8); i += blockDim.x) d[i] = s[i];
+  __threadfence_system();
+}
+
 __global__ void __launch_bounds__(256) k_ferr_final(FErrArgs a, CtrlState* ctrl) {
   __shared__ double red[16];
-  if (ctrl->hold) return;
+  if (ctrl->hold) {
+    mirror_ctrl(a.mirror, ctrl);
+    return;
+  }
   const int nb = a.gx * a.gy;
   double s0 = 0.0, s1 = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) {
@@ -1187,6 +1202,7 @@ __global__ void __launch_bounds__(256) k_ferr_final(FErrArgs a, CtrlState* ctrl)
   __syncthreads();
   fused_decide(ctrl, a.G, a.rmax, a.skip, a.would_skip, a.yhat);
   if (threadIdx.x == 0) ctrl->hold = ctrl->decision != DEC_NONE ? 1 : 0;
+  mirror_ctrl(a.mirror, ctrl);
 }
 
 // ---------------------------------------------------------------- launchers

@@ -378,7 +378,9 @@ tdb_status setup(tdb_ctx* h, const tdb_config* cfg) {
   for (int m = 0; m < 2; ++m) {
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->ctrl_hb[m]), sizeof(CtrlState), hipHostMallocDefault);
     if (e != hipSuccess) { h->err = "hipHostMalloc failed"; return TDB_ENOMEM; }
-    HIPCHK(hipEventCreateWithFlags(&h->ev_ctrl[m], hipEventDisableTiming));
+    // no system-scope fence at the event: the host reads only the pinned mirror after
+    // it, which the final error kernel has written and fenced at system scope itself
+    HIPCHK(hipEventCreateWithFlags(&h->ev_ctrl[m], hipEventDisableTiming | hipEventDisableSystemFence));
   }
   h->ctrl_h = h->ctrl_hb[0];
   {
@@ -1287,8 +1289,10 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s, const TD* D = n
   // nothing; the host acts on the decision and enqueues this step again.
   const int m_new = h->pending ? 1 - h->mirror : h->mirror;
   auto enqueue = [&](StepArgs& Ax) -> tdb_status {
+    // the final error kernel writes the controller state into this step's pinned
+    // mirror itself (no separate copy on the stream)
+    Ax.ea.mirror = h->ctrl_hb[m_new];
     TRY((enqueue_fused_step<TD, T>(h, Ax, s)));
-    HIPCHK(hipMemcpyAsync(h->ctrl_hb[m_new], h->ctrl, sizeof(CtrlState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(h->ev_ctrl[m_new], s));
     return TDB_OK;
   };
