@@ -2,10 +2,11 @@
 // streams whose first two ranks are at most 32 and whose third mode has at most 8
 // entries (the variables / species / components mode of the target workloads).
 //
-// Tile: 16 rows of mode 1 x T2 (16, 32 or 64) rows of mode 2 x all N3 of mode 3;
-// 8 waves (4 for large grids and batches). The pseudo-inverses are staged in LDS with the tile when they fit. Z and D
-// are kept in LDS as [c][i2][i1] with the mode-1 index XOR-swizzled by the low bits of
-// i2, so that the operand reads of every product below fall in distinct LDS banks.
+// Tile: 16 rows of mode 1 x T2 (16, 32 or 64) rows of mode 2 x all N3 of mode 3, run
+// by 16, 8 or 4 waves (the kernels at the end of this file say when). The
+// pseudo-inverses are staged in LDS with the tile when they fit. Z and D are kept in
+// LDS as [c][i2][i1] with the mode-1 index XOR-swizzled by the low bits of i2, so that
+// the operand reads of every product below fall in distinct LDS banks.
 //   Z[c2][i1][i2] = sum_c D[i1][i2][c] B3[c][c2]        (VALU, from the loaded fibers)
 //   Y[c][i1][b]   = sum_i2 D[c][i1][i2] B2[i2][b]      (only if mode 3 is not full rank)
 //   F1[i1][b,c2]  = sum_i2 Z[c2][i1][i2] B2[i2][b]
