@@ -152,6 +152,61 @@ def _cpu_baseline(sp, start, budget_s=15.0, max_steps=60):
                       f"(FP64 numpy oracle, {el:.1f} s, snapshot generation excluded)"}
 
 
+def _scaling_sweep(sizes, steps, reps=5):
+    """TDB step against HOSVD as N grows (N x N x N cubes of the five-term analytic
+    stream, FP32 storage, ranks fixed at (5, 5, 5)): the cost of one fused TDB step
+    (pipelined ingest, averaged over `steps`) and of one HOSVD of a snapshot (Grams,
+    eigenpairs, core projection: what a per-snapshot HOSVD would cost; the median
+    over `reps` fresh initialisations), and the log-log slopes of both against S."""
+    import torch
+    from streams import analytic_cp5_spec
+    from paper_2201_06958_amd import Compressor
+    rows = []
+    for n in sizes:
+        sp = analytic_cp5_spec(n=n, steps=steps + 2)
+        snaps = [sp.snapshot(k, device="cuda").to(torch.float32) for k in range(steps + 2)]
+        torch.cuda.synchronize()
+        ts = []
+        for rep in range(reps + 1):
+            c = Compressor(sp.dims, sp.dt, rank_max=sp.rank_max, rank_init=sp.rank_init, weights=sp.weights,
+                           data_dtype="f32", precision="f32", adaptive=False, eps_th=1.0, snapshot_mode="borrow")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c.init(snaps[0])
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            if rep < reps:
+                c.close()
+        hosvd = sorted(ts[1:])[len(ts[1:]) // 2]      # the first initialisation loads code
+        c.ingest(snaps[1])
+        c.flush()
+        torch.cuda.synchronize()
+        c.profile_enable(True)
+        t0 = time.perf_counter()
+        for k in range(2, steps + 2):
+            c.ingest(snaps[k])
+        c.flush()
+        torch.cuda.synchronize()
+        step = (time.perf_counter() - t0) / steps
+        pj = c.profile_read("project")
+        c.close()
+        rows.append({"N": n, "S": n ** 3, "hosvd_ms": 1e3 * hosvd, "tdb_step_us": 1e6 * step,
+                     "hosvd_over_step": hosvd / step, "pass_launches": pj["launches"],
+                     "pass_avg_us": 1e3 * pj["total_ms"] / max(pj["launches"], 1)})
+        print(f"[bench] sweep N={n}: HOSVD {1e3 * hosvd:.3f} ms, TDB step {1e6 * step:.1f} us, "
+              f"stage pass {rows[-1]['pass_avg_us']:.1f} us x {rows[-1]['pass_launches']}",
+              file=sys.stderr, flush=True)
+
+    def slope(key):
+        xs = [math.log(r["S"]) for r in rows]
+        ys = [math.log(r[key]) for r in rows]
+        mx, my = sum(xs) / len(xs), sum(ys) / len(ys)
+        return sum((x - mx) * (y - my) for x, y in zip(xs, ys)) / sum((x - mx) ** 2 for x in xs)
+
+    return {"sweep": "tdb-vs-hosvd", "data": "synthetic", "stream": "analytic five-term, FP32, ranks (5,5,5)",
+            "rows": rows, "slope_tdb_step_vs_S": slope("tdb_step_us"), "slope_hosvd_vs_S": slope("hosvd_ms")}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,6 +222,10 @@ def main():
     ap.add_argument("--ensemble-steps", type=int, default=20)
     ap.add_argument("--bf16-steps", type=int, default=300,
                     help="steps of the BF16-split form of the headline stream (0 = skip)")
+    ap.add_argument("--scaling-sweep", type=str, default="",
+                    help="comma-separated cube sizes N: time a TDB step against an HOSVD of an "
+                         "N x N x N snapshot for each (prints one JSON line and nothing else)")
+    ap.add_argument("--sweep-steps", type=int, default=50, help="TDB steps timed per size of the sweep")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (a known-size reference for "
                          "hardware traffic counters)")
@@ -179,6 +238,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.scaling_sweep:
+        sizes = [int(x) for x in args.scaling_sweep.split(",") if x.strip()]
+        print(json.dumps(_scaling_sweep(sizes, max(args.sweep_steps, 10))), flush=True)
+        return
     sp, desc = _workload(args)
     print(f"[bench] generating {args.warmup + args.steps + 1} snapshots on the device", file=sys.stderr,
           flush=True)
