@@ -54,8 +54,9 @@ def pass_kernel(request):
 CASES = [((37, 70, 5), (17, 9, 3)), ((50, 130, 7), (32, 20, 7)), ((21, 65, 8), (8, 32, 4)),
          ((16, 64, 4), (16, 16, 4)), ((90, 40, 3), (24, 17, 2)),
          # one 16 x 32 tile per compute unit (sixteen waves): exact tiles with 16-byte
-         # fiber loads; ragged tiles in both modes, a 6-entry third mode, ranks past 16
-         ((256, 512, 8), (15, 15, 4)), ((250, 500, 6), (20, 18, 4))]
+         # fiber loads; ragged tiles in both modes, a 6-entry third mode, ranks past 16;
+         # 16 x 64 tiles (two fibers per loading thread) with a 4-entry third mode
+         ((256, 512, 8), (15, 15, 4)), ((250, 500, 6), (20, 18, 4)), ((512, 512, 4), (12, 10, 3))]
 
 
 def _mpass_waves(dims):
