@@ -182,13 +182,16 @@ tdb_status tdb_get_stats(tdb_handle h, tdb_stats* out);
 /* Free everything the handle owns. NULL-safe. */
 void tdb_destroy(tdb_handle h);
 
-/* Kernel timing for measurement tools. While enabled, the library brackets every
- * launch of a bulk pass with a pair of HIP events recorded on the caller's stream:
+/* Kernel timing for measurement tools. While enabled, the library brackets the
+ * launches of a bulk pass with a pair of HIP events recorded on the caller's stream:
  * TDB_PASS_PROJECT is one Heun stage's projection of the data difference (two per
- * snapshot), TDB_PASS_ERROR is the weighted error pass (one per snapshot). Enabling
- * clears the counters. tdb_profile_read synchronises the recorded events and
- * returns the number of launches, their summed duration in milliseconds and the
- * algorithmic bytes one launch must read (snapshot bytes it streams). */
+ * snapshot), TDB_PASS_ERROR is the weighted error pass (one per snapshot). on = 0
+ * turns timing off, on = 1 times every launch, on = k > 1 times the passes of every
+ * k-th step only (the events themselves cost time on the stream; the averages are
+ * over the timed launches). Enabling clears the counters. tdb_profile_read
+ * synchronises the recorded events and returns the number of timed launches, their
+ * summed duration in milliseconds and the algorithmic bytes one launch must read
+ * (snapshot bytes it streams). */
 enum { TDB_PASS_PROJECT = 0, TDB_PASS_ERROR = 1 };
 tdb_status tdb_profile_enable(tdb_handle h, int32_t on);
 tdb_status tdb_profile_read(tdb_handle h, int32_t pass, int64_t* launches, double* total_ms,

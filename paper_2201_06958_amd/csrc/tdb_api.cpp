@@ -101,8 +101,12 @@ struct tdb_ctx {
   CtrlState* ctrl_hb[2] = {};    // pinned mirrors of the controller state, one per step in flight
   hipEvent_t ev_ctrl[2] = {};
   int mirror = 0;                // mirror of the newest step
-  // optional pass timing (events recorded on the caller's stream)
+  // optional pass timing (events recorded on the caller's stream), of every step or of
+  // every prof_every-th step (prof_now: the step being enqueued is timed)
   bool prof = false;
+  int prof_every = 1;
+  long long prof_steps = 0;
+  bool prof_now = true;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[2];
 
@@ -788,7 +792,7 @@ struct PassTimer {
   hipEvent_t a = nullptr, b = nullptr;
   PassTimer(tdb_ctx* h_, int pass_, hipStream_t s_, bool by_dispatch_ = false)
       : h(h_), pass(pass_), s(s_), by_dispatch(by_dispatch_) {
-    if (!h->prof) return;
+    if (!h->prof || !h->prof_now) return;
     a = take_event(h);
     b = take_event(h);
     if (a && b && !by_dispatch) (void)hipEventRecord(a, s);
@@ -818,6 +822,7 @@ tdb_status euler_commit(tdb_ctx* h, hipStream_t s);
 // D (may be NULL): a given data derivative in place of (V1 - V_prev)/dt.
 template <typename TD, typename T>
 tdb_status ingest_impl(tdb_ctx* h, const TD* V1, hipStream_t s, const TD* D = nullptr) {
+  h->prof_now = h->prof_every <= 1 || h->prof_steps++ % h->prof_every == 0;
   // the projected operand: V1 - V_prev (scaled by 1/dt), or D itself
   const TD* Vp = D ? D : V1;
   const TD* V0 = D ? nullptr : static_cast<const TD*>(h->Vprev);
@@ -1215,6 +1220,7 @@ tdb_status finish_step(tdb_ctx* h, const TD* V1, hipStream_t s) {
 // The kernels of one fused step, enqueued on s (no host synchronisation).
 template <typename TD, typename T>
 tdb_status enqueue_fused_step(tdb_ctx* h, StepArgs& A, hipStream_t s) {
+  h->prof_now = h->prof_every <= 1 || h->prof_steps++ % h->prof_every == 0;
   if (!h->post_valid) TRY(fused_post<T>(h, s));
   const int stages = h->cfg.integrator == TDB_INT_EULER ? 1 : 2;
   for (int stage = 1; stage <= stages; ++stage) {
@@ -1957,6 +1963,9 @@ tdb_status tdb_profile_enable(tdb_handle h, int32_t on) {
     v.clear();
   }
   h->prof = on != 0;
+  h->prof_every = on > 1 ? on : 1;
+  h->prof_steps = 0;
+  h->prof_now = true;
   return TDB_OK;
 }
 

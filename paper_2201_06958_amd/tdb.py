@@ -285,8 +285,9 @@ class Compressor:
             "sigma16": [list(s.sigma[n][:SIGMA_K]) for n in range(p)],
         }
 
-    def profile_enable(self, on: bool = True):
-        self._check(self.lib.tdb_profile_enable(self.h, 1 if on else 0))
+    def profile_enable(self, on: bool = True, every: int = 1):
+        """Pass timing: every launch (every=1) or the passes of every `every`-th step."""
+        self._check(self.lib.tdb_profile_enable(self.h, max(1, int(every)) if on else 0))
 
     def profile_read(self, pass_name: str = "project") -> dict:
         n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()

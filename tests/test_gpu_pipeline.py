@@ -97,3 +97,25 @@ def test_pipelined_plume_fp32_matches_synchronous():
     torch.cuda.synchronize()
     ref = _run(sp, snaps, "copy", "f32", 1, rank_max=(32, 32, 8))
     _same(_run(sp, snaps, "borrow", "f32", 0, rank_max=(32, 32, 8)), ref)
+
+
+def test_pass_timing_sampled_every_kth_step():
+    """Pass timing of every k-th step: 2 projection launches and 1 error launch per
+    timed step, none in between; every step timed with k = 1."""
+    _say("case pass timing sampled")
+    sp = plume_spec(nx=64, ny=32, nv=8, steps=13)
+    snaps = [sp.snapshot(k, device="cuda") for k in range(13)]
+    from paper_2201_06958_amd import Compressor
+    for every, timed in ((1, 12), (4, 3), (5, 3)):
+        g = Compressor(sp.dims, sp.dt, rank_max=(16, 16, 8), weights=sp.weights, data_dtype="f32",
+                       precision="f32", adaptive=False, rank_init=(6, 6, 3), eps_th=1.0)
+        g.init(snaps[0])
+        g.profile_enable(True, every=every)
+        for k in range(1, 13):
+            g.ingest(snaps[k])
+        g.flush()
+        pj, er = g.profile_read("project"), g.profile_read("error")
+        assert pj["launches"] == 2 * timed, (every, pj)
+        assert er["launches"] == timed, (every, er)
+        assert pj["total_ms"] > 0.0
+        g.close()
