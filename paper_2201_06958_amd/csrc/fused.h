@@ -112,6 +112,8 @@ struct FErrArgs {
   const float* yhat;         // the gate's prediction (log10 of the error)
   CtrlState* mirror;         // pinned host copy of the controller state the final kernel
                              // writes at its end (NULL: none)
+  unsigned long long* seq;   // pinned word set to seq_val once the mirror is written
+  unsigned long long seq_val;
 };
 
 // ev0/ev1 (may be null): events stamped by the dispatch itself at kernel start and end.

@@ -1169,22 +1169,28 @@ __device__ __forceinline__ void fused_decide(CtrlState* ctrl, const double* cons
 
 // One block: fixed-order sum of the error-pass partials, then the controller. A
 // decision other than none raises the hold flag for the host.
-// The controller state copied by the whole block into its pinned host mirror (the
-// host reads it once the step's event has completed).
-__device__ __forceinline__ void mirror_ctrl(CtrlState* dst, const CtrlState* src) {
+// The controller state copied by the whole block into its pinned host mirror, then
+// the step's sequence number into its pinned word: the host spins on that word and
+// reads the mirror once it holds the number it expects.
+__device__ __forceinline__ void mirror_ctrl(const FErrArgs& a, const CtrlState* src) {
   static_assert(sizeof(CtrlState) % 8 == 0, "controller state copied in 8-byte words");
-  if (!dst) return;
+  if (!a.mirror) return;
   __syncthreads();
   const unsigned long long* s = reinterpret_cast<const unsigned long long*>(src);
-  unsigned long long* d = reinterpret_cast<unsigned long long*>(dst);
+  unsigned long long* d = reinterpret_cast<unsigned long long*>(a.mirror);
   for (int i = threadIdx.x; i < (int)(sizeof(CtrlState) / 8); i += blockDim.x) d[i] = s[i];
   __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0 && a.seq) {
+    *reinterpret_cast<volatile unsigned long long*>(a.seq) = a.seq_val;
+    __threadfence_system();
+  }
 }
 
 __global__ void __launch_bounds__(256) k_ferr_final(FErrArgs a, CtrlState* ctrl) {
   __shared__ double red[16];
   if (ctrl->hold) {
-    mirror_ctrl(a.mirror, ctrl);
+    mirror_ctrl(a, ctrl);
     return;
   }
   const int nb = a.gx * a.gy;
@@ -1202,7 +1208,7 @@ __global__ void __launch_bounds__(256) k_ferr_final(FErrArgs a, CtrlState* ctrl)
   __syncthreads();
   fused_decide(ctrl, a.G, a.rmax, a.skip, a.would_skip, a.yhat);
   if (threadIdx.x == 0) ctrl->hold = ctrl->decision != DEC_NONE ? 1 : 0;
-  mirror_ctrl(a.mirror, ctrl);
+  mirror_ctrl(a, ctrl);
 }
 
 // ---------------------------------------------------------------- launchers

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -99,7 +100,9 @@ struct tdb_ctx {
   const void* Vpend = nullptr;   // its snapshot (kept by the caller until the next call)
   hipStream_t pend_stream = nullptr;
   CtrlState* ctrl_hb[2] = {};    // pinned mirrors of the controller state, one per step in flight
-  hipEvent_t ev_ctrl[2] = {};
+  hipEvent_t ev_ctrl[2] = {};   // recorded on demand: another stream waits for a pending step
+  unsigned long long* seq_h = nullptr;   // pinned words the final error kernel sets per mirror
+  unsigned long long seq_next = 0, seq_want[2] = {0, 0};
   int mirror = 0;                // mirror of the newest step
   // optional pass timing (events recorded on the caller's stream), of every step or of
   // every prof_every-th step (prof_now: the step being enqueued is timed)
@@ -119,6 +122,7 @@ struct tdb_ctx {
     for (void* q : allocs) (void)hipFree(q);
     for (CtrlState* m : ctrl_hb)
       if (m) (void)hipHostFree(m);
+    if (seq_h) (void)hipHostFree(seq_h);
   }
 };
 
@@ -385,6 +389,11 @@ tdb_status setup(tdb_ctx* h, const tdb_config* cfg) {
     // no system-scope fence at the event: the host reads only the pinned mirror after
     // it, which the final error kernel has written and fenced at system scope itself
     HIPCHK(hipEventCreateWithFlags(&h->ev_ctrl[m], hipEventDisableTiming | hipEventDisableSystemFence));
+  }
+  {
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->seq_h), 2 * sizeof(unsigned long long), hipHostMallocDefault);
+    if (e != hipSuccess) { h->err = "hipHostMalloc failed"; return TDB_ENOMEM; }
+    h->seq_h[0] = h->seq_h[1] = 0ull;
   }
   h->ctrl_h = h->ctrl_hb[0];
   {
@@ -1247,13 +1256,35 @@ tdb_status enqueue_fused_step(tdb_ctx* h, StepArgs& A, hipStream_t s) {
   return TDB_OK;
 }
 
+// Waits until the final error kernel of the step enqueued with mirror m has written
+// that mirror (it sets the mirror's sequence word last). A step that has not reported
+// after a long spin is left to the runtime: the stream is synchronised, which also
+// reports a failed launch.
+tdb_status wait_mirror(tdb_ctx* h, int m) {
+  volatile unsigned long long* w = h->seq_h + m;
+  const unsigned long long want = h->seq_want[m];
+  for (long long it = 0; *w != want; ++it) {
+    if (it == (1ll << 24)) {
+      HIPCHK(hipStreamSynchronize(h->pend_stream));
+      if (*w != want) {
+        h->err = "the pending step did not report its controller state";
+        return TDB_EHIP;
+      }
+      break;
+    }
+    __builtin_ia32_pause();
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  return TDB_OK;
+}
+
 // Reads the decision of the newest enqueued step and acts on it (reinitialisation,
 // statistics). Waits only for that step's controller state.
 template <typename TD, typename T>
 tdb_status resolve_step(tdb_ctx* h) {
   if (!h->pending) return TDB_OK;
   h->pending = false;
-  HIPCHK(hipEventSynchronize(h->ev_ctrl[h->mirror]));
+  TRY(wait_mirror(h, h->mirror));
   h->ctrl_h = h->ctrl_hb[h->mirror];
   for (int n = 0; n < h->p; ++n) h->r[n] = h->ctrl_h->ranks[n];
   return finish_step<TD, T>(h, static_cast<const TD*>(h->Vpend), h->pend_stream);
@@ -1271,7 +1302,10 @@ template <typename TD, typename T>
 tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s, const TD* D = nullptr) {
   if (D) TRY(resolve_pending(h));
   // work enqueued earlier on another stream comes first
-  if (h->pending && h->pend_stream != s) HIPCHK(hipStreamWaitEvent(s, h->ev_ctrl[h->mirror], 0));
+  if (h->pending && h->pend_stream != s) {
+    HIPCHK(hipEventRecord(h->ev_ctrl[h->mirror], h->pend_stream));
+    HIPCHK(hipStreamWaitEvent(s, h->ev_ctrl[h->mirror], 0));
+  }
   StepArgs A;
   tdb_status bs = build_step_args(h, h->r, V1, h->Vprev, A, D);
   if (bs == TDB_EUNSUPPORTED) {
@@ -1298,14 +1332,16 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s, const TD* D = n
     // the final error kernel writes the controller state into this step's pinned
     // mirror itself (no separate copy on the stream)
     Ax.ea.mirror = h->ctrl_hb[m_new];
+    Ax.ea.seq = h->seq_h + m_new;
+    Ax.ea.seq_val = ++h->seq_next;
+    h->seq_want[m_new] = h->seq_next;
     TRY((enqueue_fused_step<TD, T>(h, Ax, s)));
-    HIPCHK(hipEventRecord(h->ev_ctrl[m_new], s));
     return TDB_OK;
   };
   TRY(enqueue(A));
   if (h->pending) {
     h->pending = false;
-    HIPCHK(hipEventSynchronize(h->ev_ctrl[h->mirror]));
+    TRY(wait_mirror(h, h->mirror));
     h->ctrl_h = h->ctrl_hb[h->mirror];
     for (int n = 0; n < h->p; ++n) h->r[n] = h->ctrl_h->ranks[n];
     const bool acted = h->ctrl_h->decision != DEC_NONE;
