@@ -234,7 +234,7 @@ def main():
                          "hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (the design notes, "
               "'How the path would shard').", file=sys.stderr)
         sys.exit(2)
     import torch

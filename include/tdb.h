@@ -43,7 +43,7 @@ enum {
   TDB_EHIP = 3,          /* a HIP runtime call failed                             */
   TDB_ESTATE = 4,        /* call out of order (e.g. ingest before init)           */
   TDB_ENUMERIC = 5,      /* non-finite data, or an unrecoverable singular core    */
-  TDB_EUNSUPPORTED = 6   /* a valid request this build does not implement         */
+  TDB_EUNSUPPORTED = 6   /* a valid request the library does not implement        */
 };
 
 enum { TDB_F64 = 0, TDB_F32 = 1 };                      /* snapshot storage type  */
@@ -54,18 +54,18 @@ enum {                                                   /* controller events   
   TDB_EV_NONE = 0, TDB_EV_REINIT = 1, TDB_EV_ADD = 2, TDB_EV_REMOVE = 3, TDB_EV_NUMERIC = 4
 };
 
-#define TDB_MAX_ORDER 8       /* ABI array size; this build supports 2 <= p <= 4   */
+#define TDB_MAX_ORDER 8       /* ABI array size; the library supports 2 <= p <= 4 */
 #define TDB_SIGMA_K 16        /* leading core singular values reported per mode    */
 
 typedef struct tdb_ctx* tdb_handle;
 
 /* Configuration of one stream (Sec. 2.3, 2.5). Copied at init. */
 typedef struct {
-  int32_t order;                       /* p, 2..4 in this build                        */
+  int32_t order;                       /* p, 2..4 in this library                      */
   int64_t dims[TDB_MAX_ORDER];         /* N_n; a mode may be a flattened group of axes */
   int32_t rank_init[TDB_MAX_ORDER];    /* all 0 => chosen by the rank rule at init     */
   int32_t rank_max[TDB_MAX_ORDER];     /* caps; clamped to N_n and to the product of
-                                          the other caps; each <= 64 in this build     */
+                                          the other caps; each <= 64 in this library   */
   const double* weights[TDB_MAX_ORDER];/* host arrays of N_n positive quadrature
                                           weights (diagonal W^(n)); NULL => 1/N_n      */
   double dt;                           /* uniform snapshot spacing, > 0                */

@@ -164,15 +164,15 @@ tdb_status dallocT(tdb_ctx* h, T** out, size_t count) {
 tdb_status validate(const tdb_config* c, std::string& msg) {
   if (!c) { msg = "config is NULL"; return TDB_EINVAL; }
   if (c->order < 2 || c->order > TDB_MAX_ORDER) { msg = "order must be in [2, 8]"; return TDB_EINVAL; }
-  if (c->order > TDB_P) { msg = "this build supports tensor order 2..4"; return TDB_EUNSUPPORTED; }
+  if (c->order > TDB_P) { msg = "the library supports tensor order 2..4"; return TDB_EUNSUPPORTED; }
   for (int n = 0; n < c->order; ++n) {
     if (c->dims[n] < 1) { msg = "dims must be positive"; return TDB_EINVAL; }
     if (c->rank_max[n] < 1) { msg = "rank_max must be positive"; return TDB_EINVAL; }
     if (c->rank_max[n] > TDB_RCAP && c->rank_max[n] < c->dims[n]) {
-      msg = "rank_max above 64 is not supported by this build";
+      msg = "rank_max above 64 is not supported by the library";
       return TDB_EUNSUPPORTED;
     }
-    if (c->dims[n] > TDB_NEIG) { msg = "mode sizes above 512 are not supported by this build"; return TDB_EUNSUPPORTED; }
+    if (c->dims[n] > TDB_NEIG) { msg = "mode sizes above 512 are not supported by the library"; return TDB_EUNSUPPORTED; }
     if (c->rank_init[n] < 0) { msg = "rank_init must be >= 0"; return TDB_EINVAL; }
     if (c->weights[n]) {
       for (long long i = 0; i < c->dims[n]; ++i)
