@@ -78,7 +78,8 @@ typedef struct {
                                           and the products hi*hi + hi*lo + lo*hi
                                           accumulated in FP32, where the shapes allow
                                           (order 3, N_3 <= 8, r_1, r_2 <= 32), else
-                                          as F32; the error pass in FP32            */
+                                          as F32 (tdb_stats.precision_used reports
+                                          what each step ran); the error pass in FP32 */
   int32_t path;                        /* TDB_PATH_*: AUTO picks FUSED where supported */
   int32_t adaptive;                    /* 0 = fixed ranks (eps is still reported)      */
   int32_t snapshot_mode;               /* TDB_COPY: the library keeps its own copy of
@@ -117,16 +118,28 @@ typedef struct {
                                           pass of this step (eps is then NaN)          */
   int32_t would_skip;                  /* the gate's verdict, also when it observes    */
   double eps_pred;                     /* the gate's predicted eps (NaN without one)   */
+  int32_t precision_used;              /* TDB_PREC_* the last step's stage pass ran in
+                                          (-1 before the first step)                   */
+  int32_t path_used;                   /* TDB_PATH_FUSED or TDB_PATH_PLAIN of the last
+                                          step (0 before the first step)               */
+  int64_t fused_steps, plain_steps;    /* steps taken on each path since init (a fused
+                                          stream falls back to the plain path for a step
+                                          whose stage pass does not fit the LDS)       */
+  int64_t n_nonfinite;                 /* steps not applied for NaN/Inf data           */
 } tdb_stats;
 
 /* Initialise from the first snapshot by a weighted HOSVD (Sec. 2.3). V0_dev: device
  * tensor in data_dtype. Allocates all device workspace (sized by the caps). On
- * success *out owns it; on failure *out is NULL. */
+ * success *out owns it; on failure *out is NULL (TDB_ENUMERIC when V0 holds NaN or
+ * Inf). */
 tdb_status tdb_init(const tdb_config* cfg, const void* V0_dev, void* stream, tdb_handle* out);
 
 /* Initialise from given factors instead of a HOSVD (parity and restart use).
  * ranks[n] gives the core shape; C_host is the C-contiguous r_1 x ... x r_p core;
- * U_host[n] is the row-major N_n x r_n basis, expected W-orthonormal. */
+ * U_host[n] is the row-major N_n x r_n basis, expected W-orthonormal. TDB_ENUMERIC
+ * for NaN or Inf in V0 or the factors. A rank-deficient core is accepted: the first
+ * step then finds its pseudo-inverse singular (Sec. 2.2) and restarts from a HOSVD
+ * of that step's snapshot (event TDB_EV_NUMERIC). */
 tdb_status tdb_init_from_factors(const tdb_config* cfg, const void* V0_dev,
                                  const int32_t* ranks, const double* C_host,
                                  const double* const* U_host, void* stream, tdb_handle* out);
@@ -135,6 +148,13 @@ tdb_status tdb_init_from_factors(const tdb_config* cfg, const void* V0_dev,
  * two Heun stages of eqs. (Corecont)/(basecont), W-orthonormal QR with the factor
  * folded into the core, weighted error pass, controller (and HOSVD reinit when it
  * fires).
+ * Non-finite data: when the difference quotient holds NaN or Inf (the first stage's
+ * core derivative is then not finite, which the device checks), the step is not
+ * applied: core, bases, ranks, step count and statistics stay those of the last
+ * finite step and TDB_ENUMERIC is returned (by the call that reads the step, see
+ * below). The snapshot still becomes the previous snapshot, so the next step's
+ * difference quotient is also non-finite and is not applied either; the stream goes
+ * on from the snapshot after that.
  * With TDB_COPY snapshots it returns after one small read-back of the controller
  * result, so the step is complete. With TDB_BORROW snapshots on the fused third-order
  * path the call is pipelined: it enqueues this step on `stream`, then reads the
@@ -156,12 +176,14 @@ tdb_status tdb_ingest_snapshot(tdb_handle h, const void* V_dev, void* stream);
  * difference quotient is) instead of (V_{k+1} - V_k)/dt. V_dev still serves the
  * weighted error and becomes the previous snapshot of the next difference quotient.
  * The step runs synchronously (any pipelined step is resolved first): D_dev is read
- * by this call only. TDB_EINVAL for NULL pointers; otherwise as tdb_ingest_snapshot. */
+ * by this call only. TDB_EINVAL for NULL pointers; TDB_ENUMERIC, with nothing
+ * changed, when V_dev or D_dev holds NaN or Inf; otherwise as tdb_ingest_snapshot. */
 tdb_status tdb_ingest_with_derivative(tdb_handle h, const void* V_dev, const void* D_dev, void* stream);
 
 /* Read the newest enqueued step's decision and act on it (see tdb_ingest_snapshot);
  * afterwards every step is complete and the statistics are those of the last one.
- * No effect when nothing is pending. TDB_ENUMERIC if that step's error is not finite. */
+ * No effect when nothing is pending. TDB_ENUMERIC if that step was not applied for
+ * non-finite data. */
 tdb_status tdb_flush(tdb_handle h);
 
 /* Copy the current ranks, core and bases to the host. ranks_out: TDB_MAX_ORDER ints
@@ -170,13 +192,25 @@ tdb_status tdb_flush(tdb_handle h);
 tdb_status tdb_get_core_and_bases(tdb_handle h, int32_t rotate, int32_t* ranks_out,
                                   double* C_host, double* const* U_host);
 
-/* Write the dense reconstruction C x_1 U_1 ... x_p U_p into out_dev (data_dtype). */
+/* Write the dense reconstruction of eq. (reconstructed) (Sec. 2.2), the Tucker product
+ * C x_1 U_1 ... x_p U_p, into out_dev: S values in data_dtype, C-contiguous over
+ * (N_1, ..., N_p), caller-owned device memory. Enqueued on `stream` after any
+ * pending step is resolved. TDB_EINVAL for a NULL out_dev. */
 tdb_status tdb_reconstruct(tdb_handle h, void* out_dev, void* stream);
 
-/* Change the thresholds; applies from the next ingest. */
+/* Change the error threshold eps_th of eq. (error) and the captured-energy
+ * percentage gamma_th of eq. (percentage) (Sec. 2.5: mode addition when the error
+ * exceeds eps_th, removal and rank choice within the budget); gamma_th <= 0 uses
+ * the budget (eps_th/2)^2. Applies from the next ingest; a stream in the state
+ * where the caps cannot meet the threshold keeps its raised trigger until a
+ * reinitialisation meets it. TDB_EINVAL unless eps_th > 0 and gamma_th < 100. */
 tdb_status tdb_set_threshold(tdb_handle h, double eps_th, double gamma_th);
 
-/* Stats of the last step (or of init). */
+/* Statistics of the last applied step (or of init) into *out: the weighted error
+ * eq. (error) and ||V||_W (Sec. 2.5), the ranks and event, the leading singular values
+ * of the core unfoldings (Sec. 2.4, the diagonal of eq. (rot)), the compression ratio
+ * CR and its time-weighted mean (Sec. 2.6), event counts, the gate's fields and the
+ * path and precision the last step ran in. Resolves a pending step first. */
 tdb_status tdb_get_stats(tdb_handle h, tdb_stats* out);
 
 /* Free everything the handle owns. NULL-safe. */
@@ -270,6 +304,20 @@ tdb_status tdb_gate_train_step(tdb_gate g, const float* X_dev, const float* t_de
 void tdb_gate_destroy(tdb_gate g);
 const char* tdb_gate_last_error(tdb_gate g);
 tdb_status tdb_batch_gate_attach(tdb_batch b, tdb_gate g, const float* feat_mean_std_host, int32_t mode);
+
+/* The gate on a single stream (the fused third-order path; batch members use
+ * tdb_batch_gate_attach). params_host: n_params == TDB_GATE_PARAMS FP32 values in the
+ * layout above; feat_mean_std_host: 384 means then 384 standard deviations. Both are
+ * copied into the handle (no trainer needs to stay alive). mode as for batches:
+ * TDB_GATE_ACTIVE skips the exact error pass of eq. (error) (Sec. 2.5) when the
+ * prediction allows (that step's eps is then NaN and it takes no add/remove
+ * decision), TDB_GATE_SHADOW only reports the verdict, TDB_GATE_RECORD forms the
+ * core singular values every step (params may be NULL), TDB_GATE_OFF detaches.
+ * Resolves a pending step first. TDB_EUNSUPPORTED on the plain path; TDB_ESTATE for
+ * a batch member; TDB_EINVAL for a wrong count, non-finite parameters or
+ * non-positive standard deviations. */
+tdb_status tdb_gate_load(tdb_handle h, const float* params_host, const float* feat_mean_std_host, int32_t n_params,
+                         int32_t mode);
 
 /* Layout check for language bindings: writes sizeof(tdb_config) and sizeof(tdb_stats)
  * (either pointer may be NULL). Needs no device. */

@@ -157,12 +157,26 @@ static __device__ void jacobi_wave(double* A, int rn, int* pairs) {
 // window. Returns true when the removal test has to run, which needs the singular
 // values of the core unfoldings (c->sigma).
 static __device__ bool controller_pre(CtrlState* c) {
-  c->eps = sqrt(fmax(c->eps2, 0.0));
-  c->nu = sqrt(fmax(c->nu2, 0.0));
+  c->eps = sqrt_sum_sq(c->eps2);
+  c->nu = sqrt_sum_sq(c->nu2);
   c->event = 0;
   c->eps_after = __builtin_nan("");
   c->rank_changed = 0;
-  if (c->numeric & 3) { c->decision = DEC_NUMERIC; return false; }
+  // a numerical event (the state was kept) comes before an error that is not finite
+  // only because of it; non-finite data come first
+  if (!(c->numeric & NUM_NONFINITE) && (c->numeric & (NUM_CORE | NUM_BASIS))) {
+    c->decision = DEC_NUMERIC;
+    return false;
+  }
+  if ((c->numeric & NUM_NONFINITE) || !isfinite(c->eps2) || !isfinite(c->nu2)) {
+    // non-finite data: the step was not applied; the flags its stages raised on the
+    // non-finite values go with it (a failure of the next step's core Gram, found on
+    // the kept state, stays for that step)
+    c->numeric &= NUM_NEXT;
+    c->eps = __builtin_nan("");
+    c->decision = DEC_NONFINITE;
+    return false;
+  }
   if (!c->adaptive) { c->decision = DEC_NONE; return false; }
   const double eps = c->eps;
   if (eps > c->eps_trig) { c->decision = DEC_ADD; return false; }

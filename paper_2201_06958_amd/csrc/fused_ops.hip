@@ -62,7 +62,11 @@ __device__ __forceinline__ void freduce_body(const FReduceArgs& a, int stage, Ct
   if (ctrl->hold || (stage == 2 && ctrl->numeric)) return;
   // A singular core found while preparing this step (bit 4, set by k_fpost) belongs
   // to this step's first stage, like the failure of its pseudo-inverse would.
-  if (stage == 1 && bx == 0 && threadIdx.x == 0 && (ctrl->numeric & 4)) ctrl->numeric = 1;
+  // (atomics: other blocks may be raising NUM_NONFINITE meanwhile)
+  if (stage == 1 && bx == 0 && threadIdx.x == 0 && (ctrl->numeric & NUM_NEXT)) {
+    atomicOr(&ctrl->numeric, NUM_CORE);
+    atomicAnd(&ctrl->numeric, ~NUM_NEXT);
+  }
   const T* part = static_cast<const T*>(a.part);
   const long long nH1 = a.need_h1 ? (long long)a.N1 * a.r1 : 0;
   const long long nH2 = a.need_h2 ? (long long)a.N2 * a.r2 : 0;
@@ -127,6 +131,9 @@ __device__ __forceinline__ void freduce_body(const FReduceArgs& a, int stage, Ct
     } else {
       const double cd = s * inv_dt;
       if (stage == 1) {
+        // every entry of the data derivative reaches every entry of C_dot, so NaN or
+        // Inf anywhere in the snapshots shows here; the step is then not applied
+        if (!isfinite(cd)) atomicOr(&ctrl->numeric, NUM_NONFINITE);
         a.kC[q] = cd;
         a.Cs[q] = a.C0[q] + a.dt * cd;
       } else {
@@ -753,11 +760,15 @@ __device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, 
     double* Lil = T3 + (long long)r1 * r2 * N3;         // rq*rq
     double* Ul = Lil + rq * rq;                         // POST_CH * rq (raw rows)
     double* Un = Ul + POST_CH * rq;                     // POST_CH * rq (normalised rows)
-    const bool norm = a.Li[0] != nullptr && !ctrl->numeric;
+    // a step that was not applied (numerical event or non-finite data) skipped the QR:
+    // U_n needs no normalisation and T3 is formed here from the kept state. NUM_NEXT
+    // is left out: this kernel's own mode blocks may be raising it meanwhile.
+    const bool kept = (ctrl->numeric & ~NUM_NEXT) != 0;
+    const bool norm = a.Li[0] != nullptr && !kept;
     const long long per2 = (N2 + a.eblocks - 1) / a.eblocks;
     const bool erows = (long long)eb * per2 < N2;
     if (erows) {
-      if (a.T3) {
+      if (a.T3 && !kept) {
         g2l(T3, a.T3, r1 * r2 * (int)N3);
       } else {
         for (long long t = threadIdx.x; t < (long long)r1 * r2 * N3; t += blockDim.x) {
@@ -1135,7 +1146,7 @@ __device__ __forceinline__ void fused_decide(CtrlState* ctrl, const double* cons
     ctrl->gated = (skip && *skip) ? 1 : 0;
     ctrl->would_skip = would_skip ? *would_skip : 0;
     ctrl->eps_pred = (yhat && isfinite(*yhat)) ? pow(10.0, (double)*yhat) : __builtin_nan("");
-    if (ctrl->gated) {
+    if (ctrl->gated && !(ctrl->numeric & NUM_NONFINITE)) {
       // no exact error this step: no decision, and the slope window starts over so that
       // a removal always rests on consecutive exact errors
       ctrl->eps = __builtin_nan("");
@@ -1207,7 +1218,8 @@ __global__ void __launch_bounds__(256) k_ferr_final(FErrArgs a, CtrlState* ctrl)
   }
   __syncthreads();
   fused_decide(ctrl, a.G, a.rmax, a.skip, a.would_skip, a.yhat);
-  if (threadIdx.x == 0) ctrl->hold = ctrl->decision != DEC_NONE ? 1 : 0;
+  // a discarded step (non-finite data) needs nothing from the host before the next one
+  if (threadIdx.x == 0) ctrl->hold = (ctrl->decision != DEC_NONE && ctrl->decision != DEC_NONFINITE) ? 1 : 0;
   mirror_ctrl(a, ctrl);
 }
 

@@ -163,6 +163,18 @@ __global__ void __launch_bounds__(128) kb_gate_infer(GateStepArgs g) {
   __shared__ int runs;
   const int s = blockIdx.x;
   const CtrlState* c = g.ctrl[s];
+  // a held step does not run at all; a step with non-finite data is not applied, so
+  // its singular values (those of the kept state) join no history and the exact pass
+  // runs (and reports the non-finite data)
+  if (c->hold) return;
+  if (c->numeric & NUM_NONFINITE) {
+    if (threadIdx.x == 0) {
+      g.yhat[s] = __builtin_nanf("");
+      g.skip[s] = 0;
+      g.would_skip[s] = 0;
+    }
+    return;
+  }
   float* hist = g.hist + (long long)s * GATE_W * GATE_ROW;
   const int cnt = g.hcount[s];
   const int slot = cnt % GATE_W;

@@ -251,9 +251,9 @@ __global__ void __launch_bounds__(256) k_rank_select(SelectArgs a, CtrlState* c)
   } else if (a.mode == DEC_ADD) {
     if (threadIdx.x == 0) for (int n = 0; n < p; ++n) r[n] = cur[n];
     __syncthreads();
-    const double e2 = fmax(nu2h - sub_energy(a.Cmax, a.caps, r, p, red), 0.0);
+    const double e2 = nu2h - sub_energy(a.Cmax, a.caps, r, p, red);
     event = EV_REINIT;
-    if (sqrt(e2) > c->eps_th) {
+    if (!(sqrt_sum_sq(e2) <= c->eps_th)) {
       greedy(a, r, nu2h, B, red, &stop);
       bool same = true;
       for (int n = 0; n < p; ++n) same = same && r[n] == cur[n];
@@ -309,15 +309,15 @@ __global__ void __launch_bounds__(256) k_rank_select(SelectArgs a, CtrlState* c)
     const long long tot_u = a.N[n] * a.ldU[n];
     for (long long t = threadIdx.x; t < tot_u; t += blockDim.x) a.U0[n][t] = a.Umax[n][t];
   }
-  const double e2 = fmax(nu2h - sub_energy(a.Cmax, a.caps, r, p, red), 0.0);
+  const double e2 = nu2h - sub_energy(a.Cmax, a.caps, r, p, red);
   if (threadIdx.x == 0) {
     int changed = 0;
     for (int n = 0; n < p; ++n) { changed |= (r[n] != cur[n]); c->ranks[n] = r[n]; }
     c->rank_changed = changed;
-    const double er = sqrt(e2);
+    const double er = sqrt_sum_sq(e2);   // NaN stays NaN (non-finite data)
     if (a.mode == DEC_INIT) {
       c->eps = er;
-      c->nu = sqrt(nu2h);
+      c->nu = sqrt_sum_sq(nu2h);
       c->eps_after = __builtin_nan("");
       c->unmet = 0;
       c->eps_trig = c->eps_th;

@@ -160,6 +160,8 @@ __global__ void __launch_bounds__(TDB_BLOCK) k_rhs_stage(RhsArgs a, CtrlState* c
     for (long long t = blockIdx.y * blockDim.x + threadIdx.x; t < nc; t += (long long)gridDim.y * blockDim.x) {
       const double cd = a.Cdot[t] * inv_dt;
       if (a.stage == 1) {
+        // NaN or Inf anywhere in the data derivative reaches every entry of C_dot
+        if (!isfinite(cd)) atomicOr(&ctrl->numeric, NUM_NONFINITE);
         a.kC[t] = cd;
         a.Cs[t] = a.C0[t] + a.dt * cd;
       } else {

@@ -165,6 +165,28 @@ hipError_t launch_err_final(const double* partials, int nblocks, CtrlState* ctrl
   return hipGetLastError();
 }
 
+__global__ void k_flag_clear(int* flag) { *flag = 0; }
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_nonfinite(const T* __restrict__ x, long long n, int* flag) {
+  int bad = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    bad |= isfinite(x[i]) ? 0 : 1;
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+template <typename T>
+hipError_t launch_nonfinite_check(const T* x, long long n, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(1), 0, s, flag);
+  long long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL((k_nonfinite<T>), dim3((unsigned)blocks), dim3(256), 0, s, x, n, flag);
+  return hipGetLastError();
+}
+template hipError_t launch_nonfinite_check<float>(const float*, long long, int*, hipStream_t);
+template hipError_t launch_nonfinite_check<double>(const double*, long long, int*, hipStream_t);
+
 template <typename TI, typename TO>
 __global__ void k_convert(const TI* __restrict__ in, TO* __restrict__ out, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;

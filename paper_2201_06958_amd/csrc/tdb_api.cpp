@@ -90,6 +90,16 @@ struct tdb_ctx {
   unsigned* counters = nullptr;
   int ferr_gx = 1, ferr_gy = 1;
   long long fused_steps = 0, plain_steps = 0;
+  long long n_nonfinite = 0;     // steps discarded for non-finite data
+  int last_prec = -1;            // TDB_PREC_* the last step's stage pass ran in
+  int last_path = 0;             // TDB_PATH_PLAIN or TDB_PATH_FUSED of the last step
+  int* d_flag = nullptr;         // device word of the non-finite checks
+  // learned gate of a single stream (fused path): the handle's own copy of the
+  // parameters and feature statistics, the singular-value history and the verdicts
+  int gate_mode = 0;             // GATE_*
+  float *g_params = nullptr, *g_mean = nullptr, *g_std = nullptr, *g_hist = nullptr, *g_yhat = nullptr;
+  int *g_hcount = nullptr, *g_skip = nullptr, *g_would = nullptr;
+  CtrlState** g_ctab = nullptr;  // device array holding ctrl (the inference kernel takes a table)
   bool batch_owned = false;      // lives inside a tdb_batch
   bool sigma_stale = false;      // stats.sigma not refreshed since the last batched step
   // pipelined ingest (fused path, borrowed snapshots): each call enqueues its step and
@@ -130,6 +140,7 @@ struct tdb_ctx {
   do {                                                                                 \
     hipError_t e_ = (expr);                                                            \
     if (e_ != hipSuccess) {                                                            \
+      (void)hipGetLastError(); /* clear it, or the next launch check reports it */   \
       h->err = std::string(#expr) + ": " + hipGetErrorString(e_);                      \
       return TDB_EHIP;                                                                 \
     }                                                                                  \
@@ -382,6 +393,7 @@ tdb_status setup(tdb_ctx* h, const tdb_config* cfg) {
   TRY(dalloc(h, &h->wsA, (size_t)h->S * h->celt));
   TRY(dalloc(h, &h->wsB, (size_t)h->S * h->celt));
   TRY(dallocT(h, &h->err_part, 2 * (size_t)h->err_blocks));
+  TRY(dallocT(h, &h->d_flag, 1));
   TRY(dalloc(h, reinterpret_cast<void**>(&h->ctrl), sizeof(CtrlState)));
   for (int m = 0; m < 2; ++m) {
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->ctrl_hb[m]), sizeof(CtrlState), hipHostMallocDefault);
@@ -776,6 +788,11 @@ void fill_stats(tdb_ctx* h, bool initial) {
   st.gated = initial ? 0 : c.gated;
   st.would_skip = initial ? 0 : c.would_skip;
   st.eps_pred = initial ? NAN : c.eps_pred;
+  st.precision_used = h->last_prec;
+  st.path_used = h->last_path;
+  st.fused_steps = h->fused_steps;
+  st.plain_steps = h->plain_steps;
+  st.n_nonfinite = h->n_nonfinite;
 }
 
 hipEvent_t take_event(tdb_ctx* h) {
@@ -824,6 +841,34 @@ tdb_status keep_previous(tdb_ctx* h, const TD* V, hipStream_t s) {
     h->Vprev = V;
   }
   return TDB_OK;
+}
+
+// *bad = whether any of the S values at x is NaN or infinite (synchronises s).
+template <typename TD>
+tdb_status has_nonfinite(tdb_ctx* h, const TD* x, hipStream_t s, bool* bad) {
+  HIPCHK(launch_nonfinite_check<TD>(x, h->S, h->d_flag, s));
+  int v = 0;
+  HIPCHK(hipMemcpyAsync(&v, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *bad = v != 0;
+  return TDB_OK;
+}
+
+tdb_status has_nonfinite_any(tdb_ctx* h, const void* x, hipStream_t s, bool* bad) {
+  if (h->data32) return has_nonfinite<float>(h, static_cast<const float*>(x), s, bad);
+  return has_nonfinite<double>(h, static_cast<const double*>(x), s, bad);
+}
+
+// A step whose data derivative held NaN or Inf was not applied on the device (the
+// first stage's core derivative raised the flag, the later kernels kept the state):
+// the snapshot still becomes the previous one, nothing else of the stream changes.
+template <typename TD>
+tdb_status discard_step(tdb_ctx* h, const TD* V1, hipStream_t s) {
+  TRY(keep_previous<TD>(h, V1, s));
+  h->n_nonfinite += 1;
+  h->err = "non-finite values (NaN or Inf) in the data derivative: the step was not applied (core, bases and "
+           "statistics are those of the last finite step)";
+  return TDB_ENUMERIC;
 }
 
 tdb_status euler_commit(tdb_ctx* h, hipStream_t s);
@@ -894,9 +939,13 @@ tdb_status ingest_impl(tdb_ctx* h, const TD* V1, hipStream_t s, const TD* D = nu
   }
   HIPCHK(launch_controller(h->ctrl, s));
   TRY(pull_ctrl(h, s));
+  h->last_path = TDB_PATH_PLAIN;
+  h->last_prec = h->f32 ? TDB_PREC_F32 : TDB_PREC_F64;
+  h->plain_steps += 1;
+  const int dec = h->ctrl_h->decision;
+  if (dec == DEC_NONFINITE) return discard_step<TD>(h, V1, s);
   h->step += 1;
   h->t_now = h->step * h->cfg.dt;
-  const int dec = h->ctrl_h->decision;
   if (dec != DEC_NONE) {
     TRY(hosvd_select<TD>(h, V1, dec, s));
     TRY(pull_ctrl(h, s));
@@ -1062,7 +1111,8 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
 
   FFinishArgs ga{};
   bool cil = false;
-  ga.m_inline = rl == h->r ? 1 : 0;   // a single stream forms M_n in the row blocks
+  // a single stream forms M_n in the row blocks when their LDS holds C_dot and the P_n
+  ga.m_inline = (rl == h->r && small_lds(h, rl, &cil, true) <= (size_t)h->lds_max) ? 1 : 0;
   A.lds_fin = small_lds(h, rl, &cil, ga.m_inline != 0);
   ga.core_in_lds = cil ? 1 : 0;
   ga.rmax = max_rank_of(rl, 3);
@@ -1172,6 +1222,13 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
   for (int n = 0; n < 3; ++n) ea.G[n] = h->Gsave[n];
   ea.rmax = max_rank_of(rl, 3);
   A.blocks_err = h->ferr_gx * h->ferr_gy;
+  // every small kernel's LDS must fit, or the step goes to the plain path
+  const size_t lmax = (size_t)h->lds_max;
+  if (A.lds_fin > lmax || (!ga.m_inline && A.lds_mprep > lmax) || A.lds_qr > lmax || A.lds_post > lmax ||
+      ferr_final_lds(ea.rmax) > lmax) {
+    h->err = "the fused step's small kernels do not fit in LDS at these ranks";
+    return TDB_EUNSUPPORTED;
+  }
   return TDB_OK;
 }
 
@@ -1209,14 +1266,17 @@ tdb_status fused_post(tdb_ctx* h, hipStream_t s) {
 // keep the snapshot for the next difference quotient, record the statistics.
 template <typename TD, typename T>
 tdb_status finish_step(tdb_ctx* h, const TD* V1, hipStream_t s) {
+  const int dec = h->ctrl_h->decision;
+  if (dec == DEC_NONFINITE) return discard_step<TD>(h, V1, s);
   h->step += 1;
   h->t_now = h->step * h->cfg.dt;
-  const int dec = h->ctrl_h->decision;
   if (dec != DEC_NONE) {
     TRY(hosvd_select<TD>(h, V1, dec, s));
     TRY(pull_ctrl(h, s));
     TRY(fused_post<T>(h, s));
     TRY(pull_ctrl(h, s));
+    if (h->gate_mode != GATE_OFF && !h->batch_owned)   // the singular-value history starts over
+      HIPCHK(hipMemsetAsync(h->g_hcount, 0, sizeof(int), s));
   }
   TRY(keep_previous<TD>(h, V1, s));
   // the host copy holds this step's singular values only after a reinit (pulled in
@@ -1230,6 +1290,8 @@ tdb_status finish_step(tdb_ctx* h, const TD* V1, hipStream_t s) {
 template <typename TD, typename T>
 tdb_status enqueue_fused_step(tdb_ctx* h, StepArgs& A, hipStream_t s) {
   h->prof_now = h->prof_every <= 1 || h->prof_steps++ % h->prof_every == 0;
+  h->last_path = TDB_PATH_FUSED;
+  h->last_prec = A.pl.mfma == MPASS_BF16S ? TDB_PREC_BF16SPLIT : (h->f32 ? TDB_PREC_F32 : TDB_PREC_F64);
   if (!h->post_valid) TRY(fused_post<T>(h, s));
   const int stages = h->cfg.integrator == TDB_INT_EULER ? 1 : 2;
   for (int stage = 1; stage <= stages; ++stage) {
@@ -1249,6 +1311,25 @@ tdb_status enqueue_fused_step(tdb_ctx* h, StepArgs& A, hipStream_t s) {
   HIPCHK(launch_fqr(A.qa, A.lds_qr, h->ctrl, s));
   HIPCHK(launch_fpost<T>(A.pa, A.lds_post, h->ctrl, s));
   h->post_valid = true;
+  if (h->gate_mode != GATE_OFF && !h->batch_owned) {
+    // the learned gate predicts this step's error from the singular values the
+    // post-step kernel just formed, and may skip the exact error pass
+    GateStepArgs g{};
+    g.params = h->g_params;
+    g.mean = h->g_mean;
+    g.stdv = h->g_std;
+    g.ctrl = h->g_ctab;
+    g.hist = h->g_hist;
+    g.hcount = h->g_hcount;
+    g.yhat = h->g_yhat;
+    g.skip = h->g_skip;
+    g.would_skip = h->g_would;
+    g.mode = h->gate_mode;
+    HIPCHK(gate_infer(g, 1, s));
+    A.ea.skip = h->g_skip;
+    A.ea.would_skip = h->g_would;
+    A.ea.yhat = h->g_yhat;
+  }
   {
     PassTimer pt(h, TDB_PASS_ERROR, s, true);
     HIPCHK((launch_ferr<TD, T>(A.ea, h->ctrl, s, pt.start(), pt.stop())));
@@ -1314,7 +1395,6 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s, const TD* D = n
   }
   if (bs == TDB_EUNSUPPORTED) {
     h->post_valid = false;
-    h->plain_steps += 1;
     return ingest_impl<TD, T>(h, V1, s, D);
   }
   TRY(bs);
@@ -1339,20 +1419,24 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s, const TD* D = n
     return TDB_OK;
   };
   TRY(enqueue(A));
+  // TDB_ENUMERIC of the previous step (discarded for non-finite data) is returned once
+  // this step is in flight
+  tdb_status prev = TDB_OK;
   if (h->pending) {
     h->pending = false;
     TRY(wait_mirror(h, h->mirror));
     h->ctrl_h = h->ctrl_hb[h->mirror];
     for (int n = 0; n < h->p; ++n) h->r[n] = h->ctrl_h->ranks[n];
-    const bool acted = h->ctrl_h->decision != DEC_NONE;
+    const int dec = h->ctrl_h->decision;
+    const bool acted = dec != DEC_NONE && dec != DEC_NONFINITE;   // the device holds the steps behind it
     if (acted) HIPCHK(hipStreamSynchronize(s));   // the held step has drained
-    TRY((finish_step<TD, T>(h, static_cast<const TD*>(h->Vpend), h->pend_stream)));
+    prev = finish_step<TD, T>(h, static_cast<const TD*>(h->Vpend), h->pend_stream);
+    if (prev != TDB_OK && prev != TDB_ENUMERIC) return prev;
     if (acted) {
       StepArgs A2;
       tdb_status b2 = build_step_args(h, h->r, V1, h->Vprev, A2);
       if (b2 == TDB_EUNSUPPORTED) {
         h->post_valid = false;
-        h->plain_steps += 1;
         return ingest_impl<TD, T>(h, V1, s);
       }
       TRY(b2);
@@ -1364,7 +1448,7 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s, const TD* D = n
   h->pend_stream = s;
   h->mirror = m_new;
   h->pending = true;
-  return TDB_OK;
+  return prev;
 }
 
 template <typename TD>
@@ -1441,6 +1525,7 @@ struct tdb_batch_ctx {
   size_t lds_pass = 0, lds_fin = 0, lds_qr = 0, lds_post = 0, lds_mprep = 0, lds_final = 0;
   size_t lds_rows = 0, lds_exp = 0;   // row blocks of the finish, expansion blocks of the post-step
   int mflavor = 0;                  // MPASS_* of the batched stage pass (one for all streams)
+  std::vector<int> pass_blocks, pass_T1, pass_T2;   // each stream's stage-pass grid, fixed at the caps
   double bytes_pass = 0.0, bytes_err = 0.0;
   bool dirty = true;
   bool prof = false;
@@ -1478,6 +1563,7 @@ struct tdb_gate_ctx {
   do {                                                                                 \
     hipError_t e_ = (expr);                                                            \
     if (e_ != hipSuccess) {                                                            \
+      (void)hipGetLastError();                                                         \
       g->err = std::string(#expr) + ": " + hipGetErrorString(e_);                      \
       return TDB_EHIP;                                                                 \
     }                                                                                  \
@@ -1487,6 +1573,7 @@ struct tdb_gate_ctx {
   do {                                                                                 \
     hipError_t e_ = (expr);                                                            \
     if (e_ != hipSuccess) {                                                            \
+      (void)hipGetLastError();                                                         \
       b->err = std::string(#expr) + ": " + hipGetErrorString(e_);                      \
       return TDB_EHIP;                                                                 \
     }                                                                                  \
@@ -1547,6 +1634,16 @@ tdb_status batch_upload_args(tdb_batch_ctx* b, hipStream_t s) {
     StepArgs A;
     tdb_status r = build_step_args(h, h->caps, nullptr, nullptr, A);
     if (r != TDB_OK) { b->err = "stream " + std::to_string(i) + ": " + h->err; return r; }
+    // The launch (grid, block map, pass kernel) was fixed at the caps: the tiles at the
+    // current ranks must be exactly those blocks, and their partial slots and LDS must
+    // fit what was allocated, or the step is refused before any launch.
+    if (A.pl.T1 != b->pass_T1[i] || A.pl.T2 != b->pass_T2[i] || A.blocks_pass != b->pass_blocks[i] ||
+        A.pl.mfma != b->mflavor || A.pl.lds > (size_t)h->lds_max ||
+        (long long)A.pl.nt1 * A.pl.nt2 * A.pl.slot > h->fpart_elems) {
+      b->err = "stream " + std::to_string(i) + ": the stage-pass tiles at ranks (" + std::to_string(h->r[0]) + ", " +
+               std::to_string(h->r[1]) + ", " + std::to_string(h->r[2]) + ") do not fit the launch fixed at the caps";
+      return TDB_EUNSUPPORTED;
+    }
     lds_pass = std::max(lds_pass, A.pl.lds);
     b->h_fa[0][i] = A.fa[0];
     b->h_fa[1][i] = A.fa[1];
@@ -1618,6 +1715,9 @@ tdb_status batch_setup(tdb_batch_ctx* b) {
       return TDB_EUNSUPPORTED;
     }
     c_pass[i] = A.blocks_pass;
+    b->pass_blocks.push_back(A.blocks_pass);
+    b->pass_T1.push_back(A.pl.T1);
+    b->pass_T2.push_back(A.pl.T2);
     c_red[i] = A.blocks_red;
     c_fin0[i] = A.blocks_fin[0];
     c_fin1[i] = A.blocks_fin[1];
@@ -1731,6 +1831,7 @@ tdb_status batch_step(tdb_batch_ctx* b, const void* const* V, hipStream_t s) {
   }
   BHIPCHK(hipMemcpyAsync(b->h_sum, b->d_sum, n * sizeof(BatchSummary), hipMemcpyDeviceToHost, s));
   BHIPCHK(hipStreamSynchronize(s));
+  int first_bad = -1, n_bad = 0;
   for (int i = 0; i < n; ++i) {
     tdb_ctx* h = b->st[i];
     const BatchSummary& q = b->h_sum[i];
@@ -1750,11 +1851,24 @@ tdb_status batch_step(tdb_batch_ctx* b, const void* const* V, hipStream_t s) {
     h->post_valid = true;
     const int r0[3] = {h->r[0], h->r[1], h->r[2]};
     tdb_status r = finish_step<TD, T>(h, static_cast<const TD*>(V[i]), s);
-    if (r != TDB_OK) { b->err = "stream " + std::to_string(i) + ": " + h->err; return r; }
+    if (r == TDB_ENUMERIC) {   // this stream's step was discarded; the others went on
+      if (first_bad < 0) first_bad = i;
+      ++n_bad;
+    } else if (r != TDB_OK) {
+      b->err = "stream " + std::to_string(i) + ": " + h->err;
+      return r;
+    }
     if (h->r[0] != r0[0] || h->r[1] != r0[1] || h->r[2] != r0[2]) b->dirty = true;
     if (q.decision != DEC_NONE && b->gate_mode != GATE_OFF)   // the singular values start over
       BHIPCHK(hipMemsetAsync(b->d_ghcount + i, 0, sizeof(int), s));
     h->fused_steps += 1;
+    h->last_path = TDB_PATH_FUSED;
+    h->last_prec = b->mflavor == MPASS_BF16S ? TDB_PREC_BF16SPLIT : (h->f32 ? TDB_PREC_F32 : TDB_PREC_F64);
+  }
+  if (n_bad > 0) {
+    b->err = std::to_string(n_bad) + " stream(s), the first " + std::to_string(first_bad) +
+             ", had non-finite data: their steps were not applied (the other streams advanced)";
+    return TDB_ENUMERIC;
   }
   return TDB_OK;
 }
@@ -1771,7 +1885,12 @@ tdb_status tdb_init(const tdb_config* cfg, const void* V0_dev, void* stream, tdb
   tdb_status st = create(cfg, &h);
   if (st != TDB_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  auto run = [&]() -> tdb_status { return init_hosvd(h, V0_dev, s); };
+  auto run = [&]() -> tdb_status {
+    bool bad = false;
+    TRY(has_nonfinite_any(h, V0_dev, s, &bad));
+    if (bad) { h->err = "non-finite values (NaN or Inf) in the first snapshot"; return TDB_ENUMERIC; }
+    return init_hosvd(h, V0_dev, s);
+  };
   st = run();
   if (st != TDB_OK) {
     g_create_error = h->err;
@@ -1794,12 +1913,23 @@ tdb_status tdb_init_from_factors(const tdb_config* cfg, const void* V0_dev, cons
   if (st != TDB_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   auto run = [&]() -> tdb_status {
+    bool bad = false;
+    TRY(has_nonfinite_any(h, V0_dev, s, &bad));
+    if (bad) { h->err = "non-finite values (NaN or Inf) in the first snapshot"; return TDB_ENUMERIC; }
     for (int n = 0; n < h->p; ++n) {
       if (ranks[n] < 1 || ranks[n] > h->caps[n] || !U_host[n]) {
         h->err = "ranks must be in [1, cap] with a basis for every mode";
         return TDB_EINVAL;
       }
       h->r[n] = ranks[n];
+    }
+    {
+      bool fin = true;
+      const long long csz = prod_ll(h->r, h->p);
+      for (long long i = 0; i < csz; ++i) fin = fin && std::isfinite(C_host[i]);
+      for (int n = 0; n < h->p; ++n)
+        for (long long i = 0; i < h->N[n] * h->r[n]; ++i) fin = fin && std::isfinite(U_host[n][i]);
+      if (!fin) { h->err = "non-finite values in the given core or bases"; return TDB_ENUMERIC; }
     }
     for (int n = 0; n < h->p; ++n)
       if (h->r[n] > prod_ll(h->r, h->p, n)) {
@@ -1818,7 +1948,7 @@ tdb_status tdb_init_from_factors(const tdb_config* cfg, const void* V0_dev, cons
     else TRY(init_eps<double>(h, static_cast<const double*>(V0_dev), s));
     TRY(core_sigma(h, false, s));
     TRY(pull_ctrl(h, s));
-    h->ctrl_h->eps = std::sqrt(std::max(h->ctrl_h->eps2, 0.0));
+    h->ctrl_h->eps = std::sqrt(std::max(h->ctrl_h->eps2, 0.0));   // finite: V0 and the factors were checked
     h->ctrl_h->nu = std::sqrt(std::max(h->ctrl_h->nu2, 0.0));
     HIPCHK(hipMemcpy(h->ctrl, h->ctrl_h, sizeof(CtrlState), hipMemcpyHostToDevice));
     if (h->data32) TRY(keep_previous<float>(h, static_cast<const float*>(V0_dev), s));
@@ -1843,12 +1973,7 @@ tdb_status tdb_ingest_snapshot(tdb_handle h, const void* V_dev, void* stream) {
   if (!V_dev) { h->err = "V_dev is NULL"; return TDB_EINVAL; }
   if (h->batch_owned) { h->err = "this stream belongs to a batch: use tdb_batch_ingest"; return TDB_ESTATE; }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  tdb_status st = h->data32 ? ingest_dispatch<float>(h, V_dev, s) : ingest_dispatch<double>(h, V_dev, s);
-  if (st == TDB_OK && !std::isfinite(h->stats.eps)) {
-    h->err = "non-finite reconstruction error (NaN or Inf in the snapshot?)";
-    return TDB_ENUMERIC;
-  }
-  return st;
+  return h->data32 ? ingest_dispatch<float>(h, V_dev, s) : ingest_dispatch<double>(h, V_dev, s);
 }
 
 tdb_status tdb_ingest_with_derivative(tdb_handle h, const void* V_dev, const void* D_dev, void* stream) {
@@ -1857,23 +1982,25 @@ tdb_status tdb_ingest_with_derivative(tdb_handle h, const void* V_dev, const voi
   if (!V_dev || !D_dev) { h->err = "V_dev and D_dev must not be NULL"; return TDB_EINVAL; }
   if (h->batch_owned) { h->err = "this stream belongs to a batch: use tdb_batch_ingest"; return TDB_ESTATE; }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  tdb_status st = h->data32 ? ingest_dispatch<float>(h, V_dev, s, D_dev) : ingest_dispatch<double>(h, V_dev, s, D_dev);
-  if (st == TDB_OK && !std::isfinite(h->stats.eps)) {
-    h->err = "non-finite reconstruction error (NaN or Inf in the snapshot or derivative?)";
+  TRY(resolve_pending(h));
+  // the derivative reaches the core derivative (and the device check) but the snapshot
+  // only the error pass, after the state is advanced: both are checked first
+  bool bad_v = false, bad_d = false;
+  TRY(has_nonfinite_any(h, V_dev, s, &bad_v));
+  TRY(has_nonfinite_any(h, D_dev, s, &bad_d));
+  if (bad_v || bad_d) {
+    h->n_nonfinite += 1;
+    h->err = std::string("non-finite values (NaN or Inf) in the ") + (bad_v ? "snapshot" : "derivative") +
+             ": the step was not taken";
     return TDB_ENUMERIC;
   }
-  return st;
+  return h->data32 ? ingest_dispatch<float>(h, V_dev, s, D_dev) : ingest_dispatch<double>(h, V_dev, s, D_dev);
 }
 
 tdb_status tdb_flush(tdb_handle h) {
   if (!h) { g_create_error = "handle is NULL"; return TDB_EINVAL; }
   if (!h->ready) { h->err = "handle is not initialised"; return TDB_ESTATE; }
-  TRY(resolve_pending(h));
-  if (!std::isfinite(h->stats.eps)) {
-    h->err = "non-finite reconstruction error (NaN or Inf in the snapshot?)";
-    return TDB_ENUMERIC;
-  }
-  return TDB_OK;
+  return resolve_pending(h);
 }
 
 tdb_status tdb_get_core_and_bases(tdb_handle h, int32_t rotate, int32_t* ranks_out, double* C_host,
@@ -1980,6 +2107,10 @@ tdb_status tdb_get_stats(tdb_handle h, tdb_stats* out) {
         h->stats.sigma[n][i] = (n < h->p && i < h->r[n]) ? h->ctrl_h->sigma[n][i] : 0.0;
     h->sigma_stale = false;
   }
+  // counters that also move on a step that was not applied
+  h->stats.fused_steps = h->fused_steps;
+  h->stats.plain_steps = h->plain_steps;
+  h->stats.n_nonfinite = h->n_nonfinite;
   *out = h->stats;
   return TDB_OK;
 }
@@ -2066,7 +2197,13 @@ tdb_status tdb_batch_create(int32_t n, const tdb_config* cfgs, const void* const
         b->err = "internal: stream " + std::to_string(i) + " buffer precision differs from the batch";
         return TDB_EINVAL;
       }
-      r = init_hosvd(h, V0_dev[i], s);
+      bool bad = false;
+      r = has_nonfinite_any(h, V0_dev[i], s, &bad);
+      if (r == TDB_OK && bad) {
+        h->err = "non-finite values (NaN or Inf) in the first snapshot";
+        r = TDB_ENUMERIC;
+      }
+      if (r == TDB_OK) r = init_hosvd(h, V0_dev[i], s);
       if (r == TDB_OK) r = b->f32 ? fused_post<float>(h, s) : fused_post<double>(h, s);
       if (r == TDB_OK) r = pull_ctrl(h, s);
       if (r != TDB_OK) { b->err = "stream " + std::to_string(i) + ": " + h->err; return r; }
@@ -2093,13 +2230,7 @@ tdb_status tdb_batch_ingest(tdb_batch b, const void* const* V_dev, void* stream)
   tdb_status st;
   if (b->data32) st = b->f32 ? batch_step<float, float>(b, V_dev, s) : batch_step<float, double>(b, V_dev, s);
   else st = b->f32 ? batch_step<double, float>(b, V_dev, s) : batch_step<double, double>(b, V_dev, s);
-  if (st != TDB_OK) return st;
-  for (int i = 0; i < b->n; ++i)
-    if (!b->st[i]->stats.gated && !std::isfinite(b->st[i]->stats.eps)) {
-      b->err = "stream " + std::to_string(i) + ": non-finite reconstruction error";
-      return TDB_ENUMERIC;
-    }
-  return TDB_OK;
+  return st;
 }
 
 tdb_status tdb_batch_stream(tdb_batch b, int32_t i, tdb_handle* out) {
@@ -2292,6 +2423,56 @@ tdb_status tdb_batch_gate_attach(tdb_batch b, tdb_gate g, const float* feat_mean
   b->gate_mode = (mode == GATE_RECORD && !g) ? GATE_OFF : mode;
   for (tdb_ctx* h : b->st) h->sigma_every_step = mode != GATE_OFF;
   b->dirty = true;
+  return TDB_OK;
+}
+
+tdb_status tdb_gate_load(tdb_handle h, const float* params_host, const float* feat_mean_std_host, int32_t n_params,
+                         int32_t mode) {
+  if (!h) { g_create_error = "handle is NULL"; return TDB_EINVAL; }
+  if (!h->ready) { h->err = "handle is not initialised"; return TDB_ESTATE; }
+  if (h->batch_owned) { h->err = "this stream belongs to a batch: use tdb_batch_gate_attach"; return TDB_ESTATE; }
+  if (mode < GATE_OFF || mode > GATE_SHADOW) { h->err = "bad gate mode"; return TDB_EINVAL; }
+  const bool net = mode == GATE_ACTIVE || mode == GATE_SHADOW;
+  if (mode != GATE_OFF && !h->fused) {
+    h->err = "the learned gate runs on the fused third-order path only";
+    return TDB_EUNSUPPORTED;
+  }
+  if (net && (!params_host || !feat_mean_std_host || n_params != GATE_NP)) {
+    h->err = "active and shadow modes need TDB_GATE_PARAMS parameters and 768 feature statistics";
+    return TDB_EINVAL;
+  }
+  TRY(resolve_pending(h));
+  HIPCHK(hipDeviceSynchronize());
+  if (!h->g_params) {
+    TRY(dallocT(h, &h->g_params, (size_t)GATE_NP));
+    TRY(dallocT(h, &h->g_mean, (size_t)GATE_IN));
+    TRY(dallocT(h, &h->g_std, (size_t)GATE_IN));
+    TRY(dallocT(h, &h->g_hist, (size_t)GATE_W * GATE_ROW));
+    TRY(dallocT(h, &h->g_yhat, 1));
+    TRY(dallocT(h, &h->g_hcount, 1));
+    TRY(dallocT(h, &h->g_skip, 1));
+    TRY(dallocT(h, &h->g_would, 1));
+    TRY(dallocT(h, &h->g_ctab, 1));
+    HIPCHK(hipMemcpy(h->g_ctab, &h->ctrl, sizeof(CtrlState*), hipMemcpyHostToDevice));
+  }
+  if (net) {
+    for (int i = 0; i < GATE_NP; ++i)
+      if (!std::isfinite(params_host[i])) { h->err = "non-finite gate parameter"; return TDB_EINVAL; }
+    for (int i = 0; i < GATE_IN; ++i)
+      if (!(feat_mean_std_host[GATE_IN + i] > 0.0f) || !std::isfinite(feat_mean_std_host[i])) {
+        h->err = "feature means must be finite and standard deviations positive";
+        return TDB_EINVAL;
+      }
+    HIPCHK(hipMemcpy(h->g_params, params_host, GATE_NP * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->g_mean, feat_mean_std_host, GATE_IN * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->g_std, feat_mean_std_host + GATE_IN, GATE_IN * sizeof(float), hipMemcpyHostToDevice));
+  }
+  HIPCHK(hipMemset(h->g_hcount, 0, sizeof(int)));
+  HIPCHK(hipMemset(h->g_skip, 0, sizeof(int)));
+  HIPCHK(hipMemset(h->g_would, 0, sizeof(int)));
+  // RECORD keeps the singular values every step (for training histories), no network
+  h->gate_mode = mode == GATE_RECORD ? GATE_OFF : mode;
+  h->sigma_every_step = mode != GATE_OFF;
   return TDB_OK;
 }
 

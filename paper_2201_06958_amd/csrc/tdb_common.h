@@ -13,7 +13,17 @@
 enum { EV_NONE = 0, EV_REINIT = 1, EV_ADD = 2, EV_REMOVE = 3, EV_NUMERIC = 4 };
 
 // Controller decisions taken on the device after the error pass.
-enum { DEC_NONE = 0, DEC_ADD = 1, DEC_REMOVE = 2, DEC_NUMERIC = 3, DEC_INIT = 4 };
+// DEC_NONFINITE: the step's data derivative held NaN or Inf; the step was not applied
+// (core and bases kept) and the host reports TDB_ENUMERIC.
+enum { DEC_NONE = 0, DEC_ADD = 1, DEC_REMOVE = 2, DEC_NUMERIC = 3, DEC_INIT = 4, DEC_NONFINITE = 5 };
+
+// Bits of CtrlState::numeric.
+enum {
+  NUM_CORE = 1,        // a stage's core Gram failed its Cholesky test (pseudo-inverse)
+  NUM_BASIS = 2,       // a basis Gram failed its Cholesky test (re-orthonormalisation)
+  NUM_NEXT = 4,        // the next step's core Gram failed (found by the post-step kernel)
+  NUM_NONFINITE = 8    // the first stage's core derivative is not finite (NaN/Inf data)
+};
 
 // A direction whose full-data singular value is below this fraction of its mode's
 // largest is numerically absent: adding it would make a core Gram matrix singular.
@@ -43,7 +53,7 @@ struct CtrlState {
   // outputs of the last step
   int decision;       // DEC_*
   int event;          // TDB_EV_* (see tdb.h)
-  int numeric;        // set when a core Gram or a basis Gram failed its Cholesky test
+  int numeric;        // NUM_* bits: a failed Cholesky test or non-finite data
   int rank_changed;
   double eps2, nu2;   // from the error pass
   double eps, nu, eps_after;
@@ -55,6 +65,10 @@ struct CtrlState {
   int hold;           // a decision awaits the host: the fused kernels of a step enqueued
                       // after it do nothing until the host has acted and cleared it
 };
+
+// Square root of a sum of squares: a tiny negative value from rounding becomes 0, and
+// a NaN stays NaN (fmax(NaN, 0) would turn non-finite data into a zero error).
+__device__ __forceinline__ double sqrt_sum_sq(double x) { return x >= 0.0 ? sqrt(x) : (x < 0.0 ? 0.0 : x); }
 
 __device__ __forceinline__ double warp_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);

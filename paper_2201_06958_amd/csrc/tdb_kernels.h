@@ -79,6 +79,10 @@ hipError_t launch_err_partials(const TV* V, const TR* R, int p, const long long*
                                const double* const* w, double* partials, int nblocks,
                                hipStream_t s);
 hipError_t launch_err_final(const double* partials, int nblocks, CtrlState* ctrl, hipStream_t s);
+// *flag (device int, set to 0 by the launcher) becomes 1 if any of the n values is NaN
+// or infinite.
+template <typename T>
+hipError_t launch_nonfinite_check(const T* x, long long n, int* flag, hipStream_t s);
 // Elementwise conversions.
 template <typename TI, typename TO>
 hipError_t launch_convert(const TI* in, TO* out, long long n, hipStream_t s);

@@ -76,6 +76,11 @@ class TdbStats(ctypes.Structure):
         ("gated", ctypes.c_int32),
         ("would_skip", ctypes.c_int32),
         ("eps_pred", ctypes.c_double),
+        ("precision_used", ctypes.c_int32),
+        ("path_used", ctypes.c_int32),
+        ("fused_steps", ctypes.c_int64),
+        ("plain_steps", ctypes.c_int64),
+        ("n_nonfinite", ctypes.c_int64),
     ]
 
 
@@ -125,6 +130,8 @@ def load_library(path: str = LIB_PATH):
     lib.tdb_batch_profile_read.argtypes = [H, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.tdb_batch_gate_attach.argtypes = [H, H, ctypes.POINTER(ctypes.c_float), ctypes.c_int32]
+    lib.tdb_gate_load.argtypes = [H, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float), ctypes.c_int32,
+                                  ctypes.c_int32]
     F = ctypes.POINTER(ctypes.c_float)
     lib.tdb_gate_create.argtypes = [ctypes.c_int32, ctypes.POINTER(H)]
     lib.tdb_gate_set_params.argtypes = [H, F]
@@ -143,7 +150,7 @@ def load_library(path: str = LIB_PATH):
     for name in ("tdb_init", "tdb_init_from_factors", "tdb_ingest_snapshot", "tdb_flush", "tdb_get_core_and_bases",
                  "tdb_reconstruct", "tdb_set_threshold", "tdb_get_stats", "tdb_batch_create",
                  "tdb_batch_ingest", "tdb_batch_stream", "tdb_batch_profile_enable",
-                 "tdb_batch_profile_read", "tdb_batch_gate_attach", "tdb_gate_create", "tdb_gate_set_params",
+                 "tdb_batch_profile_read", "tdb_batch_gate_attach", "tdb_gate_load", "tdb_gate_create", "tdb_gate_set_params",
                  "tdb_gate_get_params", "tdb_gate_forward", "tdb_gate_grad", "tdb_gate_train_step"):
         getattr(lib, name).restype = ctypes.c_int32
     a, b = ctypes.c_int64(), ctypes.c_int64()
@@ -283,7 +290,27 @@ class Compressor:
             "n_numeric": s.n_numeric, "gated": bool(s.gated), "would_skip": bool(s.would_skip),
             "eps_pred": s.eps_pred,
             "sigma16": [list(s.sigma[n][:SIGMA_K]) for n in range(p)],
+            "precision_used": {-1: None, PREC_F64: "f64", PREC_F32: "f32",
+                               PREC_BF16SPLIT: "bf16s"}.get(s.precision_used),
+            "path_used": {0: None, PATH_PLAIN: "plain", PATH_FUSED: "fused"}.get(s.path_used),
+            "fused_steps": s.fused_steps, "plain_steps": s.plain_steps, "n_nonfinite": s.n_nonfinite,
         }
+
+    def gate_load(self, params=None, mean_std=None, mode: str = "active"):
+        """Copy a trained gate (TDB_GATE_PARAMS floats) and its feature statistics (768
+        floats: means, then standard deviations) into this stream. mode: off | record |
+        active | shadow."""
+        mid = {"off": 0, "record": 1, "active": 2, "shadow": 3}[mode]
+        pp = ms = None
+        n = 0
+        if params is not None:
+            self._gp = np.ascontiguousarray(params, dtype=np.float32)
+            pp = self._gp.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+            n = int(self._gp.size)
+        if mean_std is not None:
+            self._gms = np.ascontiguousarray(mean_std, dtype=np.float32)
+            ms = self._gms.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        self._check(self.lib.tdb_gate_load(self.h, pp, ms, n, mid))
 
     def profile_enable(self, on: bool = True, every: int = 1):
         """Pass timing: every launch (every=1) or the passes of every `every`-th step."""

@@ -67,6 +67,7 @@ def test_null_handle_calls_fail_cleanly():
     assert lib.tdb_set_threshold(None, 1.0, 0.0) == tdb.EINVAL
     s = tdb.TdbStats()
     assert lib.tdb_get_stats(None, ctypes.byref(s)) == tdb.EINVAL
+    assert lib.tdb_gate_load(None, None, None, 0, 0) == tdb.EINVAL
     lib.tdb_destroy(None)
 
 

@@ -135,3 +135,92 @@ def test_trained_gate_skips_error_passes_without_misdecisions():
         for a, c in zip(U0, U1):
             assert np.array_equal(a, c)
     g.close()
+
+
+def _single_stream(seed=3):
+    sp = plume_spec(nx=128, ny=64, nv=8, steps=30, noise_seed=seed)
+    cfg = dict(dims=sp.dims, dt=sp.dt, rank_max=(32, 32, 8), weights=sp.weights, data_dtype="f32",
+               precision="f32", adaptive=True, eps_th=sp.eps_th, snapshot_mode="borrow")
+    return sp, cfg
+
+
+def test_single_stream_gate_features_match_training_features():
+    """Train/serve skew: in shadow mode the device predicts from FP32 log10 features
+    it forms itself; the same network evaluated in FP64 on features built by the
+    training pipeline (numpy log10 of the reported singular values) must agree."""
+    from paper_2201_06958_amd import Compressor
+    from paper_2201_06958_amd import gate as GP
+    sp, cfg = _single_stream()
+    _say("case single-stream gate features")
+    rng = np.random.default_rng(5)
+    theta = gate_init_params(11)
+    ms = np.concatenate([rng.normal(size=GO.N_IN) - 3.0, rng.uniform(0.5, 2.0, size=GO.N_IN)]).astype(np.float32)
+    g = Compressor(**cfg)
+    g.init(sp.snapshot(0, device="cuda"))
+    g.gate_load(theta, ms, "shadow")
+    snaps = [sp.snapshot(k, device="cuda") for k in range(sp.steps + 1)]
+    sig_hist = []
+    worst = 0.0
+    checked = 0
+    for k in range(1, sp.steps + 1):
+        g.ingest(snaps[k])
+        g.flush()
+        st = g.stats()
+        if st["event"]:
+            sig_hist = []
+            continue
+        sig_hist.append(np.asarray(st["sigma16"])[:3, :16])
+        if len(sig_hist) >= 8:
+            x = GP.window_features(np.asarray(sig_hist[-8:]))
+            xs = (x - ms[:GO.N_IN].astype(np.float64)) / ms[GO.N_IN:].astype(np.float64)
+            y, _ = GO.forward(theta.astype(np.float64), xs[None, :])
+            yd = np.log10(st["eps_pred"])
+            worst = max(worst, abs(float(y[0]) - yd))
+            checked += 1
+    _say(f"  {checked} predictions, worst |log10 difference| {worst:.2e}")
+    assert checked >= 10
+    assert worst < 1e-4 * max(1.0, abs(float(y[0])))
+    g.close()
+
+
+@pytest.mark.parametrize("bias,expect_skip", [(-40.0, True), (10.0, False)])
+def test_single_stream_gate_active_skips_and_keeps_state(bias, expect_skip):
+    """tdb_gate_load on one stream: a network whose output is the constant b3 skips
+    every pass it may (b3 far below the threshold) or none (b3 above it); the
+    compressed state equals the always-exact run's bit for bit, and a skipped step
+    reports NaN as its error. The analytic stream at fixed ranks with a tiny
+    threshold has no removal candidate, so only the prediction decides."""
+    from paper_2201_06958_amd import Compressor
+    from streams import analytic_cp5_spec
+    sp = analytic_cp5_spec(n=32, steps=30)
+    cfg = dict(dims=sp.dims, dt=sp.dt, rank_max=(5, 5, 5), rank_init=(5, 5, 5), weights=sp.weights,
+               data_dtype="f64", precision="f64", adaptive=False, eps_th=1e-8, snapshot_mode="borrow")
+    _say(f"case single-stream gate active b3={bias}")
+    theta = np.zeros(GO.N_PARAMS, dtype=np.float32)
+    theta[-1] = bias
+    ms = np.concatenate([np.zeros(384), np.ones(384)]).astype(np.float32)
+    snaps = [torch.from_numpy(sp.snapshot_np(k)).cuda() for k in range(sp.steps + 1)]
+    states, gated = [], 0
+    for mode in ("off", "active"):
+        g = Compressor(**cfg)
+        g.init(snaps[0])
+        if mode == "active":
+            g.gate_load(theta, ms, "active")
+        for k in range(1, sp.steps + 1):
+            g.ingest(snaps[k])
+            if mode == "active":
+                g.flush()
+                st = g.stats()
+                if st["gated"]:
+                    gated += 1
+                    assert np.isnan(st["eps"])
+                else:
+                    assert np.isfinite(st["eps"])
+        states.append(g.get_core_and_bases())
+        g.close()
+    (r0, C0, U0), (r1, C1, U1) = states
+    assert r0 == r1 and np.array_equal(C0, C1)
+    for a, c in zip(U0, U1):
+        assert np.array_equal(a, c)
+    _say(f"  gated steps {gated}")
+    assert (gated == sp.steps - 7) if expect_skip else (gated == 0)

@@ -32,6 +32,18 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
+def _sigma_rel(sig_dev, sig_orc):
+    """Largest difference of the leading (up to 16) core singular values per mode,
+    relative to the mode's largest: the core compared through its invariants (after a
+    reinitialisation the bases of two runs may differ by rotations within clusters of
+    close singular values)."""
+    worst = 0.0
+    for sd, so in zip(sig_dev, sig_orc):
+        k = min(len(sd), len(so), 16)
+        worst = max(worst, float(np.abs(np.asarray(sd[:k]) - so[:k]).max() / so[0]))
+    return worst
+
+
 @pytest.fixture(scope="module", autouse=True)
 def _gpu():
     if not torch.cuda.is_available():
@@ -104,7 +116,55 @@ def test_fixed_rank_random_streams(dims, ranks, pass_kernel, precision):
     rel = _rel(O.reconstruct(C, U), orc.reconstruct())
     relc = _rel(C, orc.C)
     _say(f"  reconstruction rel {rel:.2e}, core rel {relc:.2e}")
-    assert rel < bar and relc < 10 * bar
+    # both runs start from the same factors and evolve by the same smooth equations,
+    # so the core is compared as it is (same gauge), at the stated bar
+    assert rel < bar and relc < bar
+    g.close()
+
+
+# Ranks above 32 (the reactive-flow stream's caps are (64, 64, 8)): the generic stage
+# pass takes them, or the plain path where the fused step's small kernels do not fit
+# in LDS; a BF16-split request there runs FP32 products. The statistics report which.
+HIGH_RANK_CASES = [((150, 130, 8), (40, 36, 6)), ((200, 96, 8), (64, 48, 8)), ((97, 110, 6), (33, 40, 5))]
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16s"])
+@pytest.mark.parametrize("dims,ranks", HIGH_RANK_CASES)
+def test_fixed_rank_high_ranks(dims, ranks, precision):
+    _say(f"case high-rank {precision} dims {dims} ranks {ranks}")
+    rng = np.random.default_rng(sum(dims) + sum(ranks))
+    w = []
+    for n in dims:
+        x = rng.uniform(0.5, 1.5, size=n)
+        w.append(x / x.sum())
+    base = np.zeros(dims)
+    for q in range(max(ranks) + 8):
+        a = [rng.normal(size=n) for n in dims]
+        base += 0.9 ** q * np.einsum("i,j,k->ijk", *a)
+    snaps = [(base + 0.002 * k * rng.normal(size=dims)).astype(np.float32) for k in range(6)]
+    cfg = O.OracleConfig(dims=dims, weights=w, dt=0.05, rank_max=ranks, rank_init=ranks, adaptive=False, eps_th=1.0)
+    h = O.hosvd(snaps[0].astype(np.float64), w, ranks)
+    C0, U0 = h.truncate(ranks)
+    orc = O.OracleTDB(cfg).init_from_factors(snaps[0].astype(np.float64), C0, U0)
+    from paper_2201_06958_amd import Compressor
+    g = Compressor(dims, 0.05, rank_max=ranks, rank_init=ranks, weights=w, data_dtype="f32", precision=precision,
+                   adaptive=False, path="fused", eps_th=1.0)
+    g.init_from_factors(_dev(snaps[0]), C0, U0)
+    bar = BAR[precision]
+    for k in range(1, len(snaps)):
+        rec = orc.ingest(snaps[k].astype(np.float64))
+        g.ingest(_dev(snaps[k]))
+        st = g.stats()
+        assert abs(st["eps"] - rec.eps) <= bar * rec.nu, k
+    r, C, U = g.get_core_and_bases()
+    rel = _rel(O.reconstruct(C, U), orc.reconstruct())
+    relc = _rel(C, orc.C)
+    st = g.stats()
+    _say(f"  ran {st['path_used']} {st['precision_used']}: reconstruction rel {rel:.2e}, core rel {relc:.2e}")
+    assert st["path_used"] in ("fused", "plain")
+    assert st["fused_steps"] + st["plain_steps"] == len(snaps) - 1
+    assert st["precision_used"] in (("f32",) if precision == "f32" else ("f32", "bf16s"))
+    assert rel < bar and relc < bar
     g.close()
 
 
@@ -130,8 +190,9 @@ def test_plume_adaptive(precision):
         assert abs(st["eps"] - rec.eps) <= bar * rec.nu, k
     r, C, U = g.get_core_and_bases()
     rel = _rel(O.reconstruct(C, U), orc.reconstruct())
-    _say(f"  ranks {r}, reconstruction rel {rel:.2e}")
-    assert rel < bar
+    rels = _sigma_rel(g.stats()["sigma"], O.core_singular_values(orc.C))
+    _say(f"  ranks {r}, reconstruction rel {rel:.2e}, core singular values rel {rels:.2e}")
+    assert rel < bar and rels < bar
     g.close()
 
 
@@ -162,6 +223,7 @@ def test_batch_ensemble(precision):
     for i, o in enumerate(orcs):
         r, C, U = b.streams[i].get_core_and_bases()
         rel = _rel(O.reconstruct(C, U), o.reconstruct())
-        _say(f"  stream {i} {specs[i].dims} ranks {r}: reconstruction rel {rel:.2e}")
-        assert rel < bar
+        rels = _sigma_rel(b.streams[i].stats()["sigma"], O.core_singular_values(o.C))
+        _say(f"  stream {i} {specs[i].dims} ranks {r}: reconstruction rel {rel:.2e}, sigma rel {rels:.2e}")
+        assert rel < bar and rels < bar
     b.close()

@@ -50,6 +50,16 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
+def _sigma_rel(sig_dev, sig_orc):
+    """Largest difference of the leading (up to 16) core singular values per mode,
+    relative to the mode's largest (the core compared through its invariants)."""
+    worst = 0.0
+    for sd, so in zip(sig_dev, sig_orc):
+        k = min(len(sd), len(so), 16)
+        worst = max(worst, float(np.abs(np.asarray(sd[:k]) - so[:k]).max() / so[0]))
+    return worst
+
+
 @pytest.fixture(scope="module", autouse=True)
 def _gpu():
     if not torch.cuda.is_available():
@@ -228,8 +238,10 @@ def test_plume_fp32_against_oracle(path, nx, ny, steps):
     r, C, U = g.get_core_and_bases()
     rec_g = O.reconstruct(C, U)
     rel = _rel(rec_g, orc.reconstruct())
-    _say(f"  fp32 plume: reconstruction rel diff {rel:.3e}, worst eps diff / nu {worst:.3e}")
-    assert rel < 1e-6
+    rels = _sigma_rel(g.stats()["sigma"], O.core_singular_values(orc.C))
+    _say(f"  fp32 plume: reconstruction rel diff {rel:.3e}, worst eps diff / nu {worst:.3e}, "
+         f"core singular values rel {rels:.3e}")
+    assert rel < 1e-6 and worst < 1e-6 and rels < 1e-6
     g.close()
 
 
@@ -252,8 +264,9 @@ def test_ensemble_member_fp32_against_oracle(path):
         assert abs(st["eps"] - rec.eps) <= 1e-6 * rec.nu, k
     r, C, U = g.get_core_and_bases()
     rel = _rel(O.reconstruct(C, U), orc.reconstruct())
-    _say(f"  ensemble member: ranks {r}, reconstruction rel diff {rel:.3e}")
-    assert rel < 1e-6
+    rels = _sigma_rel(g.stats()["sigma"], O.core_singular_values(orc.C))
+    _say(f"  ensemble member: ranks {r}, reconstruction rel diff {rel:.3e}, core singular values rel {rels:.3e}")
+    assert rel < 1e-6 and rels < 1e-6
     g.close()
 
 
