@@ -319,6 +319,29 @@ tdb_status tdb_batch_gate_attach(tdb_batch b, tdb_gate g, const float* feat_mean
 tdb_status tdb_gate_load(tdb_handle h, const float* params_host, const float* feat_mean_std_host, int32_t n_params,
                          int32_t mode);
 
+/* ---- For callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.
+ * The dense reconstruction of tdb_reconstruct, C x_1 U_1 ... x_p U_p, from factors the
+ * caller holds on the device, with the intermediates of the n-mode product chain in a
+ * fixed scratch array inside the library: TDB_NOALLOC_SCRATCH doubles (64 MiB) per GPU,
+ * held from the first call on that GPU until the process ends. The call allocates no
+ * memory (no hipMalloc, no host allocation on success).
+ * order: 2..4; dims[n] = N_n and ranks[n] = r_n with 1 <= r_n <= N_n; C_dev: the
+ * C-contiguous r_1 x ... x r_p FP64 core; U_dev: a host array of `order` device
+ * pointers, U_dev[n] the row-major N_n x r_n FP64 basis; out_dev: S values in
+ * data_dtype (TDB_F64 | TDB_F32), C-contiguous, caller-owned. Enqueued on `stream`
+ * (products in FP64, rounded once into data_dtype).
+ * TDB_EINVAL for bad arguments or when an intermediate exceeds TDB_NOALLOC_SCRATCH / 2
+ * doubles (the modes are contracted in order of increasing N_n / r_n; the largest
+ * intermediate is the product of all but the last such mode's size and that rank);
+ * TDB_EHIP for a failed launch; messages from tdb_last_error(NULL).
+ * Every call on one GPU shares that GPU's array and leaves the last call's
+ * intermediates in it: calls that overlap on one GPU (on different streams or
+ * threads) race and must be ordered by the caller. */
+#define TDB_NOALLOC_SCRATCH 8388608
+tdb_status tdb_reconstruct_noalloc(int32_t order, const int64_t* dims, const int32_t* ranks, const double* C_dev,
+                                   const double* const* U_dev, int32_t data_dtype, void* out_dev, void* stream);
+
 /* Layout check for language bindings: writes sizeof(tdb_config) and sizeof(tdb_stats)
  * (either pointer may be NULL). Needs no device. */
 void tdb_struct_sizes(int64_t* config_bytes, int64_t* stats_bytes);

@@ -5,6 +5,7 @@
 #include "tdb_kernels.h"
 #include "fused.h"
 #include "gate.h"
+#include "noalloc.h"
 
 #include <hip/hip_runtime.h>
 
@@ -2473,6 +2474,42 @@ tdb_status tdb_gate_load(tdb_handle h, const float* params_host, const float* fe
   // RECORD keeps the singular values every step (for training histories), no network
   h->gate_mode = mode == GATE_RECORD ? GATE_OFF : mode;
   h->sigma_every_step = mode != GATE_OFF;
+  return TDB_OK;
+}
+
+static_assert(NOALLOC_SCRATCH_DOUBLES == TDB_NOALLOC_SCRATCH, "scratch size of the header and the library");
+
+tdb_status tdb_reconstruct_noalloc(int32_t order, const int64_t* dims, const int32_t* ranks, const double* C_dev,
+                                   const double* const* U_dev, int32_t data_dtype, void* out_dev, void* stream) {
+  // (messages are set on failure only: a successful call allocates nothing at all)
+  if (order < 2 || order > TDB_P) { g_create_error = "order must be 2..4"; return TDB_EINVAL; }
+  if (!dims || !ranks || !C_dev || !U_dev || !out_dev) { g_create_error = "NULL argument"; return TDB_EINVAL; }
+  if (data_dtype != TDB_F64 && data_dtype != TDB_F32) { g_create_error = "bad data_dtype"; return TDB_EINVAL; }
+  long long d[TDB_P] = {1, 1, 1, 1};
+  int r[TDB_P] = {1, 1, 1, 1};
+  double S = 1.0;
+  for (int n = 0; n < order; ++n) {
+    if (dims[n] < 1 || ranks[n] < 1 || ranks[n] > dims[n] || !U_dev[n]) {
+      g_create_error = "need 1 <= ranks[n] <= dims[n] and a basis for every mode";
+      return TDB_EINVAL;
+    }
+    d[n] = dims[n];
+    r[n] = ranks[n];
+    S *= (double)dims[n];
+  }
+  if (S > 9.0e15) { g_create_error = "tensor too large"; return TDB_EINVAL; }
+  const NoallocPlan pl = noalloc_plan(order, d, r);
+  if (pl.max_inter > NOALLOC_SCRATCH_DOUBLES / 2) {
+    g_create_error = "an intermediate of the product chain exceeds the fixed scratch (TDB_NOALLOC_SCRATCH / 2 doubles)";
+    return TDB_EINVAL;
+  }
+  const hipError_t e = noalloc_reconstruct(pl, d, r, C_dev, U_dev, data_dtype == TDB_F32 ? 1 : 0, out_dev,
+                                           static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    g_create_error = std::string("tdb_reconstruct_noalloc: ") + hipGetErrorString(e);
+    return TDB_EHIP;
+  }
   return TDB_OK;
 }
 

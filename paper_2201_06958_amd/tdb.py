@@ -120,6 +120,10 @@ def load_library(path: str = LIB_PATH):
     lib.tdb_profile_read.argtypes = [H, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.tdb_profile_read.restype = ctypes.c_int32
+    lib.tdb_reconstruct_noalloc.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                            ctypes.POINTER(ctypes.c_int32), P, ctypes.POINTER(P), ctypes.c_int32, P,
+                                            P]
+    lib.tdb_reconstruct_noalloc.restype = ctypes.c_int32
     lib.tdb_struct_sizes.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     lib.tdb_struct_sizes.restype = None
     lib.tdb_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(TdbConfig), ctypes.POINTER(P), P,
@@ -159,6 +163,23 @@ def load_library(path: str = LIB_PATH):
         raise RuntimeError("tdb.h struct layout does not match the binding")
     _lib = lib
     return lib
+
+
+def reconstruct_noalloc(C, U, out, stream=None):
+    """tdb_reconstruct_noalloc: out (a contiguous float32 or float64 device tensor of
+    the full shape) <- C x_1 U[0] ... from contiguous float64 device tensors C and U[n]
+    (N_n x r_n), with no device allocation inside the library."""
+    lib = load_library()
+    p = C.dim()
+    dims = (ctypes.c_int64 * MAX_ORDER)(*([int(u.shape[0]) for u in U] + [0] * (MAX_ORDER - p)))
+    ranks = (ctypes.c_int32 * MAX_ORDER)(*([int(s) for s in C.shape] + [0] * (MAX_ORDER - p)))
+    uptr = (ctypes.c_void_p * MAX_ORDER)(*([_dev_ptr(u).value for u in U] + [None] * (MAX_ORDER - p)))
+    import torch
+    dt = F32 if out.dtype == torch.float32 else F64
+    st = lib.tdb_reconstruct_noalloc(p, dims, ranks, _dev_ptr(C), uptr, dt, _dev_ptr(out), _stream_ptr(stream))
+    if st != OK:
+        raise TDBError(st, (lib.tdb_last_error(None) or b"").decode())
+    return out
 
 
 def _stream_ptr(stream):

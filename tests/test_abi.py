@@ -71,6 +71,28 @@ def test_null_handle_calls_fail_cleanly():
     lib.tdb_destroy(None)
 
 
+def test_noalloc_reconstruct_validates_before_device_work():
+    """tdb_reconstruct_noalloc refuses bad arguments and intermediates larger than half
+    its fixed scratch before any HIP call (the pointers here are never dereferenced)."""
+    from paper_2201_06958_amd import tdb
+    lib = tdb.load_library()
+    dummy = ctypes.c_void_p(1)
+    uptr = (ctypes.c_void_p * 8)(1, 1, 1, None, None, None, None, None)
+    out = ctypes.c_void_p(1)
+
+    def call(order, dims, ranks, dtype=tdb.F64):
+        d = (ctypes.c_int64 * 8)(*(list(dims) + [0] * (8 - len(dims))))
+        r = (ctypes.c_int32 * 8)(*(list(ranks) + [0] * (8 - len(ranks))))
+        return lib.tdb_reconstruct_noalloc(order, d, r, dummy, uptr, dtype, out, None)
+
+    assert call(1, (4,), (2,)) == tdb.EINVAL
+    assert call(3, (4, 4, 4), (5, 2, 2)) == tdb.EINVAL            # rank above the mode size
+    assert call(3, (4, 4, 4), (2, 2, 2), dtype=7) == tdb.EINVAL
+    # 2048 x 2048 x 4 doubles after the first product: above TDB_NOALLOC_SCRATCH / 2
+    assert call(3, (2048, 2048, 4), (2048, 2048, 4)) == tdb.EINVAL
+    assert b"scratch" in lib.tdb_last_error(None)
+
+
 def _cfg3(tdb):
     cfg = tdb.TdbConfig()
     cfg.order = 3
