@@ -205,6 +205,16 @@ template <typename TD, typename T>
 hipError_t launch_batch_fpass(const FPassArgs* tab, const void* const* v1, const void* const* v0, BatchMap m,
                               int blocks, size_t lds, hipStream_t s, hipEvent_t ev0 = nullptr,
                               hipEvent_t ev1 = nullptr);
+// Column-block stage pass of batches (rpass.hip): T2 columns of mode 2 with all of
+// modes 1 and 3 per workgroup of 8 waves; the mode-3 product is applied to the small
+// results. T2 follows the mode-3 extent the batch's streams share (rpass_cols_for).
+int rpass_cols_for(int n3c);
+size_t rpass_lds_bytes(int T2, int r1, int r2, int N3);
+bool rpass_shape_ok(int r1, int r2, int r3, int T2, int N3);
+template <typename TD>
+hipError_t launch_batch_rpass(const FPassArgs* tab, const void* const* v1, const void* const* v0, BatchMap m,
+                              int blocks, int flavor, int n3c, int vw, size_t lds, hipStream_t s,
+                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename TD>
 hipError_t launch_batch_mpass(const FPassArgs* tab, const void* const* v1, const void* const* v0, BatchMap m,
                               int blocks, int flavor, size_t lds, hipStream_t s, hipEvent_t ev0 = nullptr,

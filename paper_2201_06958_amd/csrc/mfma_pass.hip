@@ -21,112 +21,10 @@
 #include "tdb_common.h"
 #include "tdb_kernels.h"
 #include "fused.h"
+#include "mfma_util.h"
 #include <hip/hip_ext.h>
 
 namespace tdb {
-
-typedef float mf4 __attribute__((ext_vector_type(4)));
-typedef __bf16 mbf8 __attribute__((ext_vector_type(8)));
-
-// One 16 x 16 block C += A B over K (valid K entries Kv): A(m, k) = fa(m, k0, j) and
-// B(k, n) = fb(k0, j, n) with k = k0 + j, k0 a multiple of 16 and j < 16, for m < Mv,
-// n < Nv, zero elsewhere. Lane l feeds row/column l % 16 and the K slice selected by
-// l / 16. Operand reads are never predicated: lanes outside the block read a valid
-// entry (indices clamped into the block) and zero it, so each group of 16 K entries
-// is loaded in one go, and the next group while the current one's matrix
-// instructions run.
-template <int MF, typename FA, typename FB>
-__device__ __forceinline__ mf4 mma_blockf(FA fa, int Mv, FB fb, int Nv, int Kv, mf4 acc) {
-  const int l = threadIdx.x & 63;
-  const int mn = l & 15, kg = l >> 4;
-  const bool am = mn < Mv, bn = mn < Nv;
-  const int mc = am ? mn : Mv - 1, nc = bn ? mn : Nv - 1;
-  if (MF == MPASS_F32) {
-    const int nfull = Kv & ~15;
-    float xa[4], xb[4];
-    auto load = [&](int k0) {
-#pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        xa[st] = fa(mc, k0, 4 * st + kg);
-        xb[st] = fb(k0, 4 * st + kg, nc);
-      }
-    };
-    if (nfull > 0) load(0);
-    for (int k0 = 0; k0 < nfull; k0 += 16) {
-      float a[4], b[4];
-#pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        a[st] = am ? xa[st] : 0.0f;
-        b[st] = bn ? xb[st] : 0.0f;
-      }
-      if (k0 + 16 < nfull) load(k0 + 16);
-#pragma unroll
-      for (int st = 0; st < 4; ++st) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st], b[st], acc, 0, 0, 0);
-    }
-    if (nfull < Kv) {
-      float a[4], b[4];
-#pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        const int j = 4 * st + kg;
-        const bool kv = nfull + j < Kv;
-        const int jc = kv ? j : Kv - 1 - nfull;
-        const float x = fa(mc, nfull, jc), y = fb(nfull, jc, nc);
-        a[st] = (am && kv) ? x : 0.0f;
-        b[st] = (bn && kv) ? y : 0.0f;
-      }
-#pragma unroll
-      for (int st = 0; st < 4; ++st) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st], b[st], acc, 0, 0, 0);
-    }
-  } else {
-    for (int k0 = 0; k0 < Kv; k0 += 32) {
-      mbf8 ah, al, bh, bl;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = k0 + 8 * kg + j;
-        const bool kv = k < Kv;
-        const int kc = kv ? k : Kv - 1;
-        const int kb = kc & ~15;
-        const float x = fa(mc, kb, kc - kb), y = fb(kb, kc - kb, nc);
-        const float a = (am && kv) ? x : 0.0f;
-        const float b = (bn && kv) ? y : 0.0f;
-        const __bf16 a1 = (__bf16)a, b1 = (__bf16)b;
-        ah[j] = a1;
-        al[j] = (__bf16)(a - (float)a1);
-        bh[j] = b1;
-        bl[j] = (__bf16)(b - (float)b1);
-      }
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
-    }
-  }
-  return acc;
-}
-
-// The same with strided operands: A(m, k) = A[m*sam + k*sak], B(k, n) = B[k*sbk + n*sbn].
-template <int MF>
-__device__ __forceinline__ mf4 mma_block(const float* A, int sam, int sak, int Mv, const float* B, int sbk, int sbn,
-                                         int Nv, int Kv, mf4 acc) {
-  return mma_blockf<MF>([&](int m, int k0, int j) { return A[m * sam + (k0 + j) * sak]; }, Mv,
-                        [&](int k0, int j, int n) { return B[(k0 + j) * sbk + n * sbn]; }, Nv, Kv, acc);
-}
-
-// Z and D slices in LDS: entry (i1, i2) of a 16 x T2 slice at i2*16 + (i1 ^ (i2 & 15)).
-// Reading a 16-row column block along i2 (F1, Y) or a 16-column row block along i1
-// (F2) then touches 64 distinct banks per instruction, with no padding.
-__device__ __forceinline__ int zsw(int i1, int i2) { return i2 * 16 + (i1 ^ (i2 & 15)); }
-// The same for i2 = k0 + j with k0 a multiple of 16 and j < 16.
-__device__ __forceinline__ int zsw16(int i1, int k0, int j) { return (k0 + j) * 16 + (i1 ^ j); }
-
-// Store a 16 x 16 block: lane l holds rows 4*(l/16) + i, column l % 16.
-__device__ __forceinline__ void store_block(const mf4& acc, float* C, int scm, int scn, int Mv, int Nv) {
-  const int l = threadIdx.x & 63;
-  const int n = l & 15, m0 = 4 * (l >> 4);
-  if (n >= Nv) return;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-    if (m0 + i < Mv) C[(m0 + i) * scm + n * scn] = acc[i];
-}
 
 // LDS floats of one tile (T1 = 16) for ranks (r1, r2, r3), N3 and T2; `pst` stages
 // the pseudo-inverses that are needed (h1, h2, f3).

@@ -43,6 +43,8 @@ struct tdb_ctx {
   bool f32 = false;          // bulk passes in FP32 (or BF16-split products with FP32 sums)
   bool bf16s = false;        // BF16-split products in the matrix-core stage pass
   bool no_mfma = false;      // keep the generic stage pass (a batch with mixed shapes)
+  bool no_rpass = false;     // keep the tile pass in a batch (streams that disagree)
+  int rpass_cols = 64;       // columns of mode 2 per workgroup of the column-block pass
   bool data32 = false;       // snapshots stored as FP32
   size_t celt = 8;           // bytes per compute element
   size_t delt = 8;           // bytes per data element
@@ -229,6 +231,7 @@ long long prod_ll(const int* a, int p, int skip = -1) {
 struct PassPlan {
   int T1 = 1, T2 = 1, nt1 = 1, nt2 = 1, stage_p = 0;
   int mfma = 0;              // MPASS_* flavour of the stage pass
+  int rows = 0;              // 1: the column-block pass of batches (T1 = N1 padded, T2 columns)
   long long slot = 0;
   size_t lds = 0;
   bool ok = false;
@@ -266,6 +269,17 @@ bool mfma_ok(const tdb_ctx* h, const int* r, bool worst) {
   return mpass_bytes(h, r, 16, false, worst) <= (size_t)h->lds_max;
 }
 
+// Whether a batch member takes the column-block pass at ranks r (TDB_RPASS=0 turns it
+// off).
+bool rpass_ok(const tdb_ctx* h, const int* r, bool worst) {
+  if (!h->batch_owned || h->no_rpass || !mfma_ok(h, r, worst)) return false;
+  if (const char* env = std::getenv("TDB_RPASS"))
+    if (env[0] == '0') return false;
+  if (!rpass_shape_ok(r[0], r[1], r[2], h->rpass_cols, (int)h->N[2])) return false;
+  if (h->N[0] * h->N[1] * h->N[2] >= (1LL << 31)) return false;   // 32-bit offsets
+  return rpass_lds_bytes(h->rpass_cols, r[0], r[1], (int)h->N[2]) <= (size_t)h->lds_max;
+}
+
 // LDS up to which two matrix-core tiles still share a compute unit (160 KB each);
 // the pseudo-inverses are staged only within it, since occupancy hides more latency
 // than the staging saves.
@@ -278,6 +292,20 @@ size_t mpass_occupancy_budget(const tdb_ctx* h) { return std::min<size_t>((size_
 PassPlan plan_pass(const tdb_ctx* h, const int* r, bool worst = false) {
   PassPlan pl;
   const long long N1 = h->N[0], N2 = h->N[1], N3 = h->N[2];
+  if (rpass_ok(h, r, worst)) {
+    const int T2 = h->rpass_cols;
+    const int N1p = (int)((N1 + 15) & ~15LL);
+    pl.mfma = h->bf16s ? MPASS_BF16S : MPASS_F32;
+    pl.rows = 1;
+    pl.T1 = N1p;
+    pl.T2 = T2;
+    pl.nt1 = 1;
+    pl.nt2 = (int)((N2 + T2 - 1) / T2);
+    pl.slot = (long long)N1p * r[0] + (long long)T2 * r[1] + N3 * r[2] + (long long)r[0] * r[1] * r[2];
+    pl.lds = rpass_lds_bytes(T2, r[0], r[1], (int)N3);
+    pl.ok = true;
+    return pl;
+  }
   if (mfma_ok(h, r, worst)) {
     int T2 = 64;
     while (T2 > 16 && mpass_bytes(h, r, T2, false, worst) > (size_t)h->lds_max) T2 /= 2;
@@ -324,6 +352,15 @@ PassPlan plan_under(const tdb_ctx* h, const int* r, const PassPlan& base) {
   PassPlan pl = base;
   pl.slot = (long long)base.T1 * r[0] + (long long)base.T2 * r[1] + h->N[2] * r[2] + (long long)r[0] * r[1] * r[2];
   if (!base.ok) { pl.ok = false; return pl; }
+  if (base.rows) {
+    if (!rpass_shape_ok(r[0], r[1], r[2], base.T2, (int)h->N[2])) {
+      pl.ok = false;
+      return pl;
+    }
+    pl.lds = rpass_lds_bytes(base.T2, r[0], r[1], (int)h->N[2]);
+    if (pl.lds > (size_t)h->lds_max) pl.ok = false;
+    return pl;
+  }
   if (base.mfma) {
     // LDS of the current ranks (a batch launches with the largest over its streams)
     if (r[0] > 32 || r[1] > 32 || mpass_bytes(h, r, base.T2, false, false) > (size_t)h->lds_max) {
@@ -1526,6 +1563,9 @@ struct tdb_batch_ctx {
   size_t lds_pass = 0, lds_fin = 0, lds_qr = 0, lds_post = 0, lds_mprep = 0, lds_final = 0;
   size_t lds_rows = 0, lds_exp = 0;   // row blocks of the finish, expansion blocks of the post-step
   int mflavor = 0;                  // MPASS_* of the batched stage pass (one for all streams)
+  int rows = 0;                     // 1: the row-block pass (every stream takes it)
+  int vw = 0;                       // fiber load width of the row-block pass this step
+  int rp_n3c = 0;                   // mode-3 extent the column-block kernel is built for (0: any)
   std::vector<int> pass_blocks, pass_T1, pass_T2;   // each stream's stage-pass grid, fixed at the caps
   double bytes_pass = 0.0, bytes_err = 0.0;
   bool dirty = true;
@@ -1597,13 +1637,28 @@ tdb_status balloc(tdb_batch_ctx* b, X** d, X** hp, size_t count) {
   return TDB_OK;
 }
 
-// Block map of one batched kernel from the per-stream block counts.
-tdb_status make_map(tdb_batch_ctx* b, const std::vector<int>& counts, BatchMap* m, int* total) {
-  std::vector<int> start(counts.size() + 1, 0);
-  for (size_t i = 0; i < counts.size(); ++i) start[i + 1] = start[i] + counts[i];
-  std::vector<int> sid(std::max(start.back(), 1), 0);
-  for (size_t i = 0; i < counts.size(); ++i)
-    for (int k = start[i]; k < start[i + 1]; ++k) sid[k] = (int)i;
+// Block map of one batched kernel from the per-stream block counts. With `weight`
+// (the work of one block of each stream) the streams' block ranges are laid out
+// heaviest first, so the longest blocks are dispatched first and the short ones fill
+// the end of the launch; start[i] is then the first block of stream i but start[i+1]
+// is not its end, which only kernels that take their block count elsewhere may use.
+tdb_status make_map(tdb_batch_ctx* b, const std::vector<int>& counts, BatchMap* m, int* total,
+                    const std::vector<double>* weight = nullptr) {
+  const size_t n = counts.size();
+  std::vector<int> order(n);
+  for (size_t i = 0; i < n; ++i) order[i] = (int)i;
+  if (weight)
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return (*weight)[x] > (*weight)[y]; });
+  std::vector<int> start(n + 1, 0);
+  int acc = 0;
+  for (size_t j = 0; j < n; ++j) {
+    start[order[j]] = acc;
+    acc += counts[order[j]];
+  }
+  start[n] = acc;
+  std::vector<int> sid(std::max(acc, 1), 0);
+  for (size_t i = 0; i < n; ++i)
+    for (int k = start[i]; k < start[i] + counts[i]; ++k) sid[k] = (int)i;
   int *d_sid = nullptr, *d_start = nullptr;
   TRY(balloc<int>(b, &d_sid, nullptr, sid.size()));
   TRY(balloc<int>(b, &d_start, nullptr, start.size()));
@@ -1639,7 +1694,7 @@ tdb_status batch_upload_args(tdb_batch_ctx* b, hipStream_t s) {
     // current ranks must be exactly those blocks, and their partial slots and LDS must
     // fit what was allocated, or the step is refused before any launch.
     if (A.pl.T1 != b->pass_T1[i] || A.pl.T2 != b->pass_T2[i] || A.blocks_pass != b->pass_blocks[i] ||
-        A.pl.mfma != b->mflavor || A.pl.lds > (size_t)h->lds_max ||
+        A.pl.mfma != b->mflavor || A.pl.rows != b->rows || A.pl.lds > (size_t)h->lds_max ||
         (long long)A.pl.nt1 * A.pl.nt2 * A.pl.slot > h->fpart_elems) {
       b->err = "stream " + std::to_string(i) + ": the stage-pass tiles at ranks (" + std::to_string(h->r[0]) + ", " +
                std::to_string(h->r[1]) + ", " + std::to_string(h->r[2]) + ") do not fit the launch fixed at the caps";
@@ -1692,6 +1747,23 @@ tdb_status batch_setup(tdb_batch_ctx* b) {
   // one stage-pass kernel serves every stream: the matrix-core pass only when all
   // streams take it at their caps
   {
+    // the row-block pass only when every stream takes it; then the tile matrix-core
+    // pass only when every stream takes that; else the generic pass
+    {
+      // the column-block kernel is built for the mode-3 extent the streams share (4 or
+      // 8; else any up to 8), and that fixes its column count
+      int n3c = (int)b->st[0]->N[2];
+      for (int i = 1; i < n; ++i)
+        if (b->st[i]->N[2] != n3c) n3c = 0;
+      if (n3c != 4 && n3c != 8) n3c = 0;
+      b->rp_n3c = n3c;
+      for (int i = 0; i < n; ++i) b->st[i]->rpass_cols = rpass_cols_for(n3c);
+    }
+    bool all_rows = true;
+    for (int i = 0; i < n; ++i) all_rows = all_rows && plan_pass(b->st[i], b->st[i]->caps, true).rows == 1;
+    if (!all_rows)
+      for (int i = 0; i < n; ++i) b->st[i]->no_rpass = true;
+    b->rows = all_rows ? 1 : 0;
     int first = -1;
     bool mixed = false;
     for (int i = 0; i < n; ++i) {
@@ -1704,6 +1776,7 @@ tdb_status batch_setup(tdb_batch_ctx* b) {
     b->mflavor = mixed ? 0 : first;
   }
   std::vector<int> c_pass(n), c_red(n), c_fin0(n), c_fin1(n), c_qr(n, 3), c_qa(n), c_post(n), c_exp(n), c_err(n);
+  std::vector<double> w_pass(n, 0.0);
   for (int i = 0; i < n; ++i) {
     tdb_ctx* h = b->st[i];
     StepArgs A;
@@ -1716,6 +1789,7 @@ tdb_status batch_setup(tdb_batch_ctx* b) {
       return TDB_EUNSUPPORTED;
     }
     c_pass[i] = A.blocks_pass;
+    w_pass[i] = (double)A.pl.T1 * A.pl.T2 * h->N[2];
     b->pass_blocks.push_back(A.blocks_pass);
     b->pass_T1.push_back(A.pl.T1);
     b->pass_T2.push_back(A.pl.T2);
@@ -1742,7 +1816,7 @@ tdb_status batch_setup(tdb_batch_ctx* b) {
     b->bytes_pass += 2.0 * (double)h->S * (double)h->delt;
     b->bytes_err += (double)h->S * (double)h->delt;
   }
-  TRY(make_map(b, c_pass, &b->m_pass, &b->g_pass));
+  TRY(make_map(b, c_pass, &b->m_pass, &b->g_pass, &w_pass));
   TRY(make_map(b, c_red, &b->m_red, &b->g_red));
   TRY(make_map(b, c_fin0, &b->m_fin[0], &b->g_fin[0]));
   TRY(make_map(b, c_fin1, &b->m_fin[1], &b->g_fin[1]));
@@ -1777,6 +1851,16 @@ tdb_status batch_step(tdb_batch_ctx* b, const void* const* V, hipStream_t s) {
     b->h_v1[i] = V[i];
     b->h_v0[i] = b->st[i]->Vprev;
   }
+  {
+    // whole fibers as float4 loads when every stream's snapshots allow it
+    int vw = (sizeof(TD) == 4) ? (int)b->st[0]->N[2] : 0;
+    if (vw != 4 && vw != 8) vw = 0;
+    for (int i = 0; i < n && vw; ++i) {
+      const uintptr_t a1 = reinterpret_cast<uintptr_t>(b->h_v1[i]), a0 = reinterpret_cast<uintptr_t>(b->h_v0[i]);
+      if (b->st[i]->N[2] != vw || ((a1 | a0) & 15) != 0 || !b->h_v0[i]) vw = 0;
+    }
+    b->vw = vw;
+  }
   BHIPCHK(hipMemcpyAsync(b->d_v1, b->h_v1, n * sizeof(void*), hipMemcpyHostToDevice, s));
   BHIPCHK(hipMemcpyAsync(b->d_v0, b->h_v0, n * sizeof(void*), hipMemcpyHostToDevice, s));
   if (b->dirty) TRY(batch_upload_args(b, s));
@@ -1788,7 +1872,10 @@ tdb_status batch_step(tdb_batch_ctx* b, const void* const* V, hipStream_t s) {
       if (e0 && e1) b->ev_used[TDB_PASS_PROJECT].push_back({e0, e1});
       else e0 = e1 = nullptr;
     }
-    if (b->mflavor)
+    if (b->rows)
+      BHIPCHK((launch_batch_rpass<TD>(b->d_fa[st], b->d_v1, b->d_v0, b->m_pass, b->g_pass, b->mflavor, b->rp_n3c, b->vw,
+                                      b->lds_pass, s, e0, e1)));
+    else if (b->mflavor)
       BHIPCHK((launch_batch_mpass<TD>(b->d_fa[st], b->d_v1, b->d_v0, b->m_pass, b->g_pass, b->mflavor, b->lds_pass,
                                       s, e0, e1)));
     else

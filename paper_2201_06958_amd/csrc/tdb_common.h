@@ -9,6 +9,17 @@
 #define TDB_NEIG 512     // largest mode size for the device HOSVD eigensolver
 #define TDB_BLOCK 256    // threads per block of the small FP64 kernels
 
+// Pointers into device memory that the kernels take from argument tables held in
+// device memory: the compiler cannot tell that they address global memory and would
+// use flat instructions, and a flat access in flight makes every later wait drain all
+// memory counters (no load can be kept in flight across a local-memory access). The
+// kernels convert them once with gmem and keep the global type.
+#define TDB_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ TDB_GLOBAL T* gmem(T* p) {
+  return (TDB_GLOBAL T*)p;
+}
+
 // Controller events (same values as the TDB_EV_* codes of the public header).
 enum { EV_NONE = 0, EV_REINIT = 1, EV_ADD = 2, EV_REMOVE = 3, EV_NUMERIC = 4 };
 
