@@ -236,9 +236,13 @@ hipError_t launch_batch_fqr(const FQrArgs* tab, CtrlState* const* ctab, BatchMap
 template <typename T>
 hipError_t launch_batch_fpost(const FPostArgs* tab, CtrlState* const* ctab, BatchMap m, int blocks, size_t lds,
                               int role, hipStream_t s);
+// r1c (4..32, a multiple of 4): the column-block error pass compiled for r1 <= r1c
+// (every stream's plan has gx = ceil(M/FEC_COLS) blocks of all rows, gy = 1); 0: the
+// slab pass.
+#define FEC_COLS 256
 template <typename TD, typename T>
 hipError_t launch_batch_ferr(const FErrArgs* tab, const void* const* v1, BatchMap m, int blocks, int nstreams,
-                             CtrlState* const* ctab, BatchSummary* out, size_t lds_final, hipStream_t s,
+                             CtrlState* const* ctab, BatchSummary* out, size_t lds_final, int r1c, hipStream_t s,
                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 }  // namespace tdb

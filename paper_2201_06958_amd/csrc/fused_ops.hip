@@ -1464,11 +1464,130 @@ template hipError_t launch_batch_fpost<float>(const FPostArgs*, CtrlState* const
 template hipError_t launch_batch_fpost<double>(const FPostArgs*, CtrlState* const*, BatchMap, int, size_t, int,
                                                hipStream_t);
 
+// Column-block error pass of batches (eq. (error)): block bx of a stream takes the
+// FEC_COLS consecutive columns j = FEC_COLS bx + t of the mode-1 unfolding
+// (j = i2*N3 + i3) with all N1 rows. Thread t keeps its column of E (a < r1, zero up to
+// R1C) in registers; the rows of U1 (compute type) and w1 are staged in LDS FEC_ROWS at
+// a time and read as broadcasts; the snapshot rows stream through, the next FEC_PF rows
+// in flight while FEC_PF are used (loads past the last row clamp to it, so every load
+// is issued on every path). A column's sums over its rows are w1[i] d_i^2 and
+// w1[i] v_i^2 in FP64, scaled by w23[j] once; the block's fixed-order sum is its
+// partial.
+#define FEC_ROWS 128
+#define FEC_PF 8
+template <typename TD, typename T, int R1C>
+__global__ void __launch_bounds__(FEC_COLS) kb_ferr_cols(const FErrArgs* __restrict__ tab, const void* const* v1,
+                                                         BatchMap m) {
+  __shared__ double red[16];
+  __shared__ __align__(16) T U1s[FEC_ROWS * R1C];
+  __shared__ double w1s[FEC_ROWS];
+  const int s = m.sid[blockIdx.x];
+  const FErrArgs a = tab[s];
+  const int bx = blockIdx.x - m.start[s];
+  TDB_GLOBAL double* part = gmem(a.part);
+  if (a.skip && *gmem(a.skip)) {
+    // the learned gate skips this step's pass
+    if (threadIdx.x == 0) {
+      part[2 * bx] = 0.0;
+      part[2 * bx + 1] = 0.0;
+    }
+    return;
+  }
+  const long long M = a.M;
+  const int N1 = a.N1, r1 = a.r1, tid = threadIdx.x;
+  const long long j = (long long)bx * FEC_COLS + tid;
+  const bool jok = j < M;
+  const long long jc = jok ? j : M - 1;
+  const TDB_GLOBAL TD* V = gmem(static_cast<const TD*>(v1[s])) + jc;
+  const TDB_GLOBAL T* E = gmem(static_cast<const T*>(a.E)) + jc;
+  const TDB_GLOBAL T* U1 = gmem(static_cast<const T*>(a.U1c));
+  const TDB_GLOBAL double* w1 = gmem(a.w1);
+  T e[R1C];
+#pragma unroll
+  for (int k = 0; k < R1C; ++k) {
+    const T x = E[(long long)min(k, r1 - 1) * M];
+    e[k] = k < r1 ? x : (T)0;
+  }
+  const double w23j = gmem(a.w23)[jc];
+  double se = 0.0, sv = 0.0;
+  TD va[FEC_PF], vb[FEC_PF];
+  auto vload = [&](TD (&vv)[FEC_PF], int i0) {
+#pragma unroll
+    for (int q = 0; q < FEC_PF; ++q) vv[q] = V[(long long)min(i0 + q, N1 - 1) * M];
+  };
+  auto rows = [&](const TD (&vv)[FEC_PF], int g0, int nr) {
+#pragma unroll
+    for (int q = 0; q < FEC_PF; ++q) {
+      const int il = g0 + q;
+      if (il < nr) {
+        const T* u = U1s + il * R1C;
+        T x = (T)0;
+#pragma unroll
+        for (int k = 0; k < R1C; ++k) x += u[k] * e[k];
+        const T v = (T)vv[q];
+        const T d = v - x;
+        const double wi = w1s[il];
+        se += wi * (double)(d * d);
+        sv += wi * (double)(v * v);
+      }
+    }
+  };
+  vload(va, 0);
+  for (int c0 = 0; c0 < N1; c0 += FEC_ROWS) {
+    const int nr = min(FEC_ROWS, N1 - c0);
+    __syncthreads();
+    {
+      // rows c0 .. c0+nr of U1, zero-padded to R1C columns, eight loads in flight
+      const int ne = nr * R1C;
+      for (int t0 = 0; t0 < ne; t0 += 8 * FEC_COLS) {
+        T x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int t = min(t0 + u * FEC_COLS + tid, ne - 1);
+          const int q = t / R1C, k = t - (t / R1C) * R1C;
+          x[u] = U1[(long long)(c0 + q) * r1 + min(k, r1 - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int t = t0 + u * FEC_COLS + tid;
+          if (t < ne) U1s[t] = (t - (t / R1C) * R1C) < r1 ? x[u] : (T)0;
+        }
+      }
+      if (tid < nr) w1s[tid] = w1[c0 + tid];
+    }
+    __syncthreads();
+    // a full chunk ends with the first rows of the next one in flight in va
+    for (int g0 = 0; g0 < nr; g0 += 2 * FEC_PF) {
+      vload(vb, c0 + g0 + FEC_PF);
+      rows(va, g0, nr);
+      vload(va, c0 + g0 + 2 * FEC_PF);
+      rows(vb, g0 + FEC_PF, nr);
+    }
+  }
+  se = jok ? se * w23j : 0.0;
+  sv = jok ? sv * w23j : 0.0;
+  se = block_sum(se, red);
+  sv = block_sum(sv, red);
+  if (tid == 0) {
+    part[2 * bx] = se;
+    part[2 * bx + 1] = sv;
+  }
+}
+
 template <typename TD, typename T>
 hipError_t launch_batch_ferr(const FErrArgs* tab, const void* const* v1, BatchMap m, int blocks, int nstreams,
-                             CtrlState* const* ctab, BatchSummary* out, size_t lds_final, hipStream_t s,
+                             CtrlState* const* ctab, BatchSummary* out, size_t lds_final, int r1c, hipStream_t s,
                              hipEvent_t ev0, hipEvent_t ev1) {
-  hipExtLaunchKernelGGL((kb_ferr<TD, T>), dim3(blocks), dim3(256), 0u, s, ev0, ev1, 0u, tab, v1, m);
+  switch (r1c) {
+#define FEC_CASE(R)                                                                                            \
+  case R:                                                                                                      \
+    hipExtLaunchKernelGGL((kb_ferr_cols<TD, T, R>), dim3(blocks), dim3(FEC_COLS), 0u, s, ev0, ev1, 0u, tab, v1, m); \
+    break;
+    FEC_CASE(4) FEC_CASE(8) FEC_CASE(12) FEC_CASE(16) FEC_CASE(20) FEC_CASE(24) FEC_CASE(28) FEC_CASE(32)
+#undef FEC_CASE
+    default:
+      hipExtLaunchKernelGGL((kb_ferr<TD, T>), dim3(blocks), dim3(256), 0u, s, ev0, ev1, 0u, tab, v1, m);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)kb_ferr_final, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_final);
@@ -1477,12 +1596,12 @@ hipError_t launch_batch_ferr(const FErrArgs* tab, const void* const* v1, BatchMa
   return hipGetLastError();
 }
 template hipError_t launch_batch_ferr<float, float>(const FErrArgs*, const void* const*, BatchMap, int, int, CtrlState* const*,
-                                                   BatchSummary*, size_t, hipStream_t, hipEvent_t, hipEvent_t);
+                                                   BatchSummary*, size_t, int, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_batch_ferr<float, double>(const FErrArgs*, const void* const*, BatchMap, int, int, CtrlState* const*,
-                                                   BatchSummary*, size_t, hipStream_t, hipEvent_t, hipEvent_t);
+                                                   BatchSummary*, size_t, int, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_batch_ferr<double, double>(const FErrArgs*, const void* const*, BatchMap, int, int, CtrlState* const*,
-                                                   BatchSummary*, size_t, hipStream_t, hipEvent_t, hipEvent_t);
+                                                   BatchSummary*, size_t, int, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_batch_ferr<double, float>(const FErrArgs*, const void* const*, BatchMap, int, int, CtrlState* const*,
-                                                   BatchSummary*, size_t, hipStream_t, hipEvent_t, hipEvent_t);
+                                                   BatchSummary*, size_t, int, hipStream_t, hipEvent_t, hipEvent_t);
 
 }  // namespace tdb

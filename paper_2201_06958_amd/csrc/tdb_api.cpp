@@ -44,6 +44,7 @@ struct tdb_ctx {
   bool bf16s = false;        // BF16-split products in the matrix-core stage pass
   bool no_mfma = false;      // keep the generic stage pass (a batch with mixed shapes)
   bool no_rpass = false;     // keep the tile pass in a batch (streams that disagree)
+  bool ferr_cols = false;    // batch member on the column-block error pass
   int rpass_cols = 64;       // columns of mode 2 per workgroup of the column-block pass
   bool data32 = false;       // snapshots stored as FP32
   size_t celt = 8;           // bytes per compute element
@@ -574,7 +575,8 @@ tdb_status setup_fused(tdb_ctx* h, const std::vector<std::vector<double>>& wh) {
   const long long M = h->N[1] * h->N[2];
   h->ferr_gx = (int)std::max<long long>(1, std::min<long long>(64, (M + 255) / 256));
   h->ferr_gy = (int)((h->N[0] + FERR_T1 - 1) / FERR_T1);
-  TRY(dallocT(h, &h->ferr_part, 2 * (size_t)h->ferr_gx * h->ferr_gy));
+  // partials of the slab error pass or of the column-block one (batches)
+  TRY(dallocT(h, &h->ferr_part, 2 * std::max<size_t>((size_t)h->ferr_gx * h->ferr_gy, (size_t)((M + FEC_COLS - 1) / FEC_COLS))));
   TRY(dalloc(h, reinterpret_cast<void**>(&h->counters), 8 * sizeof(unsigned)));
   HIPCHK(hipMemset(h->counters, 0, 8 * sizeof(unsigned)));
   return TDB_OK;
@@ -1260,6 +1262,13 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
   for (int n = 0; n < 3; ++n) ea.G[n] = h->Gsave[n];
   ea.rmax = max_rank_of(rl, 3);
   A.blocks_err = h->ferr_gx * h->ferr_gy;
+  if (h->ferr_cols) {
+    // column-block error pass: FEC_COLS columns of the mode-1 unfolding with all rows per block
+    ea.T1 = 0;
+    ea.gx = (int)((ea.M + FEC_COLS - 1) / FEC_COLS);
+    ea.gy = 1;
+    A.blocks_err = ea.gx;
+  }
   // every small kernel's LDS must fit, or the step goes to the plain path
   const size_t lmax = (size_t)h->lds_max;
   if (A.lds_fin > lmax || (!ga.m_inline && A.lds_mprep > lmax) || A.lds_qr > lmax || A.lds_post > lmax ||
@@ -1566,6 +1575,7 @@ struct tdb_batch_ctx {
   int rows = 0;                     // 1: the row-block pass (every stream takes it)
   int vw = 0;                       // fiber load width of the row-block pass this step
   int rp_n3c = 0;                   // mode-3 extent the column-block kernel is built for (0: any)
+  int err_r1c = 0;                  // column-block error pass compiled for r1 <= err_r1c (0: slab pass)
   std::vector<int> pass_blocks, pass_T1, pass_T2;   // each stream's stage-pass grid, fixed at the caps
   double bytes_pass = 0.0, bytes_err = 0.0;
   bool dirty = true;
@@ -1775,8 +1785,18 @@ tdb_status batch_setup(tdb_batch_ctx* b) {
       for (int i = 0; i < n; ++i) b->st[i]->no_mfma = true;
     b->mflavor = mixed ? 0 : first;
   }
+  {
+    // the column-block error pass keeps a column of E in registers: every stream's
+    // mode-1 rank cap at most 32 (compiled for the cap rounded up to 4)
+    int r1max = 0;
+    for (int i = 0; i < n; ++i) r1max = std::max(r1max, b->st[i]->caps[0]);
+    const char* env = std::getenv("TDB_FERR_COLS");
+    const bool cols = r1max <= 32 && !(env && env[0] == '0');
+    b->err_r1c = cols ? (r1max + 3) / 4 * 4 : 0;
+    for (int i = 0; i < n; ++i) b->st[i]->ferr_cols = cols;
+  }
   std::vector<int> c_pass(n), c_red(n), c_fin0(n), c_fin1(n), c_qr(n, 3), c_qa(n), c_post(n), c_exp(n), c_err(n);
-  std::vector<double> w_pass(n, 0.0);
+  std::vector<double> w_pass(n, 0.0), w_err(n, 0.0);
   for (int i = 0; i < n; ++i) {
     tdb_ctx* h = b->st[i];
     StepArgs A;
@@ -1800,6 +1820,7 @@ tdb_status batch_setup(tdb_batch_ctx* b) {
     c_qa[i] = A.blocks_qr;
     c_exp[i] = A.pa.eblocks;
     c_err[i] = A.blocks_err;
+    w_err[i] = b->err_r1c ? (double)h->N[0] : 1.0;
     {
       long long msum = 0;
       for (int k = 0; k < 3; ++k) msum += (long long)h->caps[k] * h->caps[k];
@@ -1824,7 +1845,7 @@ tdb_status batch_setup(tdb_batch_ctx* b) {
   TRY(make_map(b, c_qa, &b->m_qa, &b->g_qa));
   TRY(make_map(b, c_post, &b->m_post, &b->g_post));
   TRY(make_map(b, c_exp, &b->m_exp, &b->g_exp));
-  TRY(make_map(b, c_err, &b->m_err, &b->g_err));
+  TRY(make_map(b, c_err, &b->m_err, &b->g_err, &w_err));
   const size_t nn = (size_t)n;
   TRY(balloc(b, &b->d_fa[0], &b->h_fa[0], nn));
   TRY(balloc(b, &b->d_fa[1], &b->h_fa[1], nn));
@@ -1914,7 +1935,7 @@ tdb_status batch_step(tdb_batch_ctx* b, const void* const* V, hipStream_t s) {
       if (e0 && e1) b->ev_used[TDB_PASS_ERROR].push_back({e0, e1});
       else e0 = e1 = nullptr;
     }
-    BHIPCHK((launch_batch_ferr<TD, T>(b->d_ea, b->d_v1, b->m_err, b->g_err, n, b->d_ctab, b->d_sum, b->lds_final, s,
+    BHIPCHK((launch_batch_ferr<TD, T>(b->d_ea, b->d_v1, b->m_err, b->g_err, n, b->d_ctab, b->d_sum, b->lds_final, b->err_r1c, s,
                                       e0, e1)));
   }
   BHIPCHK(hipMemcpyAsync(b->h_sum, b->d_sum, n * sizeof(BatchSummary), hipMemcpyDeviceToHost, s));
