@@ -126,6 +126,8 @@ typedef struct {
                                           stream falls back to the plain path for a step
                                           whose stage pass does not fit the LDS)       */
   int64_t n_nonfinite;                 /* steps not applied for NaN/Inf data           */
+  int64_t graph_steps;                 /* batch members: launches of the batch's step
+                                          replayed from a HIP graph (0 otherwise)      */
 } tdb_stats;
 
 /* Initialise from the first snapshot by a weighted HOSVD (Sec. 2.3). V0_dev: device
@@ -245,7 +247,18 @@ tdb_status tdb_profile_read(tdb_handle h, int32_t pass, int64_t* launches, doubl
  *   the LDS at its caps.
  * tdb_batch_ingest: V_dev is a host array of n device pointers, one snapshot per
  *   stream, each C-contiguous in data_dtype. Snapshot ownership as in
- *   tdb_ingest_snapshot, per stream.
+ *   tdb_ingest_snapshot, per stream. When every stream has TDB_BORROW snapshots the
+ *   call is pipelined as tdb_ingest_snapshot is: it enqueues this step for all
+ *   streams on `stream`, then reads the previous step's summaries (without
+ *   synchronising the device) and acts on the decisions that need the host; the
+ *   device holds such a stream's part of this step, which then runs again for those
+ *   streams alone. The newest step is read by the next ingest, by tdb_batch_flush or
+ *   by any call that returns a member's results; TDB_ENUMERIC is reported by the call
+ *   that reads the step. The launches of a step are replayed from a HIP graph, one per
+ *   step parity, captured again when the launch shapes change (TDB_GRAPH=0 in the
+ *   environment launches them one by one; TDB_PIPELINE=0 reads every step at once).
+ * tdb_batch_flush: reads the newest step if it has not been read; returns its
+ *   status.
  * tdb_batch_stream: a handle of stream i for tdb_get_stats, tdb_get_core_and_bases,
  *   tdb_reconstruct and tdb_set_threshold. The batch owns it: tdb_ingest_snapshot on
  *   it returns TDB_ESTATE and tdb_destroy ignores it.
@@ -257,6 +270,7 @@ typedef struct tdb_batch_ctx* tdb_batch;
 tdb_status tdb_batch_create(int32_t n, const tdb_config* cfgs, const void* const* V0_dev, void* stream,
                             tdb_batch* out);
 tdb_status tdb_batch_ingest(tdb_batch b, const void* const* V_dev, void* stream);
+tdb_status tdb_batch_flush(tdb_batch b);
 tdb_status tdb_batch_stream(tdb_batch b, int32_t i, tdb_handle* out);
 tdb_status tdb_batch_profile_enable(tdb_batch b, int32_t on);
 tdb_status tdb_batch_profile_read(tdb_batch b, int32_t pass, int64_t* launches, double* total_ms,

@@ -108,6 +108,7 @@ struct FErrArgs {
   const double* G[3];        // core Grams of the committed state (lazy singular values)
   int rmax;                  // largest rank (LDS of the final kernel)
   const int* skip;           // the learned gate skips this pass (NULL: never)
+  const int* hold;           // the controller's hold flag (batches: the pass does nothing while set)
   const int* would_skip;     // the gate's verdict, recorded in the controller state
   const float* yhat;         // the gate's prediction (log10 of the error)
   CtrlState* mirror;         // pinned host copy of the controller state the final kernel
@@ -240,9 +241,17 @@ hipError_t launch_batch_fpost(const FPostArgs* tab, CtrlState* const* ctab, Batc
 // (every stream's plan has gx = ceil(M/FEC_COLS) blocks of all rows, gy = 1); 0: the
 // slab pass.
 #define FEC_COLS 256
+// The final kernel writes stream i's summary to out[i] (streams found held write
+// nothing) and, with counter (device, zero between launches) given, advances *seq once
+// every stream's summary is visible to the host.
 template <typename TD, typename T>
 hipError_t launch_batch_ferr(const FErrArgs* tab, const void* const* v1, BatchMap m, int blocks, int nstreams,
-                             CtrlState* const* ctab, BatchSummary* out, size_t lds_final, int r1c, hipStream_t s,
-                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                             CtrlState* const* ctab, BatchSummary* out, unsigned* counter, unsigned long long* seq,
+                             size_t lds_final, int r1c, hipStream_t s, hipEvent_t ev0 = nullptr,
+                             hipEvent_t ev1 = nullptr);
+hipError_t launch_batch_fetch_ptrs(const void* const* h1, const void* const* h0, const void** d1, const void** d0,
+                                   int n, hipStream_t s);
+hipError_t launch_batch_hold_mask(CtrlState* const* ctab, const int* mask, int* save, int n, int restore,
+                                  hipStream_t s);
 
 }  // namespace tdb

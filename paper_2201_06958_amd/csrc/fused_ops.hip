@@ -1355,48 +1355,107 @@ template <typename TD, typename T>
 __global__ void __launch_bounds__(256) kb_ferr(const FErrArgs* __restrict__ tab, const void* const* v1, BatchMap m) {
   const int s = m.sid[blockIdx.x];
   FErrArgs a = tab[s];
+  if (a.hold && *gmem(a.hold)) return;   // a decision awaits the host
   a.V = v1[s];
   const int l = blockIdx.x - m.start[s];
   ferr_body<TD, T>(a, l % a.gx, l / a.gx, a.gx);
 }
 
 // One block per stream: the fixed-order sum of that stream's error-pass partials,
-// its controller decision, and the summary the host reads.
+// its controller decision, and the summary the host reads. A decision that needs the
+// host (any but none and a discarded step) raises the stream's hold flag: the kernels
+// of steps enqueued behind it do nothing for that stream until the host has acted. A
+// stream found held reports nothing (its step did not run). `out` may be pinned host
+// memory: every block counts itself done after its summary is visible system-wide, and
+// the last one resets the count and advances *seq, on which the host waits.
 __global__ void __launch_bounds__(256) kb_ferr_final(const FErrArgs* __restrict__ tab, CtrlState* const* ctab,
-                                                     BatchSummary* out) {
+                                                     BatchSummary* out, unsigned* counter,
+                                                     unsigned long long* seq) {
   __shared__ double red[16];
+  __shared__ int held;
   const int s = blockIdx.x;
-  const double* part = tab[s].part;
-  const int nb = tab[s].gx * tab[s].gy;
   CtrlState* ctrl = ctab[s];
-  double s0 = 0.0, s1 = 0.0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-    s0 += part[2 * i];
-    s1 += part[2 * i + 1];
-  }
-  s0 = block_sum(s0, red);
-  s1 = block_sum(s1, red);
-  if (threadIdx.x == 0 && !(tab[s].skip && *tab[s].skip)) {
-    ctrl->eps2 = s0;
-    ctrl->nu2 = s1;
-  }
+  if (threadIdx.x == 0) held = ctrl->hold;
   __syncthreads();
-  fused_decide(ctrl, tab[s].G, tab[s].rmax, tab[s].skip, tab[s].would_skip, tab[s].yhat);
-  if (threadIdx.x == 0) {
-    BatchSummary q;
-    q.decision = ctrl->decision;
-    q.event = ctrl->event;
-    q.numeric = ctrl->numeric;
-    q.gated = ctrl->gated;
-    for (int k = 0; k < 5; ++k) q.n_events[k] = ctrl->n_events[k];
-    q.would_skip = ctrl->would_skip;
-    q.eps = ctrl->eps;
-    q.nu = ctrl->nu;
-    q.eps2 = ctrl->eps2;
-    q.nu2 = ctrl->nu2;
-    q.eps_pred = ctrl->eps_pred;
-    out[s] = q;
+  if (!held) {
+    const double* part = tab[s].part;
+    const int nb = tab[s].gx * tab[s].gy;
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+      s0 += part[2 * i];
+      s1 += part[2 * i + 1];
+    }
+    s0 = block_sum(s0, red);
+    s1 = block_sum(s1, red);
+    if (threadIdx.x == 0 && !(tab[s].skip && *tab[s].skip)) {
+      ctrl->eps2 = s0;
+      ctrl->nu2 = s1;
+    }
+    __syncthreads();
+    fused_decide(ctrl, tab[s].G, tab[s].rmax, tab[s].skip, tab[s].would_skip, tab[s].yhat);
+    if (threadIdx.x == 0) {
+      ctrl->hold = (ctrl->decision != DEC_NONE && ctrl->decision != DEC_NONFINITE) ? 1 : 0;
+      BatchSummary q;
+      q.decision = ctrl->decision;
+      q.event = ctrl->event;
+      q.numeric = ctrl->numeric;
+      q.gated = ctrl->gated;
+      for (int k = 0; k < 5; ++k) q.n_events[k] = ctrl->n_events[k];
+      q.would_skip = ctrl->would_skip;
+      q.eps = ctrl->eps;
+      q.nu = ctrl->nu;
+      q.eps2 = ctrl->eps2;
+      q.nu2 = ctrl->nu2;
+      q.eps_pred = ctrl->eps_pred;
+      out[s] = q;
+    }
   }
+  if (threadIdx.x == 0 && counter) {
+    __threadfence_system();
+    if (atomicAdd(counter, 1u) == gridDim.x - 1) {
+      atomicExch(counter, 0u);
+      __threadfence_system();
+      volatile unsigned long long* w = seq;
+      *w = *w + 1;
+      __threadfence_system();
+    }
+  }
+}
+
+// The step's snapshot pointers from the pinned tables the host filled for it into the
+// device tables the kernels read.
+__global__ void kb_fetch_ptrs(const void* const* h1, const void* const* h0, const void** d1, const void** d0,
+                              int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    d1[i] = h1[i];
+    d0[i] = h0[i];
+  }
+}
+
+// Streams with mask[i] set are held for a re-run of the other streams' step: their
+// hold flag is saved and raised (restore = 0), or put back (restore = 1).
+__global__ void kb_hold_mask(CtrlState* const* ctab, const int* mask, int* save, int n, int restore) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    if (!mask[i]) continue;
+    if (restore) {
+      ctab[i]->hold = save[i];
+    } else {
+      save[i] = ctab[i]->hold;
+      ctab[i]->hold = 1;
+    }
+  }
+}
+
+hipError_t launch_batch_fetch_ptrs(const void* const* h1, const void* const* h0, const void** d1, const void** d0,
+                                   int n, hipStream_t s) {
+  hipLaunchKernelGGL(kb_fetch_ptrs, dim3((n + 255) / 256), dim3(256), 0, s, h1, h0, d1, d0, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_hold_mask(CtrlState* const* ctab, const int* mask, int* save, int n, int restore,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(kb_hold_mask, dim3((n + 255) / 256), dim3(256), 0, s, ctab, mask, save, n, restore);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -1483,6 +1542,7 @@ __global__ void __launch_bounds__(FEC_COLS) kb_ferr_cols(const FErrArgs* __restr
   __shared__ double w1s[FEC_ROWS];
   const int s = m.sid[blockIdx.x];
   const FErrArgs a = tab[s];
+  if (a.hold && *gmem(a.hold)) return;   // a decision awaits the host
   const int bx = blockIdx.x - m.start[s];
   TDB_GLOBAL double* part = gmem(a.part);
   if (a.skip && *gmem(a.skip)) {
@@ -1576,8 +1636,8 @@ __global__ void __launch_bounds__(FEC_COLS) kb_ferr_cols(const FErrArgs* __restr
 
 template <typename TD, typename T>
 hipError_t launch_batch_ferr(const FErrArgs* tab, const void* const* v1, BatchMap m, int blocks, int nstreams,
-                             CtrlState* const* ctab, BatchSummary* out, size_t lds_final, int r1c, hipStream_t s,
-                             hipEvent_t ev0, hipEvent_t ev1) {
+                             CtrlState* const* ctab, BatchSummary* out, unsigned* counter, unsigned long long* seq,
+                             size_t lds_final, int r1c, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   switch (r1c) {
 #define FEC_CASE(R)                                                                                            \
   case R:                                                                                                      \
@@ -1592,16 +1652,20 @@ hipError_t launch_batch_ferr(const FErrArgs* tab, const void* const* v1, BatchMa
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)kb_ferr_final, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_final);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kb_ferr_final, dim3(nstreams), dim3(256), lds_final, s, tab, ctab, out);
+  hipLaunchKernelGGL(kb_ferr_final, dim3(nstreams), dim3(256), lds_final, s, tab, ctab, out, counter, seq);
   return hipGetLastError();
 }
 template hipError_t launch_batch_ferr<float, float>(const FErrArgs*, const void* const*, BatchMap, int, int, CtrlState* const*,
-                                                   BatchSummary*, size_t, int, hipStream_t, hipEvent_t, hipEvent_t);
+                                                   BatchSummary*, unsigned*, unsigned long long*, size_t, int,
+                                                   hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_batch_ferr<float, double>(const FErrArgs*, const void* const*, BatchMap, int, int, CtrlState* const*,
-                                                   BatchSummary*, size_t, int, hipStream_t, hipEvent_t, hipEvent_t);
+                                                   BatchSummary*, unsigned*, unsigned long long*, size_t, int,
+                                                   hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_batch_ferr<double, double>(const FErrArgs*, const void* const*, BatchMap, int, int, CtrlState* const*,
-                                                   BatchSummary*, size_t, int, hipStream_t, hipEvent_t, hipEvent_t);
+                                                   BatchSummary*, unsigned*, unsigned long long*, size_t, int,
+                                                   hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_batch_ferr<double, float>(const FErrArgs*, const void* const*, BatchMap, int, int, CtrlState* const*,
-                                                   BatchSummary*, size_t, int, hipStream_t, hipEvent_t, hipEvent_t);
+                                                   BatchSummary*, unsigned*, unsigned long long*, size_t, int,
+                                                   hipStream_t, hipEvent_t, hipEvent_t);
 
 }  // namespace tdb

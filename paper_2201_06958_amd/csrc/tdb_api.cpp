@@ -105,6 +105,7 @@ struct tdb_ctx {
   int *g_hcount = nullptr, *g_skip = nullptr, *g_would = nullptr;
   CtrlState** g_ctab = nullptr;  // device array holding ctrl (the inference kernel takes a table)
   bool batch_owned = false;      // lives inside a tdb_batch
+  tdb_batch_ctx* owner = nullptr;   // that batch (its pending step is resolved for reads)
   bool sigma_stale = false;      // stats.sigma not refreshed since the last batched step
   // pipelined ingest (fused path, borrowed snapshots): each call enqueues its step and
   // then reads the previous step's decision, so the device never waits for the host
@@ -805,6 +806,10 @@ double compression_ratio(const tdb_ctx* h) {
   return num / (den + core);
 }
 
+// batch members: their batch's newest step is read first; graph replay count
+tdb_status batch_resolve(tdb_batch_ctx* b);
+long long batch_graph_steps(const tdb_batch_ctx* b);
+
 void fill_stats(tdb_ctx* h, bool initial) {
   const CtrlState& c = *h->ctrl_h;
   tdb_stats& st = h->stats;
@@ -833,6 +838,7 @@ void fill_stats(tdb_ctx* h, bool initial) {
   st.fused_steps = h->fused_steps;
   st.plain_steps = h->plain_steps;
   st.n_nonfinite = h->n_nonfinite;
+  st.graph_steps = h->owner ? batch_graph_steps(h->owner) : 0;
 }
 
 hipEvent_t take_event(tdb_ctx* h) {
@@ -1258,6 +1264,7 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
   ea.w1 = h->w[0];
   ea.w23 = h->w23;
   ea.part = h->ferr_part;
+  ea.hold = &h->ctrl->hold;
   ea.counter = h->counters + 1;
   for (int n = 0; n < 3; ++n) ea.G[n] = h->Gsave[n];
   ea.rmax = max_rank_of(rl, 3);
@@ -1419,6 +1426,7 @@ tdb_status resolve_step(tdb_ctx* h) {
 }
 
 tdb_status resolve_pending(tdb_ctx* h) {
+  if (h->owner) return batch_resolve(h->owner);
   if (!h->pending) return TDB_OK;
   if (h->data32) return h->f32 ? resolve_step<float, float>(h) : resolve_step<float, double>(h);
   return h->f32 ? resolve_step<double, float>(h) : resolve_step<double, double>(h);
@@ -1564,8 +1572,30 @@ struct tdb_batch_ctx {
   FPostArgs *d_pa = nullptr, *h_pa = nullptr;
   FErrArgs *d_ea = nullptr, *h_ea = nullptr;
   CtrlState** d_ctab = nullptr;
-  const void **d_v1 = nullptr, **d_v0 = nullptr, **h_v1 = nullptr, **h_v0 = nullptr;
-  BatchSummary *d_sum = nullptr, *h_sum = nullptr;
+  const void **d_v1 = nullptr, **d_v0 = nullptr;
+  // A step's snapshot pointers go to pinned tables by step parity (a kernel copies them
+  // to d_v1/d_v0), its summaries to pinned buffers by parity, and the last block of its
+  // final error kernel advances the parity's sequence word. With pipelining (every
+  // stream borrows its snapshots) the host reads a step while the next one runs; a
+  // stream whose decision needs the host is held by the device until the host has
+  // acted, and its next step runs again for it alone.
+  const void** h_vt[2][2] = {};     // [parity][V1, V0], pinned
+  BatchSummary* h_sumb[2] = {};     // pinned
+  unsigned long long* seq_h = nullptr;   // pinned, one word per parity
+  unsigned long long seq_want[2] = {0, 0};
+  unsigned* d_counter = nullptr;
+  int* h_mask = nullptr;            // pinned: streams held while the others' step runs again
+  int* d_hsave = nullptr;
+  bool pipelined = false, pending = false;
+  int parity = 0;                   // parity of the next step
+  std::vector<const void*> pend_V;
+  hipStream_t pend_stream = nullptr;
+  // the step's launches as one graph per parity (TDB_GRAPH=0: plain launches)
+  bool use_graph = true;
+  long long graph_steps = 0;        // launches replayed from a graph
+  hipStream_t cap = nullptr;        // captures only (a graph launches on the caller's stream)
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int gkey[2] = {-1, -1};
   // block maps (fixed at creation: grids are sized at the caps)
   BatchMap m_pass{}, m_red{}, m_fin[2]{}, m_qr{}, m_qa{}, m_post{}, m_exp{}, m_err{};
   int g_pass = 0, g_red = 0, g_fin[2] = {0, 0}, g_qr = 0, g_qa = 0, g_post = 0, g_exp = 0, g_err = 0;
@@ -1589,6 +1619,9 @@ struct tdb_batch_ctx {
   int *d_ghcount = nullptr, *d_gskip = nullptr, *d_gwould = nullptr;
 
   ~tdb_batch_ctx() {
+    for (hipGraphExec_t& g : gexec)
+      if (g) (void)hipGraphExecDestroy(g);
+    if (cap) (void)hipStreamDestroy(cap);
     for (auto& v : ev_used)
       for (auto& e : v) { ev_pool.push_back(e.first); ev_pool.push_back(e.second); }
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
@@ -1644,6 +1677,15 @@ tdb_status balloc(tdb_batch_ctx* b, X** d, X** hp, size_t count) {
     b->host.push_back(r);
     *hp = static_cast<X*>(r);
   }
+  return TDB_OK;
+}
+
+template <typename X>
+tdb_status halloc(tdb_batch_ctx* b, X** hp, size_t count) {
+  void* r = nullptr;
+  BHIPCHK(hipHostMalloc(&r, std::max<size_t>(count, 1) * sizeof(X), hipHostMallocDefault));
+  b->host.push_back(r);
+  *hp = static_cast<X*>(r);
   return TDB_OK;
 }
 
@@ -1748,6 +1790,7 @@ tdb_status batch_upload_args(tdb_batch_ctx* b, hipStream_t s) {
   BHIPCHK(hipMemcpyAsync(b->d_ea, b->h_ea, n * sizeof(FErrArgs), hipMemcpyHostToDevice, s));
   b->lds_pass = lds_pass;   // the stage pass of the current ranks
   b->dirty = false;
+  b->gkey[0] = b->gkey[1] = -1;   // launch shapes may have changed: capture again
   return TDB_OK;
 }
 
@@ -1855,9 +1898,27 @@ tdb_status batch_setup(tdb_batch_ctx* b) {
   TRY(balloc(b, &b->d_qa, &b->h_qa, nn));
   TRY(balloc(b, &b->d_pa, &b->h_pa, nn));
   TRY(balloc(b, &b->d_ea, &b->h_ea, nn));
-  TRY(balloc(b, &b->d_v1, &b->h_v1, nn));
-  TRY(balloc(b, &b->d_v0, &b->h_v0, nn));
-  TRY(balloc(b, &b->d_sum, &b->h_sum, nn));
+  TRY(balloc<const void*>(b, &b->d_v1, nullptr, nn));
+  TRY(balloc<const void*>(b, &b->d_v0, nullptr, nn));
+  for (int q = 0; q < 2; ++q) {
+    TRY(halloc<const void*>(b, &b->h_vt[q][0], nn));
+    TRY(halloc<const void*>(b, &b->h_vt[q][1], nn));
+    TRY(halloc<BatchSummary>(b, &b->h_sumb[q], nn));
+  }
+  TRY(halloc<unsigned long long>(b, &b->seq_h, 2));
+  b->seq_h[0] = b->seq_h[1] = 0;
+  TRY(balloc<unsigned>(b, &b->d_counter, nullptr, 1));
+  BHIPCHK(hipMemset(b->d_counter, 0, sizeof(unsigned)));
+  TRY(halloc<int>(b, &b->h_mask, nn));
+  TRY(balloc<int>(b, &b->d_hsave, nullptr, nn));
+  {
+    const char* env = std::getenv("TDB_PIPELINE");
+    bool borrow = true;
+    for (int i = 0; i < n; ++i) borrow = borrow && b->st[i]->cfg.snapshot_mode == TDB_BORROW;
+    b->pipelined = borrow && !(env && env[0] == '0');
+    const char* genv = std::getenv("TDB_GRAPH");
+    b->use_graph = !(genv && genv[0] == '0');
+  }
   std::vector<CtrlState*> ct(nn);
   for (int i = 0; i < n; ++i) ct[i] = b->st[i]->ctrl;
   TRY(balloc<CtrlState*>(b, &b->d_ctab, nullptr, nn));
@@ -1865,26 +1926,11 @@ tdb_status batch_setup(tdb_batch_ctx* b) {
   return TDB_OK;
 }
 
+// The launches of one batched step for snapshot parity p (no host synchronisation).
 template <typename TD, typename T>
-tdb_status batch_step(tdb_batch_ctx* b, const void* const* V, hipStream_t s) {
+tdb_status batch_kernels(tdb_batch_ctx* b, int p, hipStream_t s) {
   const int n = b->n;
-  for (int i = 0; i < n; ++i) {
-    b->h_v1[i] = V[i];
-    b->h_v0[i] = b->st[i]->Vprev;
-  }
-  {
-    // whole fibers as float4 loads when every stream's snapshots allow it
-    int vw = (sizeof(TD) == 4) ? (int)b->st[0]->N[2] : 0;
-    if (vw != 4 && vw != 8) vw = 0;
-    for (int i = 0; i < n && vw; ++i) {
-      const uintptr_t a1 = reinterpret_cast<uintptr_t>(b->h_v1[i]), a0 = reinterpret_cast<uintptr_t>(b->h_v0[i]);
-      if (b->st[i]->N[2] != vw || ((a1 | a0) & 15) != 0 || !b->h_v0[i]) vw = 0;
-    }
-    b->vw = vw;
-  }
-  BHIPCHK(hipMemcpyAsync(b->d_v1, b->h_v1, n * sizeof(void*), hipMemcpyHostToDevice, s));
-  BHIPCHK(hipMemcpyAsync(b->d_v0, b->h_v0, n * sizeof(void*), hipMemcpyHostToDevice, s));
-  if (b->dirty) TRY(batch_upload_args(b, s));
+  BHIPCHK(launch_batch_fetch_ptrs(b->h_vt[p][0], b->h_vt[p][1], b->d_v1, b->d_v0, n, s));
   for (int st = 0; st < 2; ++st) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (b->prof) {
@@ -1894,8 +1940,8 @@ tdb_status batch_step(tdb_batch_ctx* b, const void* const* V, hipStream_t s) {
       else e0 = e1 = nullptr;
     }
     if (b->rows)
-      BHIPCHK((launch_batch_rpass<TD>(b->d_fa[st], b->d_v1, b->d_v0, b->m_pass, b->g_pass, b->mflavor, b->rp_n3c, b->vw,
-                                      b->lds_pass, s, e0, e1)));
+      BHIPCHK((launch_batch_rpass<TD>(b->d_fa[st], b->d_v1, b->d_v0, b->m_pass, b->g_pass, b->mflavor, b->rp_n3c,
+                                      b->vw, b->lds_pass, s, e0, e1)));
     else if (b->mflavor)
       BHIPCHK((launch_batch_mpass<TD>(b->d_fa[st], b->d_v1, b->d_v0, b->m_pass, b->g_pass, b->mflavor, b->lds_pass,
                                       s, e0, e1)));
@@ -1935,15 +1981,89 @@ tdb_status batch_step(tdb_batch_ctx* b, const void* const* V, hipStream_t s) {
       if (e0 && e1) b->ev_used[TDB_PASS_ERROR].push_back({e0, e1});
       else e0 = e1 = nullptr;
     }
-    BHIPCHK((launch_batch_ferr<TD, T>(b->d_ea, b->d_v1, b->m_err, b->g_err, n, b->d_ctab, b->d_sum, b->lds_final, b->err_r1c, s,
-                                      e0, e1)));
+    BHIPCHK((launch_batch_ferr<TD, T>(b->d_ea, b->d_v1, b->m_err, b->g_err, n, b->d_ctab, b->h_sumb[p], b->d_counter,
+                                      b->seq_h + p, b->lds_final, b->err_r1c, s, e0, e1)));
   }
-  BHIPCHK(hipMemcpyAsync(b->h_sum, b->d_sum, n * sizeof(BatchSummary), hipMemcpyDeviceToHost, s));
-  BHIPCHK(hipStreamSynchronize(s));
+  return TDB_OK;
+}
+
+// Enqueues the step of parity p: a replay of the parity's graph when it was captured
+// with the current launch shapes (argument tables and LDS sizes change only through
+// batch_upload_args, which drops the graphs; the fiber width is the key), else the
+// launches themselves, captured first when graphs are on. A capture that fails turns
+// graphs off for the batch and the launches run as they are.
+template <typename TD, typename T>
+tdb_status batch_enqueue(tdb_batch_ctx* b, int p, hipStream_t s) {
+  const bool graph = b->use_graph && !b->prof;
+  const int key = b->vw;
+  if (graph && b->gexec[p] && b->gkey[p] == key) {
+    BHIPCHK(hipGraphLaunch(b->gexec[p], s));
+    b->graph_steps += 1;
+  } else if (graph) {
+    if (b->gexec[p]) {
+      (void)hipGraphExecDestroy(b->gexec[p]);
+      b->gexec[p] = nullptr;
+      b->gkey[p] = -1;
+    }
+    bool ok = b->cap || hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) == hipSuccess;
+    if (ok) ok = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed) == hipSuccess;
+    tdb_status r = TDB_OK;
+    hipGraph_t g = nullptr;
+    if (ok) {
+      r = batch_kernels<TD, T>(b, p, b->cap);
+      ok = hipStreamEndCapture(b->cap, &g) == hipSuccess && g != nullptr && r == TDB_OK;
+      if (ok) ok = hipGraphInstantiate(&b->gexec[p], g, nullptr, nullptr, 0) == hipSuccess;
+      if (g) (void)hipGraphDestroy(g);
+    }
+    (void)hipGetLastError();
+    if (ok) {
+      b->gkey[p] = key;
+      BHIPCHK(hipGraphLaunch(b->gexec[p], s));
+      b->graph_steps += 1;
+    } else {
+      if (b->gexec[p]) (void)hipGraphExecDestroy(b->gexec[p]);
+      b->gexec[p] = nullptr;
+      b->use_graph = false;
+      TRY((batch_kernels<TD, T>(b, p, s)));
+    }
+  } else {
+    TRY((batch_kernels<TD, T>(b, p, s)));
+  }
+  b->seq_want[p] += 1;
+  return TDB_OK;
+}
+
+// Waits for the summaries of the newest step of parity p (the sequence word of the
+// parity reaches the number of final kernels enqueued for it; a step that does not
+// report after a long spin is left to the runtime, which also reports a failed launch)
+// and applies them, stream by stream. acted[i]: stream i's decision needed the host
+// (which then drained the device before acting on it).
+template <typename TD, typename T>
+tdb_status batch_process(tdb_batch_ctx* b, int p, const std::vector<const void*>& V, hipStream_t s,
+                         std::vector<char>& acted) {
+  const int n = b->n;
+  {
+    volatile unsigned long long* w = b->seq_h + p;
+    const unsigned long long want = b->seq_want[p];
+    for (long long it = 0; *w != want; ++it) {
+      if (it == (1ll << 24)) {
+        BHIPCHK(hipStreamSynchronize(s));
+        if (*w != want) {
+          b->err = "the pending batch step did not report its summaries";
+          return TDB_EHIP;
+        }
+        break;
+      }
+      __builtin_ia32_pause();
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+  }
+  acted.assign(n, 0);
+  bool drained = false;
   int first_bad = -1, n_bad = 0;
   for (int i = 0; i < n; ++i) {
     tdb_ctx* h = b->st[i];
-    const BatchSummary& q = b->h_sum[i];
+    const BatchSummary& q = b->h_sumb[p][i];
     CtrlState& c = *h->ctrl_h;
     c.decision = q.decision;
     c.event = q.event;
@@ -1958,6 +2078,11 @@ tdb_status batch_step(tdb_batch_ctx* b, const void* const* V, hipStream_t s) {
     c.would_skip = q.would_skip;
     c.eps_pred = q.eps_pred;
     h->post_valid = true;
+    acted[i] = q.decision != DEC_NONE && q.decision != DEC_NONFINITE;
+    if (acted[i] && !drained) {   // the step enqueued behind this one (held for it) drains first
+      BHIPCHK(hipStreamSynchronize(s));
+      drained = true;
+    }
     const int r0[3] = {h->r[0], h->r[1], h->r[2]};
     tdb_status r = finish_step<TD, T>(h, static_cast<const TD*>(V[i]), s);
     if (r == TDB_ENUMERIC) {   // this stream's step was discarded; the others went on
@@ -1980,6 +2105,77 @@ tdb_status batch_step(tdb_batch_ctx* b, const void* const* V, hipStream_t s) {
     return TDB_ENUMERIC;
   }
   return TDB_OK;
+}
+
+// One batched step. Pipelined: enqueue it, then read the previous step and act on its
+// decisions; the streams that needed the host were held by the device during this
+// step, which then runs again for them alone (the others held meanwhile). Without
+// pipelining the step is read at once. TDB_ENUMERIC reports a discarded step of the
+// step read by this call.
+template <typename TD, typename T>
+tdb_status batch_step(tdb_batch_ctx* b, const void* const* V, hipStream_t s) {
+  const int n = b->n;
+  const int p = b->parity;
+  for (int i = 0; i < n; ++i) {
+    b->h_vt[p][0][i] = V[i];
+    b->h_vt[p][1][i] = b->st[i]->Vprev;
+  }
+  {
+    // whole fibers as float4 loads when every stream's snapshots allow it
+    int vw = (sizeof(TD) == 4) ? (int)b->st[0]->N[2] : 0;
+    if (vw != 4 && vw != 8) vw = 0;
+    for (int i = 0; i < n && vw; ++i) {
+      const uintptr_t a1 = reinterpret_cast<uintptr_t>(b->h_vt[p][0][i]);
+      const uintptr_t a0 = reinterpret_cast<uintptr_t>(b->h_vt[p][1][i]);
+      if (b->st[i]->N[2] != vw || ((a1 | a0) & 15) != 0 || !b->h_vt[p][1][i]) vw = 0;
+    }
+    b->vw = vw;
+  }
+  if (b->dirty) TRY(batch_upload_args(b, s));
+  TRY((batch_enqueue<TD, T>(b, p, s)));
+  tdb_status prev = TDB_OK;
+  std::vector<char> acted;
+  if (b->pending) {
+    b->pending = false;
+    prev = batch_process<TD, T>(b, 1 - p, b->pend_V, b->pend_stream, acted);
+    if (prev != TDB_OK && prev != TDB_ENUMERIC) return prev;
+    int na = 0;
+    for (int i = 0; i < n; ++i) na += acted[i] ? 1 : 0;
+    if (na > 0) {
+      for (int i = 0; i < n; ++i) b->h_mask[i] = acted[i] ? 0 : 1;
+      BHIPCHK(launch_batch_hold_mask(b->d_ctab, b->h_mask, b->d_hsave, n, 0, s));
+      if (b->dirty) TRY(batch_upload_args(b, s));
+      TRY((batch_enqueue<TD, T>(b, p, s)));
+      BHIPCHK(launch_batch_hold_mask(b->d_ctab, b->h_mask, b->d_hsave, n, 1, s));
+    }
+  }
+  for (int i = 0; i < n; ++i) b->st[i]->Vprev = V[i];
+  b->pend_V.assign(V, V + n);
+  b->pend_stream = s;
+  b->pending = true;
+  b->parity = 1 - p;
+  if (!b->pipelined) {
+    b->pending = false;
+    return batch_process<TD, T>(b, p, b->pend_V, s, acted);
+  }
+  return prev;
+}
+
+template <typename TD, typename T>
+tdb_status batch_resolve_as(tdb_batch_ctx* b) {
+  if (!b->pending) return TDB_OK;
+  b->pending = false;
+  std::vector<char> acted;
+  return batch_process<TD, T>(b, 1 - b->parity, b->pend_V, b->pend_stream, acted);
+}
+
+long long batch_graph_steps(const tdb_batch_ctx* b) { return b->graph_steps; }
+
+// Reads the newest batched step if it has not been read (the calls that return results
+// of a batch member come here first).
+tdb_status batch_resolve(tdb_batch_ctx* b) {
+  if (b->data32) return b->f32 ? batch_resolve_as<float, float>(b) : batch_resolve_as<float, double>(b);
+  return b->f32 ? batch_resolve_as<double, float>(b) : batch_resolve_as<double, double>(b);
 }
 
 }  // namespace
@@ -2220,6 +2416,7 @@ tdb_status tdb_get_stats(tdb_handle h, tdb_stats* out) {
   h->stats.fused_steps = h->fused_steps;
   h->stats.plain_steps = h->plain_steps;
   h->stats.n_nonfinite = h->n_nonfinite;
+  h->stats.graph_steps = h->owner ? batch_graph_steps(h->owner) : 0;
   *out = h->stats;
   return TDB_OK;
 }
@@ -2302,6 +2499,7 @@ tdb_status tdb_batch_create(int32_t n, const tdb_config* cfgs, const void* const
       if (r != TDB_OK) { b->err = "stream " + std::to_string(i) + ": " + g_create_error; return r; }
       b->st.push_back(h);
       h->batch_owned = true;
+      h->owner = b;
       if (h->f32 != b->f32 || h->data32 != b->data32) {
         b->err = "internal: stream " + std::to_string(i) + " buffer precision differs from the batch";
         return TDB_EINVAL;
@@ -2351,6 +2549,10 @@ tdb_status tdb_batch_stream(tdb_batch b, int32_t i, tdb_handle* out) {
 
 tdb_status tdb_batch_profile_enable(tdb_batch b, int32_t on) {
   if (!b) { g_create_error = "batch is NULL"; return TDB_EINVAL; }
+  {
+    const tdb_status r = batch_resolve(b);
+    if (r != TDB_OK && r != TDB_ENUMERIC) return r;
+  }
   BHIPCHK(hipDeviceSynchronize());
   for (auto& v : b->ev_used) {
     for (auto& e : v) { b->ev_pool.push_back(e.first); b->ev_pool.push_back(e.second); }
@@ -2364,6 +2566,10 @@ tdb_status tdb_batch_profile_read(tdb_batch b, int32_t pass, int64_t* launches, 
                                   double* bytes_per_launch) {
   if (!b) { g_create_error = "batch is NULL"; return TDB_EINVAL; }
   if (pass != TDB_PASS_PROJECT && pass != TDB_PASS_ERROR) { b->err = "bad pass id"; return TDB_EINVAL; }
+  {
+    const tdb_status r = batch_resolve(b);
+    if (r != TDB_OK && r != TDB_ENUMERIC) return r;
+  }
   double ms = 0.0;
   for (auto& e : b->ev_used[pass]) {
     BHIPCHK(hipEventSynchronize(e.second));
@@ -2381,6 +2587,11 @@ void tdb_batch_destroy(tdb_batch b) {
   if (!b) return;
   (void)hipDeviceSynchronize();
   delete b;
+}
+
+tdb_status tdb_batch_flush(tdb_batch b) {
+  if (!b) { g_create_error = "batch is NULL"; return TDB_EINVAL; }
+  return batch_resolve(b);
 }
 
 const char* tdb_batch_last_error(tdb_batch b) {
@@ -2503,6 +2714,10 @@ tdb_status tdb_batch_gate_attach(tdb_batch b, tdb_gate g, const float* feat_mean
   if (mode != GATE_OFF && mode != GATE_RECORD && (!g || !feat_mean_std_host)) {
     b->err = "a gate and its feature statistics are needed";
     return TDB_EINVAL;
+  }
+  {
+    const tdb_status r = batch_resolve(b);
+    if (r != TDB_OK && r != TDB_ENUMERIC) return r;
   }
   BHIPCHK(hipDeviceSynchronize());
   const size_t n = (size_t)b->n;

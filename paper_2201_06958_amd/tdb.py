@@ -81,6 +81,7 @@ class TdbStats(ctypes.Structure):
         ("fused_steps", ctypes.c_int64),
         ("plain_steps", ctypes.c_int64),
         ("n_nonfinite", ctypes.c_int64),
+        ("graph_steps", ctypes.c_int64),
     ]
 
 
@@ -129,6 +130,7 @@ def load_library(path: str = LIB_PATH):
     lib.tdb_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(TdbConfig), ctypes.POINTER(P), P,
                                      ctypes.POINTER(H)]
     lib.tdb_batch_ingest.argtypes = [H, ctypes.POINTER(P), P]
+    lib.tdb_batch_flush.argtypes = [H]
     lib.tdb_batch_stream.argtypes = [H, ctypes.c_int32, ctypes.POINTER(H)]
     lib.tdb_batch_profile_enable.argtypes = [H, ctypes.c_int32]
     lib.tdb_batch_profile_read.argtypes = [H, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
@@ -153,7 +155,7 @@ def load_library(path: str = LIB_PATH):
     lib.tdb_batch_last_error.restype = ctypes.c_char_p
     for name in ("tdb_init", "tdb_init_from_factors", "tdb_ingest_snapshot", "tdb_flush", "tdb_get_core_and_bases",
                  "tdb_reconstruct", "tdb_set_threshold", "tdb_get_stats", "tdb_batch_create",
-                 "tdb_batch_ingest", "tdb_batch_stream", "tdb_batch_profile_enable",
+                 "tdb_batch_ingest", "tdb_batch_flush", "tdb_batch_stream", "tdb_batch_profile_enable",
                  "tdb_batch_profile_read", "tdb_batch_gate_attach", "tdb_gate_load", "tdb_gate_create", "tdb_gate_set_params",
                  "tdb_gate_get_params", "tdb_gate_forward", "tdb_gate_grad", "tdb_gate_train_step"):
         getattr(lib, name).restype = ctypes.c_int32
@@ -315,6 +317,7 @@ class Compressor:
                                PREC_BF16SPLIT: "bf16s"}.get(s.precision_used),
             "path_used": {0: None, PATH_PLAIN: "plain", PATH_FUSED: "fused"}.get(s.path_used),
             "fused_steps": s.fused_steps, "plain_steps": s.plain_steps, "n_nonfinite": s.n_nonfinite,
+            "graph_steps": s.graph_steps,
         }
 
     def gate_load(self, params=None, mean_std=None, mode: str = "active"):
@@ -393,6 +396,10 @@ class Batch:
 
     def ingest(self, Vs, stream=None):
         self._check(self.lib.tdb_batch_ingest(self.h, self._ptrs(Vs), _stream_ptr(stream)))
+
+    def flush(self):
+        """Read the newest step if it has not been read (pipelined batches)."""
+        self._check(self.lib.tdb_batch_flush(self.h))
 
     def gate_attach(self, gate, mean_std=None, mode: str = "active"):
         """Use a trained Gate (kept alive by the caller) with the given feature statistics

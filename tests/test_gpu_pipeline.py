@@ -119,3 +119,109 @@ def test_pass_timing_sampled_every_kth_step():
         assert er["launches"] == timed, (every, er)
         assert pj["total_ms"] > 0.0
         g.close()
+
+
+# ---------------------------------------------------------------- batches
+
+def _switched_at(t_on, t_peak, t_low, seed, dims):
+    h_min = 0.002
+
+    def h(t):
+        if t <= t_on:
+            return 0.0
+        if t <= t_peak:
+            return 2.0 * (t - t_on)
+        if t <= t_low:
+            return 0.2 + (h_min - 0.2) * (t - t_peak) / (t_low - t_peak)
+        return h_min
+
+    return switched_term_spec(dims=dims, steps=120, seed=seed, profile=h, profile2=lambda t: 0.004 * math.exp(-t))
+
+
+def _run_batch(specs, snaps, mode, precision, read_every, env, rank_max=None):
+    """Ingest every step of a batch; read every member's statistics after every
+    `read_every`-th call (0: only at the end). Returns (events, per-member results)."""
+    import os
+    from paper_2201_06958_amd import Batch
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        cfgs = [dict(dims=sp.dims, dt=sp.dt, rank_max=rank_max or sp.rank_max, rank_init=sp.rank_init,
+                     weights=sp.weights, data_dtype=sp.storage, precision=precision, adaptive=sp.adaptive,
+                     eps_th=sp.eps_th if sp.eps_th > 0 else 1.0, snapshot_mode=mode) for sp in specs]
+        b = Batch(cfgs).init([s[0] for s in snaps])
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    events = []
+    steps = len(snaps[0]) - 1
+    for k in range(1, steps + 1):
+        b.ingest([s[k] for s in snaps])
+        if read_every and k % read_every == 0:
+            for i, m in enumerate(b.streams):
+                st = m.stats()
+                if st["event"]:
+                    events.append((k, i, st["event"], st["ranks"]))
+    b.flush()
+    res = []
+    for m in b.streams:
+        st = m.stats()
+        r, C, U = m.get_core_and_bases()
+        res.append((events, st, r, C, U))
+    b.close()
+    return events, res
+
+
+def _same_batch(a, b):
+    for x, y in zip(a[1], b[1]):
+        _same(x, y)
+
+
+def test_batch_pipelined_and_graphs_match_synchronous():
+    """Two switched-term streams whose add and removal steps differ (so a step runs again
+    for one member while the other went on), FP64: the pipelined batch, with the step's
+    launches replayed from graphs or issued one by one, and whichever calls read the
+    decisions, equals the synchronous batch bit for bit."""
+    specs = [_switched_at(0.05, 0.15, 0.35, 3, (16, 14, 6)), _switched_at(0.12, 0.2, 0.45, 5, (18, 12, 5))]
+    _say("case pipelined batch, two switched-term streams 120 steps, FP64")
+    snaps = [[torch.from_numpy(np.ascontiguousarray(sp.snapshot_np(k))).to("cuda") for k in range(sp.steps + 1)]
+             for sp in specs]
+    torch.cuda.synchronize()
+    ref = _run_batch(specs, snaps, "copy", "f64", 1, {"TDB_GRAPH": "0"})
+    ev = ref[0]
+    assert {e[1] for e in ev if e[2] == "add"} == {0, 1}, ev      # both members add
+    assert {e[1] for e in ev if e[2] == "remove"} == {0, 1}, ev   # and remove
+    assert len({e[0] for e in ev}) == len(ev), ev                # never on the same step
+    _say("  events", ev)
+    for env in ({"TDB_GRAPH": "1"}, {"TDB_GRAPH": "0"}):
+        for every in (1, 0, 5):
+            _say("  borrow", env, "read every", every)
+            got = _run_batch(specs, snaps, "borrow", "f64", every, env)
+            if every == 1:
+                assert got[0] == ev
+            graphs = got[1][0][1]["graph_steps"]
+            # every step and every run again for held members, all but the captures
+            assert (graphs >= 100) if env["TDB_GRAPH"] == "1" else (graphs == 0), graphs
+            _same_batch(got, ref)
+    # the synchronous batch with graphs is the same too
+    _same_batch(_run_batch(specs, snaps, "copy", "f64", 0, {"TDB_GRAPH": "1"}), ref)
+
+
+def test_batch_pipelined_fp32_mixed_matches_synchronous():
+    """A reactive-flow stream (8 variables) and two Fourier ensemble members (4
+    variables) in one FP32 batch, adaptive ranks: pipelined with graphs against the
+    synchronous batch, bit for bit."""
+    from streams import fourier_ensemble_specs
+    pl = plume_spec(nx=96, ny=64, nv=8, steps=24)
+    fe = fourier_ensemble_specs(n_streams=2, steps=24, seed0=3000)
+    specs = [pl] + fe
+    _say("case pipelined batch FP32", [sp.dims for sp in specs])
+    snaps = [[sp.snapshot(k, device="cuda") for k in range(25)] for sp in specs]
+    torch.cuda.synchronize()
+    ref = _run_batch(specs, snaps, "copy", "f32", 0, {"TDB_GRAPH": "0"}, rank_max=(24, 24, 4))
+    got = _run_batch(specs, snaps, "borrow", "f32", 0, {"TDB_GRAPH": "1"}, rank_max=(24, 24, 4))
+    assert got[1][0][1]["graph_steps"] >= 20
+    _same_batch(got, ref)
