@@ -1,21 +1,24 @@
 #!/usr/bin/env python3
 """Throughput of the TDB in situ compressor on one MI355X.
 
-Workload (default): the reactive-flow-shaped stream, a 512 x 256 x 8 FP32 tensor
-(3 advected plumes with reaction fronts, 8 Arrhenius-scaled variables, 1e-6 noise),
-dt 5e-4, adaptive ranks from the rank rule with error threshold 1e-4 and caps
-(64, 64, 8). One step = one snapshot ingested: two Heun stages of the projection
-pass, the small FP64 work, the re-orthonormalisation, the weighted error pass and
-the controller (with any HOSVD reinitialisation it triggers).
+Headline workload: the batched stochastic ensemble. 256 independent streams of 2-D
+fields on grids drawn uniformly from {128,192,256}^2 with 4 variables (FP32
+snapshots), each variable a sum of 16 random Fourier modes (amplitudes N(0,1)|k|^-5/6,
+phases drifting at rates U(0.5, 2)); adaptive ranks capped at 24 per mode, error
+threshold 1e-5. One step = one snapshot of every stream ingested (256 snapshots) by
+the batched fused path: two Heun stages of the column-block projection pass, the
+small FP64 work, the re-orthonormalisation, the weighted error pass and the
+controller, pipelined (the host reads a step while the next one runs) and replayed
+from HIP graphs.
 
-All snapshots of the run are generated on the device before timing (a ring far
-larger than the 256 MB last-level cache), so every stage pass streams its snapshot
-pair from HBM at least once. Prints one JSON line.
+All snapshots of the run are generated on the device before timing. One step's 256
+snapshots hold 151 MB and a stage pass streams two steps' worth (302 MB), more than
+the 256 MB last-level cache, so the passes read HBM. Prints one JSON line.
 
-Besides the headline line, the same JSON carries: the same stream with the stage
-pass in BF16-split products ("bf16_split"); the batched ensemble of independent
-Fourier-mode streams of uneven grids ("ensemble", 256 streams by default, one batch
-step = one snapshot of every stream); the plain FP64 GPU path; and the CPU oracle.
+Besides the headline, the line carries: the same ensemble with BF16-split products;
+the plain FP64 GPU path on a sample of its streams; the single reactive-flow-shaped
+stream (512 x 256 x 8, FP32) with its own pass roofline; and the FP64 CPU oracle
+timed on the host's cores at one thread and at all physical cores.
 """
 from __future__ import annotations
 
@@ -23,136 +26,215 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
-# HBM bytes per stage-pass launch from hardware counters (FETCH_SIZE / WRITE_SIZE,
-# calibrated against a copy of known size); ignored once the kernel's sources change.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_pass_plume512x256x8_fp32.txt")
-PROFILE_EVERY = 8          # pass timing sampled on every 8th step of the timed run
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak
+LLC_BYTES = 256 << 20      # MI355X last-level (Infinity) cache
+PROFILE_EVERY = 8          # pass timing sampled on every 8th step of a timed run
+# HBM bytes per launch from hardware counters (FETCH_SIZE / WRITE_SIZE, calibrated
+# against a copy of known size); ignored once the kernel's sources change.
 ENSEMBLE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_ensemble256_fp32.txt")
+PLUME_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_pass_plume512x256x8_fp32.txt")
+ENSEMBLE_PASS = "kb_rpass<float, 1, 4, true>"   # the column-block pass, FP32 products, float4 fibers
+PLUME_PASS = "k_mpass_w16<float, 1>"
 METRIC = "snapshots/s ingested + HBM GB/s vs plain FP64 GPU at <=1e-6 rel err"
 
 
-def _workload(args):
-    from streams import plume_spec
-    sp = plume_spec(steps=args.warmup + args.steps + 1)
-    desc = {"workload": "plume-512x256x8-fp32 (reactive-flow-shaped stream)",
-            "dims": list(sp.dims), "dt": sp.dt, "eps_th": sp.eps_th, "rank_max": [64, 64, 8],
-            "adaptive": True, "snapshot_storage": "f32", "noise": 1e-6}
-    return sp, desc
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def _make_snapshots(sp, n, device):
-    import torch
-    out = []
-    for k in range(n):
-        out.append(sp.snapshot(k, device=device))
-    torch.cuda.synchronize()
-    return out
-
-
-def _run_gpu(sp, snaps, warmup, steps, precision, path, profile=True):
-    import torch
-    from paper_2201_06958_amd import Compressor
-    cmp = Compressor(sp.dims, sp.dt, rank_max=(64, 64, 8), weights=sp.weights, data_dtype="f32",
-                     precision=precision, path=path, adaptive=True, snapshot_mode="borrow",
-                     eps_th=sp.eps_th)
-    cmp.init(snaps[0])
-    for k in range(1, warmup + 1):
-        cmp.ingest(snaps[k])
-    cmp.flush()
-    torch.cuda.synchronize()
-    if profile:
-        # the dispatch-stamped events cost time on the stream: the passes of every
-        # PROFILE_EVERY-th step are timed (a sample spread over the timed region)
-        cmp.profile_enable(True, every=PROFILE_EVERY)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(warmup + 1, warmup + steps + 1):
-        cmp.ingest(snaps[k])
-    cmp.flush()   # the last step's decision is acted on inside the timed region
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st = cmp.stats()
-    prof = {}
-    if profile:
-        prof = {"project": cmp.profile_read("project"), "error": cmp.profile_read("error")}
-    cmp.close()
-    return t1 - t0, st, prof
-
-
-def _run_ensemble(n, warmup, steps, precision="f32"):
-    """The batched ensemble: n Fourier-mode streams of grids from {128,192,256}^2 x 4,
-    caps 24, threshold 1e-5, one batch step per snapshot of every stream."""
-    import torch
+def _ensemble_specs(n, steps):
     from streams import fourier_ensemble_specs
+    return fourier_ensemble_specs(n_streams=n, steps=steps)
+
+
+def _ensemble_desc(n, specs):
+    grids = sorted({(sp.dims[0], sp.dims[1]) for sp in specs})
+    return {"workload": f"fourier-ensemble-{n}x{{128,192,256}}^2x4-fp32 (batched stochastic ensemble)",
+            "streams": n, "grids": [list(g) for g in grids], "variables": 4, "fourier_modes": 16,
+            "rank_max": list(specs[0].rank_max), "eps_th": specs[0].eps_th, "dt": specs[0].dt,
+            "adaptive": True, "snapshot_storage": "f32",
+            "elements_per_step": sum(sp.dims[0] * sp.dims[1] * sp.dims[2] for sp in specs)}
+
+
+def _run_ensemble(specs, snaps, warmup, steps, precision, profile_every):
+    """The batched ensemble: warmup steps, then `steps` timed steps bracketed by a device
+    synchronisation (the last step is read inside the timed region)."""
+    import torch
     from paper_2201_06958_amd import Batch
-    specs = fourier_ensemble_specs(n_streams=n, steps=warmup + steps + 1)
-    snaps = [[sp.snapshot(k, device="cuda") for sp in specs] for k in range(warmup + steps + 1)]
-    torch.cuda.synchronize()
-    elems = sum(sp.dims[0] * sp.dims[1] * sp.dims[2] for sp in specs)
     cfgs = [dict(dims=sp.dims, dt=sp.dt, rank_max=sp.rank_max, weights=sp.weights, data_dtype="f32",
                  precision=precision, adaptive=True, eps_th=sp.eps_th, snapshot_mode="borrow") for sp in specs]
     b = Batch(cfgs).init(snaps[0])
     for k in range(1, warmup + 1):
         b.ingest(snaps[k])
+    b.flush()
     torch.cuda.synchronize()
-    b.profile_enable(True)
+    if profile_every:
+        b.profile_enable(True, every=profile_every)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(warmup + 1, warmup + steps + 1):
         b.ingest(snaps[k])
+    b.flush()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    pj, er = b.profile_read("project"), b.profile_read("error")
-    pav = pj["total_ms"] / max(pj["launches"], 1) * 1e-3
-    eav = er["total_ms"] / max(er["launches"], 1) * 1e-3
-    ranks = [b.streams[i].ranks() for i in range(n)]
+    prof = {}
+    if profile_every:
+        prof = {"project": b.profile_read("project"), "error": b.profile_read("error")}
+    sts = [m.stats() for m in b.streams]
     b.close()
-    step_bytes = 5.0 * 4.0 * elems   # two stage passes over two snapshots, one error pass
-    traffic = None
-    if precision == "f32" and n == 256:
-        from paper_2201_06958_amd.profsum import read_pass_traffic
-        traffic = read_pass_traffic(ENSEMBLE_TRAFFIC_FILE, "kb_mpass<float, 1>")
-    return {"workload": f"fourier-ensemble-{n}x{{128,192,256}}^2x4-fp32", "streams": n, "steps": steps,
-            "precision": precision, "elements_per_step": elems,
-            "value": n * steps / el, "unit": "snapshots/s", "ms_per_step": 1e3 * el / steps,
-            "step_hbm_frac": step_bytes / (el / steps) / (HBM_PEAK_GBS * 1e9),
-            "pass": {"avg_launch_us": pav * 1e6, "achieved_GBs": pj["bytes_per_launch"] / pav / 1e9,
-                     "frac": pj["bytes_per_launch"] / pav / 1e9 / HBM_PEAK_GBS,
+    return el, sts, prof
+
+
+def _avg_s(p):
+    return p["total_ms"] / max(p["launches"], 1) * 1e-3
+
+
+def _run_plain(specs, snaps, steps):
+    """The plain FP64 GPU path (unfused per-mode TTMs, FP64 products) on the given
+    streams, one after another: one step of each after one warm-up step."""
+    import torch
+    from paper_2201_06958_amd import Compressor
+    total = 0.0
+    for i, sp in enumerate(specs):
+        c = Compressor(sp.dims, sp.dt, rank_max=sp.rank_max, weights=sp.weights, data_dtype="f32",
+                       precision="f64", path="plain", adaptive=True, eps_th=sp.eps_th, snapshot_mode="borrow")
+        c.init(snaps[0][i])
+        c.ingest(snaps[1][i])
+        c.flush()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(2, steps + 2):
+            c.ingest(snaps[k][i])
+        c.flush()
+        torch.cuda.synchronize()
+        total += time.perf_counter() - t0
+        c.close()
+    return len(specs) * steps / total
+
+
+def _run_plume(warmup, steps):
+    """The single reactive-flow-shaped stream (512 x 256 x 8, FP32, caps (64, 64, 8),
+    threshold 1e-4), pipelined, passes timed on every PROFILE_EVERY-th step."""
+    import torch
+    from streams import plume_spec
+    from paper_2201_06958_amd import Compressor
+    sp = plume_spec(steps=warmup + steps + 1)
+    snaps = [sp.snapshot(k, device="cuda") for k in range(warmup + steps + 1)]
+    torch.cuda.synchronize()
+    c = Compressor(sp.dims, sp.dt, rank_max=(64, 64, 8), weights=sp.weights, data_dtype="f32", precision="f32",
+                   adaptive=True, snapshot_mode="borrow", eps_th=sp.eps_th)
+    c.init(snaps[0])
+    for k in range(1, warmup + 1):
+        c.ingest(snaps[k])
+    c.flush()
+    torch.cuda.synchronize()
+    c.profile_enable(True, every=PROFILE_EVERY)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(warmup + 1, warmup + steps + 1):
+        c.ingest(snaps[k])
+    c.flush()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = c.stats()
+    pj, er = c.profile_read("project"), c.profile_read("error")
+    c.close()
+    ring = len(snaps) * snaps[0].numel() * 4
+    pav, eav = _avg_s(pj), _avg_s(er)
+    from paper_2201_06958_amd.profsum import read_pass_traffic
+    traffic = read_pass_traffic(PLUME_TRAFFIC_FILE, PLUME_PASS)
+    return {"workload": "plume-512x256x8-fp32 (reactive-flow-shaped stream)", "steps": steps,
+            "value": steps / el, "unit": "snapshots/s", "ms_per_step": 1e3 * el / steps,
+            "ring_bytes": ring, "cache_resident": ring <= LLC_BYTES,
+            "pass": {"kernel_name": PLUME_PASS, "avg_launch_us": pav * 1e6, "launches": pj["launches"],
                      "algorithmic_bytes_per_launch": pj["bytes_per_launch"],
-                     "traffic": traffic["traffic_bytes"] if traffic else None,
-                     "traffic_read_write": [traffic["read_bytes"], traffic["write_bytes"]] if traffic else None},
+                     "achieved_GBs": pj["bytes_per_launch"] / pav / 1e9,
+                     "frac": pj["bytes_per_launch"] / pav / 1e9 / HBM_PEAK_GBS,
+                     "traffic": traffic["traffic_bytes"] if traffic else None},
             "error_pass": {"avg_launch_us": eav * 1e6, "achieved_GBs": er["bytes_per_launch"] / eav / 1e9},
-            "max_ranks": [max(r[i] for r in ranks) for i in range(3)]}
+            "final_stats": {"ranks": st["ranks"], "eps": st["eps"], "crbar": st["crbar"], "n_add": st["n_add"],
+                            "n_reinit": st["n_reinit"], "n_remove": st["n_remove"]}}
 
 
-def _cpu_baseline(sp, start, budget_s=15.0, max_steps=60):
-    """The FP64 numpy oracle on the host: init at snapshot `start`, then as many
-    steps as fit in the budget (bounded sample of the same workload)."""
+# ---------------------------------------------------------------- CPU oracle
+
+def _physical_cores():
+    """Physical cores from lscpu (cores per socket x sockets), capped by the CPUs this
+    process may run on."""
+    phys = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        kv = {}
+        for ln in out.splitlines():
+            if ":" in ln:
+                k, v = ln.split(":", 1)
+                kv[k.strip()] = v.strip()
+        phys = int(kv["Core(s) per socket"]) * int(kv.get("Socket(s)", "1"))
+        model = kv.get("Model name", "")
+    except Exception:
+        model = ""
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return min(phys or avail, avail), phys, avail, model
+
+
+def _cpu_worker(n_streams, warm, timed):
+    """The FP64 numpy oracle on the first n_streams ensemble streams: per stream an
+    HOSVD initialisation, `warm` steps, then `timed` timed steps; prints the median
+    per-snapshot ingest time and the threads the BLAS pools hold."""
     import numpy as np
     from oracle import tdb_oracle as O
+    specs = _ensemble_specs(256, warm + timed + 1)[:n_streams]
+    times = []
+    for sp in specs:
+        snaps = [sp.snapshot_np(k).astype(np.float64) for k in range(warm + timed + 1)]
+        o = O.OracleTDB(O.OracleConfig(dims=sp.dims, weights=sp.weights, dt=sp.dt, rank_max=sp.rank_max,
+                                       rank_init=None, adaptive=True, eps_th=sp.eps_th)).init(snaps[0])
+        for k in range(1, warm + 1):
+            o.ingest(snaps[k])
+        for k in range(warm + 1, warm + timed + 1):
+            t0 = time.perf_counter()
+            o.ingest(snaps[k])
+            times.append(time.perf_counter() - t0)
+    threads = None
     try:
         from threadpoolctl import threadpool_info
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
-    cfg = O.OracleConfig(dims=sp.dims, weights=sp.weights, dt=sp.dt, rank_max=(64, 64, 8),
-                         rank_init=None, adaptive=True, eps_th=sp.eps_th)
-    o = O.OracleTDB(cfg).init(sp.snapshot_np(start).astype(np.float64), t0=sp.time(start))
-    n = 0
-    t0 = time.perf_counter()
-    while n < max_steps and time.perf_counter() - t0 < budget_s:
-        o.ingest(sp.snapshot_np(start + 1 + n).astype(np.float64))
-        n += 1
-    el = time.perf_counter() - t0
-    return {"value": n / el, "unit": "snapshots/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{n} consecutive steps of the same stream after an HOSVD init at step {start} "
-                      f"(FP64 numpy oracle, {el:.1f} s, snapshot generation excluded)"}
+    except Exception:
+        pass
+    times.sort()
+    print(json.dumps({"median_s": times[len(times) // 2], "samples": len(times), "blas_threads": threads}))
+
+
+def _cpu_baseline(n_streams=32, warm=5, timed=5):
+    """The oracle in child processes (so the BLAS thread count is fixed before numpy
+    loads): one thread, then all physical cores available to this process."""
+    cores, phys, avail, model = _physical_cores()
+    runs = {}
+    for nt in (1, cores):
+        env = dict(os.environ)
+        for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "BLIS_NUM_THREADS"):
+            env[k] = str(nt)
+        out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-oracle-worker",
+                              f"{n_streams},{warm},{timed}"], capture_output=True, text=True, env=env,
+                             timeout=900)
+        if out.returncode != 0:
+            raise RuntimeError(out.stderr[-2000:])
+        runs[nt] = json.loads(out.stdout.strip().splitlines()[-1])
+    sample = (f"the FP64 numpy oracle on the first {n_streams} ensemble streams: per stream an HOSVD "
+              f"initialisation and {warm} warm-up steps, then {timed} timed steps; median per-snapshot "
+              f"ingest time (snapshot generation excluded) over {runs[cores]['samples']} snapshots")
+    all_c = runs[cores]
+    return {"value": 1.0 / all_c["median_s"], "unit": "snapshots/s", "cores": cores, "kind": "oracle",
+            "sample": sample, "blas_threads": all_c["blas_threads"],
+            "one_thread": {"value": 1.0 / runs[1]["median_s"], "unit": "snapshots/s", "cores": 1},
+            "host": {"lscpu_physical_cores": phys, "cpus_available": avail, "model": model}}
 
 
 def _scaling_sweep(sizes, steps, reps=5):
@@ -196,9 +278,8 @@ def _scaling_sweep(sizes, steps, reps=5):
         rows.append({"N": n, "S": n ** 3, "hosvd_ms": 1e3 * hosvd, "tdb_step_us": 1e6 * step,
                      "hosvd_over_step": hosvd / step, "pass_launches": pj["launches"],
                      "pass_avg_us": 1e3 * pj["total_ms"] / max(pj["launches"], 1)})
-        print(f"[bench] sweep N={n}: HOSVD {1e3 * hosvd:.3f} ms, TDB step {1e6 * step:.1f} us, "
-              f"stage pass {rows[-1]['pass_avg_us']:.1f} us x {rows[-1]['pass_launches']}",
-              file=sys.stderr, flush=True)
+        _log(f"sweep N={n}: HOSVD {1e3 * hosvd:.3f} ms, TDB step {1e6 * step:.1f} us, "
+             f"stage pass {rows[-1]['pass_avg_us']:.1f} us x {rows[-1]['pass_launches']}")
 
     def slope(key):
         xs = [math.log(r["S"]) for r in rows]
@@ -211,31 +292,33 @@ def _scaling_sweep(sizes, steps, reps=5):
 
 
 def main():
-    ap = argparse.ArgumentParser(description=__doc__)
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--path", default="auto", choices=["auto", "plain", "fused"])
-    ap.add_argument("--plain-steps", type=int, default=200,
-                    help="steps of the plain FP64 GPU path timed for comparison (0 = skip)")
+    ap.add_argument("--steps", type=int, default=100, help="timed ensemble steps")
+    ap.add_argument("--warmup", type=int, default=10, help="untimed ensemble steps first")
+    ap.add_argument("--streams", type=int, default=256, help="streams of the ensemble")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="the headline only (no BF16-split, plain FP64 GPU or reactive-flow records)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--ensemble-streams", type=int, default=256,
-                    help="streams of the batched ensemble measurement (0 = skip)")
-    ap.add_argument("--ensemble-steps", type=int, default=20)
-    ap.add_argument("--bf16-steps", type=int, default=300,
-                    help="steps of the BF16-split form of the headline stream (0 = skip)")
+    ap.add_argument("--plain-streams", type=int, default=16,
+                    help="ensemble streams the plain FP64 GPU path is timed on")
+    ap.add_argument("--plume-steps", type=int, default=300, help="timed steps of the reactive-flow stream")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 256 MiB device-to-device copy (a known-size reference for "
+                         "hardware traffic counters)")
     ap.add_argument("--scaling-sweep", type=str, default="",
                     help="comma-separated cube sizes N: time a TDB step against an HOSVD of an "
                          "N x N x N snapshot for each (prints one JSON line and nothing else)")
     ap.add_argument("--sweep-steps", type=int, default=50, help="TDB steps timed per size of the sweep")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run a 256 MiB device-to-device copy (a known-size reference for "
-                         "hardware traffic counters)")
+    ap.add_argument("--cpu-oracle-worker", type=str, default="", help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_oracle_worker:
+        n, w, t = (int(x) for x in args.cpu_oracle_worker.split(","))
+        _cpu_worker(n, w, t)
+        return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the library has no multi-GPU path (the design notes, "
-              "'How the path would shard').", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the design notes say how the "
+              "path would shard); run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
@@ -245,10 +328,13 @@ def main():
         sizes = [int(x) for x in args.scaling_sweep.split(",") if x.strip()]
         print(json.dumps(_scaling_sweep(sizes, max(args.sweep_steps, 10))), flush=True)
         return
-    sp, desc = _workload(args)
-    print(f"[bench] generating {args.warmup + args.steps + 1} snapshots on the device", file=sys.stderr,
-          flush=True)
-    snaps = _make_snapshots(sp, args.warmup + args.steps + 1, "cuda")
+    n = args.streams
+    total = args.warmup + args.steps + 1
+    specs = _ensemble_specs(n, total)
+    desc = _ensemble_desc(n, specs)
+    _log(f"generating {total} snapshots of each of {n} streams on the device")
+    snaps = [[sp.snapshot(k, device="cuda") for sp in specs] for k in range(total)]
+    torch.cuda.synchronize()
     if args.calibrate_copy:
         x = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
@@ -256,69 +342,76 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         del x, y
-    print("[bench] timed run", file=sys.stderr, flush=True)
-    el, st, prof = _run_gpu(sp, snaps, args.warmup, args.steps, args.precision, args.path)
-    value = args.steps / el
-    pj = prof["project"]
-    avg_s = pj["total_ms"] / max(pj["launches"], 1) * 1e-3
-    achieved = pj["bytes_per_launch"] / avg_s / 1e9 if avg_s > 0 else 0.0
-    er = prof["error"]
-    er_avg_s = er["total_ms"] / max(er["launches"], 1) * 1e-3
-    traffic = None
-    if args.precision == "f32" and args.path != "plain":
-        from paper_2201_06958_amd.profsum import read_pass_traffic
-        traffic = read_pass_traffic(TRAFFIC_FILE, "k_mpass_w16<float, 1>")
-    plain = None
-    if args.plain_steps > 0:
-        print("[bench] plain FP64 GPU path", file=sys.stderr, flush=True)
-        n_pl = min(args.plain_steps, args.steps)
-        el_p, st_p, _ = _run_gpu(sp, snaps, args.warmup, n_pl, "f64", "plain", profile=False)
-        plain = {"value": n_pl / el_p, "unit": "snapshots/s", "steps": n_pl,
-                 "speedup": value / (n_pl / el_p)}
-    bf16 = None
-    if args.bf16_steps > 0 and args.precision == "f32":
-        print("[bench] BF16-split stage pass", file=sys.stderr, flush=True)
-        n_b = min(args.bf16_steps, args.steps)
-        el_b, st_b, pr_b = _run_gpu(sp, snaps, args.warmup, n_b, "bf16s", args.path)
-        pb = pr_b["project"]
-        pbav = pb["total_ms"] / max(pb["launches"], 1) * 1e-3
-        bf16 = {"value": n_b / el_b, "unit": "snapshots/s", "steps": n_b, "pass_avg_launch_us": pbav * 1e6,
-                "pass_achieved_GBs": pb["bytes_per_launch"] / pbav / 1e9, "final_eps": st_b["eps"],
-                "final_ranks": st_b["ranks"]}
-    ens = None
-    if args.ensemble_streams > 0:
+    _log("timed run (FP32 products)")
+    el, sts, prof = _run_ensemble(specs, snaps, args.warmup, args.steps, "f32", PROFILE_EVERY)
+    value = n * args.steps / el
+    pj, er = prof["project"], prof["error"]
+    pav, eav = _avg_s(pj), _avg_s(er)
+    achieved = pj["bytes_per_launch"] / pav / 1e9
+    step_s = el / args.steps
+    elems = desc["elements_per_step"]
+    step_bytes = 5.0 * 4.0 * elems     # two stages x (V_k+1, V_k), one error pass
+    from paper_2201_06958_amd.profsum import read_pass_traffic
+    traffic = read_pass_traffic(ENSEMBLE_TRAFFIC_FILE, ENSEMBLE_PASS)
+    ring = total * elems * 4
+    extras = {}
+    if not args.no_extras:
+        _log("BF16-split products")
+        n_b = max(10, args.steps // 2)
+        el_b, sts_b, prof_b = _run_ensemble(specs, snaps, args.warmup, n_b, "bf16s", PROFILE_EVERY)
+        pb = _avg_s(prof_b["project"])
+        extras["ensemble_bf16_split"] = {
+            "value": n * n_b / el_b, "unit": "snapshots/s", "steps": n_b, "ms_per_step": 1e3 * el_b / n_b,
+            "pass_avg_launch_us": pb * 1e6, "pass_achieved_GBs": prof_b["project"]["bytes_per_launch"] / pb / 1e9,
+            "max_ranks": [max(s["ranks"][i] for s in sts_b) for i in range(3)]}
+        ns = min(args.plain_streams, n)
+        _log(f"plain FP64 GPU path on {ns} streams")
+        plain_v = _run_plain(specs[:ns], [row[:ns] for row in snaps[:5]], 3)
+        extras["plain_fp64_gpu"] = {
+            "value": plain_v, "unit": "snapshots/s",
+            "sample": f"the first {ns} ensemble streams one after another (unfused per-mode TTMs, FP64 "
+                      f"products), 3 steps each after one warm-up step",
+            "speedup": value / plain_v}
         del snaps
         torch.cuda.empty_cache()
-        print(f"[bench] batched ensemble of {args.ensemble_streams} streams", file=sys.stderr, flush=True)
-        ens = _run_ensemble(args.ensemble_streams, 3, args.ensemble_steps)
+        _log("reactive-flow-shaped stream")
+        extras["plume_c2"] = _run_plume(20, args.plume_steps)
+    else:
+        del snaps
     cpu = None
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = _cpu_baseline(sp, args.warmup)
+        _log("cpu baseline (oracle, 1 thread and all physical cores)")
+        cpu = _cpu_baseline()
     line = {
         "metric": METRIC, "value": value, "unit": "snapshots/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
-        "config": dict(desc, path=args.path, precision=args.precision),
+        "warmup": args.warmup, "ms_per_step": 1e3 * step_s, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": dict(desc, precision="f32", path="fused-batched", ring_bytes=ring,
+                       cache_resident=ring <= LLC_BYTES),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic["traffic_bytes"] if traffic else None,
                      "traffic_unit": "bytes/launch",
                      "traffic_read_write": ([traffic["read_bytes"], traffic["write_bytes"]]
                                             if traffic else None),
-                     "kernel": "stage projection pass (one Heun stage; k_mpass_w16, matrix cores)",
-                     "avg_launch_us": avg_s * 1e6, "launches": pj["launches"],
+                     "kernel": "column-block stage projection pass, one Heun stage of all 256 streams "
+                               "(matrix cores, FP32 products)",
+                     "kernel_name": ENSEMBLE_PASS,
+                     "avg_launch_us": pav * 1e6, "launches": pj["launches"],
                      "timed_every_nth_step": PROFILE_EVERY,
-                     "algorithmic_bytes_per_launch": pj["bytes_per_launch"]},
-        "error_pass": {"avg_launch_us": er_avg_s * 1e6,
-                       "achieved_GBs": er["bytes_per_launch"] / er_avg_s / 1e9 if er_avg_s > 0 else 0.0},
-        "final_stats": {"ranks": st["ranks"], "eps": st["eps"], "crbar": st["crbar"],
-                        "n_add": st["n_add"], "n_reinit": st["n_reinit"], "n_remove": st["n_remove"]},
-        "plain_fp64_gpu": plain,
-        "bf16_split": bf16,
-        "ensemble": ens,
+                     "algorithmic_bytes_per_launch": pj["bytes_per_launch"],
+                     "step_algorithmic_bytes": step_bytes,
+                     "step_frac": step_bytes / step_s / 1e9 / HBM_PEAK_GBS},
+        "error_pass": {"kernel_name": "kb_ferr_cols<float, float, 24>", "avg_launch_us": eav * 1e6,
+                       "algorithmic_bytes_per_launch": er["bytes_per_launch"],
+                       "achieved_GBs": er["bytes_per_launch"] / eav / 1e9},
+        "final_stats": {"max_ranks": [max(s["ranks"][i] for s in sts) for i in range(3)],
+                        "max_eps_over_nu": max(s["eps"] / s["nu"] for s in sts),
+                        "events": {k: sum(s[k] for s in sts) for k in ("n_add", "n_remove", "n_reinit")},
+                        "graph_steps": sts[0]["graph_steps"]},
         "cpu_baseline": cpu,
     }
+    line.update(extras)
     print(json.dumps(line), flush=True)
 
 

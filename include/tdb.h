@@ -264,7 +264,8 @@ tdb_status tdb_profile_read(tdb_handle h, int32_t pass, int64_t* launches, doubl
  *   it returns TDB_ESTATE and tdb_destroy ignores it.
  * tdb_batch_profile_enable / _read: as tdb_profile_enable / _read for the batched
  *   stage pass and error pass (one launch covers all streams; the bytes per launch
- *   are summed over streams).
+ *   are summed over streams). A timed step is launched without its graph (the events
+ *   are stamped by the dispatches themselves).
  * tdb_batch_destroy frees the batch and all its streams; NULL-safe. */
 typedef struct tdb_batch_ctx* tdb_batch;
 tdb_status tdb_batch_create(int32_t n, const tdb_config* cfgs, const void* const* V0_dev, void* stream,

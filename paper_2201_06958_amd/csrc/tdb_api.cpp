@@ -1609,7 +1609,10 @@ struct tdb_batch_ctx {
   std::vector<int> pass_blocks, pass_T1, pass_T2;   // each stream's stage-pass grid, fixed at the caps
   double bytes_pass = 0.0, bytes_err = 0.0;
   bool dirty = true;
-  bool prof = false;
+  bool prof = false;                // pass timing on
+  int prof_every = 1;               // the passes of every prof_every-th step are timed
+  long long prof_steps = 0;
+  bool prof_now = false;            // this step is timed
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[2];
   // learned gate (parameters owned by the trainer that was attached)
@@ -1933,7 +1936,7 @@ tdb_status batch_kernels(tdb_batch_ctx* b, int p, hipStream_t s) {
   BHIPCHK(launch_batch_fetch_ptrs(b->h_vt[p][0], b->h_vt[p][1], b->d_v1, b->d_v0, n, s));
   for (int st = 0; st < 2; ++st) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (b->prof) {
+    if (b->prof_now) {
       e0 = take_bevent(b);
       e1 = take_bevent(b);
       if (e0 && e1) b->ev_used[TDB_PASS_PROJECT].push_back({e0, e1});
@@ -1975,7 +1978,7 @@ tdb_status batch_kernels(tdb_batch_ctx* b, int p, hipStream_t s) {
   }
   {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (b->prof) {
+    if (b->prof_now) {
       e0 = take_bevent(b);
       e1 = take_bevent(b);
       if (e0 && e1) b->ev_used[TDB_PASS_ERROR].push_back({e0, e1});
@@ -1994,7 +1997,7 @@ tdb_status batch_kernels(tdb_batch_ctx* b, int p, hipStream_t s) {
 // graphs off for the batch and the launches run as they are.
 template <typename TD, typename T>
 tdb_status batch_enqueue(tdb_batch_ctx* b, int p, hipStream_t s) {
-  const bool graph = b->use_graph && !b->prof;
+  const bool graph = b->use_graph && !b->prof_now;
   const int key = b->vw;
   if (graph && b->gexec[p] && b->gkey[p] == key) {
     BHIPCHK(hipGraphLaunch(b->gexec[p], s));
@@ -2132,6 +2135,7 @@ tdb_status batch_step(tdb_batch_ctx* b, const void* const* V, hipStream_t s) {
     b->vw = vw;
   }
   if (b->dirty) TRY(batch_upload_args(b, s));
+  b->prof_now = b->prof && b->prof_steps++ % b->prof_every == 0;
   TRY((batch_enqueue<TD, T>(b, p, s)));
   tdb_status prev = TDB_OK;
   std::vector<char> acted;
@@ -2559,6 +2563,8 @@ tdb_status tdb_batch_profile_enable(tdb_batch b, int32_t on) {
     v.clear();
   }
   b->prof = on != 0;
+  b->prof_every = on > 1 ? on : 1;
+  b->prof_steps = 0;
   return TDB_OK;
 }
 

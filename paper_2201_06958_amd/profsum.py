@@ -3,6 +3,7 @@
     python -m paper_2201_06958_amd.profsum stats DB --command CMD [--bench JSON] [--out FILE]
     python -m paper_2201_06958_amd.profsum pmc FETCH_DB WRITE_DB --command-fetch CMD
         --command-write CMD [--copy-bytes N] [--out FILE]
+    python -m paper_2201_06958_amd.profsum counters DB --command CMD [--match NAME] [--out FILE]
 
 `stats` tabulates per-kernel call counts and average durations from a
 `rocprofv3 --kernel-trace --stats` run (and, given the JSON lines bench.py printed
@@ -41,6 +42,11 @@ PASS_KERNELS = {
     "k_mpass_w4<float, 1>": _MATRIX,     # four-wave tiles (larger grids)
     "kb_mpass<float, 1>": _MATRIX,       # four-wave tiles for a batch of streams
     "k_fpass<float, float>": _GENERIC,   # generic pass
+    # column-block pass of batches (FP32 products; BF16-split), 4-entry fibers as float4
+    "kb_rpass<float, 1, 4, true>": ("rpass.hip", "mfma_util.h", "fused.h", "tdb_common.h", "tdb_kernels.h"),
+    "kb_rpass<float, 2, 4, true>": ("rpass.hip", "mfma_util.h", "fused.h", "tdb_common.h", "tdb_kernels.h"),
+    # column-block error pass of batches (mode-1 rank cap 24)
+    "kb_ferr_cols<float, float, 24>": ("fused_ops.hip", "fused.h", "tdb_common.h", "device_util.h"),
 }
 PASS_KERNEL = "k_mpass_w16<float, 1>"     # the pass of the reactive-flow workload
 
@@ -76,10 +82,11 @@ def stats_text(db: str, command: str, bench_json: str | None = None, bench_plain
            f"{'kernel':60s} {'calls':>7s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}"]
     for name, calls, total, avg, pct in rows[:top]:
         out.append(f"{_short(name)[:60]:60s} {calls:7d} {avg:10.2f} {total / 1e3:10.3f} {pct:6.2f}")
-    prof = [r for r in rows if ("tdb::" + PASS_KERNEL + "(") in r[0]]
     if bench_json:
         b = _bench_line(bench_json)
         rf = b["roofline"]
+        kern = rf.get("kernel_name", PASS_KERNEL)
+        prof = [r for r in rows if ("tdb::" + kern + "(") in r[0]]
         out += ["", "bench.py line printed by the profiled run:",
                 f"    value {b['value']:.1f} {b['unit']}, ms_per_step {b['ms_per_step']:.4f}",
                 f"    stage pass average launch (HIP events in bench.py): {rf['avg_launch_us']:.2f} us"
@@ -162,6 +169,27 @@ def read_pass_traffic(path: str, kernel: str = PASS_KERNEL):
     return None
 
 
+def counters_text(db: str, command: str, match: str) -> str:
+    """Per-dispatch averages of every counter of a `--pmc` run for the kernels whose
+    name contains `match` (one row per kernel and counter)."""
+    con = sqlite3.connect(db)
+    cols = [r[1] for r in con.execute("pragma table_info(counters_collection)")]
+    cands = [c for c in cols if c == "counter_name"] + [c for c in cols if "counter" in c and "name" in c]
+    if not cands:
+        raise SystemExit(f"no counter-name column among {cols}")
+    name_col = cands[0]
+    rows = con.execute(f"select kernel_name, {name_col}, value from counters_collection").fetchall()
+    agg = defaultdict(list)
+    for k, c, v in rows:
+        if match in k:
+            agg[(_short(k), c)].append(v)
+    out = ["# rocprofv3 --pmc (counters per dispatch)", "", "command:", f"    {command}", "",
+           f"{'kernel':40s} {'counter':34s} {'n':>5s} {'avg_per_dispatch':>18s}"]
+    for (k, c), vals in sorted(agg.items()):
+        out.append(f"{k[:40]:40s} {c[:34]:34s} {len(vals):5d} {sum(vals) / len(vals):18.1f}")
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -178,9 +206,16 @@ def main(argv=None):
     p.add_argument("--command-write", required=True)
     p.add_argument("--copy-bytes", type=int, default=256 * 1024 * 1024)
     p.add_argument("--out")
+    c = sub.add_parser("counters")
+    c.add_argument("db")
+    c.add_argument("--command", required=True)
+    c.add_argument("--match", default="tdb::")
+    c.add_argument("--out")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         text = stats_text(a.db, a.command, a.bench, a.bench_plain)
+    elif a.cmd == "counters":
+        text = counters_text(a.db, a.command, a.match)
     else:
         text, _ = pmc_text(a.fetch_db, a.write_db, a.command_fetch, a.command_write, a.copy_bytes)
     if a.out:

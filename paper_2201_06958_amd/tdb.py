@@ -411,8 +411,8 @@ class Batch:
             ms = self._ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
         self._check(self.lib.tdb_batch_gate_attach(self.h, gate.h if gate is not None else None, ms, mid))
 
-    def profile_enable(self, on: bool = True):
-        self._check(self.lib.tdb_batch_profile_enable(self.h, 1 if on else 0))
+    def profile_enable(self, on: bool = True, every: int = 1):
+        self._check(self.lib.tdb_batch_profile_enable(self.h, max(1, int(every)) if on else 0))
 
     def profile_read(self, pass_name: str = "project") -> dict:
         n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()

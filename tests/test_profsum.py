@@ -51,3 +51,18 @@ def test_stats_text(tmp_path):
     text = profsum.stats_text(str(db), "the command")
     assert "tdb::k_mpass_w16<float, 1>" in text and "the command" in text
     assert text.index("k_mpass") < text.index("k_fqr")
+
+
+def test_counters_text(tmp_path):
+    db = tmp_path / "c.db"
+    con = sqlite3.connect(db)
+    con.execute("create table counters_collection (kernel_name text, counter_name text, value real)")
+    con.executemany("insert into counters_collection values (?, ?, ?)",
+                    [("void tdb::kb_rpass<float, 1, 4, true>(x)", "SQ_INSTS_MFMA", 100.0),
+                     ("void tdb::kb_rpass<float, 1, 4, true>(x)", "SQ_INSTS_MFMA", 300.0),
+                     ("void other(x)", "SQ_INSTS_MFMA", 7.0)])
+    con.commit()
+    con.close()
+    text = profsum.counters_text(str(db), "cmd", "kb_rpass")
+    row = [ln for ln in text.splitlines() if "SQ_INSTS_MFMA" in ln]
+    assert len(row) == 1 and row[0].split()[-1] == "200.0" and row[0].split()[-2] == "2"
