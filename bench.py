@@ -88,8 +88,9 @@ def _run_ensemble(specs, snaps, warmup, steps, precision, profile_every):
     if profile_every:
         prof = {"project": b.profile_read("project"), "error": b.profile_read("error")}
     sts = [m.stats() for m in b.streams]
+    plan = b.plan()
     b.close()
-    return el, sts, prof
+    return el, sts, dict(prof, plan=plan)
 
 
 def _avg_s(p):
@@ -387,7 +388,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": 1e3 * step_s, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": dict(desc, precision="f32", path="fused-batched", ring_bytes=ring,
-                       cache_resident=ring <= LLC_BYTES),
+                       cache_resident=ring <= LLC_BYTES, kernel_plan=prof["plan"]),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic["traffic_bytes"] if traffic else None,

@@ -272,6 +272,26 @@ tdb_status tdb_batch_create(int32_t n, const tdb_config* cfgs, const void* const
                             tdb_batch* out);
 tdb_status tdb_batch_ingest(tdb_batch b, const void* const* V_dev, void* stream);
 tdb_status tdb_batch_flush(tdb_batch b);
+
+/* The batch's kernel plan, chosen once at creation (host-written struct, caller-owned).
+ * The stage pass of every member is one kernel: matrix-core column blocks of all rows
+ * (pass_kind 2; pass_cols columns of mode 2 per workgroup), matrix-core tiles (1) or
+ * vector-ALU tiles (0); the error pass takes column blocks of the mode-1 unfolding
+ * (err_kind 1) or row slabs (0). With more than one candidate, each is timed on the
+ * first snapshots (the pass over three launches after one untimed; the partials only,
+ * no state changes) and the fastest kept; the choice is cached for the process per
+ * shape class (storage and compute types, the members' extents and caps).
+ * source: 0 the fixed rule (TDB_AUTOTUNE=0 in the environment, or TDB_RPASS_COLS
+ * forcing the column count), 1 timed at creation,
+ * 2 the cached plan of an earlier batch of the same class. pass_us: the timed
+ * candidates' average launch (column blocks of 64, of 32 columns, matrix-core tiles;
+ * 0 = not timed); err_us: row slabs, column blocks. */
+typedef struct {
+  int32_t pass_kind, pass_cols, err_kind, source;
+  double pass_us[3];
+  double err_us[2];
+} tdb_batch_plan_info;
+tdb_status tdb_batch_plan(tdb_batch b, tdb_batch_plan_info* out);
 tdb_status tdb_batch_stream(tdb_batch b, int32_t i, tdb_handle* out);
 tdb_status tdb_batch_profile_enable(tdb_batch b, int32_t on);
 tdb_status tdb_batch_profile_read(tdb_batch b, int32_t pass, int64_t* launches, double* total_ms,

@@ -210,11 +210,12 @@ hipError_t launch_batch_fpass(const FPassArgs* tab, const void* const* v1, const
 // modes 1 and 3 per workgroup of 8 waves; the mode-3 product is applied to the small
 // results. T2 follows the mode-3 extent the batch's streams share (rpass_cols_for).
 int rpass_cols_for(int n3c);
+bool rpass_cols_ok(int n3c, int t2);
 size_t rpass_lds_bytes(int T2, int r1, int r2, int N3);
 bool rpass_shape_ok(int r1, int r2, int r3, int T2, int N3);
 template <typename TD>
 hipError_t launch_batch_rpass(const FPassArgs* tab, const void* const* v1, const void* const* v0, BatchMap m,
-                              int blocks, int flavor, int n3c, int vw, size_t lds, hipStream_t s,
+                              int blocks, int flavor, int n3c, int t2, int vw, size_t lds, hipStream_t s,
                               hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename TD>
 hipError_t launch_batch_mpass(const FPassArgs* tab, const void* const* v1, const void* const* v0, BatchMap m,
@@ -249,6 +250,9 @@ hipError_t launch_batch_ferr(const FErrArgs* tab, const void* const* v1, BatchMa
                              CtrlState* const* ctab, BatchSummary* out, unsigned* counter, unsigned long long* seq,
                              size_t lds_final, int r1c, hipStream_t s, hipEvent_t ev0 = nullptr,
                              hipEvent_t ev1 = nullptr);
+template <typename TD, typename T>
+hipError_t launch_batch_ferr_partials(const FErrArgs* tab, const void* const* v1, BatchMap m, int blocks, int r1c,
+                                      hipStream_t s);
 hipError_t launch_batch_fetch_ptrs(const void* const* h1, const void* const* h0, const void** d1, const void** d0,
                                    int n, hipStream_t s);
 hipError_t launch_batch_hold_mask(CtrlState* const* ctab, const int* mask, int* save, int n, int restore,

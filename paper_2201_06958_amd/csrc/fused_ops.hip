@@ -1634,6 +1634,31 @@ __global__ void __launch_bounds__(FEC_COLS) kb_ferr_cols(const FErrArgs* __restr
   }
 }
 
+// The error pass's partials alone (no controller): the column-block form for r1c > 0.
+template <typename TD, typename T>
+hipError_t launch_batch_ferr_partials(const FErrArgs* tab, const void* const* v1, BatchMap m, int blocks, int r1c,
+                                      hipStream_t s) {
+  switch (r1c) {
+#define FEC_CASE(R)                                                                                 \
+  case R:                                                                                           \
+    hipLaunchKernelGGL((kb_ferr_cols<TD, T, R>), dim3(blocks), dim3(FEC_COLS), 0u, s, tab, v1, m); \
+    break;
+    FEC_CASE(4) FEC_CASE(8) FEC_CASE(12) FEC_CASE(16) FEC_CASE(20) FEC_CASE(24) FEC_CASE(28) FEC_CASE(32)
+#undef FEC_CASE
+    default:
+      hipLaunchKernelGGL((kb_ferr<TD, T>), dim3(blocks), dim3(256), 0u, s, tab, v1, m);
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_batch_ferr_partials<float, float>(const FErrArgs*, const void* const*, BatchMap, int, int,
+                                                             hipStream_t);
+template hipError_t launch_batch_ferr_partials<float, double>(const FErrArgs*, const void* const*, BatchMap, int, int,
+                                                              hipStream_t);
+template hipError_t launch_batch_ferr_partials<double, double>(const FErrArgs*, const void* const*, BatchMap, int,
+                                                               int, hipStream_t);
+template hipError_t launch_batch_ferr_partials<double, float>(const FErrArgs*, const void* const*, BatchMap, int, int,
+                                                              hipStream_t);
+
 template <typename TD, typename T>
 hipError_t launch_batch_ferr(const FErrArgs* tab, const void* const* v1, BatchMap m, int blocks, int nstreams,
                              CtrlState* const* ctab, BatchSummary* out, unsigned* counter, unsigned long long* seq,

@@ -38,9 +38,10 @@ namespace tdb {
 constexpr int RP_NW = 8;    // waves per workgroup
 constexpr int RP_PS = 20;   // row stride (floats) of 16-entry operand rows in LDS
 
-// Columns of mode 2 per workgroup for a compile-time mode-3 extent (0: run time).
-__host__ __device__ constexpr int rp_cols(int n3c) { return n3c == 4 ? 64 : 32; }
-int rpass_cols_for(int n3c) { return rp_cols(n3c); }
+// Columns of mode 2 per workgroup: 64 or 32 for a mode-3 extent of 4, 32 otherwise
+// (the F2' accumulators of 8 entries of mode 3 would not fit beside 64 columns).
+int rpass_cols_for(int n3c) { return n3c == 4 ? 64 : 32; }
+bool rpass_cols_ok(int n3c, int t2) { return t2 == 32 || (t2 == 64 && n3c == 4); }
 
 // LDS regions (float offsets). Region X = [0, oB1) holds D and the H1 blocks during the
 // subtiles, the raw copies of B2's rows, P1, P2 and B3 before them and F2' (as A for
@@ -150,9 +151,8 @@ __device__ __forceinline__ mf4 mmk(mf4 acc, const float* A, int sa, const float*
   return acc;
 }
 
-template <typename TD, int MF, int N3C, bool VEC, int NB1, int NB2>
+template <typename TD, int MF, int N3C, bool VEC, int T2, int NB1, int NB2>
 __device__ __forceinline__ void rpass_body(const FPassArgs& a, int bx) {
-  constexpr int T2 = rp_cols(N3C);
   constexpr int DS = T2 + 4;                            // row stride of D and B2^T
   constexpr int NBC = T2 / 16;                          // 16-column chunks of the block
   constexpr int N3M = N3C ? N3C : 8;                    // largest mode-3 extent
@@ -469,7 +469,7 @@ __device__ __forceinline__ void rpass_body(const FPassArgs& a, int bx) {
   }
 }
 
-template <typename TD, int MF, int N3C, bool VEC>
+template <typename TD, int MF, int N3C, bool VEC, int T2>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) kb_rpass(
     const FPassArgs* __restrict__ tab, const void* const* v1, const void* const* v0, BatchMap m) {
   const int s = m.sid[blockIdx.x];
@@ -480,50 +480,57 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
   const int bx = blockIdx.x - m.start[s];
   // rank blocks of modes 1 and 2 (the host admits ranks up to 32)
   const int sel = (a.r1 > 16 ? 2 : 0) + (a.r2 > 16 ? 1 : 0);
-  if (sel == 0) rpass_body<TD, MF, N3C, VEC, 1, 1>(a, bx);
-  else if (sel == 1) rpass_body<TD, MF, N3C, VEC, 1, 2>(a, bx);
-  else if (sel == 2) rpass_body<TD, MF, N3C, VEC, 2, 1>(a, bx);
-  else rpass_body<TD, MF, N3C, VEC, 2, 2>(a, bx);
+  if (sel == 0) rpass_body<TD, MF, N3C, VEC, T2, 1, 1>(a, bx);
+  else if (sel == 1) rpass_body<TD, MF, N3C, VEC, T2, 1, 2>(a, bx);
+  else if (sel == 2) rpass_body<TD, MF, N3C, VEC, T2, 2, 1>(a, bx);
+  else rpass_body<TD, MF, N3C, VEC, T2, 2, 2>(a, bx);
 }
 
-template <typename TD, int MF, int N3C, bool VEC>
+template <typename TD, int MF, int N3C, bool VEC, int T2>
 hipError_t launch_rpass_as(const FPassArgs* tab, const void* const* v1, const void* const* v0, BatchMap m, int blocks,
                            size_t lds, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  hipError_t e = hipFuncSetAttribute((const void*)kb_rpass<TD, MF, N3C, VEC>,
+  hipError_t e = hipFuncSetAttribute((const void*)kb_rpass<TD, MF, N3C, VEC, T2>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipExtLaunchKernelGGL((kb_rpass<TD, MF, N3C, VEC>), dim3(blocks), dim3(RP_NW * 64), (uint32_t)lds, s, ev0, ev1, 0u,
-                        tab, v1, v0, m);
+  hipExtLaunchKernelGGL((kb_rpass<TD, MF, N3C, VEC, T2>), dim3(blocks), dim3(RP_NW * 64), (uint32_t)lds, s, ev0, ev1,
+                        0u, tab, v1, v0, m);
   return hipGetLastError();
 }
 
 template <typename TD, int MF>
 hipError_t launch_rpass_mf(const FPassArgs* tab, const void* const* v1, const void* const* v0, BatchMap m, int blocks,
-                           int n3c, bool vec, size_t lds, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                           int n3c, bool vec, int t2, size_t lds, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if constexpr (sizeof(TD) == 4) {
-    if (vec && n3c == 4) return launch_rpass_as<TD, MF, 4, true>(tab, v1, v0, m, blocks, lds, s, ev0, ev1);
-    if (vec && n3c == 8) return launch_rpass_as<TD, MF, 8, true>(tab, v1, v0, m, blocks, lds, s, ev0, ev1);
+    if (vec && n3c == 4)
+      return t2 == 64 ? launch_rpass_as<TD, MF, 4, true, 64>(tab, v1, v0, m, blocks, lds, s, ev0, ev1)
+                      : launch_rpass_as<TD, MF, 4, true, 32>(tab, v1, v0, m, blocks, lds, s, ev0, ev1);
+    if (vec && n3c == 8) return launch_rpass_as<TD, MF, 8, true, 32>(tab, v1, v0, m, blocks, lds, s, ev0, ev1);
   }
-  if (n3c == 4) return launch_rpass_as<TD, MF, 4, false>(tab, v1, v0, m, blocks, lds, s, ev0, ev1);
-  if (n3c == 8) return launch_rpass_as<TD, MF, 8, false>(tab, v1, v0, m, blocks, lds, s, ev0, ev1);
-  return launch_rpass_as<TD, MF, 0, false>(tab, v1, v0, m, blocks, lds, s, ev0, ev1);
+  if (n3c == 4)
+    return t2 == 64 ? launch_rpass_as<TD, MF, 4, false, 64>(tab, v1, v0, m, blocks, lds, s, ev0, ev1)
+                    : launch_rpass_as<TD, MF, 4, false, 32>(tab, v1, v0, m, blocks, lds, s, ev0, ev1);
+  if (n3c == 8) return launch_rpass_as<TD, MF, 8, false, 32>(tab, v1, v0, m, blocks, lds, s, ev0, ev1);
+  return launch_rpass_as<TD, MF, 0, false, 32>(tab, v1, v0, m, blocks, lds, s, ev0, ev1);
 }
 
-// n3c: the mode-3 extent shared by every stream of the launch (4 or 8), else 0; the
-// streams' plans use T2 = rpass_cols_for(n3c). vw: 4 or 8 when every stream's snapshots
-// are FP32 with N3 = vw on 16-byte addresses (whole fibers as float4 loads), else 0.
+// n3c: the mode-3 extent shared by every stream of the launch (4 or 8), else 0; t2: the
+// columns of mode 2 every stream's plan uses (rpass_cols_ok). vw: 4 or 8 when every
+// stream's snapshots are FP32 with N3 = vw on 16-byte addresses (whole fibers as float4
+// loads), else 0.
 template <typename TD>
 hipError_t launch_batch_rpass(const FPassArgs* tab, const void* const* v1, const void* const* v0, BatchMap m,
-                              int blocks, int flavor, int n3c, int vw, size_t lds, hipStream_t s, hipEvent_t ev0,
-                              hipEvent_t ev1) {
+                              int blocks, int flavor, int n3c, int t2, int vw, size_t lds, hipStream_t s,
+                              hipEvent_t ev0, hipEvent_t ev1) {
   if (n3c != 4 && n3c != 8) n3c = 0;
+  if (!rpass_cols_ok(n3c, t2)) return hipErrorInvalidValue;
   const bool vec = sizeof(TD) == 4 && vw != 0 && vw == n3c;
-  return flavor == MPASS_F32 ? launch_rpass_mf<TD, MPASS_F32>(tab, v1, v0, m, blocks, n3c, vec, lds, s, ev0, ev1)
-                             : launch_rpass_mf<TD, MPASS_BF16S>(tab, v1, v0, m, blocks, n3c, vec, lds, s, ev0, ev1);
+  return flavor == MPASS_F32
+             ? launch_rpass_mf<TD, MPASS_F32>(tab, v1, v0, m, blocks, n3c, vec, t2, lds, s, ev0, ev1)
+             : launch_rpass_mf<TD, MPASS_BF16S>(tab, v1, v0, m, blocks, n3c, vec, t2, lds, s, ev0, ev1);
 }
 template hipError_t launch_batch_rpass<float>(const FPassArgs*, const void* const*, const void* const*, BatchMap, int,
-                                              int, int, int, size_t, hipStream_t, hipEvent_t, hipEvent_t);
+                                              int, int, int, int, size_t, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_batch_rpass<double>(const FPassArgs*, const void* const*, const void* const*, BatchMap,
-                                               int, int, int, int, size_t, hipStream_t, hipEvent_t, hipEvent_t);
+                                               int, int, int, int, int, size_t, hipStream_t, hipEvent_t, hipEvent_t);
 
 }  // namespace tdb

@@ -10,6 +10,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <unordered_map>
+#include <mutex>
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -1605,6 +1608,8 @@ struct tdb_batch_ctx {
   int rows = 0;                     // 1: the row-block pass (every stream takes it)
   int vw = 0;                       // fiber load width of the row-block pass this step
   int rp_n3c = 0;                   // mode-3 extent the column-block kernel is built for (0: any)
+  int rp_t2 = 64;                   // its columns of mode 2 per workgroup
+  tdb_batch_plan_info tune{};       // the plan and how it was chosen
   int err_r1c = 0;                  // column-block error pass compiled for r1 <= err_r1c (0: slab pass)
   std::vector<int> pass_blocks, pass_T1, pass_T2;   // each stream's stage-pass grid, fixed at the caps
   double bytes_pass = 0.0, bytes_err = 0.0;
@@ -1797,26 +1802,27 @@ tdb_status batch_upload_args(tdb_batch_ctx* b, hipStream_t s) {
   return TDB_OK;
 }
 
-// Launch shapes at the caps, block maps, tables.
-tdb_status batch_setup(tdb_batch_ctx* b) {
+// The batch's plan: which stage-pass kernel, its columns per block, which error pass.
+struct BatchChoice {
+  int pass_kind = 2;   // 0: vector-ALU tiles, 1: matrix-core tiles, 2: matrix-core column blocks
+  int cols = 64;       // columns of mode 2 per column block
+  int err_cols = 1;    // 1: column-block error pass, 0: row slabs
+};
+
+// Launch shapes at the caps and block maps for choice c (every stream the same kernel;
+// the column-block pass only when every stream takes it, then the matrix-core tiles
+// only when every stream takes those; else the vector-ALU tiles).
+tdb_status batch_plan(tdb_batch_ctx* b, const BatchChoice& c) {
   const int n = b->n;
-  // one stage-pass kernel serves every stream: the matrix-core pass only when all
-  // streams take it at their caps
+  for (int i = 0; i < n; ++i) {
+    b->st[i]->no_rpass = c.pass_kind != 2;
+    b->st[i]->no_mfma = c.pass_kind == 0;
+    b->st[i]->rpass_cols = c.cols;
+  }
+  b->rp_t2 = c.cols;
   {
-    // the row-block pass only when every stream takes it; then the tile matrix-core
-    // pass only when every stream takes that; else the generic pass
-    {
-      // the column-block kernel is built for the mode-3 extent the streams share (4 or
-      // 8; else any up to 8), and that fixes its column count
-      int n3c = (int)b->st[0]->N[2];
-      for (int i = 1; i < n; ++i)
-        if (b->st[i]->N[2] != n3c) n3c = 0;
-      if (n3c != 4 && n3c != 8) n3c = 0;
-      b->rp_n3c = n3c;
-      for (int i = 0; i < n; ++i) b->st[i]->rpass_cols = rpass_cols_for(n3c);
-    }
-    bool all_rows = true;
-    for (int i = 0; i < n; ++i) all_rows = all_rows && plan_pass(b->st[i], b->st[i]->caps, true).rows == 1;
+    bool all_rows = c.pass_kind == 2;
+    for (int i = 0; i < n && all_rows; ++i) all_rows = plan_pass(b->st[i], b->st[i]->caps, true).rows == 1;
     if (!all_rows)
       for (int i = 0; i < n; ++i) b->st[i]->no_rpass = true;
     b->rows = all_rows ? 1 : 0;
@@ -1836,11 +1842,16 @@ tdb_status batch_setup(tdb_batch_ctx* b) {
     // mode-1 rank cap at most 32 (compiled for the cap rounded up to 4)
     int r1max = 0;
     for (int i = 0; i < n; ++i) r1max = std::max(r1max, b->st[i]->caps[0]);
-    const char* env = std::getenv("TDB_FERR_COLS");
-    const bool cols = r1max <= 32 && !(env && env[0] == '0');
+    const bool cols = c.err_cols && r1max <= 32;
     b->err_r1c = cols ? (r1max + 3) / 4 * 4 : 0;
     for (int i = 0; i < n; ++i) b->st[i]->ferr_cols = cols;
   }
+  b->pass_blocks.clear();
+  b->pass_T1.clear();
+  b->pass_T2.clear();
+  b->lds_pass = b->lds_fin = b->lds_qr = b->lds_post = b->lds_mprep = b->lds_final = 0;
+  b->lds_rows = b->lds_exp = 0;
+  b->bytes_pass = b->bytes_err = 0.0;
   std::vector<int> c_pass(n), c_red(n), c_fin0(n), c_fin1(n), c_qr(n, 3), c_qa(n), c_post(n), c_exp(n), c_err(n);
   std::vector<double> w_pass(n, 0.0), w_err(n, 0.0);
   for (int i = 0; i < n; ++i) {
@@ -1892,6 +1903,167 @@ tdb_status batch_setup(tdb_batch_ctx* b) {
   TRY(make_map(b, c_post, &b->m_post, &b->g_post));
   TRY(make_map(b, c_exp, &b->m_exp, &b->g_exp));
   TRY(make_map(b, c_err, &b->m_err, &b->g_err, &w_err));
+  b->dirty = true;
+  b->gkey[0] = b->gkey[1] = -1;
+  return TDB_OK;
+}
+
+// Plans chosen by timing, per shape class of batch (storage and compute types and the
+// members' extents and caps), for the life of the process.
+std::mutex g_tune_mu;
+std::unordered_map<std::string, BatchChoice> g_tune_cache;
+
+std::string tune_key(const tdb_batch_ctx* b) {
+  std::vector<std::array<long long, 6>> v;
+  for (const tdb_ctx* h : b->st)
+    v.push_back({h->N[0], h->N[1], h->N[2], h->caps[0], h->caps[1], h->caps[2]});
+  std::sort(v.begin(), v.end());
+  std::string k = std::to_string(b->data32) + "/" + std::to_string(b->f32) + "/" +
+                  std::to_string(b->st[0]->bf16s ? 1 : 0) + ":";
+  for (const auto& e : v)
+    for (long long x : e) k += std::to_string(x) + ",";
+  return k;
+}
+
+// Average duration (us) of `reps` launches of the stage pass (stage-1 tables) or of the
+// error pass's partials under the current plan, after one untimed launch, on the first
+// snapshots (their difference is zero: the kernels' cost does not depend on the values).
+// Both only write partial buffers that every step overwrites.
+template <typename TD, typename T>
+tdb_status time_plan(tdb_batch_ctx* b, bool pass, hipStream_t s, double* us) {
+  const int n = b->n, reps = 3;
+  for (int i = 0; i < n; ++i) b->h_vt[0][0][i] = b->h_vt[0][1][i] = b->st[i]->Vprev;
+  b->vw = 0;
+  if (sizeof(TD) == 4 && (b->st[0]->N[2] == 4 || b->st[0]->N[2] == 8)) {
+    int vw = (int)b->st[0]->N[2];
+    for (int i = 0; i < n && vw; ++i)
+      if (b->st[i]->N[2] != vw || (reinterpret_cast<uintptr_t>(b->h_vt[0][0][i]) & 15) != 0) vw = 0;
+    b->vw = vw;
+  }
+  TRY(batch_upload_args(b, s));
+  BHIPCHK(launch_batch_fetch_ptrs(b->h_vt[0][0], b->h_vt[0][1], b->d_v1, b->d_v0, n, s));
+  hipEvent_t e0 = take_bevent(b), e1 = take_bevent(b);
+  if (!e0 || !e1) { b->err = "hipEventCreate failed"; return TDB_EHIP; }
+  for (int k = 0; k <= reps; ++k) {
+    if (k == 1) BHIPCHK(hipEventRecord(e0, s));
+    if (pass) {
+      if (b->rows)
+        BHIPCHK((launch_batch_rpass<TD>(b->d_fa[0], b->d_v1, b->d_v0, b->m_pass, b->g_pass, b->mflavor, b->rp_n3c,
+                                        b->rp_t2, b->vw, b->lds_pass, s)));
+      else if (b->mflavor)
+        BHIPCHK((launch_batch_mpass<TD>(b->d_fa[0], b->d_v1, b->d_v0, b->m_pass, b->g_pass, b->mflavor,
+                                        b->lds_pass, s)));
+      else
+        BHIPCHK((launch_batch_fpass<TD, T>(b->d_fa[0], b->d_v1, b->d_v0, b->m_pass, b->g_pass, b->lds_pass, s)));
+    } else {
+      BHIPCHK((launch_batch_ferr_partials<TD, T>(b->d_ea, b->d_v1, b->m_err, b->g_err, b->err_r1c, s)));
+    }
+  }
+  BHIPCHK(hipEventRecord(e1, s));
+  BHIPCHK(hipEventSynchronize(e1));
+  float ms = 0.0f;
+  BHIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  b->ev_pool.push_back(e0);
+  b->ev_pool.push_back(e1);
+  *us = 1e3 * (double)ms / reps;
+  return TDB_OK;
+}
+
+// Chooses the plan: the cached one of an earlier batch of the same shape class, else, when
+// more than one candidate applies and TDB_AUTOTUNE is not 0, the fastest by time_plan
+// (stage pass first: column blocks of 64 and of 32 columns for a shared mode-3 extent of
+// 4, and the matrix-core tiles; then the error pass: column blocks and row slabs), else
+// the fixed rule (column blocks of 64 columns for N3 = 4, else 32; column-block error
+// pass).
+template <typename TD, typename T>
+tdb_status batch_tune(tdb_batch_ctx* b, hipStream_t s) {
+  const int n = b->n;
+  int n3c = (int)b->st[0]->N[2];
+  for (int i = 1; i < n; ++i)
+    if (b->st[i]->N[2] != n3c) n3c = 0;
+  if (n3c != 4 && n3c != 8) n3c = 0;
+  b->rp_n3c = n3c;
+  BatchChoice rule;
+  rule.pass_kind = 2;
+  rule.cols = rpass_cols_for(n3c);
+  rule.err_cols = 1;
+  const char* env = std::getenv("TDB_AUTOTUNE");
+  bool tune = !(env && env[0] == '0');
+  if (const char* ce = std::getenv("TDB_RPASS_COLS")) {
+    // a forced column count (32, or 64 with N3 = 4) takes the fixed rule with it
+    const int tc = std::atoi(ce);
+    if (rpass_cols_ok(n3c, tc)) {
+      rule.cols = tc;
+      tune = false;
+    }
+  }
+  const std::string key = tune_key(b);
+  b->tune = tdb_batch_plan_info{};
+  if (tune) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      TRY(batch_plan(b, it->second));
+      b->tune.source = 2;
+      return TDB_OK;
+    }
+  }
+  if (!tune) {
+    TRY(batch_plan(b, rule));
+    b->tune.source = 0;
+    return TDB_OK;
+  }
+  // stage-pass candidates that apply to every stream
+  std::vector<BatchChoice> cands;
+  BatchChoice c64 = rule, c32 = rule, ctile = rule;
+  c64.cols = 64;
+  c32.cols = 32;
+  ctile.pass_kind = 1;
+  ctile.cols = 32;
+  if (n3c == 4) cands.push_back(c64);
+  cands.push_back(c32);
+  cands.push_back(ctile);
+  BatchChoice best = rule;
+  double best_us = 1e30;
+  int timed = 0;
+  for (const BatchChoice& c : cands) {
+    TRY(batch_plan(b, c));
+    // a candidate the streams cannot all take falls back to another kernel: skip it
+    if ((c.pass_kind == 2) != (b->rows == 1) || (c.pass_kind >= 1 && !b->mflavor)) continue;
+    double us = 0.0;
+    TRY((time_plan<TD, T>(b, true, s, &us)));
+    const int slot = c.pass_kind == 1 ? 2 : (c.cols == 64 ? 0 : 1);
+    b->tune.pass_us[slot] = us;
+    ++timed;
+    if (us < best_us) { best_us = us; best = c; }
+  }
+  if (timed == 0) best = rule;
+  // error pass
+  int r1max = 0;
+  for (int i = 0; i < n; ++i) r1max = std::max(r1max, b->st[i]->caps[0]);
+  if (r1max <= 32) {
+    double eus[2] = {0.0, 0.0};
+    for (int ec = 0; ec < 2; ++ec) {
+      BatchChoice c = best;
+      c.err_cols = ec;
+      TRY(batch_plan(b, c));
+      TRY((time_plan<TD, T>(b, false, s, &eus[ec])));
+      b->tune.err_us[ec] = eus[ec];
+    }
+    best.err_cols = eus[1] <= eus[0] ? 1 : 0;
+  } else {
+    best.err_cols = 0;
+  }
+  TRY(batch_plan(b, best));
+  b->tune.source = 1;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune_cache[key] = best;
+  return TDB_OK;
+}
+
+// Tables, pinned buffers and the plan of a new batch (its members initialised).
+tdb_status batch_setup(tdb_batch_ctx* b, hipStream_t s) {
+  const int n = b->n;
   const size_t nn = (size_t)n;
   TRY(balloc(b, &b->d_fa[0], &b->h_fa[0], nn));
   TRY(balloc(b, &b->d_fa[1], &b->h_fa[1], nn));
@@ -1926,6 +2098,11 @@ tdb_status batch_setup(tdb_batch_ctx* b) {
   for (int i = 0; i < n; ++i) ct[i] = b->st[i]->ctrl;
   TRY(balloc<CtrlState*>(b, &b->d_ctab, nullptr, nn));
   BHIPCHK(hipMemcpy(b->d_ctab, ct.data(), nn * sizeof(CtrlState*), hipMemcpyHostToDevice));
+  tdb_status r;
+  if (b->data32) r = b->f32 ? batch_tune<float, float>(b, s) : batch_tune<float, double>(b, s);
+  else r = b->f32 ? batch_tune<double, float>(b, s) : batch_tune<double, double>(b, s);
+  TRY(r);
+  BHIPCHK(hipStreamSynchronize(s));
   return TDB_OK;
 }
 
@@ -1944,7 +2121,7 @@ tdb_status batch_kernels(tdb_batch_ctx* b, int p, hipStream_t s) {
     }
     if (b->rows)
       BHIPCHK((launch_batch_rpass<TD>(b->d_fa[st], b->d_v1, b->d_v0, b->m_pass, b->g_pass, b->mflavor, b->rp_n3c,
-                                      b->vw, b->lds_pass, s, e0, e1)));
+                                      b->rp_t2, b->vw, b->lds_pass, s, e0, e1)));
     else if (b->mflavor)
       BHIPCHK((launch_batch_mpass<TD>(b->d_fa[st], b->d_v1, b->d_v0, b->m_pass, b->g_pass, b->mflavor, b->lds_pass,
                                       s, e0, e1)));
@@ -2520,7 +2697,7 @@ tdb_status tdb_batch_create(int32_t n, const tdb_config* cfgs, const void* const
       if (r != TDB_OK) { b->err = "stream " + std::to_string(i) + ": " + h->err; return r; }
       h->ready = true;
     }
-    return batch_setup(b);
+    return batch_setup(b, s);
   };
   tdb_status st = run();
   if (st != TDB_OK) {
@@ -2593,6 +2770,17 @@ void tdb_batch_destroy(tdb_batch b) {
   if (!b) return;
   (void)hipDeviceSynchronize();
   delete b;
+}
+
+tdb_status tdb_batch_plan(tdb_batch b, tdb_batch_plan_info* out) {
+  if (!b) { g_create_error = "batch is NULL"; return TDB_EINVAL; }
+  if (!out) { b->err = "out is NULL"; return TDB_EINVAL; }
+  tdb_batch_plan_info q = b->tune;
+  q.pass_kind = b->rows ? 2 : (b->mflavor ? 1 : 0);
+  q.pass_cols = b->rows ? b->rp_t2 : (b->pass_T2.empty() ? 0 : b->pass_T2[0]);
+  q.err_kind = b->err_r1c ? 1 : 0;
+  *out = q;
+  return TDB_OK;
 }
 
 tdb_status tdb_batch_flush(tdb_batch b) {

@@ -131,6 +131,7 @@ def load_library(path: str = LIB_PATH):
                                      ctypes.POINTER(H)]
     lib.tdb_batch_ingest.argtypes = [H, ctypes.POINTER(P), P]
     lib.tdb_batch_flush.argtypes = [H]
+    lib.tdb_batch_plan.argtypes = [H, ctypes.POINTER(TdbBatchPlan)]
     lib.tdb_batch_stream.argtypes = [H, ctypes.c_int32, ctypes.POINTER(H)]
     lib.tdb_batch_profile_enable.argtypes = [H, ctypes.c_int32]
     lib.tdb_batch_profile_read.argtypes = [H, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
@@ -155,7 +156,8 @@ def load_library(path: str = LIB_PATH):
     lib.tdb_batch_last_error.restype = ctypes.c_char_p
     for name in ("tdb_init", "tdb_init_from_factors", "tdb_ingest_snapshot", "tdb_flush", "tdb_get_core_and_bases",
                  "tdb_reconstruct", "tdb_set_threshold", "tdb_get_stats", "tdb_batch_create",
-                 "tdb_batch_ingest", "tdb_batch_flush", "tdb_batch_stream", "tdb_batch_profile_enable",
+                 "tdb_batch_ingest", "tdb_batch_flush", "tdb_batch_plan", "tdb_batch_stream",
+                 "tdb_batch_profile_enable",
                  "tdb_batch_profile_read", "tdb_batch_gate_attach", "tdb_gate_load", "tdb_gate_create", "tdb_gate_set_params",
                  "tdb_gate_get_params", "tdb_gate_forward", "tdb_gate_grad", "tdb_gate_train_step"):
         getattr(lib, name).restype = ctypes.c_int32
@@ -359,6 +361,11 @@ class Compressor:
             pass
 
 
+class TdbBatchPlan(ctypes.Structure):
+    _fields_ = [("pass_kind", ctypes.c_int32), ("pass_cols", ctypes.c_int32), ("err_kind", ctypes.c_int32),
+                ("source", ctypes.c_int32), ("pass_us", ctypes.c_double * 3), ("err_us", ctypes.c_double * 2)]
+
+
 class Batch:
     """Many independent third-order streams advanced together (see tdb.h): one launch
     per kernel covers every stream. `configs` holds one keyword dict per stream with
@@ -400,6 +407,16 @@ class Batch:
     def flush(self):
         """Read the newest step if it has not been read (pipelined batches)."""
         self._check(self.lib.tdb_batch_flush(self.h))
+
+    def plan(self) -> dict:
+        """The kernel plan chosen at creation (see tdb_batch_plan)."""
+        q = TdbBatchPlan()
+        self._check(self.lib.tdb_batch_plan(self.h, ctypes.byref(q)))
+        kinds = {0: "vector-alu-tiles", 1: "matrix-core-tiles", 2: "matrix-core-columns"}
+        return {"pass": kinds[q.pass_kind], "pass_cols": q.pass_cols,
+                "error_pass": "columns" if q.err_kind else "row-slabs",
+                "source": {0: "rule", 1: "timed", 2: "cached"}[q.source],
+                "pass_us": list(q.pass_us), "err_us": list(q.err_us)}
 
     def gate_attach(self, gate, mean_std=None, mode: str = "active"):
         """Use a trained Gate (kept alive by the caller) with the given feature statistics

@@ -227,3 +227,87 @@ def test_batch_ensemble(precision):
         _say(f"  stream {i} {specs[i].dims} ranks {r}: reconstruction rel {rel:.2e}, sigma rel {rels:.2e}")
         assert rel < bar and rels < bar
     b.close()
+
+
+@pytest.mark.parametrize("cols", [32, 64])
+@pytest.mark.parametrize("precision", ["f32", "bf16s"])
+def test_batch_ensemble_column_counts(cols, precision):
+    """The column-block pass with 32 and with 64 columns of mode 2 per workgroup (the two
+    shapes the batch's tuner chooses between for a mode-3 extent of 4), forced, against
+    the oracle."""
+    old = os.environ.get("TDB_RPASS_COLS")
+    os.environ["TDB_RPASS_COLS"] = str(cols)
+    try:
+        steps = 5
+        specs = fourier_ensemble_specs(n_streams=3, steps=steps, seed0=2100)
+        _say(f"case column-block pass {cols} columns {precision} {[sp.dims for sp in specs]}")
+        from paper_2201_06958_amd import Batch
+        data = [[sp.snapshot_np(k) for k in range(steps + 1)] for sp in specs]
+        cfgs, orcs = [], []
+        for sp, d in zip(specs, data):
+            cfgs.append(dict(dims=sp.dims, dt=sp.dt, rank_max=sp.rank_max, weights=sp.weights, data_dtype="f32",
+                             precision=precision, adaptive=True, eps_th=sp.eps_th))
+            orcs.append(O.OracleTDB(O.OracleConfig(dims=sp.dims, weights=sp.weights, dt=sp.dt, rank_max=sp.rank_max,
+                                                   rank_init=None, adaptive=True, eps_th=sp.eps_th))
+                        .init(d[0].astype(np.float64)))
+        b = Batch(cfgs).init([_dev(d[0]) for d in data])
+    finally:
+        if old is None:
+            os.environ.pop("TDB_RPASS_COLS", None)
+        else:
+            os.environ["TDB_RPASS_COLS"] = old
+    pl = b.plan()
+    assert pl["pass"] == "matrix-core-columns" and pl["pass_cols"] == cols and pl["source"] == "rule", pl
+    bar = BAR[precision]
+    for k in range(1, steps + 1):
+        b.ingest([_dev(d[k]) for d in data])
+        for i, o in enumerate(orcs):
+            rec = o.ingest(data[i][k].astype(np.float64))
+            st = b.streams[i].stats()
+            assert st["event"] == rec.event, (k, i)
+            assert abs(st["eps"] - rec.eps) <= bar * rec.nu, (k, i)
+    for i, o in enumerate(orcs):
+        r, C, U = b.streams[i].get_core_and_bases()
+        rel = _rel(O.reconstruct(C, U), o.reconstruct())
+        rels = _sigma_rel(b.streams[i].stats()["sigma"], O.core_singular_values(o.C))
+        assert rel < bar and rels < bar, (i, rel, rels)
+    b.close()
+
+
+def test_batch_plan_tuned_then_cached():
+    """The batch's plan: timed at the first creation for a shape class (two or more stage-
+    pass candidates and both error passes timed), the same plan from the cache at the
+    second, the fixed rule with TDB_AUTOTUNE=0."""
+    specs = fourier_ensemble_specs(n_streams=4, steps=2, seed0=2200)
+    from paper_2201_06958_amd import Batch
+
+    def make():
+        cfgs = [dict(dims=sp.dims, dt=sp.dt, rank_max=sp.rank_max, weights=sp.weights, data_dtype="f32",
+                     precision="f32", adaptive=True, eps_th=sp.eps_th, snapshot_mode="borrow") for sp in specs]
+        return Batch(cfgs).init([sp.snapshot(0, device="cuda") for sp in specs])
+
+    _say("case batch plan tuner")
+    b1 = make()
+    p1 = b1.plan()
+    _say("  ", p1)
+    assert p1["source"] in ("timed", "cached"), p1
+    if p1["source"] == "timed":
+        assert sum(1 for x in p1["pass_us"] if x > 0) >= 2 and all(x > 0 for x in p1["err_us"]), p1
+    b1.close()
+    b2 = make()
+    p2 = b2.plan()
+    assert p2["source"] == "cached" and {k: p2[k] for k in ("pass", "pass_cols", "error_pass")} == \
+        {k: p1[k] for k in ("pass", "pass_cols", "error_pass")}, (p1, p2)
+    b2.close()
+    old = os.environ.get("TDB_AUTOTUNE")
+    os.environ["TDB_AUTOTUNE"] = "0"
+    try:
+        b3 = make()
+    finally:
+        if old is None:
+            os.environ.pop("TDB_AUTOTUNE", None)
+        else:
+            os.environ["TDB_AUTOTUNE"] = old
+    p3 = b3.plan()
+    assert p3["source"] == "rule" and p3["pass"] == "matrix-core-columns" and p3["pass_cols"] == 64, p3
+    b3.close()
