@@ -141,16 +141,28 @@ def rhs(C: np.ndarray, U: Sequence[np.ndarray], w: Sequence[np.ndarray], D: np.n
     return Cdot, Udot
 
 
-def heun_step(C, U, w, D, dt):
-    """Explicit second-order Runge-Kutta step (Heun / trapezoid) with the data
-    derivative D held over both stages."""
+def heun_step(C, U, w, D, dt, D2=None):
+    """Explicit second-order Runge-Kutta step (Heun / trapezoid): stage 1 at t_k with
+    the data derivative D, stage 2 at t_{k+1} with D2 (D held over both stages when
+    D2 is None)."""
     k1C, k1U = rhs(C, U, w, D)
     Cs = C + dt * k1C
     Us = [Un + dt * kU for Un, kU in zip(U, k1U)]
-    k2C, k2U = rhs(Cs, Us, w, D)
+    k2C, k2U = rhs(Cs, Us, w, D if D2 is None else D2)
     C1 = C + 0.5 * dt * (k1C + k2C)
     U1 = [Un + 0.5 * dt * (a + b) for Un, a, b in zip(U, k1U, k2U)]
     return C1, U1
+
+
+def fd2_stage_derivatives(V_m1, V_0, V_1, dt):
+    """Second-order finite differences of the data at the two Heun stage times from
+    the snapshots at t_{k-1}, t_k, t_{k+1} (Sec. 2.3 names first-order and central
+    differences; this reading takes the central difference at t_k for stage 1 and the
+    one-sided second-order difference at t_{k+1} for stage 2):
+        D(t_k)     ~ (V_1 - V_m1) / (2 dt)
+        D(t_{k+1}) ~ (3 V_1 - 4 V_0 + V_m1) / (2 dt)
+    Both are exact for data quadratic in t."""
+    return (V_1 - V_m1) / (2.0 * dt), (3.0 * V_1 - 4.0 * V_0 + V_m1) / (2.0 * dt)
 
 
 def euler_step(C, U, w, D, dt):
@@ -287,6 +299,7 @@ class OracleConfig:
     gamma_th: float = 0.0           # > 0: paper-style percentage budget
     slope_window: int = 10
     integrator: str = "heun"        # 'heun' or 'euler'
+    fd_order: int = 1               # 1: (V_{k+1} - V_k)/dt over both stages; 2: fd2_stage_derivatives
 
     def caps(self):
         """Rank caps clamped to the mode sizes and to the product of the other caps."""
@@ -418,6 +431,7 @@ class OracleTDB:
             r = rank_rule(h, self.caps, self.budget2(h.nu2), [1] * V0.ndim)
         self.C, self.U = h.truncate(r)
         self.V_prev = V0.copy()
+        self.V_prev2 = None
         self.t = t0
         self.k = 0
         eps0 = math.sqrt(h.truncation_error2(r))
@@ -431,6 +445,7 @@ class OracleTDB:
         self.C = np.array(C, dtype=np.float64)
         self.U = [np.array(u, dtype=np.float64) for u in U]
         self.V_prev = np.asarray(V0, dtype=np.float64).copy()
+        self.V_prev2 = None
         self.t = t0
         self.k = 0
         eps0, nu0 = error_and_norm(self.V_prev, self.C, self.U, self.w)
@@ -452,20 +467,29 @@ class OracleTDB:
     def ingest(self, V_new: np.ndarray, D: Optional[np.ndarray] = None, force: Optional[str] = None):
         """Advance the state from t_k to t_{k+1} with snapshot V_{k+1}.
 
-        D defaults to the first-order difference (V_{k+1} - V_k)/dt (Sec. 2.3).
+        D defaults to the first-order difference (V_{k+1} - V_k)/dt (Sec. 2.3), or with
+        fd_order 2 (from the second step on) to the stage derivatives of
+        fd2_stage_derivatives; a given D is held over both stages, a given pair
+        (D1, D2) gives the two stages' derivatives.
         `force` (replay mode) overrides the controller's decision with the one a
         device run took: '', 'add', 'reinit', 'remove'."""
         cfg = self.cfg
         V_new = np.asarray(V_new, dtype=np.float64)
         dt = cfg.dt
-        if D is None:
-            D = (V_new - self.V_prev) / dt
+        D2 = None
+        if isinstance(D, tuple):
+            D, D2 = D
+        elif D is None:
+            if cfg.fd_order == 2 and getattr(self, "V_prev2", None) is not None:
+                D, D2 = fd2_stage_derivatives(self.V_prev2, self.V_prev, V_new, dt)
+            else:
+                D = (V_new - self.V_prev) / dt
         numeric = False
         try:
             if cfg.integrator == "euler":
                 C1, U1 = euler_step(self.C, self.U, self.w, D, dt)
             else:
-                C1, U1 = heun_step(self.C, self.U, self.w, D, dt)
+                C1, U1 = heun_step(self.C, self.U, self.w, D, dt, D2)
             self.C, self.U = reorthonormalize(C1, U1, self.w)
         except NumericalEvent:
             numeric = True
@@ -479,6 +503,7 @@ class OracleTDB:
         rec.sigma = core_singular_values(self.C)
         rec.cr = compression_ratio(cfg.dims, rec.ranks)
         self.records.append(rec)
+        self.V_prev2 = self.V_prev
         self.V_prev = V_new.copy()
         return rec
 
