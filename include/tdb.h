@@ -95,6 +95,19 @@ typedef struct {
                                           explicit first-order Euler step (Sec. 2.4,
                                           the time-scheme comparison of Sec. 3.1);
                                           single streams only                          */
+  int32_t fd_order;                    /* data derivative (Sec. 2.3): 0 or 1, the first-
+                                          order quotient (V_{k+1} - V_k)/dt held over
+                                          both stages; 2, second-order differences from
+                                          V_{k-1}, V_k, V_{k+1}: the central difference
+                                          at t_k for the first stage, the one-sided
+                                          (3 V_{k+1} - 4 V_k + V_{k-1})/(2 dt) at t_{k+1}
+                                          for the second (the first step after init
+                                          takes the first-order quotient). 2 keeps two
+                                          earlier snapshots (TDB_COPY: two copies;
+                                          TDB_BORROW: the caller keeps the last two
+                                          snapshots intact), needs two more data-sized
+                                          buffers and steps synchronously; single
+                                          streams only                                 */
 } tdb_config;
 
 #define TDB_INT_HEUN 0

@@ -187,6 +187,35 @@ hipError_t launch_nonfinite_check(const T* x, long long n, int* flag, hipStream_
 template hipError_t launch_nonfinite_check<float>(const float*, long long, int*, hipStream_t);
 template hipError_t launch_nonfinite_check<double>(const double*, long long, int*, hipStream_t);
 
+// The two stage derivatives of the second-order difference (Sec. 2.3): D1 at t_k by
+// the central difference and D2 at t_{k+1} by the one-sided second-order difference,
+// from the snapshots at t_{k-1} (Vm), t_k (V0) and t_{k+1} (V1). Formed in FP64 and
+// stored in the data type; c = 1 / (2 dt). A grid-stride loop, one element per
+// thread per pass (the loads of the three snapshots are coalesced).
+template <typename T>
+__global__ void __launch_bounds__(256) k_fd2(const T* __restrict__ Vm, const T* __restrict__ V0,
+                                             const T* __restrict__ V1, T* __restrict__ D1, T* __restrict__ D2,
+                                             long long n, double c) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const double a = (double)Vm[i], b = (double)V0[i], x = (double)V1[i];
+    D1[i] = (T)((x - a) * c);
+    D2[i] = (T)((3.0 * x - 4.0 * b + a) * c);
+  }
+}
+
+template <typename T>
+hipError_t launch_fd2(const T* Vm, const T* V0, const T* V1, T* D1, T* D2, long long n, double dt, hipStream_t s) {
+  long long blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL((k_fd2<T>), dim3((unsigned)blocks), dim3(256), 0, s, Vm, V0, V1, D1, D2, n, 0.5 / dt);
+  return hipGetLastError();
+}
+template hipError_t launch_fd2<float>(const float*, const float*, const float*, float*, float*, long long, double,
+                                      hipStream_t);
+template hipError_t launch_fd2<double>(const double*, const double*, const double*, double*, double*, long long,
+                                       double, hipStream_t);
+
 template <typename TI, typename TO>
 __global__ void k_convert(const TI* __restrict__ in, TO* __restrict__ out, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;

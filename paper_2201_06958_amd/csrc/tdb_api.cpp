@@ -74,6 +74,11 @@ struct tdb_ctx {
   // snapshots
   const void* Vprev = nullptr;
   void* Vcopy = nullptr;
+  // second-order differences: the snapshot before Vprev (NULL until two are held), the
+  // second copy buffer (TDB_COPY) and the two stage derivatives
+  const void* Vprev2 = nullptr;
+  void* Vcopy2 = nullptr;
+  void* Dfd[2] = {nullptr, nullptr};
   // bookkeeping
   std::string err;
   tdb_stats stats{};
@@ -219,6 +224,7 @@ tdb_status validate(const tdb_config* c, std::string& msg) {
     return TDB_EINVAL;
   }
   if (c->integrator != TDB_INT_HEUN && c->integrator != TDB_INT_EULER) { msg = "bad integrator"; return TDB_EINVAL; }
+  if (c->fd_order < 0 || c->fd_order > 2) { msg = "fd_order must be 0, 1 or 2"; return TDB_EINVAL; }
   return TDB_OK;
 }
 
@@ -453,7 +459,8 @@ tdb_status setup(tdb_ctx* h, const tdb_config* cfg) {
   h->ctrl_h = h->ctrl_hb[0];
   {
     const char* env = std::getenv("TDB_PIPELINE");
-    h->pipelined = cfg->snapshot_mode == TDB_BORROW && !(env && env[0] == '0');
+    // second-order differences read three snapshots and step synchronously
+    h->pipelined = cfg->snapshot_mode == TDB_BORROW && cfg->fd_order != 2 && !(env && env[0] == '0');
   }
   // ---- HOSVD buffers
   size_t gpart = 0;
@@ -481,6 +488,11 @@ tdb_status setup(tdb_ctx* h, const tdb_config* cfg) {
     TRY(dallocT(h, &h->eig_vec, (size_t)TDB_P * TDB_NEIG * 64 * 6));
   }
   if (cfg->snapshot_mode == TDB_COPY) TRY(dalloc(h, &h->Vcopy, (size_t)h->S * h->delt));
+  if (cfg->fd_order == 2) {
+    if (cfg->snapshot_mode == TDB_COPY) TRY(dalloc(h, &h->Vcopy2, (size_t)h->S * h->delt));
+    TRY(dalloc(h, &h->Dfd[0], (size_t)h->S * h->delt));
+    TRY(dalloc(h, &h->Dfd[1], (size_t)h->S * h->delt));
+  }
 
   // ---- weights and their mode-wise products
   std::vector<std::vector<double>> wh(h->p);
@@ -881,11 +893,16 @@ struct PassTimer {
   }
 };
 
+// V becomes the previous snapshot; with second-order differences the previous one
+// becomes the one before (TDB_COPY alternates between two copy buffers).
 template <typename TD>
 tdb_status keep_previous(tdb_ctx* h, const TD* V, hipStream_t s) {
+  const bool two = h->cfg.fd_order == 2;
+  if (two) h->Vprev2 = h->Vprev;
   if (h->cfg.snapshot_mode == TDB_COPY) {
-    HIPCHK(hipMemcpyAsync(h->Vcopy, V, (size_t)h->S * sizeof(TD), hipMemcpyDeviceToDevice, s));
-    h->Vprev = h->Vcopy;
+    void* dst = two && h->Vprev == h->Vcopy ? h->Vcopy2 : h->Vcopy;
+    HIPCHK(hipMemcpyAsync(dst, V, (size_t)h->S * sizeof(TD), hipMemcpyDeviceToDevice, s));
+    h->Vprev = dst;
   } else {
     h->Vprev = V;
   }
@@ -922,9 +939,10 @@ tdb_status discard_step(tdb_ctx* h, const TD* V1, hipStream_t s) {
 
 tdb_status euler_commit(tdb_ctx* h, hipStream_t s);
 
-// D (may be NULL): a given data derivative in place of (V1 - V_prev)/dt.
+// D (may be NULL): a given data derivative in place of (V1 - V_prev)/dt; D2 (may be
+// NULL): the second stage's derivative when it differs from D.
 template <typename TD, typename T>
-tdb_status ingest_impl(tdb_ctx* h, const TD* V1, hipStream_t s, const TD* D = nullptr) {
+tdb_status ingest_impl(tdb_ctx* h, const TD* V1, hipStream_t s, const TD* D = nullptr, const TD* D2 = nullptr) {
   h->prof_now = h->prof_every <= 1 || h->prof_steps++ % h->prof_every == 0;
   // the projected operand: V1 - V_prev (scaled by 1/dt), or D itself
   const TD* Vp = D ? D : V1;
@@ -964,7 +982,7 @@ tdb_status ingest_impl(tdb_ctx* h, const TD* V1, hipStream_t s, const TD* D = nu
     TRY(stage_prep<T>(h, h->Cs, h->Us, s));
     {
       PassTimer pt(h, TDB_PASS_PROJECT, s);
-      TRY((project_plain<TD, T>(h, Vp, V0, s)));
+      TRY((project_plain<TD, T>(h, D2 ? D2 : Vp, V0, s)));
     }
     ra.stage = 2;
     HIPCHK(launch_rhs_stage(ra, h->ctrl, s));
@@ -1107,9 +1125,10 @@ tdb_status build_post_args(tdb_ctx* h, const int* rl, FPostArgs& pa, size_t& lds
 
 // Returns TDB_EUNSUPPORTED when the stage pass does not fit (the caller may fall back
 // to the plain path).
-// D (may be NULL): a given data derivative, projected in place of (V1 - V0)/dt.
+// D (may be NULL): a given data derivative, projected in place of (V1 - V0)/dt; D2
+// (may be NULL, only with D): the second stage's derivative.
 tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void* V0, StepArgs& A,
-                           const void* D = nullptr) {
+                           const void* D = nullptr, const void* D2 = nullptr) {
   const PassPlan base = plan_pass(h, rl, rl != h->r);
   if (!base.ok) { h->err = "stage-pass tile does not fit in LDS"; return TDB_EUNSUPPORTED; }
   const PassPlan pl = rl == h->r ? base : plan_under(h, h->r, base);
@@ -1138,6 +1157,7 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
   A.fa[0].P1 = h->P[0]; A.fa[0].P2 = h->P[1]; A.fa[0].P3 = h->P[2];
   A.fa[1] = fa;
   A.fa[1].P1 = h->P2[0]; A.fa[1].P2 = h->P2[1]; A.fa[1].P3 = h->P2[2];
+  if (D && D2) A.fa[1].V1 = D2;
 
   FReduceArgs& ra = A.ra;
   ra = FReduceArgs{};
@@ -1436,9 +1456,9 @@ tdb_status resolve_pending(tdb_ctx* h) {
 }
 
 // D (may be NULL): a given data derivative; such a step runs synchronously (D is read
-// by this call only).
+// by this call only). D2 (may be NULL): the second stage's derivative.
 template <typename TD, typename T>
-tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s, const TD* D = nullptr) {
+tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s, const TD* D = nullptr, const TD* D2 = nullptr) {
   if (D) TRY(resolve_pending(h));
   // work enqueued earlier on another stream comes first
   if (h->pending && h->pend_stream != s) {
@@ -1446,14 +1466,14 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s, const TD* D = n
     HIPCHK(hipStreamWaitEvent(s, h->ev_ctrl[h->mirror], 0));
   }
   StepArgs A;
-  tdb_status bs = build_step_args(h, h->r, V1, h->Vprev, A, D);
+  tdb_status bs = build_step_args(h, h->r, V1, h->Vprev, A, D, D2);
   if (bs == TDB_EUNSUPPORTED) {
     TRY(resolve_pending(h));
-    bs = build_step_args(h, h->r, V1, h->Vprev, A, D);   // the ranks may have changed
+    bs = build_step_args(h, h->r, V1, h->Vprev, A, D, D2);   // the ranks may have changed
   }
   if (bs == TDB_EUNSUPPORTED) {
     h->post_valid = false;
-    return ingest_impl<TD, T>(h, V1, s, D);
+    return ingest_impl<TD, T>(h, V1, s, D, D2);
   }
   TRY(bs);
   h->fused_steps += 1;
@@ -1509,16 +1529,29 @@ tdb_status ingest_fused(tdb_ctx* h, const TD* V1, hipStream_t s, const TD* D = n
   return prev;
 }
 
+// With second-order differences and two earlier snapshots held, the step's two stage
+// derivatives are formed first (Sec. 2.3) and projected as given derivatives; the
+// first step after init takes the first-order quotient.
 template <typename TD>
 tdb_status ingest_dispatch(tdb_ctx* h, const void* V, hipStream_t s, const void* D = nullptr) {
   const TD* Vt = static_cast<const TD*>(V);
   const TD* Dt = static_cast<const TD*>(D);
-  if (h->fused) {
-    if (h->f32) return ingest_fused<TD, float>(h, Vt, s, Dt);
-    return ingest_fused<TD, double>(h, Vt, s, Dt);
+  const TD* D2t = nullptr;
+  if (!D && h->cfg.fd_order == 2 && h->Vprev2) {
+    TRY(resolve_pending(h));
+    TD* d1 = static_cast<TD*>(h->Dfd[0]);
+    TD* d2 = static_cast<TD*>(h->Dfd[1]);
+    HIPCHK(launch_fd2<TD>(static_cast<const TD*>(h->Vprev2), static_cast<const TD*>(h->Vprev), Vt, d1, d2, h->S,
+                          h->cfg.dt, s));
+    Dt = d1;
+    D2t = d2;
   }
-  if (h->f32) return ingest_impl<TD, float>(h, Vt, s, Dt);
-  return ingest_impl<TD, double>(h, Vt, s, Dt);
+  if (h->fused) {
+    if (h->f32) return ingest_fused<TD, float>(h, Vt, s, Dt, D2t);
+    return ingest_fused<TD, double>(h, Vt, s, Dt, D2t);
+  }
+  if (h->f32) return ingest_impl<TD, float>(h, Vt, s, Dt, D2t);
+  return ingest_impl<TD, double>(h, Vt, s, Dt, D2t);
 }
 
 template <typename TD>
@@ -2662,6 +2695,10 @@ tdb_status tdb_batch_create(int32_t n, const tdb_config* cfgs, const void* const
       }
       if (c.integrator != TDB_INT_HEUN) {
         b->err = "stream " + std::to_string(i) + ": batches step with the Heun integrator only";
+        return TDB_EUNSUPPORTED;
+      }
+      if (c.fd_order == 2) {
+        b->err = "stream " + std::to_string(i) + ": batches take the first-order difference quotient only";
         return TDB_EUNSUPPORTED;
       }
       if ((c.data_dtype == TDB_F32) != b->data32 || c.precision != cfgs[0].precision) {

@@ -83,6 +83,10 @@ hipError_t launch_err_final(const double* partials, int nblocks, CtrlState* ctrl
 // or infinite.
 template <typename T>
 hipError_t launch_nonfinite_check(const T* x, long long n, int* flag, hipStream_t s);
+// Second-order stage derivatives from three consecutive snapshots (n values each):
+// D1 = (V1 - Vm) / (2 dt) at t_k, D2 = (3 V1 - 4 V0 + Vm) / (2 dt) at t_{k+1}.
+template <typename T>
+hipError_t launch_fd2(const T* Vm, const T* V0, const T* V1, T* D1, T* D2, long long n, double dt, hipStream_t s);
 // Elementwise conversions.
 template <typename TI, typename TO>
 hipError_t launch_convert(const TI* in, TO* out, long long n, hipStream_t s);

@@ -54,6 +54,7 @@ class TdbConfig(ctypes.Structure):
         ("gamma_th", ctypes.c_double),
         ("slope_window", ctypes.c_int32),
         ("integrator", ctypes.c_int32),
+        ("fd_order", ctypes.c_int32),
     ]
 
 
@@ -207,7 +208,7 @@ class Compressor:
                  weights: Optional[Sequence[np.ndarray]] = None, data_dtype: str = "f32",
                  precision: str = "f32", path: str = "auto", adaptive: bool = True,
                  snapshot_mode: str = "copy", eps_th: float = 1e-4, gamma_th: float = 0.0,
-                 slope_window: int = 0, integrator: str = "heun"):
+                 slope_window: int = 0, integrator: str = "heun", fd_order: int = 1):
         self.lib = load_library()
         p = len(dims)
         self.dims = tuple(int(d) for d in dims)
@@ -234,6 +235,7 @@ class Compressor:
         cfg.gamma_th = float(gamma_th)
         cfg.slope_window = int(slope_window)
         cfg.integrator = {"heun": INT_HEUN, "euler": INT_EULER}[integrator]
+        cfg.fd_order = int(fd_order)
         self.cfg = cfg
         self.h = ctypes.c_void_p()
 

@@ -38,6 +38,7 @@ def test_struct_layout_matches_binding():
 @pytest.mark.parametrize("field,value,code", [
     ("order", 1, 1), ("order", 9, 1), ("order", 5, 6), ("dt", 0.0, 1), ("data_dtype", 7, 1),
     ("precision", 9, 1), ("slope_window", 1, 1), ("snapshot_mode", 5, 1), ("integrator", 2, 1),
+    ("fd_order", 3, 1), ("fd_order", -1, 1),
 ])
 def test_invalid_config_is_rejected_before_any_device_work(field, value, code):
     from paper_2201_06958_amd import tdb
