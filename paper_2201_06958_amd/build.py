@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtdb.so")
 OBJDIR = os.path.join(ROOT, "_build")
-SOURCES = ["small_ops.hip", "stream_ops.hip", "hosvd_ops.hip", "eig_ops.hip", "fused_ops.hip", "fused_pass.hip", "mfma_pass.hip", "gate_ops.hip",
+SOURCES = ["small_ops.hip", "stream_ops.hip", "dbo_ops.hip", "hosvd_ops.hip", "eig_ops.hip", "fused_ops.hip", "fused_pass.hip", "mfma_pass.hip", "gate_ops.hip",
            "noalloc_ops.hip", "rpass.hip",
            "tdb_api.cpp"]
 ARCH = "gfx950"

@@ -6,6 +6,7 @@
 #include "fused.h"
 #include "gate.h"
 #include "noalloc.h"
+#include "dbo.h"
 
 #include <hip/hip_runtime.h>
 
@@ -46,6 +47,13 @@ struct tdb_ctx {
   bool f32 = false;          // bulk passes in FP32 (or BF16-split products with FP32 sums)
   bool bf16s = false;        // BF16-split products in the matrix-core stage pass
   bool no_mfma = false;      // keep the generic stage pass (a batch with mixed shapes)
+  bool dbo = false;          // order 2 on the row passes (tall first mode, short second)
+  bool tall = false;         // the first mode exceeds the eigensolver's size: its HOSVD
+                             // basis comes from the second mode's eigenvectors
+  double* dbo_wk = nullptr;  // small FP64 work area of the row passes
+  void* dbo_bt = nullptr;    // W2 U2 of both stages in the compute type
+  double* dbo_part = nullptr;
+  int dbo_nblk = 1;
   bool no_rpass = false;     // keep the tile pass in a batch (streams that disagree)
   bool ferr_cols = false;    // batch member on the column-block error pass
   int rpass_cols = 64;       // columns of mode 2 per workgroup of the column-block pass
@@ -196,7 +204,13 @@ tdb_status validate(const tdb_config* c, std::string& msg) {
       msg = "rank_max above 64 is not supported by the library";
       return TDB_EUNSUPPORTED;
     }
-    if (c->dims[n] > TDB_NEIG) { msg = "mode sizes above 512 are not supported by the library"; return TDB_EUNSUPPORTED; }
+    if (c->dims[n] > TDB_NEIG && !(n == 0 && c->order == 2 && c->path != TDB_PATH_PLAIN && c->dims[1] <= DBO_KMAX)) {
+      msg = c->order == 2 && n == 1 && c->dims[0] <= DBO_KMAX
+                ? "an order-2 stream takes its tall mode first (V is N1 x N2 with N2 <= 32 unit-stride)"
+                : "mode sizes above 512 are supported only for the first mode of an order-2 stream whose second "
+                  "mode has at most 32 entries";
+      return TDB_EUNSUPPORTED;
+    }
     if (c->rank_init[n] < 0) { msg = "rank_init must be >= 0"; return TDB_EINVAL; }
     if (c->weights[n]) {
       for (long long i = 0; i < c->dims[n]; ++i)
@@ -419,6 +433,10 @@ tdb_status setup(tdb_ctx* h, const tdb_config* cfg) {
   h->core_cap = prod_ll(h->caps, h->p);
   h->Rmax = 1;
   for (int n = 0; n < h->p; ++n) h->Rmax = std::max(h->Rmax, prod_ll(h->caps, h->p, n));
+  // order 2 with a short second mode steps on the row passes; a first mode beyond the
+  // eigensolver's size takes its HOSVD basis from the second mode's eigenvectors
+  h->dbo = h->p == 2 && cfg->path != TDB_PATH_PLAIN && h->N[1] <= DBO_KMAX && h->N[0] >= h->N[1];
+  h->tall = h->dbo && h->N[0] > TDB_NEIG;
 
   // ---- state and stage buffers
   TRY(dallocT(h, &h->C0, h->core_cap));
@@ -460,15 +478,16 @@ tdb_status setup(tdb_ctx* h, const tdb_config* cfg) {
   {
     const char* env = std::getenv("TDB_PIPELINE");
     // second-order differences read three snapshots and step synchronously
-    h->pipelined = cfg->snapshot_mode == TDB_BORROW && cfg->fd_order != 2 && !(env && env[0] == '0');
+    h->pipelined = cfg->snapshot_mode == TDB_BORROW && cfg->fd_order != 2 && !h->dbo && !(env && env[0] == '0');
   }
   // ---- HOSVD buffers
   size_t gpart = 0;
   for (int n = 0; n < h->p; ++n) {
-    TRY(dallocT(h, &h->G[n], (size_t)h->N[n] * h->N[n]));
-    TRY(dallocT(h, &h->eigw[n], (size_t)h->N[n] * (h->caps[n] + 7)));
     TRY(dallocT(h, &h->sig[n], (size_t)h->caps[n] + 1));
     TRY(dallocT(h, &h->Umax[n], (size_t)h->N[n] * h->ldU[n]));
+    if (h->tall && n == 0) continue;   // no Gram of the tall mode (see hosvd_select)
+    TRY(dallocT(h, &h->G[n], (size_t)h->N[n] * h->N[n]));
+    TRY(dallocT(h, &h->eigw[n], (size_t)h->N[n] * (h->caps[n] + 7)));
     TRY(dallocT(h, &h->Bmax[n], (size_t)h->N[n] * h->caps[n]));
     const long long nt = (h->N[n] + 63) / 64;
     const long long K = h->S / h->N[n];
@@ -539,6 +558,13 @@ tdb_status setup(tdb_ctx* h, const tdb_config* cfg) {
   *h->ctrl_h = c;
   HIPCHK(hipMemcpy(h->ctrl, h->ctrl_h, sizeof(CtrlState), hipMemcpyHostToDevice));
   TRY(setup_fused(h, wh));
+  if (h->dbo) {
+    const int tr = dbo_rows(dbo_bucket((int)h->N[1]));
+    h->dbo_nblk = (int)std::max<long long>(1, std::min<long long>(DBO_GRID, (h->N[0] + tr - 1) / tr));
+    TRY(dallocT(h, &h->dbo_wk, (size_t)DBO_WK_SIZE));
+    TRY(dalloc(h, &h->dbo_bt, (size_t)2 * DBO_KMAX * DBO_RMAX * h->celt));
+    TRY(dallocT(h, &h->dbo_part, (size_t)h->dbo_nblk * dbo_slot_max((int)h->N[1])));
+  }
   return TDB_OK;
 }
 
@@ -721,9 +747,106 @@ tdb_status core_sigma(tdb_ctx* h, bool with_vectors, hipStream_t s) {
   return TDB_OK;
 }
 
+DboArgs dbo_args(tdb_ctx* h) {
+  DboArgs a{};
+  a.M = h->N[0];
+  a.K = (int)h->N[1];
+  a.r = h->r[0];
+  a.ldU1 = h->ldU[0];
+  a.ldU2 = h->ldU[1];
+  a.full2 = h->r[1] >= h->N[1] ? 1 : 0;
+  a.euler = h->cfg.integrator == TDB_INT_EULER ? 1 : 0;
+  a.TR = dbo_rows(dbo_bucket(a.K));
+  a.nblk = h->dbo_nblk;
+  a.caps = h->caps[0];
+  a.dt = h->cfg.dt;
+  a.dscale = 1.0 / h->cfg.dt;
+  a.U1 = h->U0[0];
+  a.kU1 = h->kU[0];
+  a.w1 = h->w[0];
+  a.w2 = h->w[1];
+  a.part = h->dbo_part;
+  a.wk = h->dbo_wk;
+  a.Bt = h->dbo_bt;
+  a.C0 = h->C0;
+  a.U2 = h->U0[1];
+  a.kU2 = h->kU[1];
+  a.Us2 = h->Us[1];
+  a.Cs = h->Cs;
+  a.kC = h->kC;
+  return a;
+}
+
+// HOSVD of an order-2 stream whose first mode is tall: the second mode's weighted Gram
+// and eigenvectors Umax2 give the first mode's basis as the left singular vectors of
+// the weighted unfolding, Umax1 = V (W2 Umax2) Sigma^-1, each column sign-fixed like
+// an eigenvector (largest entry of W1^(1/2) Umax1 positive, lowest row on a tie); the
+// core at the caps is diag(sign * sigma) (Sec. 2.3).
+template <typename TD>
+tdb_status hosvd_tall(tdb_ctx* h, const TD* V, int mode, hipStream_t s) {
+  HIPCHK(hipMemsetAsync(&h->ctrl->hold, 0, sizeof(int), s));
+  HosvdModeArgs m{};
+  m.n = 1;
+  m.A = h->N[0];
+  m.Bsz = 1;
+  m.Nn = h->N[1];
+  m.wa = h->wa[1];
+  m.wb = h->wb[1];
+  m.wn = h->w[1];
+  const long long K = m.A;
+  const int nch = (int)gram_chunks(K);
+  long long kchunk = (K + nch - 1) / nch;
+  kchunk = (kchunk + 15) / 16 * 16;
+  HIPCHK(launch_gram_partials<TD>(V, m, h->gpart, kchunk, nch, s));
+  HIPCHK(launch_gram_reduce(h->gpart, h->G[1], m, nch, s));
+  EigBatch eb{};
+  eb.count = 1;
+  EigArgs& e = eb.m[0];
+  e.Nn = (int)h->N[1];
+  e.k = h->caps[1];
+  e.ldu = h->ldU[1];
+  e.G = h->G[1];
+  e.work = h->eigw[1];
+  e.sig = h->sig[1];
+  e.Umax = h->Umax[1];
+  e.Bmax = h->Bmax[1];
+  e.wn = h->w[1];
+  HIPCHK(launch_trace(h->G[1], h->N[1], h->nu2h, s));
+  HIPCHK(launch_sym_eig(eb, h->eig_lam, h->eig_vec, s));
+  DboArgs a = dbo_args(h);
+  a.V1 = V;
+  a.r = 1;
+  a.Umax1 = h->Umax[0];
+  a.sig2 = h->sig[1];
+  a.Bmax2 = h->Bmax[1];
+  a.sig1 = h->sig[0];
+  a.Cmax = h->Cmax;
+  HIPCHK((launch_dbo_rows<TD, double>(a, DBO_MAP, h->ctrl, s)));
+  HIPCHK(launch_dbo_small<double>(a, DBO_SIGN, h->ctrl, s));
+  HIPCHK((launch_dbo_rows<TD, double>(a, DBO_FLIP, h->ctrl, s)));
+  SelectArgs sa{};
+  sa.p = 2;
+  sa.mode = mode;
+  sa.Cmax = h->Cmax;
+  sa.nu2h = h->nu2h;
+  sa.C0 = h->C0;
+  for (int n = 0; n < 2; ++n) {
+    sa.caps[n] = h->caps[n];
+    sa.N[n] = h->N[n];
+    sa.ldU[n] = h->ldU[n];
+    sa.rank_init[n] = h->cfg.rank_init[n];
+    sa.sig[n] = h->sig[n];
+    sa.Umax[n] = h->Umax[n];
+    sa.U0[n] = h->U0[n];
+  }
+  HIPCHK(launch_rank_select(sa, h->ctrl, s));
+  return TDB_OK;
+}
+
 // Weighted HOSVD of V at the caps (Sec. 2.3) followed by the rank selection `mode`.
 template <typename TD>
 tdb_status hosvd_select(tdb_ctx* h, const TD* V, int mode, hipStream_t s) {
+  if (h->tall) return hosvd_tall<TD>(h, V, mode, s);
   const int p = h->p;
   // the decision is being acted on: release the steps held behind it
   HIPCHK(hipMemsetAsync(&h->ctrl->hold, 0, sizeof(int), s));
@@ -1023,6 +1146,63 @@ tdb_status ingest_impl(tdb_ctx* h, const TD* V1, hipStream_t s, const TD* D = nu
   // the host copy holds this step's singular values only after a reinit (pulled in
   // full) or when a single stream formed them and pulled the controller state
   h->sigma_stale = !(dec != DEC_NONE || (h->sigma_every_step && !h->batch_owned));
+  fill_stats(h, false);
+  return TDB_OK;
+}
+
+// One step of an order-2 stream on the row passes (Sec. 2.2 with p = 2; Heun or
+// Euler, Sec. 2.4): stage preparation, the stage-1 sums, the stage-1 finish fused with
+// the stage-2 sums, the stage-2 finish with the new basis' Gram and the error sums,
+// the small kernels between them, and U1 <- U1 L^-T of the Cholesky QR. D, D2: given
+// stage derivatives (or NULL for the difference of snapshots).
+template <typename TD, typename T>
+tdb_status ingest_dbo(tdb_ctx* h, const TD* V1, hipStream_t s, const TD* D = nullptr, const TD* D2 = nullptr) {
+  h->prof_now = h->prof_every <= 1 || h->prof_steps++ % h->prof_every == 0;
+  DboArgs a = dbo_args(h);
+  a.V1 = V1;
+  a.V0 = D ? nullptr : h->Vprev;
+  a.D1 = D;
+  a.D2 = D ? D2 : nullptr;
+  a.dscale = D ? 1.0 : 1.0 / h->cfg.dt;
+  CtrlState* c = h->ctrl;
+  HIPCHK(launch_dbo_small<T>(a, DBO_PREP, c, s));
+  {
+    PassTimer pt(h, TDB_PASS_PROJECT, s);
+    HIPCHK((launch_dbo_rows<TD, T>(a, DBO_PASS1, c, s)));
+  }
+  HIPCHK(launch_dbo_small<T>(a, DBO_MID1, c, s));
+  if (a.euler) {
+    PassTimer pt(h, TDB_PASS_ERROR, s);
+    HIPCHK((launch_dbo_rows<TD, T>(a, DBO_FINE, c, s)));
+  } else {
+    {
+      PassTimer pt(h, TDB_PASS_PROJECT, s);
+      HIPCHK((launch_dbo_rows<TD, T>(a, DBO_FIN1, c, s)));
+    }
+    HIPCHK(launch_dbo_small<T>(a, DBO_MID2, c, s));
+    PassTimer pt(h, TDB_PASS_ERROR, s);
+    HIPCHK((launch_dbo_rows<TD, T>(a, DBO_FIN2, c, s)));
+  }
+  HIPCHK(launch_dbo_small<T>(a, DBO_END, c, s));
+  HIPCHK((launch_dbo_rows<TD, T>(a, DBO_NORM, c, s)));
+  TRY(core_sigma(h, false, s));
+  HIPCHK(launch_controller(c, s));
+  TRY(pull_ctrl(h, s));
+  h->last_path = TDB_PATH_FUSED;
+  h->last_prec = h->f32 ? TDB_PREC_F32 : TDB_PREC_F64;
+  h->fused_steps += 1;
+  const int dec = h->ctrl_h->decision;
+  if (dec == DEC_NONFINITE) return discard_step<TD>(h, V1, s);
+  h->step += 1;
+  h->t_now = h->step * h->cfg.dt;
+  if (dec != DEC_NONE) {
+    TRY(hosvd_select<TD>(h, V1, dec, s));
+    TRY(pull_ctrl(h, s));
+    TRY(core_sigma(h, false, s));
+    TRY(pull_ctrl(h, s));
+  }
+  TRY(keep_previous<TD>(h, V1, s));
+  h->sigma_stale = !(dec != DEC_NONE || h->sigma_every_step);
   fill_stats(h, false);
   return TDB_OK;
 }
@@ -1545,6 +1725,10 @@ tdb_status ingest_dispatch(tdb_ctx* h, const void* V, hipStream_t s, const void*
                           h->cfg.dt, s));
     Dt = d1;
     D2t = d2;
+  }
+  if (h->dbo) {
+    if (h->f32) return ingest_dbo<TD, float>(h, Vt, s, Dt, D2t);
+    return ingest_dbo<TD, double>(h, Vt, s, Dt, D2t);
   }
   if (h->fused) {
     if (h->f32) return ingest_fused<TD, float>(h, Vt, s, Dt, D2t);
