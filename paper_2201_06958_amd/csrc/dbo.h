@@ -17,7 +17,7 @@ namespace tdb {
 
 #define DBO_KMAX 32     // largest short mode
 #define DBO_RMAX 32     // largest rank
-#define DBO_GRID 256    // row blocks; each walks chunks of rows
+#define DBO_GRID 512    // row blocks; each walks chunks of rows
 
 // Row-kernel phases.
 enum {
@@ -78,8 +78,8 @@ struct DboArgs {
 
 // Row bucket: the short mode rounded up to 8, 16 or 32.
 __host__ __device__ inline int dbo_bucket(int K) { return K <= 8 ? 8 : (K <= 16 ? 16 : 32); }
-// Rows per chunk for a bucket (the chunk's rows of X and Y sit in LDS).
-__host__ __device__ inline int dbo_rows(int nb) { return nb <= 16 ? 256 : 128; }
+// Rows per chunk for a bucket (each row's vectors sit in LDS: 74, 79 and 108 KB).
+__host__ __device__ inline int dbo_rows(int nb) { return nb <= 8 ? 256 : (nb <= 16 ? 128 : 64); }
 // Doubles of one partial-sum slot for a phase.
 __host__ __device__ inline int dbo_slot(int phase, int r, int K) {
   if (phase == DBO_PASS1 || phase == DBO_FIN1) return r * (r + K);

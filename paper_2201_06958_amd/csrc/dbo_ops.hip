@@ -17,57 +17,60 @@ namespace tdb {
 size_t dbo_lds_bytes(int nb) {
   const int TR = dbo_rows(nb);
   const size_t small = 5 * (size_t)nb * nb;   // two W2 U2, P1, M1 and E (or L^-1)
-  return (small + (size_t)TR * ((nb + 1) + (2 * nb + 1))) * sizeof(double);
+  return (small + (size_t)TR * (2 * (nb + 1) + (2 * nb + 1))) * sizeof(double);
 }
 
 // ---------------------------------------------------------------- row passes
-template <typename TD, typename T, int NB>
-__device__ __forceinline__ void dbo_load_d(const DboArgs& a, const void* D, long long i, T (&d)[NB]) {
+template <int NB>
+__device__ __forceinline__ void dbo_load_u(const double* U, long long i, int ld, int r, double (&u)[NB]) {
+#pragma unroll
+  for (int q = 0; q < NB; ++q) u[q] = q < r ? U[i * ld + q] : 0.0;
+}
+
+// The row's stage derivative into LDS (doubles): D's row, or V1 - V0.
+template <typename TD, int NB>
+__device__ __forceinline__ void dbo_stage_d(const DboArgs& a, const void* D, long long i, double* out) {
   const int K = a.K;
   if (D) {
     const TD* p = static_cast<const TD*>(D) + i * K;
-#pragma unroll
-    for (int j = 0; j < NB; ++j) d[j] = j < K ? (T)p[j] : (T)0;
+    for (int j = 0; j < K; ++j) out[j] = (double)p[j];
   } else {
     const TD* p1 = static_cast<const TD*>(a.V1) + i * K;
     const TD* p0 = static_cast<const TD*>(a.V0) + i * K;
-#pragma unroll
-    for (int j = 0; j < NB; ++j) d[j] = j < K ? (T)p1[j] - (T)p0[j] : (T)0;
+    for (int j = 0; j < K; ++j) out[j] = (double)p1[j] - (double)p0[j];
   }
 }
 
-// f = d B (B is K x r in LDS, row stride NB, zero-padded)
+template <int NB>
+__device__ __forceinline__ void dbo_stage_u(const double* U, long long i, int ld, int r, double* out) {
+  for (int q = 0; q < r; ++q) out[q] = U[i * ld + q];
+}
+
+// f = d B: d (K entries) in LDS, B (K x r, stride NB, zero-padded) in LDS.
 template <typename T, int NB>
-__device__ __forceinline__ void dbo_dB(const T (&d)[NB], const T* B, T (&f)[NB]) {
+__device__ __forceinline__ void dbo_dB_lds(const double* d, int K, const T* B, T (&f)[NB]) {
 #pragma unroll
   for (int q = 0; q < NB; ++q) f[q] = (T)0;
+  for (int j = 0; j < K; ++j) {
+    const T dj = (T)d[j];
 #pragma unroll
-  for (int j = 0; j < NB; ++j) {
-#pragma unroll
-    for (int q = 0; q < NB; ++q) f[q] += d[j] * B[j * NB + q];
+    for (int q = 0; q < NB; ++q) f[q] += dj * B[j * NB + q];
   }
 }
 
-// y = (f P - u M) * s  (P, M r x r in LDS, stride NB, zero-padded)
-template <typename T, int NB>
-__device__ __forceinline__ void dbo_rhs(const T (&f)[NB], const double (&u)[NB], const double* P, const double* Mm,
-                                        double s, double (&y)[NB]) {
+// y = (f P - u M) * s: f and u (r entries) in LDS, P and M (stride NB, zero-padded).
+template <int NB>
+__device__ __forceinline__ void dbo_rhs_lds(const double* f, const double* u, int r, const double* P,
+                                            const double* Mm, double s, double (&y)[NB]) {
 #pragma unroll
   for (int q = 0; q < NB; ++q) y[q] = 0.0;
-#pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    const double fc = (double)f[c], uc = u[c];
+  for (int c = 0; c < r; ++c) {
+    const double fc = f[c], uc = u[c];
 #pragma unroll
     for (int q = 0; q < NB; ++q) y[q] += fc * P[c * NB + q] - uc * Mm[c * NB + q];
   }
 #pragma unroll
   for (int q = 0; q < NB; ++q) y[q] *= s;
-}
-
-template <int NB>
-__device__ __forceinline__ void dbo_load_u(const double* U, long long i, int ld, int r, double (&u)[NB]) {
-#pragma unroll
-  for (int q = 0; q < NB; ++q) u[q] = q < r ? U[i * ld + q] : 0.0;
 }
 
 // Registers are bounded by the occupancy each bucket can reach (the compiler would
@@ -86,6 +89,7 @@ k_dbo_rows(DboArgs a, CtrlState* ctrl) {
   T* sB1 = sB0 + NB * NB;                         // the same, stage 2
   double* X = lds + 5 * NB * NB;     // TR x XS (the W2 U2 pair takes at most 2 NB^2 doubles)
   double* Y = X + (size_t)TR * XS;   // TR x YS
+  double* Z = Y + (size_t)TR * YS;   // TR x XS: each row's basis row
   const int cols = PH == DBO_MAP || PH == DBO_FLIP ? a.caps : r;
   // the stage matrices, zero-padded to NB x NB
   for (int t = tid; t < NB * NB; t += blockDim.x) {
@@ -120,7 +124,6 @@ k_dbo_rows(DboArgs a, CtrlState* ctrl) {
   // outputs of at most 128 entries are split over row segments so that every thread works
   const int noutp = nout <= 64 ? 64 : (nout <= 128 ? 128 : 256);
   const int nseg = nout <= 128 ? 256 / noutp : 1;
-  const int o0 = nseg > 1 ? tid % noutp : tid, seg = nseg > 1 ? tid / noutp : 0;
   constexpr int NQ = (NB * 2 * NB + 255) / 256;   // >= outputs per thread when nseg == 1
   double acc[NQ];
 #pragma unroll
@@ -131,62 +134,68 @@ k_dbo_rows(DboArgs a, CtrlState* ctrl) {
 
   const long long nchunk = (a.M + TR - 1) / TR;
   for (long long ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
-    const long long i = ch * TR + tid;
-    const int nrows = (int)min((long long)TR, a.M - ch * TR);
     // an offset the compiler cannot see through: the stage matrices are read from LDS
-    // where they are used, not held in registers across the chunks
+    // and the per-thread indices formed where they are used, not held in registers
+    // across the chunks
     int zo = 0;
     asm volatile("" : "+s"(zo));
+    const int tt = tid + zo;
+    const long long i = ch * TR + tt;
+    const int nrows = (int)min((long long)TR, a.M - ch * TR);
     const double* P = sP + zo;
     const double* Mm = sM + zo;
     const double* E = sE + zo;
     const T* B0 = sB0 + zo;
     const T* B1 = sB1 + zo;
-    if (tid < TR && i < a.M) {
-      double* xr = X + (size_t)tid * XS;
-      double* yr = Y + (size_t)tid * YS;
+    if (tt < TR && i < a.M) {
+      double* xr = X + (size_t)tt * XS;
+      double* yr = Y + (size_t)tt * YS;
       const double w1 = a.w1[i];
+      double* zr = Z + (size_t)tt * XS;
+      // the row's derivative goes to yr[r ..], its basis row to zr; the contractions
+      // loop over the contracted index with only their outputs in registers
       if (PH == DBO_PASS1 || PH == DBO_FIN1) {
-        T d[NB], f[NB];
-        double u[NB];
-        dbo_load_d<TD, T, NB>(a, a.D1, i, d);
-        dbo_load_u<NB>(a.U1, i, a.ldU1, r, u);
-        dbo_dB<T, NB>(d, B0, f);
+        dbo_stage_d<TD, NB>(a, a.D1, i, yr + r);
+        dbo_stage_u<NB>(a.U1, i, a.ldU1, r, zr);
+        T f[NB];
+        dbo_dB_lds<T, NB>(yr + r, K, B0, f);
         if (PH == DBO_FIN1) {
-          double ud[NB];
-          dbo_rhs<T, NB>(f, u, P, Mm, a.dscale, ud);
 #pragma unroll
-          for (int q = 0; q < NB; ++q) {
-            if (q < r) a.kU1[i * a.ldU1 + q] = ud[q];
-            u[q] += a.dt * ud[q];
-          }
-          if (a.D2) dbo_load_d<TD, T, NB>(a, a.D2, i, d);
-          dbo_dB<T, NB>(d, B1, f);
+          for (int q = 0; q < NB; ++q)
+            if (q < r) yr[q] = (double)f[q];
+          double ud[NB];
+          dbo_rhs_lds<NB>(yr, zr, r, P, Mm, a.dscale, ud);
+#pragma unroll
+          for (int q = 0; q < NB; ++q)
+            if (q < r) {
+              a.kU1[i * a.ldU1 + q] = ud[q];
+              zr[q] += a.dt * ud[q];
+            }
+          if (a.D2) dbo_stage_d<TD, NB>(a, a.D2, i, yr + r);
+          dbo_dB_lds<T, NB>(yr + r, K, B1, f);
         }
 #pragma unroll
         for (int q = 0; q < NB; ++q)
           if (q < r) {
-            xr[q] = w1 * u[q];
+            xr[q] = w1 * zr[q];
             yr[q] = (double)f[q];
           }
-#pragma unroll
-        for (int j = 0; j < NB; ++j)
-          if (j < K) yr[r + j] = (double)d[j];
       } else if (PH == DBO_FIN2 || PH == DBO_FINE) {
-        double un[NB];
-        {
-          T d[NB], f[NB];
-          double us[NB];
-          const void* Dst = PH == DBO_FIN2 ? (a.D2 ? a.D2 : a.D1) : a.D1;
-          dbo_load_d<TD, T, NB>(a, Dst, i, d);
-          dbo_dB<T, NB>(d, PH == DBO_FIN2 ? B1 : B0, f);
-          dbo_load_u<NB>(a.U1, i, a.ldU1, r, us);
-          if (PH == DBO_FIN2) {
-#pragma unroll
-            for (int q = 0; q < NB; ++q) us[q] += q < r ? a.dt * a.kU1[i * a.ldU1 + q] : 0.0;
-          }
-          dbo_rhs<T, NB>(f, us, P, Mm, a.dscale, un);
+        const void* Dst = PH == DBO_FIN2 ? (a.D2 ? a.D2 : a.D1) : a.D1;
+        dbo_stage_d<TD, NB>(a, Dst, i, yr + r);
+        dbo_stage_u<NB>(a.U1, i, a.ldU1, r, zr);
+        if (PH == DBO_FIN2) {
+          for (int q = 0; q < r; ++q) zr[q] += a.dt * a.kU1[i * a.ldU1 + q];
         }
+        {
+          T f[NB];
+          dbo_dB_lds<T, NB>(yr + r, K, PH == DBO_FIN2 ? B1 : B0, f);
+#pragma unroll
+          for (int q = 0; q < NB; ++q)
+            if (q < r) xr[q] = (double)f[q];
+        }
+        double un[NB];
+        dbo_rhs_lds<NB>(xr, zr, r, P, Mm, a.dscale, un);
         // un holds the stage's basis derivative; the new basis row from U1 and kU1
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
@@ -255,9 +264,9 @@ k_dbo_rows(DboArgs a, CtrlState* ctrl) {
     if (PH == DBO_NORM || PH == DBO_FLIP) continue;
     __syncthreads();
     if (PH == DBO_MAP) {
-      if (tid < cols) {
+      if (tt < cols) {
         for (int t = 0; t < nrows; ++t) {
-          const double x = X[(size_t)t * XS + tid];
+          const double x = X[(size_t)t * XS + tt];
           if (fabs(x) > bmax) {
             bmax = fabs(x);
             brow = ch * TR + t;
@@ -266,6 +275,7 @@ k_dbo_rows(DboArgs a, CtrlState* ctrl) {
         }
       }
     } else {
+      const int o0 = nseg > 1 ? tt % noutp : tt, seg = nseg > 1 ? tt / noutp : 0;
       const int rs = nseg > 1 ? (nrows * seg) / nseg : 0;
       const int re = nseg > 1 ? (nrows * (seg + 1)) / nseg : nrows;
 #pragma unroll
@@ -293,6 +303,7 @@ k_dbo_rows(DboArgs a, CtrlState* ctrl) {
   }
   if (nseg > 1) {
     // segments in order: seg 0 + seg 1 (+ seg 2 + seg 3)
+    const int o0 = tid % noutp, seg = tid / noutp;
     X[tid] = acc[0];
     __syncthreads();
     if (seg == 0 && o0 < nout) {
@@ -408,12 +419,40 @@ __device__ void dbo_weighted_basis(const DboArgs& a, const double* U2, int st) {
   }
 }
 
-// Sums over the row blocks' partial slots, in block order: S[o] for o < slot.
-__device__ void dbo_reduce(const DboArgs& a, int slot, double* S) {
-  for (int o = threadIdx.x; o < slot; o += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < a.nblk; ++b) s += a.part[(size_t)b * slot + o];
-    S[o] = s;
+// Sums over the row blocks' partial slots: S[o] for o < slot. With fewer outputs than
+// threads, G groups of threads each sum every G-th block (loads in flight together),
+// and the groups' sums are added in group order; the order is fixed either way.
+__device__ void dbo_reduce(const DboArgs& a, int slot, double* S, double* tmp) {
+  const int G = slot >= (int)blockDim.x ? 1 : min((int)blockDim.x / slot, 16);
+  const int t = threadIdx.x;
+  if (G > 1) {
+    if (t < G * slot) {
+      const int o = t % slot, g = t / slot;
+      double s = 0.0;
+      int b = g;
+      // eight loads in flight, added in the same order as one at a time
+      for (; b + 7 * G < a.nblk; b += 8 * G) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = a.part[(size_t)(b + u * G) * slot + o];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+      }
+      for (; b < a.nblk; b += G) s += a.part[(size_t)b * slot + o];
+      tmp[g * slot + o] = s;
+    }
+    __syncthreads();
+    for (int o = t; o < slot; o += blockDim.x) {
+      double s = 0.0;
+      for (int g = 0; g < G; ++g) s += tmp[g * slot + o];
+      S[o] = s;
+    }
+  } else {
+    for (int o = t; o < slot; o += blockDim.x) {
+      double s = 0.0;
+      for (int b = 0; b < a.nblk; ++b) s += a.part[(size_t)b * slot + o];
+      S[o] = s;
+    }
   }
   __syncthreads();
 }
@@ -492,6 +531,15 @@ __global__ void __launch_bounds__(256) k_dbo_small(DboArgs a, CtrlState* ctrl, i
   __shared__ double Cd[DBO_RR];
   __shared__ double U2d[DBO_KMAX * DBO_RMAX];
   const int r = a.r, K = a.K;
+  // a singular core found while the previous step prepared this one belongs to this
+  // step's first stage, like a failure of its own preparation
+  if (step == DBO_MID1 && (ctrl->numeric & NUM_NEXT) && !(ctrl->numeric & ~NUM_NEXT)) {
+    if (threadIdx.x == 0) {
+      atomicOr(&ctrl->numeric, NUM_CORE);
+      atomicAnd(&ctrl->numeric, ~NUM_NEXT);
+    }
+    return;
+  }
   if (step != DBO_SIGN && ctrl->numeric) return;
   if (step == DBO_PREP) {
     if (!dbo_pinv(a, a.C0, 0, G, Li, Gi)) {
@@ -503,7 +551,7 @@ __global__ void __launch_bounds__(256) k_dbo_small(DboArgs a, CtrlState* ctrl, i
   }
   if (step == DBO_MID1 || step == DBO_MID2) {
     const int st = step == DBO_MID1 ? 0 : 1;
-    dbo_reduce(a, r * (r + K), S);
+    dbo_reduce(a, r * (r + K), S, Cd);
     if (!dbo_cdot(a, S, st, Cd)) {
       if (threadIdx.x == 0) atomicOr(&ctrl->numeric, NUM_NONFINITE);
       return;
@@ -547,7 +595,7 @@ __global__ void __launch_bounds__(256) k_dbo_small(DboArgs a, CtrlState* ctrl, i
   }
   if (step == DBO_END) {
     const int ny = r + 2;
-    dbo_reduce(a, (r + 1) * ny, S);
+    dbo_reduce(a, (r + 1) * ny, S, Cd);
     if (threadIdx.x == 0) {
       ctrl->eps2 = S[r * ny + r];
       ctrl->nu2 = S[r * ny + r + 1];
@@ -599,6 +647,13 @@ __global__ void __launch_bounds__(256) k_dbo_small(DboArgs a, CtrlState* ctrl, i
     }
     __syncthreads();
     for (int t = threadIdx.x; t < K * r; t += blockDim.x) a.U2[(t / r) * a.ldU2 + t % r] = U2d[t];
+    __syncthreads();
+    // the next step's stage-1 pseudo-inverses and W2 U2 at the new state
+    if (!dbo_pinv(a, a.C0, 0, G, Li, Gi)) {
+      if (threadIdx.x == 0) atomicOr(&ctrl->numeric, NUM_NEXT);
+      return;
+    }
+    dbo_weighted_basis<T>(a, a.U2, 0);
     return;
   }
   // DBO_SIGN: the HOSVD map's column argmax over the blocks (larger |x| wins, the

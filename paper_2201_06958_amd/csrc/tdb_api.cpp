@@ -54,6 +54,7 @@ struct tdb_ctx {
   void* dbo_bt = nullptr;    // W2 U2 of both stages in the compute type
   double* dbo_part = nullptr;
   int dbo_nblk = 1;
+  bool dbo_prep = false;     // stage-1 operands of the current state are prepared
   bool no_rpass = false;     // keep the tile pass in a batch (streams that disagree)
   bool ferr_cols = false;    // batch member on the column-block error pass
   int rpass_cols = 64;       // columns of mode 2 per workgroup of the column-block pass
@@ -1165,7 +1166,10 @@ tdb_status ingest_dbo(tdb_ctx* h, const TD* V1, hipStream_t s, const TD* D = nul
   a.D2 = D ? D2 : nullptr;
   a.dscale = D ? 1.0 : 1.0 / h->cfg.dt;
   CtrlState* c = h->ctrl;
-  HIPCHK(launch_dbo_small<T>(a, DBO_PREP, c, s));
+  // the previous step's last kernel prepared this one's first stage, unless the host
+  // has replaced the state since
+  if (!h->dbo_prep) HIPCHK(launch_dbo_small<T>(a, DBO_PREP, c, s));
+  h->dbo_prep = true;
   {
     PassTimer pt(h, TDB_PASS_PROJECT, s);
     HIPCHK((launch_dbo_rows<TD, T>(a, DBO_PASS1, c, s)));
@@ -1196,6 +1200,7 @@ tdb_status ingest_dbo(tdb_ctx* h, const TD* V1, hipStream_t s, const TD* D = nul
   h->step += 1;
   h->t_now = h->step * h->cfg.dt;
   if (dec != DEC_NONE) {
+    h->dbo_prep = false;
     TRY(hosvd_select<TD>(h, V1, dec, s));
     TRY(pull_ctrl(h, s));
     TRY(core_sigma(h, false, s));
