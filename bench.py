@@ -30,6 +30,8 @@ import subprocess
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -162,6 +164,71 @@ def _run_plume(warmup, steps):
             "error_pass": {"avg_launch_us": eav * 1e6, "achieved_GBs": er["bytes_per_launch"] / eav / 1e9},
             "final_stats": {"ranks": st["ranks"], "eps": st["eps"], "crbar": st["crbar"], "n_add": st["n_add"],
                             "n_reinit": st["n_reinit"], "n_remove": st["n_remove"]}}
+
+
+def _tdb1_vs_tdb2(warmup, steps):
+    """The reactive-flow-shaped stream compressed two ways at the same threshold
+    (Sec. 3.2): TDB-1, third order (x1, x2, variables) with caps (64, 64, 8), and
+    TDB-2, the DBO form of order 2 with x1 and x2 grouped into one mode of 131072 rows
+    (row passes), caps (8, 8). Both adaptive from the HOSVD of the first snapshot;
+    per-step eps and events from untimed runs, throughput of TDB-2 from a timed one.
+    Storage counts the core and bases at the final ranks, as Sec. 3.2 writes it."""
+    import torch
+    from streams import plume_spec
+    from paper_2201_06958_amd import Compressor
+    sp = plume_spec(steps=warmup + steps + 1)
+    n1, n2, nv = sp.dims
+    snaps = [sp.snapshot(k, device="cuda") for k in range(warmup + steps + 1)]
+    torch.cuda.synchronize()
+    w12 = np.kron(sp.weights[0], sp.weights[1])
+    out = {"workload": f"plume-{n1}x{n2}x{nv}-fp32, eps_th {sp.eps_th:g}", "steps": steps}
+    for name in ("tdb1", "tdb2"):
+        if name == "tdb1":
+            mk = lambda: Compressor(sp.dims, sp.dt, rank_max=(64, 64, nv), weights=sp.weights, data_dtype="f32",
+                                    precision="f32", adaptive=True, eps_th=sp.eps_th)
+            view = lambda x: x
+        else:
+            mk = lambda: Compressor((n1 * n2, nv), sp.dt, rank_max=(nv, nv), weights=[w12, sp.weights[2]],
+                                    data_dtype="f32", precision="f32", adaptive=True, eps_th=sp.eps_th)
+            view = lambda x: x.view(n1 * n2, nv)
+        c = mk()
+        c.init(view(snaps[0]))
+        eps, ranks = [], []
+        for k in range(1, warmup + steps + 1):
+            c.ingest(view(snaps[k]))
+            st = c.stats()
+            eps.append(st["eps"])
+            ranks.append(st["ranks"])
+        st = c.stats()
+        c.close()
+        r = st["ranks"]
+        if name == "tdb1":
+            storage = r[0] * n1 + r[1] * n2 + r[2] * nv + r[0] * r[1] * r[2]
+        else:
+            storage = r[0] * n1 * n2 + r[1] * nv + r[0] * r[1]
+        # timed run (no statistics read between steps)
+        c = mk()
+        c.init(view(snaps[0]))
+        for k in range(1, warmup + 1):
+            c.ingest(view(snaps[k]))
+        c.flush()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(warmup + 1, warmup + steps + 1):
+            c.ingest(view(snaps[k]))
+        c.flush()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        stt = c.stats()
+        c.close()
+        e = np.array(eps[warmup:])
+        out[name] = {"value": steps / el, "unit": "snapshots/s", "ms_per_step": 1e3 * el / steps,
+                     "path": stt["path_used"], "final_ranks": r, "crbar": st["crbar"],
+                     "storage_floats": storage, "n_reinit": st["n_reinit"], "n_add": st["n_add"],
+                     "n_remove": st["n_remove"], "eps_max": float(np.nanmax(e)), "eps_mean": float(np.nanmean(e)),
+                     "max_rank_sum": int(max(sum(x) for x in ranks))}
+    out["storage_ratio_tdb2_over_tdb1"] = out["tdb2"]["storage_floats"] / out["tdb1"]["storage_floats"]
+    return out
 
 
 # ---------------------------------------------------------------- CPU oracle
@@ -311,6 +378,9 @@ def main():
                     help="comma-separated cube sizes N: time a TDB step against an HOSVD of an "
                          "N x N x N snapshot for each (prints one JSON line and nothing else)")
     ap.add_argument("--sweep-steps", type=int, default=50, help="TDB steps timed per size of the sweep")
+    ap.add_argument("--tdb1-vs-tdb2", action="store_true",
+                    help="only compare TDB-1 (third order) with TDB-2 (order 2, grouped spatial mode) on the "
+                         "reactive-flow-shaped stream over --plume-steps steps (prints one JSON line)")
     ap.add_argument("--cpu-oracle-worker", type=str, default="", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_oracle_worker:
@@ -325,6 +395,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.tdb1_vs_tdb2:
+        print(json.dumps(_tdb1_vs_tdb2(10, args.plume_steps)), flush=True)
+        return
     if args.scaling_sweep:
         sizes = [int(x) for x in args.scaling_sweep.split(",") if x.strip()]
         print(json.dumps(_scaling_sweep(sizes, max(args.sweep_steps, 10))), flush=True)
@@ -377,6 +450,8 @@ def main():
         torch.cuda.empty_cache()
         _log("reactive-flow-shaped stream")
         extras["plume_c2"] = _run_plume(20, args.plume_steps)
+        _log("TDB-1 against TDB-2 (grouped spatial mode) on the reactive-flow-shaped stream")
+        extras["tdb1_vs_tdb2"] = _tdb1_vs_tdb2(10, args.plume_steps)
     else:
         del snaps
     cpu = None

@@ -59,7 +59,15 @@ enum {                                                   /* controller events   
 
 typedef struct tdb_ctx* tdb_handle;
 
-/* Configuration of one stream (Sec. 2.3, 2.5). Copied at init. */
+/* Configuration of one stream (Sec. 2.3, 2.5). Copied at init.
+ *
+ * Order 2 with a short second mode (dims[1] <= 32, dims[0] >= dims[1], path AUTO or
+ * FUSED) is the DBO form of Sec. 2.2 and TDB-2 of Sec. 3.2: a snapshot is the
+ * dims[0] x dims[1] row-major matrix, e.g. a field (x1, x2, variables) with x1 and x2
+ * grouped into the first mode (weights the product of the two axes' weights). Such a
+ * stream steps on row passes and synchronously; its first mode may exceed 512 entries
+ * (its HOSVD basis is then taken from the second mode's eigenvectors). Every other mode
+ * of every stream has at most 512 entries. */
 typedef struct {
   int32_t order;                       /* p, 2..4 in this library                      */
   int64_t dims[TDB_MAX_ORDER];         /* N_n; a mode may be a flattened group of axes */
