@@ -231,6 +231,72 @@ def _tdb1_vs_tdb2(warmup, steps):
     return out
 
 
+def _samples_as_mode(warmup, steps, nx=128, ny=64, nv=8, s=(4, 4)):
+    """Samples as a tensor mode (Sec. 3.3, eq. (UQ)) against independent streams: the
+    s1 x s2 stochastic reactive-flow samples compressed as one order-4 tensor (sample
+    mode first, product Gauss weights) and as a batch of independent third-order streams,
+    both adaptive at the same threshold. The tensor's eps is the weighted RMS over the
+    samples; the batch's is formed from its members' eps with the same weights.
+    Compression counts the core and bases of each at every step (time-weighted)."""
+    import torch
+    from streams import stochastic_plume_spec
+    from paper_2201_06958_amd import Compressor, Batch
+    sp = stochastic_plume_spec(nx=nx, ny=ny, nv=nv, s=s, steps=warmup + steps + 1)
+    S = sp.dims[0]
+    snaps = [sp.snapshot(k, device="cuda") for k in range(warmup + steps + 1)]
+    torch.cuda.synchronize()
+    out = {"workload": f"stochastic-plume {S} samples x {nx}x{ny}x{nv} fp32, eps_th {sp.eps_th:g}", "steps": steps}
+    # one tensor
+    c = Compressor(sp.dims, sp.dt, rank_max=(S, 32, 32, nv), weights=sp.weights, data_dtype="f32",
+                   precision="f32", adaptive=True, eps_th=sp.eps_th)
+    c.init(snaps[0])
+    eps = []
+    for k in range(1, warmup + 1):
+        c.ingest(snaps[k])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(warmup + 1, warmup + steps + 1):
+        c.ingest(snaps[k])
+        eps.append(c.stats()["eps"])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = c.stats()
+    c.close()
+    out["tensor"] = {"value": S * steps / el, "unit": "sample-snapshots/s", "ms_per_step": 1e3 * el / steps,
+                     "path": st["path_used"], "final_ranks": st["ranks"], "crbar": st["crbar"],
+                     "eps_mean": float(np.mean(eps)), "eps_max": float(np.max(eps)),
+                     "events": {k: st[k] for k in ("n_add", "n_remove", "n_reinit")}}
+    # independent streams
+    specs = sp.meta["sample_specs"]
+    b = Batch([dict(dims=q.dims, dt=q.dt, rank_max=(32, 32, nv), weights=q.weights, data_dtype="f32",
+                    precision="f32", adaptive=True, snapshot_mode="borrow", eps_th=sp.eps_th) for q in specs])
+    b.init([snaps[0][i] for i in range(S)])
+    for k in range(1, warmup + 1):
+        b.ingest([snaps[k][i] for i in range(S)])
+    b.flush()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(warmup + 1, warmup + steps + 1):
+        b.ingest([snaps[k][i] for i in range(S)])
+    b.flush()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sts = [m.stats() for m in b.streams]
+    b.close()
+    wq = sp.weights[0]
+    elems = nx * ny * nv
+    # aggregate compression: all samples' values over all members' stored floats (time-weighted
+    # per member, combined as the sum of stored floats)
+    stored = sum(elems / m["crbar"] for m in sts)
+    out["independent"] = {"value": S * steps / el, "unit": "sample-snapshots/s", "ms_per_step": 1e3 * el / steps,
+                          "max_ranks": [max(m["ranks"][i] for m in sts) for i in range(3)],
+                          "crbar": S * elems / stored,
+                          "eps_weighted_rms_end": float(np.sqrt(sum(w * m["eps"] ** 2 for w, m in zip(wq, sts)))),
+                          "events": {k: sum(m[k] for m in sts) for k in ("n_add", "n_remove", "n_reinit")}}
+    out["cr_ratio_tensor_over_independent"] = out["tensor"]["crbar"] / out["independent"]["crbar"]
+    return out
+
+
 # ---------------------------------------------------------------- CPU oracle
 
 def _physical_cores():
@@ -378,6 +444,9 @@ def main():
                     help="comma-separated cube sizes N: time a TDB step against an HOSVD of an "
                          "N x N x N snapshot for each (prints one JSON line and nothing else)")
     ap.add_argument("--sweep-steps", type=int, default=50, help="TDB steps timed per size of the sweep")
+    ap.add_argument("--samples-as-mode", action="store_true",
+                    help="only compare 16 stochastic samples compressed as one order-4 tensor with the same "
+                         "samples as independent streams over --plume-steps steps (prints one JSON line)")
     ap.add_argument("--tdb1-vs-tdb2", action="store_true",
                     help="only compare TDB-1 (third order) with TDB-2 (order 2, grouped spatial mode) on the "
                          "reactive-flow-shaped stream over --plume-steps steps (prints one JSON line)")
@@ -395,6 +464,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.samples_as_mode:
+        print(json.dumps(_samples_as_mode(10, args.plume_steps)), flush=True)
+        return
     if args.tdb1_vs_tdb2:
         print(json.dumps(_tdb1_vs_tdb2(10, args.plume_steps)), flush=True)
         return

@@ -9,6 +9,7 @@ from .generators import (  # noqa: F401
     StreamSpec,
     analytic_cp5_spec,
     plume_spec,
+    stochastic_plume_spec,
     fourier_ensemble_specs,
     channel_spec,
     runge_spec,

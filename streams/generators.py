@@ -169,7 +169,7 @@ _PLUME_R = (0.05, 0.04, 0.06)
 
 def plume_spec(nx: int = 512, ny: int = 256, nv: int = 8, steps: int = 1000,
                dt: float = 5e-4, noise: float = 1e-6, noise_seed: int = 2,
-               centre_shift=(0.0, 0.0)) -> StreamSpec:
+               centre_shift=(0.0, 0.0), width_scale: float = 1.0, growth: float = 2.0) -> StreamSpec:
     """Reactive-flow-shaped stream: 3 advected Gaussian plumes with tanh reaction
     fronts and Arrhenius-like variable scaling, on the periodic box [0,2)x[0,1).
 
@@ -195,8 +195,8 @@ def plume_spec(nx: int = 512, ny: int = 256, nv: int = 8, steps: int = 1000,
             dy = Y - cy
             dy = dy - ly * torch.round(dy / ly)
             d = torch.sqrt(dx * dx + dy * dy)
-            g = torch.exp(-(d * d) / (2.0 * _PLUME_S[m] ** 2))
-            R = _PLUME_R[m] * (1.0 + 2.0 * t)
+            g = torch.exp(-(d * d) / (2.0 * (_PLUME_S[m] * width_scale) ** 2))
+            R = _PLUME_R[m] * (1.0 + growth * t)
             theta = 0.5 * (1.0 + torch.tanh((R - d) / 0.02))
             gs.append(g)
             th.append(theta)
@@ -218,6 +218,45 @@ def plume_spec(nx: int = 512, ny: int = 256, nv: int = 8, steps: int = 1000,
         name=f"plume-{nx}x{ny}x{nv}", dims=dims, weights=_uniform_weights(dims), dt=dt,
         steps=steps, field_fn=fld, storage="f32", eps_th=1e-4, rank_init=None,
         rank_max=(64, 64, nv), adaptive=True, meta={"start_ranks": (4, 4, 4)})
+
+
+# --------------------------------------------------------------------------- samples as a mode
+def stochastic_plume_spec(nx: int = 128, ny: int = 64, nv: int = 8, s=(4, 4), steps: int = 200,
+                          dt: float = 5e-4, weights: str = "pcm", spread: float = 0.25,
+                          noise: float = 1e-6) -> StreamSpec:
+    """Samples as a tensor mode (the stochastic case of Sec. 3.3, eq. (UQ)): the
+    reactive-flow-shaped field for s1 x s2 values (xi1, xi2) of two random
+    coefficients, on the tensor-product Gauss-Legendre points of [-1, 1]^2. Coefficient
+    xi1 scales the plume widths by 1 + spread xi1 (a diffusion-like parameter), xi2 the
+    reaction fronts' growth rate by 1 + spread xi2. The samples are stacked along a
+    leading mode (xi1 slow, xi2 fast), so a snapshot is (S, nx, ny, nv) and sample i is
+    the i-th contiguous block. Sample-mode weights: the product Gauss weights
+    (probabilistic collocation, "pcm") or 1/S (Monte Carlo, "mc"), normalised to sum 1.
+    Sample i draws its noise from seed 2 + 1000 i + k at snapshot k."""
+    g1, q1 = np.polynomial.legendre.leggauss(s[0])
+    g2, q2 = np.polynomial.legendre.leggauss(s[1])
+    pts = [(a, b) for a in g1 for b in g2]
+    specs = [plume_spec(nx, ny, nv, steps, dt, noise=noise, noise_seed=2 + 1000 * i,
+                        width_scale=1.0 + spread * a, growth=2.0 * (1.0 + spread * b))
+             for i, (a, b) in enumerate(pts)]
+    S = len(pts)
+    if weights == "pcm":
+        wq = np.kron(q1, q2)
+        wq = wq / wq.sum()
+    elif weights == "mc":
+        wq = np.full(S, 1.0 / S)
+    else:
+        raise ValueError(f"unknown sample weights {weights!r}")
+
+    def fld(t, device, dtype):
+        return torch.stack([sp.field_fn(t, device, dtype) for sp in specs])
+
+    dims = (S, nx, ny, nv)
+    return StreamSpec(
+        name=f"stochastic-plume-{S}x{nx}x{ny}x{nv}", dims=dims, weights=[wq] + list(specs[0].weights), dt=dt,
+        steps=steps, field_fn=fld, storage="f32", eps_th=1e-4, rank_init=None,
+        rank_max=(S, 32, 32, nv), adaptive=True,
+        meta={"samples": pts, "sample_weights": weights, "sample_specs": specs})
 
 
 # --------------------------------------------------------------------------- C3
