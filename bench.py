@@ -524,6 +524,8 @@ def main():
         extras["plume_c2"] = _run_plume(20, args.plume_steps)
         _log("TDB-1 against TDB-2 (grouped spatial mode) on the reactive-flow-shaped stream")
         extras["tdb1_vs_tdb2"] = _tdb1_vs_tdb2(10, args.plume_steps)
+        _log("16 stochastic samples as one order-4 tensor against independent streams")
+        extras["samples_as_mode"] = _samples_as_mode(10, 100)
     else:
         del snaps
     cpu = None
