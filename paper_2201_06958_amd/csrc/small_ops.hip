@@ -19,6 +19,27 @@ __device__ __forceinline__ long long unf_index(int a, long long col, int rn, lon
   return (o * rn + a) * inner + in;
 }
 
+// sum_q w[q] x[q * sx] y[q * sy] for q < n in increasing order, with eight rows'
+// loads in flight at a time.
+__device__ __forceinline__ double wdot3(const double* __restrict__ w, const double* __restrict__ x, int sx,
+                                        const double* __restrict__ y, int sy, long long n) {
+  double s = 0.0;
+  long long q = 0;
+  for (; q + 8 <= n; q += 8) {
+    double a[8], b[8], c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a[u] = w[q + u];
+      b[u] = x[(q + u) * sx];
+      c[u] = y[(q + u) * sy];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += a[u] * b[u] * c[u];
+  }
+  for (; q < n; ++q) s += w[q] * x[q * sx] * y[q * sy];
+  return s;
+}
+
 // Gram matrix G = A A^T of the mode-n unfolding of a dense core, into LDS (ld = rn).
 __device__ void core_gram(const double* __restrict__ C, int rn, long long R, long long inner,
                           double* G) {
@@ -29,9 +50,14 @@ __device__ void core_gram(const double* __restrict__ C, int rn, long long R, lon
     while ((a + 1) * (a + 2) / 2 <= t) ++a;
     while (a * (a + 1) / 2 > t) --a;
     const int b = t - a * (a + 1) / 2;
+    // the columns c = o * inner + in in increasing order, without a division per term
     double s = 0.0;
-    for (long long c = 0; c < R; ++c)
-      s += C[unf_index(a, c, rn, inner)] * C[unf_index(b, c, rn, inner)];
+    const long long nout = R / inner;
+    for (long long o = 0; o < nout; ++o) {
+      const double* pa = C + (o * rn + a) * inner;
+      const double* pb = C + (o * rn + b) * inner;
+      for (long long in = 0; in < inner; ++in) s += pa[in] * pb[in];
+    }
     G[a * rn + b] = s;
     G[b * rn + a] = s;
   }
@@ -182,9 +208,7 @@ __global__ void __launch_bounds__(TDB_BLOCK) k_rhs_stage(RhsArgs a, CtrlState* c
   if (!full) {
     for (int t = threadIdx.x; t < rn * rn; t += blockDim.x) {
       const int i = t / rn, j = t % rn;
-      double s = 0.0;
-      for (long long q = 0; q < Nn; ++q) s += w[q] * Ust[q * ld + i] * H[q * rn + j];
-      M[t] = s;
+      M[t] = wdot3(w, Ust + i, ld, H + j, rn, Nn);
     }
   }
   __syncthreads();
@@ -232,8 +256,7 @@ __global__ void __launch_bounds__(TDB_BLOCK) k_qr_fold(QrArgs a, CtrlState* ctrl
         while ((i + 1) * (i + 2) / 2 <= t) ++i;
         while (i * (i + 1) / 2 > t) --i;
         const int j = t - i * (i + 1) / 2;
-        double s = 0.0;
-        for (long long q = 0; q < Nn; ++q) s += w[q] * U[q * ld + i] * U[q * ld + j];
+        const double s = wdot3(w, U + i, ld, U + j, ld, Nn);
         L[i * rn + j] = s;
         L[j * rn + i] = s;
       }

@@ -56,29 +56,40 @@ TTM_INST(double, float, float)
 
 // H[i, a] = sum_col F_(n)[i, col] P[col, a]; F has dims (outer, Nn, inner) C-ordered
 // and its mode-n unfolding enumerates (o, in) with in fastest, like the core's.
+// One block per row i: thread t takes output a = t % rn and every G-th column (G =
+// blockDim / rn slices, columns in increasing order within a slice); the slices are
+// added in slice order, so the sum's order is fixed.
 template <typename T>
 __global__ void __launch_bounds__(256) k_fold_h(const T* __restrict__ F, const T* __restrict__ P,
                                                 double* __restrict__ H, long long Nn, int rn,
                                                 long long outer, long long inner) {
-  const long long total = Nn * rn;
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-       t += (long long)gridDim.x * blockDim.x) {
-    const long long i = t / rn;
-    const int a = (int)(t - i * rn);
+  __shared__ double part[256];
+  const int G = (int)blockDim.x / rn;
+  const int t = threadIdx.x, a = t % rn, g = t / rn;
+  const long long R = outer * inner;
+  for (long long i = blockIdx.x; i < Nn; i += gridDim.x) {
     double acc = 0.0;
-    for (long long o = 0; o < outer; ++o) {
-      const T* fp = F + (o * Nn + i) * inner;
-      const T* pp = P + (o * inner) * rn + a;
-      for (long long in = 0; in < inner; ++in) acc += (double)fp[in] * (double)pp[in * rn];
+    if (g < G) {
+      for (long long c = g; c < R; c += G) {
+        const long long o = c / inner, in = c - o * inner;
+        acc += (double)F[(o * Nn + i) * inner + in] * (double)P[c * rn + a];
+      }
     }
-    H[t] = acc;
+    part[t] = acc;
+    __syncthreads();
+    if (t < rn) {
+      double s = 0.0;
+      for (int q = 0; q < G; ++q) s += part[q * rn + t];
+      H[i * rn + t] = s;
+    }
+    __syncthreads();
   }
 }
 
 template <typename T>
 hipError_t launch_fold_h(const T* F, const T* P, double* H, long long Nn, int rn, long long outer,
                          long long inner, hipStream_t s) {
-  long long blocks = (Nn * rn + 255) / 256;
+  long long blocks = Nn;
   if (blocks < 1) blocks = 1;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_fold_h<T>, dim3((unsigned)blocks), dim3(256), 0, s, F, P, H, Nn, rn, outer, inner);

@@ -69,6 +69,7 @@ struct tdb_ctx {
   double *U0[TDB_P] = {}, *Us[TDB_P] = {}, *kU[TDB_P] = {}, *H[TDB_P] = {}, *w[TDB_P] = {};
   void *B[TDB_P] = {}, *P[TDB_P] = {}, *Uc[TDB_P] = {};
   void *Cc = nullptr, *wsA = nullptr, *wsB = nullptr;
+  void* wsZ[2] = {nullptr, nullptr};   // plain path: the two shared first contractions
   double *err_part = nullptr;
   int err_blocks = 1024;
   CtrlState* ctrl = nullptr;
@@ -460,6 +461,7 @@ tdb_status setup(tdb_ctx* h, const tdb_config* cfg) {
   }
   TRY(dalloc(h, &h->wsA, (size_t)h->S * h->celt));
   TRY(dalloc(h, &h->wsB, (size_t)h->S * h->celt));
+  for (int z = 0; z < 2; ++z) TRY(dalloc(h, &h->wsZ[z], (size_t)h->S * h->celt));
   TRY(dallocT(h, &h->err_part, 2 * (size_t)h->err_blocks));
   TRY(dallocT(h, &h->d_flag, 1));
   TRY(dalloc(h, reinterpret_cast<void**>(&h->ctrl), sizeof(CtrlState)));
@@ -650,35 +652,50 @@ tdb_status stage_prep(tdb_ctx* h, const double* C, double* const* U, hipStream_t
 template <typename TD, typename T>
 tdb_status project_plain(tdb_ctx* h, const TD* V1, const TD* V0, hipStream_t s) {
   const int p = h->p;
+  // the two modes that reduce the data most (largest N/r), contracted first: every F_n
+  // with n != a continues from D x_a B_a^T, F_a from D x_b B_b^T, so the snapshot pair is
+  // read twice per stage instead of p times
+  std::vector<int> ord(p);
+  for (int k = 0; k < p; ++k) ord[k] = k;
+  auto by_ratio = [&](int x, int y) {
+    const double rx = (double)h->N[x] / h->r[x], ry = (double)h->N[y] / h->r[y];
+    return rx != ry ? rx > ry : x < y;
+  };
+  std::sort(ord.begin(), ord.end(), by_ratio);
+  const int first[2] = {ord[0], ord[1]};
+  T* Z[2] = {static_cast<T*>(h->wsZ[0]), static_cast<T*>(h->wsZ[1])};
+  for (int z = 0; z < 2; ++z) {
+    const int k = first[z];
+    long long A = 1, Bz = 1;
+    for (int j = 0; j < k; ++j) A *= h->N[j];
+    for (int j = k + 1; j < p; ++j) Bz *= h->N[j];
+    HIPCHK((launch_ttm<TD, T, T>(V1, V0, Z[z], static_cast<const T*>(h->B[k]), h->r[k], 1, A, (int)h->N[k],
+                                 h->r[k], Bz, s)));
+  }
+  T* bufs[2] = {static_cast<T*>(h->wsA), static_cast<T*>(h->wsB)};
   for (int n = 0; n < p; ++n) {
-    std::vector<int> order;
-    for (int k = 0; k < p; ++k)
-      if (k != n) order.push_back(k);
-    std::sort(order.begin(), order.end(), [&](int x, int y) {
-      const double rx = (double)h->N[x] / h->r[x], ry = (double)h->N[y] / h->r[y];
-      return rx != ry ? rx > ry : x < y;
-    });
+    const int zi = n == first[0] ? 1 : 0;
+    const int done = first[zi];
     long long cd[TDB_P];
     for (int k = 0; k < p; ++k) cd[k] = h->N[k];
-    T* bufs[2] = {static_cast<T*>(h->wsA), static_cast<T*>(h->wsB)};
-    int cur = -1;
-    for (size_t q = 0; q < order.size(); ++q) {
-      const int k = order[q];
+    cd[done] = h->r[done];
+    std::vector<int> order;
+    for (int k : ord)
+      if (k != n && k != done) order.push_back(k);
+    const T* cur = Z[zi];
+    int next = 0;
+    for (int k : order) {
       long long A = 1, Bz = 1;
       for (int j = 0; j < k; ++j) A *= cd[j];
       for (int j = k + 1; j < p; ++j) Bz *= cd[j];
-      T* out = bufs[cur == 0 ? 1 : 0];
-      if (q == 0) {
-        HIPCHK((launch_ttm<TD, T, T>(V1, V0, out, static_cast<const T*>(h->B[k]), h->r[k], 1, A,
-                                     (int)cd[k], h->r[k], Bz, s)));
-      } else {
-        HIPCHK((launch_ttm<T, T, T>(bufs[cur], nullptr, out, static_cast<const T*>(h->B[k]), h->r[k], 1,
-                                    A, (int)cd[k], h->r[k], Bz, s)));
-      }
+      T* out = bufs[next];
+      HIPCHK((launch_ttm<T, T, T>(cur, nullptr, out, static_cast<const T*>(h->B[k]), h->r[k], 1, A, (int)cd[k],
+                                  h->r[k], Bz, s)));
       cd[k] = h->r[k];
-      cur = (cur == 0) ? 1 : 0;
+      cur = out;
+      next = 1 - next;
     }
-    const T* F = bufs[cur];
+    const T* F = cur;
     long long outer = 1, inner = 1;
     for (int k = 0; k < n; ++k) outer *= h->r[k];
     for (int k = n + 1; k < p; ++k) inner *= h->r[k];
