@@ -297,6 +297,157 @@ def _samples_as_mode(warmup, steps, nx=128, ny=64, nv=8, s=(4, 4)):
     return out
 
 
+def _run_c1(steps=200, warmup=5):
+    """The plain single-stream case: the five-term analytic 64^3 stream in FP64, fixed
+    ranks (5, 5, 5), Heun with the first-order difference, on the fused FP64 path and on
+    the plain FP64 per-mode path; their final states agree to the stated 1e-6."""
+    import torch
+    from streams import analytic_cp5_spec
+    from paper_2201_06958_amd import Compressor
+    sp = analytic_cp5_spec(n=64, steps=warmup + steps)
+    snaps = [sp.snapshot(k, device="cuda") for k in range(warmup + steps + 1)]
+    torch.cuda.synchronize()
+    out = {"workload": "analytic-64^3-fp64, ranks (5, 5, 5) fixed, dt 1e-3", "steps": steps}
+    recs = {}
+    for path in ("fused", "plain"):
+        c = Compressor(sp.dims, sp.dt, rank_max=(5, 5, 5), rank_init=(5, 5, 5), weights=sp.weights, data_dtype="f64",
+                       precision="f64", path=path, adaptive=False, eps_th=1.0)
+        c.init(snaps[0])
+        for k in range(1, warmup + 1):
+            c.ingest(snaps[k])
+        c.flush()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(warmup + 1, warmup + steps + 1):
+            c.ingest(snaps[k])
+        c.flush()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st = c.stats()
+        rec = torch.empty_like(snaps[0])
+        c.reconstruct(rec)
+        torch.cuda.synchronize()
+        recs[path] = rec
+        c.close()
+        out[path] = {"value": steps / el, "unit": "snapshots/s", "ms_per_step": 1e3 * el / steps,
+                     "path_used": st["path_used"], "eps_over_nu": st["eps"] / st["nu"],
+                     "achieved_GBs_step": 5 * sp.size * 8 / (el / steps) / 1e9}
+    out["max_rel_diff_fused_vs_plain"] = float((recs["fused"] - recs["plain"]).abs().max() /
+                                               recs["plain"].abs().max())
+    out["speedup_fused_over_plain"] = out["fused"]["value"] / out["plain"]["value"]
+    return out
+
+
+def _run_c4(steps=30, warmup=5):
+    """The channel-flow-shaped stream, 192 x 129 x 192 x 3 FP32, adaptive (caps (40, 40,
+    40, 3), threshold 1e-3). Order 4 runs on the plain per-mode path; BF16-split
+    products are not available for it, so precision_used reports FP32."""
+    import torch
+    from streams import channel_spec
+    from paper_2201_06958_amd import Compressor
+    sp = channel_spec(steps=warmup + steps)
+    snaps = [sp.snapshot(k, device="cuda") for k in range(warmup + steps + 1)]
+    torch.cuda.synchronize()
+    c = Compressor(sp.dims, sp.dt, rank_max=sp.rank_max, weights=sp.weights, data_dtype="f32",
+                   precision="bf16s", adaptive=True, eps_th=sp.eps_th)
+    t0 = time.perf_counter()
+    c.init(snaps[0])
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t0
+    for k in range(1, warmup + 1):
+        c.ingest(snaps[k])
+    c.flush()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(warmup + 1, warmup + steps + 1):
+        c.ingest(snaps[k])
+    c.flush()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = c.stats()
+    c.close()
+    return {"workload": "channel-192x129x192x3-fp32, caps (40, 40, 40, 3), eps_th 1e-3", "steps": steps,
+            "value": steps / el, "unit": "snapshots/s", "ms_per_step": 1e3 * el / steps,
+            "init_hosvd_ms": 1e3 * t_init, "path_used": st["path_used"], "precision_used": st["precision_used"],
+            "ranks": st["ranks"], "eps": st["eps"], "crbar": st["crbar"],
+            "events": {k: st[k] for k in ("n_add", "n_remove", "n_reinit")},
+            "achieved_GBs_step": 5 * sp.size * 4 / (el / steps) / 1e9}
+
+
+def _run_c5(train_steps=150, eval_steps=30):
+    """The learned error gate at a larger scale: trained on the histories of 48 held-out
+    ensemble members and 16 reactive-flow streams of 256 x 128 x 8 (windows of 8 exact
+    steps without a reinitialisation), evaluated on the 256-stream ensemble together
+    with 64 reactive-flow streams of 512 x 256 x 8 (shifted plumes, their own noise
+    seeds): skipped error passes, mis-decisions against the exact pass, decisions of
+    the gated and exact runs, and snapshots/s gated against always exact."""
+    from streams import fourier_ensemble_specs, plume_spec, gate_init_params
+    from paper_2201_06958_amd import Gate
+    from paper_2201_06958_amd import gate as GP
+
+    def cfg(sp, caps):
+        return dict(dims=sp.dims, dt=sp.dt, rank_max=caps, weights=sp.weights, data_dtype="f32",
+                    precision="f32", adaptive=True, eps_th=sp.eps_th, snapshot_mode="copy")
+
+    def streams(seed0, n_ens, n_plume, size, steps):
+        specs = fourier_ensemble_specs(n_streams=n_ens, seed0=seed0, steps=steps + 1)
+        cfgs = [cfg(q, q.rank_max) for q in specs]
+        rng = np.random.default_rng(seed0)
+        for j in range(n_plume):
+            q = plume_spec(nx=size[0], ny=size[1], nv=8, steps=steps + 1, noise_seed=100 * seed0 + 17 * j,
+                           centre_shift=(float(rng.uniform(0, 2)), float(rng.uniform(0, 1))))
+            specs.append(q)
+            cfgs.append(cfg(q, (32, 32, 8)))
+        cache = {}
+
+        def snapshot(k):
+            if k not in cache:
+                cache.clear()
+                cache[k] = [q.snapshot(k, device="cuda") for q in specs]
+            return cache[k]
+        return specs, cfgs, snapshot
+
+    specs, cfgs, snap = streams(5000, 48, 16, (256, 128), train_steps)
+    t0 = time.perf_counter()
+    h = GP.record_histories(cfgs, snap, train_steps)
+    X, t = GP.make_samples(h)
+    ms = GP.standardisation(X)
+    g = Gate(max_batch=1024)
+    g.set_params(gate_init_params(11))
+    hist = GP.train(g, X, t, ms, epochs=30, batch=256, lr=1e-3)
+    t_train = time.perf_counter() - t0
+    specs2 = fourier_ensemble_specs(n_streams=256, seed0=1000, steps=eval_steps + 1)
+    cfgs2 = [cfg(q, q.rank_max) for q in specs2]
+    rng = np.random.default_rng(9000)
+    for j in range(64):
+        q = plume_spec(steps=eval_steps + 1, noise_seed=9000 + 17 * j,
+                       centre_shift=(float(rng.uniform(0, 2)), float(rng.uniform(0, 1))))
+        specs2.append(q)
+        cfgs2.append(cfg(q, (32, 32, 8)))   # the stream's ranks stay near (15, 15, 4)
+    import torch
+    # every evaluation snapshot is generated before the runs, so that the timed loops
+    # measure the compression only
+    allsnaps = [[q.snapshot(k, device="cuda") for q in specs2] for k in range(eval_steps + 1)]
+    torch.cuda.synchronize()
+    ev = GP.evaluate(cfgs2, lambda k: allsnaps[k], eval_steps, g, ms, [q.eps_th for q in specs2])
+    g.close()
+    ev.update({"workload": "gate: trained on 48 ensemble + 16 reactive-flow (256x128x8) histories; evaluated on "
+                           "the 256-stream ensemble + 64 reactive-flow streams (512x256x8)",
+               "train_samples": int(X.shape[0]), "train_loss_first_last": [hist[0], hist[-1]],
+               "train_wall_s": t_train, "eval_steps": eval_steps,
+               "speedup_gated_over_exact": ev["snapshots_per_s_gated"] / ev["snapshots_per_s_exact"]})
+    return ev
+
+
+def _guarded(name, fn, *a):
+    """An extra record: its failure is reported in the line, not raised."""
+    try:
+        return fn(*a)
+    except Exception as e:  # noqa: BLE001 - the headline must still be printed
+        _log(f"{name} failed: {e!r}")
+        return {"error": repr(e)}
+
+
 # ---------------------------------------------------------------- CPU oracle
 
 def _physical_cores():
@@ -444,6 +595,9 @@ def main():
                     help="comma-separated cube sizes N: time a TDB step against an HOSVD of an "
                          "N x N x N snapshot for each (prints one JSON line and nothing else)")
     ap.add_argument("--sweep-steps", type=int, default=50, help="TDB steps timed per size of the sweep")
+    ap.add_argument("--configs", type=str, default="",
+                    help="only run the named configuration records (comma-separated: c1, c4, c5) and print "
+                         "them as one JSON line")
     ap.add_argument("--samples-as-mode", action="store_true",
                     help="only compare 16 stochastic samples compressed as one order-4 tensor with the same "
                          "samples as independent streams over --plume-steps steps (prints one JSON line)")
@@ -464,6 +618,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.configs:
+        fns = {"c1": _run_c1, "c4": _run_c4, "c5": _run_c5}
+        print(json.dumps({c: fns[c]() for c in args.configs.split(",") if c}), flush=True)
+        return
     if args.samples_as_mode:
         print(json.dumps(_samples_as_mode(10, args.plume_steps)), flush=True)
         return
@@ -521,11 +679,17 @@ def main():
         del snaps
         torch.cuda.empty_cache()
         _log("reactive-flow-shaped stream")
-        extras["plume_c2"] = _run_plume(20, args.plume_steps)
+        extras["plume_c2"] = _guarded("plume", _run_plume, 20, args.plume_steps)
         _log("TDB-1 against TDB-2 (grouped spatial mode) on the reactive-flow-shaped stream")
-        extras["tdb1_vs_tdb2"] = _tdb1_vs_tdb2(10, args.plume_steps)
+        extras["tdb1_vs_tdb2"] = _guarded("tdb1_vs_tdb2", _tdb1_vs_tdb2, 10, args.plume_steps)
         _log("16 stochastic samples as one order-4 tensor against independent streams")
-        extras["samples_as_mode"] = _samples_as_mode(10, 100)
+        extras["samples_as_mode"] = _guarded("samples_as_mode", _samples_as_mode, 10, 100)
+        _log("analytic 64^3 FP64, fused against plain")
+        extras["c1_analytic_fp64"] = _guarded("c1", _run_c1)
+        _log("channel-flow-shaped stream (order 4)")
+        extras["c4_channel"] = _guarded("c4", _run_c4)
+        _log("learned error gate at scale")
+        extras["c5_gate"] = _guarded("c5", _run_c5)
     else:
         del snaps
     cpu = None

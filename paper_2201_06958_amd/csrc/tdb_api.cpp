@@ -571,6 +571,24 @@ tdb_status setup(tdb_ctx* h, const tdb_config* cfg) {
   return TDB_OK;
 }
 
+// Grows the stage-pass partial buffer to hold `elems` entries (a quarter more, for the
+// ranks that follow), after the device has finished every step that used the old one.
+tdb_status ensure_fpart(tdb_ctx* h, long long elems) {
+  if (elems <= h->fpart_elems) return TDB_OK;
+  if (h->fpart) HIPCHK(hipDeviceSynchronize());
+  const long long want = elems + elems / 4;
+  void* q = nullptr;
+  TRY(dalloc(h, &q, (size_t)want * h->celt));
+  if (h->fpart) {
+    auto it = std::find(h->allocs.begin(), h->allocs.end(), h->fpart);
+    if (it != h->allocs.end()) h->allocs.erase(it);
+    HIPCHK(hipFree(h->fpart));
+  }
+  h->fpart = q;
+  h->fpart_elems = want;
+  return TDB_OK;
+}
+
 tdb_status setup_fused(tdb_ctx* h, const std::vector<std::vector<double>>& wh) {
   h->fused = h->p == 3 && h->cfg.path != TDB_PATH_PLAIN;
   if (!h->fused) return TDB_OK;
@@ -580,27 +598,16 @@ tdb_status setup_fused(tdb_ctx* h, const std::vector<std::vector<double>>& wh) {
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lds = 65536;
   // dynamic LDS budget: the device limit minus room for the kernels' static LDS
   h->lds_max = lds - 4096;
-  // partial buffer: enough for the ranks-1 plan and the caps plan
-  // (for the generic and the matrix-core tiles alike: a batch may switch the latter off)
+  // partial buffer: the single-stream plans at ranks 1 and at the caps, with a quarter
+  // more for the ranks between; a plan that needs more (other ranks, or the tiles of a
+  // batch) grows it when its step is built (ensure_fpart)
   int ones[3] = {1, 1, 1};
-  long long tiles = 1, slot = 1;
-  // (single-stream and batch tile choices too: a context may join a batch)
-  for (int variant = 0; variant < 4; ++variant) {
-    h->no_mfma = (variant & 1) == 0;
-    h->batch_owned = (variant & 2) != 0;
-    const PassPlan p1 = plan_pass(h, ones, h->batch_owned), pc = plan_pass(h, h->caps, h->batch_owned);
-    for (const PassPlan* q : {&p1, &pc})
-      if (q->ok) {
-        tiles = std::max(tiles, (long long)q->nt1 * q->nt2);
-        slot = std::max(slot, q->slot);
-      }
+  long long need = 1;
+  for (const int* rr : {(const int*)ones, (const int*)h->caps}) {
+    const PassPlan q = plan_pass(h, rr, false);
+    if (q.ok) need = std::max(need, (long long)q.nt1 * q.nt2 * q.slot);
   }
-  h->no_mfma = false;
-  h->batch_owned = false;
-  long long capslot = (long long)h->caps[0] * h->caps[1] * h->caps[2] + 3LL * 64 * 64 + 64 * (h->N[0] + h->N[1] + h->N[2]);
-  slot = std::max(slot, std::min(capslot, slot * 4));
-  h->fpart_elems = tiles * slot;
-  TRY(dalloc(h, &h->fpart, (size_t)h->fpart_elems * h->celt));
+  TRY(ensure_fpart(h, need));
   for (int n = 0; n < 3; ++n) {
     TRY(dallocT(h, &h->Lq[n], (size_t)TDB_RCAP * TDB_RCAP));
     TRY(dallocT(h, &h->qpart[n], (size_t)((h->N[n] + QR_ROWS - 1) / QR_ROWS) * h->caps[n] * h->caps[n]));
@@ -1334,10 +1341,11 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
   const PassPlan base = plan_pass(h, rl, rl != h->r);
   if (!base.ok) { h->err = "stage-pass tile does not fit in LDS"; return TDB_EUNSUPPORTED; }
   const PassPlan pl = rl == h->r ? base : plan_under(h, h->r, base);
-  if (!pl.ok || (long long)pl.nt1 * pl.nt2 * pl.slot > h->fpart_elems) {
+  if (!pl.ok) {
     h->err = "stage-pass partials do not fit";
     return TDB_EUNSUPPORTED;
   }
+  TRY(ensure_fpart(h, (long long)pl.nt1 * pl.nt2 * pl.slot));
   A.pl = pl;
   A.blocks_pass = pl.nt1 * pl.nt2;
   FPassArgs fa{};
@@ -2100,9 +2108,9 @@ tdb_status batch_plan(tdb_batch_ctx* b, const BatchChoice& c) {
     if (r != TDB_OK) { b->err = "stream " + std::to_string(i) + ": " + h->err; return r; }
     // the plan at the caps must also hold the partials of the caps
     const PassPlan pc = plan_pass(h, h->caps, true);
-    if ((long long)pc.nt1 * pc.nt2 * pc.slot > h->fpart_elems) {
-      b->err = "stream " + std::to_string(i) + ": stage-pass partials at the caps do not fit";
-      return TDB_EUNSUPPORTED;
+    if (ensure_fpart(h, (long long)pc.nt1 * pc.nt2 * pc.slot) != TDB_OK) {
+      b->err = "stream " + std::to_string(i) + ": stage-pass partials at the caps: " + h->err;
+      return TDB_ENOMEM;
     }
     c_pass[i] = A.blocks_pass;
     w_pass[i] = (double)A.pl.T1 * A.pl.T2 * h->N[2];
