@@ -588,6 +588,9 @@ def main():
     ap.add_argument("--plain-streams", type=int, default=16,
                     help="ensemble streams the plain FP64 GPU path is timed on")
     ap.add_argument("--plume-steps", type=int, default=300, help="timed steps of the reactive-flow stream")
+    ap.add_argument("--calibrate-traffic", action="store_true",
+                    help="only run the traffic-counter calibration kernels (a 256 MiB copy, a 256 MiB "
+                         "read-only sum, a gather of one float per 128-byte line) and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (a known-size reference for "
                          "hardware traffic counters)")
@@ -627,6 +630,19 @@ def main():
         return
     if args.tdb1_vs_tdb2:
         print(json.dumps(_tdb1_vs_tdb2(10, args.plume_steps)), flush=True)
+        return
+    if args.calibrate_traffic:
+        # known footprints for FETCH_SIZE / WRITE_SIZE: a copy reads and writes 256 MiB, the
+        # sum reads 256 MiB and writes one value, the gather touches 2 Mi lines of 128 B and
+        # writes 8 MiB
+        x = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+            _ = x.sum()
+            _ = x.view(-1, 32)[:, 0].contiguous()
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy 268435456 B; sum 268435456 B; gather 2097152 lines of 128 B"}))
         return
     if args.scaling_sweep:
         sizes = [int(x) for x in args.scaling_sweep.split(",") if x.strip()]

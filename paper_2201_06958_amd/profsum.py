@@ -169,6 +169,44 @@ def read_pass_traffic(path: str, kernel: str = PASS_KERNEL):
     return None
 
 
+def calibration_text(fetch_db: str, write_db: str, cmd_f: str, cmd_w: str) -> str:
+    """FETCH_SIZE and WRITE_SIZE of the calibration kernels of `bench.py
+    --calibrate-traffic` against their known footprints: the scale each implies for
+    whole-line streaming (copy, read-only sum) and what the one-float-per-128-byte-line
+    gather reads per line at the copy's scale."""
+    fa, wa = _per_kernel(fetch_db), _per_kernel(write_db)
+    MiB = 1024.0 * 1024.0
+
+    def pick(agg, word):
+        ks = [k for k in agg if word in k[0]]
+        if not ks:
+            return None
+        k = max(ks, key=lambda q: max(agg[q]))
+        return max(agg[k])
+    copy_f, copy_w = pick(fa, "copyBuffer"), pick(wa, "copyBuffer")
+    sum_f = pick(fa, "reduce_kernel")
+    # the gather is the element-wise kernel that reads (the buffer's fill only writes);
+    # its write reading is taken for the same kernel and grid
+    gk = [k for k in fa if "elementwise_kernel" in k[0]]
+    gkey = max(gk, key=lambda q: max(fa[q])) if gk else None
+    gat_f = max(fa[gkey]) if gkey else None
+    gat_w = max(wa[gkey]) if gkey and gkey in wa else None
+    out = ["# traffic-counter calibration (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, KiB per dispatch)", "",
+           "commands:", f"    {cmd_f}", f"    {cmd_w}", ""]
+    if copy_f:
+        sc = 256 * MiB / 1024.0 / copy_f
+        out.append(f"copy of 256 MiB:   FETCH {copy_f:12.1f} KiB -> read scale {sc:.4f}; "
+                   f"WRITE {copy_w or 0:12.1f} KiB -> write scale {256 * 1024.0 / copy_w if copy_w else float('nan'):.4f}")
+        if sum_f:
+            out.append(f"sum of 256 MiB:    FETCH {sum_f:12.1f} KiB -> read scale {256 * 1024.0 / sum_f:.4f} "
+                       f"(copy's scale gives {sum_f * sc / 1024.0:.1f} MiB for 256 MiB read)")
+        if gat_f:
+            per_line = gat_f * 1024.0 * sc / (2 * MiB)
+            out.append(f"gather, 1 float per 128 B line (2 Mi lines): FETCH {gat_f:12.1f} KiB -> at the copy's scale "
+                       f"{per_line:.1f} B per line read; WRITE {gat_w or 0:.1f} KiB (8 MiB written)")
+    return "\n".join(out) + "\n"
+
+
 def counters_text(db: str, command: str, match: str) -> str:
     """Per-dispatch averages of every counter of a `--pmc` run for the kernels whose
     name contains `match` (one row per kernel and counter)."""
@@ -193,6 +231,12 @@ def counters_text(db: str, command: str, match: str) -> str:
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
+    cb = sub.add_parser("calib")
+    cb.add_argument("fetch_db")
+    cb.add_argument("write_db")
+    cb.add_argument("--command-fetch", required=True)
+    cb.add_argument("--command-write", required=True)
+    cb.add_argument("--out")
     s = sub.add_parser("stats")
     s.add_argument("db")
     s.add_argument("--command", required=True)
@@ -216,6 +260,8 @@ def main(argv=None):
         text = stats_text(a.db, a.command, a.bench, a.bench_plain)
     elif a.cmd == "counters":
         text = counters_text(a.db, a.command, a.match)
+    elif a.cmd == "calib":
+        text = calibration_text(a.fetch_db, a.write_db, a.command_fetch, a.command_write)
     else:
         text, _ = pmc_text(a.fetch_db, a.write_db, a.command_fetch, a.command_write, a.copy_bytes)
     if a.out:
