@@ -1137,6 +1137,29 @@ __global__ void __launch_bounds__(256) k_ferr(FErrArgs a, CtrlState* ctrl) {
 // Controller of the fused path: the decision up to the removal test; only when that
 // test has to run are the singular values of the core unfoldings formed, one wave per
 // mode, from the Grams kept by the post-step kernel.
+// Whether the symmetric n x n matrix A (LDS, row-major) minus tau I has an eigenvalue
+// at or below zero: its Cholesky factorisation, right-looking, meets a pivot that is not
+// positive. One wave, lanes in step; A is overwritten.
+__device__ __forceinline__ bool wave_shifted_not_pd(double* A, int n, double tau) {
+  const int l = threadIdx.x & 63;
+  for (int t = l; t < n; t += 64) A[t * n + t] -= tau;
+  wave_fence();
+  for (int k = 0; k < n; ++k) {
+    const double piv = A[k * n + k];
+    if (!(piv > 0.0)) return true;
+    const double d = sqrt(piv);
+    for (int i = k + 1 + l; i < n; i += 64) A[i * n + k] /= d;
+    wave_fence();
+    const int m = n - k - 1;
+    for (int t = l; t < m * m; t += 64) {
+      const int i = k + 1 + t / m, j = k + 1 + t % m;
+      if (j <= i) A[i * n + j] -= A[i * n + k] * A[j * n + k];
+    }
+    wave_fence();
+  }
+  return false;
+}
+
 __device__ __forceinline__ void fused_decide(CtrlState* ctrl, const double* const* G, int rmax, const int* skip,
                                              const int* would_skip, const float* yhat) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1162,20 +1185,28 @@ __device__ __forceinline__ void fused_decide(CtrlState* ctrl, const double* cons
   }
   __syncthreads();
   if (!need) return;
+  // The removal test of the controller: some mode whose weakest direction fits the
+  // budget with the error, eps^2 + sigma_min(C_(n))^2 <= B. sigma_min^2 is the smallest
+  // eigenvalue of the core Gram G_n, so the test is whether G_n - (B - eps^2) I has an
+  // eigenvalue at or below zero: whether its Cholesky factorisation meets a pivot that
+  // is not positive. One wave per mode.
+  __shared__ int hit[3];
+  if (threadIdx.x < 3) hit[threadIdx.x] = 0;
+  __syncthreads();
+  const double B = ctrl->gamma_th > 0.0 ? (1.0 - ctrl->gamma_th / 100.0) * ctrl->nu2
+                                        : 0.25 * ctrl->eps_th * ctrl->eps_th;
+  const double tau = B - ctrl->eps * ctrl->eps;
   const int w = threadIdx.x >> 6;
-  if (w < 3 && G[w]) {
+  if (w < 3 && G[w] && tau >= 0.0) {
     const int rn = ctrl->ranks[w];
     double* A = lds + w * (rmax * rmax + 5 * rmax);
-    double* lam = A + rmax * rmax;
-    double* ws = lam + rmax;
     for (int t = threadIdx.x & 63; t < rn * rn; t += 64) A[t] = G[w][t];
     wave_fence();
-    wave_eigvals(A, rn, lam, ws);
-    for (int i = threadIdx.x & 63; i < TDB_RCAP; i += 64)
-      ctrl->sigma[w][i] = i < rn ? sqrt(fmax(lam[i], 0.0)) : 0.0;
+    const bool not_pd = wave_shifted_not_pd(A, rn, tau);
+    if ((threadIdx.x & 63) == 0) hit[w] = not_pd ? 1 : 0;
   }
   __syncthreads();
-  if (threadIdx.x == 0) controller_remove(ctrl);
+  if (threadIdx.x == 0 && (hit[0] || hit[1] || hit[2])) ctrl->decision = DEC_REMOVE;
 }
 
 // One block: fixed-order sum of the error-pass partials, then the controller. A
@@ -1198,8 +1229,21 @@ __device__ __forceinline__ void mirror_ctrl(const FErrArgs& a, const CtrlState* 
   }
 }
 
-__global__ void __launch_bounds__(256) k_ferr_final(FErrArgs a, CtrlState* ctrl) {
+// The controller state copied between global memory and LDS by the whole block in
+// 8-byte words: the decision then reads and writes its few dozen fields in LDS instead
+// of one dependent global round trip each.
+__device__ __forceinline__ void ctrl_copy(CtrlState* dst, const CtrlState* src) {
+  const unsigned long long* q = reinterpret_cast<const unsigned long long*>(src);
+  unsigned long long* d = reinterpret_cast<unsigned long long*>(dst);
+  for (int i = threadIdx.x; i < (int)(sizeof(CtrlState) / 8); i += blockDim.x) d[i] = q[i];
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_ferr_final(FErrArgs a, CtrlState* gctrl) {
   __shared__ double red[16];
+  __shared__ CtrlState cs;
+  ctrl_copy(&cs, gctrl);
+  CtrlState* ctrl = &cs;
   if (ctrl->hold) {
     mirror_ctrl(a, ctrl);
     return;
@@ -1220,6 +1264,8 @@ __global__ void __launch_bounds__(256) k_ferr_final(FErrArgs a, CtrlState* ctrl)
   fused_decide(ctrl, a.G, a.rmax, a.skip, a.would_skip, a.yhat);
   // a discarded step (non-finite data) needs nothing from the host before the next one
   if (threadIdx.x == 0) ctrl->hold = (ctrl->decision != DEC_NONE && ctrl->decision != DEC_NONFINITE) ? 1 : 0;
+  __syncthreads();
+  ctrl_copy(gctrl, ctrl);
   mirror_ctrl(a, ctrl);
 }
 
@@ -1372,11 +1418,12 @@ __global__ void __launch_bounds__(256) kb_ferr_final(const FErrArgs* __restrict_
                                                      BatchSummary* out, unsigned* counter,
                                                      unsigned long long* seq) {
   __shared__ double red[16];
-  __shared__ int held;
+  __shared__ CtrlState cs;
   const int s = blockIdx.x;
-  CtrlState* ctrl = ctab[s];
-  if (threadIdx.x == 0) held = ctrl->hold;
-  __syncthreads();
+  CtrlState* gctrl = ctab[s];
+  ctrl_copy(&cs, gctrl);
+  CtrlState* ctrl = &cs;
+  const int held = ctrl->hold;
   if (!held) {
     const double* part = tab[s].part;
     const int nb = tab[s].gx * tab[s].gy;
@@ -1409,6 +1456,8 @@ __global__ void __launch_bounds__(256) kb_ferr_final(const FErrArgs* __restrict_
       q.eps_pred = ctrl->eps_pred;
       out[s] = q;
     }
+    __syncthreads();
+    ctrl_copy(gctrl, ctrl);
   }
   if (threadIdx.x == 0 && counter) {
     __threadfence_system();
