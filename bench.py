@@ -42,7 +42,13 @@ PROFILE_EVERY = 8          # pass timing sampled on every 8th step of a timed ru
 # against a copy of known size); ignored once the kernel's sources change.
 ENSEMBLE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_ensemble256_fp32.txt")
 PLUME_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_pass_plume512x256x8_fp32.txt")
-ENSEMBLE_PASS = "kb_rpass<float, 1, 4, true>"   # the column-block pass, FP32 products, float4 fibers
+def _pass_kernel_name(plan, flavor=1):
+    """The stage-pass kernel a batch's plan runs (FP32 products: flavor 1; BF16-split: 2)."""
+    if plan["pass"] == "matrix-core-columns":
+        return f"kb_rpass<float, {flavor}, 4, true, {plan['pass_cols']}>"
+    if plan["pass"] == "matrix-core-tiles":
+        return f"kb_mpass<float, {flavor}>"
+    return "kb_fpass<float, float>"
 PLUME_PASS = "k_mpass_w16<float, 1>"
 METRIC = "snapshots/s ingested + HBM GB/s vs plain FP64 GPU at <=1e-6 rel err"
 
@@ -672,7 +678,8 @@ def main():
     elems = desc["elements_per_step"]
     step_bytes = 5.0 * 4.0 * elems     # two stages x (V_k+1, V_k), one error pass
     from paper_2201_06958_amd.profsum import read_pass_traffic
-    traffic = read_pass_traffic(ENSEMBLE_TRAFFIC_FILE, ENSEMBLE_PASS)
+    pass_name = _pass_kernel_name(prof["plan"])
+    traffic = read_pass_traffic(ENSEMBLE_TRAFFIC_FILE, pass_name)
     ring = total * elems * 4
     extras = {}
     if not args.no_extras:
@@ -726,7 +733,7 @@ def main():
                                             if traffic else None),
                      "kernel": "column-block stage projection pass, one Heun stage of all 256 streams "
                                "(matrix cores, FP32 products)",
-                     "kernel_name": ENSEMBLE_PASS,
+                     "kernel_name": pass_name,
                      "avg_launch_us": pav * 1e6, "launches": pj["launches"],
                      "timed_every_nth_step": PROFILE_EVERY,
                      "algorithmic_bytes_per_launch": pj["bytes_per_launch"],

@@ -20,9 +20,14 @@ def test_pmc_scaling_and_record(tmp_path):
     # the copy of 1 MiB reads as 512 KiB on FETCH and 1024 KiB on WRITE -> scales 2 and 1
     f = tmp_path / "f.db"
     w = tmp_path / "w.db"
-    _counter_db(f, [(copy, 4096, 512.0), (copy, 64, 1.0), (kpass, 1000, 100.0), (kpass, 1000, 110.0)])
-    _counter_db(w, [(copy, 4096, 1024.0), (copy, 64, 1.0), (kpass, 1000, 20.0), (kpass, 1000, 20.0)])
+    # eight dispatches of the pass (a record), four of a batch pass seen only while a
+    # plan was being timed (no record)
+    ktune = "void tdb::kb_rpass<float, 1, 4, true, 32>(tdb::FPassArgs)"
+    _counter_db(f, [(copy, 4096, 512.0), (copy, 64, 1.0)] + [(kpass, 1000, 100.0), (kpass, 1000, 110.0)] * 4
+                + [(ktune, 500, 50.0)] * 4)
+    _counter_db(w, [(copy, 4096, 1024.0), (copy, 64, 1.0)] + [(kpass, 1000, 20.0)] * 8 + [(ktune, 500, 5.0)] * 4)
     text, recs = profsum.pmc_text(str(f), str(w), "cmd f", "cmd w", 1024 * 1024)
+    assert "kb_rpass<float, 1, 4, true, 32>" not in recs
     rec = recs["k_mpass_w16<float, 1>"]
     assert abs(rec["read_scale"] - 2.0) < 1e-12 and abs(rec["write_scale"] - 1.0) < 1e-12
     assert abs(rec["read_bytes"] - 105.0 * 2 * 1024) < 1e-6
