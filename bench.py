@@ -610,6 +610,9 @@ def main():
     ap.add_argument("--samples-as-mode", action="store_true",
                     help="only compare 16 stochastic samples compressed as one order-4 tensor with the same "
                          "samples as independent streams over --plume-steps steps (prints one JSON line)")
+    ap.add_argument("--plume-only", action="store_true",
+                    help="only run the reactive-flow-shaped stream (512 x 256 x 8, FP32) over --plume-steps steps "
+                         "(prints its record as one JSON line; with --calibrate-copy the 256 MiB copy first)")
     ap.add_argument("--tdb1-vs-tdb2", action="store_true",
                     help="only compare TDB-1 (third order) with TDB-2 (order 2, grouped spatial mode) on the "
                          "reactive-flow-shaped stream over --plume-steps steps (prints one JSON line)")
@@ -627,6 +630,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.plume_only:
+        if args.calibrate_copy:
+            x = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+            y = torch.empty_like(x)
+            for _ in range(3):
+                y.copy_(x)
+            torch.cuda.synchronize()
+            del x, y
+        print(json.dumps(_run_plume(20, args.plume_steps)), flush=True)
+        return
     if args.configs:
         fns = {"c1": _run_c1, "c4": _run_c4, "c5": _run_c5}
         print(json.dumps({c: fns[c]() for c in args.configs.split(",") if c}), flush=True)
