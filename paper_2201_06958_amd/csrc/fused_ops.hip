@@ -285,6 +285,155 @@ __global__ void __launch_bounds__(256) k_fmprep(FFinishArgs a, CtrlState* ctrl) 
 }
 
 // ---------------------------------------------------------------- finish a stage
+// Per-lane choice among three per-mode values. The argument blocks sit in global
+// memory (a batch's table) or the kernel arguments: indexing them with a lane-varying
+// mode would turn every field access into a dependent vector load, so each field is
+// read at a constant index (a scalar load) and chosen per lane.
+template <typename V>
+__device__ __forceinline__ V sel3(int n, V v0, V v1, V v2) {
+  return n == 0 ? v0 : (n == 1 ? v1 : v2);
+}
+
+// One pass of a row block over FIN_EPT * blockDim.x consecutive elements from `base`
+// of the flat order over the rows of the three bases (mode by mode, r_n entries a
+// row). Element f needs the r_n entries of its row of U*, which lie within rmax - 1
+// places of f in that order: the pass stages its elements and that halo into LDS (at
+// most (FIN_EPT + 1) * blockDim.x values, ranks being at most 64), with every operand
+// of the pass (and, in the first pass, the M_n) loaded in one round trip before any
+// LDS store, instead of r_n dependent loads per element. The loads are unconditional,
+// from indices clamped into range, so that no branch separates them; what a lane loads
+// past the end is never used.
+template <typename T, bool LOADM, int ST>
+__device__ __forceinline__ void fin_rows_pass(const FFinishArgs& a, long long base, long long tot,
+                                              double* const* Ml, const int* mcnt, double* tile) {
+  const int nt = (int)blockDim.x, tid = (int)threadIdx.x;
+  const int halo = a.rmax - 1;
+  const int tw = FIN_EPT * nt + 2 * halo;
+  const int r0 = a.r[0], r1 = a.r[1], r2 = a.r[2];
+  const long long L0 = a.N[0] * r0, L01 = L0 + a.N[1] * r1;
+  const int ld0 = a.ldU[0], ld1 = a.ldU[1], ld2 = a.ldU[2];
+  const bool act0 = r0 < a.N[0], act1 = r1 < a.N[1], act2 = r2 < a.N[2];
+  // flat index f -> mode n, index q within the mode, row i, column j, entry e of U_n
+  auto locate = [&](long long f, int& n, long long& q, long long& i, int& j, long long& e) {
+    n = f < L0 ? 0 : (f < L01 ? 1 : 2);
+    q = f - sel3<long long>(n, 0, L0, L01);
+    const int rn = sel3(n, r0, r1, r2);
+    i = q < 2147483647LL ? (long long)((unsigned)q / (unsigned)rn) : q / rn;
+    j = (int)(q - i * rn);
+    e = i * sel3(n, ld0, ld1, ld2) + j;
+  };
+  const double* U00 = a.U0[0];
+  const double* U01 = a.U0[1];
+  const double* U02 = a.U0[2];
+  const double* Ust0 = ST == 1 ? U00 : a.Us[0];
+  const double* Ust1 = ST == 1 ? U01 : a.Us[1];
+  const double* Ust2 = ST == 1 ? U02 : a.Us[2];
+  const int c01 = mcnt[0] + mcnt[1], call = c01 + mcnt[2];
+  double mv[LOADM ? FIN_MU : 1];
+  if (LOADM) {
+#pragma unroll
+    for (int u = 0; u < FIN_MU; ++u) {
+      const int t = min(u * nt + tid, call - 1);
+      const int n = t < mcnt[0] ? 0 : (t < c01 ? 1 : 2);
+      mv[u] = *gmem(sel3<const double*>(n, a.M[0], a.M[1], a.M[2]) + (t - sel3(n, 0, mcnt[0], c01)));
+    }
+  }
+  double tv[FIN_EPT + 1];
+#pragma unroll
+  for (int u = 0; u <= FIN_EPT; ++u) {
+    const long long f = min(max(base - halo + u * nt + tid, 0LL), tot - 1);
+    int n, j;
+    long long q, i, e;
+    locate(f, n, q, i, j, e);
+    tv[u] = *gmem(sel3(n, Ust0, Ust1, Ust2) + e);
+  }
+  double hv[FIN_EPT], av[FIN_EPT], bv[FIN_EPT];
+#pragma unroll
+  for (int u = 0; u < FIN_EPT; ++u) {
+    const long long t = min(base + u * nt + tid, tot - 1);
+    int n, j;
+    long long q, i, e;
+    locate(t, n, q, i, j, e);
+    // (a mode kept at full rank has no H_n: its lanes read U_n instead and ignore it)
+    const double* hp = sel3(n, act0, act1, act2) ? sel3(n, a.H[0], a.H[1], a.H[2]) + q : sel3(n, U00, U01, U02) + e;
+    hv[u] = *gmem(hp);
+    if (ST == 1) {
+      av[u] = *gmem(sel3(n, a.w[0], a.w[1], a.w[2]) + i);
+      bv[u] = 0.0;
+    } else {
+      av[u] = *gmem(sel3<const double*>(n, a.kU[0], a.kU[1], a.kU[2]) + e);
+      bv[u] = *gmem(sel3(n, U00, U01, U02) + e);
+    }
+  }
+  if (LOADM) {
+#pragma unroll
+    for (int u = 0; u < FIN_MU; ++u) {
+      const int t = u * nt + tid;
+      if (t < call) {
+        const int n = t < mcnt[0] ? 0 : (t < c01 ? 1 : 2);
+        sel3(n, Ml[0], Ml[1], Ml[2])[t - sel3(n, 0, mcnt[0], c01)] = mv[u];
+      }
+    }
+    // the rest of the M_n (rank caps above about 26 in every mode)
+    for (int t = FIN_MU * nt + tid; t < call; t += nt) {
+      const int n = t < mcnt[0] ? 0 : (t < c01 ? 1 : 2);
+      const int e = t - sel3(n, 0, mcnt[0], c01);
+      sel3(n, Ml[0], Ml[1], Ml[2])[e] = sel3<const double*>(n, a.M[0], a.M[1], a.M[2])[e];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u <= FIN_EPT; ++u) {
+    const int x = u * nt + tid;
+    if (x < tw) tile[x] = tv[u];
+  }
+  __syncthreads();
+  const double inv_dt = a.dscale;   // 1/dt for a difference quotient, 1 for a given derivative
+  const double dt = a.dt;
+#pragma unroll
+  for (int u = 0; u < FIN_EPT; ++u) {
+    const long long t = base + u * nt + tid;
+    if (t < tot) {
+      int n, j;
+      long long q, i, e;
+      locate(t, n, q, i, j, e);
+      const int rn = sel3(n, r0, r1, r2);
+      const int x = u * nt + tid + halo;   // element t in the tile
+      double ud = 0.0;
+      if (sel3(n, act0, act1, act2)) {
+        const double* M = sel3(n, Ml[0], Ml[1], Ml[2]);
+        const double* ur = tile + x - j;
+        double s = hv[u];
+        for (int k = 0; k < rn; ++k) s -= ur[k] * M[k * rn + j];
+        ud = s * inv_dt;
+      }
+      if (ST == 1) {
+        *gmem(sel3(n, a.kU[0], a.kU[1], a.kU[2]) + e) = ud;
+        const double us = tile[x] + dt * ud;
+        *gmem(sel3(n, a.Us[0], a.Us[1], a.Us[2]) + e) = us;
+        *gmem(sel3(n, static_cast<T*>(a.B[0]), static_cast<T*>(a.B[1]), static_cast<T*>(a.B[2])) + q) =
+            (T)(av[u] * us);
+      } else {
+        *gmem(sel3(n, a.U0[0], a.U0[1], a.U0[2]) + e) = bv[u] + 0.5 * dt * (av[u] + ud);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// All passes of one row block.
+template <typename T, int ST>
+__device__ __forceinline__ void fin_rows(const FFinishArgs& a, long long tot, long long bx, double* const* Ml,
+                                         const int* mcnt, double* tile) {
+  const long long span = (long long)FIN_EPT * blockDim.x;
+  const long long step = (long long)a.rowblocks * span;
+  long long base = bx * span;
+  if (mcnt[0] + mcnt[1] + mcnt[2] > 0) {
+    fin_rows_pass<T, true, ST>(a, base, tot, Ml, mcnt, tile);
+    base += step;
+  }
+  for (; base < tot; base += step) fin_rows_pass<T, false, ST>(a, base, tot, Ml, mcnt, tile);
+}
+
 // Blocks [0, rowblocks): rows of every mode: U_dot = (H - U M)/dt, Heun update and,
 // in stage 1, the weighted basis B_n = W_n U* of the next stage.
 // Blocks [rowblocks, rowblocks + 3) (stage 1 only): pseudo-inverse P_n at the stage
@@ -298,9 +447,17 @@ __device__ __forceinline__ void ffinish_body(const FFinishArgs& a, int stage, Ct
   if (ctrl->hold || (stage == 2 && ctrl->numeric)) return;
   const double inv_dt = a.dscale;   // 1/dt for a difference quotient, 1 for a given derivative
   if (ROLE == ROLE_ROWS || (ROLE == ROLE_ALL && (int)bx < a.rowblocks)) {
+    long long tot = 0;
+    for (int n = 0; n < 3; ++n) tot += a.N[n] * a.r[n];
+    // a batch sizes the grid for the rank caps: blocks past the current ranks' rows
+    // leave before loading anything (block-uniform, ahead of every barrier)
+    const long long span = (long long)FIN_EPT * blockDim.x;
+    if ((long long)bx * span >= tot) return;
     // M_n (r_n x r_n) into LDS: formed once per stage by k_fmprep, or here (a single
     // stream, where the extra launch would cost more than the repeated small product)
     double* Ml[3];
+    double* tile;                // the rows of the pass's elements (see fin_rows_pass)
+    int mcnt[3] = {0, 0, 0};     // M_n values still to load
     if (ROLE == ROLE_ALL && a.m_inline) {   // (a batch forms M_n in its own kernel)
       const double* cd = stage == 1 ? a.kC : a.Cdot2;   // this stage's C_dot
       const int csz = a.r[0] * a.r[1] * a.r[2];
@@ -347,6 +504,7 @@ __device__ __forceinline__ void ffinish_body(const FFinishArgs& a, int stage, Ct
       int msum = 0;
       for (int n = 0; n < 3; ++n) msum += a.r[n] * a.r[n];
       double* part = lds + moff + msum;
+      tile = part + FIN_PART;
       for (int n = 0; n < 3; ++n) {
         Ml[n] = lds + moff;
         const int rr = a.r[n];
@@ -357,45 +515,19 @@ __device__ __forceinline__ void ffinish_body(const FFinishArgs& a, int stage, Ct
         }
         moff += rr * rr;
       }
+      __syncthreads();
     } else {
+      // the M_n arrive with the first pass's operands (one round trip for all of them)
       int off = 0;
       for (int n = 0; n < 3; ++n) {
         Ml[n] = lds + off;
-        const int rr = a.r[n];
-        if (rr < a.N[n])
-          g2l(Ml[n], a.M[n], rr * rr);
-        off += rr * rr;
+        mcnt[n] = a.r[n] < a.N[n] ? a.r[n] * a.r[n] : 0;
+        off += a.r[n] * a.r[n];
       }
+      tile = lds + off;
     }
-    __syncthreads();
-    long long tot = 0;
-    for (int n = 0; n < 3; ++n) tot += a.N[n] * a.r[n];
-    for (long long t = (long long)bx * blockDim.x + threadIdx.x; t < tot;
-         t += (long long)a.rowblocks * blockDim.x) {
-      long long q = t;
-      int n = 0;
-      while (q >= a.N[n] * a.r[n]) { q -= a.N[n] * a.r[n]; ++n; }
-      const int rn = a.r[n], ld = a.ldU[n];
-      const long long i = q / rn;
-      const int j = (int)(q - i * rn);
-      const double* Ust = stage == 1 ? a.U0[n] : a.Us[n];
-      double ud = 0.0;
-      if (rn < a.N[n]) {
-        double s = a.H[n][q];
-        const double* M = Ml[n];
-        const double* ur = Ust + i * ld;
-        for (int k = 0; k < rn; ++k) s -= ur[k] * M[k * rn + j];
-        ud = s * inv_dt;
-      }
-      if (stage == 1) {
-        a.kU[n][i * ld + j] = ud;
-        const double us = a.U0[n][i * ld + j] + a.dt * ud;
-        a.Us[n][i * ld + j] = us;
-        static_cast<T*>(a.B[n])[q] = (T)(a.w[n][i] * us);
-      } else {
-        a.U0[n][i * ld + j] += 0.5 * a.dt * (a.kU[n][i * ld + j] + ud);
-      }
-    }
+    if (stage == 1) fin_rows<T, 1>(a, tot, bx, Ml, mcnt, tile);
+    else fin_rows<T, 2>(a, tot, bx, Ml, mcnt, tile);
     return;
   }
   if (ROLE == ROLE_ROWS) return;

@@ -1275,7 +1275,9 @@ size_t small_lds(const tdb_ctx* h, const int* rl, bool* core_in_lds, bool m_inli
   long long msum = 0;
   for (int n = 0; n < h->p; ++n) msum += (long long)rl[n] * rl[n];
   // finish rows stage the three M_n (and, forming them inline, C_dot and the three P_n)
-  const size_t rows = (size_t)msum * 8 + (m_inline ? (size_t)csz * 8 + 3 * (size_t)csz * h->celt + 8 + FIN_PART * 8 : 0);
+  // and a tile of FIN_EPT * 256 row elements with rm - 1 on either side
+  const size_t rows = (size_t)msum * 8 + (m_inline ? (size_t)csz * 8 + 3 * (size_t)csz * h->celt + 8 + FIN_PART * 8 : 0) +
+                      (FIN_EPT * 256 + 2 * (size_t)rm) * 8;
   const size_t base = std::max<size_t>((3 * (size_t)rm * rm + 5 * (size_t)rm + 64 + FQR_GP) * 8, rows);
   *core_in_lds = base + (size_t)csz * 8 <= (size_t)h->lds_max;
   return base + (*core_in_lds ? (size_t)csz * 8 : 0);
@@ -1399,7 +1401,8 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
   ga.dscale = dscale;
   long long rows = 0;
   for (int n = 0; n < 3; ++n) rows += h->N[n] * rl[n];
-  ga.rowblocks = (int)std::max<long long>(1, std::min<long long>(1024, (rows + 255) / 256));
+  const long long span = (long long)FIN_EPT * 256;   // row elements of one block pass
+  ga.rowblocks = (int)std::max<long long>(1, std::min<long long>(1024, (rows + span - 1) / span));
   ga.Cs = h->Cs;
   ga.kC = h->kC;
   ga.Cdot2 = h->Cdot2;
@@ -2126,9 +2129,11 @@ tdb_status batch_plan(tdb_batch_ctx* b, const BatchChoice& c) {
     c_err[i] = A.blocks_err;
     w_err[i] = b->err_r1c ? (double)h->N[0] : 1.0;
     {
+      // the three M_n and the row tile (FIN_EPT * 256 elements with rmax - 1 on either side)
       long long msum = 0;
       for (int k = 0; k < 3; ++k) msum += (long long)h->caps[k] * h->caps[k];
-      b->lds_rows = std::max(b->lds_rows, (size_t)msum * 8);
+      const size_t tile = FIN_EPT * 256 + 2 * (size_t)max_rank_of(h->caps, 3);
+      b->lds_rows = std::max(b->lds_rows, ((size_t)msum + tile) * 8);
       bool sall = false;
       b->lds_exp = std::max(b->lds_exp, post_exp_lds(h, h->caps, A.pa.eblocks, &sall));
     }
