@@ -971,7 +971,7 @@ __device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, 
         // (U L^-T)[q][j] = sum_{k <= j} U[q][k] L^-1[j][k], four entries per thread at a time
         for (int t0 = threadIdx.x; t0 < nsum; t0 += 4 * (int)blockDim.x) {
           // entry u: row offset ur, L^-1 row offset lr, column jj, output index on
-          int ur[4], lr[4], jj[4], on[4], mm[4], qq[4];
+          int ur[4], lr[4], jj[4], on[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int t = min(t0 + u * (int)blockDim.x, nsum - 1);
@@ -979,8 +979,6 @@ __device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, 
             const int e = t - (m == 0 ? 0 : (m == 1 ? e0 : e0 + e1));
             const int rm = m == 0 ? q0 : (m == 1 ? q1 : q2);
             const int q = e / rm, j = e - q * rm;
-            mm[u] = m;
-            qq[u] = q;
             jj[u] = j;
             ur[u] = (m == 0 ? oU0 : (m == 1 ? oU1 : oU2)) + q * rm;
             lr[u] = (m == 0 ? oL0 : (m == 1 ? oL1 : oL2)) + j * rm;
@@ -994,18 +992,11 @@ __device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, 
               if (k <= jj[u]) sv[u] += base[ur[u] + k] * base[lr[u] + k];
           }
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int t = t0 + u * (int)blockDim.x;
-            if (t < nsum) {
-              base[on[u]] = sv[u];
-              const int m = mm[u];
-              double* Uw = m == 0 ? a.Uw[0] : (m == 1 ? a.Uw[1] : a.Uw[2]);
-              const int ia = m == 0 ? ia0 : (m == 1 ? ia1 : ia2);
-              const int ld = m == 0 ? ld0 : (m == 1 ? ld1 : ld2);
-              Uw[(long long)(ia + qq[u]) * ld + jj[u]] = sv[u];
-            }
-          }
+          for (int u = 0; u < 4; ++u)
+            if (t0 + u * (int)blockDim.x < nsum) base[on[u]] = sv[u];
         }
+        // (the normalised rows go back to U_n with the other stores below: a barrier
+        // after global stores would wait for them)
         __syncthreads();
       }
       // the normalised rows
@@ -1018,9 +1009,13 @@ __device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, 
         const double* Ur = base + (m == 0 ? oR0 : (m == 1 ? oR1 : oR2));
         const double* w = a.w[m] + ia;
         T* B = static_cast<T*>(a.B[m]) + (long long)ia * rm;
+        const int ld = m == 0 ? ld0 : (m == 1 ? ld1 : ld2);
+        double* Uw = norm ? a.Uw[m] + (long long)ia * ld : nullptr;
         for (int t = threadIdx.x; t < n_e; t += blockDim.x) {
           const int q = t / rm;
-          B[t] = (T)(w[q] * Ur[t]);
+          const double u = Ur[t];
+          B[t] = (T)(w[q] * u);
+          if (norm) Uw[(long long)q * ld + (t - q * rm)] = u;
         }
         if (m == 0) {
           T* U1c = static_cast<T*>(a.U1c) + (long long)ia * rm;

@@ -43,9 +43,11 @@ constexpr int RP_PS = 20;   // row stride (floats) of 16-entry operand rows in L
 int rpass_cols_for(int n3c) { return n3c == 4 ? 64 : 32; }
 bool rpass_cols_ok(int n3c, int t2) { return t2 == 32 || (t2 == 64 && n3c == 4); }
 
-// LDS regions (float offsets). Region X = [0, oB1) holds D and the H1 blocks during the
-// subtiles, the raw copies of B2's rows, P1, P2 and B3 before them and F2' (as A for
-// H2) and F3 after them.
+// LDS regions (float offsets). Region X = [0, oB2) holds the raw copies of B2's rows, P1
+// and B3 before the subtiles, D and the H1 blocks during them, and F2' (as A for H2) and
+// F3 after them. B2^T and B3 stay for the whole block. Region S holds B1 and P1' during
+// the subtiles and P2' after them (P2' is formed from global memory once the subtiles
+// are done), so that a block fits twice in a compute unit's LDS at rank caps up to 24.
 struct RpLayout {
   int nfc;                                       // 16-entry chunks of f = a*N3 + c
   int oHp, oF3, oB1, oB2, oP1, oP2, oB3, total;
@@ -58,19 +60,21 @@ __host__ __device__ inline RpLayout rp_layout(int T2, int r1, int r2, int N3) {
   const int d = N3 * 16 * DS;
   const int hp = N3 * nb2 * nb1 * 16 * RP_PS;
   const int fin = L.nfc * T2 * RP_PS + r1 * r2 * N3;
-  const int raw = T2 * r2 + 2 * r1 * r2 * N3 + N3 * N3;   // r3 <= N3
+  const int raw = T2 * r2 + r1 * r2 * N3 + N3 * N3;   // r3 <= N3
   int x = d + hp;
   x = x > fin ? x : fin;
   x = x > raw ? x : raw;
   x = (x + 3) & ~3;
   L.oHp = d;
   L.oF3 = L.nfc * T2 * RP_PS;
-  L.oB1 = x;
-  L.oB2 = L.oB1 + nb1 * 16 * RP_PS;
-  L.oP1 = L.oB2 + nb2 * 16 * DS;
-  L.oP2 = L.oP1 + N3 * nb2 * nb1 * 16 * RP_PS;
-  L.oB3 = L.oP2 + L.nfc * nb2 * 16 * RP_PS;
-  L.total = L.oB3 + N3 * N3;
+  L.oB2 = x;
+  L.oB3 = L.oB2 + nb2 * 16 * DS;
+  const int oS = L.oB3 + ((N3 * N3 + 3) & ~3);
+  L.oB1 = oS;
+  L.oP1 = L.oB1 + nb1 * 16 * RP_PS;
+  L.oP2 = oS;
+  const int s1 = nb1 * 16 * RP_PS + N3 * nb2 * nb1 * 16 * RP_PS, s2 = L.nfc * nb2 * 16 * RP_PS;
+  L.total = oS + (s1 > s2 ? s1 : s2);
   return L;
 }
 
@@ -264,38 +268,34 @@ __device__ __forceinline__ void rpass_body(const FPassArgs& a, int bx) {
   load_sub(ra, 0);
   if constexpr (DEPTH == 2) load_sub(rb, 1);
 
-  // ---- the block's B2 rows, P1, P2 and B3, copied as they are into region X with all
-  // loads of a round in flight together, then formed into the operand rows: B2^T and
-  // the pseudo-inverses folded with B3 (zero-padded)
+  // ---- the block's B2 rows, P1 and B3, copied as they are into region X with all
+  // loads of a round in flight together, then formed into the operand rows: B2^T and P1
+  // folded with B3 (zero-padded)
   const int nB2 = ncol * r2, nP = r1 * r2 * r3, nB3 = N3 * r3;
   float* rB2 = sm;
   float* rP1 = rB2 + nB2;
-  float* rP2 = rP1 + nP;
-  float* rB3 = rP2 + nP;
+  float* rB3 = rP1 + nP;
   {
     const TDB_GLOBAL float* gB2 = gmem(static_cast<const float*>(a.B2)) + i2_0 * r2;
     const TDB_GLOBAL float* gP1 = gmem(static_cast<const float*>(a.P1));
-    const TDB_GLOBAL float* gP2 = gmem(static_cast<const float*>(a.P2));
     const TDB_GLOBAL float* gB3 = gmem(static_cast<const float*>(a.B3));
-    const int nP1 = a.need_h1 ? nP : 0, nP2 = a.need_h2 ? nP : 0;
+    const int nP1 = a.need_h1 ? nP : 0;
     const int nmax = max(max(nB2, nP), nB3);
     for (int base = 0; base < nmax; base += 4 * 512) {
-      float v[4][4];
+      float v[3][4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int t = base + tid + u * 512;
         v[0][u] = gB2[min(t, nB2 - 1)];
         v[1][u] = nP1 ? gP1[min(t, nP1 - 1)] : 0.0f;
-        v[2][u] = nP2 ? gP2[min(t, nP2 - 1)] : 0.0f;
-        v[3][u] = gB3[min(t, nB3 - 1)];
+        v[2][u] = gB3[min(t, nB3 - 1)];
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int t = base + tid + u * 512;
         if (t < nB2) rB2[t] = v[0][u];
         if (t < nP1) rP1[t] = v[1][u];
-        if (t < nP2) rP2[t] = v[2][u];
-        if (t < nB3) rB3[t] = v[3][u];
+        if (t < nB3) rB3[t] = v[2][u];
       }
     }
   }
@@ -314,17 +314,6 @@ __device__ __forceinline__ void rpass_body(const FPassArgs& a, int bx) {
     if (a.need_h1 && aa < r1 && b < r2)
       for (int c2 = 0; c2 < r3; ++c2) v += rB3[c * r3 + c2] * rP1[(b * r3 + c2) * r1 + aa];
     P1T[rest * RP_PS + bl] = v;
-  }
-  // P2'[f = a*N3 + c][b] = sum_c2 B3[c][c2] P2[(a*r3 + c2)][b], columns b of chunk fc
-  for (int t = tid; t < L.nfc * NB2 * 256; t += 512) {
-    const int fl = t & 15, rest = t >> 4;
-    const int b = rest % (NB2 * 16), fc = rest / (NB2 * 16), f = 16 * fc + fl;
-    float v = 0.0f;
-    if (a.need_h2 && b < r2 && f < r1 * N3) {
-      const int ai = f / N3, c = f % N3;
-      for (int c2 = 0; c2 < r3; ++c2) v += rB3[c * r3 + c2] * rP2[(ai * r3 + c2) * r2 + b];
-    }
-    P2T[rest * RP_PS + fl] = v;
   }
   // region X is read above and written by the first subtile
   __syncthreads();
@@ -399,9 +388,8 @@ __device__ __forceinline__ void rpass_body(const FPassArgs& a, int bx) {
   } else {
     for (int s = 0; s < nsub; ++s) subtile(ra, s);
   }
-  // the last H1 rows read region X
+  // the last H1 rows read region X, the last subtile B1 and P1' (region S)
   __syncthreads();
-
   // ---- F3 from the F2'^T registers; F2' into the A rows of H2 (padded K entries zero)
   {
     const int K2 = r1 * N3;
@@ -434,6 +422,47 @@ __device__ __forceinline__ void rpass_body(const FPassArgs& a, int bx) {
           for (int ib = 0; ib < NBC; ++ib)
 #pragma unroll
             for (int i = 0; i < 4; ++i) F[(16 * ib + 4 * g + i) * RP_PS] = acc2[gq][ib][i];
+        }
+      }
+    }
+  }
+  // P2'[f = a*N3 + c][b] = sum_c2 B3[c][c2] P2[(a*r3 + c2)][b] into region S: one thread
+  // per (a, b) loads its r3 entries of P2 (all in flight, from clamped indices) once the
+  // F2' registers are free
+  constexpr int P2U = 2;   // (a, b) pairs per thread: r1 r2 <= 2 * 512 for ranks up to 32
+  const int nab = a.need_h2 ? r1 * r2 : 0;
+  float p2r[P2U][N3M];
+  {
+    const TDB_GLOBAL float* gP2 = gmem(static_cast<const float*>(a.P2));
+#pragma unroll
+    for (int u = 0; u < P2U; ++u) {
+      const int t = min(tid + 512 * u, max(nab - 1, 0));
+      const int ai = t / r2, b = t - (t / r2) * r2;
+#pragma unroll
+      for (int c2 = 0; c2 < N3M; ++c2) p2r[u][c2] = nab ? gP2[(ai * r3 + min(c2, r3 - 1)) * r2 + b] : 0.0f;
+    }
+  }
+
+  // the padding of P2' (and all of it when H2 is not needed), while the loads are in flight
+  for (int t = tid; t < L.nfc * NB2 * 256; t += 512) {
+    const int fl = t & 15, rest = t >> 4;
+    const int b = rest % (NB2 * 16), f = 16 * (rest / (NB2 * 16)) + fl;
+    if (!(nab && b < r2 && f < r1 * N3)) P2T[rest * RP_PS + fl] = 0.0f;
+  }
+#pragma unroll
+  for (int u = 0; u < P2U; ++u) {
+    const int t = tid + 512 * u;
+    if (t < nab) {
+      const int ai = t / r2, b = t - (t / r2) * r2;
+#pragma unroll
+      for (int c = 0; c < N3M; ++c) {
+        if (c < N3) {
+          float v = 0.0f;
+#pragma unroll
+          for (int c2 = 0; c2 < N3M; ++c2)
+            if (c2 < r3) v += B3s[c * r3 + c2] * p2r[u][c2];
+          const int f = ai * N3 + c;
+          P2T[((f >> 4) * NB2 * 16 + b) * RP_PS + (f & 15)] = v;
         }
       }
     }

@@ -1308,7 +1308,7 @@ tdb_status build_post_args(tdb_ctx* h, const int* rl, FPostArgs& pa, size_t& lds
   const long long etot = (long long)rl[0] * h->N[1] * h->N[2];
   // a batch gives each expansion block four times the work (fewer blocks, each of which
   // stages T3 and the factors once)
-  const long long eper = rl != h->r ? 1024 : 256;
+  const long long eper = rl != h->r ? 2048 : 256;
   pa.eblocks = (int)std::max<long long>(1, std::min<long long>(std::min<long long>(256, h->N[1]), (etot + eper - 1) / eper));
   bool sall = false;
   const size_t elds = post_exp_lds(h, rl, pa.eblocks, &sall);
