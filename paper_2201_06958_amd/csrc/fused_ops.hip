@@ -23,33 +23,6 @@ namespace tdb {
 typedef double md4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------- reduction
-// Sum of count values p[k*stride] in a fixed order with 8 independent partial sums
-// (so that 8 loads are in flight per thread); deterministic for a given count.
-template <typename T>
-__device__ __forceinline__ double sum_strided(const T* __restrict__ p, long long stride, int count) {
-  double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0, s6 = 0, s7 = 0;
-  int k = 0;
-  for (; k + 8 <= count; k += 8) {
-    const T* q = p + (long long)k * stride;
-    s0 += (double)q[0];
-    s1 += (double)q[stride];
-    s2 += (double)q[2 * stride];
-    s3 += (double)q[3 * stride];
-    s4 += (double)q[4 * stride];
-    s5 += (double)q[5 * stride];
-    s6 += (double)q[6 * stride];
-    s7 += (double)q[7 * stride];
-  }
-  for (; k < count; ++k) {
-    const double v = (double)p[(long long)k * stride];
-    switch (k & 7) {
-      case 0: s0 += v; break; case 1: s1 += v; break; case 2: s2 += v; break; case 3: s3 += v; break;
-      case 4: s4 += v; break; case 5: s5 += v; break; case 6: s6 += v; break; default: s7 += v; break;
-    }
-  }
-  return ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7));
-}
-
 // Sums the per-tile partials in a fixed order (FP64) into H_n and C_dot, and applies
 // the Heun update to the core (stage 1: k = C_dot/dt, C* = C + dt k; stage 2:
 // C <- C + dt/2 (k + C_dot/dt)). Each output is summed by L lanes of one wave (lane
@@ -79,66 +52,104 @@ __device__ __forceinline__ void freduce_body(const FReduceArgs& a, int stage, Ct
   const long long oH2 = (long long)a.T1 * a.r1, oH3 = oH2 + (long long)a.T2 * a.r2;
   const long long oC = oH3 + (long long)a.N3 * a.r3;
   const double inv_dt = a.dscale;   // 1/dt for a difference quotient, 1 for a given derivative
-  // e4 is a multiple of 64 and so is the stride: every wave runs the same trip count
-  for (long long t = (long long)bx * blockDim.x + threadIdx.x; t < e4; t += (long long)gx * blockDim.x) {
-    int kind, L;
-    long long u;
-    if (t < e1) { kind = 0; L = L1; u = t; }
-    else if (t < e2) { kind = 1; L = L2; u = t - e1; }
-    else if (t < e3) { kind = 2; L = L3; u = t - e2; }
-    else { kind = 3; L = L3; u = t - e3; }
-    const int Q = 64 / L;
-    const int lw = (int)(u & 63);
-    const long long q = (u >> 6) * Q + (lw % Q);
-    const int j = lw / Q;
-    const long long nq = kind == 0 ? nH1 : kind == 1 ? nH2 : kind == 2 ? nH3 : nC;
-    const bool valid = q < nq;
-    double s = 0.0;
-    if (valid) {
-      const T* base;
-      long long stride;
-      int count;
-      if (kind == 0) {
-        const long long i1 = q / a.r1;
-        const int ai = (int)(q - i1 * a.r1);
-        const int t1 = (int)(i1 / a.T1), i1l = (int)(i1 - (long long)t1 * a.T1);
-        base = part + (long long)(t1 * a.nt2) * a.slot + i1l * a.r1 + ai;
-        stride = a.slot;
-        count = a.nt2;
-      } else if (kind == 1) {
-        const long long i2 = q / a.r2;
-        const int b = (int)(q - i2 * a.r2);
-        const int t2 = (int)(i2 / a.T2), i2l = (int)(i2 - (long long)t2 * a.T2);
-        base = part + (long long)t2 * a.slot + oH2 + i2l * a.r2 + b;
-        stride = (long long)a.nt2 * a.slot;
-        count = a.nt1;
-      } else {
-        base = part + (kind == 2 ? oH3 : oC) + q;
-        stride = a.slot;
-        count = ntiles;
+  // e4 is a multiple of 64 and so is the stride: every wave runs the same trip count.
+  // A thread takes RED_U outputs per pass, with the (at most 8) partials of all of them
+  // loaded from clamped indices before any is added, so that a pass costs one memory
+  // round trip; the partials of one lane are added in a fixed tree.
+  const long long S = (long long)gx * blockDim.x;
+  for (long long t0 = (long long)bx * blockDim.x + threadIdx.x; t0 < e4; t0 += RED_U * S) {
+    double pv[RED_U][8];
+    int cntv[RED_U], jv[RED_U], kindv[RED_U], Lv[RED_U], Qv[RED_U];
+    long long qv[RED_U];
+    const T* basev[RED_U];
+    long long stv[RED_U];
+#pragma unroll
+    for (int u = 0; u < RED_U; ++u) {
+      const long long t = t0 + u * S;
+      int kind, L;
+      long long uu;
+      if (t < e1) { kind = 0; L = L1; uu = t; }
+      else if (t < e2) { kind = 1; L = L2; uu = t - e1; }
+      else if (t < e3) { kind = 2; L = L3; uu = t - e2; }
+      else { kind = 3; L = L3; uu = t - e3; }
+      const int Q = 64 / L;
+      const int lw = (int)(uu & 63);
+      const long long q = (uu >> 6) * Q + (lw % Q);
+      const int j = lw / Q;
+      const long long nq = kind == 0 ? nH1 : kind == 1 ? nH2 : kind == 2 ? nH3 : nC;
+      const bool valid = t < e4 && q < nq;
+      const T* base = part;
+      long long stride = 0;
+      int count = 0;
+      if (valid) {
+        if (kind == 0) {
+          const long long i1 = q / a.r1;
+          const int ai = (int)(q - i1 * a.r1);
+          const int t1 = (int)(i1 / a.T1), i1l = (int)(i1 - (long long)t1 * a.T1);
+          base = part + (long long)(t1 * a.nt2) * a.slot + i1l * a.r1 + ai;
+          stride = a.slot;
+          count = a.nt2;
+        } else if (kind == 1) {
+          const long long i2 = q / a.r2;
+          const int b = (int)(q - i2 * a.r2);
+          const int t2 = (int)(i2 / a.T2), i2l = (int)(i2 - (long long)t2 * a.T2);
+          base = part + (long long)t2 * a.slot + oH2 + i2l * a.r2 + b;
+          stride = (long long)a.nt2 * a.slot;
+          count = a.nt1;
+        } else {
+          base = part + (kind == 2 ? oH3 : oC) + q;
+          stride = a.slot;
+          count = ntiles;
+        }
       }
-      const int cnt = (count - j + L - 1) / L;
-      if (cnt > 0) s = sum_strided(base + (long long)j * stride, stride * L, cnt);
+      const int cnt = valid ? max((count - j + L - 1) / L, 0) : 0;
+      base += (long long)j * stride;
+      stride *= L;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) pv[u][k] = (double)gmem(base)[(long long)min(k, max(cnt - 1, 0)) * stride];
+      cntv[u] = cnt;
+      jv[u] = j;
+      kindv[u] = valid ? kind : -1;
+      Lv[u] = L;
+      Qv[u] = Q;
+      qv[u] = q;
+      basev[u] = base;
+      stv[u] = stride;
     }
-    for (int o = L >> 1; o >= 1; o >>= 1) s += __shfl_xor(s, o * Q, 64);
-    if (!valid || j != 0) continue;
-    if (kind == 0) {
-      a.H[0][q] = s;
-    } else if (kind == 1) {
-      a.H[1][q] = s;
-    } else if (kind == 2) {
-      a.H[2][q] = s;
-    } else {
-      const double cd = s * inv_dt;
-      if (stage == 1) {
-        // every entry of the data derivative reaches every entry of C_dot, so NaN or
-        // Inf anywhere in the snapshots shows here; the step is then not applied
-        if (!isfinite(cd)) atomicOr(&ctrl->numeric, NUM_NONFINITE);
-        a.kC[q] = cd;
-        a.Cs[q] = a.C0[q] + a.dt * cd;
+#pragma unroll
+    for (int u = 0; u < RED_U; ++u) {
+      if (t0 + u * S >= e4) break;   // wave-uniform
+      const int cnt = cntv[u];
+      double sk[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) sk[k] = k < cnt ? pv[u][k] : 0.0;
+      // partials past the eighth (only for more than 8 L of them): added in the same
+      // eight accumulators, in order
+      for (int k = 8; k < cnt; ++k) sk[k & 7] += (double)basev[u][(long long)k * stv[u]];
+      double s = ((sk[0] + sk[1]) + (sk[2] + sk[3])) + ((sk[4] + sk[5]) + (sk[6] + sk[7]));
+      const int L = Lv[u], Q = Qv[u];
+      for (int o = L >> 1; o >= 1; o >>= 1) s += __shfl_xor(s, o * Q, 64);
+      const int kind = kindv[u];
+      if (kind < 0 || jv[u] != 0) continue;
+      const long long q = qv[u];
+      if (kind == 0) {
+        a.H[0][q] = s;
+      } else if (kind == 1) {
+        a.H[1][q] = s;
+      } else if (kind == 2) {
+        a.H[2][q] = s;
       } else {
-        a.Cdot2[q] = cd;
-        a.C0[q] += 0.5 * a.dt * (a.kC[q] + cd);
+        const double cd = s * inv_dt;
+        if (stage == 1) {
+          // every entry of the data derivative reaches every entry of C_dot, so NaN or
+          // Inf anywhere in the snapshots shows here; the step is then not applied
+          if (!isfinite(cd)) atomicOr(&ctrl->numeric, NUM_NONFINITE);
+          a.kC[q] = cd;
+          a.Cs[q] = a.C0[q] + a.dt * cd;
+        } else {
+          a.Cdot2[q] = cd;
+          a.C0[q] += 0.5 * a.dt * (a.kC[q] + cd);
+        }
       }
     }
   }

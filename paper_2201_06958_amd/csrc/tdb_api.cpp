@@ -1387,7 +1387,9 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
     FReduceArgs big = ra;
     big.r1 = rl[0]; big.r2 = rl[1]; big.r3 = rl[2];
     big.need_h1 = big.need_h2 = big.need_f3 = 1;
-    A.blocks_red = (int)std::max<long long>(1, std::min<long long>(1024, (freduce_items(big) + 255) / 256));
+    // (a batch gives each thread RED_U outputs: fewer blocks, each a single round trip)
+    const long long per = rl != h->r ? 256LL * RED_U : 256LL;
+    A.blocks_red = (int)std::max<long long>(1, std::min<long long>(1024, (freduce_items(big) + per - 1) / per));
   }
 
   FFinishArgs ga{};
