@@ -305,21 +305,21 @@ __device__ __forceinline__ V sel3(int n, V v0, V v1, V v2) {
   return n == 0 ? v0 : (n == 1 ? v1 : v2);
 }
 
-// One pass of a row block over FIN_EPT * blockDim.x consecutive elements from `base`
+// One pass of a row block over EPT * blockDim.x consecutive elements from `base`
 // of the flat order over the rows of the three bases (mode by mode, r_n entries a
 // row). Element f needs the r_n entries of its row of U*, which lie within rmax - 1
 // places of f in that order: the pass stages its elements and that halo into LDS (at
-// most (FIN_EPT + 1) * blockDim.x values, ranks being at most 64), with every operand
+// most (EPT + 1) * blockDim.x values, ranks being at most 64), with every operand
 // of the pass (and, in the first pass, the M_n) loaded in one round trip before any
 // LDS store, instead of r_n dependent loads per element. The loads are unconditional,
 // from indices clamped into range, so that no branch separates them; what a lane loads
 // past the end is never used.
-template <typename T, bool LOADM, int ST>
+template <typename T, bool LOADM, int ST, int EPT>
 __device__ __forceinline__ void fin_rows_pass(const FFinishArgs& a, long long base, long long tot,
                                               double* const* Ml, const int* mcnt, double* tile) {
   const int nt = (int)blockDim.x, tid = (int)threadIdx.x;
   const int halo = a.rmax - 1;
-  const int tw = FIN_EPT * nt + 2 * halo;
+  const int tw = EPT * nt + 2 * halo;
   const int r0 = a.r[0], r1 = a.r[1], r2 = a.r[2];
   const long long L0 = a.N[0] * r0, L01 = L0 + a.N[1] * r1;
   const int ld0 = a.ldU[0], ld1 = a.ldU[1], ld2 = a.ldU[2];
@@ -349,18 +349,18 @@ __device__ __forceinline__ void fin_rows_pass(const FFinishArgs& a, long long ba
       mv[u] = *gmem(sel3<const double*>(n, a.M[0], a.M[1], a.M[2]) + (t - sel3(n, 0, mcnt[0], c01)));
     }
   }
-  double tv[FIN_EPT + 1];
+  double tv[EPT + 1];
 #pragma unroll
-  for (int u = 0; u <= FIN_EPT; ++u) {
+  for (int u = 0; u <= EPT; ++u) {
     const long long f = min(max(base - halo + u * nt + tid, 0LL), tot - 1);
     int n, j;
     long long q, i, e;
     locate(f, n, q, i, j, e);
     tv[u] = *gmem(sel3(n, Ust0, Ust1, Ust2) + e);
   }
-  double hv[FIN_EPT], av[FIN_EPT], bv[FIN_EPT];
+  double hv[EPT], av[EPT], bv[EPT];
 #pragma unroll
-  for (int u = 0; u < FIN_EPT; ++u) {
+  for (int u = 0; u < EPT; ++u) {
     const long long t = min(base + u * nt + tid, tot - 1);
     int n, j;
     long long q, i, e;
@@ -393,7 +393,7 @@ __device__ __forceinline__ void fin_rows_pass(const FFinishArgs& a, long long ba
     }
   }
 #pragma unroll
-  for (int u = 0; u <= FIN_EPT; ++u) {
+  for (int u = 0; u <= EPT; ++u) {
     const int x = u * nt + tid;
     if (x < tw) tile[x] = tv[u];
   }
@@ -401,7 +401,7 @@ __device__ __forceinline__ void fin_rows_pass(const FFinishArgs& a, long long ba
   const double inv_dt = a.dscale;   // 1/dt for a difference quotient, 1 for a given derivative
   const double dt = a.dt;
 #pragma unroll
-  for (int u = 0; u < FIN_EPT; ++u) {
+  for (int u = 0; u < EPT; ++u) {
     const long long t = base + u * nt + tid;
     if (t < tot) {
       int n, j;
@@ -431,18 +431,19 @@ __device__ __forceinline__ void fin_rows_pass(const FFinishArgs& a, long long ba
   __syncthreads();
 }
 
-// All passes of one row block.
-template <typename T, int ST>
+// All passes of one row block (EPT elements a thread and pass: FIN_EPT for a batch, whose
+// grids are large, one for a single stream, whose blocks are few).
+template <typename T, int ST, int EPT>
 __device__ __forceinline__ void fin_rows(const FFinishArgs& a, long long tot, long long bx, double* const* Ml,
                                          const int* mcnt, double* tile) {
-  const long long span = (long long)FIN_EPT * blockDim.x;
+  const long long span = (long long)EPT * blockDim.x;
   const long long step = (long long)a.rowblocks * span;
   long long base = bx * span;
   if (mcnt[0] + mcnt[1] + mcnt[2] > 0) {
-    fin_rows_pass<T, true, ST>(a, base, tot, Ml, mcnt, tile);
+    fin_rows_pass<T, true, ST, EPT>(a, base, tot, Ml, mcnt, tile);
     base += step;
   }
-  for (; base < tot; base += step) fin_rows_pass<T, false, ST>(a, base, tot, Ml, mcnt, tile);
+  for (; base < tot; base += step) fin_rows_pass<T, false, ST, EPT>(a, base, tot, Ml, mcnt, tile);
 }
 
 // Blocks [0, rowblocks): rows of every mode: U_dot = (H - U M)/dt, Heun update and,
@@ -462,7 +463,8 @@ __device__ __forceinline__ void ffinish_body(const FFinishArgs& a, int stage, Ct
     for (int n = 0; n < 3; ++n) tot += a.N[n] * a.r[n];
     // a batch sizes the grid for the rank caps: blocks past the current ranks' rows
     // leave before loading anything (block-uniform, ahead of every barrier)
-    const long long span = (long long)FIN_EPT * blockDim.x;
+    constexpr int EPT = ROLE == ROLE_ROWS ? FIN_EPT : 1;
+    const long long span = (long long)EPT * blockDim.x;
     if ((long long)bx * span >= tot) return;
     // M_n (r_n x r_n) into LDS: formed once per stage by k_fmprep, or here (a single
     // stream, where the extra launch would cost more than the repeated small product)
@@ -537,8 +539,8 @@ __device__ __forceinline__ void ffinish_body(const FFinishArgs& a, int stage, Ct
       }
       tile = lds + off;
     }
-    if (stage == 1) fin_rows<T, 1>(a, tot, bx, Ml, mcnt, tile);
-    else fin_rows<T, 2>(a, tot, bx, Ml, mcnt, tile);
+    if (stage == 1) fin_rows<T, 1, EPT>(a, tot, bx, Ml, mcnt, tile);
+    else fin_rows<T, 2, EPT>(a, tot, bx, Ml, mcnt, tile);
     return;
   }
   if (ROLE == ROLE_ROWS) return;

@@ -1403,7 +1403,8 @@ tdb_status build_step_args(tdb_ctx* h, const int* rl, const void* V1, const void
   ga.dscale = dscale;
   long long rows = 0;
   for (int n = 0; n < 3; ++n) rows += h->N[n] * rl[n];
-  const long long span = (long long)FIN_EPT * 256;   // row elements of one block pass
+  // row elements of one block pass: FIN_EPT a thread in a batch, one for a single stream
+  const long long span = (rl != h->r ? (long long)FIN_EPT : 1LL) * 256;
   ga.rowblocks = (int)std::max<long long>(1, std::min<long long>(1024, (rows + span - 1) / span));
   ga.Cs = h->Cs;
   ga.kC = h->kC;
