@@ -752,7 +752,7 @@ def main():
                      "algorithmic_bytes_per_launch": pj["bytes_per_launch"],
                      "step_algorithmic_bytes": step_bytes,
                      "step_frac": step_bytes / step_s / 1e9 / HBM_PEAK_GBS},
-        "error_pass": {"kernel_name": "kb_ferr_cols<float, float, 24>", "avg_launch_us": eav * 1e6,
+        "error_pass": {"kernel_name": "kb_ferr_mf<float, 24>", "avg_launch_us": eav * 1e6,
                        "algorithmic_bytes_per_launch": er["bytes_per_launch"],
                        "achieved_GBs": er["bytes_per_launch"] / eav / 1e9},
         "final_stats": {"max_ranks": [max(s["ranks"][i] for s in sts) for i in range(3)],

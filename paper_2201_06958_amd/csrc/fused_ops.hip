@@ -14,6 +14,7 @@
 #include "tdb_common.h"
 #include "tdb_kernels.h"
 #include "fused.h"
+#include <type_traits>
 #include "device_util.h"
 #include <hip/hip_ext.h>
 #include <math.h>
@@ -1823,14 +1824,162 @@ __global__ void __launch_bounds__(FEC_COLS) kb_ferr_cols(const FErrArgs* __restr
   }
 }
 
+// The same column-block error pass with the reconstruction U1 E on the matrix cores
+// (FP32 compute): wave w of block bx takes the 64 columns FEC_COLS bx + 64 w + 16 c + q
+// (c < 4 groups of 16), and each 16-row block of the mode-1 unfolding is reconstructed
+// as four 16 x 16 FP32 products over K = R1C (16x16x4 instructions: lane (q, g) feeds
+// U1[row q][4 kc + g] and E[4 kc + g][column q] and receives rows 4 g .. 4 g + 3 of
+// column q). E stays in registers, the U1 rows and w1 are staged in LDS FEC_ROWS at a
+// time, and the snapshot values of the next 16-row block are in flight while one is
+// used. Sums as in kb_ferr_cols: w1[i] d^2 and w1[i] v^2 in FP64 per column, scaled by
+// w23[j], then the block's fixed-order sum.
+typedef float fec4 __attribute__((ext_vector_type(4)));
+template <typename TD, int R1C>
+__global__ void __launch_bounds__(FEC_COLS) kb_ferr_mf(const FErrArgs* __restrict__ tab, const void* const* v1,
+                                                       BatchMap m) {
+  constexpr int KC = R1C / 4;
+  __shared__ double red[16];
+  __shared__ __align__(16) float U1s[FEC_ROWS * R1C];
+  __shared__ double w1s[FEC_ROWS];
+  const int s = m.sid[blockIdx.x];
+  const FErrArgs a = tab[s];
+  if (a.hold && *gmem(a.hold)) return;   // a decision awaits the host
+  const int bx = blockIdx.x - m.start[s];
+  TDB_GLOBAL double* part = gmem(a.part);
+  if (a.skip && *gmem(a.skip)) {
+    // the learned gate skips this step's pass
+    if (threadIdx.x == 0) {
+      part[2 * bx] = 0.0;
+      part[2 * bx + 1] = 0.0;
+    }
+    return;
+  }
+  const long long M = a.M;
+  const int N1 = a.N1, r1 = a.r1, tid = threadIdx.x;
+  const int lane = tid & 63, q = lane & 15, g = lane >> 4, wv = tid >> 6;
+  long long jc[4];
+  bool jok[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const long long j = (long long)bx * FEC_COLS + 64 * wv + 16 * c + q;
+    jok[c] = j < M;
+    jc[c] = jok[c] ? j : M - 1;
+  }
+  const TDB_GLOBAL TD* V = gmem(static_cast<const TD*>(v1[s]));
+  const TDB_GLOBAL float* E = gmem(static_cast<const float*>(a.E));
+  const TDB_GLOBAL float* U1 = gmem(static_cast<const float*>(a.U1c));
+  const TDB_GLOBAL double* w1 = gmem(a.w1);
+  float eB[4][KC];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      const int k = 4 * kc + g;
+      const float x = E[(long long)min(k, r1 - 1) * M + jc[c]];
+      eB[c][kc] = k < r1 ? x : 0.0f;
+    }
+  double w23[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) w23[c] = gmem(a.w23)[jc[c]];
+  double se[4] = {0.0, 0.0, 0.0, 0.0}, sv[4] = {0.0, 0.0, 0.0, 0.0};
+  // snapshot values of the 16-row block from row i0: rows i0 + 4g + ii of the four columns
+  auto vload = [&](float (&vv)[16], int i0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii)
+        vv[4 * c + ii] = (float)V[(long long)min(i0 + 4 * g + ii, N1 - 1) * M + jc[c]];
+  };
+  // the 16-row block rb of the staged chunk from row c0 (its values in vv)
+  auto block = [&](const float (&vv)[16], int c0, int rb) {
+    fec4 acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = fec4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      const float av = U1s[(16 * rb + q) * R1C + 4 * kc + g];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, eB[c][kc], acc[c], 0, 0, 0);
+    }
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int rl = 16 * rb + 4 * g + ii;
+      if (c0 + rl < N1) {
+        const double wi = w1s[rl];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const float v = vv[4 * c + ii];
+          const float d = v - acc[c][ii];
+          se[c] += wi * (double)(d * d);
+          sv[c] += wi * (double)(v * v);
+        }
+      }
+    }
+  };
+  float va[16], vb[16];
+  vload(va, 0);
+  for (int c0 = 0; c0 < N1; c0 += FEC_ROWS) {
+    const int nr = min(FEC_ROWS, N1 - c0);
+    __syncthreads();
+    {
+      // rows c0 .. c0+nr of U1, zero-padded to R1C columns, eight loads in flight
+      const int ne = nr * R1C;
+      for (int t0 = 0; t0 < ne; t0 += 8 * FEC_COLS) {
+        float x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int t = min(t0 + u * FEC_COLS + tid, ne - 1);
+          const int qq = t / R1C, k = t - (t / R1C) * R1C;
+          x[u] = U1[(long long)(c0 + qq) * r1 + min(k, r1 - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int t = t0 + u * FEC_COLS + tid;
+          if (t < ne) U1s[t] = (t - (t / R1C) * R1C) < r1 ? x[u] : 0.0f;
+        }
+      }
+      if (tid < nr) w1s[tid] = w1[c0 + tid];
+    }
+    __syncthreads();
+    // blocks in pairs: each has the next one's values in flight
+    const int nb = (nr + 15) >> 4;
+    for (int rb = 0; rb < nb; rb += 2) {
+      vload(vb, c0 + 16 * rb + 16);
+      block(va, c0, rb);
+      if (rb + 1 < nb) {
+        vload(va, c0 + 16 * rb + 32);
+        block(vb, c0, rb + 1);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) va[u] = vb[u];   // (the next chunk's first block)
+      }
+    }
+  }
+  double st = 0.0, sq = 0.0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    st += jok[c] ? se[c] * w23[c] : 0.0;
+    sq += jok[c] ? sv[c] * w23[c] : 0.0;
+  }
+  st = block_sum(st, red);
+  sq = block_sum(sq, red);
+  if (tid == 0) {
+    part[2 * bx] = st;
+    part[2 * bx + 1] = sq;
+  }
+}
+
 // The error pass's partials alone (no controller): the column-block form for r1c > 0.
 template <typename TD, typename T>
 hipError_t launch_batch_ferr_partials(const FErrArgs* tab, const void* const* v1, BatchMap m, int blocks, int r1c,
                                       hipStream_t s) {
   switch (r1c) {
-#define FEC_CASE(R)                                                                                 \
-  case R:                                                                                           \
-    hipLaunchKernelGGL((kb_ferr_cols<TD, T, R>), dim3(blocks), dim3(FEC_COLS), 0u, s, tab, v1, m); \
+#define FEC_CASE(R)                                                                                   \
+  case R:                                                                                             \
+    if constexpr (std::is_same<T, float>::value)                                                      \
+      hipLaunchKernelGGL((kb_ferr_mf<TD, R>), dim3(blocks), dim3(FEC_COLS), 0u, s, tab, v1, m);       \
+    else                                                                                              \
+      hipLaunchKernelGGL((kb_ferr_cols<TD, T, R>), dim3(blocks), dim3(FEC_COLS), 0u, s, tab, v1, m);  \
     break;
     FEC_CASE(4) FEC_CASE(8) FEC_CASE(12) FEC_CASE(16) FEC_CASE(20) FEC_CASE(24) FEC_CASE(28) FEC_CASE(32)
 #undef FEC_CASE
@@ -1855,7 +2004,11 @@ hipError_t launch_batch_ferr(const FErrArgs* tab, const void* const* v1, BatchMa
   switch (r1c) {
 #define FEC_CASE(R)                                                                                            \
   case R:                                                                                                      \
-    hipExtLaunchKernelGGL((kb_ferr_cols<TD, T, R>), dim3(blocks), dim3(FEC_COLS), 0u, s, ev0, ev1, 0u, tab, v1, m); \
+    if constexpr (std::is_same<T, float>::value)                                                               \
+      hipExtLaunchKernelGGL((kb_ferr_mf<TD, R>), dim3(blocks), dim3(FEC_COLS), 0u, s, ev0, ev1, 0u, tab, v1, m); \
+    else                                                                                                       \
+      hipExtLaunchKernelGGL((kb_ferr_cols<TD, T, R>), dim3(blocks), dim3(FEC_COLS), 0u, s, ev0, ev1, 0u, tab, v1, \
+                            m);                                                                                \
     break;
     FEC_CASE(4) FEC_CASE(8) FEC_CASE(12) FEC_CASE(16) FEC_CASE(20) FEC_CASE(24) FEC_CASE(28) FEC_CASE(32)
 #undef FEC_CASE

@@ -48,7 +48,9 @@ PASS_KERNELS = {
     "kb_rpass<float, 1, 4, true, 32>": ("rpass.hip", "mfma_util.h", "fused.h", "tdb_common.h", "tdb_kernels.h"),
     "kb_rpass<float, 2, 4, true, 64>": ("rpass.hip", "mfma_util.h", "fused.h", "tdb_common.h", "tdb_kernels.h"),
     "kb_rpass<float, 2, 4, true, 32>": ("rpass.hip", "mfma_util.h", "fused.h", "tdb_common.h", "tdb_kernels.h"),
-    # column-block error pass of batches (mode-1 rank cap 24)
+    # column-block error pass of batches (mode-1 rank cap 24; the reconstruction on the
+    # matrix cores for FP32 compute, on the vector ALU otherwise)
+    "kb_ferr_mf<float, 24>": ("fused_ops.hip", "fused.h", "tdb_common.h", "device_util.h"),
     "kb_ferr_cols<float, float, 24>": ("fused_ops.hip", "fused.h", "tdb_common.h", "device_util.h"),
 }
 PASS_KERNEL = "k_mpass_w16<float, 1>"     # the pass of the reactive-flow workload
