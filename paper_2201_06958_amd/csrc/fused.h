@@ -6,7 +6,7 @@ namespace tdb {
 
 #define FERR_T1 8   // mode-1 slabs per block of the error pass
 #define FIN_PART 1024 // LDS doubles for the partial blocks of the small matrix-core products
-#define FIN_EPT 4      // basis-row elements per thread in one pass of a finish row block
+#define FIN_EPT 2      // basis-row elements per thread in one pass of a batch's finish row block
 #define RED_U 4        // outputs per thread in one pass of the partial reduction
 #define FIN_MU 8       // M_n values per thread loaded together with the first pass's operands
 #define FQR_GP 1024   // LDS doubles for the QR's partial Gram blocks (four 16 x 16)
