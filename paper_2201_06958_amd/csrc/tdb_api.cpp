@@ -145,6 +145,12 @@ struct tdb_ctx {
   bool prof_now = true;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[2];
+  // a second stream (default priority) for the kernels that run beside another one: the
+  // stage-1 pseudo-inverses beside the row blocks, the post-step's mode blocks beside its
+  // expansion blocks (fork and join by events, captured into the step's graph)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork[2] = {}, ev_join[2] = {};
+  bool side_failed = false;
 
   ~tdb_ctx() {
     for (auto& v : ev_used)
@@ -1873,6 +1879,12 @@ struct tdb_batch_ctx {
   bool prof_now = false;            // this step is timed
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[2];
+  // a second stream (default priority) for the kernels that run beside another one: the
+  // stage-1 pseudo-inverses beside the row blocks, the post-step's mode blocks beside its
+  // expansion blocks (fork and join by events, captured into the step's graph)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork[2] = {}, ev_join[2] = {};
+  bool side_failed = false;
   // learned gate (parameters owned by the trainer that was attached)
   int gate_mode = GATE_OFF;
   const float* gate_params = nullptr;
@@ -1883,6 +1895,11 @@ struct tdb_batch_ctx {
     for (hipGraphExec_t& g : gexec)
       if (g) (void)hipGraphExecDestroy(g);
     if (cap) (void)hipStreamDestroy(cap);
+    if (side) (void)hipStreamDestroy(side);
+    for (int k = 0; k < 2; ++k) {
+      if (ev_fork[k]) (void)hipEventDestroy(ev_fork[k]);
+      if (ev_join[k]) (void)hipEventDestroy(ev_join[k]);
+    }
     for (auto& v : ev_used)
       for (auto& e : v) { ev_pool.push_back(e.first); ev_pool.push_back(e.second); }
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
@@ -2394,15 +2411,38 @@ tdb_status batch_kernels(tdb_batch_ctx* b, int p, hipStream_t s) {
                                          e1)));
     BHIPCHK(launch_batch_freduce<T>(b->d_ra, b->d_ctab, b->m_red, b->g_red, st + 1, s));
     BHIPCHK(launch_batch_fmprep<T>(b->d_ga[st], b->d_ctab, b->m_qr, b->g_qr, st + 1, b->lds_mprep, s));
-    // the row blocks (both stages) and the stage-1 pseudo-inverses as separate kernels
+    // the row blocks (both stages) and the stage-1 pseudo-inverses as separate kernels;
+    // the two share no buffer (a single stream runs them as one launch), so with a side
+    // stream the pseudo-inverses run beside the row blocks
+    const bool fork = st == 0 && b->side;
+    if (fork) {
+      BHIPCHK(hipEventRecord(b->ev_fork[0], s));
+      BHIPCHK(hipStreamWaitEvent(b->side, b->ev_fork[0], 0));
+      BHIPCHK(launch_batch_ffinish<T>(b->d_ga[st], b->d_ctab, b->m_qr, b->g_qr, st + 1, b->lds_fin, ROLE_PINV,
+                                      b->side));
+      BHIPCHK(hipEventRecord(b->ev_join[0], b->side));
+    }
     BHIPCHK(launch_batch_ffinish<T>(b->d_ga[st], b->d_ctab, b->m_fin[1], b->g_fin[1], st + 1, b->lds_rows, ROLE_ROWS,
                                     s));
-    if (st == 0)
+    if (fork)
+      BHIPCHK(hipStreamWaitEvent(s, b->ev_join[0], 0));
+    else if (st == 0)
       BHIPCHK(launch_batch_ffinish<T>(b->d_ga[st], b->d_ctab, b->m_qr, b->g_qr, st + 1, b->lds_fin, ROLE_PINV, s));
   }
   BHIPCHK(launch_batch_fqr(b->d_qa, b->d_ctab, b->m_qa, b->g_qa, b->lds_qr, s));
-  BHIPCHK(launch_batch_fpost<T>(b->d_pa, b->d_ctab, b->m_qr, b->g_qr, b->lds_post, ROLE_MODES, s));
-  BHIPCHK(launch_batch_fpost<T>(b->d_pa, b->d_ctab, b->m_exp, b->g_exp, b->lds_exp, ROLE_EXP, s));
+  // the post-step's mode blocks (core Grams, next pseudo-inverses) and expansion blocks
+  // likewise share no buffer
+  if (b->side) {
+    BHIPCHK(hipEventRecord(b->ev_fork[1], s));
+    BHIPCHK(hipStreamWaitEvent(b->side, b->ev_fork[1], 0));
+    BHIPCHK(launch_batch_fpost<T>(b->d_pa, b->d_ctab, b->m_qr, b->g_qr, b->lds_post, ROLE_MODES, b->side));
+    BHIPCHK(hipEventRecord(b->ev_join[1], b->side));
+    BHIPCHK(launch_batch_fpost<T>(b->d_pa, b->d_ctab, b->m_exp, b->g_exp, b->lds_exp, ROLE_EXP, s));
+    BHIPCHK(hipStreamWaitEvent(s, b->ev_join[1], 0));
+  } else {
+    BHIPCHK(launch_batch_fpost<T>(b->d_pa, b->d_ctab, b->m_qr, b->g_qr, b->lds_post, ROLE_MODES, s));
+    BHIPCHK(launch_batch_fpost<T>(b->d_pa, b->d_ctab, b->m_exp, b->g_exp, b->lds_exp, ROLE_EXP, s));
+  }
   if (b->gate_mode != GATE_OFF) {
     GateStepArgs g{};
     g.params = b->gate_params;
@@ -2438,6 +2478,20 @@ tdb_status batch_kernels(tdb_batch_ctx* b, int p, hipStream_t s) {
 // graphs off for the batch and the launches run as they are.
 template <typename TD, typename T>
 tdb_status batch_enqueue(tdb_batch_ctx* b, int p, hipStream_t s) {
+  if (!b->side && !b->side_failed) {
+    // the side stream and its events, made once, before any capture (without them every
+    // kernel runs on s)
+    bool ok = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) == hipSuccess;
+    for (int k = 0; k < 2 && ok; ++k)
+      ok = hipEventCreateWithFlags(&b->ev_fork[k], hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&b->ev_join[k], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      (void)hipGetLastError();
+      if (b->side) (void)hipStreamDestroy(b->side);
+      b->side = nullptr;
+      b->side_failed = true;
+    }
+  }
   const bool graph = b->use_graph && !b->prof_now;
   const int key = b->vw;
   if (graph && b->gexec[p] && b->gkey[p] == key) {
