@@ -2410,10 +2410,10 @@ tdb_status batch_kernels(tdb_batch_ctx* b, int p, hipStream_t s) {
       BHIPCHK((launch_batch_fpass<TD, T>(b->d_fa[st], b->d_v1, b->d_v0, b->m_pass, b->g_pass, b->lds_pass, s, e0,
                                          e1)));
     BHIPCHK(launch_batch_freduce<T>(b->d_ra, b->d_ctab, b->m_red, b->g_red, st + 1, s));
-    BHIPCHK(launch_batch_fmprep<T>(b->d_ga[st], b->d_ctab, b->m_qr, b->g_qr, st + 1, b->lds_mprep, s));
     // the row blocks (both stages) and the stage-1 pseudo-inverses as separate kernels;
-    // the two share no buffer (a single stream runs them as one launch), so with a side
-    // stream the pseudo-inverses run beside the row blocks
+    // the pseudo-inverses need only the stage core and share no buffer with the M prep
+    // or the row blocks (a single stream runs the two finish roles as one launch), so
+    // with a side stream they run beside those
     const bool fork = st == 0 && b->side;
     if (fork) {
       BHIPCHK(hipEventRecord(b->ev_fork[0], s));
@@ -2422,6 +2422,7 @@ tdb_status batch_kernels(tdb_batch_ctx* b, int p, hipStream_t s) {
                                       b->side));
       BHIPCHK(hipEventRecord(b->ev_join[0], b->side));
     }
+    BHIPCHK(launch_batch_fmprep<T>(b->d_ga[st], b->d_ctab, b->m_qr, b->g_qr, st + 1, b->lds_mprep, s));
     BHIPCHK(launch_batch_ffinish<T>(b->d_ga[st], b->d_ctab, b->m_fin[1], b->g_fin[1], st + 1, b->lds_rows, ROLE_ROWS,
                                     s));
     if (fork)
