@@ -278,6 +278,9 @@ tdb_status tdb_profile_read(tdb_handle h, int32_t pass, int64_t* launches, doubl
  *   that reads the step. The launches of a step are replayed from a HIP graph, one per
  *   step parity, captured again when the launch shapes change (TDB_GRAPH=0 in the
  *   environment launches them one by one; TDB_PIPELINE=0 reads every step at once).
+ *   Two kernels of a step run on a second stream the batch owns (default priority),
+ *   forked from and joined back to `stream` by events within the step, so work that
+ *   follows on `stream`, or a synchronisation of it, sees the whole step.
  * tdb_batch_flush: reads the newest step if it has not been read; returns its
  *   status.
  * tdb_batch_stream: a handle of stream i for tdb_get_stats, tdb_get_core_and_bases,
