@@ -140,3 +140,57 @@ def test_batch_stream_handles_are_owned_by_the_batch():
     b.ingest([_dev(sp.snapshot_np(1))])
     assert b.streams[0].stats()["step"] == 1
     b.close()
+
+
+def _tucker_walk(dims, ranks, seed, steps, amp=0.005):
+    """A Tucker tensor with a diagonally dominant core (every unfolding well conditioned)
+    plus a small random walk, in FP32."""
+    rng = np.random.default_rng(seed)
+    C = 0.2 * rng.normal(size=ranks)
+    for i in range(min(ranks)):
+        C[(i,) * len(ranks)] += 1.0 - 0.1 * i
+    X = C
+    for k, (N, r) in enumerate(zip(dims, ranks)):
+        X = np.moveaxis(np.tensordot(rng.normal(size=(N, r)), X, axes=([1], [k])), 0, k)
+    snaps = [X]
+    for _ in range(steps):
+        snaps.append(snaps[-1] + amp * rng.normal(size=dims))
+    w = []
+    for n in dims:
+        x = rng.uniform(0.5, 1.5, size=n)
+        w.append(x / x.sum())
+    return w, [s.astype(np.float32) for s in snaps]
+
+
+def test_batch_fp32_ragged_shapes_against_oracle():
+    """FP32 data and passes at fixed ranks on shapes that leave ragged tails everywhere:
+    mode-1 sizes that are not multiples of the 16-row blocks of the matrix-core error
+    pass, column counts N2*N3 that are not multiples of its 64-column waves, ranks that
+    are not multiples of 4, a full-rank third mode. eps per step within 1e-6 of nu and
+    the final reconstruction at 1e-6 relative, against the FP64 oracle fed the same
+    rounded snapshots."""
+    cases = [((20, 17, 9), (3, 4, 2)), ((37, 29, 3), (5, 4, 3)), ((70, 45, 5), (6, 5, 4))]
+    steps = 6
+    from paper_2201_06958_amd import Batch
+    data, cfgs, orcs = [], [], []
+    for i, (dims, ranks) in enumerate(cases):
+        w, snaps = _tucker_walk(dims, ranks, 300 + i, steps)
+        data.append(snaps)
+        cfgs.append(dict(dims=dims, dt=0.05, rank_max=ranks, rank_init=ranks, weights=w, data_dtype="f32",
+                         precision="f32", adaptive=False, eps_th=1.0))
+        oc = O.OracleConfig(dims=dims, weights=w, dt=0.05, rank_max=ranks, rank_init=ranks, adaptive=False,
+                            eps_th=1.0)
+        orcs.append(O.OracleTDB(oc).init(snaps[0].astype(np.float64)))
+    _say("case batch fp32 ragged", cases)
+    b = Batch(cfgs).init([_dev(d[0]) for d in data])
+    for k in range(1, steps + 1):
+        b.ingest([_dev(d[k]) for d in data])
+        for i, o in enumerate(orcs):
+            rec = o.ingest(data[i][k].astype(np.float64))
+            st = b.streams[i].stats()
+            assert abs(st["eps"] - rec.eps) <= 1e-6 * rec.nu, (k, i, st["eps"], rec.eps)
+    for i, o in enumerate(orcs):
+        r, C, U = b.streams[i].get_core_and_bases()
+        assert tuple(r[:3]) == tuple(o.ranks)
+        assert _rel(O.reconstruct(C, U), o.reconstruct()) < 1e-6, i
+    b.close()
