@@ -4,11 +4,17 @@
     python -m paper_2201_06958_amd.profsum pmc FETCH_DB WRITE_DB --command-fetch CMD
         --command-write CMD [--copy-bytes N] [--out FILE]
     python -m paper_2201_06958_amd.profsum counters DB --command CMD [--match NAME] [--out FILE]
+    python -m paper_2201_06958_amd.profsum timeline DB --command CMD [--first NAME] [--out FILE]
 
 `stats` tabulates per-kernel call counts and average durations from a
 `rocprofv3 --kernel-trace --stats` run (and, given the JSON lines bench.py printed
 with and without the profiler, the stage-pass launch duration bench.py measured itself
 with dispatch-stamped HIP events, so the two clocks can be compared).
+
+`timeline` splits a `--kernel-trace` run's library kernels into steps at each launch of
+the step's first kernel (`--first`), and gives each of the last steps' span against the
+time some kernel was running (the union of their intervals), then one step kernel by
+kernel, start and end from the step's start.
 
 `pmc` turns two counter runs (`--pmc FETCH_SIZE`, then `--pmc WRITE_SIZE`, each with
 `--kernel-trace`) into HBM bytes per dispatch. The raw counters are scaled by what
@@ -237,6 +243,49 @@ def counters_text(db: str, command: str, match: str) -> str:
     return "\n".join(out) + "\n"
 
 
+def step_timeline(rows, first):
+    """rows: (name, start_ns, end_ns) in start order. Steps begin at each kernel whose name
+    contains `first`; returns [(span_us, busy_us, kernels)] for the complete steps and the
+    kernels of the last complete step as (name, start_us, end_us) from its start."""
+    marks = [i for i, r in enumerate(rows) if first in r[0]]
+    steps, last = [], []
+    for a, b in zip(marks, marks[1:]):
+        seg = rows[a:b]
+        iv = sorted((st, en) for _, st, en in seg)
+        busy, cs, ce = 0, iv[0][0], iv[0][1]
+        for st, en in iv[1:]:
+            if st > ce:
+                busy += ce - cs
+                cs, ce = st, en
+            else:
+                ce = max(ce, en)
+        busy += ce - cs
+        span = max(en for _, _, en in seg) - seg[0][1]
+        steps.append((span / 1e3, busy / 1e3, len(seg)))
+        t0 = seg[0][1]
+        last = [(n, (st - t0) / 1e3, (en - t0) / 1e3) for n, st, en in seg]
+    return steps, last
+
+
+def timeline_text(db: str, command: str, first: str = "kb_fetch_ptrs", nsteps: int = 10) -> str:
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, start, end from kernels order by start").fetchall()
+    con.close()
+    rows = [(_short(str(n)), int(st), int(en)) for n, st, en in rows if "tdb::" in str(n)]
+    steps, last = step_timeline(rows, first)
+    out = ["# rocprofv3 --kernel-trace: timeline of the library's kernels per step", "",
+           "command:", "    " + command, "",
+           f"steps start at each launch of {first}; the last {min(nsteps, len(steps))} complete steps "
+           "(busy: time some kernel was running)", ""]
+    for span, busy, k in steps[-nsteps:]:
+        out.append(f"    span {span:8.1f} us   busy {busy:8.1f} us   kernels {k}")
+    out += ["", "the last complete step (us from its first kernel's start):", "",
+            f"{'start':>9} {'end':>9} {'length':>8}  kernel"]
+    for n, st, en in last:
+        out.append(f"{st:9.1f} {en:9.1f} {en - st:8.1f}  {n[:90]}")
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -264,8 +313,15 @@ def main(argv=None):
     c.add_argument("--command", required=True)
     c.add_argument("--match", default="tdb::")
     c.add_argument("--out")
+    t = sub.add_parser("timeline")
+    t.add_argument("db")
+    t.add_argument("--command", required=True)
+    t.add_argument("--first", default="kb_fetch_ptrs", help="the first kernel of a step")
+    t.add_argument("--out")
     a = ap.parse_args(argv)
-    if a.cmd == "stats":
+    if a.cmd == "timeline":
+        text = timeline_text(a.db, a.command, a.first)
+    elif a.cmd == "stats":
         text = stats_text(a.db, a.command, a.bench, a.bench_plain)
     elif a.cmd == "counters":
         text = counters_text(a.db, a.command, a.match)

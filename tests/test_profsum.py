@@ -71,3 +71,25 @@ def test_counters_text(tmp_path):
     text = profsum.counters_text(str(db), "cmd", "kb_rpass")
     row = [ln for ln in text.splitlines() if "SQ_INSTS_MFMA" in ln]
     assert len(row) == 1 and row[0].split()[-1] == "200.0" and row[0].split()[-2] == "2"
+
+
+def test_step_timeline(tmp_path):
+    """Steps split at the first kernel; busy time is the union of overlapping kernels."""
+    rows = [("tdb::kb_fetch_ptrs", 0, 5_000), ("tdb::kb_rpass<float>", 5_000, 105_000),
+            ("tdb::kb_fpost<float, 1>", 110_000, 150_000), ("tdb::kb_fpost<float, 2>", 120_000, 200_000),
+            ("tdb::kb_fetch_ptrs", 210_000, 215_000), ("tdb::kb_rpass<float>", 215_000, 300_000),
+            ("tdb::kb_fetch_ptrs", 310_000, 311_000)]
+    steps, last = profsum.step_timeline(rows, "kb_fetch_ptrs")
+    assert len(steps) == 2
+    span, busy, k = steps[0]
+    assert abs(span - 200.0) < 1e-9 and abs(busy - 195.0) < 1e-9 and k == 4
+    assert abs(steps[1][0] - 90.0) < 1e-9 and abs(steps[1][1] - 90.0) < 1e-9
+    assert last[0][1] == 0.0 and abs(last[-1][2] - 90.0) < 1e-9
+    db = tmp_path / "k.db"
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, start int, end int)")
+    con.executemany("insert into kernels values (?, ?, ?)", [(f"void {n}(x)", a, b) for n, a, b in rows])
+    con.commit()
+    con.close()
+    text = profsum.timeline_text(str(db), "the command")
+    assert "the command" in text and "busy    195.0 us" in text
