@@ -15,6 +15,8 @@
 #include "tdb_kernels.h"
 #include "fused.h"
 #include <type_traits>
+#include <map>
+#include <mutex>
 #include "device_util.h"
 #include <hip/hip_ext.h>
 #include <math.h>
@@ -22,6 +24,24 @@
 namespace tdb {
 
 typedef double md4 __attribute__((ext_vector_type(4)));
+
+// A kernel's dynamic-LDS limit raised only when a launch asks for more than it was given
+// on the current device: the attribute call is otherwise a runtime call of a few
+// microseconds on every launch of a single stream's step, which the host issues one
+// kernel at a time.
+static hipError_t lds_limit(const void* f, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, int> given;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  int& g = given[{f, dev}];
+  if ((int)lds <= g) return hipSuccess;
+  e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess) g = (int)lds;
+  return e;
+}
 
 // ---------------------------------------------------------------- reduction
 // Sums the per-tile partials in a fixed order (FP64) into H_n and C_dot, and applies
@@ -1425,8 +1445,7 @@ template hipError_t launch_freduce<double>(const FReduceArgs&, CtrlState*, hipSt
 
 template <typename T>
 hipError_t launch_ffinish(const FFinishArgs& a, size_t lds, CtrlState* c, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_ffinish<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
+  hipError_t e = lds_limit((const void*)k_ffinish<T>, lds);
   if (e != hipSuccess) return e;
   const int blocks = a.rowblocks + (a.stage == 1 ? 3 : 0);
   hipLaunchKernelGGL(k_ffinish<T>, dim3(blocks), dim3(256), lds, s, a, c);
@@ -1437,7 +1456,7 @@ template hipError_t launch_ffinish<double>(const FFinishArgs&, size_t, CtrlState
 
 template <typename T>
 hipError_t launch_fmprep(const FFinishArgs& a, size_t lds, CtrlState* c, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_fmprep<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = lds_limit((const void*)k_fmprep<T>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fmprep<T>, dim3(3), dim3(256), lds, s, a, c);
   return hipGetLastError();
@@ -1470,7 +1489,7 @@ hipError_t launch_euler_commit(const CommitArgs& a, CtrlState* c, hipStream_t s)
 }
 
 hipError_t launch_fqr(const FQrArgs& a, size_t lds, CtrlState* c, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_fqr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = lds_limit((const void*)k_fqr, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fqr, dim3(a.nb[0] + a.nb[1] + a.nb[2]), dim3(256), lds, s, a, c);
   return hipGetLastError();
@@ -1478,8 +1497,7 @@ hipError_t launch_fqr(const FQrArgs& a, size_t lds, CtrlState* c, hipStream_t s)
 
 template <typename T>
 hipError_t launch_fpost(const FPostArgs& a, size_t lds, CtrlState* c, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_fpost<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
+  hipError_t e = lds_limit((const void*)k_fpost<T>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fpost<T>, dim3(3 + a.eblocks), dim3(256), lds, s, a, c);
   return hipGetLastError();
@@ -1493,7 +1511,7 @@ hipError_t launch_ferr(const FErrArgs& a, CtrlState* c, hipStream_t s, hipEvent_
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t fl = ferr_final_lds(a.rmax);
-  e = hipFuncSetAttribute((const void*)k_ferr_final, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fl);
+  e = lds_limit((const void*)k_ferr_final, fl);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_ferr_final, dim3(1), dim3(256), fl, s, a, c);
   return hipGetLastError();
