@@ -898,6 +898,39 @@ __device__ __forceinline__ void fqr_body(const FQrArgs& a, CtrlState* ctrl, int 
 
 __global__ void __launch_bounds__(256) k_fqr(FQrArgs a, CtrlState* ctrl) { fqr_body(a, ctrl, blockIdx.x); }
 
+// The expansion rows E[a][i0 + il][i3] = sum_b U2r[il][b] T3[a][b][i3] for il < nr, the
+// rows U2r (r2 a row) and T3 (r1 x r2 x N3) in LDS, the sum over b in order. The index
+// decomposition takes small_div (a float reciprocal and one correction) below 2^22
+// outputs, so that it does not outweigh the r2 multiply-adds of an output.
+template <typename T>
+__device__ __forceinline__ void expansion_rows(T* E, const double* U2r, const double* T3, int r1, int r2, int nr,
+                                               int i0, long long N2, long long N3) {
+  const long long tot = (long long)r1 * nr * N3;
+  if (tot < (1LL << 22)) {
+    const int n3 = (int)N3;
+    const float i_n3 = 1.0f / (float)n3, i_nr = 1.0f / (float)nr;
+    for (int t = threadIdx.x; t < (int)tot; t += blockDim.x) {
+      const int q = small_div(t, n3, i_n3), i3 = t - q * n3;
+      const int ai = small_div(q, nr, i_nr), il = q - ai * nr;
+      const double* u2 = U2r + il * r2;
+      const double* t3 = T3 + ai * r2 * n3 + i3;
+      double sv = 0.0;
+      for (int b = 0; b < r2; ++b) sv += u2[b] * t3[b * n3];
+      E[((long long)ai * N2 + i0 + il) * N3 + i3] = (T)sv;
+    }
+  } else {
+    for (long long t = threadIdx.x; t < tot; t += blockDim.x) {
+      const long long i3 = t % N3, q = t / N3;
+      const int il = (int)(q % nr), ai = (int)(q / nr);
+      const double* u2 = U2r + il * r2;
+      const double* t3 = T3 + (long long)ai * r2 * N3 + i3;
+      double sv = 0.0;
+      for (int b = 0; b < r2; ++b) sv += u2[b] * t3[(long long)b * N3];
+      E[((long long)ai * N2 + i0 + il) * N3 + i3] = (T)sv;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- post-step
 // Blocks [0, 3): for mode n at the new state: the core Gram (kept for the controller),
 // its eigenvalues when asked for (core singular values) and the pseudo-inverse P_n for
@@ -1056,20 +1089,7 @@ __device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, 
           for (int t = threadIdx.x; t < n_e; t += blockDim.x) U1c[t] = (T)Ur[t];
         }
       }
-      if (nr1 > 0) {
-        T* E = static_cast<T*>(a.E);
-        const double* U2r = base + oR1;
-        const int nr = nr1;
-        for (long long t = threadIdx.x; t < (long long)r1 * nr * N3; t += blockDim.x) {
-          const long long i3 = t % N3, q = t / N3;
-          const int il = (int)(q % nr), ai = (int)(q / nr);
-          const double* u2 = U2r + il * r2;
-          const double* t3 = T3 + (long long)ai * r2 * N3 + i3;
-          double sv = 0.0;
-          for (int b = 0; b < r2; ++b) sv += u2[b] * t3[(long long)b * N3];
-          E[((long long)ai * N2 + ia1 + il) * N3 + i3] = (T)sv;
-        }
-      }
+      if (nr1 > 0) expansion_rows<T>(static_cast<T*>(a.E), base + oR1, T3, r1, r2, nr1, ia1, N2, N3);
       return;
     }
     for (int m = 0; m < 3; ++m) {
@@ -1128,18 +1148,7 @@ __device__ __forceinline__ void fpost_body(const FPostArgs& a, CtrlState* ctrl, 
           T* U1c = static_cast<T*>(a.U1c);
           for (int t = threadIdx.x; t < nr * rm; t += blockDim.x) U1c[c0 * rm + t] = (T)Uc[t];
         }
-        if (m == 1) {
-          T* E = static_cast<T*>(a.E);
-          for (long long t = threadIdx.x; t < (long long)r1 * nr * N3; t += blockDim.x) {
-            const long long i3 = t % N3, q = t / N3;
-            const int il = (int)(q % nr), ai = (int)(q / nr);
-            const double* u2 = Uc + il * r2;
-            const double* t3 = T3 + (long long)ai * r2 * N3 + i3;
-            double sv = 0.0;
-            for (int b = 0; b < r2; ++b) sv += u2[b] * t3[(long long)b * N3];
-            E[((long long)ai * N2 + c0 + il) * N3 + i3] = (T)sv;
-          }
-        }
+        if (m == 1) expansion_rows<T>(static_cast<T*>(a.E), Uc, T3, r1, r2, nr, (int)c0, N2, N3);
       }
     }
     return;
