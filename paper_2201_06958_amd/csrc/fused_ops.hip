@@ -1553,7 +1553,9 @@ __global__ void __launch_bounds__(256) kb_fmprep(const FFinishArgs* __restrict__
   fmprep_body<T>(tab[s], stage, ctab[s], blockIdx.x - m.start[s]);
 }
 
-__global__ void __launch_bounds__(256) kb_fqr(const FQrArgs* __restrict__ tab, CtrlState* const* ctab, BatchMap m) {
+// A batch's QR takes one workgroup per stream (all its slabs): 1024 threads, so that the
+// slab loads, Grams and the fold of a stream are spread over sixteen waves.
+__global__ void __launch_bounds__(1024) kb_fqr(const FQrArgs* __restrict__ tab, CtrlState* const* ctab, BatchMap m) {
   const int s = m.sid[blockIdx.x];
   fqr_body(tab[s], ctab[s], blockIdx.x - m.start[s]);
 }
@@ -1719,7 +1721,7 @@ hipError_t launch_batch_fqr(const FQrArgs* tab, CtrlState* const* ctab, BatchMap
                             hipStream_t s) {
   hipError_t e = hipFuncSetAttribute((const void*)kb_fqr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kb_fqr, dim3(blocks), dim3(256), lds, s, tab, ctab, m);
+  hipLaunchKernelGGL(kb_fqr, dim3(blocks), dim3(1024), lds, s, tab, ctab, m);
   return hipGetLastError();
 }
 
